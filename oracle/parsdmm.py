@@ -1,0 +1,468 @@
+"""Plain FP64 CPU oracle of PARSDMM (Peters & Herrmann, "Algorithms and
+software for projections onto intersections of convex and non-convex sets
+with applications to inverse problems", arXiv:1902.09699).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, calls or
+links this module; only the test suite, the smoke check and the CPU-baseline
+leg of the benchmark do.  It shares no code with the HIP path.
+
+It is written to be checked against the paper by eye: every linear operator
+is an explicit sparse matrix built from its Kronecker definition, the system
+matrix C is formed as a sparse matrix from eq. (sys_mat) with the current
+rho at every x-update (the incremental update of eq. C_update gives the same
+matrix up to rounding), the x-update is plain
+conjugate gradients, the l1-ball projection sorts, and the cardinality
+projection uses a stable full sort.  Everything is float64.
+
+Readings of the paper that the text leaves open (they are stated again in the
+docstrings where they act):
+
+* grid vectors are C-ordered: axis 0 is z (vertical, slowest), the last axis
+  is x; D along an axis is the forward difference of eq. (FD_mat) lifted by
+  Kronecker products with identities on the other axes;
+* the prox of the squared distance divides by 1 + rho_{p+1} (eq. prox_sq_dist),
+  not by 1 + rho_i as the PARSDMM listing prints;
+* CG stops when ||r|| < cg_rel * ||r_0||, where r_0 is the residual of the warm
+  start x^k (eq. cg_stop: ||b|| cancels), or after cg_max steps; with
+  cg_fixed it runs exactly cg_max steps unless the residual is exactly zero;
+* adapt-rho-gamma uses the y of the current iteration before its update for
+  v-hat, its first call only stores the k0 snapshot, a correlation with a zero
+  norm counts as unreliable, gamma is capped at gamma_max and each rho_i
+  (i <= p) is kept within [rho_{p+1}/R, R rho_{p+1}] after rho_{p+1} moves;
+* the stopping test runs when k is a multiple of stop_every (k >= evol_hist);
+* initial values: x = m, y_i = A_i m, v_i = 0, rho_i = rho0, gamma_i = gamma0;
+* cardinality keeps exactly k entries: largest |w| first, ties to the lower
+  linear index.
+
+Parity of the adapt-rho-gamma trajectory (beyond its hand-checked single
+calls) and of cardinality end-to-end runs is unpinned: the paper prints no
+worked example and the non-convex set has no closed-form reference.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+AXIS_OPS = {
+    2: {"I": (), "DZ": (0,), "DX": (1,), "GRAD": (0, 1), "LAT": (1,)},
+    3: {"I": (), "DZ": (0,), "DY": (1,), "DX": (2,), "GRAD": (0, 1, 2), "LAT": (1, 2)},
+}
+
+
+# ---------------------------------------------------------------------------
+# Linear operators (Sec. "Notation, assumptions, and definitions", eq. FD_mat)
+# ---------------------------------------------------------------------------
+
+def fd_matrix(n: int, h: float) -> sp.csr_matrix:
+    """The (n-1) x n first-order forward difference of eq. (FD_mat): row j
+    holds -1/h at column j and +1/h at column j+1."""
+    rows, cols, vals = [], [], []
+    for j in range(n - 1):
+        rows += [j, j]
+        cols += [j, j + 1]
+        vals += [-1.0 / h, 1.0 / h]
+    return sp.csr_matrix((vals, (rows, cols)), shape=(n - 1, n), dtype=np.float64)
+
+
+def axis_difference(shape, h, axis: int) -> sp.csr_matrix:
+    """D along one grid axis, lifted with identities: for a 2D grid and
+    axis z this is D_z (x) I_x, for axis x it is I_z (x) D_x (eq. FD_mat and
+    the Kronecker definition that follows it)."""
+    factors = [sp.identity(n, dtype=np.float64, format="csr") for n in shape]
+    factors[axis] = fd_matrix(shape[axis], h[axis])
+    out = factors[0]
+    for f in factors[1:]:
+        out = sp.kron(out, f, format="csr")
+    return out.tocsr()
+
+
+def operator(op: str, shape, h=None) -> sp.csr_matrix:
+    """A_i for one set.  "I" is the identity; "DZ"/"DY"/"DX" one difference;
+    "GRAD" stacks every axis difference (anisotropic total variation, as in
+    the 341x400 example's TV set); "LAT" stacks the lateral ones (y, x)."""
+    shape = tuple(int(n) for n in shape)
+    h = tuple(float(v) for v in (h if h is not None else (1.0,) * len(shape)))
+    n_pts = int(np.prod(shape))
+    if op == "I":
+        return sp.identity(n_pts, dtype=np.float64, format="csr")
+    axes = AXIS_OPS[len(shape)][op]
+    return sp.vstack([axis_difference(shape, h, a) for a in axes], format="csr")
+
+
+# ---------------------------------------------------------------------------
+# Projections onto simple sets (Table set-overview) and the distance prox
+# ---------------------------------------------------------------------------
+
+def project_bounds(w, lo, hi):
+    """Element-wise bounds lo <= w[i] <= hi."""
+    return np.minimum(np.maximum(w, lo), hi)
+
+
+def project_l1(w, tau):
+    """Euclidean projection onto {y : ||y||_1 <= tau} by sorting (the
+    sort-and-threshold method the paper cites, Duchi et al. 2008): if w is
+    inside the ball it is returned; otherwise with u = |w| sorted descending
+    and c its running sum, rho is the largest j with u_j > (c_j - tau)/j,
+    theta = (c_rho - tau)/rho and y = sign(w) max(|w| - theta, 0)."""
+    w = np.asarray(w, dtype=np.float64)
+    if tau <= 0.0:
+        return np.zeros_like(w)
+    a = np.abs(w)
+    if a.sum() <= tau:
+        return w.copy()
+    u = np.sort(a)[::-1]
+    c = np.cumsum(u)
+    j = np.arange(1, u.size + 1)
+    rho = int(np.nonzero(u - (c - tau) / j > 0)[0][-1]) + 1
+    theta = (c[rho - 1] - tau) / rho
+    return np.sign(w) * np.maximum(a - theta, 0.0)
+
+
+def l1_threshold(w, tau):
+    """The theta used by project_l1 (0 when w is already inside)."""
+    a = np.abs(np.asarray(w, dtype=np.float64))
+    if tau <= 0.0:
+        return float(a.max()) if a.size else 0.0
+    if a.sum() <= tau:
+        return 0.0
+    u = np.sort(a)[::-1]
+    c = np.cumsum(u)
+    j = np.arange(1, u.size + 1)
+    rho = int(np.nonzero(u - (c - tau) / j > 0)[0][-1]) + 1
+    return float((c[rho - 1] - tau) / rho)
+
+
+def card_support(w, k):
+    """Indices kept by the cardinality projection card(y) <= k: the k entries
+    of largest |w|, ties broken toward the lower linear index (stable sort)."""
+    w = np.asarray(w, dtype=np.float64)
+    order = np.lexsort((np.arange(w.size), -np.abs(w)))
+    return np.sort(order[: int(k)])
+
+
+def project_card(w, k):
+    """Projection onto {y : card(y) <= k} (a non-convex set): keep k entries."""
+    w = np.asarray(w, dtype=np.float64)
+    y = np.zeros_like(w)
+    keep = card_support(w, k)
+    y[keep] = w[keep]
+    return y
+
+
+def project_set(s: dict, w):
+    kind = s["kind"]
+    if kind == "bounds":
+        return project_bounds(w, s["lo"], s["hi"])
+    if kind == "l1":
+        return project_l1(w, s["tau"])
+    if kind == "card":
+        return project_card(w, s["k"])
+    raise ValueError(f"unknown set kind {kind!r}")
+
+
+def prox_sq_dist(w, m, rho):
+    """prox of f(z) = 1/2 ||z - m||^2 with penalty rho: (m + rho w)/(1 + rho),
+    eq. (prox_sq_dist)."""
+    return (m + rho * w) / (1.0 + rho)
+
+
+# ---------------------------------------------------------------------------
+# Options and state
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Options:
+    max_iter: int = 200
+    cg_max: int = 10
+    cg_fixed: bool = True
+    cg_rel: float = 0.1
+    adapt_every: int = 2
+    stop_every: int = 0          # 0: no stopping test, run max_iter iterations
+    evol_hist: int = 5
+    eps_evol: float = 1e-2
+    eps_feas: float = 1e-3
+    rho0: float = 1.0
+    gamma0: float = 1.0
+    eps_corr: float = 0.3
+    rho_ratio_max: float = 100.0
+    gamma_max: float = 1.999
+
+
+@dataclass
+class Snapshot:
+    vhat: np.ndarray
+    v: np.ndarray
+    s: np.ndarray
+    y: np.ndarray
+
+
+@dataclass
+class State:
+    """Everything PARSDMM carries between iterations.  Index p (the last) is
+    the extra identity block A_{p+1} = I with f_{p+1} = 1/2 ||. - m||^2."""
+    x: np.ndarray
+    y: list
+    v: list
+    rho: np.ndarray
+    gamma: np.ndarray
+    k: int = 1
+    snaps: list = field(default_factory=list)
+    x_hist: list = field(default_factory=list)
+    cg_steps: int = 0
+    converged: bool = False
+    r_feas: np.ndarray | None = None
+    r_evol: float = math.inf
+
+
+class Problem:
+    """m, the grid, the sets and everything precomputed from them: the
+    operators A_1..A_p, A_{p+1} = I and B_i = A_i^T A_i (PARSDMM listing,
+    initialisation)."""
+
+    def __init__(self, m, shape, sets, h=None):
+        self.shape = tuple(int(n) for n in shape)
+        self.h = tuple(float(v) for v in (h if h is not None else (1.0,) * len(self.shape)))
+        self.m = np.asarray(m, dtype=np.float64).reshape(-1)
+        self.n = self.m.size
+        self.sets = [dict(s) for s in sets]
+        self.A = [operator(s["op"], self.shape, self.h) for s in self.sets]
+        self.A.append(sp.identity(self.n, dtype=np.float64, format="csr"))
+        self.B = [(a.T @ a).tocsr() for a in self.A]
+        self.p = len(self.sets)
+
+    def system_matrix(self, rho) -> sp.csr_matrix:
+        """C = sum_{i=1}^{p+1} rho_i A_i^T A_i, eq. (sys_mat)."""
+        c = self.B[0] * rho[0]
+        for i in range(1, self.p + 1):
+            c = c + self.B[i] * rho[i]
+        return c.tocsr()
+
+    def prox(self, i, w, rho_i):
+        if i == self.p:
+            return prox_sq_dist(w, self.m, rho_i)
+        return project_set(self.sets[i], w)
+
+
+def initial_state(prob: Problem, opts: Options) -> State:
+    """x = m, y_i = A_i m, v_i = 0, rho_i = rho0, gamma_i = gamma0, k = 1."""
+    x = prob.m.copy()
+    y = [a @ x for a in prob.A]
+    v = [np.zeros(a.shape[0]) for a in prob.A]
+    n = prob.p + 1
+    return State(x=x, y=y, v=v, rho=np.full(n, opts.rho0), gamma=np.full(n, opts.gamma0),
+                 snaps=[None] * n, x_hist=[x.copy()])
+
+
+# ---------------------------------------------------------------------------
+# x-update: conjugate gradients on C x = b (eqs. SDMM_adaptive, sys_mat, cg_stop)
+# ---------------------------------------------------------------------------
+
+def rhs(prob: Problem, st: State) -> np.ndarray:
+    """b = sum_{i=1}^{p+1} A_i^T (rho_i y_i + v_i)."""
+    b = np.zeros(prob.n)
+    for i, a in enumerate(prob.A):
+        b += a.T @ (st.rho[i] * st.y[i] + st.v[i])
+    return b
+
+
+def cg(C, b, x0, cg_rel=0.1, cg_max=10, fixed=True):
+    """Plain conjugate gradients from the warm start x0.  Returns (x, steps).
+    Stops when ||r|| < cg_rel ||r_0|| (unless ``fixed``), when the residual is
+    exactly zero, or after cg_max steps.  A non-positive curvature p^T C p with
+    a non-zero residual raises (C is SPD in exact arithmetic)."""
+    x = np.array(x0, dtype=np.float64, copy=True)
+    r = b - C @ x
+    rr = float(r @ r)
+    rr0 = rr
+    p = r.copy()
+    steps = 0
+    for j in range(cg_max):
+        if rr == 0.0:
+            break
+        if not fixed and j > 0 and rr < cg_rel * cg_rel * rr0:
+            break
+        q = C @ p
+        pq = float(p @ q)
+        if not pq > 0.0:
+            raise FloatingPointError("CG breakdown: p^T C p <= 0")
+        alpha = rr / pq
+        x += alpha * p
+        r -= alpha * q
+        rr_new = float(r @ r)
+        beta = rr_new / rr
+        p = r + beta * p
+        rr = rr_new
+        steps += 1
+    return x, steps
+
+
+# ---------------------------------------------------------------------------
+# adapt-rho-gamma (the second algorithm listing), one set at a time
+# ---------------------------------------------------------------------------
+
+def _spectral(d_a, d_b, eps_corr):
+    """Correlation test and hybrid steepest-descent / minimum-gradient
+    spectral estimate for one pair (Delta-h-hat, Delta-v-hat) or
+    (Delta-g-hat, Delta-v).  Returns (reliable, estimate)."""
+    ab = float(d_a @ d_b)
+    aa = float(d_a @ d_a)
+    bb = float(d_b @ d_b)
+    den = math.sqrt(aa) * math.sqrt(bb)
+    if den == 0.0:
+        return False, 0.0
+    corr = ab / den
+    if not corr > eps_corr:
+        return False, 0.0
+    mg = ab / aa
+    sd = bb / ab
+    est = mg if 2.0 * mg > sd else sd - 0.5 * mg
+    return True, est
+
+
+def adapt_rho_gamma(s, y_old, y_new, v_old, v_new, rho, gamma, snap, eps_corr=0.3):
+    """One call of adapt-rho-gamma for one set.
+
+    v-hat = v^k + rho (y^k - s^{k+1}), with y^k the y before this iteration's
+    update.  Against the previous call's snapshot: dh = s - s0,
+    dvh = vhat - vhat0, dg = -(y^{k+1} - y0), dv = v^{k+1} - v0; both pairs go
+    through the correlation test and the spectral estimate; the four cases
+    give (sqrt(a b), 1 + 2 sqrt(a b)/(a + b)), (a, 1.9), (b, 1.1) or
+    (rho, 1.5).  Without a snapshot (first call) rho and gamma are kept.
+    Returns (rho, gamma, new snapshot)."""
+    vhat = v_old + rho * (y_old - s)
+    new_snap = Snapshot(vhat=vhat.copy(), v=v_new.copy(), s=s.copy(), y=y_new.copy())
+    if snap is None:
+        return rho, gamma, new_snap
+    dh = s - snap.s
+    dvh = vhat - snap.vhat
+    dg = -(y_new - snap.y)
+    dv = v_new - snap.v
+    ok_a, a = _spectral(dh, dvh, eps_corr)
+    ok_b, b = _spectral(dg, dv, eps_corr)
+    if ok_a and ok_b:
+        g = math.sqrt(a * b)
+        return g, 1.0 + 2.0 * g / (a + b), new_snap
+    if ok_a:
+        return a, 1.9, new_snap
+    if ok_b:
+        return b, 1.1, new_snap
+    return rho, 1.5, new_snap
+
+
+def guard_parameters(rho, gamma, opts: Options):
+    """gamma_i <= gamma_max (the relaxation must stay below 2) and
+    rho_{p+1}/R <= rho_i <= R rho_{p+1} for i <= p (the paper limits the
+    ratio to keep C well conditioned without giving R)."""
+    rho = np.array(rho, dtype=np.float64)
+    gamma = np.minimum(np.array(gamma, dtype=np.float64), opts.gamma_max)
+    r_last = rho[-1]
+    rho[:-1] = np.clip(rho[:-1], r_last / opts.rho_ratio_max, r_last * opts.rho_ratio_max)
+    return rho, gamma
+
+
+# ---------------------------------------------------------------------------
+# Stopping conditions (eqs. feas_stop, obj_stop, stopping_conditions)
+# ---------------------------------------------------------------------------
+
+def feasibility_error(s: dict, ax):
+    """r_feas = ||A x - P_C(A x)|| / ||A x||; with A x = 0 it is 0 when A x is
+    in C and infinity otherwise."""
+    proj = project_set(s, ax)
+    num = float(np.linalg.norm(ax - proj))
+    den = float(np.linalg.norm(ax))
+    if den == 0.0:
+        return 0.0 if num == 0.0 else math.inf
+    return num / den
+
+
+def relative_evolution(x, history):
+    """r_evol = max_j ||x^k - x^{k-j}|| / ||x^k|| over the stored history."""
+    nx = float(np.linalg.norm(x))
+    worst = max(float(np.linalg.norm(x - h)) for h in history)
+    if nx == 0.0:
+        return 0.0 if worst == 0.0 else math.inf
+    return worst / nx
+
+
+# ---------------------------------------------------------------------------
+# One PARSDMM iteration and the full run (the PARSDMM listing)
+# ---------------------------------------------------------------------------
+
+def x_update(prob: Problem, st: State, opts: Options) -> int:
+    """x^{k+1} = C^{-1} sum_i A_i^T (rho_i y_i + v_i) by warm-started CG."""
+    C = prob.system_matrix(st.rho)
+    b = rhs(prob, st)
+    st.x, steps = cg(C, b, st.x, opts.cg_rel, opts.cg_max, opts.cg_fixed)
+    st.cg_steps += steps
+    return steps
+
+
+def set_updates(prob: Problem, st: State):
+    """For i = 1..p+1: s_i = A_i x, x-bar_i = gamma_i s_i + (1 - gamma_i) y_i,
+    y_i = prox_i(x-bar_i - v_i/rho_i), v_i += rho_i (y_i - x-bar_i).
+    Returns the s_i and the pre-update y_i and v_i (adapt-rho-gamma needs them)."""
+    s_all, y_old, v_old = [], [], []
+    for i, a in enumerate(prob.A):
+        s = a @ st.x
+        xbar = st.gamma[i] * s + (1.0 - st.gamma[i]) * st.y[i]
+        w = xbar - st.v[i] / st.rho[i]
+        y_old.append(st.y[i])
+        v_old.append(st.v[i])
+        st.y[i] = prob.prox(i, w, st.rho[i])
+        st.v[i] = st.v[i] + st.rho[i] * (st.y[i] - xbar)
+        s_all.append(s)
+    return s_all, y_old, v_old
+
+
+def stop_test(prob: Problem, st: State, opts: Options) -> bool:
+    st.r_feas = np.array([feasibility_error(s, a @ st.x) for s, a in zip(prob.sets, prob.A)])
+    st.r_evol = relative_evolution(st.x, st.x_hist[-opts.evol_hist - 1:-1])
+    return bool(st.r_evol < opts.eps_evol and np.all(st.r_feas < opts.eps_feas))
+
+
+def adapt(prob: Problem, st: State, s_all, y_old, v_old, opts: Options):
+    """adapt-rho-gamma for every i = 1..p+1, then the guards; C follows from
+    the new rho at the next x-update."""
+    rho, gamma = st.rho.copy(), st.gamma.copy()
+    for i in range(prob.p + 1):
+        rho[i], gamma[i], st.snaps[i] = adapt_rho_gamma(
+            s_all[i], y_old[i], st.y[i], v_old[i], st.v[i], st.rho[i], st.gamma[i],
+            st.snaps[i], opts.eps_corr)
+    st.rho, st.gamma = guard_parameters(rho, gamma, opts)
+
+
+def iterate(prob: Problem, st: State, opts: Options, schedule=None) -> bool:
+    """One PARSDMM iteration.  ``schedule`` (optional) maps k to (rho, gamma)
+    to use in iteration k instead of the adapted values (schedule-locked
+    replay of another run).  Returns True when the stopping test passed."""
+    if schedule is not None and st.k in schedule:
+        st.rho = np.array(schedule[st.k][0], dtype=np.float64)
+        st.gamma = np.array(schedule[st.k][1], dtype=np.float64)
+    x_update(prob, st, opts)
+    s_all, y_old, v_old = set_updates(prob, st)
+    st.x_hist.append(st.x.copy())
+    if len(st.x_hist) > opts.evol_hist + 1:
+        st.x_hist.pop(0)
+    stop = False
+    if opts.stop_every and st.k % opts.stop_every == 0 and st.k >= opts.evol_hist:
+        stop = stop_test(prob, st, opts)
+    if not stop and opts.adapt_every and st.k % opts.adapt_every == 1 % opts.adapt_every:
+        adapt(prob, st, s_all, y_old, v_old, opts)
+    st.k += 1
+    return stop
+
+
+def parsdmm(m, shape, sets, opts: Options | None = None, h=None, schedule=None,
+            state: State | None = None):
+    """Project m onto the intersection of the sets.  Returns (x, state)."""
+    opts = opts or Options()
+    prob = Problem(m, shape, sets, h)
+    st = state if state is not None else initial_state(prob, opts)
+    while st.k <= opts.max_iter:
+        if iterate(prob, st, opts, schedule):
+            st.converged = True
+            break
+    return st.x.reshape(prob.shape), st
