@@ -1,0 +1,226 @@
+/*
+ * sip.h — C ABI of the MI355X (gfx950) PARSDMM library (libsip.so).
+ *
+ * PARSDMM (Peters & Herrmann, arXiv:1902.09699) projects a model m on a 2D or
+ * 3D regular grid onto the intersection of p sets V_i = {x | A_i x in C_i}
+ * (Sec. "PARSDMM: Exploiting similarity between constraint sets", eq.
+ * proj_intersect_indicator).  The library adds the identity block
+ * A_{p+1} = I with the squared-distance prox (eqs. PARSDMM_2, prox_sq_dist)
+ * and runs the iteration of eq. SDMM_adaptive / the PARSDMM listing:
+ * a warm-started CG x-update on C = sum_i rho_i A_i^T A_i + rho_{p+1} I
+ * (eqs. sys_mat, cg_stop), the per-set relaxation, projection and multiplier
+ * update, the adapt-rho-gamma listing every adapt_every iterations and,
+ * optionally, the stopping test of eqs. feas_stop / obj_stop.
+ *
+ * Conventions
+ *  - Grids are C-ordered: axis 0 is z (vertical, slowest), the last axis is
+ *    x (contiguous).  2D: n = {nz, nx}; 3D: n = {nz, ny, nx}.
+ *  - D_a is the forward difference of eq. FD_mat along axis a, scaled by
+ *    1/h[a]; its output lives on the grid with the last layer along a unused.
+ *  - Every device pointer is HIP device memory of the plan's field type
+ *    (float or double), C-ordered, N = prod(n) elements, 256-byte alignment
+ *    not required.  The caller owns m and x.  Streams are hipStream_t passed
+ *    as void*; NULL means the default stream.
+ *  - Functions return sip_status (0 on success).  No exception crosses the
+ *    ABI.  Plans and batches are not thread-safe; different plans on
+ *    different streams are.
+ *  - Results are bit-reproducible for float fields: the per-instance work
+ *    decomposition and every reduction order depend only on the instance
+ *    itself, not on the other instances sharing a batch.
+ */
+#ifndef SIP_H
+#define SIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIP_MAX_SETS 16   /* the paper works with up to about 16 sets */
+
+typedef enum {
+  SIP_OK = 0,
+  SIP_EINVAL = -1,       /* bad shape, set parameter, option or argument */
+  SIP_ENOMEM = -2,       /* device or host allocation failed */
+  SIP_EHIP = -3,         /* a HIP runtime call failed */
+  SIP_ENUMERIC = -4,     /* non-finite input/iterate or CG breakdown (p^T C p <= 0) */
+  SIP_EUNSUPPORTED = -5, /* combination the library does not implement */
+  SIP_EBUDGET = -6       /* batch: no free slot or not enough arena memory */
+} sip_status;
+
+typedef enum { SIP_F32 = 0, SIP_F64 = 1 } sip_dtype;
+
+/* Linear operators A_i (Sec. "Notation", eq. FD_mat; Table set-overview). */
+typedef enum {
+  SIP_OP_I = 0,    /* identity */
+  SIP_OP_DZ = 1,   /* D_z (x) I: vertical difference */
+  SIP_OP_DY = 2,   /* 3D only */
+  SIP_OP_DX = 3,   /* I (x) D_x: horizontal difference */
+  SIP_OP_GRAD = 4, /* [D_z; (D_y;) D_x] stacked: anisotropic total variation */
+  SIP_OP_LAT = 5   /* [(D_y;) D_x] stacked: lateral differences */
+} sip_op;
+
+/* Simple sets C_i (Table set-overview). */
+typedef enum {
+  SIP_SET_BOUNDS = 0, /* lo <= (A x)[j] <= hi, +-INFINITY allowed */
+  SIP_SET_L1 = 1,     /* ||A x||_1 <= tau */
+  SIP_SET_CARD = 2    /* card(A x) <= k: keep the k largest |.|, ties to the lower index */
+} sip_set_kind;
+
+typedef struct {
+  int32_t ndim;   /* 2 or 3 */
+  int32_t reserved;
+  int64_t n[3];   /* sizes, axis 0 first; every size >= 1, N < 2^31 */
+  double h[3];    /* grid spacings (> 0) used by the difference operators */
+} sip_grid;
+
+typedef struct {
+  int32_t kind;   /* sip_set_kind */
+  int32_t op;     /* sip_op; the operator's axes need at least 2 points */
+  double lo, hi;  /* BOUNDS: lo <= hi */
+  double tau;     /* L1: tau >= 0 */
+  int64_t k;      /* CARD: 1 <= k <= rows of A */
+} sip_set;
+
+typedef struct {
+  int32_t max_iter;     /* PARSDMM iterations (cap when stopping is on); default 200 */
+  int32_t cg_max;       /* CG steps per x-update (cap); default 10 */
+  int32_t cg_fixed;     /* 1: exactly cg_max steps unless the residual is exactly 0 */
+  int32_t adapt_every;  /* adapt-rho-gamma when k mod adapt_every == 1; 0 = off; default 2 */
+  int32_t stop_every;   /* stopping test when k mod stop_every == 0; 0 = off (default) */
+  int32_t evol_hist;    /* history length s of r_evol; default 5, at most 8 */
+  double rho0, gamma0;  /* initial penalty and relaxation; default 1, 1 */
+  double eps_corr;      /* correlation threshold of adapt-rho-gamma; default 0.3 */
+  double rho_ratio_max; /* rho_i kept within [rho_{p+1}/R, R rho_{p+1}]; default 100 */
+  double gamma_max;     /* relaxation cap below 2; default 1.999 */
+  double eps_evol;      /* default 1e-2 */
+  double eps_feas;      /* default 1e-3 */
+  double cg_rel;        /* CG stops when ||r|| < cg_rel ||r_0||; default 0.1 */
+  int32_t field;        /* sip_dtype of m, x and every field; reductions are always FP64 */
+  int32_t log_schedule; /* 1: record (rho, gamma) of every iteration (sip_batch_schedule) */
+} sip_opts;
+
+typedef struct {
+  int32_t status;     /* sip_status of this instance */
+  int32_t iters;      /* iterations run */
+  int32_t cg_steps;   /* CG steps run, summed over iterations */
+  int32_t converged;  /* 1 when the stopping test passed */
+  int32_t nsets;
+  int32_t reserved;
+  double r_evol;                    /* last evaluated r_evol (eq. obj_stop), or -1 */
+  double r_feas[SIP_MAX_SETS];      /* last evaluated r_feas_i (eq. feas_stop), or -1 */
+  double rho[SIP_MAX_SETS + 1];     /* final rho_i, index nsets is rho_{p+1} */
+  double gamma[SIP_MAX_SETS + 1];   /* final gamma_i */
+} sip_result;
+
+typedef struct sip_batch sip_batch;
+
+/* Readable name of a status code (static storage). */
+const char* sip_strerror(int32_t status);
+
+/* Fill *o with the defaults listed in sip_opts. */
+int32_t sip_opts_default(sip_opts* o);
+
+/* Rows M_i of A_i on the grid (e.g. (nz-1) nx for D_z on nz x nx), or -1. */
+int64_t sip_set_rows(const sip_grid* g, const sip_set* s);
+
+/* Check a grid + set list + options; SIP_OK or SIP_EINVAL / SIP_EUNSUPPORTED. */
+int32_t sip_validate(const sip_grid* g, const sip_set* sets, int32_t nsets, const sip_opts* o);
+
+/* Exact device bytes one instance occupies in a batch arena (state vectors,
+ * adapt snapshots, selection scratch, scalars), rounded to 256 bytes. */
+int64_t sip_workspace_bytes(const sip_grid* g, const sip_set* sets, int32_t nsets,
+                            const sip_opts* o);
+
+/* One blocking projection (the PARSDMM listing): x <- P_{cap V_i}(m).
+ * m_dev and x_dev are device arrays of N field elements; x_dev may equal
+ * m_dev.  Allocates the instance workspace, runs up to max_iter iterations on
+ * `stream`, waits, fills *res (may be NULL) and frees the workspace.
+ * Returns the instance status. */
+int32_t sip_project(const sip_grid* g, const sip_set* sets, int32_t nsets, const sip_opts* o,
+                    const void* m_dev, void* x_dev, sip_result* res, void* stream);
+
+/* B independent projections of uneven size in one batch: instance b has grid
+ * grids[b], sets sets_flat[off_b .. off_b + nsets[b]) (off_b = sum of earlier
+ * nsets) and device arrays m_dev[b], x_dev[b].  Every phase of an iteration
+ * is one launch over a work table of all instances' tiles, and `graph_iters`
+ * iterations are replayed as one captured HIP graph.  Blocks until every
+ * instance stopped; res (array of B, may be NULL) gets the per-instance
+ * results.  Returns SIP_OK or the first failing instance's status. */
+int32_t sip_project_batched(int32_t B, const sip_grid* grids, const sip_set* sets_flat,
+                            const int32_t* nsets, const sip_opts* o,
+                            const void* const* m_dev, void* const* x_dev,
+                            sip_result* res, int32_t graph_iters, void* stream);
+
+/* ---- resident batches (the served form and step-level control) ---------- */
+
+/* A batch holds up to max_slots instances whose state stays on the device in
+ * an arena of arena_bytes (one allocation made here; admission never
+ * allocates again).  All instances share the options and field type. */
+int32_t sip_batch_create(sip_batch** out, int32_t max_slots, int64_t arena_bytes,
+                         const sip_opts* o);
+int32_t sip_batch_destroy(sip_batch* b);
+
+/* Admit one instance: carve its workspace from the arena and enqueue its
+ * initialisation (x = m, y_i = A_i m, v_i = 0, rho_i = rho0, gamma_i = gamma0,
+ * k = 1) on `stream`.  m_dev must stay valid until the initialisation ran;
+ * x_dev receives the iterate in place until the slot is removed.
+ * SIP_EBUDGET when no slot is free or the arena has no room. */
+int32_t sip_batch_add(sip_batch* b, const sip_grid* g, const sip_set* sets, int32_t nsets,
+                      const void* m_dev, void* x_dev, int32_t* slot, void* stream);
+
+/* Enqueue `iters` iterations for every active, unfinished instance on
+ * `stream` (a captured graph replayed; instances that finish stop early). */
+int32_t sip_batch_run(sip_batch* b, int32_t iters, void* stream);
+
+/* Wait for `stream`, then report per slot whether the instance finished
+ * (done[s] = 1, stopped or reached max_iter or failed), was running (0) or
+ * the slot is free (-1).  done has max_slots entries. */
+int32_t sip_batch_poll(sip_batch* b, int32_t* done, void* stream);
+
+/* Wait for `stream`, copy the slot's result and release its workspace. */
+int32_t sip_batch_remove(sip_batch* b, int32_t slot, sip_result* res, void* stream);
+
+/* Wait for `stream` and copy the slot's current result without removing it. */
+int32_t sip_batch_result(sip_batch* b, int32_t slot, sip_result* res, void* stream);
+
+/* Device arrays of a slot's state for export/import by the caller (same
+ * stream ordering rules as any device memory).  which: 0 y_i, 1 v_i,
+ * 2 vhat snapshot, 3 v snapshot, 4 y snapshot (i = nsets means the identity
+ * block p+1); 5 r, 6 x-snapshot buffer 0, 7 x-snapshot buffer 1.  Set
+ * arrays hold one N-element block per operator component (z, y, x order)
+ * with the unused last layer along the component's axis kept at zero. */
+int32_t sip_batch_field(sip_batch* b, int32_t slot, int32_t which, int32_t set,
+                        void** dev_ptr, int64_t* count);
+
+/* Read / overwrite a slot's scalars: rho and gamma (nsets+1 each), the
+ * iteration counter k and whether adapt-rho-gamma holds a snapshot. */
+int32_t sip_batch_get_params(sip_batch* b, int32_t slot, double* rho, double* gamma,
+                             int32_t* k, int32_t* have_snapshot, void* stream);
+int32_t sip_batch_set_params(sip_batch* b, int32_t slot, const double* rho, const double* gamma,
+                             int32_t k, int32_t have_snapshot, void* stream);
+
+/* With opts.log_schedule: copy (rho, gamma) used in iterations 1..n
+ * (n = min(iters run, max_n)) as n rows of nsets+1 values each. */
+int32_t sip_batch_schedule(sip_batch* b, int32_t slot, double* rho, double* gamma,
+                           int32_t max_n, int32_t* n, void* stream);
+
+/* Work decomposition: grid points per item of the point kernels (RHS, CG,
+ * projection) and of the threshold-set kernels, each a multiple of 256 and
+ * grown when an instance would need more than max_items items.  Results are
+ * bit-identical for any batch composition at fixed tile settings.  Applies
+ * from the next sip_batch_run.  Defaults 4096/1024 and 4096/512. */
+int32_t sip_batch_set_tiles(sip_batch* b, int32_t pt_points, int32_t pt_max_items, int32_t thr_points,
+                            int32_t thr_max_items);
+
+/* Per-kernel launch statistics of the last sip_batch_run: number of work
+ * items of each phase (rhs/CG, threshold, selection, instance). */
+int32_t sip_batch_items(sip_batch* b, int32_t* n_point_items, int32_t* n_thr_items,
+                        int32_t* n_pipelines, int32_t* n_instances);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIP_H */

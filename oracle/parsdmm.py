@@ -215,6 +215,7 @@ class State:
     converged: bool = False
     r_feas: np.ndarray | None = None
     r_evol: float = math.inf
+    w_last: list = field(default_factory=list)   # prox arguments of the last iteration
 
 
 class Problem:
@@ -405,10 +406,12 @@ def set_updates(prob: Problem, st: State):
     y_i = prox_i(x-bar_i - v_i/rho_i), v_i += rho_i (y_i - x-bar_i).
     Returns the s_i and the pre-update y_i and v_i (adapt-rho-gamma needs them)."""
     s_all, y_old, v_old = [], [], []
+    st.w_last = []
     for i, a in enumerate(prob.A):
         s = a @ st.x
         xbar = st.gamma[i] * s + (1.0 - st.gamma[i]) * st.y[i]
         w = xbar - st.v[i] / st.rho[i]
+        st.w_last.append(w)
         y_old.append(st.y[i])
         v_old.append(st.v[i])
         st.y[i] = prob.prox(i, w, st.rho[i])

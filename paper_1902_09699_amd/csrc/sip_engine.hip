@@ -1,0 +1,836 @@
+// Host engine and C ABI of libsip: instance layout in a device arena, work
+// tables, HIP-graph capture of iterations, admission / retirement of
+// resident instances (the batched and served forms), results.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "sip_internal.h"
+
+namespace sip {
+
+struct Tables;
+template <typename T> void launch_iteration(hipStream_t st, const Tables& t, const Opts& o);
+template <typename T> void launch_init(hipStream_t st, const InstDesc* D, int inst, int64_t N);
+void launch_zero(hipStream_t st, uint32_t* a, int64_t n);
+void launch_zero(hipStream_t st, double* a, int64_t n);
+
+namespace {
+
+constexpr int64_t kAlign = 256;
+inline int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// ---------------------------------------------------------------- arena
+
+// First-fit allocator over one device allocation; admission never calls the
+// HIP allocator.
+class Arena {
+ public:
+  bool init(int64_t bytes) {
+    if (bytes <= 0) return false;
+    if (hipMalloc(&base_, (size_t)bytes) != hipSuccess) { base_ = nullptr; return false; }
+    size_ = bytes;
+    free_[0] = bytes;
+    return true;
+  }
+  ~Arena() { if (base_) (void)hipFree(base_); }
+  char* alloc(int64_t bytes) {
+    bytes = align_up(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        const int64_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > bytes) free_[off + bytes] = len - bytes;
+        used_[off] = bytes;
+        return base_ + off;
+      }
+    }
+    return nullptr;
+  }
+  void release(char* p) {
+    const int64_t off = p - base_;
+    auto u = used_.find(off);
+    if (u == used_.end()) return;
+    int64_t len = u->second;
+    used_.erase(u);
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && nx->first == off + len) { len += nx->second; nx = free_.erase(nx); }
+    if (nx != free_.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) { pv->second += len; return; }
+    }
+    free_[off] = len;
+  }
+  int64_t free_bytes() const { int64_t s = 0; for (auto& f : free_) s += f.second; return s; }
+
+ private:
+  char* base_ = nullptr;
+  int64_t size_ = 0;
+  std::map<int64_t, int64_t> free_, used_;
+};
+
+// ------------------------------------------------------ set / grid helpers
+
+struct OpInfo { int ncomp; int axis[3]; };
+
+// Internal axes: 0 = z, 1 = y, 2 = x; a 2D grid has ny = 1.
+bool op_info(int ndim, int op, OpInfo& oi) {
+  oi.ncomp = 0;
+  auto add = [&](int a) { oi.axis[oi.ncomp++] = a; };
+  switch (op) {
+    case SIP_OP_I: oi.ncomp = 1; oi.axis[0] = -1; return true;
+    case SIP_OP_DZ: add(0); return true;
+    case SIP_OP_DY: if (ndim != 3) return false; add(1); return true;
+    case SIP_OP_DX: add(2); return true;
+    case SIP_OP_GRAD: add(0); if (ndim == 3) add(1); add(2); return true;
+    case SIP_OP_LAT: if (ndim == 3) add(1); add(2); return true;
+    default: return false;
+  }
+}
+
+void internal_dims(const sip_grid& g, int64_t n[3], double h[3]) {
+  if (g.ndim == 3) {
+    for (int a = 0; a < 3; ++a) { n[a] = g.n[a]; h[a] = g.h[a]; }
+  } else {
+    n[0] = g.n[0]; n[1] = 1; n[2] = g.n[1];
+    h[0] = g.h[0]; h[1] = 1.0; h[2] = g.h[1];
+  }
+}
+
+int64_t rows_of(const sip_grid& g, const sip_set& s) {
+  OpInfo oi;
+  if (!op_info(g.ndim, s.op, oi)) return -1;
+  int64_t n[3]; double h[3];
+  internal_dims(g, n, h);
+  const int64_t N = n[0] * n[1] * n[2];
+  if (oi.axis[0] < 0) return N;
+  int64_t rows = 0;
+  for (int c = 0; c < oi.ncomp; ++c) rows += N / n[oi.axis[c]] * (n[oi.axis[c]] - 1);
+  return rows;
+}
+
+int32_t validate(const sip_grid* g, const sip_set* sets, int32_t nsets, const sip_opts* o) {
+  if (!g || !o || (nsets > 0 && !sets)) return SIP_EINVAL;
+  if (g->ndim != 2 && g->ndim != 3) return SIP_EINVAL;
+  if (nsets < 0 || nsets > SIP_MAX_SETS) return SIP_EINVAL;
+  if (o->field != SIP_F32 && o->field != SIP_F64) return SIP_EINVAL;
+  int64_t N = 1;
+  for (int a = 0; a < g->ndim; ++a) {
+    if (g->n[a] < 1 || !(g->h[a] > 0.0) || !std::isfinite(g->h[a])) return SIP_EINVAL;
+    N *= g->n[a];
+    if (N >= (int64_t(1) << 31)) return SIP_EINVAL;
+  }
+  if (o->max_iter < 1 || o->cg_max < 0 || o->adapt_every < 0 || o->stop_every < 0) return SIP_EINVAL;
+  if (o->stop_every > 0 && (o->evol_hist < 1 || o->evol_hist > kMaxHist - 1)) return SIP_EINVAL;
+  if (!(o->rho0 > 0.0) || !(o->gamma0 >= 1.0 && o->gamma0 < 2.0)) return SIP_EINVAL;
+  if (!(o->rho_ratio_max >= 1.0) || !(o->gamma_max >= 1.0 && o->gamma_max < 2.0)) return SIP_EINVAL;
+  if (!(o->cg_rel > 0.0)) return SIP_EINVAL;
+  int64_t n[3]; double h[3];
+  internal_dims(*g, n, h);
+  for (int i = 0; i < nsets; ++i) {
+    const sip_set& s = sets[i];
+    OpInfo oi;
+    if (!op_info(g->ndim, s.op, oi)) return SIP_EINVAL;
+    for (int c = 0; c < oi.ncomp; ++c)
+      if (oi.axis[c] >= 0 && n[oi.axis[c]] < 2) return SIP_EINVAL;
+    const int64_t M = rows_of(*g, s);
+    switch (s.kind) {
+      case SIP_SET_BOUNDS:
+        if (std::isnan(s.lo) || std::isnan(s.hi) || s.lo > s.hi) return SIP_EINVAL;
+        break;
+      case SIP_SET_L1:
+        if (!(s.tau >= 0.0) || !std::isfinite(s.tau)) return SIP_EINVAL;
+        break;
+      case SIP_SET_CARD:
+        if (s.k < 1 || s.k > M) return SIP_EINVAL;
+        break;
+      default:
+        return SIP_EINVAL;
+    }
+  }
+  return SIP_OK;
+}
+
+bool is_thr(const sip_set& s) { return s.kind == SIP_SET_L1 || s.kind == SIP_SET_CARD; }
+
+// Byte layout of one instance's workspace.
+struct Layout {
+  int64_t total = 0;
+  int64_t log = -1, m, r, p0, p1, yl, vl, vh0l = -1, v0l = -1, y0l = -1, xs0 = -1, xs1 = -1, ring = -1;
+  struct SetL { int64_t y, v, vh0 = -1, v0 = -1, y0 = -1; int64_t sel[2] = {-1, -1}, hc[2] = {-1, -1},
+                hs[2] = {-1, -1}, cand[2] = {-1, -1}; } set[SIP_MAX_SETS];
+};
+
+Layout layout_of(const sip_grid& g, const sip_set* sets, int nsets, const sip_opts& o) {
+  Layout L;
+  int64_t n[3]; double h[3];
+  internal_dims(g, n, h);
+  const int64_t N = n[0] * n[1] * n[2];
+  const int64_t esz = o.field == SIP_F64 ? 8 : 4;
+  const int64_t vec = align_up(N * esz);
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) { const int64_t at = off; off += align_up(bytes); return at; };
+  if (o.log_schedule) L.log = take((int64_t)o.max_iter * 2 * kMaxUnits * 8);
+  L.m = take(vec); L.r = take(vec); L.p0 = take(vec); L.p1 = take(vec);
+  L.yl = take(vec); L.vl = take(vec);
+  const bool adapt = o.adapt_every > 0, stop = o.stop_every > 0;
+  if (adapt) { L.vh0l = take(vec); L.v0l = take(vec); L.y0l = take(vec); L.xs0 = take(vec); L.xs1 = take(vec); }
+  if (stop) L.ring = take((int64_t)(o.evol_hist + 1) * vec);
+  for (int i = 0; i < nsets; ++i) {
+    OpInfo oi;
+    op_info(g.ndim, sets[i].op, oi);
+    const int64_t blk = oi.ncomp * vec;
+    auto& S = L.set[i];
+    S.y = take(blk); S.v = take(blk);
+    if (adapt) { S.vh0 = take(blk); S.v0 = take(blk); S.y0 = take(blk); }
+    if (is_thr(sets[i])) {
+      for (int src = 0; src < (stop ? 2 : 1); ++src) {
+        S.sel[src] = take(sizeof(SelState));
+        S.hc[src] = take(kNB * 4);
+        S.hs[src] = take(kNB * 8);
+        S.cand[src] = take((int64_t)oi.ncomp * N * esz);
+      }
+    }
+  }
+  L.total = align_up(off);
+  return L;
+}
+
+Opts kernel_opts(const sip_opts& o) {
+  Opts k;
+  k.cg_max = o.cg_max; k.cg_fixed = o.cg_fixed; k.adapt_every = o.adapt_every; k.stop_every = o.stop_every;
+  k.evol_hist = o.evol_hist; k.max_iter = o.max_iter;
+  k.cg_rel2 = o.cg_rel * o.cg_rel; k.eps_corr = o.eps_corr; k.rho_ratio_max = o.rho_ratio_max;
+  k.gamma_max = o.gamma_max; k.eps_evol = o.eps_evol; k.eps_feas = o.eps_feas;
+  return k;
+}
+
+// Points per item: a tile of whole 256-point chunks, at least `base`, and
+// few enough items that the per-instance partial reductions stay short.
+int64_t tile_points(int64_t N, int64_t base, int64_t max_items) {
+  int64_t t = std::max<int64_t>(base, (N + max_items - 1) / max_items);
+  return (t + kBlock - 1) / kBlock * kBlock;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ batch
+
+struct Slot {
+  bool used = false;
+  sip_grid grid{};
+  int nsets = 0;
+  sip_set sets[SIP_MAX_SETS]{};
+  char* ws = nullptr;
+  Layout L;
+  InstDesc desc{};
+  void* x = nullptr;
+  int64_t N = 0;
+};
+
+struct TileCfg { int64_t pt_base = 4096, pt_max_items = 1024, thr_base = 4096, thr_max_items = 512; };
+
+}  // namespace sip
+
+struct sip_batch {
+  sip_opts opts{};
+  sip::Opts kopts{};
+  int max_slots = 0;
+  sip::Arena arena;
+  std::vector<sip::Slot> slots;
+  hipStream_t cap_stream = nullptr;
+  // device
+  sip::InstDesc* d_desc = nullptr;
+  double* d_scal = nullptr;   // [max_slots][S_COUNT]
+  double* h_scal = nullptr;   // pinned mirror
+  // work tables (device, capacity-managed)
+  sip::PtItem* d_pt = nullptr; int cap_pt = 0;
+  sip::ThrItem* d_thr = nullptr; int cap_thr = 0;
+  sip::SelItem* d_sel = nullptr; int cap_sel = 0;
+  int32_t* d_inst = nullptr; int cap_inst = 0;
+  double *d_rr = nullptr, *d_pq = nullptr, *d_proj = nullptr, *d_thrw = nullptr, *d_thra = nullptr;
+  uint32_t* d_tie = nullptr;
+  int cap_ppt = 0, cap_pthr = 0;   // item capacity of the partial-sum buffers
+  sip::Tables tab{};
+  bool dirty = true;
+  std::map<int, hipGraphExec_t> graphs;
+  sip::TileCfg tiles;
+};
+
+namespace sip {
+namespace {
+
+#define HIP_OK(expr)                                  \
+  do {                                                \
+    if ((expr) != hipSuccess) return SIP_EHIP;        \
+  } while (0)
+
+template <typename P>
+int32_t ensure(P*& ptr, int& cap, int need, size_t elem_bytes) {
+  if (need <= cap && ptr) return SIP_OK;
+  int nc = std::max(need, std::max(64, cap * 2));
+  if (ptr) { HIP_OK(hipFree(ptr)); ptr = nullptr; }
+  HIP_OK(hipMalloc((void**)&ptr, (size_t)nc * elem_bytes));
+  cap = nc;
+  return SIP_OK;
+}
+
+void drop_graphs(sip_batch* b) {
+  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
+}
+
+int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
+  std::vector<PtItem> pt;
+  std::vector<ThrItem> thr;
+  std::vector<SelItem> sel;
+  std::vector<int32_t> inst;
+  bool any_card = false;
+  for (int si = 0; si < b->max_slots; ++si) {
+    Slot& s = b->slots[si];
+    if (!s.used) continue;
+    inst.push_back(si);
+    const int N = (int)s.N;
+    const int64_t tp = tile_points(N, b->tiles.pt_base, b->tiles.pt_max_items);
+    s.desc.pt_begin = (int)pt.size();
+    for (int64_t p0 = 0; p0 < N; p0 += tp) pt.push_back(PtItem{si, (int)p0, (int)std::min<int64_t>(tp, N - p0), 0});
+    s.desc.pt_end = (int)pt.size();
+    const int64_t tt = tile_points(N, b->tiles.thr_base, b->tiles.thr_max_items);
+    for (int k = 0; k < s.nsets; ++k) {
+      SetDesc& sd = s.desc.sets[k];
+      if (sd.thr < 0) continue;
+      if (sd.kind == SIP_SET_CARD) any_card = true;
+      for (int src = 0; src < (b->opts.stop_every > 0 ? 2 : 1); ++src) {
+        sel.push_back(SelItem{si, k, src, 0});
+        sd.item_begin[src] = (int)thr.size();
+        for (int64_t p0 = 0; p0 < N; p0 += tt)
+          thr.push_back(ThrItem{si, k, src, 0, (int)p0, (int)std::min<int64_t>(tt, N - p0)});
+        sd.item_end[src] = (int)thr.size();
+      }
+    }
+  }
+  // nothing queued may still read the tables or partial buffers replaced below
+  HIP_OK(hipStreamSynchronize(stream));
+  int32_t rc;
+  const int npt = std::max<int>((int)pt.size(), 1), nthr = std::max<int>((int)thr.size(), 1);
+  if ((rc = ensure(b->d_pt, b->cap_pt, npt, sizeof(PtItem)))) return rc;
+  if ((rc = ensure(b->d_thr, b->cap_thr, nthr, sizeof(ThrItem)))) return rc;
+  if ((rc = ensure(b->d_sel, b->cap_sel, (int)std::max<size_t>(sel.size(), 1), sizeof(SelItem)))) return rc;
+  if ((rc = ensure(b->d_inst, b->cap_inst, (int)std::max<size_t>(inst.size(), 1), sizeof(int32_t)))) return rc;
+  if (b->cap_ppt < b->cap_pt) {
+    if (b->d_rr) { HIP_OK(hipFree(b->d_rr)); HIP_OK(hipFree(b->d_pq)); HIP_OK(hipFree(b->d_proj)); }
+    HIP_OK(hipMalloc((void**)&b->d_rr, (size_t)b->cap_pt * 8));
+    HIP_OK(hipMalloc((void**)&b->d_pq, (size_t)b->cap_pt * 8));
+    HIP_OK(hipMalloc((void**)&b->d_proj, (size_t)b->cap_pt * kProjParts * 8));
+    b->cap_ppt = b->cap_pt;
+  }
+  if (b->cap_pthr < b->cap_thr) {
+    if (b->d_thrw) { HIP_OK(hipFree(b->d_thrw)); HIP_OK(hipFree(b->d_thra)); HIP_OK(hipFree(b->d_tie)); }
+    HIP_OK(hipMalloc((void**)&b->d_thrw, (size_t)b->cap_thr * kThrParts * 8));
+    HIP_OK(hipMalloc((void**)&b->d_thra, (size_t)b->cap_thr * kThrParts * 8));
+    HIP_OK(hipMalloc((void**)&b->d_tie, (size_t)b->cap_thr * 3 * 4));
+    b->cap_pthr = b->cap_thr;
+  }
+  if (!pt.empty()) HIP_OK(hipMemcpyAsync(b->d_pt, pt.data(), pt.size() * sizeof(PtItem), hipMemcpyHostToDevice, stream));
+  if (!thr.empty()) HIP_OK(hipMemcpyAsync(b->d_thr, thr.data(), thr.size() * sizeof(ThrItem), hipMemcpyHostToDevice, stream));
+  if (!sel.empty()) HIP_OK(hipMemcpyAsync(b->d_sel, sel.data(), sel.size() * sizeof(SelItem), hipMemcpyHostToDevice, stream));
+  if (!inst.empty()) HIP_OK(hipMemcpyAsync(b->d_inst, inst.data(), inst.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  for (int si = 0; si < b->max_slots; ++si) {
+    if (!b->slots[si].used) continue;
+    HIP_OK(hipMemcpyAsync(b->d_desc + si, &b->slots[si].desc, sizeof(InstDesc), hipMemcpyHostToDevice, stream));
+  }
+  HIP_OK(hipStreamSynchronize(stream));
+  Tables& t = b->tab;
+  t.D = b->d_desc;
+  t.pt = b->d_pt; t.npt = (int)pt.size();
+  t.thr = b->d_thr; t.nthr = (int)thr.size();
+  t.sel = b->d_sel; t.nsel = (int)sel.size();
+  t.inst = b->d_inst; t.ninst = (int)inst.size();
+  t.rr_part = b->d_rr; t.pq_part = b->d_pq; t.proj_part = b->d_proj;
+  t.thrw_part = b->d_thrw; t.thra_part = b->d_thra; t.tie_part = b->d_tie;
+  t.any_card = any_card;
+  drop_graphs(b);
+  b->dirty = false;
+  return SIP_OK;
+}
+
+int32_t get_graph(sip_batch* b, int iters, hipGraphExec_t& out) {
+  auto it = b->graphs.find(iters);
+  if (it != b->graphs.end()) { out = it->second; return SIP_OK; }
+  HIP_OK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  for (int i = 0; i < iters; ++i) {
+    if (b->opts.field == SIP_F64) launch_iteration<double>(b->cap_stream, b->tab, b->kopts);
+    else launch_iteration<float>(b->cap_stream, b->tab, b->kopts);
+  }
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(b->cap_stream, &g) != hipSuccess || !g) return SIP_EHIP;
+  hipGraphExec_t ge = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return SIP_EHIP;
+  b->graphs[iters] = ge;
+  out = ge;
+  return SIP_OK;
+}
+
+void initial_scalars(const sip_batch* b, const Slot& s, double* S) {
+  for (int i = 0; i < S_COUNT; ++i) S[i] = 0.0;
+  const sip_opts& o = b->opts;
+  for (int u = 0; u <= s.nsets; ++u) { S[S_RHO + u] = o.rho0; S[S_GAMMA + u] = o.gamma0; }
+  double c0 = o.rho0, ca[3] = {0, 0, 0};
+  for (int u = 0; u < s.nsets; ++u) {
+    const SetDesc& sd = s.desc.sets[u];
+    if (sd.op == SIP_OP_I) c0 += o.rho0;
+    else for (int c = 0; c < sd.ncomp; ++c) ca[sd.axis[c]] += o.rho0;
+  }
+  S[S_C0] = c0;
+  for (int a = 0; a < 3; ++a) S[S_CAX + a] = ca[a] * s.desc.h2inv[a];
+  S[S_K] = 1.0;
+  S[S_REVOL] = -1.0;
+  for (int i = 0; i < SIP_MAX_SETS; ++i) S[S_RFEAS + i] = -1.0;
+}
+
+void fill_result(const Slot& s, const double* S, sip_result* r) {
+  std::memset(r, 0, sizeof(*r));
+  r->status = (int32_t)S[S_ERR];
+  r->iters = (int32_t)S[S_ITERS];
+  r->cg_steps = (int32_t)S[S_CGTOT];
+  r->converged = S[S_STATE] == 1.0 ? 1 : 0;
+  r->nsets = s.nsets;
+  r->r_evol = S[S_REVOL];
+  for (int i = 0; i < SIP_MAX_SETS; ++i) r->r_feas[i] = i < s.nsets ? S[S_RFEAS + i] : -1.0;
+  for (int u = 0; u <= s.nsets; ++u) { r->rho[u] = S[S_RHO + u]; r->gamma[u] = S[S_GAMMA + u]; }
+}
+
+int32_t read_scal(sip_batch* b, hipStream_t stream) {
+  HIP_OK(hipMemcpyAsync(b->h_scal, b->d_scal, (size_t)b->max_slots * S_COUNT * 8, hipMemcpyDeviceToHost, stream));
+  HIP_OK(hipStreamSynchronize(stream));
+  return SIP_OK;
+}
+
+}  // namespace
+}  // namespace sip
+
+using namespace sip;
+
+// ==================================================================== C ABI
+
+extern "C" {
+
+const char* sip_strerror(int32_t st) {
+  switch (st) {
+    case SIP_OK: return "ok";
+    case SIP_EINVAL: return "invalid argument";
+    case SIP_ENOMEM: return "out of memory";
+    case SIP_EHIP: return "HIP runtime error";
+    case SIP_ENUMERIC: return "numerical failure (non-finite value or CG breakdown)";
+    case SIP_EUNSUPPORTED: return "unsupported";
+    case SIP_EBUDGET: return "batch full (slots or arena)";
+    default: return "unknown status";
+  }
+}
+
+int32_t sip_opts_default(sip_opts* o) {
+  if (!o) return SIP_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->max_iter = 200; o->cg_max = 10; o->cg_fixed = 0; o->adapt_every = 2; o->stop_every = 0; o->evol_hist = 5;
+  o->rho0 = 1.0; o->gamma0 = 1.0; o->eps_corr = 0.3; o->rho_ratio_max = 100.0; o->gamma_max = 1.999;
+  o->eps_evol = 1e-2; o->eps_feas = 1e-3; o->cg_rel = 0.1; o->field = SIP_F32; o->log_schedule = 0;
+  return SIP_OK;
+}
+
+int64_t sip_set_rows(const sip_grid* g, const sip_set* s) {
+  if (!g || !s || (g->ndim != 2 && g->ndim != 3)) return -1;
+  return rows_of(*g, *s);
+}
+
+int32_t sip_validate(const sip_grid* g, const sip_set* sets, int32_t nsets, const sip_opts* o) {
+  return validate(g, sets, nsets, o);
+}
+
+int64_t sip_workspace_bytes(const sip_grid* g, const sip_set* sets, int32_t nsets, const sip_opts* o) {
+  if (validate(g, sets, nsets, o) != SIP_OK) return -1;
+  return layout_of(*g, sets, nsets, *o).total;
+}
+
+int32_t sip_batch_create(sip_batch** out, int32_t max_slots, int64_t arena_bytes, const sip_opts* o) {
+  if (!out || !o || max_slots < 1 || arena_bytes <= 0) return SIP_EINVAL;
+  sip_opts probe = *o;
+  sip_grid g{}; g.ndim = 2; g.n[0] = 2; g.n[1] = 2; g.h[0] = g.h[1] = 1.0;
+  if (validate(&g, nullptr, 0, &probe) != SIP_OK) return SIP_EINVAL;
+  sip_batch* b = new (std::nothrow) sip_batch();
+  if (!b) return SIP_ENOMEM;
+  b->opts = *o;
+  b->kopts = kernel_opts(*o);
+  b->max_slots = max_slots;
+  b->slots.resize(max_slots);
+  if (!b->arena.init(arena_bytes)) { delete b; return SIP_ENOMEM; }
+  if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) { delete b; return SIP_EHIP; }
+  if (hipMalloc((void**)&b->d_desc, sizeof(InstDesc) * max_slots) != hipSuccess ||
+      hipMalloc((void**)&b->d_scal, sizeof(double) * S_COUNT * max_slots) != hipSuccess ||
+      hipHostMalloc((void**)&b->h_scal, sizeof(double) * S_COUNT * max_slots, 0) != hipSuccess) {
+    sip_batch_destroy(b);
+    return SIP_ENOMEM;
+  }
+  std::memset(b->h_scal, 0, sizeof(double) * S_COUNT * max_slots);
+  if (hipMemcpy(b->d_scal, b->h_scal, sizeof(double) * S_COUNT * max_slots, hipMemcpyHostToDevice) != hipSuccess) {
+    sip_batch_destroy(b);
+    return SIP_EHIP;
+  }
+  *out = b;
+  return SIP_OK;
+}
+
+int32_t sip_batch_destroy(sip_batch* b) {
+  if (!b) return SIP_OK;
+  drop_graphs(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  void* dev[] = {b->d_desc, b->d_scal, b->d_pt, b->d_thr, b->d_sel, b->d_inst, b->d_rr, b->d_pq,
+                 b->d_proj, b->d_thrw, b->d_thra, b->d_tie};
+  for (void* p : dev) if (p) (void)hipFree(p);
+  if (b->h_scal) (void)hipHostFree(b->h_scal);
+  delete b;
+  return SIP_OK;
+}
+
+int32_t sip_batch_add(sip_batch* b, const sip_grid* g, const sip_set* sets, int32_t nsets, const void* m_dev,
+                      void* x_dev, int32_t* slot_out, void* stream_) {
+  if (!b || !m_dev || !x_dev) return SIP_EINVAL;
+  const int32_t vr = validate(g, sets, nsets, &b->opts);
+  if (vr != SIP_OK) return vr;
+  hipStream_t stream = (hipStream_t)stream_;
+  int si = -1;
+  for (int i = 0; i < b->max_slots; ++i) if (!b->slots[i].used) { si = i; break; }
+  if (si < 0) return SIP_EBUDGET;
+  Slot& s = b->slots[si];
+  s = Slot();
+  s.L = layout_of(*g, sets, nsets, b->opts);
+  s.ws = b->arena.alloc(s.L.total);
+  if (!s.ws) return SIP_EBUDGET;
+  s.used = true;
+  s.grid = *g;
+  s.nsets = nsets;
+  for (int i = 0; i < nsets; ++i) s.sets[i] = sets[i];
+  s.x = x_dev;
+  int64_t n[3]; double h[3];
+  internal_dims(*g, n, h);
+  s.N = n[0] * n[1] * n[2];
+  InstDesc& d = s.desc;
+  std::memset(&d, 0, sizeof(d));
+  d.ndim = g->ndim; d.nsets = nsets; d.active = 1;
+  for (int a = 0; a < 3; ++a) { d.n[a] = n[a]; d.hinv[a] = 1.0 / h[a]; d.h2inv[a] = 1.0 / (h[a] * h[a]); }
+  d.N = s.N;
+  d.stride[2] = 1; d.stride[1] = n[2]; d.stride[0] = n[1] * n[2];
+  d.div_x = make_fastdiv((uint32_t)n[2]);
+  d.div_y = make_fastdiv((uint32_t)n[1]);
+  char* w = s.ws;
+  const Layout& L = s.L;
+  auto at = [&](int64_t off) -> void* { return off >= 0 ? (void*)(w + off) : nullptr; };
+  d.m = at(L.m); d.x = x_dev; d.r = at(L.r); d.p[0] = at(L.p0); d.p[1] = at(L.p1);
+  d.xs[0] = at(L.xs0); d.xs[1] = at(L.xs1); d.ring = at(L.ring);
+  d.yl = at(L.yl); d.vl = at(L.vl); d.vh0l = at(L.vh0l); d.v0l = at(L.v0l); d.y0l = at(L.y0l);
+  d.scal = b->d_scal + (size_t)si * S_COUNT;
+  d.log = (double*)at(L.log);
+  d.log_cap = b->opts.log_schedule ? b->opts.max_iter : 0;
+  int nthr = 0;
+  for (int i = 0; i < nsets; ++i) {
+    SetDesc& sd = d.sets[i];
+    OpInfo oi;
+    op_info(g->ndim, sets[i].op, oi);
+    sd.kind = sets[i].kind; sd.op = sets[i].op; sd.ncomp = oi.ncomp;
+    for (int c = 0; c < 3; ++c) sd.axis[c] = c < oi.ncomp ? oi.axis[c] : -1;
+    sd.thr = is_thr(sets[i]) ? nthr++ : -1;
+    sd.lo = sets[i].lo; sd.hi = sets[i].hi; sd.tau = sets[i].tau; sd.k = sets[i].k;
+    sd.rows = rows_of(*g, sets[i]);
+    const auto& SL = L.set[i];
+    sd.y = at(SL.y); sd.v = at(SL.v); sd.vh0 = at(SL.vh0); sd.v0 = at(SL.v0); sd.y0 = at(SL.y0);
+    for (int src = 0; src < 2; ++src) {
+      sd.sel[src] = (SelState*)at(SL.sel[src]);
+      sd.hcnt[src] = (uint32_t*)at(SL.hc[src]);
+      sd.hsum[src] = (double*)at(SL.hs[src]);
+      sd.cand[src] = at(SL.cand[src]);
+    }
+  }
+  const size_t esz = b->opts.field == SIP_F64 ? 8 : 4;
+  double S[S_COUNT];
+  initial_scalars(b, s, S);
+  int32_t rc = SIP_OK;
+  if (hipMemcpyAsync(d.m, m_dev, (size_t)s.N * esz, hipMemcpyDeviceToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(b->d_desc + si, &d, sizeof(InstDesc), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(d.scal, S, sizeof(S), hipMemcpyHostToDevice, stream) != hipSuccess) {
+    rc = SIP_EHIP;
+  }
+  if (rc == SIP_OK) {
+    for (int i = 0; i < nsets; ++i) {
+      const SetDesc& sd = d.sets[i];
+      for (int src = 0; src < 2; ++src) {
+        if (!sd.hcnt[src]) continue;
+        launch_zero(stream, sd.hcnt[src], kNB);
+        launch_zero(stream, sd.hsum[src], kNB);
+      }
+    }
+    if (b->opts.field == SIP_F64) launch_init<double>(stream, b->d_desc, si, s.N);
+    else launch_init<float>(stream, b->d_desc, si, s.N);
+    if (hipGetLastError() != hipSuccess) rc = SIP_EHIP;
+    // the host copies above read stack memory: finish them before returning
+    if (hipStreamSynchronize(stream) != hipSuccess) rc = SIP_EHIP;
+  }
+  if (rc != SIP_OK) {
+    b->arena.release(s.ws);
+    s = Slot();
+    return rc;
+  }
+  b->dirty = true;
+  if (slot_out) *slot_out = si;
+  return SIP_OK;
+}
+
+int32_t sip_batch_run(sip_batch* b, int32_t iters, void* stream_) {
+  if (!b || iters < 0) return SIP_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  if (b->dirty) {
+    const int32_t rc = rebuild_tables(b, stream);
+    if (rc != SIP_OK) return rc;
+  }
+  if (b->tab.ninst == 0 || iters == 0) return SIP_OK;
+  hipGraphExec_t ge;
+  const int32_t rc = get_graph(b, iters, ge);
+  if (rc != SIP_OK) return rc;
+  HIP_OK(hipGraphLaunch(ge, stream));
+  return SIP_OK;
+}
+
+int32_t sip_batch_poll(sip_batch* b, int32_t* done, void* stream_) {
+  if (!b || !done) return SIP_EINVAL;
+  const int32_t rc = read_scal(b, (hipStream_t)stream_);
+  if (rc != SIP_OK) return rc;
+  for (int i = 0; i < b->max_slots; ++i) {
+    if (!b->slots[i].used) { done[i] = -1; continue; }
+    const double* S = b->h_scal + (size_t)i * S_COUNT;
+    done[i] = (S[S_STATE] != 0.0 || S[S_ERR] != 0.0) ? 1 : 0;
+  }
+  return SIP_OK;
+}
+
+int32_t sip_batch_result(sip_batch* b, int32_t slot, sip_result* res, void* stream_) {
+  if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used || !res) return SIP_EINVAL;
+  const int32_t rc = read_scal(b, (hipStream_t)stream_);
+  if (rc != SIP_OK) return rc;
+  fill_result(b->slots[slot], b->h_scal + (size_t)slot * S_COUNT, res);
+  return SIP_OK;
+}
+
+int32_t sip_batch_remove(sip_batch* b, int32_t slot, sip_result* res, void* stream_) {
+  if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return SIP_EINVAL;
+  const int32_t rc = read_scal(b, (hipStream_t)stream_);
+  if (rc != SIP_OK) return rc;
+  if (res) fill_result(b->slots[slot], b->h_scal + (size_t)slot * S_COUNT, res);
+  b->arena.release(b->slots[slot].ws);
+  b->slots[slot] = Slot();
+  b->dirty = true;
+  return SIP_OK;
+}
+
+int32_t sip_batch_field(sip_batch* b, int32_t slot, int32_t which, int32_t set, void** ptr, int64_t* count) {
+  if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used || !ptr || !count) return SIP_EINVAL;
+  const Slot& s = b->slots[slot];
+  const InstDesc& d = s.desc;
+  *ptr = nullptr;
+  *count = 0;
+  if (which <= 4) {
+    if (set < 0 || set > s.nsets) return SIP_EINVAL;
+    const bool ident = set == s.nsets;
+    const int nc = ident ? 1 : d.sets[set].ncomp;
+    void* p = nullptr;
+    switch (which) {
+      case 0: p = ident ? d.yl : d.sets[set].y; break;
+      case 1: p = ident ? d.vl : d.sets[set].v; break;
+      case 2: p = ident ? d.vh0l : d.sets[set].vh0; break;
+      case 3: p = ident ? d.v0l : d.sets[set].v0; break;
+      case 4: p = ident ? d.y0l : d.sets[set].y0; break;
+    }
+    if (!p) return SIP_EINVAL;
+    *ptr = p;
+    *count = nc * s.N;
+    return SIP_OK;
+  }
+  void* p = which == 5 ? d.r : which == 6 ? d.xs[0] : which == 7 ? d.xs[1] : nullptr;
+  if (!p) return SIP_EINVAL;
+  *ptr = p;
+  *count = s.N;
+  return SIP_OK;
+}
+
+int32_t sip_batch_get_params(sip_batch* b, int32_t slot, double* rho, double* gamma, int32_t* k, int32_t* have,
+                             void* stream_) {
+  if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return SIP_EINVAL;
+  const int32_t rc = read_scal(b, (hipStream_t)stream_);
+  if (rc != SIP_OK) return rc;
+  const double* S = b->h_scal + (size_t)slot * S_COUNT;
+  const int p = b->slots[slot].nsets;
+  for (int u = 0; u <= p; ++u) { if (rho) rho[u] = S[S_RHO + u]; if (gamma) gamma[u] = S[S_GAMMA + u]; }
+  if (k) *k = (int32_t)S[S_K];
+  if (have) *have = S[S_HAVE_SNAP] != 0.0;
+  return SIP_OK;
+}
+
+int32_t sip_batch_set_params(sip_batch* b, int32_t slot, const double* rho, const double* gamma, int32_t k,
+                             int32_t have, void* stream_) {
+  if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used || k < 1) return SIP_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  const int32_t rc = read_scal(b, stream);
+  if (rc != SIP_OK) return rc;
+  double* S = b->h_scal + (size_t)slot * S_COUNT;
+  const Slot& s = b->slots[slot];
+  const int p = s.nsets;
+  for (int u = 0; u <= p; ++u) {
+    if (rho) { if (!(rho[u] > 0.0)) return SIP_EINVAL; S[S_RHO + u] = rho[u]; }
+    if (gamma) S[S_GAMMA + u] = gamma[u];
+  }
+  double c0 = S[S_RHO + p], ca[3] = {0, 0, 0};
+  for (int u = 0; u < p; ++u) {
+    const SetDesc& sd = s.desc.sets[u];
+    if (sd.op == SIP_OP_I) c0 += S[S_RHO + u];
+    else for (int c = 0; c < sd.ncomp; ++c) ca[sd.axis[c]] += S[S_RHO + u];
+  }
+  S[S_C0] = c0;
+  for (int a = 0; a < 3; ++a) S[S_CAX + a] = ca[a] * s.desc.h2inv[a];
+  S[S_K] = (double)k;
+  S[S_HAVE_SNAP] = have ? 1.0 : 0.0;
+  S[S_STATE] = (k > b->opts.max_iter) ? 2.0 : 0.0;
+  HIP_OK(hipMemcpyAsync(b->d_scal + (size_t)slot * S_COUNT, S, sizeof(double) * S_COUNT, hipMemcpyHostToDevice, stream));
+  HIP_OK(hipStreamSynchronize(stream));
+  return SIP_OK;
+}
+
+int32_t sip_batch_schedule(sip_batch* b, int32_t slot, double* rho, double* gamma, int32_t max_n, int32_t* n,
+                           void* stream_) {
+  if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used || !n) return SIP_EINVAL;
+  const Slot& s = b->slots[slot];
+  if (!s.desc.log) return SIP_EUNSUPPORTED;
+  hipStream_t stream = (hipStream_t)stream_;
+  int32_t rc = read_scal(b, stream);
+  if (rc != SIP_OK) return rc;
+  const double* S = b->h_scal + (size_t)slot * S_COUNT;
+  int cnt = (int)S[S_K] - 1;
+  if (S[S_STATE] == 1.0) cnt = (int)S[S_ITERS];
+  cnt = std::min(cnt, std::min(max_n, s.desc.log_cap));
+  *n = cnt;
+  if (cnt <= 0) return SIP_OK;
+  std::vector<double> buf((size_t)cnt * 2 * kMaxUnits);
+  HIP_OK(hipMemcpyAsync(buf.data(), s.desc.log, buf.size() * 8, hipMemcpyDeviceToHost, stream));
+  HIP_OK(hipStreamSynchronize(stream));
+  const int p1 = s.nsets + 1;
+  for (int i = 0; i < cnt; ++i)
+    for (int u = 0; u < p1; ++u) {
+      if (rho) rho[(size_t)i * p1 + u] = buf[(size_t)i * 2 * kMaxUnits + u];
+      if (gamma) gamma[(size_t)i * p1 + u] = buf[(size_t)i * 2 * kMaxUnits + kMaxUnits + u];
+    }
+  return SIP_OK;
+}
+
+int32_t sip_batch_set_tiles(sip_batch* b, int32_t pt_points, int32_t pt_max_items, int32_t thr_points,
+                            int32_t thr_max_items) {
+  if (!b || pt_points < kBlock || thr_points < kBlock || pt_points % kBlock || thr_points % kBlock ||
+      pt_max_items < 1 || thr_max_items < 1)
+    return SIP_EINVAL;
+  b->tiles.pt_base = pt_points;
+  b->tiles.pt_max_items = pt_max_items;
+  b->tiles.thr_base = thr_points;
+  b->tiles.thr_max_items = thr_max_items;
+  b->dirty = true;
+  return SIP_OK;
+}
+
+int32_t sip_batch_items(sip_batch* b, int32_t* npt, int32_t* nthr, int32_t* nsel, int32_t* ninst) {
+  if (!b) return SIP_EINVAL;
+  if (npt) *npt = b->tab.npt;
+  if (nthr) *nthr = b->tab.nthr;
+  if (nsel) *nsel = b->tab.nsel;
+  if (ninst) *ninst = b->tab.ninst;
+  return SIP_OK;
+}
+
+static int32_t run_to_end(sip_batch* b, int32_t chunk, hipStream_t stream) {
+  const int total = b->opts.max_iter;
+  std::vector<int32_t> done(b->max_slots);
+  int ran = 0;
+  while (ran < total) {
+    const int n = std::min(chunk, total - ran);
+    int32_t rc = sip_batch_run(b, n, stream);
+    if (rc != SIP_OK) return rc;
+    ran += n;
+    if (b->opts.stop_every > 0 && ran < total) {
+      rc = sip_batch_poll(b, done.data(), stream);
+      if (rc != SIP_OK) return rc;
+      bool all = true;
+      for (int i = 0; i < b->max_slots; ++i) if (done[i] == 0) all = false;
+      if (all) break;
+    }
+  }
+  return hipStreamSynchronize(stream) == hipSuccess ? SIP_OK : SIP_EHIP;
+}
+
+int32_t sip_project(const sip_grid* g, const sip_set* sets, int32_t nsets, const sip_opts* o, const void* m_dev,
+                    void* x_dev, sip_result* res, void* stream_) {
+  const int32_t vr = validate(g, sets, nsets, o);
+  if (vr != SIP_OK) return vr;
+  hipStream_t stream = (hipStream_t)stream_;
+  const int64_t ws = sip_workspace_bytes(g, sets, nsets, o);
+  sip_batch* b = nullptr;
+  int32_t rc = sip_batch_create(&b, 1, ws, o);
+  if (rc != SIP_OK) return rc;
+  int32_t slot = -1;
+  rc = sip_batch_add(b, g, sets, nsets, m_dev, x_dev, &slot, stream);
+  if (rc == SIP_OK) rc = run_to_end(b, std::min(o->max_iter, o->stop_every > 0 ? 5 * o->stop_every : 25), stream);
+  sip_result r{};
+  if (rc == SIP_OK) rc = sip_batch_remove(b, slot, &r, stream);
+  sip_batch_destroy(b);
+  if (rc != SIP_OK) return rc;
+  if (res) *res = r;
+  return r.status;
+}
+
+int32_t sip_project_batched(int32_t B, const sip_grid* grids, const sip_set* sets_flat, const int32_t* nsets,
+                            const sip_opts* o, const void* const* m_dev, void* const* x_dev, sip_result* res,
+                            int32_t graph_iters, void* stream_) {
+  if (B < 1 || !grids || !nsets || !o || !m_dev || !x_dev) return SIP_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  int64_t total = 0;
+  int64_t off = 0;
+  for (int i = 0; i < B; ++i) {
+    const int64_t ws = sip_workspace_bytes(&grids[i], sets_flat + off, nsets[i], o);
+    if (ws < 0) return SIP_EINVAL;
+    total += ws;
+    off += nsets[i];
+  }
+  sip_batch* b = nullptr;
+  int32_t rc = sip_batch_create(&b, B, total, o);
+  if (rc != SIP_OK) return rc;
+  std::vector<int32_t> slots(B, -1);
+  off = 0;
+  for (int i = 0; i < B && rc == SIP_OK; ++i) {
+    rc = sip_batch_add(b, &grids[i], sets_flat + off, nsets[i], m_dev[i], x_dev[i], &slots[i], stream);
+    off += nsets[i];
+  }
+  if (rc == SIP_OK) rc = run_to_end(b, graph_iters > 0 ? graph_iters : 25, stream);
+  int32_t first_bad = SIP_OK;
+  if (rc == SIP_OK) {
+    for (int i = 0; i < B; ++i) {
+      sip_result r{};
+      rc = sip_batch_result(b, slots[i], &r, stream);
+      if (rc != SIP_OK) break;
+      if (res) res[i] = r;
+      if (r.status != SIP_OK && first_bad == SIP_OK) first_bad = r.status;
+    }
+  }
+  sip_batch_destroy(b);
+  return rc != SIP_OK ? rc : first_bad;
+}
+
+}  // extern "C"

@@ -1,0 +1,152 @@
+// Internal layout shared by the gfx950 kernels and the host engine of
+// libsip.  Nothing here crosses the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sip.h"
+
+namespace sip {
+
+constexpr int kBlock = 256;                 // threads per work-group (4 wave64)
+constexpr int kMaxUnits = SIP_MAX_SETS + 1; // p sets + the identity block
+constexpr int kNB = 2048;                   // buckets of a radix digit (11 bits)
+constexpr int kMaxHist = 9;                 // x-history slots (evol_hist <= 8)
+// Per point-item partial sums written by the projection kernel: 8 per unit
+// (6 adapt dots + 2 feasibility sums) then the evolution sums.
+constexpr int kUnitParts = 8;
+constexpr int kEvolOff = kUnitParts * kMaxUnits;
+constexpr int kProjParts = kEvolOff + 16;
+constexpr int kThrParts = 8;                // per threshold item
+
+// Scalar block of one instance (doubles).  Writers: the host at admission,
+// k_finish at the end of an iteration, the designated leader block of the CG
+// kernels (only slots no other block of the same launch reads).
+enum Scal : int {
+  S_RHO = 0,                    // [kMaxUnits]
+  S_GAMMA = S_RHO + kMaxUnits,  // [kMaxUnits]
+  S_C0 = S_GAMMA + kMaxUnits,   // stencil scalar of the identity part
+  S_CAX,                        // [3] stencil scalars per axis (rho / h^2 sums)
+  S_RR = S_CAX + 3,             // [2] r^T r of the current CG step, by step parity
+  S_DONE = S_RR + 2,            // [2] CG finished flags, by step parity
+  S_RR0 = S_DONE + 2,           // r^T r of the warm start
+  S_CGTOT,                      // CG steps run so far
+  S_K,                          // iteration counter k (1-based)
+  S_STATE,                      // 0 running, 1 converged, 2 reached max_iter
+  S_ERR,                        // 0 or a negative sip_status
+  S_HAVE_SNAP,                  // adapt-rho-gamma holds a k0 snapshot
+  S_REVOL,                      // last r_evol (-1: never evaluated)
+  S_ITERS,                      // iterations completed
+  S_RFEAS,                      // [SIP_MAX_SETS] last r_feas (-1: never)
+  S_COUNT = S_RFEAS + SIP_MAX_SETS + 4
+};
+
+enum SelMode : int { SEL_PROJECT = 0, SEL_INSIDE = 1, SEL_ZERO = 2, SEL_ALL = 3 };
+
+// Selection state of one pipeline (a threshold set's w = x-bar - v/rho, or
+// on stopping-test iterations its s = A x).  Keys are the IEEE bit patterns
+// of |value|; digits are resolved from the most significant end.
+struct SelState {
+  unsigned long long prefix;    // resolved high key bits (in place)
+  unsigned long long c_above;   // elements with key above the resolved prefix range
+  unsigned long long tkey;      // cardinality: key of the k-th largest magnitude
+  unsigned long long keep_ties; // cardinality: how many entries equal to tkey to keep
+  unsigned long long ties;      // cardinality: entries equal to tkey
+  unsigned long long ncand;     // candidates appended by the refine pass
+  double s_above;               // sum of the values above the resolved range
+  double theta;                 // l1: the soft threshold
+  double tk;                    // cardinality: value of the k-th largest magnitude
+  int32_t digit;                // index of the next digit to resolve
+  int32_t mode;                 // SelMode
+  int32_t need_ties;            // cardinality: rank ties by linear index
+  int32_t err;
+};
+
+struct SetDesc {
+  int32_t kind, op, ncomp, thr;   // thr: index among threshold sets or -1
+  int32_t axis[3];                // grid axis of each component (-1: identity)
+  int32_t pad_;
+  double lo, hi, tau;
+  int64_t k, rows;                // rows = M_i
+  void* y; void* v;               // ncomp blocks of N
+  void* vh0; void* v0; void* y0;  // adapt snapshots (ncomp blocks of N)
+  // pipelines: [0] values w (every iteration), [1] values s (stopping test)
+  SelState* sel[2];
+  uint32_t* hcnt[2];
+  double* hsum[2];
+  void* cand[2];                  // candidate keys (u32 or u64), ncomp*N entries
+  int32_t item_begin[2], item_end[2];  // threshold-item range of each pipeline
+};
+
+struct FastDiv {                  // n / d for 0 <= n < 2^31 (Granlund-Montgomery)
+  uint32_t d, magic, shift;
+};
+
+struct InstDesc {
+  int32_t ndim, nsets, active, pad_;
+  int64_t n[3];                   // axis sizes (3D: z, y, x; 2D: z, x, 1)
+  int64_t N;
+  int64_t stride[3];              // element stride of each axis
+  FastDiv div_x, div_y;           // point -> (row, x), row -> (z, y)
+  double hinv[3], h2inv[3];
+  void* m; void* x; void* r; void* p[2];
+  void* xs[2];                    // x snapshots of adapt-rho-gamma (alternating)
+  void* ring;                     // x history for r_evol ((evol_hist + 1) blocks)
+  void* yl; void* vl; void* vh0l; void* v0l; void* y0l;  // identity block p+1
+  double* scal;                   // Scal block
+  double* log;                    // schedule log or null
+  int32_t pt_begin, pt_end;       // point-item range
+  int32_t log_cap, pad2_;
+  SetDesc sets[SIP_MAX_SETS];
+};
+
+struct PtItem {                   // a range of grid points of one instance
+  int32_t inst;
+  int32_t begin, len;
+  int32_t pad_;
+};
+
+struct ThrItem {                  // a range of grid points of one pipeline
+  int32_t inst, set, src, comp_parts;
+  int32_t begin, len;
+};
+
+struct SelItem {                  // one pipeline
+  int32_t inst, set, src, pad_;
+};
+
+struct Opts {                     // options every kernel needs, by value
+  int32_t cg_max, cg_fixed, adapt_every, stop_every, evol_hist, max_iter;
+  double cg_rel2, eps_corr, rho_ratio_max, gamma_max, eps_evol, eps_feas;
+};
+
+// Device work tables and partial-sum buffers of one batch.
+struct Tables {
+  const InstDesc* D;
+  const PtItem* pt; int npt;
+  const ThrItem* thr; int nthr;
+  const SelItem* sel; int nsel;
+  const int32_t* inst; int ninst;
+  double* rr_part; double* pq_part; double* proj_part; double* thrw_part; double* thra_part;
+  uint32_t* tie_part;
+  bool any_card;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  uint32_t s = 0;
+  while ((1ull << s) < d) ++s;
+  f.shift = s;
+  // magic = floor(2^32 (2^s - d) / d) + 1; then n/d = (umulhi(n, magic) + n) >> s
+  f.magic = (uint32_t)(((1ull << 32) * ((1ull << s) - d)) / d + 1);
+  return f;
+}
+
+__host__ __device__ inline uint32_t fastdiv(uint32_t n, const FastDiv& f) {
+  const uint32_t t = (uint32_t)(((uint64_t)n * f.magic) >> 32);
+  return (t + n) >> f.shift;
+}
+
+}  // namespace sip

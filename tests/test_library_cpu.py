@@ -1,0 +1,84 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and its host-only entry points (validation, sizes, option
+defaults) behave.  No GPU call is made."""
+import math
+import os
+import re
+
+import pytest
+
+from paper_1902_09699_amd import sip
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "sip.h")).read()
+    pat = r"^\s*(?:const\s+char\s*\*|int32_t|int64_t)\s+(sip_[a-z_]+)\s*\("
+    return sorted(set(re.findall(pat, text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(sip.LIB_PATH):
+        from paper_1902_09699_amd import build
+        build.build()
+    return sip.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    decl = _declared()
+    assert len(decl) >= 15
+    for name in decl:
+        assert hasattr(L, name), name
+    assert sorted(sip.exported_symbols()) == decl
+
+
+def test_opts_defaults(L):
+    o = sip.make_opts()
+    assert (o.max_iter, o.cg_max, o.adapt_every, o.stop_every, o.evol_hist) == (200, 10, 2, 0, 5)
+    assert (o.rho0, o.gamma0, o.eps_corr, o.gamma_max, o.cg_rel) == (1.0, 1.0, 0.3, 1.999, 0.1)
+    assert (o.eps_evol, o.eps_feas, o.rho_ratio_max) == (1e-2, 1e-3, 100.0)
+
+
+def test_rows(L):
+    assert sip.set_rows((5, 7), {"kind": "bounds", "op": "DZ"}) == 4 * 7
+    assert sip.set_rows((5, 7), {"kind": "bounds", "op": "DX"}) == 5 * 6
+    assert sip.set_rows((5, 7), {"kind": "l1", "op": "GRAD"}) == 4 * 7 + 5 * 6
+    assert sip.set_rows((4, 5, 6), {"kind": "l1", "op": "GRAD"}) == 3 * 30 + 4 * 4 * 6 + 4 * 5 * 5
+    assert sip.set_rows((4, 5, 6), {"kind": "l1", "op": "LAT"}) == 4 * 4 * 6 + 4 * 5 * 5
+    assert sip.set_rows((341, 1361), {"kind": "card", "op": "DX"}) == 463760
+
+
+@pytest.mark.parametrize("shape,sets,ok", [
+    ((8, 8), [{"kind": "bounds", "op": "I", "lo": -1, "hi": 1}], True),
+    ((8, 8), [{"kind": "bounds", "op": "I", "lo": 1, "hi": -1}], False),
+    ((8, 8), [{"kind": "bounds", "op": "DY", "lo": 0, "hi": 1}], False),
+    ((1, 8), [{"kind": "bounds", "op": "DZ", "lo": 0, "hi": 1}], False),
+    ((1, 8), [{"kind": "bounds", "op": "DX", "lo": 0, "hi": 1}], True),
+    ((8, 8), [{"kind": "l1", "op": "GRAD", "tau": -1.0}], False),
+    ((8, 8), [{"kind": "l1", "op": "GRAD", "tau": math.inf}], False),
+    ((8, 8), [{"kind": "card", "op": "DX", "k": 0}], False),
+    ((8, 8), [{"kind": "card", "op": "DX", "k": 56}], True),
+    ((8, 8), [{"kind": "card", "op": "DX", "k": 57}], False),
+    ((8, 8), [{"kind": "bounds", "op": "I", "lo": -1, "hi": 1}] * 17, False),
+    ((8, 8, 8), [{"kind": "bounds", "op": "LAT", "lo": -1, "hi": 1}], True),
+])
+def test_validation(L, shape, sets, ok):
+    assert (sip.validate(shape, sets, sip.make_opts()) == 0) == ok
+
+
+def test_workspace_bytes_exact_and_monotone(L):
+    o = sip.make_opts()
+    a = sip.workspace_bytes((64, 64), [{"kind": "bounds", "op": "I", "lo": -1, "hi": 1}], o)
+    b = sip.workspace_bytes((64, 64), [{"kind": "bounds", "op": "I", "lo": -1, "hi": 1},
+                                       {"kind": "l1", "op": "GRAD", "tau": 1.0}], o)
+    assert a > 0 and b > a and a % 256 == 0 and b % 256 == 0
+    assert sip.workspace_bytes((64, 64), [{"kind": "bounds", "op": "I", "lo": 2, "hi": 1}], o) == -1
+    o64 = sip.make_opts("f64")
+    assert sip.workspace_bytes((64, 64), [{"kind": "bounds", "op": "I", "lo": -1, "hi": 1}], o64) > a
+
+
+def test_strerror(L):
+    assert sip.strerror(0) == "ok"
+    assert "invalid" in sip.strerror(-1)
