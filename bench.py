@@ -1,0 +1,233 @@
+"""Benchmark: PARSDMM grid-points x iterations per second on one MI355X.
+
+One step = one complete projection (state reset from m, then every
+iteration of the PARSDMM listing) of the chosen workload, inputs resident in
+HBM.  Prints one JSON line with the throughput, the roofline of the dominant
+kernel (algorithmic bytes per launch over its HIP-event-timed mean launch
+duration, against the 8 TB/s HBM peak) and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import resource
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = ("layered2d", "smooth2d", "smooth3d", "batched")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="layered2d", choices=WORKLOADS)
+    ap.add_argument("--graph-iters", type=int, default=50)
+    ap.add_argument("--reps", type=int, default=30, help="launches per kernel timing")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle sample budget (0: skip)")
+    ap.add_argument("--batched-count", type=int, default=256)
+    return ap.parse_args()
+
+
+def workload(name, args):
+    from paper_1902_09699_amd import workloads as wl
+    if name == "layered2d":
+        m, sets, field, iters = wl.layered2d_four_sets()
+        desc = "layered 341x1361 f32: box, D_z>=0, l1(D_x), card(D_x); 300 it x 10 CG"
+    elif name == "smooth2d":
+        m, sets, field, iters = wl.smooth2d_box_tv()
+        desc = "smooth 64x64 f64: box, TV ball; 200 it x 10 CG"
+    elif name == "smooth3d":
+        m, sets, field, iters = wl.smooth3d_box_tv_lat()
+        desc = "smooth 200x200x100 f32: box, TV ball, lateral slopes; 200 it x 10 CG"
+    else:
+        raise ValueError(name)
+    m = wl.rounded(m, field)
+    return [(m, wl.finalize(m, sets))], field, iters, desc
+
+
+def batched_workload(args):
+    from paper_1902_09699_amd import workloads as wl
+    out = []
+    for m, sets in wl.batched_instances(args.batched_count):
+        m = wl.rounded(m, "f32")
+        out.append((m, wl.finalize(m, sets)))
+    return out, "f32", 200, f"{args.batched_count} uneven 2D instances (sides U[32,512]), 2-5 sets; 200 it x 10 CG"
+
+
+def rows(shape, s):
+    from paper_1902_09699_amd import workloads as wl
+    return wl.rows_of(shape, s["op"])
+
+
+def algorithmic_bytes(insts, esz):
+    """Compulsory bytes of one launch of each kernel (all instances):
+    CG direction: read r, p, write p (3N); CG update: read x, r, p, write x, r
+    (5N); RHS: read x and every y_i, v_i (identity block included), write r;
+    projection (non-adapt iteration): read x, m, y_i, v_i of the bounds sets
+    and the identity block, write y_i, v_i."""
+    b = {"cg_dir": 0, "cg_upd": 0, "rhs": 0, "proj": 0}
+    for m, sets in insts:
+        N = m.size
+        sum_m = N + sum(rows(m.shape, s) for s in sets)
+        clip = N + sum(rows(m.shape, s) for s in sets if s["kind"] == "bounds")
+        b["cg_dir"] += 3 * N * esz
+        b["cg_upd"] += 5 * N * esz
+        b["rhs"] += (2 * N + 2 * sum_m) * esz
+        b["proj"] += (2 * N + 4 * clip) * esz
+    return b
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("sip_kernels.hip", "sip_internal.h"):
+        with open(os.path.join(ROOT, "paper_1902_09699_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel, wname):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if
+    they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{wname}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(insts, iters_full, budget_s):
+    """The FP64 oracle as it stands, on the first instance, for as many
+    iterations as fit the budget (at least 2)."""
+    from oracle import parsdmm as orc
+    m, sets = insts[0]
+    prob = orc.Problem(m, m.shape, sets)
+    opts = orc.Options(max_iter=iters_full, cg_max=10, cg_fixed=True)
+    st = orc.initial_state(prob, opts)
+    orc.iterate(prob, st, opts)  # first iteration: warm-up, untimed
+    ru0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    done = 0
+    while done < 2 or (time.perf_counter() - t0 < budget_s and st.k <= iters_full):
+        orc.iterate(prob, st, opts)
+        done += 1
+    wall = time.perf_counter() - t0
+    ru1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (ru1.ru_utime - ru0.ru_utime) + (ru1.ru_stime - ru0.ru_stime)
+    cores = max(1, int(round(cpu / wall)))
+    return {"value": m.size * done / wall, "unit": "grid-pts*iters/s", "cores": cores, "kind": "oracle",
+            "sample": f"iterations 2..{done + 1} of the first instance ({m.shape}), FP64 CSR oracle, "
+                      f"{wall:.1f} s wall, {cpu:.1f} s CPU"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1902_09699_amd import sip
+
+    if args.workload == "batched":
+        insts, field, iters, desc = batched_workload(args)
+    else:
+        insts, field, iters, desc = workload(args.workload, args)
+    esz = 8 if field == "f64" else 4
+    dt = torch.float64 if field == "f64" else torch.float32
+    opts = sip.make_opts(field, max_iter=iters, cg_max=10, cg_fixed=1)
+    ms = [torch.tensor(m, dtype=dt, device="cuda") for m, _ in insts]
+    xs = [torch.empty_like(m) for m in ms]
+    arena = sum(sip.workspace_bytes(m.shape, s, opts) for m, s in insts)
+    batch = sip.Batch(len(insts), arena, opts)
+    slots = [batch.add(md, s, xd) for md, (_, s), xd in zip(ms, insts, xs)]
+    assert all(s >= 0 for s in slots)
+    chunk = min(args.graph_iters, iters)
+    n_pts = sum(m.size for m, _ in insts)
+
+    def one_step():
+        for sl, md in zip(slots, ms):
+            batch.reset(sl, md)
+        left = iters
+        while left > 0:
+            n = min(chunk, left)
+            batch.run(n)
+            left -= n
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    results = [batch.result(sl) for sl in slots]
+    assert all(r["status"] == 0 and r["iters"] == iters for r in results), results[:3]
+    value = n_pts * iters * args.steps / wall
+    ms_step = 1e3 * wall / args.steps
+
+    # roofline: time each kernel on its own (HIP events on the launch stream)
+    batch.set_params(slots[0], *batch.get_params(slots[0])[:2], 2, True)
+    for sl in slots[1:]:
+        r_, g_, _, _ = batch.get_params(sl)
+        batch.set_params(sl, r_, g_, 2, True)
+    ab = algorithmic_bytes(insts, esz)
+    ids = {"cg_dir": sip.K_CG_DIR, "cg_upd": sip.K_CG_UPD, "rhs": sip.K_RHS, "proj": sip.K_PROJ}
+    per_iter = {"cg_dir": 10, "cg_upd": 10, "rhs": 1, "proj": 1}
+    kernels = {}
+    for name, kid in ids.items():
+        t_ms = batch.time_kernel(kid, args.reps)
+        kernels[name] = {"ms": t_ms, "GBs": ab[name] / (t_ms * 1e-3) / 1e9, "bytes": ab[name],
+                         "launches_per_iter": per_iter[name]}
+    dom = max(kernels, key=lambda k: kernels[k]["ms"] * kernels[k]["launches_per_iter"])
+    ach = kernels[dom]["GBs"]
+    traffic = traffic_from_profiles(dom, args.workload)
+    roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "bytes_per_launch": ab[dom], "launch_ms": round(kernels[dom]["ms"], 5)}
+    cpu = None
+    if args.cpu_seconds > 0:
+        cpu = cpu_baseline(insts, iters, args.cpu_seconds)
+    line = {
+        "metric": "PARSDMM grid-pts*iters/s",
+        "value": round(value, 1),
+        "unit": "grid-pts*iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": field,
+        "data": "synthetic (seeded generators)",
+        "config": {"workload": desc, "instances": len(insts), "grid_points": n_pts, "iterations": iters,
+                   "cg_steps": 10, "reductions": "f64"},
+        "roofline": roofline,
+        "kernels": {k: {"ms": round(v["ms"], 5), "GBs": round(v["GBs"], 1)} for k, v in kernels.items()},
+        "cpu_baseline": cpu,
+    }
+    if args.workload == "batched":
+        line["instances_per_s"] = round(len(insts) * args.steps / wall, 2)
+    print(json.dumps(line), flush=True)
+    batch.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -208,12 +208,39 @@ int32_t sip_batch_schedule(sip_batch* b, int32_t slot, double* rho, double* gamm
                            int32_t max_n, int32_t* n, void* stream);
 
 /* Work decomposition: grid points per item of the point kernels (RHS, CG,
- * projection) and of the threshold-set kernels, each a multiple of 256 and
- * grown when an instance would need more than max_items items.  Results are
- * bit-identical for any batch composition at fixed tile settings.  Applies
- * from the next sip_batch_run.  Defaults 4096/1024 and 4096/512. */
+ * projection) and of the threshold-set kernels, each a multiple of 1024 (the
+ * item kernels' block size) and grown when an instance would need more than
+ * max_items items.  Results are bit-identical for any batch composition at
+ * fixed tile settings.  Applies from the next sip_batch_run.  Defaults
+ * 2048/512 and 2048/512. */
 int32_t sip_batch_set_tiles(sip_batch* b, int32_t pt_points, int32_t pt_max_items, int32_t thr_points,
                             int32_t thr_max_items);
+
+/* Re-initialise a slot's state from a new m of the same grid (x = m,
+ * y_i = A_i m, v_i = 0, rho0/gamma0, k = 1) without touching the work tables
+ * or captured graphs. */
+int32_t sip_batch_reset(sip_batch* b, int32_t slot, const void* m_dev, void* stream);
+
+/* Kernels that sip_batch_time_kernel can time in isolation. */
+typedef enum {
+  SIP_K_RHS = 0,       /* RHS + residual + r^T r */
+  SIP_K_CG_DIR = 1,    /* CG direction update + p^T C p (step 1) */
+  SIP_K_CG_UPD = 2,    /* CG x / r update + r^T r (step 1) */
+  SIP_K_PROJ = 3,      /* bounds sets + identity block: relax, project, dual update */
+  SIP_K_THR_W = 4,     /* threshold sets: w and the first radix histogram */
+  SIP_K_THR_APPLY = 5  /* threshold sets: apply threshold + dual update */
+} sip_kernel_id;
+
+/* Launch one kernel of the iteration `reps` times on `stream` over the
+ * batch's current work tables, bracketed by HIP events, and return the mean
+ * duration per launch in *avg_ms.  The kernel really runs: the slot states
+ * change (time only after the results you need were read). */
+int32_t sip_batch_time_kernel(sip_batch* b, int32_t kernel, int32_t reps, void* stream, double* avg_ms);
+
+/* Plain device copy of `bytes` (a multiple of 16) from src to dst on
+ * `stream`: the reference kernel for achievable HBM bandwidth and for
+ * calibrating the FETCH_SIZE / WRITE_SIZE counters. */
+int32_t sip_stream_copy(void* dst, const void* src, int64_t bytes, void* stream);
 
 /* Per-kernel launch statistics of the last sip_batch_run: number of work
  * items of each phase (rhs/CG, threshold, selection, instance). */

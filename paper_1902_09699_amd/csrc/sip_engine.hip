@@ -19,6 +19,8 @@ template <typename T> void launch_iteration(hipStream_t st, const Tables& t, con
 template <typename T> void launch_init(hipStream_t st, const InstDesc* D, int inst, int64_t N);
 void launch_zero(hipStream_t st, uint32_t* a, int64_t n);
 void launch_zero(hipStream_t st, double* a, int64_t n);
+template <typename T> void launch_phase(hipStream_t st, const Tables& t, const Opts& o, int phase);
+void launch_copy(hipStream_t st, void* dst, const void* src, int64_t n16);
 
 namespace {
 
@@ -210,11 +212,13 @@ Opts kernel_opts(const sip_opts& o) {
   return k;
 }
 
-// Points per item: a tile of whole 256-point chunks, at least `base`, and
-// few enough items that the per-instance partial reductions stay short.
+constexpr int64_t kItemThreads = 1024;  // block size of the item kernels
+
+// Points per item: whole 1024-point rounds, at least `base`, and few enough
+// items that the per-instance partial reductions stay short.
 int64_t tile_points(int64_t N, int64_t base, int64_t max_items) {
   int64_t t = std::max<int64_t>(base, (N + max_items - 1) / max_items);
-  return (t + kBlock - 1) / kBlock * kBlock;
+  return (t + kItemThreads - 1) / kItemThreads * kItemThreads;
 }
 
 }  // namespace
@@ -233,7 +237,7 @@ struct Slot {
   int64_t N = 0;
 };
 
-struct TileCfg { int64_t pt_base = 4096, pt_max_items = 1024, thr_base = 4096, thr_max_items = 512; };
+struct TileCfg { int64_t pt_base = 2048, pt_max_items = 512, thr_base = 2048, thr_max_items = 512; };
 
 }  // namespace sip
 
@@ -734,9 +738,69 @@ int32_t sip_batch_schedule(sip_batch* b, int32_t slot, double* rho, double* gamm
   return SIP_OK;
 }
 
+int32_t sip_batch_reset(sip_batch* b, int32_t slot, const void* m_dev, void* stream_) {
+  if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used || !m_dev) return SIP_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  Slot& s = b->slots[slot];
+  const size_t esz = b->opts.field == SIP_F64 ? 8 : 4;
+  double S[S_COUNT];
+  initial_scalars(b, s, S);
+  HIP_OK(hipMemcpyAsync(s.desc.m, m_dev, (size_t)s.N * esz, hipMemcpyDeviceToDevice, stream));
+  HIP_OK(hipMemcpyAsync(s.desc.scal, S, sizeof(S), hipMemcpyHostToDevice, stream));
+  for (int i = 0; i < s.nsets; ++i) {
+    const SetDesc& sd = s.desc.sets[i];
+    for (int src = 0; src < 2; ++src) {
+      if (!sd.hcnt[src]) continue;
+      launch_zero(stream, sd.hcnt[src], kNB);
+      launch_zero(stream, sd.hsum[src], kNB);
+    }
+  }
+  if (b->opts.field == SIP_F64) launch_init<double>(stream, b->d_desc, slot, s.N);
+  else launch_init<float>(stream, b->d_desc, slot, s.N);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(stream));
+  return SIP_OK;
+}
+
+int32_t sip_batch_time_kernel(sip_batch* b, int32_t kernel, int32_t reps, void* stream_, double* avg_ms) {
+  if (!b || kernel < SIP_K_RHS || kernel > SIP_K_THR_APPLY || reps < 1 || !avg_ms) return SIP_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  if (b->dirty) {
+    const int32_t rc = rebuild_tables(b, stream);
+    if (rc != SIP_OK) return rc;
+  }
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  for (int w = 0; w < 2; ++w) {  // warm the caches and the code object
+    if (b->opts.field == SIP_F64) launch_phase<double>(stream, b->tab, b->kopts, kernel);
+    else launch_phase<float>(stream, b->tab, b->kopts, kernel);
+  }
+  HIP_OK(hipEventRecord(e0, stream));
+  for (int i = 0; i < reps; ++i) {
+    if (b->opts.field == SIP_F64) launch_phase<double>(stream, b->tab, b->kopts, kernel);
+    else launch_phase<float>(stream, b->tab, b->kopts, kernel);
+  }
+  HIP_OK(hipEventRecord(e1, stream));
+  HIP_OK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_ms = (double)ms / reps;
+  return SIP_OK;
+}
+
+int32_t sip_stream_copy(void* dst, const void* src, int64_t bytes, void* stream_) {
+  if (!dst || !src || bytes < 0 || bytes % 16) return SIP_EINVAL;
+  launch_copy((hipStream_t)stream_, dst, src, bytes / 16);
+  return hipGetLastError() == hipSuccess ? SIP_OK : SIP_EHIP;
+}
+
 int32_t sip_batch_set_tiles(sip_batch* b, int32_t pt_points, int32_t pt_max_items, int32_t thr_points,
                             int32_t thr_max_items) {
-  if (!b || pt_points < kBlock || thr_points < kBlock || pt_points % kBlock || thr_points % kBlock ||
+  if (!b || pt_points < kItemThreads || thr_points < kItemThreads || pt_points % kItemThreads ||
+      thr_points % kItemThreads ||
       pt_max_items < 1 || thr_max_items < 1)
     return SIP_EINVAL;
   b->tiles.pt_base = pt_points;

@@ -17,6 +17,9 @@
 
 namespace sip {
 
+constexpr int kPB = 1024;  // threads per block of the point and threshold-item kernels
+constexpr int kNW = kPB / 64;
+
 // ---------------------------------------------------------------- helpers
 
 __device__ __forceinline__ int xcd_item(int b, int G) {
@@ -30,28 +33,48 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Deterministic block sum of NV doubles; every thread receives the totals.
-template <int NV>
+// Deterministic block sum of NV doubles over NT threads (a fixed butterfly in
+// each wave, then the wave totals in order); every thread gets the totals.
+// lds needs NV * NT / 64 doubles.
+template <int NV, int NT = kBlock>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
+  constexpr int NW = NT / 64;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
 #pragma unroll
   for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
   __syncthreads();
   if (l == 0) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) lds[i * 4 + w] = v[i];
+    for (int i = 0; i < NV; ++i) lds[i * NW + w] = v[i];
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < NV; ++i) v[i] = (lds[i * 4 + 0] + lds[i * 4 + 1]) + (lds[i * 4 + 2] + lds[i * 4 + 3]);
+  for (int i = 0; i < NV; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) t += lds[i * NW + q];
+    v[i] = t;
+  }
   __syncthreads();
 }
 
-__device__ __forceinline__ double reduce_range(const double* parts, int begin, int end, int stride,
-                                               int off, double* lds) {
-  double a[1] = {0.0};
-  for (int i = begin + (int)threadIdx.x; i < end; i += kBlock) a[0] += parts[(size_t)i * stride + off];
-  block_sum<1>(a, lds);
+// Sum of parts[i * stride + off .. + NV) over items i in [begin, end).
+template <int NV, int NT = kBlock>
+__device__ __forceinline__ void reduce_range(const double* __restrict__ parts, int begin, int end, int stride,
+                                             int off, double (&out)[NV], double* lds) {
+#pragma unroll
+  for (int j = 0; j < NV; ++j) out[j] = 0.0;
+  for (int i = begin + (int)threadIdx.x; i < end; i += NT) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) out[j] += parts[(size_t)i * stride + off + j];
+  }
+  block_sum<NV, NT>(out, lds);
+}
+
+template <int NT>
+__device__ __forceinline__ double reduce_one(const double* __restrict__ parts, int begin, int end, double* lds) {
+  double a[1];
+  reduce_range<1, NT>(parts, begin, end, 1, 0, a, lds);
   return a[0];
 }
 
@@ -177,55 +200,83 @@ __global__ __launch_bounds__(kBlock) void k_init(const InstDesc* D, int inst) {
 
 // -------------------------------------------------------- RHS + residual
 
+// Items are processed in rounds of kPB * U points; the U points of a thread
+// are independent, so their loads are issued together (memory-level
+// parallelism), and __restrict__ lets stores trail loads.
+constexpr int kUcg = 4;
+constexpr int kUset = 2;
+
 // b = sum_{i<=p+1} A_i^T (rho_i y_i + v_i);  r = b - C x;  partial r^T r.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_rhs(const InstDesc* D, const PtItem* items, double* rr_part) {
-  __shared__ double lds[16];
+__global__ __launch_bounds__(kPB) void k_rhs(const InstDesc* D, const PtItem* items, double* rr_part) {
+  __shared__ double lds[kNW];
   const int iti = xcd_item(blockIdx.x, gridDim.x);
   const PtItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
   if (!inst_live(S)) return;
   const Geo g(d);
-  const T* x = (const T*)d.x;
-  T* r = (T*)d.r;
-  const T* yl = (const T*)d.yl;
-  const T* vl = (const T*)d.vl;
+  const T* __restrict__ x = (const T*)d.x;
+  T* __restrict__ r = (T*)d.r;
+  const T* __restrict__ yl = (const T*)d.yl;
+  const T* __restrict__ vl = (const T*)d.vl;
   const T rl = (T)S[S_RHO + d.nsets];
   const T c0 = (T)S[S_C0], cz = (T)S[S_CAX + 0], cy = (T)S[S_CAX + 1], cx = (T)S[S_CAX + 2];
   double acc[1] = {0.0};
   const int end = it.begin + it.len;
-  for (int P = it.begin + (int)threadIdx.x; P < end; P += kBlock) {
-    int iz, iy, ix;
-    g.coords(P, iz, iy, ix);
-    T b = rl * yl[P] + vl[P];
+  for (int base = it.begin; base < end; base += kPB * kUset) {
+    int Pu[kUset], iz[kUset], iy[kUset], ix[kUset];
+    T b[kUset];
+#pragma unroll
+    for (int u = 0; u < kUset; ++u) {
+      Pu[u] = base + u * kPB + (int)threadIdx.x;
+      const int P = Pu[u] < end ? Pu[u] : end - 1;
+      g.coords(P, iz[u], iy[u], ix[u]);
+      b[u] = rl * yl[P] + vl[P];
+    }
     for (int si = 0; si < d.nsets; ++si) {
       const SetDesc& s = d.sets[si];
       const T rs = (T)S[S_RHO + si];
       for (int c = 0; c < s.ncomp; ++c) {
-        const T* y = (const T*)s.y + (size_t)c * g.N;
-        const T* v = (const T*)s.v + (size_t)c * g.N;
+        const T* __restrict__ y = (const T*)s.y + (size_t)c * g.N;
+        const T* __restrict__ v = (const T*)s.v + (size_t)c * g.N;
         const int a = s.axis[c];
-        if (a < 0) {
-          b += rs * y[P] + v[P];
-        } else {
-          const int ia = a == 0 ? iz : (a == 1 ? iy : ix);
-          const int na = a == 0 ? g.nz : (a == 1 ? g.ny : g.nx);
-          const int st = a == 0 ? g.sz : (a == 1 ? g.sy : 1);
-          T t = 0;
-          if (ia > 0) t += rs * y[P - st] + v[P - st];
-          if (ia < na - 1) t -= rs * y[P] + v[P];
-          b += t * (T)d.hinv[a];
+        const T hi = (T)d.hinv[a < 0 ? 0 : a];
+#pragma unroll
+        for (int u = 0; u < kUset; ++u) {
+          const int P = Pu[u] < end ? Pu[u] : end - 1;
+          if (a < 0) {
+            b[u] += rs * y[P] + v[P];
+          } else {
+            const int ia = a == 0 ? iz[u] : (a == 1 ? iy[u] : ix[u]);
+            const int na = a == 0 ? g.nz : (a == 1 ? g.ny : g.nx);
+            const int st = a == 0 ? g.sz : (a == 1 ? g.sy : 1);
+            T t = 0;
+            if (ia > 0) t += rs * y[P - st] + v[P - st];
+            if (ia < na - 1) t -= rs * y[P] + v[P];
+            b[u] += t * hi;
+          }
         }
       }
     }
-    const T xc = x[P];
-    const T cxv = apply_C<T>([&](int Q) { return x[Q]; }, xc, P, iz, iy, ix, g, c0, cz, cy, cx);
-    const T rv = b - cxv;
-    r[P] = rv;
-    acc[0] += (double)rv * (double)rv;
+#pragma unroll
+    for (int u = 0; u < kUset; ++u) {
+      if (Pu[u] >= end) continue;
+      const int P = Pu[u];
+      const T xc = x[P];
+      T lz = 0, ly = 0, lx = 0;
+      if (iz[u] > 0) lz += xc - x[P - g.sz];
+      if (iz[u] < g.nz - 1) lz += xc - x[P + g.sz];
+      if (iy[u] > 0) ly += xc - x[P - g.sy];
+      if (iy[u] < g.ny - 1) ly += xc - x[P + g.sy];
+      if (ix[u] > 0) lx += xc - x[P - 1];
+      if (ix[u] < g.nx - 1) lx += xc - x[P + 1];
+      const T rv = b[u] - (c0 * xc + cz * lz + cy * ly + cx * lx);
+      r[P] = rv;
+      acc[0] += (double)rv * (double)rv;
+    }
   }
-  block_sum<1>(acc, lds);
+  block_sum<1, kPB>(acc, lds);
   if (threadIdx.x == 0) rr_part[iti] = acc[0];
 }
 
@@ -234,15 +285,15 @@ __global__ __launch_bounds__(kBlock) void k_rhs(const InstDesc* D, const PtItem*
 // Step j, first half: beta = rr_j / rr_{j-1}; p_j = r + beta p_{j-1} (p_0 = r);
 // partial p_j^T C p_j with C p_j evaluated on the fly (never stored).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_dir(const InstDesc* D, const PtItem* items, int j,
-                                                   const double* rr_part, double* pq_part, Opts o) {
-  __shared__ double lds[16];
+__global__ __launch_bounds__(kPB) void k_cg_dir(const InstDesc* D, const PtItem* items, int j,
+                                                const double* rr_part, double* pq_part, Opts o) {
+  __shared__ double lds[kNW];
   const int iti = xcd_item(blockIdx.x, gridDim.x);
   const PtItem it = items[iti];
   const InstDesc& d = D[it.inst];
   double* S = d.scal;
   if (!inst_live(S)) return;
-  const double rr = reduce_range(rr_part, d.pt_begin, d.pt_end, 1, 0, lds);
+  const double rr = reduce_one<kPB>(rr_part, d.pt_begin, d.pt_end, lds);
   bool done;
   double beta = 0.0;
   if (j == 0) {
@@ -260,50 +311,52 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir(const InstDesc* D, const PtIt
   }
   if (done || bad) return;
   const Geo g(d);
-  const T* r = (const T*)d.r;
-  const T* pin = (const T*)d.p[(j + 1) & 1];
-  T* pout = (T*)d.p[j & 1];
+  const T* __restrict__ r = (const T*)d.r;
+  const T* __restrict__ pin = (const T*)d.p[(j + 1) & 1];
+  T* __restrict__ pout = (T*)d.p[j & 1];
   const T c0 = (T)S[S_C0], cz = (T)S[S_CAX + 0], cy = (T)S[S_CAX + 1], cx = (T)S[S_CAX + 2];
   const T bt = (T)beta;
+  const bool first = j == 0;
   double acc[1] = {0.0};
   const int end = it.begin + it.len;
-  if (j == 0) {
-    for (int P = it.begin + (int)threadIdx.x; P < end; P += kBlock) {
+  for (int base = it.begin; base < end; base += kPB * kUcg) {
+#pragma unroll
+    for (int u = 0; u < kUcg; ++u) {
+      const int P = base + u * kPB + (int)threadIdx.x;
+      if (P >= end) continue;
       int iz, iy, ix;
       g.coords(P, iz, iy, ix);
-      const T pc = r[P];
-      const T q = apply_C<T>([&](int Q) { return r[Q]; }, pc, P, iz, iy, ix, g, c0, cz, cy, cx);
-      pout[P] = pc;
-      acc[0] += (double)pc * (double)q;
-    }
-  } else {
-    for (int P = it.begin + (int)threadIdx.x; P < end; P += kBlock) {
-      int iz, iy, ix;
-      g.coords(P, iz, iy, ix);
-      auto pn = [&](int Q) { return r[Q] + bt * pin[Q]; };
+      auto pn = [&](int Q) { return first ? r[Q] : r[Q] + bt * pin[Q]; };
       const T pc = pn(P);
-      const T q = apply_C<T>(pn, pc, P, iz, iy, ix, g, c0, cz, cy, cx);
+      T lz = 0, ly = 0, lx = 0;
+      if (iz > 0) lz += pc - pn(P - g.sz);
+      if (iz < g.nz - 1) lz += pc - pn(P + g.sz);
+      if (iy > 0) ly += pc - pn(P - g.sy);
+      if (iy < g.ny - 1) ly += pc - pn(P + g.sy);
+      if (ix > 0) lx += pc - pn(P - 1);
+      if (ix < g.nx - 1) lx += pc - pn(P + 1);
+      const T q = c0 * pc + cz * lz + cy * ly + cx * lx;
       pout[P] = pc;
       acc[0] += (double)pc * (double)q;
     }
   }
-  block_sum<1>(acc, lds);
+  block_sum<1, kPB>(acc, lds);
   if (threadIdx.x == 0) pq_part[iti] = acc[0];
 }
 
 // Step j, second half: alpha = rr_j / p^T C p; x += alpha p; r -= alpha C p
 // (C p recomputed from p); partial r^T r.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_upd(const InstDesc* D, const PtItem* items, int j,
-                                                   const double* pq_part, double* rr_part) {
-  __shared__ double lds[16];
+__global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* D, const PtItem* items, int j,
+                                                const double* pq_part, double* rr_part) {
+  __shared__ double lds[kNW];
   const int iti = xcd_item(blockIdx.x, gridDim.x);
   const PtItem it = items[iti];
   const InstDesc& d = D[it.inst];
   double* S = d.scal;
   if (!inst_live(S)) return;
   if (S[S_DONE + (j & 1)] != 0.0) return;
-  const double pq = reduce_range(pq_part, d.pt_begin, d.pt_end, 1, 0, lds);
+  const double pq = reduce_one<kPB>(pq_part, d.pt_begin, d.pt_end, lds);
   if (!(pq > 0.0) || !(pq <= 1.0e300)) {
     if (iti == d.pt_begin && threadIdx.x == 0) S[S_ERR] = (double)SIP_ENUMERIC;
     return;
@@ -311,24 +364,36 @@ __global__ __launch_bounds__(kBlock) void k_cg_upd(const InstDesc* D, const PtIt
   const double alpha = S[S_RR + (j & 1)] / pq;
   if (iti == d.pt_begin && threadIdx.x == 0) S[S_CGTOT] += 1.0;
   const Geo g(d);
-  T* x = (T*)d.x;
-  T* r = (T*)d.r;
-  const T* p = (const T*)d.p[j & 1];
+  T* __restrict__ x = (T*)d.x;
+  T* __restrict__ r = (T*)d.r;
+  const T* __restrict__ p = (const T*)d.p[j & 1];
   const T c0 = (T)S[S_C0], cz = (T)S[S_CAX + 0], cy = (T)S[S_CAX + 1], cx = (T)S[S_CAX + 2];
   const T al = (T)alpha;
   double acc[1] = {0.0};
   const int end = it.begin + it.len;
-  for (int P = it.begin + (int)threadIdx.x; P < end; P += kBlock) {
-    int iz, iy, ix;
-    g.coords(P, iz, iy, ix);
-    const T pc = p[P];
-    const T q = apply_C<T>([&](int Q) { return p[Q]; }, pc, P, iz, iy, ix, g, c0, cz, cy, cx);
-    x[P] = x[P] + al * pc;
-    const T rv = r[P] - al * q;
-    r[P] = rv;
-    acc[0] += (double)rv * (double)rv;
+  for (int base = it.begin; base < end; base += kPB * kUcg) {
+#pragma unroll
+    for (int u = 0; u < kUcg; ++u) {
+      const int P = base + u * kPB + (int)threadIdx.x;
+      if (P >= end) continue;
+      int iz, iy, ix;
+      g.coords(P, iz, iy, ix);
+      const T pc = p[P];
+      T lz = 0, ly = 0, lx = 0;
+      if (iz > 0) lz += pc - p[P - g.sz];
+      if (iz < g.nz - 1) lz += pc - p[P + g.sz];
+      if (iy > 0) ly += pc - p[P - g.sy];
+      if (iy < g.ny - 1) ly += pc - p[P + g.sy];
+      if (ix > 0) lx += pc - p[P - 1];
+      if (ix < g.nx - 1) lx += pc - p[P + 1];
+      const T q = c0 * pc + cz * lz + cy * ly + cx * lx;
+      x[P] = x[P] + al * pc;
+      const T rv = r[P] - al * q;
+      r[P] = rv;
+      acc[0] += (double)rv * (double)rv;
+    }
   }
-  block_sum<1>(acc, lds);
+  block_sum<1, kPB>(acc, lds);
   if (threadIdx.x == 0) rr_part[iti] = acc[0];
 }
 
@@ -341,8 +406,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_upd(const InstDesc* D, const PtIt
 // snapshot; on stopping-test iterations the feasibility sums of s.  Then the
 // x snapshot / x history writes and the r_evol sums.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_proj(const InstDesc* D, const PtItem* items, Opts o, double* parts) {
-  __shared__ double lds[8 * 4];
+__global__ __launch_bounds__(kPB) void k_proj(const InstDesc* D, const PtItem* items, Opts o, double* parts) {
+  __shared__ double lds[8 * kNW];
   const int iti = xcd_item(blockIdx.x, gridDim.x);
   const PtItem it = items[iti];
   const InstDesc& d = D[it.inst];
@@ -354,9 +419,9 @@ __global__ __launch_bounds__(kBlock) void k_proj(const InstDesc* D, const PtItem
   const bool check = is_check_iter(k, o);
   const bool have = S[S_HAVE_SNAP] != 0.0;
   const int call = adapt ? adapt_call(k, o) : 0;
-  const T* x = (const T*)d.x;
-  const T* xr = (const T*)d.xs[(call & 1) ^ 1];
-  const T* m = (const T*)d.m;
+  const T* __restrict__ x = (const T*)d.x;
+  const T* __restrict__ xr = (const T*)d.xs[(call & 1) ^ 1];
+  const T* __restrict__ m = (const T*)d.m;
   const int end = it.begin + it.len;
   double* out = parts + (size_t)iti * kProjParts;
 
@@ -374,61 +439,68 @@ __global__ __launch_bounds__(kBlock) void k_proj(const InstDesc* D, const PtItem
     for (int c = 0; c < ncomp; ++c) {
       const int axis = ident ? -1 : s->axis[c];
       const size_t off = (size_t)c * g.N;
-      T* y = (T*)(ident ? d.yl : s->y) + off;
-      T* v = (T*)(ident ? d.vl : s->v) + off;
-      T* vh0 = (T*)(ident ? d.vh0l : s->vh0) + off;
-      T* v0 = (T*)(ident ? d.v0l : s->v0) + off;
-      T* y0 = (T*)(ident ? d.y0l : s->y0) + off;
-      for (int P = it.begin + (int)threadIdx.x; P < end; P += kBlock) {
-        int iz, iy, ix;
-        g.coords(P, iz, iy, ix);
-        T sv;
-        if (!comp_value<T>(x, P, axis, iz, iy, ix, g, d, sv)) continue;
-        const T yo = y[P], vo = v[P];
-        const T xb = gam * sv + one_m_g * yo;
-        const T w = xb - vo * irho;
-        T yn;
-        if (ident) yn = (m[P] + rho * w) * inv1p;
-        else yn = w < lo ? lo : (w > hi ? hi : w);
-        const T vn = vo + rho * (yn - xb);
-        y[P] = yn;
-        v[P] = vn;
-        if (adapt) {
-          const T vh = vo + rho * (yo - sv);
-          if (have) {
-            T s0;
-            comp_value<T>(xr, P, axis, iz, iy, ix, g, d, s0);
-            const double dh = (double)sv - (double)s0;
-            const double dvh = (double)vh - (double)vh0[P];
-            const double dg = -((double)yn - (double)y0[P]);
-            const double dv = (double)vn - (double)v0[P];
-            acc[0] += dh * dvh; acc[1] += dh * dh; acc[2] += dvh * dvh;
-            acc[3] += dg * dv; acc[4] += dg * dg; acc[5] += dv * dv;
+      T* __restrict__ y = (T*)(ident ? d.yl : s->y) + off;
+      T* __restrict__ v = (T*)(ident ? d.vl : s->v) + off;
+      T* __restrict__ vh0 = (T*)(ident ? d.vh0l : s->vh0) + off;
+      T* __restrict__ v0 = (T*)(ident ? d.v0l : s->v0) + off;
+      T* __restrict__ y0 = (T*)(ident ? d.y0l : s->y0) + off;
+      for (int base = it.begin; base < end; base += kPB * kUset) {
+#pragma unroll
+        for (int uu = 0; uu < kUset; ++uu) {
+          const int P = base + uu * kPB + (int)threadIdx.x;
+          if (P >= end) continue;
+          int iz, iy, ix;
+          g.coords(P, iz, iy, ix);
+          T sv;
+          if (!comp_value<T>(x, P, axis, iz, iy, ix, g, d, sv)) continue;
+          const T yo = y[P], vo = v[P];
+          const T xb = gam * sv + one_m_g * yo;
+          const T w = xb - vo * irho;
+          T yn;
+          if (ident) yn = (m[P] + rho * w) * inv1p;
+          else yn = w < lo ? lo : (w > hi ? hi : w);
+          const T vn = vo + rho * (yn - xb);
+          y[P] = yn;
+          v[P] = vn;
+          if (adapt) {
+            const T vh = vo + rho * (yo - sv);
+            if (have) {
+              T s0;
+              comp_value<T>(xr, P, axis, iz, iy, ix, g, d, s0);
+              const double dh = (double)sv - (double)s0;
+              const double dvh = (double)vh - (double)vh0[P];
+              const double dg = -((double)yn - (double)y0[P]);
+              const double dv = (double)vn - (double)v0[P];
+              acc[0] += dh * dvh; acc[1] += dh * dh; acc[2] += dvh * dvh;
+              acc[3] += dg * dv; acc[4] += dg * dg; acc[5] += dv * dv;
+            }
+            vh0[P] = vh;
+            v0[P] = vn;
+            y0[P] = yn;
           }
-          vh0[P] = vh;
-          v0[P] = vn;
-          y0[P] = yn;
-        }
-        if (check && !ident) {
-          const T pc = sv < lo ? lo : (sv > hi ? hi : sv);
-          const double e = (double)sv - (double)pc;
-          acc[6] += e * e;
-          acc[7] += (double)sv * (double)sv;
+          if (check && !ident) {
+            const T pc = sv < lo ? lo : (sv > hi ? hi : sv);
+            const double e = (double)sv - (double)pc;
+            acc[6] += e * e;
+            acc[7] += (double)sv * (double)sv;
+          }
         }
       }
     }
-    block_sum<8>(acc, lds);
-    if (threadIdx.x < 8) out[u * kUnitParts + threadIdx.x] = acc[threadIdx.x];
+    if (adapt || check) {
+      block_sum<8, kPB>(acc, lds);
+      if (threadIdx.x < 8) out[u * kUnitParts + threadIdx.x] = acc[threadIdx.x];
+    }
   }
 
   // x snapshot for adapt-rho-gamma, x history and r_evol sums
   if (adapt || d.ring) {
-    T* xw = (T*)d.xs[call & 1];
-    T* ring = (T*)d.ring;
+    T* __restrict__ xw = (T*)d.xs[call & 1];
+    T* __restrict__ ring = (T*)d.ring;
     const int H = o.evol_hist;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double accx[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int P = it.begin + (int)threadIdx.x; P < end; P += kBlock) {
+    for (int P = it.begin + (int)threadIdx.x; P < end; P += kPB) {
       const T xv = x[P];
       if (adapt) xw[P] = xv;
       if (ring) {
@@ -443,8 +515,8 @@ __global__ __launch_bounds__(kBlock) void k_proj(const InstDesc* D, const PtItem
       }
     }
     if (check) {
-      block_sum<8>(acc, lds);
-      block_sum<8>(accx, lds);
+      block_sum<8, kPB>(acc, lds);
+      block_sum<8, kPB>(accx, lds);
       if (threadIdx.x == 0) {
         out[kEvolOff + 0] = accx[0];
         for (int jj = 1; jj <= H; ++jj) out[kEvolOff + jj] = jj <= 7 ? acc[jj] : accx[jj - 7];
@@ -460,11 +532,11 @@ __global__ __launch_bounds__(kBlock) void k_proj(const InstDesc* D, const PtItem
 // (dh, dvh) pair; radix histogram of the first key digit of |w|.
 // Pipeline 1 (stopping-test iterations): histogram of |s| and ||s||^2.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_thr_w(const InstDesc* D, const ThrItem* items, Opts o, double* parts) {
+__global__ __launch_bounds__(kPB) void k_thr_w(const InstDesc* D, const ThrItem* items, Opts o, double* parts) {
   using KT = KeyT<T>;
   __shared__ uint32_t hc[kNB];
   __shared__ double hs[kNB];
-  __shared__ double lds[8 * 4];
+  __shared__ double lds[8 * kNW];
   const int iti = xcd_item(blockIdx.x, gridDim.x);
   const ThrItem it = items[iti];
   const InstDesc& d = D[it.inst];
@@ -478,7 +550,7 @@ __global__ __launch_bounds__(kBlock) void k_thr_w(const InstDesc* D, const ThrIt
   const int call = adapt ? adapt_call(k, o) : 0;
   const SetDesc& s = d.sets[it.set];
   const bool l1 = s.kind == SIP_SET_L1;
-  for (int b = threadIdx.x; b < kNB; b += kBlock) { hc[b] = 0; hs[b] = 0.0; }
+  for (int b = threadIdx.x; b < kNB; b += kPB) { hc[b] = 0; hs[b] = 0.0; }
   __syncthreads();
   const Geo g(d);
   const T* x = (const T*)d.x;
@@ -496,7 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_thr_w(const InstDesc* D, const ThrIt
     T* y = (T*)s.y + off;
     const T* v = (const T*)s.v + off;
     T* vh0 = (T*)s.vh0 + off;
-    for (int P = it.begin + (int)threadIdx.x; P < end; P += kBlock) {
+    for (int P = it.begin + (int)threadIdx.x; P < end; P += kPB) {
       int iz, iy, ix;
       g.coords(P, iz, iy, ix);
       T sv;
@@ -531,14 +603,14 @@ __global__ __launch_bounds__(kBlock) void k_thr_w(const InstDesc* D, const ThrIt
   __syncthreads();
   uint32_t* gc = s.hcnt[it.src];
   double* gs = s.hsum[it.src];
-  for (int b = threadIdx.x; b < kNB; b += kBlock) {
+  for (int b = threadIdx.x; b < kNB; b += kPB) {
     const uint32_t cnt = hc[b];
     if (cnt) {
       atomicAdd(&gc[b], cnt);
       if (l1) atomicAdd(&gs[b], hs[b]);
     }
   }
-  block_sum<8>(acc, lds);
+  block_sum<8, kPB>(acc, lds);
   if (threadIdx.x < 8) parts[(size_t)iti * kThrParts + threadIdx.x] = acc[threadIdx.x];
 }
 
@@ -561,14 +633,25 @@ __device__ unsigned long long select_digit(SelState& st, const uint32_t* hc, con
   unsigned long long mc = 0;
   double ms = 0.0;
   for (int i = 0; i < per; ++i) { mc += hc[t * per + i]; if (l1) ms += hs[t * per + i]; }
-  lc[t] = mc;
-  ls[t] = ms;
+  // totals of the threads above this one (higher buckets), in a fixed order:
+  // an inclusive suffix scan inside each wave, then the wave totals
+  const int lane = t & 63, wv = t >> 6;
+  unsigned long long ic = mc;
+  double is = ms;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned long long oc = __shfl_down(ic, off, 64);
+    const double os = __shfl_down(is, off, 64);
+    if (lane + off < 64) { ic += oc; is += os; }
+  }
+  unsigned long long above_c = __shfl_down(ic, 1, 64);
+  double above_s = __shfl_down(is, 1, 64);
+  if (lane == 63) { above_c = 0; above_s = 0.0; }
+  if (lane == 0) { lc[wv] = ic; ls[wv] = is; }
   if (t == 0) *lbest = -1;
   __syncthreads();
-  // suffix totals above this thread's range, in a fixed order
-  unsigned long long above_c = 0;
-  double above_s = 0.0;
-  for (int q = kBlock - 1; q > t; --q) { above_c += lc[q]; above_s += ls[q]; }
+  for (int q = kBlock / 64 - 1; q > wv; --q) { above_c += lc[q]; above_s += ls[q]; }
+  __syncthreads();
   // walk own buckets from the top
   unsigned long long rc = st.c_above + above_c;
   double rs = st.s_above + above_s;
@@ -692,13 +775,12 @@ __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* D, const SelIte
 // Refine pass over all values: histogram of digit 1 among entries whose
 // digit 0 matches, and their keys appended to the candidate list.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_thr_refine(const InstDesc* D, const ThrItem* items, Opts o) {
+__global__ __launch_bounds__(kPB) void k_thr_refine(const InstDesc* D, const ThrItem* items, Opts o) {
   using KT = KeyT<T>;
   using K = typename KT::K;
   __shared__ uint32_t hc[kNB];
   __shared__ double hs[kNB];
-  __shared__ unsigned long long wbase[kBlock / 64];
-  const int iti = xcd_item(blockIdx.x, gridDim.x);
+    const int iti = xcd_item(blockIdx.x, gridDim.x);
   const ThrItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
@@ -710,7 +792,7 @@ __global__ __launch_bounds__(kBlock) void k_thr_refine(const InstDesc* D, const 
   if (st.mode != SEL_PROJECT || st.err) return;
   const bool l1 = s.kind == SIP_SET_L1;
   const int nb = 1 << KT::width(1);
-  for (int b = threadIdx.x; b < nb; b += kBlock) { hc[b] = 0; hs[b] = 0.0; }
+  for (int b = threadIdx.x; b < nb; b += kPB) { hc[b] = 0; hs[b] = 0.0; }
   __syncthreads();
   const int sh0 = digit_shift<T>(0), sh1 = digit_shift<T>(1);
   const K want = (K)(st.prefix >> sh0);
@@ -718,12 +800,12 @@ __global__ __launch_bounds__(kBlock) void k_thr_refine(const InstDesc* D, const 
   const T* x = (const T*)d.x;
   K* cand = (K*)s.cand[it.src];
   unsigned long long* ncand = &s.sel[it.src]->ncand;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int end = it.begin + it.len;
   for (int c = 0; c < s.ncomp; ++c) {
     const int axis = s.axis[c];
     const T* y = (const T*)s.y + (size_t)c * g.N;
-    for (int base = it.begin; base < end; base += kBlock) {
+    for (int base = it.begin; base < end; base += kPB) {
       const int P = base + (int)threadIdx.x;
       bool hit = false;
       K key = 0;
@@ -759,19 +841,17 @@ __global__ __launch_bounds__(kBlock) void k_thr_refine(const InstDesc* D, const 
           cand[b0 + __popcll(below)] = key;
         }
       }
-      (void)wv;
     }
   }
   __syncthreads();
   uint32_t* gc = s.hcnt[it.src];
   double* gs = s.hsum[it.src];
-  for (int b = threadIdx.x; b < nb; b += kBlock) {
+  for (int b = threadIdx.x; b < nb; b += kPB) {
     if (hc[b]) {
       atomicAdd(&gc[b], hc[b]);
       if (l1) atomicAdd(&gs[b], hs[b]);
     }
   }
-  (void)wbase;
 }
 
 // Stage 2: digit 1 from the global histogram, then the remaining digits over
@@ -838,7 +918,7 @@ __global__ __launch_bounds__(kBlock) void k_sel2(const InstDesc* D, const SelIte
 // Cardinality ties straddling the cut: count entries equal to the k-th
 // magnitude per (item, component) so the apply pass can rank them by index.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_card_ties(const InstDesc* D, const ThrItem* items, Opts o,
+__global__ __launch_bounds__(kPB) void k_card_ties(const InstDesc* D, const ThrItem* items, Opts o,
                                                       uint32_t* tie_part) {
   using KT = KeyT<T>;
   using K = typename KT::K;
@@ -861,7 +941,7 @@ __global__ __launch_bounds__(kBlock) void k_card_ties(const InstDesc* D, const T
   for (int c = 0; c < s.ncomp; ++c) {
     const T* y = (const T*)s.y + (size_t)c * g.N;
     uint32_t local = 0;
-    for (int P = it.begin + (int)threadIdx.x; P < end; P += kBlock) {
+    for (int P = it.begin + (int)threadIdx.x; P < end; P += kPB) {
       int iz, iy, ix;
       g.coords(P, iz, iy, ix);
       if (!comp_valid(s.axis[c], iz, iy, ix, g)) continue;
@@ -878,12 +958,12 @@ __global__ __launch_bounds__(kBlock) void k_card_ties(const InstDesc* D, const T
 // adapt dots of the (dg, dv) pair and the new y/v snapshots.  Pipeline 1:
 // the feasibility distance ||s - P(s)||^2.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_thr_apply(const InstDesc* D, const ThrItem* items, Opts o, double* parts,
+__global__ __launch_bounds__(kPB) void k_thr_apply(const InstDesc* D, const ThrItem* items, Opts o, double* parts,
                                                       const uint32_t* tie_part) {
   using KT = KeyT<T>;
   using K = typename KT::K;
-  __shared__ double lds[8 * 4];
-  __shared__ uint32_t wsum[kBlock / 64];
+  __shared__ double lds[8 * kNW];
+  __shared__ uint32_t wsum[kNW];
   __shared__ unsigned long long tie_base[3];
   const int iti = xcd_item(blockIdx.x, gridDim.x);
   const ThrItem it = items[iti];
@@ -932,7 +1012,7 @@ __global__ __launch_bounds__(kBlock) void k_thr_apply(const InstDesc* D, const T
     T* y0 = (T*)s.y0 + off;
     T* v0 = (T*)s.v0 + off;
     unsigned long long run = rank_ties ? tie_base[c] : 0ull;
-    for (int base = it.begin; base < end; base += kBlock) {
+    for (int base = it.begin; base < end; base += kPB) {
       const int P = base + (int)threadIdx.x;
       bool valid = false;
       T sv = 0;
@@ -973,7 +1053,7 @@ __global__ __launch_bounds__(kBlock) void k_thr_apply(const InstDesc* D, const T
         const unsigned long long below = mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
         before += (unsigned long long)__popcll(below);
         tie_keep = tie && before < st.keep_ties;
-        for (int q = 0; q < kBlock / 64; ++q) run += wsum[q];
+        for (int q = 0; q < kNW; ++q) run += wsum[q];
         __syncthreads();
       }
       if (!valid) continue;
@@ -1004,7 +1084,7 @@ __global__ __launch_bounds__(kBlock) void k_thr_apply(const InstDesc* D, const T
       }
     }
   }
-  block_sum<8>(acc, lds);
+  block_sum<8, kPB>(acc, lds);
   if (threadIdx.x < 8) parts[(size_t)iti * kThrParts + threadIdx.x] = acc[threadIdx.x];
 }
 
@@ -1028,7 +1108,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* D, const int32_t* insts, Opts o,
                                                    const double* proj_parts, const double* thrw_parts,
                                                    const double* thra_parts) {
-  __shared__ double lds[16];
+  __shared__ double lds[8 * 4];
   __shared__ double dots[kMaxUnits][8];
   __shared__ double evol[16];
   const InstDesc& d = D[insts[blockIdx.x]];
@@ -1043,32 +1123,43 @@ __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* D, const int3
   const bool check = is_check_iter(k, o);
   const int p = d.nsets;
   int err = 0;
-  for (int u = 0; u <= p; ++u) {
-    const bool thr = u < p && d.sets[u].thr >= 0;
-    for (int j = 0; j < 8; ++j) {
-      double v = 0.0;
+  if (adapt || check) {
+    for (int u = 0; u <= p; ++u) {
+      const bool thr = u < p && d.sets[u].thr >= 0;
+      double v[8];
       if (!thr) {
-        if ((adapt && j < 6) || (check && j >= 6))
-          v = reduce_range(proj_parts, d.pt_begin, d.pt_end, kProjParts, u * kUnitParts + j, lds);
+        reduce_range<8>(proj_parts, d.pt_begin, d.pt_end, kProjParts, u * kUnitParts, v, lds);
       } else {
         const SetDesc& s = d.sets[u];
-        if (adapt && j < 3) v = reduce_range(thrw_parts, s.item_begin[0], s.item_end[0], kThrParts, j, lds);
-        else if (adapt && j < 6) v = reduce_range(thra_parts, s.item_begin[0], s.item_end[0], kThrParts, j, lds);
-        else if (check && j == 6) v = reduce_range(thra_parts, s.item_begin[1], s.item_end[1], kThrParts, 6, lds);
-        else if (check && j == 7) v = reduce_range(thrw_parts, s.item_begin[1], s.item_end[1], kThrParts, 7, lds);
+        double a[8], b[8];
+        reduce_range<8>(thrw_parts, s.item_begin[0], s.item_end[0], kThrParts, 0, a, lds);
+        reduce_range<8>(thra_parts, s.item_begin[0], s.item_end[0], kThrParts, 0, b, lds);
+        for (int j = 0; j < 3; ++j) { v[j] = a[j]; v[3 + j] = b[3 + j]; }
+        v[6] = v[7] = 0.0;
+        if (check) {
+          reduce_range<8>(thrw_parts, s.item_begin[1], s.item_end[1], kThrParts, 0, a, lds);
+          reduce_range<8>(thra_parts, s.item_begin[1], s.item_end[1], kThrParts, 0, b, lds);
+          v[6] = b[6];
+          v[7] = a[7];
+        }
       }
-      if (threadIdx.x == 0) dots[u][j] = v;
+      if (threadIdx.x == 0)
+        for (int j = 0; j < 8; ++j) dots[u][j] = v[j];
     }
-    if (thr && threadIdx.x == 0) {
+  }
+  if (threadIdx.x == 0) {
+    for (int u = 0; u < p; ++u) {
+      if (d.sets[u].thr < 0) continue;
       if (d.sets[u].sel[0]->err) err = d.sets[u].sel[0]->err;
       if (check && d.sets[u].sel[1]->err) err = d.sets[u].sel[1]->err;
     }
   }
   if (check && d.ring) {
-    for (int j = 0; j <= o.evol_hist; ++j) {
-      const double v = reduce_range(proj_parts, d.pt_begin, d.pt_end, kProjParts, kEvolOff + j, lds);
-      if (threadIdx.x == 0) evol[j] = v;
-    }
+    double v[8], w[8];
+    reduce_range<8>(proj_parts, d.pt_begin, d.pt_end, kProjParts, kEvolOff, v, lds);
+    reduce_range<8>(proj_parts, d.pt_begin, d.pt_end, kProjParts, kEvolOff + 8, w, lds);
+    if (threadIdx.x == 0)
+      for (int j = 0; j < 16; ++j) evol[j] = j < 8 ? v[j] : w[j - 8];
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
@@ -1161,25 +1252,50 @@ void launch_init(hipStream_t st, const InstDesc* D, int inst, int64_t N) {
 template <typename T>
 void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
   if (t.npt > 0) {
-    k_rhs<T><<<t.npt, kBlock, 0, st>>>(t.D, t.pt, t.rr_part);
+    k_rhs<T><<<t.npt, kPB, 0, st>>>(t.D, t.pt, t.rr_part);
     for (int j = 0; j < o.cg_max; ++j) {
-      k_cg_dir<T><<<t.npt, kBlock, 0, st>>>(t.D, t.pt, j, t.rr_part, t.pq_part, o);
-      k_cg_upd<T><<<t.npt, kBlock, 0, st>>>(t.D, t.pt, j, t.pq_part, t.rr_part);
+      k_cg_dir<T><<<t.npt, kPB, 0, st>>>(t.D, t.pt, j, t.rr_part, t.pq_part, o);
+      k_cg_upd<T><<<t.npt, kPB, 0, st>>>(t.D, t.pt, j, t.pq_part, t.rr_part);
     }
-    k_proj<T><<<t.npt, kBlock, 0, st>>>(t.D, t.pt, o, t.proj_part);
+    k_proj<T><<<t.npt, kPB, 0, st>>>(t.D, t.pt, o, t.proj_part);
   }
   if (t.nthr > 0) {
-    k_thr_w<T><<<t.nthr, kBlock, 0, st>>>(t.D, t.thr, o, t.thrw_part);
+    k_thr_w<T><<<t.nthr, kPB, 0, st>>>(t.D, t.thr, o, t.thrw_part);
     k_sel1<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.sel, o);
-    k_thr_refine<T><<<t.nthr, kBlock, 0, st>>>(t.D, t.thr, o);
+    k_thr_refine<T><<<t.nthr, kPB, 0, st>>>(t.D, t.thr, o);
     k_sel2<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.sel, o);
-    if (t.any_card) k_card_ties<T><<<t.nthr, kBlock, 0, st>>>(t.D, t.thr, o, t.tie_part);
-    k_thr_apply<T><<<t.nthr, kBlock, 0, st>>>(t.D, t.thr, o, t.thra_part, t.tie_part);
+    if (t.any_card) k_card_ties<T><<<t.nthr, kPB, 0, st>>>(t.D, t.thr, o, t.tie_part);
+    k_thr_apply<T><<<t.nthr, kPB, 0, st>>>(t.D, t.thr, o, t.thra_part, t.tie_part);
   }
   if (t.ninst > 0)
     k_finish<T><<<t.ninst, kBlock, 0, st>>>(t.D, t.inst, o, t.proj_part, t.thrw_part, t.thra_part);
 }
 
+// One kernel of the iteration on its own (timing); CG kernels use step 1.
+template <typename T>
+void launch_phase(hipStream_t st, const Tables& t, const Opts& o, int phase) {
+  switch (phase) {
+    case 0: if (t.npt) k_rhs<T><<<t.npt, kPB, 0, st>>>(t.D, t.pt, t.rr_part); break;
+    case 1: if (t.npt) k_cg_dir<T><<<t.npt, kPB, 0, st>>>(t.D, t.pt, 1, t.rr_part, t.pq_part, o); break;
+    case 2: if (t.npt) k_cg_upd<T><<<t.npt, kPB, 0, st>>>(t.D, t.pt, 1, t.pq_part, t.rr_part); break;
+    case 3: if (t.npt) k_proj<T><<<t.npt, kPB, 0, st>>>(t.D, t.pt, o, t.proj_part); break;
+    case 4: if (t.nthr) k_thr_w<T><<<t.nthr, kPB, 0, st>>>(t.D, t.thr, o, t.thrw_part); break;
+    case 5: if (t.nthr) k_thr_apply<T><<<t.nthr, kPB, 0, st>>>(t.D, t.thr, o, t.thra_part, t.tie_part); break;
+    default: break;
+  }
+}
+
+// Streaming copy, 16 bytes per lane per step: the bandwidth reference.
+__global__ __launch_bounds__(kBlock) void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) dst[i] = src[i];
+}
+
+void launch_copy(hipStream_t st, void* dst, const void* src, int64_t n16) {
+  if (n16 > 0) k_copy<<<2048, kBlock, 0, st>>>((const uint4*)src, (uint4*)dst, n16);
+}
+
+template void launch_phase<float>(hipStream_t, const Tables&, const Opts&, int);
+template void launch_phase<double>(hipStream_t, const Tables&, const Opts&, int);
 template void launch_iteration<float>(hipStream_t, const Tables&, const Opts&);
 template void launch_iteration<double>(hipStream_t, const Tables&, const Opts&);
 template void launch_init<float>(hipStream_t, const InstDesc*, int, int64_t);

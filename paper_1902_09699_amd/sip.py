@@ -22,6 +22,7 @@ OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED, EBUDGET = 0, -1, -2, -3, -4, -
 F32, F64 = 0, 1
 OPS = {"I": 0, "DZ": 1, "DY": 2, "DX": 3, "GRAD": 4, "LAT": 5}
 KINDS = {"bounds": 0, "l1": 1, "card": 2}
+K_RHS, K_CG_DIR, K_CG_UPD, K_PROJ, K_THR_W, K_THR_APPLY = range(6)
 FIELD_Y, FIELD_V, FIELD_VHAT0, FIELD_V0, FIELD_Y0, FIELD_R, FIELD_XS0, FIELD_XS1 = range(8)
 
 
@@ -99,6 +100,9 @@ def lib():
         "sip_batch_schedule": (i32, [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_double), i32,
                                      C.POINTER(i32), vp]),
         "sip_batch_set_tiles": (i32, [vp, i32, i32, i32, i32]),
+        "sip_batch_reset": (i32, [vp, i32, vp, vp]),
+        "sip_batch_time_kernel": (i32, [vp, i32, i32, vp, C.POINTER(C.c_double)]),
+        "sip_stream_copy": (i32, [vp, vp, i64, vp]),
         "sip_batch_items": (i32, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
@@ -114,7 +118,7 @@ def exported_symbols():
             "sip_project", "sip_project_batched", "sip_batch_create", "sip_batch_destroy", "sip_batch_add",
             "sip_batch_run", "sip_batch_poll", "sip_batch_remove", "sip_batch_result", "sip_batch_field",
             "sip_batch_get_params", "sip_batch_set_params", "sip_batch_schedule", "sip_batch_set_tiles",
-            "sip_batch_items"]
+            "sip_batch_items", "sip_batch_reset", "sip_batch_time_kernel", "sip_stream_copy"]
 
 
 def strerror(status: int) -> str:
@@ -366,14 +370,33 @@ class Batch:
         cnt = n.value
         return (np.array(rho[:cnt * p1]).reshape(cnt, p1), np.array(gam[:cnt * p1]).reshape(cnt, p1))
 
-    def set_tiles(self, pt_points=4096, pt_max_items=1024, thr_points=4096, thr_max_items=512):
+    def set_tiles(self, pt_points=2048, pt_max_items=512, thr_points=2048, thr_max_items=512):
         check(lib().sip_batch_set_tiles(self.h, int(pt_points), int(pt_max_items), int(thr_points),
                                         int(thr_max_items)), "sip_batch_set_tiles")
+
+    def reset(self, slot, m, stream=None):
+        _check_tensor(m, m.numel(), self.opts, "m")
+        check(lib().sip_batch_reset(self.h, int(slot), C.c_void_p(m.data_ptr()), _stream_ptr(stream)),
+              "sip_batch_reset")
+
+    def time_kernel(self, kernel, reps=20, stream=None) -> float:
+        """Mean duration (ms) of one launch of an iteration kernel (HIP events)."""
+        ms = C.c_double()
+        check(lib().sip_batch_time_kernel(self.h, int(kernel), int(reps), _stream_ptr(stream), C.byref(ms)),
+              "sip_batch_time_kernel")
+        return ms.value
 
     def items(self):
         a, b, c, d = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         check(lib().sip_batch_items(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)), "sip_batch_items")
         return a.value, b.value, c.value, d.value
+
+
+def stream_copy(dst, src, stream=None):
+    """dst <- src with the library's plain copy kernel (bandwidth reference)."""
+    nbytes = src.numel() * src.element_size()
+    check(lib().sip_stream_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes,
+                                _stream_ptr(stream)), "sip_stream_copy")
 
 
 _hip = None

@@ -83,7 +83,7 @@ def make_case(kind, seed=0):
 class Slot:
     """One device instance in a fresh batch, with helpers to read its state."""
 
-    def __init__(self, m, sets, field, opts_kw, tiles=(256, 1024, 256, 512)):
+    def __init__(self, m, sets, field, opts_kw, tiles=(1024, 1024, 1024, 512)):
         import torch
         self.shape = m.shape
         self.sets = sets

