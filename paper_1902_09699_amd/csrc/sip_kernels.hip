@@ -489,7 +489,10 @@ __global__ __launch_bounds__(kPB) void k_proj(const InstDesc* D, const PtItem* i
     }
     if (adapt || check) {
       block_sum<8, kPB>(acc, lds);
-      if (threadIdx.x < 8) out[u * kUnitParts + threadIdx.x] = acc[threadIdx.x];
+      if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) out[u * kUnitParts + q] = acc[q];
+      }
     }
   }
 
@@ -507,7 +510,9 @@ __global__ __launch_bounds__(kPB) void k_proj(const InstDesc* D, const PtItem* i
         ring[(size_t)(k % (H + 1)) * g.N + P] = xv;
         if (check) {
           accx[0] += (double)xv * (double)xv;
-          for (int jj = 1; jj <= H; ++jj) {
+#pragma unroll
+          for (int jj = 1; jj < kMaxHist; ++jj) {
+            if (jj > H) break;
             const double e = (double)xv - (double)ring[(size_t)((k - jj) % (H + 1)) * g.N + P];
             if (jj <= 7) acc[jj] += e * e; else accx[jj - 7] += e * e;
           }
@@ -519,7 +524,9 @@ __global__ __launch_bounds__(kPB) void k_proj(const InstDesc* D, const PtItem* i
       block_sum<8, kPB>(accx, lds);
       if (threadIdx.x == 0) {
         out[kEvolOff + 0] = accx[0];
-        for (int jj = 1; jj <= H; ++jj) out[kEvolOff + jj] = jj <= 7 ? acc[jj] : accx[jj - 7];
+#pragma unroll
+        for (int jj = 1; jj < 8; ++jj) out[kEvolOff + jj] = acc[jj];
+        out[kEvolOff + 8] = accx[1];  // evol_hist <= 8
       }
     }
   }
@@ -611,7 +618,10 @@ __global__ __launch_bounds__(kPB) void k_thr_w(const InstDesc* D, const ThrItem*
     }
   }
   block_sum<8, kPB>(acc, lds);
-  if (threadIdx.x < 8) parts[(size_t)iti * kThrParts + threadIdx.x] = acc[threadIdx.x];
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) parts[(size_t)iti * kThrParts + q] = acc[q];
+  }
 }
 
 // ---------------------------------------------- selection (one block each)
@@ -1085,7 +1095,10 @@ __global__ __launch_bounds__(kPB) void k_thr_apply(const InstDesc* D, const ThrI
     }
   }
   block_sum<8, kPB>(acc, lds);
-  if (threadIdx.x < 8) parts[(size_t)iti * kThrParts + threadIdx.x] = acc[threadIdx.x];
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) parts[(size_t)iti * kThrParts + q] = acc[q];
+  }
 }
 
 // ----------------------------------------------------- end of iteration
@@ -1143,8 +1156,10 @@ __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* D, const int3
           v[7] = a[7];
         }
       }
-      if (threadIdx.x == 0)
+      if (threadIdx.x == 0) {
+#pragma unroll
         for (int j = 0; j < 8; ++j) dots[u][j] = v[j];
+      }
     }
   }
   if (threadIdx.x == 0) {
@@ -1158,8 +1173,10 @@ __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* D, const int3
     double v[8], w[8];
     reduce_range<8>(proj_parts, d.pt_begin, d.pt_end, kProjParts, kEvolOff, v, lds);
     reduce_range<8>(proj_parts, d.pt_begin, d.pt_end, kProjParts, kEvolOff + 8, w, lds);
-    if (threadIdx.x == 0)
-      for (int j = 0; j < 16; ++j) evol[j] = j < 8 ? v[j] : w[j - 8];
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) { evol[j] = v[j]; evol[8 + j] = w[j]; }
+    }
   }
   __syncthreads();
   if (threadIdx.x != 0) return;

@@ -64,9 +64,12 @@ def test_step_parity(kind, field):
                 sup_g, sup_o = yg != 0, yo != 0
                 assert np.array_equal(sup_g[mask], sup_o[mask]), (it, i, "card support")
                 yg, yo, vg, vo = yg[mask], yo[mask], vg[mask], vo[mask]
-            ey = rel(yg, yo)
-            # v is a difference of nearby quantities; compare against the scale of y as well
-            ev = np.linalg.norm(vg - vo) / max(np.linalg.norm(vo), np.linalg.norm(yo), 1e-30)
+            # the projection is nonexpansive: an error in its input w moves y by no
+            # more, so y and v are measured against the scale of w as well
+            wo = st.w_last[i][mask] if (i < len(sets) and sets[i]["kind"] == "card") else st.w_last[i]
+            scale = max(np.linalg.norm(yo), np.linalg.norm(wo), 1e-30)
+            ey = np.linalg.norm(yg - yo) / scale
+            ev = np.linalg.norm(vg - vo) / max(np.linalg.norm(vo), scale)
             worst = max(worst, ey, ev)
             assert ey <= tol, (it, i, "y", ey)
             assert ev <= 10 * tol, (it, i, "v", ev)
@@ -190,7 +193,6 @@ EDGE_CASES = {
     "l1_ball_contains_w": ((6, 7), [{"kind": "l1", "op": "GRAD", "tau": 1e6}]),
     "l1_tau_zero": ((6, 7), [{"kind": "l1", "op": "DZ", "tau": 0.0}]),
     "card_k_equals_rows": ((5, 8), [{"kind": "card", "op": "DX", "k": 35}, {"kind": "bounds", "op": "I", "lo": -1, "hi": 1}]),
-    "card_many_ties": ((8, 9), [{"kind": "card", "op": "I", "k": 20}]),
     "thin_3d_2x2x2": ((2, 2, 2), [{"kind": "l1", "op": "GRAD", "tau": 0.5}, {"kind": "bounds", "op": "LAT", "lo": -0.1, "hi": 0.1}]),
     "one_set_box_only": ((33, 31), [{"kind": "bounds", "op": "I", "lo": -0.1, "hi": 0.2}]),
     "no_sets": ((5, 6), []),
@@ -202,8 +204,6 @@ def test_edge_cases_f64(name):
     shape, sets = EDGE_CASES[name]
     rng = np.random.default_rng(abs(hash(name)) % 1000)
     m = rng.standard_normal(shape)
-    if name == "card_many_ties":
-        m = rng.integers(-3, 4, size=shape).astype(np.float64)
     iters = 20
     print(f"\n[edge] {name}", flush=True)
     sl = Slot(m, sets, "f64", dict(max_iter=iters, cg_max=10, cg_fixed=1))
@@ -213,4 +213,36 @@ def test_edge_cases_f64(name):
     err = rel(sl.x(), xo)
     print(f"[edge] {name}: rel err {err:.2e}", flush=True)
     assert res["status"] == 0
-    assert err <= 1e-9
+    if name == "one_set_box_only":
+        # the iterate reaches clip(m) exactly within a few iterations; after
+        # that the adapt dots are rounding noise on both sides, so compare both
+        # to the closed form instead
+        np.testing.assert_allclose(sl.x(), np.clip(m, -0.1, 0.2).ravel(), atol=1e-8)
+        np.testing.assert_allclose(xo.ravel(), np.clip(m, -0.1, 0.2).ravel(), atol=1e-8)
+    else:
+        assert err <= 1e-9
+
+
+@pytest.mark.parametrize("field", ["f64", "f32"])
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_card_exact_ties_lockstep(field, seed):
+    """Integer-valued m: many entries share the k-th magnitude exactly.  With
+    identical inputs (lockstep) the kept support, ties broken toward the lower
+    linear index, must be identical.  (Free-running, 1-ulp rounding
+    differences would break such exact ties differently on each side of a
+    non-convex set, so the comparison is per step.)"""
+    rng = np.random.default_rng(seed)
+    m = rng.integers(-3, 4, size=(8, 9)).astype(np.float64)
+    sets = [{"kind": "card", "op": "I", "k": 20}, {"kind": "card", "op": "GRAD", "k": 33}]
+    sl = Slot(m, sets, field, dict(max_iter=20, cg_max=10, cg_fixed=1))
+    prob = orc.Problem(m, m.shape, sets)
+    oo = orc.Options(max_iter=20, cg_max=10, cg_fixed=True)
+    st = orc.initial_state(prob, oo)
+    for it in range(6):
+        sync_oracle(sl, prob, st)
+        orc.iterate(prob, st, oo)
+        sl.batch.run(1)
+        for i in range(2):
+            yg = sl.arr(sip.FIELD_Y, i)
+            assert np.array_equal(yg != 0, st.y[i] != 0), (it, i)
+            assert (yg != 0).sum() <= sets[i]["k"]
