@@ -34,8 +34,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Deterministic block sum of NV doubles over NT threads (a fixed butterfly in
-// each wave, then the wave totals in order); every thread gets the totals.
-// lds needs NV * NT / 64 doubles.
+// each wave, then the wave totals in order by one thread per value); every
+// thread gets the totals.  lds needs lds_sum<NV, NT>() doubles.
+template <int NV, int NT = kBlock>
+constexpr int lds_sum() { return NV * (NT / 64 + 1); }
+
 template <int NV, int NT = kBlock>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
   constexpr int NW = NT / 64;
@@ -48,13 +51,14 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
     for (int i = 0; i < NV; ++i) lds[i * NW + w] = v[i];
   }
   __syncthreads();
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
+  if (threadIdx.x < NV) {
     double t = 0.0;
-#pragma unroll
-    for (int q = 0; q < NW; ++q) t += lds[i * NW + q];
-    v[i] = t;
+    for (int q = 0; q < NW; ++q) t += lds[threadIdx.x * NW + q];
+    lds[NV * NW + threadIdx.x] = t;
   }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = lds[NV * NW + i];
   __syncthreads();
 }
 
@@ -209,7 +213,7 @@ constexpr int kUset = 2;
 // b = sum_{i<=p+1} A_i^T (rho_i y_i + v_i);  r = b - C x;  partial r^T r.
 template <typename T>
 __global__ __launch_bounds__(kPB) void k_rhs(const InstDesc* D, const PtItem* items, double* rr_part) {
-  __shared__ double lds[kNW];
+  __shared__ double lds[lds_sum<1, kPB>()];
   const int iti = xcd_item(blockIdx.x, gridDim.x);
   const PtItem it = items[iti];
   const InstDesc& d = D[it.inst];
@@ -287,7 +291,7 @@ __global__ __launch_bounds__(kPB) void k_rhs(const InstDesc* D, const PtItem* it
 template <typename T>
 __global__ __launch_bounds__(kPB) void k_cg_dir(const InstDesc* D, const PtItem* items, int j,
                                                 const double* rr_part, double* pq_part, Opts o) {
-  __shared__ double lds[kNW];
+  __shared__ double lds[lds_sum<1, kPB>()];
   const int iti = xcd_item(blockIdx.x, gridDim.x);
   const PtItem it = items[iti];
   const InstDesc& d = D[it.inst];
@@ -349,7 +353,7 @@ __global__ __launch_bounds__(kPB) void k_cg_dir(const InstDesc* D, const PtItem*
 template <typename T>
 __global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* D, const PtItem* items, int j,
                                                 const double* pq_part, double* rr_part) {
-  __shared__ double lds[kNW];
+  __shared__ double lds[lds_sum<1, kPB>()];
   const int iti = xcd_item(blockIdx.x, gridDim.x);
   const PtItem it = items[iti];
   const InstDesc& d = D[it.inst];
@@ -407,7 +411,7 @@ __global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* D, const PtItem*
 // x snapshot / x history writes and the r_evol sums.
 template <typename T>
 __global__ __launch_bounds__(kPB) void k_proj(const InstDesc* D, const PtItem* items, Opts o, double* parts) {
-  __shared__ double lds[8 * kNW];
+  __shared__ double lds[lds_sum<8, kPB>()];
   const int iti = xcd_item(blockIdx.x, gridDim.x);
   const PtItem it = items[iti];
   const InstDesc& d = D[it.inst];
@@ -543,7 +547,7 @@ __global__ __launch_bounds__(kPB) void k_thr_w(const InstDesc* D, const ThrItem*
   using KT = KeyT<T>;
   __shared__ uint32_t hc[kNB];
   __shared__ double hs[kNB];
-  __shared__ double lds[8 * kNW];
+  __shared__ double lds[lds_sum<8, kPB>()];
   const int iti = xcd_item(blockIdx.x, gridDim.x);
   const ThrItem it = items[iti];
   const InstDesc& d = D[it.inst];
@@ -736,7 +740,7 @@ __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* D, const SelIte
   __shared__ unsigned long long lc[kBlock];
   __shared__ double ls[kBlock];
   __shared__ int lbest;
-  __shared__ double lds[8];
+  __shared__ double lds[lds_sum<2>()];
   __shared__ SelState st;
   const SelItem si = items[blockIdx.x];
   const InstDesc& d = D[si.inst];
@@ -972,7 +976,7 @@ __global__ __launch_bounds__(kPB) void k_thr_apply(const InstDesc* D, const ThrI
                                                       const uint32_t* tie_part) {
   using KT = KeyT<T>;
   using K = typename KT::K;
-  __shared__ double lds[8 * kNW];
+  __shared__ double lds[lds_sum<8, kPB>()];
   __shared__ uint32_t wsum[kNW];
   __shared__ unsigned long long tie_base[3];
   const int iti = xcd_item(blockIdx.x, gridDim.x);
@@ -1121,7 +1125,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* D, const int32_t* insts, Opts o,
                                                    const double* proj_parts, const double* thrw_parts,
                                                    const double* thra_parts) {
-  __shared__ double lds[8 * 4];
+  __shared__ double lds[lds_sum<8>()];
   __shared__ double dots[kMaxUnits][8];
   __shared__ double evol[16];
   const InstDesc& d = D[insts[blockIdx.x]];

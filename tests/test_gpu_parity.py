@@ -66,8 +66,13 @@ def test_step_parity(kind, field):
                 yg, yo, vg, vo = yg[mask], yo[mask], vg[mask], vo[mask]
             # the projection is nonexpansive: an error in its input w moves y by no
             # more, so y and v are measured against the scale of w as well
+            # float32 rounding of x reaches s = A_i x amplified by ||A_i||
+            # (at most 2 sqrt(components) / h for the difference operators)
             wo = st.w_last[i][mask] if (i < len(sets) and sets[i]["kind"] == "card") else st.w_last[i]
-            scale = max(np.linalg.norm(yo), np.linalg.norm(wo), 1e-30)
+            op = "I" if i == len(sets) else sets[i]["op"]
+            ncomp = {"I": 1, "DZ": 1, "DY": 1, "DX": 1, "GRAD": m.ndim, "LAT": m.ndim - 1}[op]
+            anorm = 1.0 if op == "I" else 2.0 * math.sqrt(ncomp)
+            scale = max(np.linalg.norm(yo), np.linalg.norm(wo), anorm * np.linalg.norm(st.x), 1e-30)
             ey = np.linalg.norm(yg - yo) / scale
             ev = np.linalg.norm(vg - vo) / max(np.linalg.norm(vo), scale)
             worst = max(worst, ey, ev)
