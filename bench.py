@@ -37,6 +37,7 @@ def parse():
     ap.add_argument("--reps", type=int, default=30, help="launches per kernel timing")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle sample budget (0: skip)")
     ap.add_argument("--batched-count", type=int, default=256)
+    ap.add_argument("--copy-mb", type=int, default=1024, help="plain-copy reference size (0: skip)")
     return ap.parse_args()
 
 
@@ -201,6 +202,23 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "bytes_per_launch": ab[dom], "launch_ms": round(kernels[dom]["ms"], 5)}
+    copy = None
+    if args.copy_mb > 0:
+        n = args.copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            sip.stream_copy(dst, src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        reps = 10
+        for _ in range(reps):
+            sip.stream_copy(dst, src)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / reps
+        copy = {"bytes_moved": 2 * n * 4, "ms": round(t, 4), "GBs": round(2 * n * 4 / (t * 1e-3) / 1e9, 1)}
+        del src, dst
     cpu = None
     if args.cpu_seconds > 0:
         cpu = cpu_baseline(insts, iters, args.cpu_seconds)
@@ -222,6 +240,7 @@ def main():
         "roofline": roofline,
         "kernels": {k: {"ms": round(v["ms"], 5), "GBs": round(v["GBs"], 1)} for k, v in kernels.items()},
         "cpu_baseline": cpu,
+        "copy_reference": copy,
     }
     if args.workload == "batched":
         line["instances_per_s"] = round(len(insts) * args.steps / wall, 2)

@@ -61,7 +61,13 @@ struct SelState {
   int32_t mode;                 // SelMode
   int32_t need_ties;            // cardinality: rank ties by linear index
   int32_t err;
+  int32_t compact_next;         // the next refine pass also appends candidate keys
+  int32_t final_;               // threshold known; later refine/select passes skip
 };
+
+// A refine pass appends candidate keys only when the bucket it refines holds
+// at most this many entries (a bigger bucket gets another histogram pass).
+constexpr unsigned long long kCandCap = 16384;
 
 struct SetDesc {
   int32_t kind, op, ncomp, thr;   // thr: index among threshold sets or -1

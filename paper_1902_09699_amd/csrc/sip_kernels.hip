@@ -778,23 +778,40 @@ __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* D, const SelIte
     }
   }
   __syncthreads();
+  if (threadIdx.x == 0) { st.final_ = 0; st.compact_next = 0; }
+  __syncthreads();
   if (st.mode == SEL_PROJECT && !st.err) {
-    select_digit<T>(st, hc, hs, kNB, 0, s, l1, lc, ls, &lbest);
-    if (threadIdx.x == 0) st.digit = 1;
+    const unsigned long long cnt = select_digit<T>(st, hc, hs, kNB, 0, s, l1, lc, ls, &lbest);
+    if (threadIdx.x == 0) {
+      st.digit = 1;
+      st.compact_next = cnt <= kCandCap ? 1 : 0;
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) *s.sel[si.src] = st;
 }
 
-// Refine pass over all values: histogram of digit 1 among entries whose
-// digit 0 matches, and their keys appended to the candidate list.
+// Whether refine pass `pass` (0 or 1) appends candidate keys: only if digits
+// remain after the one it histograms, and then when the bucket it refines is
+// small or on the second pass (the select kernel finishes over them).
 template <typename T>
-__global__ __launch_bounds__(kPB) void k_thr_refine(const InstDesc* D, const ThrItem* items, Opts o) {
+__device__ __forceinline__ bool pass_compacts(const SelState& st, int pass) {
+  return st.digit + 1 < KeyT<T>::ndig && (st.compact_next || pass == 1);
+}
+
+// Refine pass over all values: histogram of digit st.digit among entries
+// whose higher digits match the resolved prefix; when the bucket is small
+// (or on the last pass of a long key) their keys go to the candidate list,
+// appended with one atomic per block round.
+template <typename T>
+__global__ __launch_bounds__(kPB) void k_thr_refine(const InstDesc* D, const ThrItem* items, Opts o, int pass) {
   using KT = KeyT<T>;
   using K = typename KT::K;
   __shared__ uint32_t hc[kNB];
   __shared__ double hs[kNB];
-    const int iti = xcd_item(blockIdx.x, gridDim.x);
+  __shared__ uint32_t wcnt[kNW];
+  __shared__ unsigned long long bbase;
+  const int iti = xcd_item(blockIdx.x, gridDim.x);
   const ThrItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
@@ -803,22 +820,24 @@ __global__ __launch_bounds__(kPB) void k_thr_refine(const InstDesc* D, const Thr
   if (it.src == 1 && !is_check_iter(k, o)) return;
   const SetDesc& s = d.sets[it.set];
   const SelState& st = *s.sel[it.src];
-  if (st.mode != SEL_PROJECT || st.err) return;
+  if (st.mode != SEL_PROJECT || st.err || st.final_) return;
+  const int dig = st.digit;
+  const bool compact = pass_compacts<T>(st, pass);
   const bool l1 = s.kind == SIP_SET_L1;
-  const int nb = 1 << KT::width(1);
+  const int nb = 1 << KT::width(dig);
   for (int b = threadIdx.x; b < nb; b += kPB) { hc[b] = 0; hs[b] = 0.0; }
   __syncthreads();
-  const int sh0 = digit_shift<T>(0), sh1 = digit_shift<T>(1);
-  const K want = (K)(st.prefix >> sh0);
+  const int shp = digit_shift<T>(dig - 1), sh = digit_shift<T>(dig);
+  const K want = (K)(st.prefix >> shp);
   const Geo g(d);
-  const T* x = (const T*)d.x;
-  K* cand = (K*)s.cand[it.src];
+  const T* __restrict__ x = (const T*)d.x;
+  K* __restrict__ cand = (K*)s.cand[it.src];
   unsigned long long* ncand = &s.sel[it.src]->ncand;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int end = it.begin + it.len;
   for (int c = 0; c < s.ncomp; ++c) {
     const int axis = s.axis[c];
-    const T* y = (const T*)s.y + (size_t)c * g.N;
+    const T* __restrict__ y = (const T*)s.y + (size_t)c * g.N;
     for (int base = it.begin; base < end; base += kPB) {
       const int P = base + (int)threadIdx.x;
       bool hit = false;
@@ -836,24 +855,32 @@ __global__ __launch_bounds__(kPB) void k_thr_refine(const InstDesc* D, const Thr
         }
         if (valid) {
           key = KT::key(val);
-          hit = (K)(key >> sh0) == want;
+          hit = (K)(key >> shp) == want;
         }
       }
       if (hit) {
-        const int bkt = (int)((key >> sh1) & (K)(nb - 1));
+        const int bkt = (int)((key >> sh) & (K)(nb - 1));
         atomicAdd(&hc[bkt], 1u);
         if (l1) atomicAdd(&hs[bkt], KT::value(key));
       }
-      // wave-aggregated append of the candidate keys
-      const unsigned long long mask = __ballot(hit);
-      if (mask) {
-        unsigned long long b0 = 0;
-        if (lane == 0) b0 = atomicAdd(ncand, (unsigned long long)__popcll(mask));
-        b0 = __shfl(b0, 0, 64);
-        if (hit) {
-          const unsigned long long below = mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
-          cand[b0 + __popcll(below)] = key;
+      if (compact) {
+        // block-aggregated append: wave counts, one atomic for the block
+        const unsigned long long mask = __ballot(hit);
+        if (lane == 0) wcnt[wv] = (uint32_t)__popcll(mask);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          unsigned long long tot = 0;
+          for (int q = 0; q < kNW; ++q) tot += wcnt[q];
+          bbase = tot ? atomicAdd(ncand, tot) : 0ull;
         }
+        __syncthreads();
+        if (hit) {
+          unsigned long long off = bbase;
+          for (int q = 0; q < wv; ++q) off += wcnt[q];
+          const unsigned long long below = mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
+          cand[off + __popcll(below)] = key;
+        }
+        __syncthreads();
       }
     }
   }
@@ -868,11 +895,14 @@ __global__ __launch_bounds__(kPB) void k_thr_refine(const InstDesc* D, const Thr
   }
 }
 
-// Stage 2: digit 1 from the global histogram, then the remaining digits over
-// the candidate list in LDS; computes theta (l1) or the k-th magnitude and
-// the tie bookkeeping (cardinality).
+// Select the digit the refine pass histogrammed (from the global histogram,
+// which is cleared for the next pass).  If that pass appended candidates the
+// remaining digits are resolved over them in LDS; if the digit was the last
+// one the threshold is final; otherwise decide whether the next refine pass
+// appends candidates.  Ends with theta (l1) or the k-th magnitude and the tie
+// bookkeeping (cardinality) once final.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_sel2(const InstDesc* D, const SelItem* items, Opts o) {
+__global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* D, const SelItem* items, Opts o, int pass) {
   using KT = KeyT<T>;
   using K = typename KT::K;
   __shared__ uint32_t hc[kNB];
@@ -890,11 +920,13 @@ __global__ __launch_bounds__(kBlock) void k_sel2(const InstDesc* D, const SelIte
   const SetDesc& s = d.sets[si.set];
   if (threadIdx.x == 0) st = *s.sel[si.src];
   __syncthreads();
-  if (st.mode != SEL_PROJECT || st.err) return;
+  if (st.mode != SEL_PROJECT || st.err || st.final_) return;
   const bool l1 = s.kind == SIP_SET_L1;
+  const bool compacted = pass_compacts<T>(st, pass);
   uint32_t* gc = s.hcnt[si.src];
   double* gs = s.hsum[si.src];
-  int nb = 1 << KT::width(1);
+  int dig = st.digit;
+  int nb = 1 << KT::width(dig);
   for (int b = threadIdx.x; b < nb; b += kBlock) {
     hc[b] = gc[b];
     hs[b] = l1 ? gs[b] : 0.0;
@@ -902,29 +934,38 @@ __global__ __launch_bounds__(kBlock) void k_sel2(const InstDesc* D, const SelIte
     if (l1) gs[b] = 0.0;
   }
   __syncthreads();
-  unsigned long long last = select_digit<T>(st, hc, hs, nb, 1, s, l1, lc, ls, &lbest);
-  const K* cand = (const K*)s.cand[si.src];
-  const unsigned long long ncand = st.ncand;
-  for (int dig = 2; dig < KT::ndig; ++dig) {
-    if (st.err) break;
-    nb = 1 << KT::width(dig);
-    const int shp = digit_shift<T>(dig - 1), sh = digit_shift<T>(dig);
-    const K want = (K)(st.prefix >> shp);
-    for (int b = threadIdx.x; b < nb; b += kBlock) { hc[b] = 0; hs[b] = 0.0; }
-    __syncthreads();
-    for (unsigned long long i = threadIdx.x; i < ncand; i += kBlock) {
-      const K key = cand[i];
-      if ((K)(key >> shp) == want) {
-        const int bkt = (int)((key >> sh) & (K)(nb - 1));
-        atomicAdd(&hc[bkt], 1u);
-        if (l1) atomicAdd(&hs[bkt], KT::value(key));
+  unsigned long long last = select_digit<T>(st, hc, hs, nb, dig, s, l1, lc, ls, &lbest);
+  ++dig;
+  if (compacted) {
+    const K* cand = (const K*)s.cand[si.src];
+    const unsigned long long ncand = st.ncand;
+    for (; dig < KT::ndig; ++dig) {
+      if (st.err) break;
+      nb = 1 << KT::width(dig);
+      const int shp = digit_shift<T>(dig - 1), sh = digit_shift<T>(dig);
+      const K want = (K)(st.prefix >> shp);
+      for (int b = threadIdx.x; b < nb; b += kBlock) { hc[b] = 0; hs[b] = 0.0; }
+      __syncthreads();
+      for (unsigned long long i = threadIdx.x; i < ncand; i += kBlock) {
+        const K key = cand[i];
+        if ((K)(key >> shp) == want) {
+          const int bkt = (int)((key >> sh) & (K)(nb - 1));
+          atomicAdd(&hc[bkt], 1u);
+          if (l1) atomicAdd(&hs[bkt], KT::value(key));
+        }
       }
+      __syncthreads();
+      last = select_digit<T>(st, hc, hs, nb, dig, s, l1, lc, ls, &lbest);
     }
-    __syncthreads();
-    last = select_digit<T>(st, hc, hs, nb, dig, s, l1, lc, ls, &lbest);
   }
   __syncthreads();
-  if (!st.err) finish_selection<T>(st, s, last);
+  if (dig >= KT::ndig) {
+    if (!st.err) finish_selection<T>(st, s, last);
+    if (threadIdx.x == 0) st.final_ = 1;
+  } else if (threadIdx.x == 0) {
+    st.digit = dig;
+    st.compact_next = last <= kCandCap ? 1 : 0;
+  }
   __syncthreads();
   if (threadIdx.x == 0) *s.sel[si.src] = st;
 }
@@ -1283,8 +1324,10 @@ void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
   if (t.nthr > 0) {
     k_thr_w<T><<<t.nthr, kPB, 0, st>>>(t.D, t.thr, o, t.thrw_part);
     k_sel1<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.sel, o);
-    k_thr_refine<T><<<t.nthr, kPB, 0, st>>>(t.D, t.thr, o);
-    k_sel2<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.sel, o);
+    k_thr_refine<T><<<t.nthr, kPB, 0, st>>>(t.D, t.thr, o, 0);
+    k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.sel, o, 0);
+    k_thr_refine<T><<<t.nthr, kPB, 0, st>>>(t.D, t.thr, o, 1);
+    k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.sel, o, 1);
     if (t.any_card) k_card_ties<T><<<t.nthr, kPB, 0, st>>>(t.D, t.thr, o, t.tie_part);
     k_thr_apply<T><<<t.nthr, kPB, 0, st>>>(t.D, t.thr, o, t.thra_part, t.tie_part);
   }

@@ -1,0 +1,65 @@
+"""Summarise a rocprofv3 SQLite output (rocpd) as a short text table:
+per-kernel dispatch counts and mean durations, and, for counter runs, the
+mean value per dispatch of each collected counter for each kernel.
+
+    python -m paper_1902_09699_amd.profile_summary <dir-with-*results.db> [--top N]
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import os
+import sqlite3
+
+
+def _db(path):
+    if os.path.isdir(path):
+        cands = sorted(glob.glob(os.path.join(path, "**", "*results.db"), recursive=True))
+        if not cands:
+            raise FileNotFoundError(f"no *results.db under {path}")
+        path = cands[0]
+    return sqlite3.connect(path)
+
+
+def _short(name: str) -> str:
+    return name.replace("sip::", "").replace("void ", "").split("(")[0]
+
+
+def kernel_table(con, top=20):
+    """top_kernels reports microseconds."""
+    rows = con.execute("select name, total_calls, total_duration, average, percentage from top_kernels").fetchall()
+    out = [f"{'kernel':40s} {'calls':>7s} {'avg_us':>9s} {'total_ms':>10s} {'pct':>6s}"]
+    for name, calls, tot, avg, pct in rows[:top]:
+        out.append(f"{_short(name)[:40]:40s} {calls:7d} {avg:9.2f} {tot / 1e3:10.3f} {pct:6.2f}")
+    return "\n".join(out)
+
+
+def counter_table(con):
+    try:
+        cols = [c[1] for c in con.execute("pragma table_info(counters_collection)")]
+        if not cols or not con.execute("select count(*) from counters_collection").fetchone()[0]:
+            return ""
+    except sqlite3.Error:
+        return ""
+    kcol = "kernel_name" if "kernel_name" in cols else "name"
+    vcol = "value" if "value" in cols else "counter_value"
+    q = (f"select {kcol}, counter_name, avg({vcol}), count(*) from counters_collection "
+         f"group by 1, 2 order by 1, 2")
+    out = [f"{'kernel':40s} {'counter':12s} {'mean/dispatch':>16s} {'dispatches':>10s}"]
+    for name, cname, val, n in con.execute(q):
+        out.append(f"{_short(name)[:40]:40s} {cname:12s} {val:16.1f} {n:10d}")
+    return "\n".join(out)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("path")
+    ap.add_argument("--top", type=int, default=20)
+    a = ap.parse_args()
+    con = _db(a.path)
+    ct = counter_table(con)
+    print(ct if ct else kernel_table(con, a.top))
+
+
+if __name__ == "__main__":
+    main()
