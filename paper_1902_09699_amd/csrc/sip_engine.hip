@@ -260,7 +260,9 @@ struct sip_batch {
   double *d_rr = nullptr, *d_pq = nullptr, *d_proj = nullptr, *d_thrw = nullptr, *d_thra = nullptr;
   uint32_t* d_tie = nullptr;
   int cap_ppt = 0, cap_pthr = 0;   // item capacity of the partial-sum buffers
+  sip::Counts* d_counts = nullptr;
   sip::Tables tab{};
+  int live_items = 0, live_inst = 0;
   bool dirty = true;
   std::map<int, hipGraphExec_t> graphs;
   sip::TileCfg tiles;
@@ -320,18 +322,27 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   }
   // nothing queued may still read the tables or partial buffers replaced below
   HIP_OK(hipStreamSynchronize(stream));
+  // launch sizes are capacities (powers of two): a captured graph stays valid
+  // while the live counts (read by the kernels) change below them
+  auto pow2 = [](int n, int lo) { if (n <= 0) return 0; int c = lo; while (c < n) c <<= 1; return c; };
+  const int lpt = pow2((int)pt.size(), 64), lthr = pow2((int)thr.size(), 64);
+  const int lsel = pow2((int)sel.size(), 8), linst = pow2((int)inst.size(), 8);
+  const bool relaunch = lpt != b->tab.npt || lthr != b->tab.nthr || lsel != b->tab.nsel || linst != b->tab.ninst ||
+                        any_card != b->tab.any_card;
   int32_t rc;
-  const int npt = std::max<int>((int)pt.size(), 1), nthr = std::max<int>((int)thr.size(), 1);
-  if ((rc = ensure(b->d_pt, b->cap_pt, npt, sizeof(PtItem)))) return rc;
-  if ((rc = ensure(b->d_thr, b->cap_thr, nthr, sizeof(ThrItem)))) return rc;
-  if ((rc = ensure(b->d_sel, b->cap_sel, (int)std::max<size_t>(sel.size(), 1), sizeof(SelItem)))) return rc;
-  if ((rc = ensure(b->d_inst, b->cap_inst, (int)std::max<size_t>(inst.size(), 1), sizeof(int32_t)))) return rc;
+  const int old_pt = b->cap_pt, old_thr = b->cap_thr, old_sel = b->cap_sel, old_inst = b->cap_inst;
+  if ((rc = ensure(b->d_pt, b->cap_pt, std::max(lpt, 1), sizeof(PtItem)))) return rc;
+  if ((rc = ensure(b->d_thr, b->cap_thr, std::max(lthr, 1), sizeof(ThrItem)))) return rc;
+  if ((rc = ensure(b->d_sel, b->cap_sel, std::max(lsel, 1), sizeof(SelItem)))) return rc;
+  if ((rc = ensure(b->d_inst, b->cap_inst, std::max(linst, 1), sizeof(int32_t)))) return rc;
+  bool moved = old_pt != b->cap_pt || old_thr != b->cap_thr || old_sel != b->cap_sel || old_inst != b->cap_inst;
   if (b->cap_ppt < b->cap_pt) {
     if (b->d_rr) { HIP_OK(hipFree(b->d_rr)); HIP_OK(hipFree(b->d_pq)); HIP_OK(hipFree(b->d_proj)); }
     HIP_OK(hipMalloc((void**)&b->d_rr, (size_t)b->cap_pt * 8));
     HIP_OK(hipMalloc((void**)&b->d_pq, (size_t)b->cap_pt * 8));
     HIP_OK(hipMalloc((void**)&b->d_proj, (size_t)b->cap_pt * kProjParts * 8));
     b->cap_ppt = b->cap_pt;
+    moved = true;
   }
   if (b->cap_pthr < b->cap_thr) {
     if (b->d_thrw) { HIP_OK(hipFree(b->d_thrw)); HIP_OK(hipFree(b->d_thra)); HIP_OK(hipFree(b->d_tie)); }
@@ -339,7 +350,11 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
     HIP_OK(hipMalloc((void**)&b->d_thra, (size_t)b->cap_thr * kThrParts * 8));
     HIP_OK(hipMalloc((void**)&b->d_tie, (size_t)b->cap_thr * 3 * 4));
     b->cap_pthr = b->cap_thr;
+    moved = true;
   }
+  if (!b->d_counts) HIP_OK(hipMalloc((void**)&b->d_counts, sizeof(Counts)));
+  const Counts counts{(int32_t)pt.size(), (int32_t)thr.size(), (int32_t)sel.size(), (int32_t)inst.size()};
+  HIP_OK(hipMemcpyAsync(b->d_counts, &counts, sizeof(Counts), hipMemcpyHostToDevice, stream));
   if (!pt.empty()) HIP_OK(hipMemcpyAsync(b->d_pt, pt.data(), pt.size() * sizeof(PtItem), hipMemcpyHostToDevice, stream));
   if (!thr.empty()) HIP_OK(hipMemcpyAsync(b->d_thr, thr.data(), thr.size() * sizeof(ThrItem), hipMemcpyHostToDevice, stream));
   if (!sel.empty()) HIP_OK(hipMemcpyAsync(b->d_sel, sel.data(), sel.size() * sizeof(SelItem), hipMemcpyHostToDevice, stream));
@@ -351,14 +366,17 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   HIP_OK(hipStreamSynchronize(stream));
   Tables& t = b->tab;
   t.D = b->d_desc;
-  t.pt = b->d_pt; t.npt = (int)pt.size();
-  t.thr = b->d_thr; t.nthr = (int)thr.size();
-  t.sel = b->d_sel; t.nsel = (int)sel.size();
-  t.inst = b->d_inst; t.ninst = (int)inst.size();
+  t.cnt = b->d_counts;
+  t.pt = b->d_pt; t.npt = lpt;
+  t.thr = b->d_thr; t.nthr = lthr;
+  t.sel = b->d_sel; t.nsel = lsel;
+  t.inst = b->d_inst; t.ninst = linst;
   t.rr_part = b->d_rr; t.pq_part = b->d_pq; t.proj_part = b->d_proj;
   t.thrw_part = b->d_thrw; t.thra_part = b->d_thra; t.tie_part = b->d_tie;
   t.any_card = any_card;
-  drop_graphs(b);
+  b->live_items = (int)pt.size() + (int)thr.size();
+  b->live_inst = (int)inst.size();
+  if (relaunch || moved) drop_graphs(b);
   b->dirty = false;
   return SIP_OK;
 }
@@ -495,7 +513,7 @@ int32_t sip_batch_destroy(sip_batch* b) {
   drop_graphs(b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   void* dev[] = {b->d_desc, b->d_scal, b->d_pt, b->d_thr, b->d_sel, b->d_inst, b->d_rr, b->d_pq,
-                 b->d_proj, b->d_thrw, b->d_thra, b->d_tie};
+                 b->d_proj, b->d_thrw, b->d_thra, b->d_tie, b->d_counts};
   for (void* p : dev) if (p) (void)hipFree(p);
   if (b->h_scal) (void)hipHostFree(b->h_scal);
   delete b;
@@ -601,7 +619,7 @@ int32_t sip_batch_run(sip_batch* b, int32_t iters, void* stream_) {
     const int32_t rc = rebuild_tables(b, stream);
     if (rc != SIP_OK) return rc;
   }
-  if (b->tab.ninst == 0 || iters == 0) return SIP_OK;
+  if (b->live_inst == 0 || iters == 0) return SIP_OK;
   hipGraphExec_t ge;
   const int32_t rc = get_graph(b, iters, ge);
   if (rc != SIP_OK) return rc;
@@ -813,10 +831,12 @@ int32_t sip_batch_set_tiles(sip_batch* b, int32_t pt_points, int32_t pt_max_item
 
 int32_t sip_batch_items(sip_batch* b, int32_t* npt, int32_t* nthr, int32_t* nsel, int32_t* ninst) {
   if (!b) return SIP_EINVAL;
-  if (npt) *npt = b->tab.npt;
-  if (nthr) *nthr = b->tab.nthr;
-  if (nsel) *nsel = b->tab.nsel;
-  if (ninst) *ninst = b->tab.ninst;
+  int32_t c[4] = {0, 0, 0, 0};
+  if (b->d_counts && hipMemcpy(c, b->d_counts, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess) return SIP_EHIP;
+  if (npt) *npt = c[0];
+  if (nthr) *nthr = c[1];
+  if (nsel) *nsel = c[2];
+  if (ninst) *ninst = c[3];
   return SIP_OK;
 }
 

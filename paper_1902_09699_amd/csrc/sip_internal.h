@@ -127,9 +127,16 @@ struct Opts {                     // options every kernel needs, by value
   double cg_rel2, eps_corr, rho_ratio_max, gamma_max, eps_evol, eps_feas;
 };
 
-// Device work tables and partial-sum buffers of one batch.
+// Live item counts of the work tables, read by the kernels from device
+// memory so a captured graph (launched over the table capacities) stays valid
+// when instances are admitted or retired.
+struct Counts { int32_t npt, nthr, nsel, ninst; };
+
+// Device work tables and partial-sum buffers of one batch.  npt, nthr, nsel
+// and ninst are the launch sizes (capacities); cnt holds the live counts.
 struct Tables {
   const InstDesc* D;
+  const Counts* cnt;
   const PtItem* pt; int npt;
   const ThrItem* thr; int nthr;
   const SelItem* sel; int nsel;

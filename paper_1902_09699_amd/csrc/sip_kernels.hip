@@ -212,9 +212,10 @@ constexpr int kUset = 2;
 
 // b = sum_{i<=p+1} A_i^T (rho_i y_i + v_i);  r = b - C x;  partial r^T r.
 template <typename T>
-__global__ __launch_bounds__(kPB) void k_rhs(const InstDesc* D, const PtItem* items, double* rr_part) {
+__global__ __launch_bounds__(kPB) void k_rhs(const InstDesc* D, const Counts* cnt, const PtItem* items, double* rr_part) {
   __shared__ double lds[lds_sum<1, kPB>()];
-  const int iti = xcd_item(blockIdx.x, gridDim.x);
+  if ((int)blockIdx.x >= cnt->npt) return;
+  const int iti = xcd_item(blockIdx.x, cnt->npt);
   const PtItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
@@ -289,10 +290,11 @@ __global__ __launch_bounds__(kPB) void k_rhs(const InstDesc* D, const PtItem* it
 // Step j, first half: beta = rr_j / rr_{j-1}; p_j = r + beta p_{j-1} (p_0 = r);
 // partial p_j^T C p_j with C p_j evaluated on the fly (never stored).
 template <typename T>
-__global__ __launch_bounds__(kPB) void k_cg_dir(const InstDesc* D, const PtItem* items, int j,
+__global__ __launch_bounds__(kPB) void k_cg_dir(const InstDesc* D, const Counts* cnt, const PtItem* items, int j,
                                                 const double* rr_part, double* pq_part, Opts o) {
   __shared__ double lds[lds_sum<1, kPB>()];
-  const int iti = xcd_item(blockIdx.x, gridDim.x);
+  if ((int)blockIdx.x >= cnt->npt) return;
+  const int iti = xcd_item(blockIdx.x, cnt->npt);
   const PtItem it = items[iti];
   const InstDesc& d = D[it.inst];
   double* S = d.scal;
@@ -351,10 +353,11 @@ __global__ __launch_bounds__(kPB) void k_cg_dir(const InstDesc* D, const PtItem*
 // Step j, second half: alpha = rr_j / p^T C p; x += alpha p; r -= alpha C p
 // (C p recomputed from p); partial r^T r.
 template <typename T>
-__global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* D, const PtItem* items, int j,
+__global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* D, const Counts* cnt, const PtItem* items, int j,
                                                 const double* pq_part, double* rr_part) {
   __shared__ double lds[lds_sum<1, kPB>()];
-  const int iti = xcd_item(blockIdx.x, gridDim.x);
+  if ((int)blockIdx.x >= cnt->npt) return;
+  const int iti = xcd_item(blockIdx.x, cnt->npt);
   const PtItem it = items[iti];
   const InstDesc& d = D[it.inst];
   double* S = d.scal;
@@ -410,9 +413,10 @@ __global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* D, const PtItem*
 // snapshot; on stopping-test iterations the feasibility sums of s.  Then the
 // x snapshot / x history writes and the r_evol sums.
 template <typename T>
-__global__ __launch_bounds__(kPB) void k_proj(const InstDesc* D, const PtItem* items, Opts o, double* parts) {
+__global__ __launch_bounds__(kPB) void k_proj(const InstDesc* D, const Counts* cnt, const PtItem* items, Opts o, double* parts) {
   __shared__ double lds[lds_sum<8, kPB>()];
-  const int iti = xcd_item(blockIdx.x, gridDim.x);
+  if ((int)blockIdx.x >= cnt->npt) return;
+  const int iti = xcd_item(blockIdx.x, cnt->npt);
   const PtItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
@@ -543,12 +547,13 @@ __global__ __launch_bounds__(kPB) void k_proj(const InstDesc* D, const PtItem* i
 // (dh, dvh) pair; radix histogram of the first key digit of |w|.
 // Pipeline 1 (stopping-test iterations): histogram of |s| and ||s||^2.
 template <typename T>
-__global__ __launch_bounds__(kPB) void k_thr_w(const InstDesc* D, const ThrItem* items, Opts o, double* parts) {
+__global__ __launch_bounds__(kPB) void k_thr_w(const InstDesc* D, const Counts* cnt, const ThrItem* items, Opts o, double* parts) {
   using KT = KeyT<T>;
   __shared__ uint32_t hc[kNB];
   __shared__ double hs[kNB];
   __shared__ double lds[lds_sum<8, kPB>()];
-  const int iti = xcd_item(blockIdx.x, gridDim.x);
+  if ((int)blockIdx.x >= cnt->nthr) return;
+  const int iti = xcd_item(blockIdx.x, cnt->nthr);
   const ThrItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
@@ -733,7 +738,7 @@ __device__ void finish_selection(SelState& st, const SetDesc& s, unsigned long l
 // Stage 1: totals, mode, first digit.  Clears the global histogram for the
 // refine pass.  The state is worked on in LDS and written back once.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* D, const SelItem* items, Opts o) {
+__global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* D, const Counts* cnt, const SelItem* items, Opts o) {
   using KT = KeyT<T>;
   __shared__ uint32_t hc[kNB];
   __shared__ double hs[kNB];
@@ -742,6 +747,7 @@ __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* D, const SelIte
   __shared__ int lbest;
   __shared__ double lds[lds_sum<2>()];
   __shared__ SelState st;
+  if ((int)blockIdx.x >= cnt->nsel) return;
   const SelItem si = items[blockIdx.x];
   const InstDesc& d = D[si.inst];
   const double* S = d.scal;
@@ -804,14 +810,15 @@ __device__ __forceinline__ bool pass_compacts(const SelState& st, int pass) {
 // (or on the last pass of a long key) their keys go to the candidate list,
 // appended with one atomic per block round.
 template <typename T>
-__global__ __launch_bounds__(kPB) void k_thr_refine(const InstDesc* D, const ThrItem* items, Opts o, int pass) {
+__global__ __launch_bounds__(kPB) void k_thr_refine(const InstDesc* D, const Counts* cnt, const ThrItem* items, Opts o, int pass) {
   using KT = KeyT<T>;
   using K = typename KT::K;
   __shared__ uint32_t hc[kNB];
   __shared__ double hs[kNB];
   __shared__ uint32_t wcnt[kNW];
   __shared__ unsigned long long bbase;
-  const int iti = xcd_item(blockIdx.x, gridDim.x);
+  if ((int)blockIdx.x >= cnt->nthr) return;
+  const int iti = xcd_item(blockIdx.x, cnt->nthr);
   const ThrItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
@@ -902,7 +909,7 @@ __global__ __launch_bounds__(kPB) void k_thr_refine(const InstDesc* D, const Thr
 // appends candidates.  Ends with theta (l1) or the k-th magnitude and the tie
 // bookkeeping (cardinality) once final.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* D, const SelItem* items, Opts o, int pass) {
+__global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* D, const Counts* cnt, const SelItem* items, Opts o, int pass) {
   using KT = KeyT<T>;
   using K = typename KT::K;
   __shared__ uint32_t hc[kNB];
@@ -911,6 +918,7 @@ __global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* D, const Se
   __shared__ double ls[kBlock];
   __shared__ int lbest;
   __shared__ SelState st;
+  if ((int)blockIdx.x >= cnt->nsel) return;
   const SelItem si = items[blockIdx.x];
   const InstDesc& d = D[si.inst];
   const double* S = d.scal;
@@ -973,12 +981,13 @@ __global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* D, const Se
 // Cardinality ties straddling the cut: count entries equal to the k-th
 // magnitude per (item, component) so the apply pass can rank them by index.
 template <typename T>
-__global__ __launch_bounds__(kPB) void k_card_ties(const InstDesc* D, const ThrItem* items, Opts o,
+__global__ __launch_bounds__(kPB) void k_card_ties(const InstDesc* D, const Counts* cnt, const ThrItem* items, Opts o,
                                                       uint32_t* tie_part) {
   using KT = KeyT<T>;
   using K = typename KT::K;
-  __shared__ uint32_t cnt[3];
-  const int iti = xcd_item(blockIdx.x, gridDim.x);
+  __shared__ uint32_t tcnt[3];
+  if ((int)blockIdx.x >= cnt->nthr) return;
+  const int iti = xcd_item(blockIdx.x, cnt->nthr);
   const ThrItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
@@ -988,7 +997,7 @@ __global__ __launch_bounds__(kPB) void k_card_ties(const InstDesc* D, const ThrI
   if (s.kind != SIP_SET_CARD) return;
   const SelState& st = *s.sel[0];
   if (st.mode != SEL_PROJECT || st.err || !st.need_ties) return;
-  if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
+  if (threadIdx.x < 3) tcnt[threadIdx.x] = 0;
   __syncthreads();
   const Geo g(d);
   const K tkey = (K)st.tkey;
@@ -1002,10 +1011,10 @@ __global__ __launch_bounds__(kPB) void k_card_ties(const InstDesc* D, const ThrI
       if (!comp_valid(s.axis[c], iz, iy, ix, g)) continue;
       if (KT::key(y[P]) == tkey) ++local;
     }
-    if (local) atomicAdd(&cnt[c], local);
+    if (local) atomicAdd(&tcnt[c], local);
   }
   __syncthreads();
-  if (threadIdx.x < 3) tie_part[(size_t)iti * 3 + threadIdx.x] = cnt[threadIdx.x];
+  if (threadIdx.x < 3) tie_part[(size_t)iti * 3 + threadIdx.x] = tcnt[threadIdx.x];
 }
 
 // Apply pass.  Pipeline 0: y = soft threshold of w (l1) or w on the kept
@@ -1013,14 +1022,15 @@ __global__ __launch_bounds__(kPB) void k_card_ties(const InstDesc* D, const ThrI
 // adapt dots of the (dg, dv) pair and the new y/v snapshots.  Pipeline 1:
 // the feasibility distance ||s - P(s)||^2.
 template <typename T>
-__global__ __launch_bounds__(kPB) void k_thr_apply(const InstDesc* D, const ThrItem* items, Opts o, double* parts,
+__global__ __launch_bounds__(kPB) void k_thr_apply(const InstDesc* D, const Counts* cnt, const ThrItem* items, Opts o, double* parts,
                                                       const uint32_t* tie_part) {
   using KT = KeyT<T>;
   using K = typename KT::K;
   __shared__ double lds[lds_sum<8, kPB>()];
   __shared__ uint32_t wsum[kNW];
   __shared__ unsigned long long tie_base[3];
-  const int iti = xcd_item(blockIdx.x, gridDim.x);
+  if ((int)blockIdx.x >= cnt->nthr) return;
+  const int iti = xcd_item(blockIdx.x, cnt->nthr);
   const ThrItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
@@ -1163,12 +1173,13 @@ __device__ bool spectral(double ab, double aa, double bb, double eps, double& es
 // adapt-rho-gamma for i = 1..p+1 with the gamma cap and rho-ratio guard,
 // recompute the stencil scalars of C, and advance k.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* D, const int32_t* insts, Opts o,
+__global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* D, const Counts* cnt, const int32_t* insts, Opts o,
                                                    const double* proj_parts, const double* thrw_parts,
                                                    const double* thra_parts) {
   __shared__ double lds[lds_sum<8>()];
   __shared__ double dots[kMaxUnits][8];
   __shared__ double evol[16];
+  if ((int)blockIdx.x >= cnt->ninst) return;
   const InstDesc& d = D[insts[blockIdx.x]];
   double* S = d.scal;
   if (S[S_STATE] != 0.0) return;
@@ -1314,37 +1325,37 @@ void launch_init(hipStream_t st, const InstDesc* D, int inst, int64_t N) {
 template <typename T>
 void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
   if (t.npt > 0) {
-    k_rhs<T><<<t.npt, kPB, 0, st>>>(t.D, t.pt, t.rr_part);
+    k_rhs<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, t.rr_part);
     for (int j = 0; j < o.cg_max; ++j) {
-      k_cg_dir<T><<<t.npt, kPB, 0, st>>>(t.D, t.pt, j, t.rr_part, t.pq_part, o);
-      k_cg_upd<T><<<t.npt, kPB, 0, st>>>(t.D, t.pt, j, t.pq_part, t.rr_part);
+      k_cg_dir<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, j, t.rr_part, t.pq_part, o);
+      k_cg_upd<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, j, t.pq_part, t.rr_part);
     }
-    k_proj<T><<<t.npt, kPB, 0, st>>>(t.D, t.pt, o, t.proj_part);
+    k_proj<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, o, t.proj_part);
   }
   if (t.nthr > 0) {
-    k_thr_w<T><<<t.nthr, kPB, 0, st>>>(t.D, t.thr, o, t.thrw_part);
-    k_sel1<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.sel, o);
-    k_thr_refine<T><<<t.nthr, kPB, 0, st>>>(t.D, t.thr, o, 0);
-    k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.sel, o, 0);
-    k_thr_refine<T><<<t.nthr, kPB, 0, st>>>(t.D, t.thr, o, 1);
-    k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.sel, o, 1);
-    if (t.any_card) k_card_ties<T><<<t.nthr, kPB, 0, st>>>(t.D, t.thr, o, t.tie_part);
-    k_thr_apply<T><<<t.nthr, kPB, 0, st>>>(t.D, t.thr, o, t.thra_part, t.tie_part);
+    k_thr_w<T><<<t.nthr, kPB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thrw_part);
+    k_sel1<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o);
+    k_thr_refine<T><<<t.nthr, kPB, 0, st>>>(t.D, t.cnt, t.thr, o, 0);
+    k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 0);
+    k_thr_refine<T><<<t.nthr, kPB, 0, st>>>(t.D, t.cnt, t.thr, o, 1);
+    k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 1);
+    if (t.any_card) k_card_ties<T><<<t.nthr, kPB, 0, st>>>(t.D, t.cnt, t.thr, o, t.tie_part);
+    k_thr_apply<T><<<t.nthr, kPB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thra_part, t.tie_part);
   }
   if (t.ninst > 0)
-    k_finish<T><<<t.ninst, kBlock, 0, st>>>(t.D, t.inst, o, t.proj_part, t.thrw_part, t.thra_part);
+    k_finish<T><<<t.ninst, kBlock, 0, st>>>(t.D, t.cnt, t.inst, o, t.proj_part, t.thrw_part, t.thra_part);
 }
 
 // One kernel of the iteration on its own (timing); CG kernels use step 1.
 template <typename T>
 void launch_phase(hipStream_t st, const Tables& t, const Opts& o, int phase) {
   switch (phase) {
-    case 0: if (t.npt) k_rhs<T><<<t.npt, kPB, 0, st>>>(t.D, t.pt, t.rr_part); break;
-    case 1: if (t.npt) k_cg_dir<T><<<t.npt, kPB, 0, st>>>(t.D, t.pt, 1, t.rr_part, t.pq_part, o); break;
-    case 2: if (t.npt) k_cg_upd<T><<<t.npt, kPB, 0, st>>>(t.D, t.pt, 1, t.pq_part, t.rr_part); break;
-    case 3: if (t.npt) k_proj<T><<<t.npt, kPB, 0, st>>>(t.D, t.pt, o, t.proj_part); break;
-    case 4: if (t.nthr) k_thr_w<T><<<t.nthr, kPB, 0, st>>>(t.D, t.thr, o, t.thrw_part); break;
-    case 5: if (t.nthr) k_thr_apply<T><<<t.nthr, kPB, 0, st>>>(t.D, t.thr, o, t.thra_part, t.tie_part); break;
+    case 0: if (t.npt) k_rhs<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, t.rr_part); break;
+    case 1: if (t.npt) k_cg_dir<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, 1, t.rr_part, t.pq_part, o); break;
+    case 2: if (t.npt) k_cg_upd<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, 1, t.pq_part, t.rr_part); break;
+    case 3: if (t.npt) k_proj<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, o, t.proj_part); break;
+    case 4: if (t.nthr) k_thr_w<T><<<t.nthr, kPB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thrw_part); break;
+    case 5: if (t.nthr) k_thr_apply<T><<<t.nthr, kPB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thra_part, t.tie_part); break;
     default: break;
   }
 }

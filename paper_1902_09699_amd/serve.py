@@ -1,0 +1,198 @@
+"""Served form: continuous batching of projection requests on one GPU.
+
+Requests (a grid field m and a set list) arrive as a Poisson process.  They
+are admitted into a resident batch (sip_batch_*) as soon as a slot and enough
+arena bytes are free (exact sizes from sip_workspace_bytes); every admitted
+instance keeps its whole state on the device; the batch advances all
+instances together by `chunk` iterations (one captured HIP graph replay),
+after which finished instances (stopping test passed or iteration cap) are
+retired, their x copied out and their workspace returned to the arena.  The
+plain form serves the same requests one at a time through the same engine
+(a one-slot batch).
+
+    python -m paper_1902_09699_amd.serve --requests 400 --rate 200
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import json
+import math
+import os
+import sys
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_1902_09699_amd import sip  # noqa: E402
+from paper_1902_09699_amd import workloads as wl  # noqa: E402
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds after the start of the run
+    m: np.ndarray           # float64 holding float32-rounded values
+    sets: list
+    result: dict | None = None
+    x: np.ndarray | None = None
+    t_admit: float = math.nan
+    t_done: float = math.nan
+
+
+def make_requests(n, rate, frac3d=0.05, seed0=3000, max2d=1024, side3d=(64, 160)):
+    """The served mix: Poisson arrivals, 2D sides log-uniform on [64, max2d],
+    3D sides uniform on side3d with probability frac3d."""
+    arr = wl.poisson_arrivals(n, rate, seed=seed0 - 1)
+    out = []
+    for j in range(n):
+        m, sets = wl.served_request(j, seed0=seed0, frac3d=frac3d, max2d=max2d, side3d=side3d)
+        m = wl.rounded(m, "f32")
+        out.append(Request(j, float(arr[j]), m, wl.finalize(m, sets)))
+    return out
+
+
+def serving_opts(max_iter=200, stop_every=5, cg_max=10):
+    return sip.make_opts("f32", max_iter=max_iter, cg_max=cg_max, cg_fixed=0, stop_every=stop_every)
+
+
+class Server:
+    """Continuous batching over one resident batch."""
+
+    def __init__(self, opts, arena_bytes, max_slots=256, chunk=5):
+        self.opts = opts
+        self.chunk = int(chunk)
+        self.arena_bytes = int(arena_bytes)
+        self.batch = sip.Batch(max_slots, arena_bytes, opts)
+        self.max_slots = max_slots
+
+    def close(self):
+        self.batch.close()
+
+    def run(self, requests, realtime=True, log=None):
+        import torch
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        pending = collections.deque(reqs)
+        active = {}
+        rejected = []
+        peak_bytes = 0
+        in_use = 0
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0  # noqa: E731
+        chunks = 0
+        while pending or active:
+            t = now()
+            # admit every arrived request that fits, in arrival order
+            while pending and (pending[0].arrival <= t or not realtime):
+                r = pending[0]
+                need = sip.workspace_bytes(r.m.shape, r.sets, self.opts)
+                if need > self.arena_bytes:
+                    rejected.append(pending.popleft())
+                    continue
+                md = torch.tensor(r.m, dtype=torch.float32, device="cuda")
+                xd = torch.empty_like(md)
+                slot = self.batch.add(md, r.sets, xd)
+                if slot < 0:
+                    if not active:  # cannot fit even into an empty batch
+                        rejected.append(pending.popleft())
+                        continue
+                    break  # no slot or arena room: wait for a retirement
+                r.t_admit = now()
+                active[slot] = (r, md, xd, need)
+                in_use += need
+                peak_bytes = max(peak_bytes, in_use)
+                pending.popleft()
+            if active:
+                self.batch.run(self.chunk)
+                chunks += 1
+                done = self.batch.poll()
+                for slot, flag in enumerate(done):
+                    if flag == 1 and slot in active:
+                        r, md, xd, need = active.pop(slot)
+                        r.result = self.batch.remove(slot)
+                        r.x = xd.cpu().numpy()
+                        r.t_done = now()
+                        in_use -= need
+                        if log:
+                            log(r)
+            elif pending and realtime:
+                time.sleep(max(0.0, pending[0].arrival - now()))
+        return {"chunks": chunks, "peak_arena_bytes": peak_bytes, "rejected": len(rejected)}
+
+
+def serve_plain(requests, opts, arena_bytes, chunk=5):
+    """The plain per-instance form: the same engine with one slot, so each
+    request runs alone, in arrival order (graphs are reused across requests
+    whose work tables fit the same launch sizes)."""
+    srv = Server(opts, arena_bytes, max_slots=1, chunk=chunk)
+    srv.run(make_requests(2, 1e9, 0.0, seed0=9100, max2d=128), realtime=False)
+    info = srv.run(requests, realtime=True)
+    srv.close()
+    return info
+
+
+def summary(requests, label):
+    done = [r for r in requests if r.result is not None]
+    lat = np.array([r.t_done - r.arrival for r in done])
+    span = max(r.t_done for r in done) - min(r.arrival for r in requests)
+    pts_it = sum(r.m.size * r.result["iters"] for r in done)
+    return {"form": label, "completed": len(done), "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
+            "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2), "mean_ms": round(1e3 * float(lat.mean()), 2),
+            "instances_per_s": round(len(done) / span, 2), "grid_pts_iters_per_s": round(pts_it / span, 1),
+            "mean_iters": round(float(np.mean([r.result["iters"] for r in done])), 1),
+            "converged": int(sum(r.result["converged"] for r in done))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=400)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--frac3d", type=float, default=0.05)
+    ap.add_argument("--arena-gb", type=float, default=96.0)
+    ap.add_argument("--slots", type=int, default=256)
+    ap.add_argument("--chunk", type=int, default=5)
+    ap.add_argument("--max-iter", type=int, default=200)
+    ap.add_argument("--plain", action="store_true", help="also serve the same requests one at a time")
+    ap.add_argument("--plain-requests", type=int, default=0, help="requests for the plain form (0: same)")
+    ap.add_argument("--check", type=int, default=8, help="requests re-run alone to compare results")
+    a = ap.parse_args()
+    import torch
+    opts = serving_opts(a.max_iter)
+    reqs = make_requests(a.requests, a.rate, a.frac3d)
+    offered = sum(r.m.size for r in reqs) / (reqs[-1].arrival - reqs[0].arrival)
+    print(f"requests {len(reqs)}, 3D {sum(r.m.ndim == 3 for r in reqs)}, offered {offered:.3g} grid-pts/s",
+          flush=True)
+    # warm the code objects and graph capture on a few small requests
+    warm = make_requests(4, 1e9, 0.0, seed0=9000, max2d=128)
+    srv = Server(opts, int(a.arena_gb * (1 << 30)), a.slots, a.chunk)
+    srv.run(warm, realtime=False)
+    t = time.perf_counter()
+    info = srv.run(reqs, realtime=True)
+    served = summary(reqs, "served")
+    served.update(info)
+    served["wall_s"] = round(time.perf_counter() - t, 3)
+    print(json.dumps(served), flush=True)
+    # same result alone and in the mix
+    diffs = []
+    for r in reqs[: a.check]:
+        md = torch.tensor(r.m, dtype=torch.float32, device="cuda")
+        x, res = sip.project(md, r.sets, opts)
+        xa = x.cpu().numpy()
+        diffs.append(float(np.max(np.abs(xa - r.x)) / max(np.max(np.abs(xa)), 1e-30)))
+    print(json.dumps({"alone_vs_mix_max_rel_diff": max(diffs), "checked": len(diffs)}), flush=True)
+    srv.close()
+    if a.plain:
+        plain_reqs = make_requests(a.plain_requests or a.requests, a.rate, a.frac3d)
+        info = serve_plain(plain_reqs, opts, int(a.arena_gb * (1 << 30)), a.chunk)
+        plain = summary(plain_reqs, "plain")
+        plain.update(info)
+        print(json.dumps(plain), flush=True)
+
+
+if __name__ == "__main__":
+    main()

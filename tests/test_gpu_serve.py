@@ -1,0 +1,44 @@
+"""Served form on the GPU: continuous batching admits requests as slots and
+arena bytes free up, never exceeds the arena, and every result equals the
+same request projected alone."""
+import numpy as np
+import pytest
+
+from paper_1902_09699_amd import serve, sip
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_mix(n):
+    return serve.make_requests(n, rate=1e9, frac3d=0.25, seed0=5000, max2d=96, side3d=(12, 20))
+
+
+def test_served_results_equal_alone_and_respect_the_arena():
+    import torch
+    opts = serve.serving_opts(max_iter=60)
+    reqs = _small_mix(14)
+    need = [sip.workspace_bytes(r.m.shape, r.sets, opts) for r in reqs]
+    arena = 3 * max(need)          # forces queueing: at most a few fit at once
+    srv = serve.Server(opts, arena, max_slots=4, chunk=5)
+    info = srv.run(reqs, realtime=False)
+    srv.close()
+    print(f"\n[serve] peak arena {info['peak_arena_bytes']} of {arena}, chunks {info['chunks']}", flush=True)
+    assert info["rejected"] == 0
+    assert info["peak_arena_bytes"] <= arena
+    assert all(r.result is not None and r.result["status"] == 0 for r in reqs)
+    assert any(r.result["converged"] for r in reqs)
+    for r in reqs:
+        md = torch.tensor(r.m, dtype=torch.float32, device="cuda")
+        x, res = sip.project(md, r.sets, opts)
+        assert np.array_equal(x.cpu().numpy(), r.x), r.rid
+        assert res["iters"] == r.result["iters"]
+
+
+def test_oversized_request_is_rejected_not_hung():
+    opts = serve.serving_opts(max_iter=10)
+    reqs = _small_mix(3)
+    need = max(sip.workspace_bytes(r.m.shape, r.sets, opts) for r in reqs)
+    srv = serve.Server(opts, need // 4, max_slots=2, chunk=5)
+    info = srv.run(reqs, realtime=False)
+    srv.close()
+    assert info["rejected"] >= 1
