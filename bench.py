@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle sample budget (0: skip)")
     ap.add_argument("--batched-count", type=int, default=256)
     ap.add_argument("--copy-mb", type=int, default=1024, help="plain-copy reference size (0: skip)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles")
     return ap.parse_args()
 
 
@@ -159,6 +160,11 @@ def main():
     assert all(s >= 0 for s in slots)
     chunk = min(args.graph_iters, iters)
     n_pts = sum(m.size for m, _ in insts)
+    tiles = None
+    if not args.no_autotune:
+        from paper_1902_09699_amd import autotune
+        tiles, tile_ms = autotune.tune(batch, slots, ms, field, [m.shape for m, _ in insts], use_cache=False,
+                                       cache=None)
 
     def one_step():
         for sl, md in zip(slots, ms):
@@ -236,7 +242,7 @@ def main():
         "dtype": field,
         "data": "synthetic (seeded generators)",
         "config": {"workload": desc, "instances": len(insts), "grid_points": n_pts, "iterations": iters,
-                   "cg_steps": 10, "reductions": "f64"},
+                   "cg_steps": 10, "reductions": "f64", "tiles": list(tiles) if tiles else "default"},
         "roofline": roofline,
         "kernels": {k: {"ms": round(v["ms"], 5), "GBs": round(v["GBs"], 1)} for k, v in kernels.items()},
         "cpu_baseline": cpu,

@@ -208,9 +208,8 @@ int32_t sip_batch_schedule(sip_batch* b, int32_t slot, double* rho, double* gamm
                            int32_t max_n, int32_t* n, void* stream);
 
 /* Work decomposition: grid points per item of the point kernels (RHS, CG,
- * projection) and of the threshold-set kernels, each a multiple of 1024 (the
- * item kernels' block size) and grown when an instance would need more than
- * max_items items.  Results are bit-identical for any batch composition at
+ * projection) and of the threshold-set kernels, each a multiple of 256, and
+ * grown when an instance would need more than max_items items.  Results are bit-identical for any batch composition at
  * fixed tile settings.  Applies from the next sip_batch_run.  Defaults
  * 2048/512 and 2048/512. */
 int32_t sip_batch_set_tiles(sip_batch* b, int32_t pt_points, int32_t pt_max_items, int32_t thr_points,

@@ -212,13 +212,13 @@ Opts kernel_opts(const sip_opts& o) {
   return k;
 }
 
-constexpr int64_t kItemThreads = 1024;  // block size of the item kernels
+constexpr int64_t kTileQuantum = 256;  // item sizes are multiples of this
 
-// Points per item: whole 1024-point rounds, at least `base`, and few enough
-// items that the per-instance partial reductions stay short.
+// Points per item: at least `base`, and few enough items that the
+// per-instance partial reductions stay short.
 int64_t tile_points(int64_t N, int64_t base, int64_t max_items) {
   int64_t t = std::max<int64_t>(base, (N + max_items - 1) / max_items);
-  return (t + kItemThreads - 1) / kItemThreads * kItemThreads;
+  return (t + kTileQuantum - 1) / kTileQuantum * kTileQuantum;
 }
 
 }  // namespace
@@ -817,8 +817,8 @@ int32_t sip_stream_copy(void* dst, const void* src, int64_t bytes, void* stream_
 
 int32_t sip_batch_set_tiles(sip_batch* b, int32_t pt_points, int32_t pt_max_items, int32_t thr_points,
                             int32_t thr_max_items) {
-  if (!b || pt_points < kItemThreads || thr_points < kItemThreads || pt_points % kItemThreads ||
-      thr_points % kItemThreads ||
+  if (!b || pt_points < kTileQuantum || thr_points < kTileQuantum || pt_points % kTileQuantum ||
+      thr_points % kTileQuantum ||
       pt_max_items < 1 || thr_max_items < 1)
     return SIP_EINVAL;
   b->tiles.pt_base = pt_points;

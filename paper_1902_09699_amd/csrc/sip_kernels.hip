@@ -17,8 +17,12 @@
 
 namespace sip {
 
-constexpr int kPB = 1024;  // threads per block of the point and threshold-item kernels
-constexpr int kNW = kPB / 64;
+constexpr int kPB = 1024;  // threads per block of the CG and RHS kernels
+// Threads per block of the set and threshold kernels: more registers per
+// thread and no partial reduction at start, so smaller blocks let several
+// stay resident per CU (latency hiding on many small items).
+constexpr int kSB = 256;
+constexpr int kSW = kSB / 64;
 
 // ---------------------------------------------------------------- helpers
 
@@ -413,8 +417,8 @@ __global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* D, const Counts*
 // snapshot; on stopping-test iterations the feasibility sums of s.  Then the
 // x snapshot / x history writes and the r_evol sums.
 template <typename T>
-__global__ __launch_bounds__(kPB) void k_proj(const InstDesc* D, const Counts* cnt, const PtItem* items, Opts o, double* parts) {
-  __shared__ double lds[lds_sum<8, kPB>()];
+__global__ __launch_bounds__(kSB) void k_proj(const InstDesc* D, const Counts* cnt, const PtItem* items, Opts o, double* parts) {
+  __shared__ double lds[lds_sum<8, kSB>()];
   if ((int)blockIdx.x >= cnt->npt) return;
   const int iti = xcd_item(blockIdx.x, cnt->npt);
   const PtItem it = items[iti];
@@ -452,10 +456,10 @@ __global__ __launch_bounds__(kPB) void k_proj(const InstDesc* D, const Counts* c
       T* __restrict__ vh0 = (T*)(ident ? d.vh0l : s->vh0) + off;
       T* __restrict__ v0 = (T*)(ident ? d.v0l : s->v0) + off;
       T* __restrict__ y0 = (T*)(ident ? d.y0l : s->y0) + off;
-      for (int base = it.begin; base < end; base += kPB * kUset) {
+      for (int base = it.begin; base < end; base += kSB * kUset) {
 #pragma unroll
         for (int uu = 0; uu < kUset; ++uu) {
-          const int P = base + uu * kPB + (int)threadIdx.x;
+          const int P = base + uu * kSB + (int)threadIdx.x;
           if (P >= end) continue;
           int iz, iy, ix;
           g.coords(P, iz, iy, ix);
@@ -496,7 +500,7 @@ __global__ __launch_bounds__(kPB) void k_proj(const InstDesc* D, const Counts* c
       }
     }
     if (adapt || check) {
-      block_sum<8, kPB>(acc, lds);
+      block_sum<8, kSB>(acc, lds);
       if (threadIdx.x == 0) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) out[u * kUnitParts + q] = acc[q];
@@ -511,7 +515,7 @@ __global__ __launch_bounds__(kPB) void k_proj(const InstDesc* D, const Counts* c
     const int H = o.evol_hist;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double accx[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int P = it.begin + (int)threadIdx.x; P < end; P += kPB) {
+    for (int P = it.begin + (int)threadIdx.x; P < end; P += kSB) {
       const T xv = x[P];
       if (adapt) xw[P] = xv;
       if (ring) {
@@ -528,8 +532,8 @@ __global__ __launch_bounds__(kPB) void k_proj(const InstDesc* D, const Counts* c
       }
     }
     if (check) {
-      block_sum<8, kPB>(acc, lds);
-      block_sum<8, kPB>(accx, lds);
+      block_sum<8, kSB>(acc, lds);
+      block_sum<8, kSB>(accx, lds);
       if (threadIdx.x == 0) {
         out[kEvolOff + 0] = accx[0];
 #pragma unroll
@@ -547,11 +551,11 @@ __global__ __launch_bounds__(kPB) void k_proj(const InstDesc* D, const Counts* c
 // (dh, dvh) pair; radix histogram of the first key digit of |w|.
 // Pipeline 1 (stopping-test iterations): histogram of |s| and ||s||^2.
 template <typename T>
-__global__ __launch_bounds__(kPB) void k_thr_w(const InstDesc* D, const Counts* cnt, const ThrItem* items, Opts o, double* parts) {
+__global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* D, const Counts* cnt, const ThrItem* items, Opts o, double* parts) {
   using KT = KeyT<T>;
   __shared__ uint32_t hc[kNB];
   __shared__ double hs[kNB];
-  __shared__ double lds[lds_sum<8, kPB>()];
+  __shared__ double lds[lds_sum<8, kSB>()];
   if ((int)blockIdx.x >= cnt->nthr) return;
   const int iti = xcd_item(blockIdx.x, cnt->nthr);
   const ThrItem it = items[iti];
@@ -566,7 +570,7 @@ __global__ __launch_bounds__(kPB) void k_thr_w(const InstDesc* D, const Counts* 
   const int call = adapt ? adapt_call(k, o) : 0;
   const SetDesc& s = d.sets[it.set];
   const bool l1 = s.kind == SIP_SET_L1;
-  for (int b = threadIdx.x; b < kNB; b += kPB) { hc[b] = 0; hs[b] = 0.0; }
+  for (int b = threadIdx.x; b < kNB; b += kSB) { hc[b] = 0; hs[b] = 0.0; }
   __syncthreads();
   const Geo g(d);
   const T* x = (const T*)d.x;
@@ -584,7 +588,7 @@ __global__ __launch_bounds__(kPB) void k_thr_w(const InstDesc* D, const Counts* 
     T* y = (T*)s.y + off;
     const T* v = (const T*)s.v + off;
     T* vh0 = (T*)s.vh0 + off;
-    for (int P = it.begin + (int)threadIdx.x; P < end; P += kPB) {
+    for (int P = it.begin + (int)threadIdx.x; P < end; P += kSB) {
       int iz, iy, ix;
       g.coords(P, iz, iy, ix);
       T sv;
@@ -619,14 +623,14 @@ __global__ __launch_bounds__(kPB) void k_thr_w(const InstDesc* D, const Counts* 
   __syncthreads();
   uint32_t* gc = s.hcnt[it.src];
   double* gs = s.hsum[it.src];
-  for (int b = threadIdx.x; b < kNB; b += kPB) {
+  for (int b = threadIdx.x; b < kNB; b += kSB) {
     const uint32_t cnt = hc[b];
     if (cnt) {
       atomicAdd(&gc[b], cnt);
       if (l1) atomicAdd(&gs[b], hs[b]);
     }
   }
-  block_sum<8, kPB>(acc, lds);
+  block_sum<8, kSB>(acc, lds);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) parts[(size_t)iti * kThrParts + q] = acc[q];
@@ -810,12 +814,12 @@ __device__ __forceinline__ bool pass_compacts(const SelState& st, int pass) {
 // (or on the last pass of a long key) their keys go to the candidate list,
 // appended with one atomic per block round.
 template <typename T>
-__global__ __launch_bounds__(kPB) void k_thr_refine(const InstDesc* D, const Counts* cnt, const ThrItem* items, Opts o, int pass) {
+__global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* D, const Counts* cnt, const ThrItem* items, Opts o, int pass) {
   using KT = KeyT<T>;
   using K = typename KT::K;
   __shared__ uint32_t hc[kNB];
   __shared__ double hs[kNB];
-  __shared__ uint32_t wcnt[kNW];
+  __shared__ uint32_t wcnt[kSW];
   __shared__ unsigned long long bbase;
   if ((int)blockIdx.x >= cnt->nthr) return;
   const int iti = xcd_item(blockIdx.x, cnt->nthr);
@@ -832,7 +836,7 @@ __global__ __launch_bounds__(kPB) void k_thr_refine(const InstDesc* D, const Cou
   const bool compact = pass_compacts<T>(st, pass);
   const bool l1 = s.kind == SIP_SET_L1;
   const int nb = 1 << KT::width(dig);
-  for (int b = threadIdx.x; b < nb; b += kPB) { hc[b] = 0; hs[b] = 0.0; }
+  for (int b = threadIdx.x; b < nb; b += kSB) { hc[b] = 0; hs[b] = 0.0; }
   __syncthreads();
   const int shp = digit_shift<T>(dig - 1), sh = digit_shift<T>(dig);
   const K want = (K)(st.prefix >> shp);
@@ -845,7 +849,7 @@ __global__ __launch_bounds__(kPB) void k_thr_refine(const InstDesc* D, const Cou
   for (int c = 0; c < s.ncomp; ++c) {
     const int axis = s.axis[c];
     const T* __restrict__ y = (const T*)s.y + (size_t)c * g.N;
-    for (int base = it.begin; base < end; base += kPB) {
+    for (int base = it.begin; base < end; base += kSB) {
       const int P = base + (int)threadIdx.x;
       bool hit = false;
       K key = 0;
@@ -877,7 +881,7 @@ __global__ __launch_bounds__(kPB) void k_thr_refine(const InstDesc* D, const Cou
         __syncthreads();
         if (threadIdx.x == 0) {
           unsigned long long tot = 0;
-          for (int q = 0; q < kNW; ++q) tot += wcnt[q];
+          for (int q = 0; q < kSW; ++q) tot += wcnt[q];
           bbase = tot ? atomicAdd(ncand, tot) : 0ull;
         }
         __syncthreads();
@@ -894,7 +898,7 @@ __global__ __launch_bounds__(kPB) void k_thr_refine(const InstDesc* D, const Cou
   __syncthreads();
   uint32_t* gc = s.hcnt[it.src];
   double* gs = s.hsum[it.src];
-  for (int b = threadIdx.x; b < nb; b += kPB) {
+  for (int b = threadIdx.x; b < nb; b += kSB) {
     if (hc[b]) {
       atomicAdd(&gc[b], hc[b]);
       if (l1) atomicAdd(&gs[b], hs[b]);
@@ -981,7 +985,7 @@ __global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* D, const Co
 // Cardinality ties straddling the cut: count entries equal to the k-th
 // magnitude per (item, component) so the apply pass can rank them by index.
 template <typename T>
-__global__ __launch_bounds__(kPB) void k_card_ties(const InstDesc* D, const Counts* cnt, const ThrItem* items, Opts o,
+__global__ __launch_bounds__(kSB) void k_card_ties(const InstDesc* D, const Counts* cnt, const ThrItem* items, Opts o,
                                                       uint32_t* tie_part) {
   using KT = KeyT<T>;
   using K = typename KT::K;
@@ -1005,7 +1009,7 @@ __global__ __launch_bounds__(kPB) void k_card_ties(const InstDesc* D, const Coun
   for (int c = 0; c < s.ncomp; ++c) {
     const T* y = (const T*)s.y + (size_t)c * g.N;
     uint32_t local = 0;
-    for (int P = it.begin + (int)threadIdx.x; P < end; P += kPB) {
+    for (int P = it.begin + (int)threadIdx.x; P < end; P += kSB) {
       int iz, iy, ix;
       g.coords(P, iz, iy, ix);
       if (!comp_valid(s.axis[c], iz, iy, ix, g)) continue;
@@ -1022,12 +1026,12 @@ __global__ __launch_bounds__(kPB) void k_card_ties(const InstDesc* D, const Coun
 // adapt dots of the (dg, dv) pair and the new y/v snapshots.  Pipeline 1:
 // the feasibility distance ||s - P(s)||^2.
 template <typename T>
-__global__ __launch_bounds__(kPB) void k_thr_apply(const InstDesc* D, const Counts* cnt, const ThrItem* items, Opts o, double* parts,
+__global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* D, const Counts* cnt, const ThrItem* items, Opts o, double* parts,
                                                       const uint32_t* tie_part) {
   using KT = KeyT<T>;
   using K = typename KT::K;
-  __shared__ double lds[lds_sum<8, kPB>()];
-  __shared__ uint32_t wsum[kNW];
+  __shared__ double lds[lds_sum<8, kSB>()];
+  __shared__ uint32_t wsum[kSW];
   __shared__ unsigned long long tie_base[3];
   if ((int)blockIdx.x >= cnt->nthr) return;
   const int iti = xcd_item(blockIdx.x, cnt->nthr);
@@ -1077,7 +1081,7 @@ __global__ __launch_bounds__(kPB) void k_thr_apply(const InstDesc* D, const Coun
     T* y0 = (T*)s.y0 + off;
     T* v0 = (T*)s.v0 + off;
     unsigned long long run = rank_ties ? tie_base[c] : 0ull;
-    for (int base = it.begin; base < end; base += kPB) {
+    for (int base = it.begin; base < end; base += kSB) {
       const int P = base + (int)threadIdx.x;
       bool valid = false;
       T sv = 0;
@@ -1118,7 +1122,7 @@ __global__ __launch_bounds__(kPB) void k_thr_apply(const InstDesc* D, const Coun
         const unsigned long long below = mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
         before += (unsigned long long)__popcll(below);
         tie_keep = tie && before < st.keep_ties;
-        for (int q = 0; q < kNW; ++q) run += wsum[q];
+        for (int q = 0; q < kSW; ++q) run += wsum[q];
         __syncthreads();
       }
       if (!valid) continue;
@@ -1149,7 +1153,7 @@ __global__ __launch_bounds__(kPB) void k_thr_apply(const InstDesc* D, const Coun
       }
     }
   }
-  block_sum<8, kPB>(acc, lds);
+  block_sum<8, kSB>(acc, lds);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) parts[(size_t)iti * kThrParts + q] = acc[q];
@@ -1330,17 +1334,17 @@ void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
       k_cg_dir<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, j, t.rr_part, t.pq_part, o);
       k_cg_upd<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, j, t.pq_part, t.rr_part);
     }
-    k_proj<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, o, t.proj_part);
+    k_proj<T><<<t.npt, kSB, 0, st>>>(t.D, t.cnt, t.pt, o, t.proj_part);
   }
   if (t.nthr > 0) {
-    k_thr_w<T><<<t.nthr, kPB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thrw_part);
+    k_thr_w<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thrw_part);
     k_sel1<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o);
-    k_thr_refine<T><<<t.nthr, kPB, 0, st>>>(t.D, t.cnt, t.thr, o, 0);
+    k_thr_refine<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, 0);
     k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 0);
-    k_thr_refine<T><<<t.nthr, kPB, 0, st>>>(t.D, t.cnt, t.thr, o, 1);
+    k_thr_refine<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, 1);
     k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 1);
-    if (t.any_card) k_card_ties<T><<<t.nthr, kPB, 0, st>>>(t.D, t.cnt, t.thr, o, t.tie_part);
-    k_thr_apply<T><<<t.nthr, kPB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thra_part, t.tie_part);
+    if (t.any_card) k_card_ties<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.tie_part);
+    k_thr_apply<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thra_part, t.tie_part);
   }
   if (t.ninst > 0)
     k_finish<T><<<t.ninst, kBlock, 0, st>>>(t.D, t.cnt, t.inst, o, t.proj_part, t.thrw_part, t.thra_part);
@@ -1353,9 +1357,9 @@ void launch_phase(hipStream_t st, const Tables& t, const Opts& o, int phase) {
     case 0: if (t.npt) k_rhs<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, t.rr_part); break;
     case 1: if (t.npt) k_cg_dir<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, 1, t.rr_part, t.pq_part, o); break;
     case 2: if (t.npt) k_cg_upd<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, 1, t.pq_part, t.rr_part); break;
-    case 3: if (t.npt) k_proj<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, o, t.proj_part); break;
-    case 4: if (t.nthr) k_thr_w<T><<<t.nthr, kPB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thrw_part); break;
-    case 5: if (t.nthr) k_thr_apply<T><<<t.nthr, kPB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thra_part, t.tie_part); break;
+    case 3: if (t.npt) k_proj<T><<<t.npt, kSB, 0, st>>>(t.D, t.cnt, t.pt, o, t.proj_part); break;
+    case 4: if (t.nthr) k_thr_w<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thrw_part); break;
+    case 5: if (t.nthr) k_thr_apply<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thra_part, t.tie_part); break;
     default: break;
   }
 }

@@ -184,7 +184,8 @@ def main():
         x, res = sip.project(md, r.sets, opts)
         xa = x.cpu().numpy()
         diffs.append(float(np.max(np.abs(xa - r.x)) / max(np.max(np.abs(xa)), 1e-30)))
-    print(json.dumps({"alone_vs_mix_max_rel_diff": max(diffs), "checked": len(diffs)}), flush=True)
+    if diffs:
+        print(json.dumps({"alone_vs_mix_max_rel_diff": max(diffs), "checked": len(diffs)}), flush=True)
     srv.close()
     if a.plain:
         plain_reqs = make_requests(a.plain_requests or a.requests, a.rate, a.frac3d)
