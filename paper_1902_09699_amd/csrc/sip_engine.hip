@@ -259,7 +259,8 @@ struct sip_batch {
   int32_t* d_inst = nullptr; int cap_inst = 0;
   double *d_rr = nullptr, *d_pq = nullptr, *d_proj = nullptr, *d_thrw = nullptr, *d_thra = nullptr;
   uint32_t* d_tie = nullptr;
-  int cap_ppt = 0, cap_pthr = 0;   // item capacity of the partial-sum buffers
+  int cap_ppt = 0, cap_pthr = 0, cap_psp = 0;   // item capacity of the partial-sum buffers
+  sip::PtItem* d_sp = nullptr; int cap_sp = 0;
   sip::Counts* d_counts = nullptr;
   sip::Tables tab{};
   int live_items = 0, live_inst = 0;
@@ -292,7 +293,7 @@ void drop_graphs(sip_batch* b) {
 }
 
 int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
-  std::vector<PtItem> pt;
+  std::vector<PtItem> pt, sp;
   std::vector<ThrItem> thr;
   std::vector<SelItem> sel;
   std::vector<int32_t> inst;
@@ -307,6 +308,9 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
     for (int64_t p0 = 0; p0 < N; p0 += tp) pt.push_back(PtItem{si, (int)p0, (int)std::min<int64_t>(tp, N - p0), 0});
     s.desc.pt_end = (int)pt.size();
     const int64_t tt = tile_points(N, b->tiles.thr_base, b->tiles.thr_max_items);
+    s.desc.sp_begin = (int)sp.size();
+    for (int64_t p0 = 0; p0 < N; p0 += tt) sp.push_back(PtItem{si, (int)p0, (int)std::min<int64_t>(tt, N - p0), 0});
+    s.desc.sp_end = (int)sp.size();
     for (int k = 0; k < s.nsets; ++k) {
       SetDesc& sd = s.desc.sets[k];
       if (sd.thr < 0) continue;
@@ -327,21 +331,30 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   auto pow2 = [](int n, int lo) { if (n <= 0) return 0; int c = lo; while (c < n) c <<= 1; return c; };
   const int lpt = pow2((int)pt.size(), 64), lthr = pow2((int)thr.size(), 64);
   const int lsel = pow2((int)sel.size(), 8), linst = pow2((int)inst.size(), 8);
+  const int lsp = pow2((int)sp.size(), 64);
   const bool relaunch = lpt != b->tab.npt || lthr != b->tab.nthr || lsel != b->tab.nsel || linst != b->tab.ninst ||
-                        any_card != b->tab.any_card;
+                        lsp != b->tab.nsp || any_card != b->tab.any_card;
   int32_t rc;
   const int old_pt = b->cap_pt, old_thr = b->cap_thr, old_sel = b->cap_sel, old_inst = b->cap_inst;
+  const int old_sp = b->cap_sp;
   if ((rc = ensure(b->d_pt, b->cap_pt, std::max(lpt, 1), sizeof(PtItem)))) return rc;
+  if ((rc = ensure(b->d_sp, b->cap_sp, std::max(lsp, 1), sizeof(PtItem)))) return rc;
   if ((rc = ensure(b->d_thr, b->cap_thr, std::max(lthr, 1), sizeof(ThrItem)))) return rc;
   if ((rc = ensure(b->d_sel, b->cap_sel, std::max(lsel, 1), sizeof(SelItem)))) return rc;
   if ((rc = ensure(b->d_inst, b->cap_inst, std::max(linst, 1), sizeof(int32_t)))) return rc;
-  bool moved = old_pt != b->cap_pt || old_thr != b->cap_thr || old_sel != b->cap_sel || old_inst != b->cap_inst;
+  bool moved = old_pt != b->cap_pt || old_thr != b->cap_thr || old_sel != b->cap_sel || old_inst != b->cap_inst ||
+               old_sp != b->cap_sp;
   if (b->cap_ppt < b->cap_pt) {
-    if (b->d_rr) { HIP_OK(hipFree(b->d_rr)); HIP_OK(hipFree(b->d_pq)); HIP_OK(hipFree(b->d_proj)); }
+    if (b->d_rr) { HIP_OK(hipFree(b->d_rr)); HIP_OK(hipFree(b->d_pq)); }
     HIP_OK(hipMalloc((void**)&b->d_rr, (size_t)b->cap_pt * 8));
     HIP_OK(hipMalloc((void**)&b->d_pq, (size_t)b->cap_pt * 8));
-    HIP_OK(hipMalloc((void**)&b->d_proj, (size_t)b->cap_pt * kProjParts * 8));
     b->cap_ppt = b->cap_pt;
+    moved = true;
+  }
+  if (b->cap_psp < b->cap_sp) {
+    if (b->d_proj) HIP_OK(hipFree(b->d_proj));
+    HIP_OK(hipMalloc((void**)&b->d_proj, (size_t)b->cap_sp * kProjParts * 8));
+    b->cap_psp = b->cap_sp;
     moved = true;
   }
   if (b->cap_pthr < b->cap_thr) {
@@ -353,9 +366,11 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
     moved = true;
   }
   if (!b->d_counts) HIP_OK(hipMalloc((void**)&b->d_counts, sizeof(Counts)));
-  const Counts counts{(int32_t)pt.size(), (int32_t)thr.size(), (int32_t)sel.size(), (int32_t)inst.size()};
+  const Counts counts{(int32_t)pt.size(), (int32_t)thr.size(), (int32_t)sel.size(), (int32_t)inst.size(),
+                      (int32_t)sp.size(), {0, 0, 0}};
   HIP_OK(hipMemcpyAsync(b->d_counts, &counts, sizeof(Counts), hipMemcpyHostToDevice, stream));
   if (!pt.empty()) HIP_OK(hipMemcpyAsync(b->d_pt, pt.data(), pt.size() * sizeof(PtItem), hipMemcpyHostToDevice, stream));
+  if (!sp.empty()) HIP_OK(hipMemcpyAsync(b->d_sp, sp.data(), sp.size() * sizeof(PtItem), hipMemcpyHostToDevice, stream));
   if (!thr.empty()) HIP_OK(hipMemcpyAsync(b->d_thr, thr.data(), thr.size() * sizeof(ThrItem), hipMemcpyHostToDevice, stream));
   if (!sel.empty()) HIP_OK(hipMemcpyAsync(b->d_sel, sel.data(), sel.size() * sizeof(SelItem), hipMemcpyHostToDevice, stream));
   if (!inst.empty()) HIP_OK(hipMemcpyAsync(b->d_inst, inst.data(), inst.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
@@ -368,6 +383,7 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   t.D = b->d_desc;
   t.cnt = b->d_counts;
   t.pt = b->d_pt; t.npt = lpt;
+  t.sp = b->d_sp; t.nsp = lsp;
   t.thr = b->d_thr; t.nthr = lthr;
   t.sel = b->d_sel; t.nsel = lsel;
   t.inst = b->d_inst; t.ninst = linst;
@@ -513,7 +529,7 @@ int32_t sip_batch_destroy(sip_batch* b) {
   drop_graphs(b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   void* dev[] = {b->d_desc, b->d_scal, b->d_pt, b->d_thr, b->d_sel, b->d_inst, b->d_rr, b->d_pq,
-                 b->d_proj, b->d_thrw, b->d_thra, b->d_tie, b->d_counts};
+                 b->d_proj, b->d_thrw, b->d_thra, b->d_tie, b->d_counts, b->d_sp};
   for (void* p : dev) if (p) (void)hipFree(p);
   if (b->h_scal) (void)hipHostFree(b->h_scal);
   delete b;
@@ -831,7 +847,7 @@ int32_t sip_batch_set_tiles(sip_batch* b, int32_t pt_points, int32_t pt_max_item
 
 int32_t sip_batch_items(sip_batch* b, int32_t* npt, int32_t* nthr, int32_t* nsel, int32_t* ninst) {
   if (!b) return SIP_EINVAL;
-  int32_t c[4] = {0, 0, 0, 0};
+  int32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (b->d_counts && hipMemcpy(c, b->d_counts, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess) return SIP_EHIP;
   if (npt) *npt = c[0];
   if (nthr) *nthr = c[1];

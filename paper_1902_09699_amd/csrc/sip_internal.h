@@ -102,7 +102,8 @@ struct InstDesc {
   void* yl; void* vl; void* vh0l; void* v0l; void* y0l;  // identity block p+1
   double* scal;                   // Scal block
   double* log;                    // schedule log or null
-  int32_t pt_begin, pt_end;       // point-item range
+  int32_t pt_begin, pt_end;       // point-item range (RHS, CG)
+  int32_t sp_begin, sp_end;       // projection-item range (finer tiles)
   int32_t log_cap, pad2_;
   SetDesc sets[SIP_MAX_SETS];
 };
@@ -130,7 +131,7 @@ struct Opts {                     // options every kernel needs, by value
 // Live item counts of the work tables, read by the kernels from device
 // memory so a captured graph (launched over the table capacities) stays valid
 // when instances are admitted or retired.
-struct Counts { int32_t npt, nthr, nsel, ninst; };
+struct Counts { int32_t npt, nthr, nsel, ninst, nsp, pad_[3]; };
 
 // Device work tables and partial-sum buffers of one batch.  npt, nthr, nsel
 // and ninst are the launch sizes (capacities); cnt holds the live counts.
@@ -138,6 +139,7 @@ struct Tables {
   const InstDesc* D;
   const Counts* cnt;
   const PtItem* pt; int npt;
+  const PtItem* sp; int nsp;
   const ThrItem* thr; int nthr;
   const SelItem* sel; int nsel;
   const int32_t* inst; int ninst;

@@ -419,8 +419,8 @@ __global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* D, const Counts*
 template <typename T>
 __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* D, const Counts* cnt, const PtItem* items, Opts o, double* parts) {
   __shared__ double lds[lds_sum<8, kSB>()];
-  if ((int)blockIdx.x >= cnt->npt) return;
-  const int iti = xcd_item(blockIdx.x, cnt->npt);
+  if ((int)blockIdx.x >= cnt->nsp) return;
+  const int iti = xcd_item(blockIdx.x, cnt->nsp);
   const PtItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
@@ -1201,7 +1201,7 @@ __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* D, const Coun
       const bool thr = u < p && d.sets[u].thr >= 0;
       double v[8];
       if (!thr) {
-        reduce_range<8>(proj_parts, d.pt_begin, d.pt_end, kProjParts, u * kUnitParts, v, lds);
+        reduce_range<8>(proj_parts, d.sp_begin, d.sp_end, kProjParts, u * kUnitParts, v, lds);
       } else {
         const SetDesc& s = d.sets[u];
         double a[8], b[8];
@@ -1231,8 +1231,8 @@ __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* D, const Coun
   }
   if (check && d.ring) {
     double v[8], w[8];
-    reduce_range<8>(proj_parts, d.pt_begin, d.pt_end, kProjParts, kEvolOff, v, lds);
-    reduce_range<8>(proj_parts, d.pt_begin, d.pt_end, kProjParts, kEvolOff + 8, w, lds);
+    reduce_range<8>(proj_parts, d.sp_begin, d.sp_end, kProjParts, kEvolOff, v, lds);
+    reduce_range<8>(proj_parts, d.sp_begin, d.sp_end, kProjParts, kEvolOff + 8, w, lds);
     if (threadIdx.x == 0) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) { evol[j] = v[j]; evol[8 + j] = w[j]; }
@@ -1334,7 +1334,7 @@ void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
       k_cg_dir<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, j, t.rr_part, t.pq_part, o);
       k_cg_upd<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, j, t.pq_part, t.rr_part);
     }
-    k_proj<T><<<t.npt, kSB, 0, st>>>(t.D, t.cnt, t.pt, o, t.proj_part);
+    if (t.nsp) k_proj<T><<<t.nsp, kSB, 0, st>>>(t.D, t.cnt, t.sp, o, t.proj_part);
   }
   if (t.nthr > 0) {
     k_thr_w<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thrw_part);
@@ -1357,7 +1357,7 @@ void launch_phase(hipStream_t st, const Tables& t, const Opts& o, int phase) {
     case 0: if (t.npt) k_rhs<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, t.rr_part); break;
     case 1: if (t.npt) k_cg_dir<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, 1, t.rr_part, t.pq_part, o); break;
     case 2: if (t.npt) k_cg_upd<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, 1, t.pq_part, t.rr_part); break;
-    case 3: if (t.npt) k_proj<T><<<t.npt, kSB, 0, st>>>(t.D, t.cnt, t.pt, o, t.proj_part); break;
+    case 3: if (t.nsp) k_proj<T><<<t.nsp, kSB, 0, st>>>(t.D, t.cnt, t.sp, o, t.proj_part); break;
     case 4: if (t.nthr) k_thr_w<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thrw_part); break;
     case 5: if (t.nthr) k_thr_apply<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thra_part, t.tie_part); break;
     default: break;
