@@ -565,6 +565,11 @@ int32_t sip_batch_add(sip_batch* b, const sip_grid* g, const sip_set* sets, int3
   d.N = s.N;
   d.stride[2] = 1; d.stride[1] = n[2]; d.stride[0] = n[1] * n[2];
   d.div_x = make_fastdiv((uint32_t)n[2]);
+  {
+    const int64_t grp = 16 / (b->opts.field == SIP_F64 ? 8 : 4);
+    d.vec_ok = ((uintptr_t)x_dev % 16 == 0) ? 1 : 0;
+    d.vec_nb = (n[2] % grp == 0) ? 1 : 0;  // then both row strides (nx, ny*nx) are multiples
+  }
   d.div_y = make_fastdiv((uint32_t)n[1]);
   char* w = s.ws;
   const Layout& L = s.L;

@@ -90,7 +90,9 @@ struct FastDiv {                  // n / d for 0 <= n < 2^31 (Granlund-Montgomer
 };
 
 struct InstDesc {
-  int32_t ndim, nsets, active, pad_;
+  int32_t ndim, nsets, active;
+  int32_t vec_ok;                 // x and the workspace are 16-byte aligned: CG uses 128-bit groups
+  int32_t vec_nb, pad_;           // row strides are multiples of the group: 128-bit y/z neighbours
   int64_t n[3];                   // axis sizes (3D: z, y, x; 2D: z, x, 1)
   int64_t N;
   int64_t stride[3];              // element stride of each axis

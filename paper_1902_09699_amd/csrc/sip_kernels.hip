@@ -211,7 +211,6 @@ __global__ __launch_bounds__(kBlock) void k_init(const InstDesc* D, int inst) {
 // Items are processed in rounds of kPB * U points; the U points of a thread
 // are independent, so their loads are issued together (memory-level
 // parallelism), and __restrict__ lets stores trail loads.
-constexpr int kUcg = 4;
 constexpr int kUset = 2;
 
 // b = sum_{i<=p+1} A_i^T (rho_i y_i + v_i);  r = b - C x;  partial r^T r.
@@ -291,11 +290,109 @@ __global__ __launch_bounds__(kPB) void k_rhs(const InstDesc* D, const Counts* cn
 
 // ---------------------------------------------------------------- CG
 
+// 16-byte groups: a thread owns W = 16 / sizeof(T) consecutive points, loads
+// and stores them with one 128-bit access, takes its x-neighbours from the
+// adjacent lanes (shuffles) and its y/z neighbours with 128-bit loads when
+// the row stride is a multiple of W.  Groups cut by the item end, and
+// instances whose x buffer is not 16-byte aligned, take a per-point path.
+template <typename T>
+struct Grp {
+  static constexpr int W = 16 / (int)sizeof(T);
+};
+
+template <typename T>
+__device__ __forceinline__ void ld16(const T* __restrict__ p, T (&o)[Grp<T>::W]) {
+  const uint4 u = *reinterpret_cast<const uint4*>(p);
+  __builtin_memcpy(o, &u, 16);
+}
+
+template <typename T>
+__device__ __forceinline__ void st16(T* __restrict__ p, const T (&o)[Grp<T>::W]) {
+  uint4 u;
+  __builtin_memcpy(&u, o, 16);
+  *reinterpret_cast<uint4*>(p) = u;
+}
+
+// For the group of W points at P0 (all threads of the wave call this, for the
+// shuffles): c = values at the group (fetchv / fetchs give the value a
+// stencil sees), q = C c.  Returns whether the group was handled as a whole;
+// otherwise the caller runs the per-point path.
+template <typename T, typename FV, typename FS>
+__device__ __forceinline__ bool group_apply_C(int P0, bool full, int lane, const Geo& g, bool vec_nb, FV fetchv,
+                                              FS fetchs, T (&c)[Grp<T>::W], T (&q)[Grp<T>::W], T c0, T cz, T cy,
+                                              T cx) {
+  constexpr int W = Grp<T>::W;
+  if (full) {
+    fetchv(P0, c);
+  } else {
+#pragma unroll
+    for (int e = 0; e < W; ++e) c[e] = 0;
+  }
+  T left = __shfl_up(c[W - 1], 1, 64);
+  T right = __shfl_down(c[0], 1, 64);
+  const int next_full = __shfl_down(full ? 1 : 0, 1, 64);
+  if (!full) return false;
+  int iz, iy, ix0;
+  g.coords(P0, iz, iy, ix0);
+  const bool straddle = ix0 + W > g.nx;
+  if (lane == 0) left = P0 > 0 ? fetchs(P0 - 1) : (T)0;
+  if (lane == 63 || !next_full) right = P0 + W < g.N ? fetchs(P0 + W) : (T)0;
+  T ym[W], yp[W], zm[W], zp[W];
+  const bool vnb = vec_nb && !straddle;
+  if (vnb) {
+    if (iy > 0) fetchv(P0 - g.sy, ym);
+    if (iy < g.ny - 1) fetchv(P0 + g.sy, yp);
+    if (iz > 0) fetchv(P0 - g.sz, zm);
+    if (iz < g.nz - 1) fetchv(P0 + g.sz, zp);
+  }
+#pragma unroll
+  for (int e = 0; e < W; ++e) {
+    int ize = iz, iye = iy, ixe = ix0 + e;
+    if (straddle) g.coords(P0 + e, ize, iye, ixe);
+    const T ce = c[e];
+    const T lft = e > 0 ? c[e > 0 ? e - 1 : 0] : left;
+    const T rgt = e < W - 1 ? c[e < W - 1 ? e + 1 : W - 1] : right;
+    T lx = 0, ly = 0, lz = 0;
+    if (ixe > 0) lx += ce - lft;
+    if (ixe < g.nx - 1) lx += ce - rgt;
+    if (vnb) {
+      if (iye > 0) ly += ce - ym[e];
+      if (iye < g.ny - 1) ly += ce - yp[e];
+      if (ize > 0) lz += ce - zm[e];
+      if (ize < g.nz - 1) lz += ce - zp[e];
+    } else {
+      const int P = P0 + e;
+      if (iye > 0) ly += ce - fetchs(P - g.sy);
+      if (iye < g.ny - 1) ly += ce - fetchs(P + g.sy);
+      if (ize > 0) lz += ce - fetchs(P - g.sz);
+      if (ize < g.nz - 1) lz += ce - fetchs(P + g.sz);
+    }
+    q[e] = c0 * ce + cz * lz + cy * ly + cx * lx;
+  }
+  return true;
+}
+
+// (C f)(P) at one point, f given by a scalar fetch.
+template <typename T, typename FS>
+__device__ __forceinline__ T point_apply_C(int P, const Geo& g, FS f, T fc, T c0, T cz, T cy, T cx) {
+  int iz, iy, ix;
+  g.coords(P, iz, iy, ix);
+  T lz = 0, ly = 0, lx = 0;
+  if (iz > 0) lz += fc - f(P - g.sz);
+  if (iz < g.nz - 1) lz += fc - f(P + g.sz);
+  if (iy > 0) ly += fc - f(P - g.sy);
+  if (iy < g.ny - 1) ly += fc - f(P + g.sy);
+  if (ix > 0) lx += fc - f(P - 1);
+  if (ix < g.nx - 1) lx += fc - f(P + 1);
+  return c0 * fc + cz * lz + cy * ly + cx * lx;
+}
+
 // Step j, first half: beta = rr_j / rr_{j-1}; p_j = r + beta p_{j-1} (p_0 = r);
 // partial p_j^T C p_j with C p_j evaluated on the fly (never stored).
 template <typename T>
 __global__ __launch_bounds__(kPB) void k_cg_dir(const InstDesc* D, const Counts* cnt, const PtItem* items, int j,
                                                 const double* rr_part, double* pq_part, Opts o) {
+  constexpr int W = Grp<T>::W;
   __shared__ double lds[lds_sum<1, kPB>()];
   if ((int)blockIdx.x >= cnt->npt) return;
   const int iti = xcd_item(blockIdx.x, cnt->npt);
@@ -327,27 +424,36 @@ __global__ __launch_bounds__(kPB) void k_cg_dir(const InstDesc* D, const Counts*
   const T c0 = (T)S[S_C0], cz = (T)S[S_CAX + 0], cy = (T)S[S_CAX + 1], cx = (T)S[S_CAX + 2];
   const T bt = (T)beta;
   const bool first = j == 0;
+  auto fs = [&](int Q) -> T { return first ? r[Q] : r[Q] + bt * pin[Q]; };
+  auto fv = [&](int Q, T (&o)[W]) {
+    ld16<T>(r + Q, o);
+    if (!first) {
+      T b[W];
+      ld16<T>(pin + Q, b);
+#pragma unroll
+      for (int e = 0; e < W; ++e) o[e] += bt * b[e];
+    }
+  };
+  const int lane = threadIdx.x & 63;
   double acc[1] = {0.0};
   const int end = it.begin + it.len;
-  for (int base = it.begin; base < end; base += kPB * kUcg) {
+  for (int base = it.begin; base < end; base += kPB * W) {
+    const int P0 = base + (int)threadIdx.x * W;
+    const bool full = d.vec_ok && P0 + W <= end;
+    T c[W], q[W];
+    if (group_apply_C<T>(P0, full, lane, g, d.vec_nb, fv, fs, c, q, c0, cz, cy, cx)) {
+      st16<T>(pout + P0, c);
 #pragma unroll
-    for (int u = 0; u < kUcg; ++u) {
-      const int P = base + u * kPB + (int)threadIdx.x;
-      if (P >= end) continue;
-      int iz, iy, ix;
-      g.coords(P, iz, iy, ix);
-      auto pn = [&](int Q) { return first ? r[Q] : r[Q] + bt * pin[Q]; };
-      const T pc = pn(P);
-      T lz = 0, ly = 0, lx = 0;
-      if (iz > 0) lz += pc - pn(P - g.sz);
-      if (iz < g.nz - 1) lz += pc - pn(P + g.sz);
-      if (iy > 0) ly += pc - pn(P - g.sy);
-      if (iy < g.ny - 1) ly += pc - pn(P + g.sy);
-      if (ix > 0) lx += pc - pn(P - 1);
-      if (ix < g.nx - 1) lx += pc - pn(P + 1);
-      const T q = c0 * pc + cz * lz + cy * ly + cx * lx;
-      pout[P] = pc;
-      acc[0] += (double)pc * (double)q;
+      for (int e = 0; e < W; ++e) acc[0] += (double)c[e] * (double)q[e];
+    } else {
+      for (int e = 0; e < W; ++e) {
+        const int P = P0 + e;
+        if (P >= end) break;
+        const T pc = fs(P);
+        const T qq = point_apply_C<T>(P, g, fs, pc, c0, cz, cy, cx);
+        pout[P] = pc;
+        acc[0] += (double)pc * (double)qq;
+      }
     }
   }
   block_sum<1, kPB>(acc, lds);
@@ -359,6 +465,7 @@ __global__ __launch_bounds__(kPB) void k_cg_dir(const InstDesc* D, const Counts*
 template <typename T>
 __global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* D, const Counts* cnt, const PtItem* items, int j,
                                                 const double* pq_part, double* rr_part) {
+  constexpr int W = Grp<T>::W;
   __shared__ double lds[lds_sum<1, kPB>()];
   if ((int)blockIdx.x >= cnt->npt) return;
   const int iti = xcd_item(blockIdx.x, cnt->npt);
@@ -380,28 +487,38 @@ __global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* D, const Counts*
   const T* __restrict__ p = (const T*)d.p[j & 1];
   const T c0 = (T)S[S_C0], cz = (T)S[S_CAX + 0], cy = (T)S[S_CAX + 1], cx = (T)S[S_CAX + 2];
   const T al = (T)alpha;
+  auto fs = [&](int Q) -> T { return p[Q]; };
+  auto fv = [&](int Q, T (&o)[W]) { ld16<T>(p + Q, o); };
+  const int lane = threadIdx.x & 63;
   double acc[1] = {0.0};
   const int end = it.begin + it.len;
-  for (int base = it.begin; base < end; base += kPB * kUcg) {
+  for (int base = it.begin; base < end; base += kPB * W) {
+    const int P0 = base + (int)threadIdx.x * W;
+    const bool full = d.vec_ok && P0 + W <= end;
+    T c[W], q[W];
+    if (group_apply_C<T>(P0, full, lane, g, d.vec_nb, fv, fs, c, q, c0, cz, cy, cx)) {
+      T xv[W], rv[W];
+      ld16<T>(x + P0, xv);
+      ld16<T>(r + P0, rv);
 #pragma unroll
-    for (int u = 0; u < kUcg; ++u) {
-      const int P = base + u * kPB + (int)threadIdx.x;
-      if (P >= end) continue;
-      int iz, iy, ix;
-      g.coords(P, iz, iy, ix);
-      const T pc = p[P];
-      T lz = 0, ly = 0, lx = 0;
-      if (iz > 0) lz += pc - p[P - g.sz];
-      if (iz < g.nz - 1) lz += pc - p[P + g.sz];
-      if (iy > 0) ly += pc - p[P - g.sy];
-      if (iy < g.ny - 1) ly += pc - p[P + g.sy];
-      if (ix > 0) lx += pc - p[P - 1];
-      if (ix < g.nx - 1) lx += pc - p[P + 1];
-      const T q = c0 * pc + cz * lz + cy * ly + cx * lx;
-      x[P] = x[P] + al * pc;
-      const T rv = r[P] - al * q;
-      r[P] = rv;
-      acc[0] += (double)rv * (double)rv;
+      for (int e = 0; e < W; ++e) {
+        xv[e] = xv[e] + al * c[e];
+        rv[e] = rv[e] - al * q[e];
+        acc[0] += (double)rv[e] * (double)rv[e];
+      }
+      st16<T>(x + P0, xv);
+      st16<T>(r + P0, rv);
+    } else {
+      for (int e = 0; e < W; ++e) {
+        const int P = P0 + e;
+        if (P >= end) break;
+        const T pc = p[P];
+        const T qq = point_apply_C<T>(P, g, fs, pc, c0, cz, cy, cx);
+        x[P] = x[P] + al * pc;
+        const T rv = r[P] - al * qq;
+        r[P] = rv;
+        acc[0] += (double)rv * (double)rv;
+      }
     }
   }
   block_sum<1, kPB>(acc, lds);
