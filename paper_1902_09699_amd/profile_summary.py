@@ -51,11 +51,44 @@ def counter_table(con):
     return "\n".join(out)
 
 
+def counter_means(con, counter):
+    """{short kernel name: mean counter value per dispatch}."""
+    cols = [c[1] for c in con.execute("pragma table_info(counters_collection)")]
+    kcol = "kernel_name" if "kernel_name" in cols else "name"
+    vcol = "value" if "value" in cols else "counter_value"
+    q = f"select {kcol}, avg({vcol}) from counters_collection where counter_name = ? group by 1"
+    return {_short(n): v for n, v in con.execute(q, (counter,))}
+
+
+def traffic(fetch_path, write_path, kernel, copy_bytes):
+    """HBM bytes per launch of `kernel` from a FETCH_SIZE run and a
+    WRITE_SIZE run (KiB per dispatch), each scaled by what the same counter
+    reads for the plain copy kernel k_copy that reads and writes copy_bytes."""
+    f = counter_means(_db(fetch_path), "FETCH_SIZE")
+    w = counter_means(_db(write_path), "WRITE_SIZE")
+    kf = next(v for k, v in f.items() if k.startswith(kernel))
+    kw = next(v for k, v in w.items() if k.startswith(kernel))
+    cf = f["k_copy"] * 1024.0 / copy_bytes
+    cw = w["k_copy"] * 1024.0 / copy_bytes
+    read = kf * 1024.0 / cf
+    written = kw * 1024.0 / cw
+    return {"kernel": kernel, "fetch_kib": kf, "write_kib": kw, "copy_fetch_factor": cf,
+            "copy_write_factor": cw, "hbm_bytes_read": read, "hbm_bytes_written": written,
+            "hbm_bytes_per_launch": read + written}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("path")
     ap.add_argument("--top", type=int, default=20)
+    ap.add_argument("--write-db", help="with --kernel: traffic from a FETCH_SIZE db (path) and this WRITE_SIZE db")
+    ap.add_argument("--kernel")
+    ap.add_argument("--copy-bytes", type=float, default=256 * (1 << 20))
     a = ap.parse_args()
+    if a.write_db:
+        import json
+        print(json.dumps(traffic(a.path, a.write_db, a.kernel, a.copy_bytes), indent=1))
+        return
     con = _db(a.path)
     ct = counter_table(con)
     print(ct if ct else kernel_table(con, a.top))

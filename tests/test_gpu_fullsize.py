@@ -1,0 +1,85 @@
+"""Parity at the benchmark sizes (341x1361 float32 with four sets, 200x200x100
+float32 with three sets): lockstep iterations against the FP64 oracle in the
+tile configurations the benchmark uses, covering an adapt iteration (k = 3,
+the first with a snapshot) and every state array; plus properties of a
+complete benchmark-length run that hold at any size."""
+import numpy as np
+import pytest
+
+from oracle import parsdmm as orc
+from paper_1902_09699_amd import sip
+from paper_1902_09699_amd import workloads as wl
+from tests.gpu_util import Slot, rel, sync_oracle
+
+pytestmark = pytest.mark.gpu
+
+TILES = {"default": (2048, 512, 2048, 512), "tuned": (1024, 256, 2048, 256)}
+
+
+def _load(name):
+    if name == "layered2d":
+        m, sets, field, iters = wl.layered2d_four_sets()
+    else:
+        m, sets, field, iters = wl.smooth3d_box_tv_lat()
+    m = wl.rounded(m, field)
+    return m, wl.finalize(m, sets), field, iters
+
+
+@pytest.mark.parametrize("name,tiles", [("layered2d", "default"), ("layered2d", "tuned"), ("smooth3d", "tuned")])
+def test_fullsize_lockstep(name, tiles):
+    m, sets, field, iters = _load(name)
+    print(f"\n[fullsize] {name} {m.shape} tiles={TILES[tiles]}", flush=True)
+    sl = Slot(m, sets, field, dict(max_iter=iters, cg_max=10, cg_fixed=1), tiles=TILES[tiles])
+    prob = orc.Problem(m, m.shape, sets)
+    oo = orc.Options(max_iter=iters, cg_max=10, cg_fixed=True)
+    st = orc.initial_state(prob, oo)
+    for it in range(3):
+        sync_oracle(sl, prob, st)
+        orc.iterate(prob, st, oo)
+        sl.batch.run(1)
+        ex = rel(sl.x(), st.x)
+        worst = ex
+        for i in range(len(sets) + 1):
+            yg, yo = sl.arr(sip.FIELD_Y, i), st.y[i]
+            vg, vo = sl.arr(sip.FIELD_V, i), st.v[i]
+            if i < len(sets) and sets[i]["kind"] == "card":
+                a = np.abs(st.w_last[i])
+                tk = np.sort(a)[::-1][sets[i]["k"] - 1]
+                mask = np.abs(a - tk) > 1e-4 * tk
+                assert np.array_equal((yg != 0)[mask], (yo != 0)[mask])
+                assert (yg != 0).sum() <= sets[i]["k"]
+                yg, yo, vg, vo = yg[mask], yo[mask], vg[mask], vo[mask]
+            op = "I" if i == len(sets) else sets[i]["op"]
+            ncomp = {"I": 1, "DZ": 1, "DY": 1, "DX": 1, "GRAD": m.ndim, "LAT": m.ndim - 1}[op]
+            anorm = 1.0 if op == "I" else 2.0 * np.sqrt(ncomp)
+            scale = max(np.linalg.norm(yo), np.linalg.norm(st.w_last[i]), anorm * np.linalg.norm(st.x))
+            ey = np.linalg.norm(yg - yo) / scale
+            ev = np.linalg.norm(vg - vo) / max(np.linalg.norm(vo), scale)
+            worst = max(worst, ey, ev)
+            assert ey <= 1e-5 and ev <= 1e-4, (it, i, ey, ev)
+        assert ex <= 1e-5, (it, ex)
+        print(f"[fullsize] {name} iteration {it + 1}: worst rel err {worst:.2e}", flush=True)
+
+
+def test_fullsize_run_properties():
+    """A complete 341x1361 run: status, iteration and CG-step counts, and the
+    final y of every set lies in its set (the projections are exact)."""
+    m, sets, field, iters = _load("layered2d")
+    sl = Slot(m, sets, field, dict(max_iter=iters, cg_max=10, cg_fixed=1), tiles=TILES["tuned"])
+    sl.batch.run(iters)
+    res = sl.batch.result(sl.slot)
+    assert res["status"] == 0 and res["iters"] == iters and 10 * (iters - 1) <= res["cg_steps"] <= 10 * iters
+    y_box = sl.arr(sip.FIELD_Y, 0)
+    assert y_box.min() >= 1.5 and y_box.max() <= 4.5
+    y_mono = sl.arr(sip.FIELD_Y, 1)
+    assert y_mono.min() >= 0.0
+    y_l1 = sl.arr(sip.FIELD_Y, 2)
+    assert np.abs(y_l1).sum() <= sets[2]["tau"] * (1 + 1e-5)
+    y_card = sl.arr(sip.FIELD_Y, 3)
+    assert (y_card != 0).sum() <= sets[3]["k"]
+    # x approaches the intersection: transform-domain infeasibility is small
+    x = sl.x()
+    prob = orc.Problem(m, m.shape, sets)
+    print(f"\n[fullsize] rho {np.round(res['rho'], 3)}, box violation "
+          f"{max(0.0, 1.5 - x.min(), x.max() - 4.5):.2e}", flush=True)
+    assert np.abs(prob.A[2] @ x).sum() <= 1.05 * sets[2]["tau"]
