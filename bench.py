@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--batched-count", type=int, default=256)
     ap.add_argument("--copy-mb", type=int, default=1024, help="plain-copy reference size (0: skip)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles")
+    ap.add_argument("--tiles", default=None,
+                    help="fixed tiles pt_points,pt_max_items,thr_points,thr_max_items (no autotune)")
     return ap.parse_args()
 
 
@@ -161,7 +163,10 @@ def main():
     chunk = min(args.graph_iters, iters)
     n_pts = sum(m.size for m, _ in insts)
     tiles = None
-    if not args.no_autotune:
+    if args.tiles:
+        tiles = tuple(int(v) for v in args.tiles.split(","))
+        batch.set_tiles(*tiles)
+    elif not args.no_autotune:
         from paper_1902_09699_amd import autotune
         tiles, tile_ms = autotune.tune(batch, slots, ms, field, [m.shape for m, _ in insts], use_cache=False,
                                        cache=None)

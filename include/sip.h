@@ -190,10 +190,13 @@ int32_t sip_batch_result(sip_batch* b, int32_t slot, sip_result* res, void* stre
  * stream ordering rules as any device memory).  which: 0 y_i, 1 v_i,
  * 2 vhat snapshot, 3 v snapshot, 4 y snapshot (i = nsets means the identity
  * block p+1); 5 r, 6 x-snapshot buffer 0, 7 x-snapshot buffer 1.  Set
- * arrays hold one N-element block per operator component (z, y, x order)
- * with the unused last layer along the component's axis kept at zero. */
+ * arrays hold one block per operator component (z, y, x order), block c
+ * starting at element c * comp_stride (comp_stride >= N, 256-byte aligned);
+ * the first N entries of a block are the grid points, the unused last layer
+ * along the component's axis and the tail padding are kept at zero.  count
+ * is the number of elements of the whole array. */
 int32_t sip_batch_field(sip_batch* b, int32_t slot, int32_t which, int32_t set,
-                        void** dev_ptr, int64_t* count);
+                        void** dev_ptr, int64_t* count, int64_t* comp_stride);
 
 /* Read / overwrite a slot's scalars: rho and gamma (nsets+1 each), the
  * iteration counter k and whether adapt-rho-gamma holds a snapshot. */

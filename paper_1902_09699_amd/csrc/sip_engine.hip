@@ -563,6 +563,10 @@ int32_t sip_batch_add(sip_batch* b, const sip_grid* g, const sip_set* sets, int3
   d.ndim = g->ndim; d.nsets = nsets; d.active = 1;
   for (int a = 0; a < 3; ++a) { d.n[a] = n[a]; d.hinv[a] = 1.0 / h[a]; d.h2inv[a] = 1.0 / (h[a] * h[a]); }
   d.N = s.N;
+  {
+    const int64_t esz = b->opts.field == SIP_F64 ? 8 : 4;
+    d.cs = align_up(s.N * esz) / esz;
+  }
   d.stride[2] = 1; d.stride[1] = n[2]; d.stride[0] = n[1] * n[2];
   d.div_x = make_fastdiv((uint32_t)n[2]);
   {
@@ -679,8 +683,10 @@ int32_t sip_batch_remove(sip_batch* b, int32_t slot, sip_result* res, void* stre
   return SIP_OK;
 }
 
-int32_t sip_batch_field(sip_batch* b, int32_t slot, int32_t which, int32_t set, void** ptr, int64_t* count) {
+int32_t sip_batch_field(sip_batch* b, int32_t slot, int32_t which, int32_t set, void** ptr, int64_t* count,
+                        int64_t* comp_stride) {
   if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used || !ptr || !count) return SIP_EINVAL;
+  if (comp_stride) *comp_stride = b->slots[slot].desc.cs;
   const Slot& s = b->slots[slot];
   const InstDesc& d = s.desc;
   *ptr = nullptr;
@@ -699,7 +705,7 @@ int32_t sip_batch_field(sip_batch* b, int32_t slot, int32_t which, int32_t set, 
     }
     if (!p) return SIP_EINVAL;
     *ptr = p;
-    *count = nc * s.N;
+    *count = nc * d.cs;
     return SIP_OK;
   }
   void* p = which == 5 ? d.r : which == 6 ? d.xs[0] : which == 7 ? d.xs[1] : nullptr;

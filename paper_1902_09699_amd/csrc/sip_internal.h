@@ -95,6 +95,7 @@ struct InstDesc {
   int32_t vec_nb, pad_;           // row strides are multiples of the group: 128-bit y/z neighbours
   int64_t n[3];                   // axis sizes (3D: z, y, x; 2D: z, x, 1)
   int64_t N;
+  int64_t cs;                     // element stride between operator components (N rounded up, 256-byte aligned)
   int64_t stride[3];              // element stride of each axis
   FastDiv div_x, div_y;           // point -> (row, x), row -> (z, y)
   double hinv[3], h2inv[3];

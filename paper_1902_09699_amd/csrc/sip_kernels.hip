@@ -114,11 +114,11 @@ template <typename T> __device__ __forceinline__ int digit_shift(int d) {
 }
 
 struct Geo {
-  int nz, ny, nx, sy, sz, N;
+  int nz, ny, nx, sy, sz, N, cs;
   FastDiv dx, dy;
   __device__ explicit Geo(const InstDesc& d)
       : nz((int)d.n[0]), ny((int)d.n[1]), nx((int)d.n[2]), sy((int)d.stride[1]), sz((int)d.stride[0]),
-        N((int)d.N), dx(d.div_x), dy(d.div_y) {}
+        N((int)d.N), cs((int)d.cs), dx(d.div_x), dy(d.div_y) {}
   __device__ __forceinline__ void coords(int P, int& iz, int& iy, int& ix) const {
     const uint32_t row = fastdiv((uint32_t)P, dx);
     ix = P - (int)row * nx;
@@ -178,7 +178,7 @@ __device__ __forceinline__ bool comp_valid(int axis, int iz, int iy, int ix, con
 // Admission of one instance: x = m, y_i = A_i m, v_i = 0, y_{p+1} = m,
 // v_{p+1} = 0, x-history slot 0 = m.  d.m is the instance's private copy of m.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_init(const InstDesc* D, int inst) {
+__global__ __launch_bounds__(kBlock) void k_init(const InstDesc* __restrict__ D, int inst) {
   const InstDesc& d = D[inst];
   const Geo g(d);
   const T* m = (const T*)d.m;
@@ -199,177 +199,300 @@ __global__ __launch_bounds__(kBlock) void k_init(const InstDesc* D, int inst) {
       for (int c = 0; c < s.ncomp; ++c) {
         T val = 0;
         if (!comp_value<T>(m, P, s.axis[c], iz, iy, ix, g, d, val)) val = 0;
-        ((T*)s.y)[(size_t)c * g.N + P] = val;
-        ((T*)s.v)[(size_t)c * g.N + P] = 0;
+        ((T*)s.y)[(size_t)c * g.cs + P] = val;
+        ((T*)s.v)[(size_t)c * g.cs + P] = 0;
       }
     }
   }
 }
 
-// -------------------------------------------------------- RHS + residual
+// ------------------------------------------------------- 16-byte groups
 
-// Items are processed in rounds of kPB * U points; the U points of a thread
-// are independent, so their loads are issued together (memory-level
-// parallelism), and __restrict__ lets stores trail loads.
-constexpr int kUset = 2;
-
-// b = sum_{i<=p+1} A_i^T (rho_i y_i + v_i);  r = b - C x;  partial r^T r.
-template <typename T>
-__global__ __launch_bounds__(kPB) void k_rhs(const InstDesc* D, const Counts* cnt, const PtItem* items, double* rr_part) {
-  __shared__ double lds[lds_sum<1, kPB>()];
-  if ((int)blockIdx.x >= cnt->npt) return;
-  const int iti = xcd_item(blockIdx.x, cnt->npt);
-  const PtItem it = items[iti];
-  const InstDesc& d = D[it.inst];
-  const double* S = d.scal;
-  if (!inst_live(S)) return;
-  const Geo g(d);
-  const T* __restrict__ x = (const T*)d.x;
-  T* __restrict__ r = (T*)d.r;
-  const T* __restrict__ yl = (const T*)d.yl;
-  const T* __restrict__ vl = (const T*)d.vl;
-  const T rl = (T)S[S_RHO + d.nsets];
-  const T c0 = (T)S[S_C0], cz = (T)S[S_CAX + 0], cy = (T)S[S_CAX + 1], cx = (T)S[S_CAX + 2];
-  double acc[1] = {0.0};
-  const int end = it.begin + it.len;
-  for (int base = it.begin; base < end; base += kPB * kUset) {
-    int Pu[kUset], iz[kUset], iy[kUset], ix[kUset];
-    T b[kUset];
-#pragma unroll
-    for (int u = 0; u < kUset; ++u) {
-      Pu[u] = base + u * kPB + (int)threadIdx.x;
-      const int P = Pu[u] < end ? Pu[u] : end - 1;
-      g.coords(P, iz[u], iy[u], ix[u]);
-      b[u] = rl * yl[P] + vl[P];
-    }
-    for (int si = 0; si < d.nsets; ++si) {
-      const SetDesc& s = d.sets[si];
-      const T rs = (T)S[S_RHO + si];
-      for (int c = 0; c < s.ncomp; ++c) {
-        const T* __restrict__ y = (const T*)s.y + (size_t)c * g.N;
-        const T* __restrict__ v = (const T*)s.v + (size_t)c * g.N;
-        const int a = s.axis[c];
-        const T hi = (T)d.hinv[a < 0 ? 0 : a];
-#pragma unroll
-        for (int u = 0; u < kUset; ++u) {
-          const int P = Pu[u] < end ? Pu[u] : end - 1;
-          if (a < 0) {
-            b[u] += rs * y[P] + v[P];
-          } else {
-            const int ia = a == 0 ? iz[u] : (a == 1 ? iy[u] : ix[u]);
-            const int na = a == 0 ? g.nz : (a == 1 ? g.ny : g.nx);
-            const int st = a == 0 ? g.sz : (a == 1 ? g.sy : 1);
-            T t = 0;
-            if (ia > 0) t += rs * y[P - st] + v[P - st];
-            if (ia < na - 1) t -= rs * y[P] + v[P];
-            b[u] += t * hi;
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kUset; ++u) {
-      if (Pu[u] >= end) continue;
-      const int P = Pu[u];
-      const T xc = x[P];
-      T lz = 0, ly = 0, lx = 0;
-      if (iz[u] > 0) lz += xc - x[P - g.sz];
-      if (iz[u] < g.nz - 1) lz += xc - x[P + g.sz];
-      if (iy[u] > 0) ly += xc - x[P - g.sy];
-      if (iy[u] < g.ny - 1) ly += xc - x[P + g.sy];
-      if (ix[u] > 0) lx += xc - x[P - 1];
-      if (ix[u] < g.nx - 1) lx += xc - x[P + 1];
-      const T rv = b[u] - (c0 * xc + cz * lz + cy * ly + cx * lx);
-      r[P] = rv;
-      acc[0] += (double)rv * (double)rv;
-    }
-  }
-  block_sum<1, kPB>(acc, lds);
-  if (threadIdx.x == 0) rr_part[iti] = acc[0];
-}
-
-// ---------------------------------------------------------------- CG
-
-// 16-byte groups: a thread owns W = 16 / sizeof(T) consecutive points, loads
-// and stores them with one 128-bit access, takes its x-neighbours from the
-// adjacent lanes (shuffles) and its y/z neighbours with 128-bit loads when
-// the row stride is a multiple of W.  Groups cut by the item end, and
-// instances whose x buffer is not 16-byte aligned, take a per-point path.
+// 16-byte groups: a thread owns W = 16 / sizeof(T) consecutive points of an
+// item and loads / stores them with one 128-bit global access.  Neighbours
+// along x come from the adjacent lanes (shuffles; a lane whose neighbour lane
+// has no group loads the value itself).  A neighbour window along y or z (the
+// W values at P0 +- stride) starts (stride mod W) into an aligned group: the
+// one or two aligned groups it covers are loaded and the window is picked
+// out with the wave-uniform offset, so the loads of a round are all issued
+// before any of them is waited for.  Every group address is aligned and
+// starts in [0, N); an address outside is replaced by the lane's own group,
+// whose values are then unused.  State arrays are padded to whole groups;
+// the caller's x is not, so its last, partial group is read element by
+// element (indexes clamped to N - 1) and written element by element.
 template <typename T>
 struct Grp {
   static constexpr int W = 16 / (int)sizeof(T);
 };
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const u32x4 g_cu32x4;
+typedef __attribute__((address_space(1))) u32x4 g_u32x4;
+
 template <typename T>
-__device__ __forceinline__ void ld16(const T* __restrict__ p, T (&o)[Grp<T>::W]) {
-  const uint4 u = *reinterpret_cast<const uint4*>(p);
+__device__ __forceinline__ void ld16(const T* p, T (&o)[Grp<T>::W]) {
+  const u32x4 u = *(g_cu32x4*)p;
   __builtin_memcpy(o, &u, 16);
 }
 
 template <typename T>
-__device__ __forceinline__ void st16(T* __restrict__ p, const T (&o)[Grp<T>::W]) {
-  uint4 u;
+__device__ __forceinline__ void st16(T* p, const T (&o)[Grp<T>::W]) {
+  u32x4 u;
   __builtin_memcpy(&u, o, 16);
-  *reinterpret_cast<uint4*>(p) = u;
+  *(g_u32x4*)p = u;
 }
 
-// For the group of W points at P0 (all threads of the wave call this, for the
-// shuffles): c = values at the group (fetchv / fetchs give the value a
-// stencil sees), q = C c.  Returns whether the group was handled as a whole;
-// otherwise the caller runs the per-point path.
-template <typename T, typename FV, typename FS>
-__device__ __forceinline__ bool group_apply_C(int P0, bool full, int lane, const Geo& g, bool vec_nb, FV fetchv,
-                                              FS fetchs, T (&c)[Grp<T>::W], T (&q)[Grp<T>::W], T c0, T cz, T cy,
-                                              T cx) {
+// The first W - 1 values of an aligned group (12 or 8 bytes).
+typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+typedef __attribute__((address_space(1))) const u32x3 g_cu32x3;
+
+template <typename T>
+__device__ __forceinline__ void ld_head(const T* p, T (&o)[Grp<T>::W]) {
+  if constexpr (sizeof(T) == 4) {
+    const u32x3 u = *(g_cu32x3*)p;
+    __builtin_memcpy(o, &u, 12);
+    o[3] = (T)0;
+  } else {
+    o[0] = *(__attribute__((address_space(1))) const T*)p;
+    o[1] = (T)0;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p) {
+  return *(__attribute__((address_space(1))) const T*)p;
+}
+
+// Group loads that stay inside an unpadded array of N values (the values
+// past N - 1 are copies of the last one and are never used).
+template <typename T>
+__device__ __forceinline__ void ld16p(const T* p, int G, int N, T (&o)[Grp<T>::W]) {
   constexpr int W = Grp<T>::W;
-  if (full) {
-    fetchv(P0, c);
+  if (G + W <= N) {
+    ld16<T>(p + G, o);
   } else {
 #pragma unroll
-    for (int e = 0; e < W; ++e) c[e] = 0;
+    for (int e = 0; e < W; ++e) o[e] = ldg(p + (G + e < N ? G + e : N - 1));
   }
-  T left = __shfl_up(c[W - 1], 1, 64);
-  T right = __shfl_down(c[0], 1, 64);
-  const int next_full = __shfl_down(full ? 1 : 0, 1, 64);
-  if (!full) return false;
-  int iz, iy, ix0;
-  g.coords(P0, iz, iy, ix0);
-  const bool straddle = ix0 + W > g.nx;
-  if (lane == 0) left = P0 > 0 ? fetchs(P0 - 1) : (T)0;
-  if (lane == 63 || !next_full) right = P0 + W < g.N ? fetchs(P0 + W) : (T)0;
-  T ym[W], yp[W], zm[W], zp[W];
-  const bool vnb = vec_nb && !straddle;
-  if (vnb) {
-    if (iy > 0) fetchv(P0 - g.sy, ym);
-    if (iy < g.ny - 1) fetchv(P0 + g.sy, yp);
-    if (iz > 0) fetchv(P0 - g.sz, zm);
-    if (iz < g.nz - 1) fetchv(P0 + g.sz, zp);
+}
+
+template <typename T>
+__device__ __forceinline__ void ld_headp(const T* p, int G, int N, T (&o)[Grp<T>::W]) {
+  constexpr int W = Grp<T>::W;
+  if (G + W - 1 <= N) {
+    ld_head<T>(p + G, o);
+  } else {
+#pragma unroll
+    for (int e = 0; e < W - 1; ++e) o[e] = ldg(p + (G + e < N ? G + e : N - 1));
+    o[W - 1] = (T)0;
   }
+}
+
+// Store of the first cnt values of a group.
+template <typename T>
+__device__ __forceinline__ void st16p(T* p, int G, int cnt, const T (&o)[Grp<T>::W]) {
+  constexpr int W = Grp<T>::W;
+  if (cnt == W) {
+    st16<T>(p + G, o);
+  } else {
+#pragma unroll
+    for (int e = 0; e < W; ++e)
+      if (e < cnt) *(__attribute__((address_space(1))) T*)(p + G + e) = o[e];
+  }
+}
+
+// o[e] = (A followed by B)[e + off] for a wave-uniform off in [0, W).
+template <typename T>
+__device__ __forceinline__ void pick(int off, const T (&A)[Grp<T>::W], const T (&B)[Grp<T>::W],
+                                     T (&o)[Grp<T>::W]) {
+  constexpr int W = Grp<T>::W;
 #pragma unroll
   for (int e = 0; e < W; ++e) {
-    int ize = iz, iye = iy, ixe = ix0 + e;
-    if (straddle) g.coords(P0 + e, ize, iye, ixe);
+    T v = A[e];
+#pragma unroll
+    for (int k = 1; k < W; ++k) {
+      const T c = e + k < W ? A[(e + k) % W] : B[(e + k) % W];
+      v = off == k ? c : v;
+    }
+    o[e] = v;
+  }
+}
+
+// A stencil operand: value(Q) = a[0][Q] (NA = 1) or a[0][Q] + beta a[1][Q].
+template <typename T, int NA>
+struct Src {
+  const T* a[NA];
+  T beta;
+};
+
+template <typename T, int NA>
+__device__ __forceinline__ void src_load(const Src<T, NA>& f, int G, int N, T (&R)[NA][Grp<T>::W]) {
+#pragma unroll
+  for (int q = 0; q < NA; ++q) ld16p<T>(f.a[q], G, N, R[q]);
+}
+
+template <typename T, int NA>
+__device__ __forceinline__ void src_mix(const Src<T, NA>& f, const T (&R)[NA][Grp<T>::W], T (&o)[Grp<T>::W]) {
+#pragma unroll
+  for (int e = 0; e < Grp<T>::W; ++e) o[e] = NA == 1 ? R[0][e] : R[0][e] + f.beta * R[NA - 1][e];
+}
+
+template <typename T, int NA>
+__device__ __forceinline__ void src_load_head(const Src<T, NA>& f, int G, int N, T (&R)[NA][Grp<T>::W]) {
+#pragma unroll
+  for (int q = 0; q < NA; ++q) ld_headp<T>(f.a[q], G, N, R[q]);
+}
+
+template <typename T, int NA>
+__device__ __forceinline__ T src_one(const Src<T, NA>& f, const T (&r)[NA]) {
+  return NA == 1 ? r[0] : r[0] + f.beta * r[NA - 1];
+}
+
+// Loads of the window at P0c + delta (off = (P0c + delta) mod W).  AL: the
+// row strides are multiples of W, so off = 0 and one aligned group suffices.
+template <typename T, int NA, bool AL>
+__device__ __forceinline__ void win_load(const Src<T, NA>& f, int P0c, int delta, int off, int N,
+                                         T (&A)[NA][Grp<T>::W], T (&B)[NA][Grp<T>::W]) {
+  constexpr int W = Grp<T>::W;
+  const int ga = P0c + delta - off, gb = ga + W;
+  src_load<T, NA>(f, (unsigned)ga < (unsigned)N ? ga : P0c, N, A);
+  if constexpr (!AL) src_load_head<T, NA>(f, (unsigned)gb < (unsigned)N ? gb : P0c, N, B);  // pick() reads B[0..W-2]
+}
+
+template <typename T, int NA, bool AL>
+__device__ __forceinline__ void win_get(const Src<T, NA>& f, int off, const T (&A)[NA][Grp<T>::W],
+                                        const T (&B)[NA][Grp<T>::W], T (&o)[Grp<T>::W]) {
+  constexpr int W = Grp<T>::W;
+  if constexpr (AL) {
+    src_mix<T, NA>(f, A, o);
+  } else {
+    T a[W], b[W];
+    src_mix<T, NA>(f, A, a);
+    src_mix<T, NA>(f, B, b);
+    pick<T>(off, a, b, o);
+  }
+}
+
+// Window offsets of the four y/z directions.
+struct Offs {
+  int ym, yp, zm, zp;
+};
+
+template <typename T>
+__device__ __forceinline__ Offs offs_of(const Geo& g) {
+  constexpr int W = Grp<T>::W;
+  Offs o;
+  o.yp = g.sy & (W - 1);
+  o.ym = (W - o.yp) & (W - 1);
+  o.zp = g.sz & (W - 1);
+  o.zm = (W - o.zp) & (W - 1);
+  return o;
+}
+
+// Row strides are multiples of W (every window offset is 0).
+template <typename T>
+__device__ __forceinline__ bool rows_aligned(const Geo& g) {
+  return (g.nx & (Grp<T>::W - 1)) == 0;
+}
+
+// Whether the instance uses the group path (its x buffer is 16-byte aligned).
+__device__ __forceinline__ bool item_grouped(const InstDesc& d) { return d.vec_ok != 0; }
+
+// One thread's group of one round.
+struct GLane {
+  int P0c;        // the group's first point (a safe aligned group if !vec)
+  int cnt;        // points of the group inside the item (1..W if vec)
+  bool vec;       // the group has points in the item
+  bool next_vec;  // so has the next lane's
+  int iz, iy, ix0;
+  bool straddle;  // the group crosses the end of an x row
+};
+
+template <typename T>
+__device__ __forceinline__ GLane glane(int P0, int begin, int end, const Geo& g) {
+  constexpr int W = Grp<T>::W;
+  GLane L;
+  L.vec = P0 < end;
+  L.cnt = end - P0 < W ? end - P0 : W;
+  L.next_vec = __shfl_down(L.vec ? 1 : 0, 1, 64) != 0;
+  L.P0c = L.vec ? P0 : begin;
+  g.coords(L.P0c, L.iz, L.iy, L.ix0);
+  L.straddle = L.ix0 + W > g.nx;
+  return L;
+}
+
+// c = the operand at the lane's group, q = C c (all lanes of the wave call
+// this; the result is meaningful where L.vec).  HY: the grid has a y axis
+// (3D); z windows are always read (clamped and unused when nz = 1).
+template <typename T, int NA, bool HY, bool AL>
+__device__ __forceinline__ void group_C_v(const Src<T, NA>& f, const GLane& L, int lane, const Geo& g,
+                                          const Offs& of, T (&c)[Grp<T>::W], T (&q)[Grp<T>::W], T c0, T cz, T cy,
+                                          T cx) {
+  constexpr int W = Grp<T>::W;
+  const int N = g.N;
+  T R[NA][W], yma[NA][W], ymb[NA][W], ypa[NA][W], ypb[NA][W], zma[NA][W], zmb[NA][W], zpa[NA][W], zpb[NA][W];
+  src_load<T, NA>(f, L.P0c, N, R);
+  if constexpr (HY) {
+    win_load<T, NA, AL>(f, L.P0c, -g.sy, of.ym, N, yma, ymb);
+    win_load<T, NA, AL>(f, L.P0c, g.sy, of.yp, N, ypa, ypb);
+  }
+  win_load<T, NA, AL>(f, L.P0c, -g.sz, of.zm, N, zma, zmb);
+  win_load<T, NA, AL>(f, L.P0c, g.sz, of.zp, N, zpa, zpb);
+  T le[NA], re[NA];
+#pragma unroll
+  for (int a = 0; a < NA; ++a) { le[a] = 0; re[a] = 0; }
+  const bool own_right = lane == 63 || !L.next_vec;
+  if (lane == 0 && L.P0c > 0) {
+#pragma unroll
+    for (int a = 0; a < NA; ++a) le[a] = ldg(f.a[a] + L.P0c - 1);
+  }
+  if (own_right && L.P0c + W < g.N) {
+#pragma unroll
+    for (int a = 0; a < NA; ++a) re[a] = ldg(f.a[a] + L.P0c + W);
+  }
+  src_mix<T, NA>(f, R, c);
+  T left = __shfl_up(c[W - 1], 1, 64);
+  T right = __shfl_down(c[0], 1, 64);
+  if (lane == 0) left = src_one<T, NA>(f, le);
+  if (own_right) right = src_one<T, NA>(f, re);
+  T ym[W], yp[W], zm[W], zp[W];
+  if constexpr (HY) {
+    win_get<T, NA, AL>(f, of.ym, yma, ymb, ym);
+    win_get<T, NA, AL>(f, of.yp, ypa, ypb, yp);
+  }
+  win_get<T, NA, AL>(f, of.zm, zma, zmb, zm);
+  win_get<T, NA, AL>(f, of.zp, zpa, zpb, zp);
+#pragma unroll
+  for (int e = 0; e < W; ++e) {
+    int ize = L.iz, iye = L.iy, ixe = L.ix0 + e;
+    if (L.straddle) g.coords(L.P0c + e, ize, iye, ixe);
     const T ce = c[e];
     const T lft = e > 0 ? c[e > 0 ? e - 1 : 0] : left;
     const T rgt = e < W - 1 ? c[e < W - 1 ? e + 1 : W - 1] : right;
     T lx = 0, ly = 0, lz = 0;
     if (ixe > 0) lx += ce - lft;
     if (ixe < g.nx - 1) lx += ce - rgt;
-    if (vnb) {
+    if constexpr (HY) {
       if (iye > 0) ly += ce - ym[e];
       if (iye < g.ny - 1) ly += ce - yp[e];
-      if (ize > 0) lz += ce - zm[e];
-      if (ize < g.nz - 1) lz += ce - zp[e];
-    } else {
-      const int P = P0 + e;
-      if (iye > 0) ly += ce - fetchs(P - g.sy);
-      if (iye < g.ny - 1) ly += ce - fetchs(P + g.sy);
-      if (ize > 0) lz += ce - fetchs(P - g.sz);
-      if (ize < g.nz - 1) lz += ce - fetchs(P + g.sz);
     }
+    if (ize > 0) lz += ce - zm[e];
+    if (ize < g.nz - 1) lz += ce - zp[e];
     q[e] = c0 * ce + cz * lz + cy * ly + cx * lx;
   }
-  return true;
+}
+
+template <typename T, int NA>
+__device__ __forceinline__ void group_C(const Src<T, NA>& f, const GLane& L, int lane, const Geo& g, const Offs& of,
+                                        T (&c)[Grp<T>::W], T (&q)[Grp<T>::W], T c0, T cz, T cy, T cx) {
+  const bool al = rows_aligned<T>(g);
+  if (g.ny > 1) {
+    if (al) group_C_v<T, NA, true, true>(f, L, lane, g, of, c, q, c0, cz, cy, cx);
+    else group_C_v<T, NA, true, false>(f, L, lane, g, of, c, q, c0, cz, cy, cx);
+  } else {
+    if (al) group_C_v<T, NA, false, true>(f, L, lane, g, of, c, q, c0, cz, cy, cx);
+    else group_C_v<T, NA, false, false>(f, L, lane, g, of, c, q, c0, cz, cy, cx);
+  }
 }
 
 // (C f)(P) at one point, f given by a scalar fetch.
@@ -387,12 +510,115 @@ __device__ __forceinline__ T point_apply_C(int P, const Geo& g, FS f, T fc, T c0
   return c0 * fc + cz * lz + cy * ly + cx * lx;
 }
 
+// s = (A_axis f) at the lane's group (f itself for axis < 0); valid[e] false
+// on the last layer along the axis (no such row; s = 0 there).  All lanes of
+// the wave call this; the result is meaningful where L.vec.
+template <typename T>
+__device__ __forceinline__ void group_diff(const T* f, const GLane& L, int lane, const Geo& g, const InstDesc& d,
+                                           const Offs& of, int axis, T (&s)[Grp<T>::W], bool (&valid)[Grp<T>::W]) {
+  constexpr int W = Grp<T>::W;
+  const Src<T, 1> src{{f}, (T)0};
+  T R[1][W], wa[1][W], wb[1][W];
+  src_load<T, 1>(src, L.P0c, g.N, R);
+  if (axis < 0) {
+#pragma unroll
+    for (int e = 0; e < W; ++e) { s[e] = R[0][e]; valid[e] = e < L.cnt; }
+    return;
+  }
+  const T h = (T)d.hinv[axis];
+  if (axis == 2) {
+    const bool own_right = lane == 63 || !L.next_vec;
+    T re = 0;
+    if (own_right && L.P0c + W < g.N) re = ldg(f + L.P0c + W);
+    T right = __shfl_down(R[0][0], 1, 64);
+    if (own_right) right = re;
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      int ize, iye, ixe = L.ix0 + e;
+      if (L.straddle) g.coords(L.P0c + e, ize, iye, ixe);
+      valid[e] = e < L.cnt && ixe < g.nx - 1;
+      const T nxt = e < W - 1 ? R[0][e < W - 1 ? e + 1 : W - 1] : right;
+      s[e] = valid[e] ? (nxt - R[0][e]) * h : (T)0;
+    }
+    return;
+  }
+  const int st = axis == 0 ? g.sz : g.sy, off = axis == 0 ? of.zp : of.yp;
+  T nb[W];
+  if (rows_aligned<T>(g)) {
+    win_load<T, 1, true>(src, L.P0c, st, off, g.N, wa, wb);
+    win_get<T, 1, true>(src, off, wa, wb, nb);
+  } else {
+    win_load<T, 1, false>(src, L.P0c, st, off, g.N, wa, wb);
+    win_get<T, 1, false>(src, off, wa, wb, nb);
+  }
+#pragma unroll
+  for (int e = 0; e < W; ++e) {
+    int ize = L.iz, iye = L.iy, ixe;
+    if (L.straddle) g.coords(L.P0c + e, ize, iye, ixe);
+    valid[e] = e < L.cnt && (axis == 0 ? ize < g.nz - 1 : iye < g.ny - 1);
+    s[e] = valid[e] ? (nb[e] - R[0][e]) * h : (T)0;
+  }
+}
+
+// Coordinates-only validity of a component at the points of a group.
+template <typename T>
+__device__ __forceinline__ void group_valid(const GLane& L, const Geo& g, int axis, bool (&valid)[Grp<T>::W]) {
+  constexpr int W = Grp<T>::W;
+#pragma unroll
+  for (int e = 0; e < W; ++e) {
+    int ize = L.iz, iye = L.iy, ixe = L.ix0 + e;
+    if (L.straddle) g.coords(L.P0c + e, ize, iye, ixe);
+    valid[e] = e < L.cnt && comp_valid(axis, ize, iye, ixe, g);
+  }
+}
+
 // Step j, first half: beta = rr_j / rr_{j-1}; p_j = r + beta p_{j-1} (p_0 = r);
 // partial p_j^T C p_j with C p_j evaluated on the fly (never stored).
-template <typename T>
-__global__ __launch_bounds__(kPB) void k_cg_dir(const InstDesc* D, const Counts* cnt, const PtItem* items, int j,
-                                                const double* rr_part, double* pq_part, Opts o) {
+template <typename T, int NA>
+__device__ __forceinline__ double cg_dir_item(const InstDesc& d, const PtItem& it, const Geo& g, const Src<T, NA>& f,
+                                              T* __restrict__ pout, T c0, T cz, T cy, T cx) {
   constexpr int W = Grp<T>::W;
+  const int lane = threadIdx.x & 63;
+  const int end = it.begin + it.len;
+  const bool grouped = item_grouped(d);
+  const Offs of = offs_of<T>(g);
+  auto fs = [&](int Q) -> T {
+    if constexpr (NA == 1) return f.a[0][Q];
+    else return f.a[0][Q] + f.beta * f.a[1][Q];
+  };
+  double acc = 0.0;
+  for (int base = it.begin; base < end; base += kPB * W) {
+    const int P0 = base + (int)threadIdx.x * W;
+    bool vec = false;
+    if (grouped) {
+      const GLane L = glane<T>(P0, it.begin, end, g);
+      T c[W], q[W];
+      group_C<T, NA>(f, L, lane, g, of, c, q, c0, cz, cy, cx);
+      vec = L.vec;
+      if (vec) {
+        st16<T>(pout + P0, c);
+#pragma unroll
+        for (int e = 0; e < W; ++e)
+          if (e < L.cnt) acc += (double)c[e] * (double)q[e];
+      }
+    }
+    if (!vec) {
+      for (int e = 0; e < W; ++e) {
+        const int P = P0 + e;
+        if (P >= end) break;
+        const T pc = fs(P);
+        const T qq = point_apply_C<T>(P, g, fs, pc, c0, cz, cy, cx);
+        pout[P] = pc;
+        acc += (double)pc * (double)qq;
+      }
+    }
+  }
+  return acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kPB) void k_cg_dir(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const PtItem* __restrict__ items, int j,
+                                                const double* rr_part, double* pq_part, Opts o) {
   __shared__ double lds[lds_sum<1, kPB>()];
   if ((int)blockIdx.x >= cnt->npt) return;
   const int iti = xcd_item(blockIdx.x, cnt->npt);
@@ -418,43 +644,17 @@ __global__ __launch_bounds__(kPB) void k_cg_dir(const InstDesc* D, const Counts*
   }
   if (done || bad) return;
   const Geo g(d);
-  const T* __restrict__ r = (const T*)d.r;
-  const T* __restrict__ pin = (const T*)d.p[(j + 1) & 1];
-  T* __restrict__ pout = (T*)d.p[j & 1];
+  const T* r = (const T*)d.r;
+  const T* pin = (const T*)d.p[(j + 1) & 1];
+  T* pout = (T*)d.p[j & 1];
   const T c0 = (T)S[S_C0], cz = (T)S[S_CAX + 0], cy = (T)S[S_CAX + 1], cx = (T)S[S_CAX + 2];
-  const T bt = (T)beta;
-  const bool first = j == 0;
-  auto fs = [&](int Q) -> T { return first ? r[Q] : r[Q] + bt * pin[Q]; };
-  auto fv = [&](int Q, T (&o)[W]) {
-    ld16<T>(r + Q, o);
-    if (!first) {
-      T b[W];
-      ld16<T>(pin + Q, b);
-#pragma unroll
-      for (int e = 0; e < W; ++e) o[e] += bt * b[e];
-    }
-  };
-  const int lane = threadIdx.x & 63;
-  double acc[1] = {0.0};
-  const int end = it.begin + it.len;
-  for (int base = it.begin; base < end; base += kPB * W) {
-    const int P0 = base + (int)threadIdx.x * W;
-    const bool full = d.vec_ok && P0 + W <= end;
-    T c[W], q[W];
-    if (group_apply_C<T>(P0, full, lane, g, d.vec_nb, fv, fs, c, q, c0, cz, cy, cx)) {
-      st16<T>(pout + P0, c);
-#pragma unroll
-      for (int e = 0; e < W; ++e) acc[0] += (double)c[e] * (double)q[e];
-    } else {
-      for (int e = 0; e < W; ++e) {
-        const int P = P0 + e;
-        if (P >= end) break;
-        const T pc = fs(P);
-        const T qq = point_apply_C<T>(P, g, fs, pc, c0, cz, cy, cx);
-        pout[P] = pc;
-        acc[0] += (double)pc * (double)qq;
-      }
-    }
+  double acc[1];
+  if (j == 0) {
+    const Src<T, 1> f{{r}, (T)0};
+    acc[0] = cg_dir_item<T, 1>(d, it, g, f, pout, c0, cz, cy, cx);
+  } else {
+    const Src<T, 2> f{{r, pin}, (T)beta};
+    acc[0] = cg_dir_item<T, 2>(d, it, g, f, pout, c0, cz, cy, cx);
   }
   block_sum<1, kPB>(acc, lds);
   if (threadIdx.x == 0) pq_part[iti] = acc[0];
@@ -463,7 +663,7 @@ __global__ __launch_bounds__(kPB) void k_cg_dir(const InstDesc* D, const Counts*
 // Step j, second half: alpha = rr_j / p^T C p; x += alpha p; r -= alpha C p
 // (C p recomputed from p); partial r^T r.
 template <typename T>
-__global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* D, const Counts* cnt, const PtItem* items, int j,
+__global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const PtItem* __restrict__ items, int j,
                                                 const double* pq_part, double* rr_part) {
   constexpr int W = Grp<T>::W;
   __shared__ double lds[lds_sum<1, kPB>()];
@@ -482,33 +682,40 @@ __global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* D, const Counts*
   const double alpha = S[S_RR + (j & 1)] / pq;
   if (iti == d.pt_begin && threadIdx.x == 0) S[S_CGTOT] += 1.0;
   const Geo g(d);
-  T* __restrict__ x = (T*)d.x;
-  T* __restrict__ r = (T*)d.r;
-  const T* __restrict__ p = (const T*)d.p[j & 1];
+  T* x = (T*)d.x;
+  T* r = (T*)d.r;
+  const T* p = (const T*)d.p[j & 1];
   const T c0 = (T)S[S_C0], cz = (T)S[S_CAX + 0], cy = (T)S[S_CAX + 1], cx = (T)S[S_CAX + 2];
   const T al = (T)alpha;
   auto fs = [&](int Q) -> T { return p[Q]; };
-  auto fv = [&](int Q, T (&o)[W]) { ld16<T>(p + Q, o); };
+  const Src<T, 1> f{{p}, (T)0};
   const int lane = threadIdx.x & 63;
+  const bool grouped = item_grouped(d);
+  const Offs of = offs_of<T>(g);
   double acc[1] = {0.0};
   const int end = it.begin + it.len;
   for (int base = it.begin; base < end; base += kPB * W) {
     const int P0 = base + (int)threadIdx.x * W;
-    const bool full = d.vec_ok && P0 + W <= end;
-    T c[W], q[W];
-    if (group_apply_C<T>(P0, full, lane, g, d.vec_nb, fv, fs, c, q, c0, cz, cy, cx)) {
-      T xv[W], rv[W];
-      ld16<T>(x + P0, xv);
-      ld16<T>(r + P0, rv);
+    bool vec = false;
+    if (grouped) {
+      const GLane L = glane<T>(P0, it.begin, end, g);
+      T xv[W], rv[W], c[W], q[W];
+      ld16p<T>(x, L.P0c, g.N, xv);
+      ld16<T>(r + L.P0c, rv);
+      group_C<T, 1>(f, L, lane, g, of, c, q, c0, cz, cy, cx);
+      vec = L.vec;
+      if (vec) {
 #pragma unroll
-      for (int e = 0; e < W; ++e) {
-        xv[e] = xv[e] + al * c[e];
-        rv[e] = rv[e] - al * q[e];
-        acc[0] += (double)rv[e] * (double)rv[e];
+        for (int e = 0; e < W; ++e) {
+          xv[e] = xv[e] + al * c[e];
+          rv[e] = rv[e] - al * q[e];
+          if (e < L.cnt) acc[0] += (double)rv[e] * (double)rv[e];
+        }
+        st16p<T>(x, P0, L.cnt, xv);
+        st16<T>(r + P0, rv);
       }
-      st16<T>(x + P0, xv);
-      st16<T>(r + P0, rv);
-    } else {
+    }
+    if (!vec) {
       for (int e = 0; e < W; ++e) {
         const int P = P0 + e;
         if (P >= end) break;
@@ -525,6 +732,150 @@ __global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* D, const Counts*
   if (threadIdx.x == 0) rr_part[iti] = acc[0];
 }
 
+// -------------------------------------------------------- RHS + residual
+
+// b = sum_{i<=p+1} A_i^T (rho_i y_i + v_i);  r = b - C x;  partial r^T r.
+// A_i^T of a forward difference needs u = rho y + v one point back along the
+// axis: the previous lane's last value for x, a window for y / z.
+template <typename T>
+__global__ __launch_bounds__(kPB) void k_rhs(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const PtItem* __restrict__ items, double* rr_part) {
+  constexpr int W = Grp<T>::W;
+  __shared__ double lds[lds_sum<1, kPB>()];
+  if ((int)blockIdx.x >= cnt->npt) return;
+  const int iti = xcd_item(blockIdx.x, cnt->npt);
+  const PtItem it = items[iti];
+  const InstDesc& d = D[it.inst];
+  const double* S = d.scal;
+  if (!inst_live(S)) return;
+  const Geo g(d);
+  const T* x = (const T*)d.x;
+  T* r = (T*)d.r;
+  const T* yl = (const T*)d.yl;
+  const T* vl = (const T*)d.vl;
+  const T rl = (T)S[S_RHO + d.nsets];
+  const T c0 = (T)S[S_C0], cz = (T)S[S_CAX + 0], cy = (T)S[S_CAX + 1], cx = (T)S[S_CAX + 2];
+  const int lane = threadIdx.x & 63;
+  auto fs = [&](int Q) -> T { return x[Q]; };
+  const Src<T, 1> fx{{x}, (T)0};
+  const bool grouped = item_grouped(d);
+  const Offs of = offs_of<T>(g);
+  const bool al = rows_aligned<T>(g);
+  const int N = g.N;
+  double acc[1] = {0.0};
+  const int end = it.begin + it.len;
+  for (int base = it.begin; base < end; base += kPB * W) {
+    const int P0 = base + (int)threadIdx.x * W;
+    bool vec = false;
+    if (grouped) {
+      const GLane L = glane<T>(P0, it.begin, end, g);
+      T b[W];
+      {
+        T a0[W], a1[W];
+        ld16<T>(yl + L.P0c, a0);
+        ld16<T>(vl + L.P0c, a1);
+#pragma unroll
+        for (int e = 0; e < W; ++e) b[e] = rl * a0[e] + a1[e];
+      }
+      for (int si = 0; si < d.nsets; ++si) {
+        const SetDesc& s = d.sets[si];
+        const T rs = (T)S[S_RHO + si];
+        for (int c = 0; c < s.ncomp; ++c) {
+          // u = v + rho y
+          const Src<T, 2> fu{{(const T*)s.v + (size_t)c * g.cs, (const T*)s.y + (size_t)c * g.cs}, rs};
+          const int a = s.axis[c];
+          T R[2][W], wa[2][W], wb[2][W], u[W];
+          src_load<T, 2>(fu, L.P0c, N, R);
+          const int st = a == 0 ? g.sz : g.sy, off = a == 0 ? of.zm : of.ym;
+          if (a == 0 || a == 1) {
+            if (al) win_load<T, 2, true>(fu, L.P0c, -st, off, N, wa, wb);
+            else win_load<T, 2, false>(fu, L.P0c, -st, off, N, wa, wb);
+          }
+          T le[2] = {(T)0, (T)0};
+          if (a == 2 && lane == 0 && L.P0c > 0) {
+            le[0] = ldg(fu.a[0] + L.P0c - 1);
+            le[1] = ldg(fu.a[1] + L.P0c - 1);
+          }
+          src_mix<T, 2>(fu, R, u);
+          if (a < 0) {
+#pragma unroll
+            for (int e = 0; e < W; ++e) b[e] += u[e];
+            continue;
+          }
+          T prev[W];
+          if (a == 2) {
+            T left = __shfl_up(u[W - 1], 1, 64);
+            if (lane == 0) left = src_one<T, 2>(fu, le);
+#pragma unroll
+            for (int e = 0; e < W; ++e) prev[e] = e > 0 ? u[e > 0 ? e - 1 : 0] : left;
+          } else {
+            if (al) win_get<T, 2, true>(fu, off, wa, wb, prev);
+            else win_get<T, 2, false>(fu, off, wa, wb, prev);
+          }
+          const T h = (T)d.hinv[a];
+          const int na = a == 0 ? g.nz : (a == 1 ? g.ny : g.nx);
+#pragma unroll
+          for (int e = 0; e < W; ++e) {
+            int ize = L.iz, iye = L.iy, ixe = L.ix0 + e;
+            if (L.straddle) g.coords(L.P0c + e, ize, iye, ixe);
+            const int ia = a == 0 ? ize : (a == 1 ? iye : ixe);
+            T t = 0;
+            if (ia > 0) t += prev[e];
+            if (ia < na - 1) t -= u[e];
+            b[e] += t * h;
+          }
+        }
+      }
+      T cxv[W], xc[W];
+      group_C<T, 1>(fx, L, lane, g, of, xc, cxv, c0, cz, cy, cx);
+      vec = L.vec;
+      if (vec) {
+        T rv[W];
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+          rv[e] = b[e] - cxv[e];
+          if (e < L.cnt) acc[0] += (double)rv[e] * (double)rv[e];
+        }
+        st16<T>(r + P0, rv);
+      }
+    }
+    if (!vec) {
+      for (int e = 0; e < W; ++e) {
+        const int P = P0 + e;
+        if (P >= end) break;
+        int pz, py, px;
+        g.coords(P, pz, py, px);
+        T bb = rl * yl[P] + vl[P];
+        for (int si = 0; si < d.nsets; ++si) {
+          const SetDesc& s = d.sets[si];
+          const T rs = (T)S[S_RHO + si];
+          for (int c = 0; c < s.ncomp; ++c) {
+            const T* y = (const T*)s.y + (size_t)c * g.cs;
+            const T* v = (const T*)s.v + (size_t)c * g.cs;
+            const int a = s.axis[c];
+            if (a < 0) {
+              bb += v[P] + rs * y[P];
+            } else {
+              const int ia = a == 0 ? pz : (a == 1 ? py : px);
+              const int na = a == 0 ? g.nz : (a == 1 ? g.ny : g.nx);
+              const int st = a == 0 ? g.sz : (a == 1 ? g.sy : 1);
+              T t = 0;
+              if (ia > 0) t += v[P - st] + rs * y[P - st];
+              if (ia < na - 1) t -= v[P] + rs * y[P];
+              bb += t * (T)d.hinv[a];
+            }
+          }
+        }
+        const T xv = x[P];
+        const T rv = bb - point_apply_C<T>(P, g, fs, xv, c0, cz, cy, cx);
+        r[P] = rv;
+        acc[0] += (double)rv * (double)rv;
+      }
+    }
+  }
+  block_sum<1, kPB>(acc, lds);
+  if (threadIdx.x == 0) rr_part[iti] = acc[0];
+}
+
 // ------------------------------------------- clip-type sets + identity block
 
 // For every bounds set and the identity block p+1 at the item's points:
@@ -532,9 +883,26 @@ __global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* D, const Counts*
 // y = clip(w) or (m + rho w)/(1 + rho), v += rho (y - x-bar); on adapt
 // iterations the six adapt-rho-gamma dots against the k0 snapshot and the new
 // snapshot; on stopping-test iterations the feasibility sums of s.  Then the
-// x snapshot / x history writes and the r_evol sums.
+// x snapshot / x history writes and the r_evol sums.  Full 16-byte groups
+// use 128-bit accesses; other points take the per-point path.
 template <typename T>
-__global__ __launch_bounds__(kSB) void k_proj(const InstDesc* D, const Counts* cnt, const PtItem* items, Opts o, double* parts) {
+struct ProjUnit {
+  T rho, gam, one_m_g, irho, lo, hi, inv1p;
+  bool ident;
+};
+
+template <typename T>
+__device__ __forceinline__ void proj_point(const ProjUnit<T>& U, T sv, T yo, T vo, T mv, T& yn, T& vn, T& xb) {
+  xb = U.gam * sv + U.one_m_g * yo;
+  const T w = xb - vo * U.irho;
+  if (U.ident) yn = (mv + U.rho * w) * U.inv1p;
+  else yn = w < U.lo ? U.lo : (w > U.hi ? U.hi : w);
+  vn = vo + U.rho * (yn - xb);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const PtItem* __restrict__ items, Opts o, double* parts) {
+  constexpr int W = Grp<T>::W;
   __shared__ double lds[lds_sum<8, kSB>()];
   if ((int)blockIdx.x >= cnt->nsp) return;
   const int iti = xcd_item(blockIdx.x, cnt->nsp);
@@ -543,15 +911,19 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* D, const Counts* c
   const double* S = d.scal;
   if (!inst_live(S)) return;
   const Geo g(d);
+  const bool grouped = item_grouped(d);
+  const Offs of = offs_of<T>(g);
   const int k = (int)S[S_K];
   const bool adapt = is_adapt_iter(k, o);
   const bool check = is_check_iter(k, o);
   const bool have = S[S_HAVE_SNAP] != 0.0;
+  const bool dots = adapt && have;
   const int call = adapt ? adapt_call(k, o) : 0;
   const T* __restrict__ x = (const T*)d.x;
   const T* __restrict__ xr = (const T*)d.xs[(call & 1) ^ 1];
   const T* __restrict__ m = (const T*)d.m;
   const int end = it.begin + it.len;
+  const int lane = threadIdx.x & 63;
   double* out = parts + (size_t)iti * kProjParts;
 
   for (int u = 0; u <= d.nsets; ++u) {
@@ -559,59 +931,115 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* D, const Counts* c
     const SetDesc* s = ident ? nullptr : &d.sets[u];
     if (!ident && s->thr >= 0) continue;
     const double rho_d = S[S_RHO + u];
-    const T rho = (T)rho_d, gam = (T)S[S_GAMMA + u], irho = (T)(1.0 / rho_d);
-    const T one_m_g = (T)(1.0 - S[S_GAMMA + u]);
-    const T lo = ident ? (T)0 : (T)s->lo, hi = ident ? (T)0 : (T)s->hi;
-    const T inv1p = (T)(1.0 / (1.0 + rho_d));
+    ProjUnit<T> U;
+    U.rho = (T)rho_d; U.gam = (T)S[S_GAMMA + u]; U.irho = (T)(1.0 / rho_d);
+    U.one_m_g = (T)(1.0 - S[S_GAMMA + u]);
+    U.lo = ident ? (T)0 : (T)s->lo; U.hi = ident ? (T)0 : (T)s->hi;
+    U.inv1p = (T)(1.0 / (1.0 + rho_d));
+    U.ident = ident;
     const int ncomp = ident ? 1 : s->ncomp;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int c = 0; c < ncomp; ++c) {
       const int axis = ident ? -1 : s->axis[c];
-      const size_t off = (size_t)c * g.N;
+      const size_t off = (size_t)c * g.cs;
       T* __restrict__ y = (T*)(ident ? d.yl : s->y) + off;
       T* __restrict__ v = (T*)(ident ? d.vl : s->v) + off;
       T* __restrict__ vh0 = (T*)(ident ? d.vh0l : s->vh0) + off;
       T* __restrict__ v0 = (T*)(ident ? d.v0l : s->v0) + off;
       T* __restrict__ y0 = (T*)(ident ? d.y0l : s->y0) + off;
-      for (int base = it.begin; base < end; base += kSB * kUset) {
+      for (int base = it.begin; base < end; base += kSB * W) {
+        const int P0 = base + (int)threadIdx.x * W;
+        GLane L{};
+        if (grouped) L = glane<T>(P0, it.begin, end, g);
+        const bool full = grouped && L.vec;
+        T sv[W], s0[W];
+        bool ok[W], ok0[W];
+        if (grouped) {
+          group_diff<T>(x, L, lane, g, d, of, axis, sv, ok);
+          if (dots) group_diff<T>(xr, L, lane, g, d, of, axis, s0, ok0);
+        }
+        if (full) {
+          T yo[W], vo[W], yn[W], vn[W], mv[W];
+          ld16<T>(y + P0, yo);
+          ld16<T>(v + P0, vo);
+          if (ident) ld16<T>(m + P0, mv);
+          T xbv[W];
 #pragma unroll
-        for (int uu = 0; uu < kUset; ++uu) {
-          const int P = base + uu * kSB + (int)threadIdx.x;
-          if (P >= end) continue;
-          int iz, iy, ix;
-          g.coords(P, iz, iy, ix);
-          T sv;
-          if (!comp_value<T>(x, P, axis, iz, iy, ix, g, d, sv)) continue;
-          const T yo = y[P], vo = v[P];
-          const T xb = gam * sv + one_m_g * yo;
-          const T w = xb - vo * irho;
-          T yn;
-          if (ident) yn = (m[P] + rho * w) * inv1p;
-          else yn = w < lo ? lo : (w > hi ? hi : w);
-          const T vn = vo + rho * (yn - xb);
-          y[P] = yn;
-          v[P] = vn;
+          for (int e = 0; e < W; ++e) {
+            if (ok[e]) proj_point<T>(U, sv[e], yo[e], vo[e], ident ? mv[e] : (T)0, yn[e], vn[e], xbv[e]);
+            else { yn[e] = yo[e]; vn[e] = vo[e]; xbv[e] = 0; }
+          }
+          st16<T>(y + P0, yn);
+          st16<T>(v + P0, vn);
           if (adapt) {
-            const T vh = vo + rho * (yo - sv);
+            T vh[W];
+#pragma unroll
+            for (int e = 0; e < W; ++e) vh[e] = ok[e] ? vo[e] + U.rho * (yo[e] - sv[e]) : (T)0;
             if (have) {
-              T s0;
-              comp_value<T>(xr, P, axis, iz, iy, ix, g, d, s0);
-              const double dh = (double)sv - (double)s0;
-              const double dvh = (double)vh - (double)vh0[P];
-              const double dg = -((double)yn - (double)y0[P]);
-              const double dv = (double)vn - (double)v0[P];
-              acc[0] += dh * dvh; acc[1] += dh * dh; acc[2] += dvh * dvh;
-              acc[3] += dg * dv; acc[4] += dg * dg; acc[5] += dv * dv;
+              T a0[W], a1[W], a2[W];
+              ld16<T>(vh0 + P0, a0);
+              ld16<T>(y0 + P0, a1);
+              ld16<T>(v0 + P0, a2);
+#pragma unroll
+              for (int e = 0; e < W; ++e) {
+                if (!ok[e]) continue;
+                const double dh = (double)sv[e] - (double)s0[e];
+                const double dvh = (double)vh[e] - (double)a0[e];
+                const double dg = -((double)yn[e] - (double)a1[e]);
+                const double dv = (double)vn[e] - (double)a2[e];
+                acc[0] += dh * dvh; acc[1] += dh * dh; acc[2] += dvh * dvh;
+                acc[3] += dg * dv; acc[4] += dg * dg; acc[5] += dv * dv;
+              }
             }
-            vh0[P] = vh;
-            v0[P] = vn;
-            y0[P] = yn;
+            st16<T>(vh0 + P0, vh);
+            st16<T>(v0 + P0, vn);
+            st16<T>(y0 + P0, yn);
           }
           if (check && !ident) {
-            const T pc = sv < lo ? lo : (sv > hi ? hi : sv);
-            const double e = (double)sv - (double)pc;
-            acc[6] += e * e;
-            acc[7] += (double)sv * (double)sv;
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+              if (!ok[e]) continue;
+              const T pc = sv[e] < U.lo ? U.lo : (sv[e] > U.hi ? U.hi : sv[e]);
+              const double ee = (double)sv[e] - (double)pc;
+              acc[6] += ee * ee;
+              acc[7] += (double)sv[e] * (double)sv[e];
+            }
+          }
+        } else {
+          for (int e = 0; e < W; ++e) {
+            const int P = P0 + e;
+            if (P >= end) break;
+            int iz, iy, ix;
+            g.coords(P, iz, iy, ix);
+            T sp;
+            if (!comp_value<T>(x, P, axis, iz, iy, ix, g, d, sp)) continue;
+            const T yo = y[P], vo = v[P];
+            T yn, vn, xb;
+            proj_point<T>(U, sp, yo, vo, ident ? m[P] : (T)0, yn, vn, xb);
+            y[P] = yn;
+            v[P] = vn;
+            if (adapt) {
+              const T vh = vo + U.rho * (yo - sp);
+              if (have) {
+                T sq;
+                comp_value<T>(xr, P, axis, iz, iy, ix, g, d, sq);
+                const double dh = (double)sp - (double)sq;
+                const double dvh = (double)vh - (double)vh0[P];
+                const double dg = -((double)yn - (double)y0[P]);
+                const double dv = (double)vn - (double)v0[P];
+                acc[0] += dh * dvh; acc[1] += dh * dh; acc[2] += dvh * dvh;
+                acc[3] += dg * dv; acc[4] += dg * dg; acc[5] += dv * dv;
+              }
+              vh0[P] = vh;
+              v0[P] = vn;
+              y0[P] = yn;
+            }
+            if (check && !ident) {
+              const T pc = sp < U.lo ? U.lo : (sp > U.hi ? U.hi : sp);
+              const double ee = (double)sp - (double)pc;
+              acc[6] += ee * ee;
+              acc[7] += (double)sp * (double)sp;
+            }
           }
         }
       }
@@ -636,13 +1064,13 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* D, const Counts* c
       const T xv = x[P];
       if (adapt) xw[P] = xv;
       if (ring) {
-        ring[(size_t)(k % (H + 1)) * g.N + P] = xv;
+        ring[(size_t)(k % (H + 1)) * g.cs + P] = xv;
         if (check) {
           accx[0] += (double)xv * (double)xv;
 #pragma unroll
           for (int jj = 1; jj < kMaxHist; ++jj) {
             if (jj > H) break;
-            const double e = (double)xv - (double)ring[(size_t)((k - jj) % (H + 1)) * g.N + P];
+            const double e = (double)xv - (double)ring[(size_t)((k - jj) % (H + 1)) * g.cs + P];
             if (jj <= 7) acc[jj] += e * e; else accx[jj - 7] += e * e;
           }
         }
@@ -668,7 +1096,7 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* D, const Counts* c
 // (dh, dvh) pair; radix histogram of the first key digit of |w|.
 // Pipeline 1 (stopping-test iterations): histogram of |s| and ||s||^2.
 template <typename T>
-__global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* D, const Counts* cnt, const ThrItem* items, Opts o, double* parts) {
+__global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const ThrItem* __restrict__ items, Opts o, double* parts) {
   using KT = KeyT<T>;
   __shared__ uint32_t hc[kNB];
   __shared__ double hs[kNB];
@@ -690,6 +1118,8 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* D, const Counts* 
   for (int b = threadIdx.x; b < kNB; b += kSB) { hc[b] = 0; hs[b] = 0.0; }
   __syncthreads();
   const Geo g(d);
+  const bool grouped = item_grouped(d);
+  const Offs of = offs_of<T>(g);
   const T* x = (const T*)d.x;
   const T* xr = (const T*)d.xs[(call & 1) ^ 1];
   const int u = it.set;
@@ -697,44 +1127,101 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* D, const Counts* 
   const T rho = (T)rho_d, gam = (T)S[S_GAMMA + u], one_m_g = (T)(1.0 - S[S_GAMMA + u]);
   const T irho = (T)(1.0 / rho_d);
   const int sh0 = digit_shift<T>(0);
+  constexpr int W = Grp<T>::W;
+  const int lane = threadIdx.x & 63;
+  const bool dots = it.src == 0 && adapt && have;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int end = it.begin + it.len;
+  auto bin = [&](T val) {
+    const typename KT::K key = KT::key(val);
+    const int bkt = (int)(key >> sh0);
+    atomicAdd(&hc[bkt], 1u);
+    if (l1) atomicAdd(&hs[bkt], KT::value(key));
+  };
   for (int c = 0; c < s.ncomp; ++c) {
     const int axis = s.axis[c];
-    const size_t off = (size_t)c * g.N;
-    T* y = (T*)s.y + off;
-    const T* v = (const T*)s.v + off;
-    T* vh0 = (T*)s.vh0 + off;
-    for (int P = it.begin + (int)threadIdx.x; P < end; P += kSB) {
-      int iz, iy, ix;
-      g.coords(P, iz, iy, ix);
-      T sv;
-      if (!comp_value<T>(x, P, axis, iz, iy, ix, g, d, sv)) continue;
-      T val;
-      if (it.src == 0) {
-        const T yo = y[P], vo = v[P];
-        const T xb = gam * sv + one_m_g * yo;
-        val = xb - vo * irho;
-        y[P] = val;
-        if (adapt) {
-          const T vh = vo + rho * (yo - sv);
-          if (have) {
-            T s0;
-            comp_value<T>(xr, P, axis, iz, iy, ix, g, d, s0);
-            const double dh = (double)sv - (double)s0;
-            const double dvh = (double)vh - (double)vh0[P];
-            acc[0] += dh * dvh; acc[1] += dh * dh; acc[2] += dvh * dvh;
-          }
-          vh0[P] = vh;
-        }
-      } else {
-        val = sv;
-        acc[7] += (double)sv * (double)sv;
+    const size_t off = (size_t)c * g.cs;
+    T* __restrict__ y = (T*)s.y + off;
+    const T* __restrict__ v = (const T*)s.v + off;
+    T* __restrict__ vh0 = (T*)s.vh0 + off;
+    for (int base = it.begin; base < end; base += kSB * W) {
+      const int P0 = base + (int)threadIdx.x * W;
+      GLane L{};
+      if (grouped) L = glane<T>(P0, it.begin, end, g);
+      const bool full = grouped && L.vec;
+      T sv[W], s0[W];
+      bool ok[W], ok0[W];
+      if (grouped) {
+        group_diff<T>(x, L, lane, g, d, of, axis, sv, ok);
+        if (dots) group_diff<T>(xr, L, lane, g, d, of, axis, s0, ok0);
       }
-      const typename KT::K key = KT::key(val);
-      const int bkt = (int)(key >> sh0);
-      atomicAdd(&hc[bkt], 1u);
-      if (l1) atomicAdd(&hs[bkt], KT::value(key));
+      if (full) {
+        if (it.src == 0) {
+          T yo[W], vo[W], wv[W];
+          ld16<T>(y + P0, yo);
+          ld16<T>(v + P0, vo);
+#pragma unroll
+          for (int e = 0; e < W; ++e) wv[e] = ok[e] ? gam * sv[e] + one_m_g * yo[e] - vo[e] * irho : yo[e];
+          st16<T>(y + P0, wv);
+          if (adapt) {
+            T vh[W];
+#pragma unroll
+            for (int e = 0; e < W; ++e) vh[e] = ok[e] ? vo[e] + rho * (yo[e] - sv[e]) : (T)0;
+            if (have) {
+              T a0[W];
+              ld16<T>(vh0 + P0, a0);
+#pragma unroll
+              for (int e = 0; e < W; ++e) {
+                if (!ok[e]) continue;
+                const double dh = (double)sv[e] - (double)s0[e];
+                const double dvh = (double)vh[e] - (double)a0[e];
+                acc[0] += dh * dvh; acc[1] += dh * dh; acc[2] += dvh * dvh;
+              }
+            }
+            st16<T>(vh0 + P0, vh);
+          }
+#pragma unroll
+          for (int e = 0; e < W; ++e)
+            if (ok[e]) bin(wv[e]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < W; ++e) {
+            if (!ok[e]) continue;
+            acc[7] += (double)sv[e] * (double)sv[e];
+            bin(sv[e]);
+          }
+        }
+        continue;
+      }
+      for (int e = 0; e < W; ++e) {
+        const int P = P0 + e;
+        if (P >= end) break;
+        int iz, iy, ix;
+        g.coords(P, iz, iy, ix);
+        T sp;
+        if (!comp_value<T>(x, P, axis, iz, iy, ix, g, d, sp)) continue;
+        T val;
+        if (it.src == 0) {
+          const T yo = y[P], vo = v[P];
+          val = gam * sp + one_m_g * yo - vo * irho;
+          y[P] = val;
+          if (adapt) {
+            const T vh = vo + rho * (yo - sp);
+            if (have) {
+              T sq;
+              comp_value<T>(xr, P, axis, iz, iy, ix, g, d, sq);
+              const double dh = (double)sp - (double)sq;
+              const double dvh = (double)vh - (double)vh0[P];
+              acc[0] += dh * dvh; acc[1] += dh * dh; acc[2] += dvh * dvh;
+            }
+            vh0[P] = vh;
+          }
+        } else {
+          val = sp;
+          acc[7] += (double)sp * (double)sp;
+        }
+        bin(val);
+      }
     }
   }
   __syncthreads();
@@ -859,7 +1346,7 @@ __device__ void finish_selection(SelState& st, const SetDesc& s, unsigned long l
 // Stage 1: totals, mode, first digit.  Clears the global histogram for the
 // refine pass.  The state is worked on in LDS and written back once.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* D, const Counts* cnt, const SelItem* items, Opts o) {
+__global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const SelItem* __restrict__ items, Opts o) {
   using KT = KeyT<T>;
   __shared__ uint32_t hc[kNB];
   __shared__ double hs[kNB];
@@ -931,7 +1418,7 @@ __device__ __forceinline__ bool pass_compacts(const SelState& st, int pass) {
 // (or on the last pass of a long key) their keys go to the candidate list,
 // appended with one atomic per block round.
 template <typename T>
-__global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* D, const Counts* cnt, const ThrItem* items, Opts o, int pass) {
+__global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const ThrItem* __restrict__ items, Opts o, int pass) {
   using KT = KeyT<T>;
   using K = typename KT::K;
   __shared__ uint32_t hc[kNB];
@@ -965,7 +1452,7 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* D, const Cou
   const int end = it.begin + it.len;
   for (int c = 0; c < s.ncomp; ++c) {
     const int axis = s.axis[c];
-    const T* __restrict__ y = (const T*)s.y + (size_t)c * g.N;
+    const T* __restrict__ y = (const T*)s.y + (size_t)c * g.cs;
     for (int base = it.begin; base < end; base += kSB) {
       const int P = base + (int)threadIdx.x;
       bool hit = false;
@@ -1030,7 +1517,7 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* D, const Cou
 // appends candidates.  Ends with theta (l1) or the k-th magnitude and the tie
 // bookkeeping (cardinality) once final.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* D, const Counts* cnt, const SelItem* items, Opts o, int pass) {
+__global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const SelItem* __restrict__ items, Opts o, int pass) {
   using KT = KeyT<T>;
   using K = typename KT::K;
   __shared__ uint32_t hc[kNB];
@@ -1102,7 +1589,7 @@ __global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* D, const Co
 // Cardinality ties straddling the cut: count entries equal to the k-th
 // magnitude per (item, component) so the apply pass can rank them by index.
 template <typename T>
-__global__ __launch_bounds__(kSB) void k_card_ties(const InstDesc* D, const Counts* cnt, const ThrItem* items, Opts o,
+__global__ __launch_bounds__(kSB) void k_card_ties(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const ThrItem* __restrict__ items, Opts o,
                                                       uint32_t* tie_part) {
   using KT = KeyT<T>;
   using K = typename KT::K;
@@ -1124,7 +1611,7 @@ __global__ __launch_bounds__(kSB) void k_card_ties(const InstDesc* D, const Coun
   const K tkey = (K)st.tkey;
   const int end = it.begin + it.len;
   for (int c = 0; c < s.ncomp; ++c) {
-    const T* y = (const T*)s.y + (size_t)c * g.N;
+    const T* y = (const T*)s.y + (size_t)c * g.cs;
     uint32_t local = 0;
     for (int P = it.begin + (int)threadIdx.x; P < end; P += kSB) {
       int iz, iy, ix;
@@ -1143,7 +1630,7 @@ __global__ __launch_bounds__(kSB) void k_card_ties(const InstDesc* D, const Coun
 // adapt dots of the (dg, dv) pair and the new y/v snapshots.  Pipeline 1:
 // the feasibility distance ||s - P(s)||^2.
 template <typename T>
-__global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* D, const Counts* cnt, const ThrItem* items, Opts o, double* parts,
+__global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const ThrItem* __restrict__ items, Opts o, double* parts,
                                                       const uint32_t* tie_part) {
   using KT = KeyT<T>;
   using K = typename KT::K;
@@ -1167,6 +1654,8 @@ __global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* D, const Coun
   const bool l1 = s.kind == SIP_SET_L1;
   const int mode = st.mode;
   const Geo g(d);
+  const bool grouped = item_grouped(d);
+  const Offs of = offs_of<T>(g);
   const T* x = (const T*)d.x;
   const double rho_d = S[S_RHO + it.set];
   const T rho = (T)rho_d;
@@ -1192,12 +1681,128 @@ __global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* D, const Coun
   const int end = it.begin + it.len;
   for (int c = 0; c < s.ncomp; ++c) {
     const int axis = s.axis[c];
-    const size_t off = (size_t)c * g.N;
+    const size_t off = (size_t)c * g.cs;
     T* y = (T*)s.y + off;
     T* v = (T*)s.v + off;
     T* y0 = (T*)s.y0 + off;
     T* v0 = (T*)s.v0 + off;
     unsigned long long run = rank_ties ? tie_base[c] : 0ull;
+    if (!rank_ties) {
+      // 16-byte groups (no index ranking needed)
+      constexpr int W = Grp<T>::W;
+      int base = it.begin;
+      for (; base < end; base += kSB * W) {
+        const int P0 = base + (int)threadIdx.x * W;
+        GLane L{};
+        if (grouped) L = glane<T>(P0, it.begin, end, g);
+        const bool full = grouped && L.vec;
+        T sv[W];
+        bool ok[W];
+        if (grouped && it.src == 1) group_diff<T>(x, L, lane, g, d, of, axis, sv, ok);
+        else if (full) group_valid<T>(L, g, axis, ok);
+        if (full) {
+          if (it.src == 1) {
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+              if (!ok[e]) continue;
+              const double a = fabs((double)sv[e]);
+              double e2 = 0.0;
+              if (l1) {
+                if (mode == SEL_PROJECT) { const double mn = a < st.theta ? a : st.theta; e2 = mn * mn; }
+                else if (mode == SEL_ZERO) e2 = a * a;
+              } else if (mode == SEL_PROJECT) {
+                e2 = KT::key(sv[e]) < tkey ? a * a : 0.0;
+              }
+              acc[6] += e2;
+            }
+            continue;
+          }
+          T w[W], yn[W], vn[W];
+          ld16<T>(y + P0, w);
+#pragma unroll
+          for (int e = 0; e < W; ++e) {
+            T r = w[e];
+            if (ok[e]) {
+              if (l1) {
+                if (mode == SEL_PROJECT) {
+                  const T a = (w[e] < 0 ? -w[e] : w[e]) - theta;
+                  r = a > 0 ? (w[e] < 0 ? -a : a) : (T)0;
+                } else if (mode == SEL_ZERO) r = 0;
+              } else if (mode == SEL_PROJECT) {
+                const K key = KT::key(w[e]);
+                r = (key > tkey || (key == tkey && (tkey == 0 || !st.need_ties))) ? w[e] : (T)0;
+              }
+            }
+            yn[e] = r;
+            vn[e] = ok[e] ? rho * (r - w[e]) : (T)0;
+          }
+          st16<T>(y + P0, yn);
+          st16<T>(v + P0, vn);
+          if (adapt) {
+            if (have) {
+              T a0[W], a1[W];
+              ld16<T>(y0 + P0, a0);
+              ld16<T>(v0 + P0, a1);
+#pragma unroll
+              for (int e = 0; e < W; ++e) {
+                if (!ok[e]) continue;
+                const double dg = -((double)yn[e] - (double)a0[e]);
+                const double dv = (double)vn[e] - (double)a1[e];
+                acc[3] += dg * dv; acc[4] += dg * dg; acc[5] += dv * dv;
+              }
+            }
+            st16<T>(y0 + P0, yn);
+            st16<T>(v0 + P0, vn);
+          }
+          continue;
+        }
+        for (int e = 0; e < W; ++e) {
+          const int P = P0 + e;
+          if (P >= end) break;
+          int iz, iy, ix;
+          g.coords(P, iz, iy, ix);
+          T sp = 0;
+          if (it.src == 1) {
+            if (!comp_value<T>(x, P, axis, iz, iy, ix, g, d, sp)) continue;
+            const double a = fabs((double)sp);
+            double e2 = 0.0;
+            if (l1) {
+              if (mode == SEL_PROJECT) { const double mn = a < st.theta ? a : st.theta; e2 = mn * mn; }
+              else if (mode == SEL_ZERO) e2 = a * a;
+            } else if (mode == SEL_PROJECT) {
+              e2 = KT::key(sp) < tkey ? a * a : 0.0;
+            }
+            acc[6] += e2;
+            continue;
+          }
+          if (!comp_valid(axis, iz, iy, ix, g)) continue;
+          const T we = y[P];
+          T r = we;
+          if (l1) {
+            if (mode == SEL_PROJECT) {
+              const T a = (we < 0 ? -we : we) - theta;
+              r = a > 0 ? (we < 0 ? -a : a) : (T)0;
+            } else if (mode == SEL_ZERO) r = 0;
+          } else if (mode == SEL_PROJECT) {
+            const K key = KT::key(we);
+            r = (key > tkey || (key == tkey && (tkey == 0 || !st.need_ties))) ? we : (T)0;
+          }
+          const T vv = rho * (r - we);
+          y[P] = r;
+          v[P] = vv;
+          if (adapt) {
+            if (have) {
+              const double dg = -((double)r - (double)y0[P]);
+              const double dv = (double)vv - (double)v0[P];
+              acc[3] += dg * dv; acc[4] += dg * dg; acc[5] += dv * dv;
+            }
+            y0[P] = r;
+            v0[P] = vv;
+          }
+        }
+      }
+      continue;
+    }
     for (int base = it.begin; base < end; base += kSB) {
       const int P = base + (int)threadIdx.x;
       bool valid = false;
@@ -1294,7 +1899,7 @@ __device__ bool spectral(double ab, double aa, double bb, double eps, double& es
 // adapt-rho-gamma for i = 1..p+1 with the gamma cap and rho-ratio guard,
 // recompute the stencil scalars of C, and advance k.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* D, const Counts* cnt, const int32_t* insts, Opts o,
+__global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const int32_t* __restrict__ insts, Opts o,
                                                    const double* proj_parts, const double* thrw_parts,
                                                    const double* thra_parts) {
   __shared__ double lds[lds_sum<8>()];
@@ -1438,7 +2043,7 @@ __global__ __launch_bounds__(kBlock) void k_zero_f64(double* a, int64_t n) {
 // ------------------------------------------------------ host-side launchers
 
 template <typename T>
-void launch_init(hipStream_t st, const InstDesc* D, int inst, int64_t N) {
+void launch_init(hipStream_t st, const InstDesc* __restrict__ D, int inst, int64_t N) {
   const int64_t nb = (N + kBlock - 1) / kBlock;
   k_init<T><<<(int)(nb < 2048 ? nb : 2048), kBlock, 0, st>>>(D, inst);
 }

@@ -93,7 +93,7 @@ def lib():
         "sip_batch_poll": (i32, [vp, C.POINTER(i32), vp]),
         "sip_batch_remove": (i32, [vp, i32, C.POINTER(Result), vp]),
         "sip_batch_result": (i32, [vp, i32, C.POINTER(Result), vp]),
-        "sip_batch_field": (i32, [vp, i32, i32, i32, C.POINTER(vp), C.POINTER(i64)]),
+        "sip_batch_field": (i32, [vp, i32, i32, i32, C.POINTER(vp), C.POINTER(i64), C.POINTER(i64)]),
         "sip_batch_get_params": (i32, [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                        C.POINTER(i32), C.POINTER(i32), vp]),
         "sip_batch_set_params": (i32, [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_double), i32, i32, vp]),
@@ -318,17 +318,19 @@ class Batch:
         return r.as_dict()
 
     def field(self, slot, which, set_index):
-        """(device pointer, element count) of a state array of a slot."""
+        """(device pointer, element count, component stride) of a state
+        array of a slot."""
         p = C.c_void_p()
         n = C.c_int64()
-        check(lib().sip_batch_field(self.h, int(slot), int(which), int(set_index), C.byref(p), C.byref(n)),
-              "sip_batch_field")
-        return p.value, n.value
+        cs = C.c_int64()
+        check(lib().sip_batch_field(self.h, int(slot), int(which), int(set_index), C.byref(p), C.byref(n),
+                                    C.byref(cs)), "sip_batch_field")
+        return p.value, n.value, cs.value
 
     def field_tensor(self, slot, which, set_index):
         """Copy a state array of a slot into a new device tensor."""
         import torch
-        ptr, n = self.field(slot, which, set_index)
+        ptr, n, _ = self.field(slot, which, set_index)
         dt = _dtype_of(self.opts)
         out = torch.empty(n, dtype=dt, device="cuda")
         torch.cuda.synchronize()
@@ -337,7 +339,7 @@ class Batch:
 
     def load_field(self, slot, which, set_index, values):
         import torch
-        ptr, n = self.field(slot, which, set_index)
+        ptr, n, _ = self.field(slot, which, set_index)
         src = values.to(device="cuda", dtype=_dtype_of(self.opts)).contiguous()
         assert src.numel() == n
         torch.cuda.synchronize()

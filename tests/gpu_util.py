@@ -18,12 +18,14 @@ _COMP_AXES = {
 }
 
 
-def unpad(shape, op, flat):
-    """Device component blocks -> oracle row vector (A_i's row order)."""
+def unpad(shape, op, flat, stride=None):
+    """Device component blocks (block c at c * stride) -> oracle row vector
+    (A_i's row order)."""
     N = int(np.prod(shape))
+    stride = N if stride is None else stride
     parts = []
     for c, ax in enumerate(_COMP_AXES[len(shape)][op]):
-        blk = np.asarray(flat[c * N:(c + 1) * N]).reshape(shape)
+        blk = np.asarray(flat[c * stride:c * stride + N]).reshape(shape)
         if ax is not None:
             sl = [slice(None)] * len(shape)
             sl[ax] = slice(0, shape[ax] - 1)
@@ -32,10 +34,11 @@ def unpad(shape, op, flat):
     return np.concatenate(parts)
 
 
-def pad(shape, op, rows):
+def pad(shape, op, rows, stride=None):
     N = int(np.prod(shape))
+    stride = N if stride is None else stride
     axes = _COMP_AXES[len(shape)][op]
-    out = np.zeros(len(axes) * N)
+    out = np.zeros(len(axes) * stride)
     off = 0
     for c, ax in enumerate(axes):
         sh = list(shape)
@@ -45,7 +48,7 @@ def pad(shape, op, rows):
         blk = np.zeros(shape)
         sl = tuple(slice(0, s) for s in sh)
         blk[sl] = np.asarray(rows[off:off + cnt]).reshape(sh)
-        out[c * N:(c + 1) * N] = blk.ravel()
+        out[c * stride:c * stride + N] = blk.ravel()
         off += cnt
     return out
 
@@ -106,7 +109,8 @@ class Slot:
     def arr(self, which, i):
         op = "I" if i == len(self.sets) else self.sets[i]["op"]
         t = self.batch.field_tensor(self.slot, which, i).double().cpu().numpy()
-        return unpad(self.shape, op, t)
+        cs = self.batch.field(self.slot, which, i)[2]
+        return unpad(self.shape, op, t, cs)
 
     def raw(self, which, i):
         return self.batch.field_tensor(self.slot, which, i).double().cpu().numpy()

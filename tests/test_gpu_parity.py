@@ -7,6 +7,7 @@ oracle to 1e-9, float32 runs must agree to 1e-5 when the oracle replays the
 device's (rho, gamma) schedule; (3) cardinality supports must be identical
 away from ties with the k-th magnitude."""
 import math
+import zlib
 
 import numpy as np
 import pytest
@@ -204,20 +205,48 @@ EDGE_CASES = {
 }
 
 
+def _oracle_run_with_schedule(m, shape, sets, opts):
+    """Free-running oracle, also returning the (rho, gamma) used in each
+    iteration (the device schedule log's convention)."""
+    prob = orc.Problem(m, shape, sets)
+    st = orc.initial_state(prob, opts)
+    rho, gam = [], []
+    while st.k <= opts.max_iter:
+        rho.append(st.rho.copy())
+        gam.append(st.gamma.copy())
+        if orc.iterate(prob, st, opts):
+            break
+    return st.x.reshape(shape), np.array(rho), np.array(gam)
+
+
 @pytest.mark.parametrize("name", sorted(EDGE_CASES))
 def test_edge_cases_f64(name):
+    """Degenerate inputs, float64.  The adapt-rho-gamma rule is discontinuous
+    (the correlation threshold, the ratio guard), so a last-bit difference in
+    a dot product can flip one decision and send a free-running run down a
+    different but equally valid path.  The device result is therefore
+    compared to the oracle replaying the device's (rho, gamma) schedule; the
+    free-running comparison is asserted whenever both runs took the same
+    decisions."""
     shape, sets = EDGE_CASES[name]
-    rng = np.random.default_rng(abs(hash(name)) % 1000)
+    rng = np.random.default_rng(zlib.crc32(name.encode()) % 1000)
     m = rng.standard_normal(shape)
     iters = 20
     print(f"\n[edge] {name}", flush=True)
-    sl = Slot(m, sets, "f64", dict(max_iter=iters, cg_max=10, cg_fixed=1))
+    sl = Slot(m, sets, "f64", dict(max_iter=iters, cg_max=10, cg_fixed=1, log_schedule=1))
     sl.batch.run(iters)
     res = sl.batch.result(sl.slot)
-    xo, _ = orc.parsdmm(m, shape, sets, orc.Options(max_iter=iters, cg_max=10, cg_fixed=True))
-    err = rel(sl.x(), xo)
-    print(f"[edge] {name}: rel err {err:.2e}", flush=True)
     assert res["status"] == 0
+    rho, gam = sl.batch.schedule(sl.slot, iters)
+    oo = orc.Options(max_iter=iters, cg_max=10, cg_fixed=True)
+    xl, _ = orc.parsdmm(m, shape, sets, oo, schedule={k + 1: (rho[k], gam[k]) for k in range(iters)})
+    xo, rho_o, gam_o = _oracle_run_with_schedule(m, shape, sets, oo)
+    same = rho_o.shape == rho.shape and np.allclose(rho_o, rho, rtol=1e-9, atol=0) and \
+        np.allclose(gam_o, gam, rtol=1e-9, atol=0)
+    err_locked = rel(sl.x(), xl)
+    err = rel(sl.x(), xo)
+    print(f"[edge] {name}: schedule-locked rel err {err_locked:.2e}, free-running {err:.2e}, "
+          f"same schedule {same}", flush=True)
     if name == "one_set_box_only":
         # the iterate reaches clip(m) exactly within a few iterations; after
         # that the adapt dots are rounding noise on both sides, so compare both
@@ -225,7 +254,9 @@ def test_edge_cases_f64(name):
         np.testing.assert_allclose(sl.x(), np.clip(m, -0.1, 0.2).ravel(), atol=1e-5)
         np.testing.assert_allclose(xo.ravel(), np.clip(m, -0.1, 0.2).ravel(), atol=1e-5)
         assert err <= 1e-4
-    else:
+        return
+    assert err_locked <= 1e-9
+    if same:
         assert err <= 1e-9
 
 
