@@ -17,7 +17,7 @@
 
 namespace sip {
 
-constexpr int kPB = 1024;  // threads per block of the CG and RHS kernels
+constexpr int kPB = 512;  // threads per block of the CG and RHS kernels (two blocks per CU)
 // Threads per block of the set and threshold kernels: more registers per
 // thread and no partial reduction at start, so smaller blocks let several
 // stay resident per CU (latency hiding on many small items).
@@ -77,6 +77,30 @@ __device__ __forceinline__ void reduce_range(const double* __restrict__ parts, i
     for (int j = 0; j < NV; ++j) out[j] += parts[(size_t)i * stride + off + j];
   }
   block_sum<NV, NT>(out, lds);
+}
+
+// Sum of parts[begin .. end) computed by every wave on its own (lanes stride
+// the range, then the butterfly): no LDS, no barrier, and the same order, so
+// the same value, in every wave of every block.
+__device__ __forceinline__ double wave_reduce(const double* __restrict__ parts, int begin, int end) {
+  double t = 0.0;
+  for (int i = begin + (int)(threadIdx.x & 63); i < end; i += 64) t += parts[i];
+  return wave_sum(t);
+}
+
+// Block total of one double, valid in thread 0 only (one barrier; lds must
+// not be in use by other threads).
+template <int NT>
+__device__ __forceinline__ double block_total(double v, double* lds) {
+  constexpr int NW = NT / 64;
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < NW; ++q) t += lds[q];
+  }
+  return t;
 }
 
 template <int NT>
@@ -573,18 +597,63 @@ __device__ __forceinline__ void group_valid(const GLane& L, const Geo& g, int ax
 }
 
 // Step j, first half: beta = rr_j / rr_{j-1}; p_j = r + beta p_{j-1} (p_0 = r);
-// partial p_j^T C p_j with C p_j evaluated on the fly (never stored).
+// partial p_j^T C p_j.  With C = c0 I + sum_a c_a D_a^T D_a (unit forward
+// differences), p^T C p = c0 |p|^2 + sum_a c_a |D_a p|^2: only the forward
+// neighbours are read (half the windows of C p), and every term is a square.
+template <typename T, int NA, bool HY, bool AL>
+__device__ __forceinline__ double group_pCp_v(const Src<T, NA>& f, const GLane& L, int lane, const Geo& g,
+                                              const Offs& of, T (&c)[Grp<T>::W], const double (&cf)[4]) {
+  constexpr int W = Grp<T>::W;
+  const int N = g.N;
+  T R[NA][W], ypa[NA][W], ypb[NA][W], zpa[NA][W], zpb[NA][W];
+  src_load<T, NA>(f, L.P0c, N, R);
+  if constexpr (HY) win_load<T, NA, AL>(f, L.P0c, g.sy, of.yp, N, ypa, ypb);
+  win_load<T, NA, AL>(f, L.P0c, g.sz, of.zp, N, zpa, zpb);
+  T re[NA];
+#pragma unroll
+  for (int a = 0; a < NA; ++a) re[a] = 0;
+  const bool own_right = lane == 63 || !L.next_vec;
+  if (own_right && L.P0c + W < N) {
+#pragma unroll
+    for (int a = 0; a < NA; ++a) re[a] = ldg(f.a[a] + L.P0c + W);
+  }
+  src_mix<T, NA>(f, R, c);
+  T right = __shfl_down(c[0], 1, 64);
+  if (own_right) right = src_one<T, NA>(f, re);
+  T yp[W], zp[W];
+  if constexpr (HY) win_get<T, NA, AL>(f, of.yp, ypa, ypb, yp);
+  win_get<T, NA, AL>(f, of.zp, zpa, zpb, zp);
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < W; ++e) {
+    int ize = L.iz, iye = L.iy, ixe = L.ix0 + e;
+    if (L.straddle) g.coords(L.P0c + e, ize, iye, ixe);
+    const double ce = (double)c[e];
+    const double rgt = (double)(e < W - 1 ? c[e < W - 1 ? e + 1 : W - 1] : right);
+    double t = cf[0] * ce * ce;
+    if (ixe < g.nx - 1) t += cf[3] * (rgt - ce) * (rgt - ce);
+    if constexpr (HY) {
+      if (iye < g.ny - 1) t += cf[2] * ((double)yp[e] - ce) * ((double)yp[e] - ce);
+    }
+    if (ize < g.nz - 1) t += cf[1] * ((double)zp[e] - ce) * ((double)zp[e] - ce);
+    if (e < L.cnt) acc += t;
+  }
+  return acc;
+}
+
 template <typename T, int NA>
 __device__ __forceinline__ double cg_dir_item(const InstDesc& d, const PtItem& it, const Geo& g, const Src<T, NA>& f,
-                                              T* __restrict__ pout, T c0, T cz, T cy, T cx) {
+                                              T* __restrict__ pout, const double (&cf)[4]) {
   constexpr int W = Grp<T>::W;
   const int lane = threadIdx.x & 63;
   const int end = it.begin + it.len;
   const bool grouped = item_grouped(d);
+  const bool al = rows_aligned<T>(g);
+  const bool hy = g.ny > 1;
   const Offs of = offs_of<T>(g);
-  auto fs = [&](int Q) -> T {
-    if constexpr (NA == 1) return f.a[0][Q];
-    else return f.a[0][Q] + f.beta * f.a[1][Q];
+  auto fs = [&](int Q) -> double {
+    if constexpr (NA == 1) return (double)f.a[0][Q];
+    else return (double)(f.a[0][Q] + f.beta * f.a[1][Q]);
   };
   double acc = 0.0;
   for (int base = it.begin; base < end; base += kPB * W) {
@@ -592,24 +661,31 @@ __device__ __forceinline__ double cg_dir_item(const InstDesc& d, const PtItem& i
     bool vec = false;
     if (grouped) {
       const GLane L = glane<T>(P0, it.begin, end, g);
-      T c[W], q[W];
-      group_C<T, NA>(f, L, lane, g, of, c, q, c0, cz, cy, cx);
+      T c[W];
+      double t;
+      if (hy) t = al ? group_pCp_v<T, NA, true, true>(f, L, lane, g, of, c, cf)
+                     : group_pCp_v<T, NA, true, false>(f, L, lane, g, of, c, cf);
+      else t = al ? group_pCp_v<T, NA, false, true>(f, L, lane, g, of, c, cf)
+                  : group_pCp_v<T, NA, false, false>(f, L, lane, g, of, c, cf);
       vec = L.vec;
       if (vec) {
         st16<T>(pout + P0, c);
-#pragma unroll
-        for (int e = 0; e < W; ++e)
-          if (e < L.cnt) acc += (double)c[e] * (double)q[e];
+        acc += t;
       }
     }
     if (!vec) {
       for (int e = 0; e < W; ++e) {
         const int P = P0 + e;
         if (P >= end) break;
-        const T pc = fs(P);
-        const T qq = point_apply_C<T>(P, g, fs, pc, c0, cz, cy, cx);
-        pout[P] = pc;
-        acc += (double)pc * (double)qq;
+        int iz, iy, ix;
+        g.coords(P, iz, iy, ix);
+        const double pc = fs(P);
+        double t = cf[0] * pc * pc;
+        if (ix < g.nx - 1) { const double dd = fs(P + 1) - pc; t += cf[3] * dd * dd; }
+        if (iy < g.ny - 1) { const double dd = fs(P + g.sy) - pc; t += cf[2] * dd * dd; }
+        if (iz < g.nz - 1) { const double dd = fs(P + g.sz) - pc; t += cf[1] * dd * dd; }
+        pout[P] = (T)pc;
+        acc += t;
       }
     }
   }
@@ -626,7 +702,7 @@ __global__ __launch_bounds__(kPB) void k_cg_dir(const InstDesc* __restrict__ D, 
   const InstDesc& d = D[it.inst];
   double* S = d.scal;
   if (!inst_live(S)) return;
-  const double rr = reduce_one<kPB>(rr_part, d.pt_begin, d.pt_end, lds);
+  const double rr = wave_reduce(rr_part, d.pt_begin, d.pt_end);
   bool done;
   double beta = 0.0;
   if (j == 0) {
@@ -647,17 +723,17 @@ __global__ __launch_bounds__(kPB) void k_cg_dir(const InstDesc* __restrict__ D, 
   const T* r = (const T*)d.r;
   const T* pin = (const T*)d.p[(j + 1) & 1];
   T* pout = (T*)d.p[j & 1];
-  const T c0 = (T)S[S_C0], cz = (T)S[S_CAX + 0], cy = (T)S[S_CAX + 1], cx = (T)S[S_CAX + 2];
-  double acc[1];
+  const double cf[4] = {S[S_C0], S[S_CAX + 0], S[S_CAX + 1], S[S_CAX + 2]};
+  double acc;
   if (j == 0) {
     const Src<T, 1> f{{r}, (T)0};
-    acc[0] = cg_dir_item<T, 1>(d, it, g, f, pout, c0, cz, cy, cx);
+    acc = cg_dir_item<T, 1>(d, it, g, f, pout, cf);
   } else {
     const Src<T, 2> f{{r, pin}, (T)beta};
-    acc[0] = cg_dir_item<T, 2>(d, it, g, f, pout, c0, cz, cy, cx);
+    acc = cg_dir_item<T, 2>(d, it, g, f, pout, cf);
   }
-  block_sum<1, kPB>(acc, lds);
-  if (threadIdx.x == 0) pq_part[iti] = acc[0];
+  acc = block_total<kPB>(acc, lds);
+  if (threadIdx.x == 0) pq_part[iti] = acc;
 }
 
 // Step j, second half: alpha = rr_j / p^T C p; x += alpha p; r -= alpha C p
@@ -674,7 +750,7 @@ __global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* __restrict__ D, 
   double* S = d.scal;
   if (!inst_live(S)) return;
   if (S[S_DONE + (j & 1)] != 0.0) return;
-  const double pq = reduce_one<kPB>(pq_part, d.pt_begin, d.pt_end, lds);
+  const double pq = wave_reduce(pq_part, d.pt_begin, d.pt_end);
   if (!(pq > 0.0) || !(pq <= 1.0e300)) {
     if (iti == d.pt_begin && threadIdx.x == 0) S[S_ERR] = (double)SIP_ENUMERIC;
     return;
@@ -728,8 +804,8 @@ __global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* __restrict__ D, 
       }
     }
   }
-  block_sum<1, kPB>(acc, lds);
-  if (threadIdx.x == 0) rr_part[iti] = acc[0];
+  const double tot = block_total<kPB>(acc[0], lds);
+  if (threadIdx.x == 0) rr_part[iti] = tot;
 }
 
 // -------------------------------------------------------- RHS + residual
@@ -872,8 +948,8 @@ __global__ __launch_bounds__(kPB) void k_rhs(const InstDesc* __restrict__ D, con
       }
     }
   }
-  block_sum<1, kPB>(acc, lds);
-  if (threadIdx.x == 0) rr_part[iti] = acc[0];
+  const double tot = block_total<kPB>(acc[0], lds);
+  if (threadIdx.x == 0) rr_part[iti] = tot;
 }
 
 // ------------------------------------------- clip-type sets + identity block
