@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--copy-mb", type=int, default=1024, help="plain-copy reference size (0: skip)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles")
     ap.add_argument("--tiles", default=None,
-                    help="fixed tiles pt_points,pt_max_items,thr_points,thr_max_items (no autotune)")
+                    help="fixed tiles pt_points,pt_max_items,thr_points,thr_max_items[,pt_threads] (no autotune)")
     return ap.parse_args()
 
 

@@ -212,11 +212,14 @@ int32_t sip_batch_schedule(sip_batch* b, int32_t slot, double* rho, double* gamm
 
 /* Work decomposition: grid points per item of the point kernels (RHS, CG,
  * projection) and of the threshold-set kernels, each a multiple of 256, and
- * grown when an instance would need more than max_items items.  Results are bit-identical for any batch composition at
- * fixed tile settings.  Applies from the next sip_batch_run.  Defaults
- * 2048/512 and 2048/512. */
+ * grown when an instance would need more than max_items items; pt_threads
+ * (256 or 512) is the block size of the RHS and CG kernels.  Results are
+ * bit-identical for any batch composition at fixed tile settings.  Applies
+ * from the next sip_batch_run.  Defaults 2048/512, 2048/512, 512 threads.
+ * SIP_EINVAL for sizes that are not multiples of 256, max_items < 1 or
+ * another thread count. */
 int32_t sip_batch_set_tiles(sip_batch* b, int32_t pt_points, int32_t pt_max_items, int32_t thr_points,
-                            int32_t thr_max_items);
+                            int32_t thr_max_items, int32_t pt_threads);
 
 /* Re-initialise a slot's state from a new m of the same grid (x = m,
  * y_i = A_i m, v_i = 0, rho0/gamma0, k = 1) without touching the work tables

@@ -237,7 +237,7 @@ struct Slot {
   int64_t N = 0;
 };
 
-struct TileCfg { int64_t pt_base = 2048, pt_max_items = 512, thr_base = 2048, thr_max_items = 512; };
+struct TileCfg { int64_t pt_base = 2048, pt_max_items = 512, thr_base = 2048, thr_max_items = 512; int pt_threads = 512; };
 
 }  // namespace sip
 
@@ -390,9 +390,11 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   t.rr_part = b->d_rr; t.pq_part = b->d_pq; t.proj_part = b->d_proj;
   t.thrw_part = b->d_thrw; t.thra_part = b->d_thra; t.tie_part = b->d_tie;
   t.any_card = any_card;
+  const bool threads_changed = t.pt_threads != (int)b->tiles.pt_threads;
+  t.pt_threads = (int)b->tiles.pt_threads;
   b->live_items = (int)pt.size() + (int)thr.size();
   b->live_inst = (int)inst.size();
-  if (relaunch || moved) drop_graphs(b);
+  if (relaunch || moved || threads_changed) drop_graphs(b);
   b->dirty = false;
   return SIP_OK;
 }
@@ -843,11 +845,12 @@ int32_t sip_stream_copy(void* dst, const void* src, int64_t bytes, void* stream_
 }
 
 int32_t sip_batch_set_tiles(sip_batch* b, int32_t pt_points, int32_t pt_max_items, int32_t thr_points,
-                            int32_t thr_max_items) {
+                            int32_t thr_max_items, int32_t pt_threads) {
   if (!b || pt_points < kTileQuantum || thr_points < kTileQuantum || pt_points % kTileQuantum ||
-      thr_points % kTileQuantum ||
-      pt_max_items < 1 || thr_max_items < 1)
+      thr_points % kTileQuantum || pt_max_items < 1 || thr_max_items < 1 ||
+      (pt_threads != 256 && pt_threads != 512))
     return SIP_EINVAL;
+  b->tiles.pt_threads = pt_threads;
   b->tiles.pt_base = pt_points;
   b->tiles.pt_max_items = pt_max_items;
   b->tiles.thr_base = thr_points;

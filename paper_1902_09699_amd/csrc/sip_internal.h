@@ -149,6 +149,7 @@ struct Tables {
   double* rr_part; double* pq_part; double* proj_part; double* thrw_part; double* thra_part;
   uint32_t* tie_part;
   bool any_card;
+  int pt_threads;  // threads per block of the RHS and CG kernels (256 or 512)
 };
 
 inline FastDiv make_fastdiv(uint32_t d) {

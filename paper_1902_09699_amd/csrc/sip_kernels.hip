@@ -17,7 +17,6 @@
 
 namespace sip {
 
-constexpr int kPB = 512;  // threads per block of the CG and RHS kernels (two blocks per CU)
 // Threads per block of the set and threshold kernels: more registers per
 // thread and no partial reduction at start, so smaller blocks let several
 // stay resident per CU (latency hiding on many small items).
@@ -641,7 +640,7 @@ __device__ __forceinline__ double group_pCp_v(const Src<T, NA>& f, const GLane& 
   return acc;
 }
 
-template <typename T, int NA>
+template <typename T, int NA, int NT>
 __device__ __forceinline__ double cg_dir_item(const InstDesc& d, const PtItem& it, const Geo& g, const Src<T, NA>& f,
                                               T* __restrict__ pout, const double (&cf)[4]) {
   constexpr int W = Grp<T>::W;
@@ -656,7 +655,7 @@ __device__ __forceinline__ double cg_dir_item(const InstDesc& d, const PtItem& i
     else return (double)(f.a[0][Q] + f.beta * f.a[1][Q]);
   };
   double acc = 0.0;
-  for (int base = it.begin; base < end; base += kPB * W) {
+  for (int base = it.begin; base < end; base += NT * W) {
     const int P0 = base + (int)threadIdx.x * W;
     bool vec = false;
     if (grouped) {
@@ -692,10 +691,10 @@ __device__ __forceinline__ double cg_dir_item(const InstDesc& d, const PtItem& i
   return acc;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kPB) void k_cg_dir(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const PtItem* __restrict__ items, int j,
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_cg_dir(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const PtItem* __restrict__ items, int j,
                                                 const double* rr_part, double* pq_part, Opts o) {
-  __shared__ double lds[lds_sum<1, kPB>()];
+  __shared__ double lds[lds_sum<1, NT>()];
   if ((int)blockIdx.x >= cnt->npt) return;
   const int iti = xcd_item(blockIdx.x, cnt->npt);
   const PtItem it = items[iti];
@@ -727,22 +726,22 @@ __global__ __launch_bounds__(kPB) void k_cg_dir(const InstDesc* __restrict__ D, 
   double acc;
   if (j == 0) {
     const Src<T, 1> f{{r}, (T)0};
-    acc = cg_dir_item<T, 1>(d, it, g, f, pout, cf);
+    acc = cg_dir_item<T, 1, NT>(d, it, g, f, pout, cf);
   } else {
     const Src<T, 2> f{{r, pin}, (T)beta};
-    acc = cg_dir_item<T, 2>(d, it, g, f, pout, cf);
+    acc = cg_dir_item<T, 2, NT>(d, it, g, f, pout, cf);
   }
-  acc = block_total<kPB>(acc, lds);
+  acc = block_total<NT>(acc, lds);
   if (threadIdx.x == 0) pq_part[iti] = acc;
 }
 
 // Step j, second half: alpha = rr_j / p^T C p; x += alpha p; r -= alpha C p
 // (C p recomputed from p); partial r^T r.
-template <typename T>
-__global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const PtItem* __restrict__ items, int j,
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_cg_upd(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const PtItem* __restrict__ items, int j,
                                                 const double* pq_part, double* rr_part) {
   constexpr int W = Grp<T>::W;
-  __shared__ double lds[lds_sum<1, kPB>()];
+  __shared__ double lds[lds_sum<1, NT>()];
   if ((int)blockIdx.x >= cnt->npt) return;
   const int iti = xcd_item(blockIdx.x, cnt->npt);
   const PtItem it = items[iti];
@@ -770,7 +769,7 @@ __global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* __restrict__ D, 
   const Offs of = offs_of<T>(g);
   double acc[1] = {0.0};
   const int end = it.begin + it.len;
-  for (int base = it.begin; base < end; base += kPB * W) {
+  for (int base = it.begin; base < end; base += NT * W) {
     const int P0 = base + (int)threadIdx.x * W;
     bool vec = false;
     if (grouped) {
@@ -804,7 +803,7 @@ __global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* __restrict__ D, 
       }
     }
   }
-  const double tot = block_total<kPB>(acc[0], lds);
+  const double tot = block_total<NT>(acc[0], lds);
   if (threadIdx.x == 0) rr_part[iti] = tot;
 }
 
@@ -813,10 +812,10 @@ __global__ __launch_bounds__(kPB) void k_cg_upd(const InstDesc* __restrict__ D, 
 // b = sum_{i<=p+1} A_i^T (rho_i y_i + v_i);  r = b - C x;  partial r^T r.
 // A_i^T of a forward difference needs u = rho y + v one point back along the
 // axis: the previous lane's last value for x, a window for y / z.
-template <typename T>
-__global__ __launch_bounds__(kPB) void k_rhs(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const PtItem* __restrict__ items, double* rr_part) {
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_rhs(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const PtItem* __restrict__ items, double* rr_part) {
   constexpr int W = Grp<T>::W;
-  __shared__ double lds[lds_sum<1, kPB>()];
+  __shared__ double lds[lds_sum<1, NT>()];
   if ((int)blockIdx.x >= cnt->npt) return;
   const int iti = xcd_item(blockIdx.x, cnt->npt);
   const PtItem it = items[iti];
@@ -839,7 +838,7 @@ __global__ __launch_bounds__(kPB) void k_rhs(const InstDesc* __restrict__ D, con
   const int N = g.N;
   double acc[1] = {0.0};
   const int end = it.begin + it.len;
-  for (int base = it.begin; base < end; base += kPB * W) {
+  for (int base = it.begin; base < end; base += NT * W) {
     const int P0 = base + (int)threadIdx.x * W;
     bool vec = false;
     if (grouped) {
@@ -948,7 +947,7 @@ __global__ __launch_bounds__(kPB) void k_rhs(const InstDesc* __restrict__ D, con
       }
     }
   }
-  const double tot = block_total<kPB>(acc[0], lds);
+  const double tot = block_total<NT>(acc[0], lds);
   if (threadIdx.x == 0) rr_part[iti] = tot;
 }
 
@@ -2124,14 +2123,29 @@ void launch_init(hipStream_t st, const InstDesc* __restrict__ D, int inst, int64
   k_init<T><<<(int)(nb < 2048 ? nb : 2048), kBlock, 0, st>>>(D, inst);
 }
 
+// RHS and the CG steps with NT threads per block.
+template <typename T, int NT>
+void launch_cg(hipStream_t st, const Tables& t, const Opts& o) {
+  k_rhs<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, t.rr_part);
+  for (int j = 0; j < o.cg_max; ++j) {
+    k_cg_dir<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, j, t.rr_part, t.pq_part, o);
+    k_cg_upd<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, j, t.pq_part, t.rr_part);
+  }
+}
+
+template <typename T, int NT>
+void launch_point_phase(hipStream_t st, const Tables& t, const Opts& o, int phase) {
+  if (!t.npt) return;
+  if (phase == 0) k_rhs<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, t.rr_part);
+  if (phase == 1) k_cg_dir<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, 1, t.rr_part, t.pq_part, o);
+  if (phase == 2) k_cg_upd<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, 1, t.pq_part, t.rr_part);
+}
+
 template <typename T>
 void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
   if (t.npt > 0) {
-    k_rhs<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, t.rr_part);
-    for (int j = 0; j < o.cg_max; ++j) {
-      k_cg_dir<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, j, t.rr_part, t.pq_part, o);
-      k_cg_upd<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, j, t.pq_part, t.rr_part);
-    }
+    if (t.pt_threads == 256) launch_cg<T, 256>(st, t, o);
+    else launch_cg<T, 512>(st, t, o);
     if (t.nsp) k_proj<T><<<t.nsp, kSB, 0, st>>>(t.D, t.cnt, t.sp, o, t.proj_part);
   }
   if (t.nthr > 0) {
@@ -2152,9 +2166,12 @@ void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
 template <typename T>
 void launch_phase(hipStream_t st, const Tables& t, const Opts& o, int phase) {
   switch (phase) {
-    case 0: if (t.npt) k_rhs<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, t.rr_part); break;
-    case 1: if (t.npt) k_cg_dir<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, 1, t.rr_part, t.pq_part, o); break;
-    case 2: if (t.npt) k_cg_upd<T><<<t.npt, kPB, 0, st>>>(t.D, t.cnt, t.pt, 1, t.pq_part, t.rr_part); break;
+    case 0:
+    case 1:
+    case 2:
+      if (t.pt_threads == 256) launch_point_phase<T, 256>(st, t, o, phase);
+      else launch_point_phase<T, 512>(st, t, o, phase);
+      break;
     case 3: if (t.nsp) k_proj<T><<<t.nsp, kSB, 0, st>>>(t.D, t.cnt, t.sp, o, t.proj_part); break;
     case 4: if (t.nthr) k_thr_w<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thrw_part); break;
     case 5: if (t.nthr) k_thr_apply<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thra_part, t.tie_part); break;

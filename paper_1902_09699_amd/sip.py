@@ -99,7 +99,7 @@ def lib():
         "sip_batch_set_params": (i32, [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_double), i32, i32, vp]),
         "sip_batch_schedule": (i32, [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_double), i32,
                                      C.POINTER(i32), vp]),
-        "sip_batch_set_tiles": (i32, [vp, i32, i32, i32, i32]),
+        "sip_batch_set_tiles": (i32, [vp, i32, i32, i32, i32, i32]),
         "sip_batch_reset": (i32, [vp, i32, vp, vp]),
         "sip_batch_time_kernel": (i32, [vp, i32, i32, vp, C.POINTER(C.c_double)]),
         "sip_stream_copy": (i32, [vp, vp, i64, vp]),
@@ -372,9 +372,9 @@ class Batch:
         cnt = n.value
         return (np.array(rho[:cnt * p1]).reshape(cnt, p1), np.array(gam[:cnt * p1]).reshape(cnt, p1))
 
-    def set_tiles(self, pt_points=2048, pt_max_items=512, thr_points=2048, thr_max_items=512):
+    def set_tiles(self, pt_points=2048, pt_max_items=512, thr_points=2048, thr_max_items=512, pt_threads=512):
         check(lib().sip_batch_set_tiles(self.h, int(pt_points), int(pt_max_items), int(thr_points),
-                                        int(thr_max_items)), "sip_batch_set_tiles")
+                                        int(thr_max_items), int(pt_threads)), "sip_batch_set_tiles")
 
     def reset(self, slot, m, stream=None):
         _check_tensor(m, m.numel(), self.opts, "m")

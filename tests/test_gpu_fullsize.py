@@ -13,7 +13,8 @@ from tests.gpu_util import Slot, rel, sync_oracle
 
 pytestmark = pytest.mark.gpu
 
-TILES = {"default": (2048, 512, 2048, 512), "tuned": (1024, 256, 2048, 256)}
+TILES = {"default": (2048, 512, 2048, 512, 512), "tuned": (1024, 256, 2048, 256, 512),
+         "small_blocks": (2048, 1024, 4096, 512, 256)}
 
 
 def _load(name):
@@ -25,7 +26,8 @@ def _load(name):
     return m, wl.finalize(m, sets), field, iters
 
 
-@pytest.mark.parametrize("name,tiles", [("layered2d", "default"), ("layered2d", "tuned"), ("smooth3d", "tuned")])
+@pytest.mark.parametrize("name,tiles", [("layered2d", "default"), ("layered2d", "tuned"), ("layered2d", "small_blocks"),
+                                        ("smooth3d", "tuned"), ("smooth3d", "small_blocks")])
 def test_fullsize_lockstep(name, tiles):
     m, sets, field, iters = _load(name)
     print(f"\n[fullsize] {name} {m.shape} tiles={TILES[tiles]}", flush=True)

@@ -34,16 +34,17 @@ def _card_mask(w, k, rtol):
     return np.abs(a - tk) > rtol * max(tk, 1e-300)
 
 
-@pytest.mark.parametrize("kind,field", [
-    ("box_tv_2d", "f64"), ("box_tv_2d", "f32"),
-    ("four_sets_2d", "f32"), ("four_sets_2d", "f64"),
-    ("box_tv_lat_3d", "f32"), ("mixed_2d", "f32"), ("mixed_3d", "f64"), ("mixed_3d", "f32"),
+@pytest.mark.parametrize("kind,field,threads", [
+    ("box_tv_2d", "f64", 512), ("box_tv_2d", "f32", 512),
+    ("four_sets_2d", "f32", 512), ("four_sets_2d", "f64", 512),
+    ("box_tv_lat_3d", "f32", 512), ("mixed_2d", "f32", 512), ("mixed_3d", "f64", 512), ("mixed_3d", "f32", 512),
+    ("four_sets_2d", "f32", 256), ("box_tv_lat_3d", "f32", 256), ("mixed_3d", "f64", 256),
 ])
-def test_step_parity(kind, field):
+def test_step_parity(kind, field, threads):
     m, sets = _prep(kind, field)
     iters = 9
-    print(f"\n[step parity] {kind} {field} shape={m.shape}", flush=True)
-    sl = Slot(m, sets, field, dict(max_iter=50, cg_max=10, cg_fixed=1))
+    print(f"\n[step parity] {kind} {field} shape={m.shape} threads={threads}", flush=True)
+    sl = Slot(m, sets, field, dict(max_iter=50, cg_max=10, cg_fixed=1), tiles=(1024, 1024, 1024, 512, threads))
     prob = orc.Problem(m, m.shape, sets)
     oo = orc.Options(max_iter=50, cg_max=10, cg_fixed=True)
     st = orc.initial_state(prob, oo)
