@@ -80,16 +80,21 @@ def algorithmic_bytes(insts, esz):
     CG direction: read r, p, write p (3N); CG update: read x, r, p, write x, r
     (5N); RHS: read x and every y_i, v_i (identity block included), write r;
     projection (non-adapt iteration): read x, m, y_i, v_i of the bounds sets
-    and the identity block, write y_i, v_i."""
-    b = {"cg_dir": 0, "cg_upd": 0, "rhs": 0, "proj": 0}
+    and the identity block, write y_i, v_i; threshold w pass: read x, y_i,
+    v_i, write w over y_i (N + 3 M_i per l1 / cardinality set); threshold
+    apply pass: read w, write y_i, v_i (3 M_i)."""
+    b = {"cg_dir": 0, "cg_upd": 0, "rhs": 0, "proj": 0, "thr_w": 0, "thr_apply": 0}
     for m, sets in insts:
         N = m.size
         sum_m = N + sum(rows(m.shape, s) for s in sets)
         clip = N + sum(rows(m.shape, s) for s in sets if s["kind"] == "bounds")
+        thr = [rows(m.shape, s) for s in sets if s["kind"] != "bounds"]
         b["cg_dir"] += 3 * N * esz
         b["cg_upd"] += 5 * N * esz
         b["rhs"] += (2 * N + 2 * sum_m) * esz
         b["proj"] += (2 * N + 4 * clip) * esz
+        b["thr_w"] += sum(N + 3 * mi for mi in thr) * esz
+        b["thr_apply"] += sum(3 * mi for mi in thr) * esz
     return b
 
 
@@ -200,10 +205,13 @@ def main():
         r_, g_, _, _ = batch.get_params(sl)
         batch.set_params(sl, r_, g_, 2, True)
     ab = algorithmic_bytes(insts, esz)
-    ids = {"cg_dir": sip.K_CG_DIR, "cg_upd": sip.K_CG_UPD, "rhs": sip.K_RHS, "proj": sip.K_PROJ}
-    per_iter = {"cg_dir": 10, "cg_upd": 10, "rhs": 1, "proj": 1}
+    ids = {"cg_dir": sip.K_CG_DIR, "cg_upd": sip.K_CG_UPD, "rhs": sip.K_RHS, "proj": sip.K_PROJ,
+           "thr_w": sip.K_THR_W, "thr_apply": sip.K_THR_APPLY}
+    per_iter = {"cg_dir": 10, "cg_upd": 10, "rhs": 1, "proj": 1, "thr_w": 1, "thr_apply": 1}
     kernels = {}
     for name, kid in ids.items():
+        if ab[name] == 0:
+            continue
         t_ms = batch.time_kernel(kid, args.reps)
         kernels[name] = {"ms": t_ms, "GBs": ab[name] / (t_ms * 1e-3) / 1e9, "bytes": ab[name],
                          "launches_per_iter": per_iter[name]}

@@ -1523,52 +1523,88 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
   const T* __restrict__ x = (const T*)d.x;
   K* __restrict__ cand = (K*)s.cand[it.src];
   unsigned long long* ncand = &s.sel[it.src]->ncand;
+  constexpr int W = Grp<T>::W;
+  constexpr int CB = W == 4 ? 3 : 2;  // bits of a per-thread hit count (0..W)
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int end = it.begin + it.len;
+  const bool grouped = item_grouped(d);
+  const Offs of = offs_of<T>(g);
   for (int c = 0; c < s.ncomp; ++c) {
     const int axis = s.axis[c];
     const T* __restrict__ y = (const T*)s.y + (size_t)c * g.cs;
-    for (int base = it.begin; base < end; base += kSB) {
-      const int P = base + (int)threadIdx.x;
-      bool hit = false;
-      K key = 0;
-      if (P < end) {
-        int iz, iy, ix;
-        g.coords(P, iz, iy, ix);
-        T val = 0;
-        bool valid;
-        if (it.src == 0) {
-          valid = comp_valid(axis, iz, iy, ix, g);
-          if (valid) val = y[P];
+    for (int base = it.begin; base < end; base += kSB * W) {
+      const int P0 = base + (int)threadIdx.x * W;
+      T val[W];
+      bool ok[W];
+      if (grouped) {
+        const GLane L = glane<T>(P0, it.begin, end, g);
+        if (it.src == 1) {
+          group_diff<T>(x, L, lane, g, d, of, axis, val, ok);
         } else {
-          valid = comp_value<T>(x, P, axis, iz, iy, ix, g, d, val);
+          group_valid<T>(L, g, axis, ok);
+          ld16<T>(y + L.P0c, val);
         }
-        if (valid) {
-          key = KT::key(val);
-          hit = (K)(key >> shp) == want;
+        if (!L.vec) {
+#pragma unroll
+          for (int e = 0; e < W; ++e) ok[e] = false;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+          const int P = P0 + e;
+          ok[e] = false;
+          val[e] = 0;
+          if (P < end) {
+            int iz, iy, ix;
+            g.coords(P, iz, iy, ix);
+            if (it.src == 0) {
+              ok[e] = comp_valid(axis, iz, iy, ix, g);
+              if (ok[e]) val[e] = y[P];
+            } else {
+              ok[e] = comp_value<T>(x, P, axis, iz, iy, ix, g, d, val[e]);
+            }
+          }
         }
       }
-      if (hit) {
-        const int bkt = (int)((key >> sh) & (K)(nb - 1));
-        atomicAdd(&hc[bkt], 1u);
-        if (l1) atomicAdd(&hs[bkt], KT::value(key));
+      K key[W];
+      bool hit[W];
+      int nhit = 0;
+#pragma unroll
+      for (int e = 0; e < W; ++e) {
+        key[e] = KT::key(val[e]);
+        hit[e] = ok[e] && (K)(key[e] >> shp) == want;
+        if (hit[e]) {
+          ++nhit;
+          const int bkt = (int)((key[e] >> sh) & (K)(nb - 1));
+          atomicAdd(&hc[bkt], 1u);
+          if (l1) atomicAdd(&hs[bkt], KT::value(key[e]));
+        }
       }
       if (compact) {
-        // block-aggregated append: wave counts, one atomic for the block
-        const unsigned long long mask = __ballot(hit);
-        if (lane == 0) wcnt[wv] = (uint32_t)__popcll(mask);
+        // block-aggregated append: wave prefix of the per-thread hit counts
+        // (one ballot per count bit), one atomic for the block
+        unsigned long long pre = 0, tot = 0;
+#pragma unroll
+        for (int bit = 0; bit < CB; ++bit) {
+          const unsigned long long m = __ballot((nhit >> bit) & 1);
+          pre += (unsigned long long)__popcll(m & below) << bit;
+          tot += (unsigned long long)__popcll(m) << bit;
+        }
+        if (lane == 0) wcnt[wv] = (uint32_t)tot;
         __syncthreads();
         if (threadIdx.x == 0) {
-          unsigned long long tot = 0;
-          for (int q = 0; q < kSW; ++q) tot += wcnt[q];
-          bbase = tot ? atomicAdd(ncand, tot) : 0ull;
+          unsigned long long t = 0;
+          for (int q = 0; q < kSW; ++q) t += wcnt[q];
+          bbase = t ? atomicAdd(ncand, t) : 0ull;
         }
         __syncthreads();
-        if (hit) {
-          unsigned long long off = bbase;
+        if (nhit) {
+          unsigned long long off = bbase + pre;
           for (int q = 0; q < wv; ++q) off += wcnt[q];
-          const unsigned long long below = mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
-          cand[off + __popcll(below)] = key;
+#pragma unroll
+          for (int e = 0; e < W; ++e)
+            if (hit[e]) cand[off++] = key[e];
         }
         __syncthreads();
       }
@@ -1685,14 +1721,33 @@ __global__ __launch_bounds__(kSB) void k_card_ties(const InstDesc* __restrict__ 
   const Geo g(d);
   const K tkey = (K)st.tkey;
   const int end = it.begin + it.len;
+  constexpr int W = Grp<T>::W;
+  const bool grouped = item_grouped(d);
   for (int c = 0; c < s.ncomp; ++c) {
     const T* y = (const T*)s.y + (size_t)c * g.cs;
     uint32_t local = 0;
-    for (int P = it.begin + (int)threadIdx.x; P < end; P += kSB) {
-      int iz, iy, ix;
-      g.coords(P, iz, iy, ix);
-      if (!comp_valid(s.axis[c], iz, iy, ix, g)) continue;
-      if (KT::key(y[P]) == tkey) ++local;
+    for (int base = it.begin; base < end; base += kSB * W) {
+      const int P0 = base + (int)threadIdx.x * W;
+      if (grouped) {
+        const GLane L = glane<T>(P0, it.begin, end, g);
+        if (L.vec) {
+          bool ok[W];
+          T v[W];
+          group_valid<T>(L, g, s.axis[c], ok);
+          ld16<T>(y + P0, v);
+#pragma unroll
+          for (int e = 0; e < W; ++e)
+            if (ok[e] && KT::key(v[e]) == tkey) ++local;
+        }
+      } else {
+        for (int e = 0; e < W; ++e) {
+          const int P = P0 + e;
+          if (P >= end) break;
+          int iz, iy, ix;
+          g.coords(P, iz, iy, ix);
+          if (comp_valid(s.axis[c], iz, iy, ix, g) && KT::key(y[P]) == tkey) ++local;
+        }
+      }
     }
     if (local) atomicAdd(&tcnt[c], local);
   }
