@@ -1135,18 +1135,49 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
     const int H = o.evol_hist;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double accx[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int P = it.begin + (int)threadIdx.x; P < end; P += kSB) {
-      const T xv = x[P];
-      if (adapt) xw[P] = xv;
-      if (ring) {
-        ring[(size_t)(k % (H + 1)) * g.cs + P] = xv;
-        if (check) {
-          accx[0] += (double)xv * (double)xv;
+    if (grouped) {
+      // 16-byte groups (the snapshot and history arrays are padded)
+      for (int P0 = it.begin + (int)threadIdx.x * W; P0 < end; P0 += kSB * W) {
+        const int cnt = end - P0 < W ? end - P0 : W;
+        T xv[W];
+        ld16p<T>(x, P0, g.N, xv);
+        if (adapt) st16<T>(xw + P0, xv);
+        if (ring) {
+          st16<T>(ring + (size_t)(k % (H + 1)) * g.cs + P0, xv);
+          if (check) {
 #pragma unroll
-          for (int jj = 1; jj < kMaxHist; ++jj) {
-            if (jj > H) break;
-            const double e = (double)xv - (double)ring[(size_t)((k - jj) % (H + 1)) * g.cs + P];
-            if (jj <= 7) acc[jj] += e * e; else accx[jj - 7] += e * e;
+            for (int e = 0; e < W; ++e)
+              if (e < cnt) accx[0] += (double)xv[e] * (double)xv[e];
+#pragma unroll
+            for (int jj = 1; jj < kMaxHist; ++jj) {
+              if (jj > H) break;
+              T rv[W];
+              ld16<T>(ring + (size_t)((k - jj) % (H + 1)) * g.cs + P0, rv);
+              double t = 0.0;
+#pragma unroll
+              for (int e = 0; e < W; ++e) {
+                const double df = (double)xv[e] - (double)rv[e];
+                if (e < cnt) t += df * df;
+              }
+              if (jj <= 7) acc[jj] += t; else accx[jj - 7] += t;
+            }
+          }
+        }
+      }
+    } else {
+      for (int P = it.begin + (int)threadIdx.x; P < end; P += kSB) {
+        const T xv = x[P];
+        if (adapt) xw[P] = xv;
+        if (ring) {
+          ring[(size_t)(k % (H + 1)) * g.cs + P] = xv;
+          if (check) {
+            accx[0] += (double)xv * (double)xv;
+#pragma unroll
+            for (int jj = 1; jj < kMaxHist; ++jj) {
+              if (jj > H) break;
+              const double e = (double)xv - (double)ring[(size_t)((k - jj) % (H + 1)) * g.cs + P];
+              if (jj <= 7) acc[jj] += e * e; else accx[jj - 7] += e * e;
+            }
           }
         }
       }
@@ -1213,6 +1244,34 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, c
     atomicAdd(&hc[bkt], 1u);
     if (l1) atomicAdd(&hs[bkt], KT::value(key));
   };
+  // a group's values, runs of equal buckets merged into one update (the
+  // bucket sums of float keys are exact, so the merge changes no result)
+  auto bin_group = [&](const T (&v)[W], const bool (&ok)[W]) {
+    int cur = -1;
+    uint32_t n = 0;
+    double sum = 0.0;
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      if (!ok[e]) continue;
+      const typename KT::K key = KT::key(v[e]);
+      const int bkt = (int)(key >> sh0);
+      if (bkt != cur) {
+        if (n) {
+          atomicAdd(&hc[cur], n);
+          if (l1) atomicAdd(&hs[cur], sum);
+        }
+        cur = bkt;
+        n = 0;
+        sum = 0.0;
+      }
+      ++n;
+      sum += KT::value(key);
+    }
+    if (n) {
+      atomicAdd(&hc[cur], n);
+      if (l1) atomicAdd(&hs[cur], sum);
+    }
+  };
   for (int c = 0; c < s.ncomp; ++c) {
     const int axis = s.axis[c];
     const size_t off = (size_t)c * g.cs;
@@ -1255,16 +1314,12 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, c
             }
             st16<T>(vh0 + P0, vh);
           }
-#pragma unroll
-          for (int e = 0; e < W; ++e)
-            if (ok[e]) bin(wv[e]);
+          bin_group(wv, ok);
         } else {
 #pragma unroll
-          for (int e = 0; e < W; ++e) {
-            if (!ok[e]) continue;
-            acc[7] += (double)sv[e] * (double)sv[e];
-            bin(sv[e]);
-          }
+          for (int e = 0; e < W; ++e)
+            if (ok[e]) acc[7] += (double)sv[e] * (double)sv[e];
+          bin_group(sv, ok);
         }
         continue;
       }
@@ -1570,16 +1625,33 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
       K key[W];
       bool hit[W];
       int nhit = 0;
+      int cur = -1;
+      uint32_t run = 0;
+      double rsum = 0.0;
 #pragma unroll
       for (int e = 0; e < W; ++e) {
         key[e] = KT::key(val[e]);
         hit[e] = ok[e] && (K)(key[e] >> shp) == want;
         if (hit[e]) {
           ++nhit;
+          // runs of equal buckets merged into one update (exact sums for float keys)
           const int bkt = (int)((key[e] >> sh) & (K)(nb - 1));
-          atomicAdd(&hc[bkt], 1u);
-          if (l1) atomicAdd(&hs[bkt], KT::value(key[e]));
+          if (bkt != cur) {
+            if (run) {
+              atomicAdd(&hc[cur], run);
+              if (l1) atomicAdd(&hs[cur], rsum);
+            }
+            cur = bkt;
+            run = 0;
+            rsum = 0.0;
+          }
+          ++run;
+          rsum += KT::value(key[e]);
         }
+      }
+      if (run) {
+        atomicAdd(&hc[cur], run);
+        if (l1) atomicAdd(&hs[cur], rsum);
       }
       if (compact) {
         // block-aggregated append: wave prefix of the per-thread hit counts
