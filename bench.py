@@ -39,6 +39,10 @@ def parse():
     ap.add_argument("--batched-count", type=int, default=256)
     ap.add_argument("--copy-mb", type=int, default=1024, help="plain-copy reference size (0: skip)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles")
+    ap.add_argument("--reduce", default="f64", choices=("f64", "f32"),
+                    help="reduction type (f32: the pure-FP32 precision ablation)")
+    ap.add_argument("--check-iters", type=int, default=10,
+                    help="iterations of the schedule-locked error check against the oracle (0: skip)")
     ap.add_argument("--tiles", default=None,
                     help="fixed tiles pt_points,pt_max_items,thr_points,thr_max_items[,pt_threads] (no autotune)")
     return ap.parse_args()
@@ -119,28 +123,73 @@ def traffic_from_profiles(kernel, wname):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(insts, iters_full, budget_s):
+def device_reference(inst, field, reduce, iters):
+    """The first instance alone on the device for `iters` iterations with the
+    (rho, gamma) schedule logged: its x and the schedule."""
+    import torch
+    from paper_1902_09699_amd import sip
+    m, sets = inst
+    opts = sip.make_opts(field, reduce=reduce, max_iter=iters, cg_max=10, cg_fixed=1, log_schedule=1)
+    md = torch.tensor(m, dtype=torch.float64 if field == "f64" else torch.float32, device="cuda")
+    xd = torch.empty_like(md)
+    b = sip.Batch(1, sip.workspace_bytes(m.shape, sets, opts), opts)
+    slot = b.add(md, sets, xd)
+    b.run(iters)
+    rho, gam = b.schedule(slot, iters)
+    x = xd.double().cpu().numpy()
+    b.close()
+    return x, {k + 1: (rho[k], gam[k]) for k in range(len(rho))}
+
+
+def oracle_sensitivity(inst, iters, schedule, field):
+    """How far the oracle's own x moves after `iters` iterations (same
+    schedule) when m is perturbed by one unit roundoff of the field type:
+    the scale an error against the oracle is to be read on."""
+    from oracle import parsdmm as orc
+    m, sets = inst
+    u = 2.0 ** -24 if field == "f32" else 2.0 ** -53
+    mp = m * (1.0 + u * np.random.default_rng(5).standard_normal(m.shape))
+    oo = orc.Options(max_iter=iters, cg_max=10, cg_fixed=True)
+    xa, _ = orc.parsdmm(m, m.shape, sets, oo, schedule=schedule)
+    xb, _ = orc.parsdmm(mp, m.shape, sets, oo, schedule=schedule)
+    return float(np.linalg.norm(xb - xa) / max(np.linalg.norm(xa), 1e-300))
+
+
+def cpu_baseline(insts, iters_full, budget_s, schedule=None, check=None):
     """The FP64 oracle as it stands, on the first instance, for as many
-    iterations as fit the budget (at least 2)."""
+    iterations as fit the budget (at least 2), replaying the device's (rho,
+    gamma) schedule where one is given; check = (k, x_device) compares the
+    oracle's x after iteration k with the device's."""
     from oracle import parsdmm as orc
     m, sets = insts[0]
     prob = orc.Problem(m, m.shape, sets)
     opts = orc.Options(max_iter=iters_full, cg_max=10, cg_fixed=True)
     st = orc.initial_state(prob, opts)
-    orc.iterate(prob, st, opts)  # first iteration: warm-up, untimed
+    err = None
+
+    def step():
+        nonlocal err
+        orc.iterate(prob, st, opts, schedule)
+        if check is not None and st.k - 1 == check[0]:
+            xo = st.x.ravel()
+            err = float(np.linalg.norm(check[1].ravel() - xo) / max(np.linalg.norm(xo), 1e-300))
+
+    step()  # first iteration: warm-up, untimed
     ru0 = resource.getrusage(resource.RUSAGE_SELF)
     t0 = time.perf_counter()
     done = 0
-    while done < 2 or (time.perf_counter() - t0 < budget_s and st.k <= iters_full):
-        orc.iterate(prob, st, opts)
+    while done < 2 or (time.perf_counter() - t0 < budget_s and st.k <= iters_full) or \
+            (check is not None and err is None and st.k <= check[0]):
+        step()
         done += 1
     wall = time.perf_counter() - t0
     ru1 = resource.getrusage(resource.RUSAGE_SELF)
     cpu = (ru1.ru_utime - ru0.ru_utime) + (ru1.ru_stime - ru0.ru_stime)
     cores = max(1, int(round(cpu / wall)))
-    return {"value": m.size * done / wall, "unit": "grid-pts*iters/s", "cores": cores, "kind": "oracle",
-            "sample": f"iterations 2..{done + 1} of the first instance ({m.shape}), FP64 CSR oracle, "
-                      f"{wall:.1f} s wall, {cpu:.1f} s CPU"}
+    out = {"value": m.size * done / wall, "unit": "grid-pts*iters/s", "cores": cores, "kind": "oracle",
+           "sample": f"iterations 2..{done + 1} of the first instance ({m.shape}), FP64 CSR oracle, "
+                     f"{wall:.1f} s wall, {cpu:.1f} s CPU"}
+    return out, err
 
 
 def main():
@@ -158,7 +207,7 @@ def main():
         insts, field, iters, desc = workload(args.workload, args)
     esz = 8 if field == "f64" else 4
     dt = torch.float64 if field == "f64" else torch.float32
-    opts = sip.make_opts(field, max_iter=iters, cg_max=10, cg_fixed=1)
+    opts = sip.make_opts(field, reduce=args.reduce, max_iter=iters, cg_max=10, cg_fixed=1)
     ms = [torch.tensor(m, dtype=dt, device="cuda") for m, _ in insts]
     xs = [torch.empty_like(m) for m in ms]
     arena = sum(sip.workspace_bytes(m.shape, s, opts) for m, s in insts)
@@ -239,8 +288,18 @@ def main():
         copy = {"bytes_moved": 2 * n * 4, "ms": round(t, 4), "GBs": round(2 * n * 4 / (t * 1e-3) / 1e9, 1)}
         del src, dst
     cpu = None
+    check = None
     if args.cpu_seconds > 0:
-        cpu = cpu_baseline(insts, iters, args.cpu_seconds)
+        sched, chk = None, None
+        kc = min(args.check_iters, iters)
+        if kc > 0:
+            xr, sched = device_reference(insts[0], field, args.reduce, kc)
+            chk = (kc, xr)
+        cpu, err = cpu_baseline(insts, iters, args.cpu_seconds, sched, chk)
+        if chk is not None:
+            check = {"iterations": kc, "rel_l2_x": err, "instance": "first",
+                     "oracle": "FP64, replaying the device (rho, gamma) schedule",
+                     "oracle_sensitivity": oracle_sensitivity(insts[0], kc, sched, field)}
     line = {
         "metric": "PARSDMM grid-pts*iters/s",
         "value": round(value, 1),
@@ -255,10 +314,11 @@ def main():
         "dtype": field,
         "data": "synthetic (seeded generators)",
         "config": {"workload": desc, "instances": len(insts), "grid_points": n_pts, "iterations": iters,
-                   "cg_steps": 10, "reductions": "f64", "tiles": list(tiles) if tiles else "default"},
+                   "cg_steps": 10, "reductions": args.reduce, "tiles": list(tiles) if tiles else "default"},
         "roofline": roofline,
         "kernels": {k: {"ms": round(v["ms"], 5), "GBs": round(v["GBs"], 1)} for k, v in kernels.items()},
         "cpu_baseline": cpu,
+        "oracle_error": check,
         "copy_reference": copy,
     }
     if args.workload == "batched":

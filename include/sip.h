@@ -98,7 +98,10 @@ typedef struct {
   double eps_evol;      /* default 1e-2 */
   double eps_feas;      /* default 1e-3 */
   double cg_rel;        /* CG stops when ||r|| < cg_rel ||r_0||; default 0.1 */
-  int32_t field;        /* sip_dtype of m, x and every field; reductions are always FP64 */
+  int32_t field;        /* sip_dtype of m, x and every field */
+  int32_t reduce;       /* sip_dtype of every reduction (CG inner products, residual and stopping
+                           norms, adapt dots, l1 bucket and prefix sums): SIP_F64 (default), or
+                           SIP_F32 with field SIP_F32 (the pure-FP32 precision ablation) */
   int32_t log_schedule; /* 1: record (rho, gamma) of every iteration (sip_batch_schedule) */
 } sip_opts;
 

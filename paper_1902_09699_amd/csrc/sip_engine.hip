@@ -15,12 +15,22 @@
 namespace sip {
 
 struct Tables;
+// The kernels are built twice: FP64 accumulation (r64) and FP32 (r32).
+namespace r64 {
 template <typename T> void launch_iteration(hipStream_t st, const Tables& t, const Opts& o);
 template <typename T> void launch_init(hipStream_t st, const InstDesc* D, int inst, int64_t N);
 void launch_zero(hipStream_t st, uint32_t* a, int64_t n);
 void launch_zero(hipStream_t st, double* a, int64_t n);
 template <typename T> void launch_phase(hipStream_t st, const Tables& t, const Opts& o, int phase);
 void launch_copy(hipStream_t st, void* dst, const void* src, int64_t n16);
+}  // namespace r64
+namespace r32 {
+template <typename T> void launch_iteration(hipStream_t st, const Tables& t, const Opts& o);
+template <typename T> void launch_phase(hipStream_t st, const Tables& t, const Opts& o, int phase);
+}  // namespace r32
+using r64::launch_init;
+using r64::launch_zero;
+using r64::launch_copy;
 
 namespace {
 
@@ -121,6 +131,7 @@ int32_t validate(const sip_grid* g, const sip_set* sets, int32_t nsets, const si
   if (g->ndim != 2 && g->ndim != 3) return SIP_EINVAL;
   if (nsets < 0 || nsets > SIP_MAX_SETS) return SIP_EINVAL;
   if (o->field != SIP_F32 && o->field != SIP_F64) return SIP_EINVAL;
+  if (o->reduce != SIP_F64 && !(o->reduce == SIP_F32 && o->field == SIP_F32)) return SIP_EINVAL;
   int64_t N = 1;
   for (int a = 0; a < g->ndim; ++a) {
     if (g->n[a] < 1 || !(g->h[a] > 0.0) || !std::isfinite(g->h[a])) return SIP_EINVAL;
@@ -404,8 +415,9 @@ int32_t get_graph(sip_batch* b, int iters, hipGraphExec_t& out) {
   if (it != b->graphs.end()) { out = it->second; return SIP_OK; }
   HIP_OK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
   for (int i = 0; i < iters; ++i) {
-    if (b->opts.field == SIP_F64) launch_iteration<double>(b->cap_stream, b->tab, b->kopts);
-    else launch_iteration<float>(b->cap_stream, b->tab, b->kopts);
+    if (b->opts.field == SIP_F64) r64::launch_iteration<double>(b->cap_stream, b->tab, b->kopts);
+    else if (b->opts.reduce == SIP_F32) r32::launch_iteration<float>(b->cap_stream, b->tab, b->kopts);
+    else r64::launch_iteration<float>(b->cap_stream, b->tab, b->kopts);
   }
   hipGraph_t g = nullptr;
   if (hipStreamEndCapture(b->cap_stream, &g) != hipSuccess || !g) return SIP_EHIP;
@@ -480,7 +492,7 @@ int32_t sip_opts_default(sip_opts* o) {
   std::memset(o, 0, sizeof(*o));
   o->max_iter = 200; o->cg_max = 10; o->cg_fixed = 0; o->adapt_every = 2; o->stop_every = 0; o->evol_hist = 5;
   o->rho0 = 1.0; o->gamma0 = 1.0; o->eps_corr = 0.3; o->rho_ratio_max = 100.0; o->gamma_max = 1.999;
-  o->eps_evol = 1e-2; o->eps_feas = 1e-3; o->cg_rel = 0.1; o->field = SIP_F32; o->log_schedule = 0;
+  o->eps_evol = 1e-2; o->eps_feas = 1e-3; o->cg_rel = 0.1; o->field = SIP_F32; o->reduce = SIP_F64; o->log_schedule = 0;
   return SIP_OK;
 }
 
@@ -820,13 +832,15 @@ int32_t sip_batch_time_kernel(sip_batch* b, int32_t kernel, int32_t reps, void* 
   HIP_OK(hipEventCreate(&e0));
   HIP_OK(hipEventCreate(&e1));
   for (int w = 0; w < 2; ++w) {  // warm the caches and the code object
-    if (b->opts.field == SIP_F64) launch_phase<double>(stream, b->tab, b->kopts, kernel);
-    else launch_phase<float>(stream, b->tab, b->kopts, kernel);
+    if (b->opts.field == SIP_F64) r64::launch_phase<double>(stream, b->tab, b->kopts, kernel);
+    else if (b->opts.reduce == SIP_F32) r32::launch_phase<float>(stream, b->tab, b->kopts, kernel);
+    else r64::launch_phase<float>(stream, b->tab, b->kopts, kernel);
   }
   HIP_OK(hipEventRecord(e0, stream));
   for (int i = 0; i < reps; ++i) {
-    if (b->opts.field == SIP_F64) launch_phase<double>(stream, b->tab, b->kopts, kernel);
-    else launch_phase<float>(stream, b->tab, b->kopts, kernel);
+    if (b->opts.field == SIP_F64) r64::launch_phase<double>(stream, b->tab, b->kopts, kernel);
+    else if (b->opts.reduce == SIP_F32) r32::launch_phase<float>(stream, b->tab, b->kopts, kernel);
+    else r64::launch_phase<float>(stream, b->tab, b->kopts, kernel);
   }
   HIP_OK(hipEventRecord(e1, stream));
   HIP_OK(hipEventSynchronize(e1));

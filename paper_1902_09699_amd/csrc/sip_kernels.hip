@@ -15,7 +15,19 @@
 
 #include "sip_internal.h"
 
+// Accumulator type of every reduction (dot products, norms, histogram and
+// prefix sums).  The library is built twice from this file: FP64
+// accumulation (namespace r64, the default) and FP32 accumulation (r32, the
+// precision ablation, selected by sip_opts.reduce).
+#ifndef SIP_ACC
+#define SIP_ACC double
+#define SIP_KNS r64
+#endif
+
 namespace sip {
+namespace SIP_KNS {
+
+using acc_t = SIP_ACC;
 
 // Threads per block of the set and threshold kernels: more registers per
 // thread and no partial reduction at start, so smaller blocks let several
@@ -30,7 +42,8 @@ __device__ __forceinline__ int xcd_item(int b, int G) {
   return x * q + (x < rem ? x : rem) + j;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
+template <typename A>
+__device__ __forceinline__ A wave_sum(A v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -42,8 +55,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <int NV, int NT = kBlock>
 constexpr int lds_sum() { return NV * (NT / 64 + 1); }
 
-template <int NV, int NT = kBlock>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
+template <int NV, int NT = kBlock, typename A>
+__device__ __forceinline__ void block_sum(A (&v)[NV], A* lds) {
   constexpr int NW = NT / 64;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
 #pragma unroll
@@ -55,7 +68,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
   }
   __syncthreads();
   if (threadIdx.x < NV) {
-    double t = 0.0;
+    A t = 0;
     for (int q = 0; q < NW; ++q) t += lds[threadIdx.x * NW + q];
     lds[NV * NW + threadIdx.x] = t;
   }
@@ -66,14 +79,14 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
 }
 
 // Sum of parts[i * stride + off .. + NV) over items i in [begin, end).
-template <int NV, int NT = kBlock>
+template <int NV, int NT = kBlock, typename A>
 __device__ __forceinline__ void reduce_range(const double* __restrict__ parts, int begin, int end, int stride,
-                                             int off, double (&out)[NV], double* lds) {
+                                             int off, A (&out)[NV], A* lds) {
 #pragma unroll
-  for (int j = 0; j < NV; ++j) out[j] = 0.0;
+  for (int j = 0; j < NV; ++j) out[j] = 0;
   for (int i = begin + (int)threadIdx.x; i < end; i += NT) {
 #pragma unroll
-    for (int j = 0; j < NV; ++j) out[j] += parts[(size_t)i * stride + off + j];
+    for (int j = 0; j < NV; ++j) out[j] += (A)parts[(size_t)i * stride + off + j];
   }
   block_sum<NV, NT>(out, lds);
 }
@@ -81,33 +94,27 @@ __device__ __forceinline__ void reduce_range(const double* __restrict__ parts, i
 // Sum of parts[begin .. end) computed by every wave on its own (lanes stride
 // the range, then the butterfly): no LDS, no barrier, and the same order, so
 // the same value, in every wave of every block.
-__device__ __forceinline__ double wave_reduce(const double* __restrict__ parts, int begin, int end) {
-  double t = 0.0;
-  for (int i = begin + (int)(threadIdx.x & 63); i < end; i += 64) t += parts[i];
+__device__ __forceinline__ acc_t wave_reduce(const double* __restrict__ parts, int begin, int end) {
+  acc_t t = 0;
+  for (int i = begin + (int)(threadIdx.x & 63); i < end; i += 64) t += (acc_t)parts[i];
   return wave_sum(t);
 }
 
 // Block total of one double, valid in thread 0 only (one barrier; lds must
 // not be in use by other threads).
-template <int NT>
-__device__ __forceinline__ double block_total(double v, double* lds) {
+template <int NT, typename A>
+__device__ __forceinline__ A block_total(A v, A* lds) {
   constexpr int NW = NT / 64;
   v = wave_sum(v);
   if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
   __syncthreads();
-  double t = 0.0;
+  A t = 0;
   if (threadIdx.x == 0) {
     for (int q = 0; q < NW; ++q) t += lds[q];
   }
   return t;
 }
 
-template <int NT>
-__device__ __forceinline__ double reduce_one(const double* __restrict__ parts, int begin, int end, double* lds) {
-  double a[1];
-  reduce_range<1, NT>(parts, begin, end, 1, 0, a, lds);
-  return a[0];
-}
 
 template <typename T> struct KeyT;
 template <> struct KeyT<float> {
@@ -600,7 +607,7 @@ __device__ __forceinline__ void group_valid(const GLane& L, const Geo& g, int ax
 // differences), p^T C p = c0 |p|^2 + sum_a c_a |D_a p|^2: only the forward
 // neighbours are read (half the windows of C p), and every term is a square.
 template <typename T, int NA, bool HY, bool AL>
-__device__ __forceinline__ double group_pCp_v(const Src<T, NA>& f, const GLane& L, int lane, const Geo& g,
+__device__ __forceinline__ acc_t group_pCp_v(const Src<T, NA>& f, const GLane& L, int lane, const Geo& g,
                                               const Offs& of, T (&c)[Grp<T>::W], const double (&cf)[4]) {
   constexpr int W = Grp<T>::W;
   const int N = g.N;
@@ -622,26 +629,26 @@ __device__ __forceinline__ double group_pCp_v(const Src<T, NA>& f, const GLane& 
   T yp[W], zp[W];
   if constexpr (HY) win_get<T, NA, AL>(f, of.yp, ypa, ypb, yp);
   win_get<T, NA, AL>(f, of.zp, zpa, zpb, zp);
-  double acc = 0.0;
+  acc_t acc = 0;
 #pragma unroll
   for (int e = 0; e < W; ++e) {
     int ize = L.iz, iye = L.iy, ixe = L.ix0 + e;
     if (L.straddle) g.coords(L.P0c + e, ize, iye, ixe);
-    const double ce = (double)c[e];
-    const double rgt = (double)(e < W - 1 ? c[e < W - 1 ? e + 1 : W - 1] : right);
-    double t = cf[0] * ce * ce;
-    if (ixe < g.nx - 1) t += cf[3] * (rgt - ce) * (rgt - ce);
+    const acc_t ce = (acc_t)c[e];
+    const acc_t rgt = (acc_t)(e < W - 1 ? c[e < W - 1 ? e + 1 : W - 1] : right);
+    acc_t t = (acc_t)cf[0] * ce * ce;
+    if (ixe < g.nx - 1) t += (acc_t)cf[3] * (rgt - ce) * (rgt - ce);
     if constexpr (HY) {
-      if (iye < g.ny - 1) t += cf[2] * ((double)yp[e] - ce) * ((double)yp[e] - ce);
+      if (iye < g.ny - 1) t += (acc_t)cf[2] * ((acc_t)yp[e] - ce) * ((acc_t)yp[e] - ce);
     }
-    if (ize < g.nz - 1) t += cf[1] * ((double)zp[e] - ce) * ((double)zp[e] - ce);
+    if (ize < g.nz - 1) t += (acc_t)cf[1] * ((acc_t)zp[e] - ce) * ((acc_t)zp[e] - ce);
     if (e < L.cnt) acc += t;
   }
   return acc;
 }
 
 template <typename T, int NA, int NT>
-__device__ __forceinline__ double cg_dir_item(const InstDesc& d, const PtItem& it, const Geo& g, const Src<T, NA>& f,
+__device__ __forceinline__ acc_t cg_dir_item(const InstDesc& d, const PtItem& it, const Geo& g, const Src<T, NA>& f,
                                               T* __restrict__ pout, const double (&cf)[4]) {
   constexpr int W = Grp<T>::W;
   const int lane = threadIdx.x & 63;
@@ -650,18 +657,18 @@ __device__ __forceinline__ double cg_dir_item(const InstDesc& d, const PtItem& i
   const bool al = rows_aligned<T>(g);
   const bool hy = g.ny > 1;
   const Offs of = offs_of<T>(g);
-  auto fs = [&](int Q) -> double {
-    if constexpr (NA == 1) return (double)f.a[0][Q];
-    else return (double)(f.a[0][Q] + f.beta * f.a[1][Q]);
+  auto fs = [&](int Q) -> acc_t {
+    if constexpr (NA == 1) return (acc_t)f.a[0][Q];
+    else return (acc_t)(f.a[0][Q] + f.beta * f.a[1][Q]);
   };
-  double acc = 0.0;
+  acc_t acc = 0;
   for (int base = it.begin; base < end; base += NT * W) {
     const int P0 = base + (int)threadIdx.x * W;
     bool vec = false;
     if (grouped) {
       const GLane L = glane<T>(P0, it.begin, end, g);
       T c[W];
-      double t;
+      acc_t t;
       if (hy) t = al ? group_pCp_v<T, NA, true, true>(f, L, lane, g, of, c, cf)
                      : group_pCp_v<T, NA, true, false>(f, L, lane, g, of, c, cf);
       else t = al ? group_pCp_v<T, NA, false, true>(f, L, lane, g, of, c, cf)
@@ -678,11 +685,11 @@ __device__ __forceinline__ double cg_dir_item(const InstDesc& d, const PtItem& i
         if (P >= end) break;
         int iz, iy, ix;
         g.coords(P, iz, iy, ix);
-        const double pc = fs(P);
-        double t = cf[0] * pc * pc;
-        if (ix < g.nx - 1) { const double dd = fs(P + 1) - pc; t += cf[3] * dd * dd; }
-        if (iy < g.ny - 1) { const double dd = fs(P + g.sy) - pc; t += cf[2] * dd * dd; }
-        if (iz < g.nz - 1) { const double dd = fs(P + g.sz) - pc; t += cf[1] * dd * dd; }
+        const acc_t pc = fs(P);
+        acc_t t = (acc_t)cf[0] * pc * pc;
+        if (ix < g.nx - 1) { const acc_t dd = fs(P + 1) - pc; t += (acc_t)cf[3] * dd * dd; }
+        if (iy < g.ny - 1) { const acc_t dd = fs(P + g.sy) - pc; t += (acc_t)cf[2] * dd * dd; }
+        if (iz < g.nz - 1) { const acc_t dd = fs(P + g.sz) - pc; t += (acc_t)cf[1] * dd * dd; }
         pout[P] = (T)pc;
         acc += t;
       }
@@ -694,7 +701,7 @@ __device__ __forceinline__ double cg_dir_item(const InstDesc& d, const PtItem& i
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_cg_dir(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const PtItem* __restrict__ items, int j,
                                                 const double* rr_part, double* pq_part, Opts o) {
-  __shared__ double lds[lds_sum<1, NT>()];
+  __shared__ acc_t lds[lds_sum<1, NT>()];
   if ((int)blockIdx.x >= cnt->npt) return;
   const int iti = xcd_item(blockIdx.x, cnt->npt);
   const PtItem it = items[iti];
@@ -723,7 +730,7 @@ __global__ __launch_bounds__(NT) void k_cg_dir(const InstDesc* __restrict__ D, c
   const T* pin = (const T*)d.p[(j + 1) & 1];
   T* pout = (T*)d.p[j & 1];
   const double cf[4] = {S[S_C0], S[S_CAX + 0], S[S_CAX + 1], S[S_CAX + 2]};
-  double acc;
+  acc_t acc;
   if (j == 0) {
     const Src<T, 1> f{{r}, (T)0};
     acc = cg_dir_item<T, 1, NT>(d, it, g, f, pout, cf);
@@ -741,7 +748,7 @@ template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_cg_upd(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const PtItem* __restrict__ items, int j,
                                                 const double* pq_part, double* rr_part) {
   constexpr int W = Grp<T>::W;
-  __shared__ double lds[lds_sum<1, NT>()];
+  __shared__ acc_t lds[lds_sum<1, NT>()];
   if ((int)blockIdx.x >= cnt->npt) return;
   const int iti = xcd_item(blockIdx.x, cnt->npt);
   const PtItem it = items[iti];
@@ -767,7 +774,7 @@ __global__ __launch_bounds__(NT) void k_cg_upd(const InstDesc* __restrict__ D, c
   const int lane = threadIdx.x & 63;
   const bool grouped = item_grouped(d);
   const Offs of = offs_of<T>(g);
-  double acc[1] = {0.0};
+  acc_t acc[1] = {0};
   const int end = it.begin + it.len;
   for (int base = it.begin; base < end; base += NT * W) {
     const int P0 = base + (int)threadIdx.x * W;
@@ -784,7 +791,7 @@ __global__ __launch_bounds__(NT) void k_cg_upd(const InstDesc* __restrict__ D, c
         for (int e = 0; e < W; ++e) {
           xv[e] = xv[e] + al * c[e];
           rv[e] = rv[e] - al * q[e];
-          if (e < L.cnt) acc[0] += (double)rv[e] * (double)rv[e];
+          if (e < L.cnt) acc[0] += (acc_t)rv[e] * (acc_t)rv[e];
         }
         st16p<T>(x, P0, L.cnt, xv);
         st16<T>(r + P0, rv);
@@ -799,11 +806,11 @@ __global__ __launch_bounds__(NT) void k_cg_upd(const InstDesc* __restrict__ D, c
         x[P] = x[P] + al * pc;
         const T rv = r[P] - al * qq;
         r[P] = rv;
-        acc[0] += (double)rv * (double)rv;
+        acc[0] += (acc_t)rv * (acc_t)rv;
       }
     }
   }
-  const double tot = block_total<NT>(acc[0], lds);
+  const acc_t tot = block_total<NT>(acc[0], lds);
   if (threadIdx.x == 0) rr_part[iti] = tot;
 }
 
@@ -815,7 +822,7 @@ __global__ __launch_bounds__(NT) void k_cg_upd(const InstDesc* __restrict__ D, c
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_rhs(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const PtItem* __restrict__ items, double* rr_part) {
   constexpr int W = Grp<T>::W;
-  __shared__ double lds[lds_sum<1, NT>()];
+  __shared__ acc_t lds[lds_sum<1, NT>()];
   if ((int)blockIdx.x >= cnt->npt) return;
   const int iti = xcd_item(blockIdx.x, cnt->npt);
   const PtItem it = items[iti];
@@ -836,7 +843,7 @@ __global__ __launch_bounds__(NT) void k_rhs(const InstDesc* __restrict__ D, cons
   const Offs of = offs_of<T>(g);
   const bool al = rows_aligned<T>(g);
   const int N = g.N;
-  double acc[1] = {0.0};
+  acc_t acc[1] = {0};
   const int end = it.begin + it.len;
   for (int base = it.begin; base < end; base += NT * W) {
     const int P0 = base + (int)threadIdx.x * W;
@@ -908,7 +915,7 @@ __global__ __launch_bounds__(NT) void k_rhs(const InstDesc* __restrict__ D, cons
 #pragma unroll
         for (int e = 0; e < W; ++e) {
           rv[e] = b[e] - cxv[e];
-          if (e < L.cnt) acc[0] += (double)rv[e] * (double)rv[e];
+          if (e < L.cnt) acc[0] += (acc_t)rv[e] * (acc_t)rv[e];
         }
         st16<T>(r + P0, rv);
       }
@@ -943,11 +950,11 @@ __global__ __launch_bounds__(NT) void k_rhs(const InstDesc* __restrict__ D, cons
         const T xv = x[P];
         const T rv = bb - point_apply_C<T>(P, g, fs, xv, c0, cz, cy, cx);
         r[P] = rv;
-        acc[0] += (double)rv * (double)rv;
+        acc[0] += (acc_t)rv * (acc_t)rv;
       }
     }
   }
-  const double tot = block_total<NT>(acc[0], lds);
+  const acc_t tot = block_total<NT>(acc[0], lds);
   if (threadIdx.x == 0) rr_part[iti] = tot;
 }
 
@@ -978,7 +985,7 @@ __device__ __forceinline__ void proj_point(const ProjUnit<T>& U, T sv, T yo, T v
 template <typename T>
 __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const PtItem* __restrict__ items, Opts o, double* parts) {
   constexpr int W = Grp<T>::W;
-  __shared__ double lds[lds_sum<8, kSB>()];
+  __shared__ acc_t lds[lds_sum<8, kSB>()];
   if ((int)blockIdx.x >= cnt->nsp) return;
   const int iti = xcd_item(blockIdx.x, cnt->nsp);
   const PtItem it = items[iti];
@@ -1013,7 +1020,7 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
     U.inv1p = (T)(1.0 / (1.0 + rho_d));
     U.ident = ident;
     const int ncomp = ident ? 1 : s->ncomp;
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    acc_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int c = 0; c < ncomp; ++c) {
       const int axis = ident ? -1 : s->axis[c];
       const size_t off = (size_t)c * g.cs;
@@ -1058,10 +1065,10 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
 #pragma unroll
               for (int e = 0; e < W; ++e) {
                 if (!ok[e]) continue;
-                const double dh = (double)sv[e] - (double)s0[e];
-                const double dvh = (double)vh[e] - (double)a0[e];
-                const double dg = -((double)yn[e] - (double)a1[e]);
-                const double dv = (double)vn[e] - (double)a2[e];
+                const acc_t dh = (acc_t)sv[e] - (acc_t)s0[e];
+                const acc_t dvh = (acc_t)vh[e] - (acc_t)a0[e];
+                const acc_t dg = -((acc_t)yn[e] - (acc_t)a1[e]);
+                const acc_t dv = (acc_t)vn[e] - (acc_t)a2[e];
                 acc[0] += dh * dvh; acc[1] += dh * dh; acc[2] += dvh * dvh;
                 acc[3] += dg * dv; acc[4] += dg * dg; acc[5] += dv * dv;
               }
@@ -1075,9 +1082,9 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
             for (int e = 0; e < W; ++e) {
               if (!ok[e]) continue;
               const T pc = sv[e] < U.lo ? U.lo : (sv[e] > U.hi ? U.hi : sv[e]);
-              const double ee = (double)sv[e] - (double)pc;
+              const acc_t ee = (acc_t)sv[e] - (acc_t)pc;
               acc[6] += ee * ee;
-              acc[7] += (double)sv[e] * (double)sv[e];
+              acc[7] += (acc_t)sv[e] * (acc_t)sv[e];
             }
           }
         } else {
@@ -1098,10 +1105,10 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
               if (have) {
                 T sq;
                 comp_value<T>(xr, P, axis, iz, iy, ix, g, d, sq);
-                const double dh = (double)sp - (double)sq;
-                const double dvh = (double)vh - (double)vh0[P];
-                const double dg = -((double)yn - (double)y0[P]);
-                const double dv = (double)vn - (double)v0[P];
+                const acc_t dh = (acc_t)sp - (acc_t)sq;
+                const acc_t dvh = (acc_t)vh - (acc_t)vh0[P];
+                const acc_t dg = -((acc_t)yn - (acc_t)y0[P]);
+                const acc_t dv = (acc_t)vn - (acc_t)v0[P];
                 acc[0] += dh * dvh; acc[1] += dh * dh; acc[2] += dvh * dvh;
                 acc[3] += dg * dv; acc[4] += dg * dg; acc[5] += dv * dv;
               }
@@ -1111,9 +1118,9 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
             }
             if (check && !ident) {
               const T pc = sp < U.lo ? U.lo : (sp > U.hi ? U.hi : sp);
-              const double ee = (double)sp - (double)pc;
+              const acc_t ee = (acc_t)sp - (acc_t)pc;
               acc[6] += ee * ee;
-              acc[7] += (double)sp * (double)sp;
+              acc[7] += (acc_t)sp * (acc_t)sp;
             }
           }
         }
@@ -1133,8 +1140,8 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
     T* __restrict__ xw = (T*)d.xs[call & 1];
     T* __restrict__ ring = (T*)d.ring;
     const int H = o.evol_hist;
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    double accx[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    acc_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    acc_t accx[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (grouped) {
       // 16-byte groups (the snapshot and history arrays are padded)
       for (int P0 = it.begin + (int)threadIdx.x * W; P0 < end; P0 += kSB * W) {
@@ -1147,16 +1154,16 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
           if (check) {
 #pragma unroll
             for (int e = 0; e < W; ++e)
-              if (e < cnt) accx[0] += (double)xv[e] * (double)xv[e];
+              if (e < cnt) accx[0] += (acc_t)xv[e] * (acc_t)xv[e];
 #pragma unroll
             for (int jj = 1; jj < kMaxHist; ++jj) {
               if (jj > H) break;
               T rv[W];
               ld16<T>(ring + (size_t)((k - jj) % (H + 1)) * g.cs + P0, rv);
-              double t = 0.0;
+              acc_t t = 0;
 #pragma unroll
               for (int e = 0; e < W; ++e) {
-                const double df = (double)xv[e] - (double)rv[e];
+                const acc_t df = (acc_t)xv[e] - (acc_t)rv[e];
                 if (e < cnt) t += df * df;
               }
               if (jj <= 7) acc[jj] += t; else accx[jj - 7] += t;
@@ -1171,11 +1178,11 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
         if (ring) {
           ring[(size_t)(k % (H + 1)) * g.cs + P] = xv;
           if (check) {
-            accx[0] += (double)xv * (double)xv;
+            accx[0] += (acc_t)xv * (acc_t)xv;
 #pragma unroll
             for (int jj = 1; jj < kMaxHist; ++jj) {
               if (jj > H) break;
-              const double e = (double)xv - (double)ring[(size_t)((k - jj) % (H + 1)) * g.cs + P];
+              const acc_t e = (acc_t)xv - (acc_t)ring[(size_t)((k - jj) % (H + 1)) * g.cs + P];
               if (jj <= 7) acc[jj] += e * e; else accx[jj - 7] += e * e;
             }
           }
@@ -1205,8 +1212,8 @@ template <typename T>
 __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const ThrItem* __restrict__ items, Opts o, double* parts) {
   using KT = KeyT<T>;
   __shared__ uint32_t hc[kNB];
-  __shared__ double hs[kNB];
-  __shared__ double lds[lds_sum<8, kSB>()];
+  __shared__ acc_t hs[kNB];
+  __shared__ acc_t lds[lds_sum<8, kSB>()];
   if ((int)blockIdx.x >= cnt->nthr) return;
   const int iti = xcd_item(blockIdx.x, cnt->nthr);
   const ThrItem it = items[iti];
@@ -1221,7 +1228,7 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, c
   const int call = adapt ? adapt_call(k, o) : 0;
   const SetDesc& s = d.sets[it.set];
   const bool l1 = s.kind == SIP_SET_L1;
-  for (int b = threadIdx.x; b < kNB; b += kSB) { hc[b] = 0; hs[b] = 0.0; }
+  for (int b = threadIdx.x; b < kNB; b += kSB) { hc[b] = 0; hs[b] = 0; }
   __syncthreads();
   const Geo g(d);
   const bool grouped = item_grouped(d);
@@ -1236,20 +1243,20 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, c
   constexpr int W = Grp<T>::W;
   const int lane = threadIdx.x & 63;
   const bool dots = it.src == 0 && adapt && have;
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  acc_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int end = it.begin + it.len;
   auto bin = [&](T val) {
     const typename KT::K key = KT::key(val);
     const int bkt = (int)(key >> sh0);
     atomicAdd(&hc[bkt], 1u);
-    if (l1) atomicAdd(&hs[bkt], KT::value(key));
+    if (l1) atomicAdd(&hs[bkt], (acc_t)KT::value(key));
   };
   // a group's values, runs of equal buckets merged into one update (the
   // bucket sums of float keys are exact, so the merge changes no result)
   auto bin_group = [&](const T (&v)[W], const bool (&ok)[W]) {
     int cur = -1;
     uint32_t n = 0;
-    double sum = 0.0;
+    acc_t sum = 0;
 #pragma unroll
     for (int e = 0; e < W; ++e) {
       if (!ok[e]) continue;
@@ -1262,10 +1269,10 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, c
         }
         cur = bkt;
         n = 0;
-        sum = 0.0;
+        sum = 0;
       }
       ++n;
-      sum += KT::value(key);
+      sum += (acc_t)KT::value(key);
     }
     if (n) {
       atomicAdd(&hc[cur], n);
@@ -1307,8 +1314,8 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, c
 #pragma unroll
               for (int e = 0; e < W; ++e) {
                 if (!ok[e]) continue;
-                const double dh = (double)sv[e] - (double)s0[e];
-                const double dvh = (double)vh[e] - (double)a0[e];
+                const acc_t dh = (acc_t)sv[e] - (acc_t)s0[e];
+                const acc_t dvh = (acc_t)vh[e] - (acc_t)a0[e];
                 acc[0] += dh * dvh; acc[1] += dh * dh; acc[2] += dvh * dvh;
               }
             }
@@ -1318,7 +1325,7 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, c
         } else {
 #pragma unroll
           for (int e = 0; e < W; ++e)
-            if (ok[e]) acc[7] += (double)sv[e] * (double)sv[e];
+            if (ok[e]) acc[7] += (acc_t)sv[e] * (acc_t)sv[e];
           bin_group(sv, ok);
         }
         continue;
@@ -1340,15 +1347,15 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, c
             if (have) {
               T sq;
               comp_value<T>(xr, P, axis, iz, iy, ix, g, d, sq);
-              const double dh = (double)sp - (double)sq;
-              const double dvh = (double)vh - (double)vh0[P];
+              const acc_t dh = (acc_t)sp - (acc_t)sq;
+              const acc_t dvh = (acc_t)vh - (acc_t)vh0[P];
               acc[0] += dh * dvh; acc[1] += dh * dh; acc[2] += dvh * dvh;
             }
             vh0[P] = vh;
           }
         } else {
           val = sp;
-          acc[7] += (double)sp * (double)sp;
+          acc[7] += (acc_t)sp * (acc_t)sp;
         }
         bin(val);
       }
@@ -1356,7 +1363,7 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, c
   }
   __syncthreads();
   uint32_t* gc = s.hcnt[it.src];
-  double* gs = s.hsum[it.src];
+  acc_t* gs = (acc_t*)s.hsum[it.src];
   for (int b = threadIdx.x; b < kNB; b += kSB) {
     const uint32_t cnt = hc[b];
     if (cnt) {
@@ -1380,30 +1387,30 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, c
 // prefix gets digit b, everything in buckets above b moves to c_above/s_above.
 // Returns the count of bucket b.
 template <typename T>
-__device__ unsigned long long select_digit(SelState& st, const uint32_t* hc, const double* hs, int nb, int dig,
-                                          const SetDesc& s, bool l1, unsigned long long* lc, double* ls,
+__device__ unsigned long long select_digit(SelState& st, const uint32_t* hc, const acc_t* hs, int nb, int dig,
+                                          const SetDesc& s, bool l1, unsigned long long* lc, acc_t* ls,
                                           int* lbest) {
   using KT = KeyT<T>;
   const int sh = digit_shift<T>(dig);
   const int per = nb / kBlock;  // nb is 1024 or 2048
   const int t = threadIdx.x;
   unsigned long long mc = 0;
-  double ms = 0.0;
+  acc_t ms = 0;
   for (int i = 0; i < per; ++i) { mc += hc[t * per + i]; if (l1) ms += hs[t * per + i]; }
   // totals of the threads above this one (higher buckets), in a fixed order:
   // an inclusive suffix scan inside each wave, then the wave totals
   const int lane = t & 63, wv = t >> 6;
   unsigned long long ic = mc;
-  double is = ms;
+  acc_t is = ms;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
     const unsigned long long oc = __shfl_down(ic, off, 64);
-    const double os = __shfl_down(is, off, 64);
+    const acc_t os = __shfl_down(is, off, 64);
     if (lane + off < 64) { ic += oc; is += os; }
   }
   unsigned long long above_c = __shfl_down(ic, 1, 64);
-  double above_s = __shfl_down(is, 1, 64);
-  if (lane == 63) { above_c = 0; above_s = 0.0; }
+  acc_t above_s = __shfl_down(is, 1, 64);
+  if (lane == 63) { above_c = 0; above_s = 0; }
   if (lane == 0) { lc[wv] = ic; ls[wv] = is; }
   if (t == 0) *lbest = -1;
   __syncthreads();
@@ -1411,16 +1418,16 @@ __device__ unsigned long long select_digit(SelState& st, const uint32_t* hc, con
   __syncthreads();
   // walk own buckets from the top
   unsigned long long rc = st.c_above + above_c;
-  double rs = st.s_above + above_s;
+  acc_t rs = (acc_t)st.s_above + above_s;
   int best = -1;
   for (int i = per - 1; i >= 0; --i) {
     const int b = t * per + i;
     const unsigned long long cb = rc + hc[b];
-    const double sb = rs + (l1 ? hs[b] : 0.0);
+    const acc_t sb = rs + (l1 ? hs[b] : (acc_t)0);
     bool ok;
     if (l1) {
-      const double L = KT::value((typename KT::K)(st.prefix | ((unsigned long long)b << sh)));
-      ok = (sb - (double)cb * L) >= s.tau;
+      const acc_t L = (acc_t)KT::value((typename KT::K)(st.prefix | ((unsigned long long)b << sh)));
+      ok = (sb - (acc_t)cb * L) >= (acc_t)s.tau;
     } else {
       ok = cb >= (unsigned long long)s.k;
     }
@@ -1436,7 +1443,7 @@ __device__ unsigned long long select_digit(SelState& st, const uint32_t* hc, con
   unsigned long long bc = 0;
   if (b >= 0 && t == b / per) {
     unsigned long long cc = st.c_above + above_c;
-    double ss = st.s_above + above_s;
+    acc_t ss = (acc_t)st.s_above + above_s;
     for (int i = per - 1; i > b - t * per; --i) { cc += hc[t * per + i]; if (l1) ss += hs[t * per + i]; }
     lc[0] = cc;
     ls[0] = ss;
@@ -1479,11 +1486,11 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const SelItem* __restrict__ items, Opts o) {
   using KT = KeyT<T>;
   __shared__ uint32_t hc[kNB];
-  __shared__ double hs[kNB];
+  __shared__ acc_t hs[kNB];
   __shared__ unsigned long long lc[kBlock];
-  __shared__ double ls[kBlock];
+  __shared__ acc_t ls[kBlock];
   __shared__ int lbest;
-  __shared__ double lds[lds_sum<2>()];
+  __shared__ acc_t lds[lds_sum<2>()];
   __shared__ SelState st;
   if ((int)blockIdx.x >= cnt->nsel) return;
   const SelItem si = items[blockIdx.x];
@@ -1495,15 +1502,15 @@ __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D,
   const SetDesc& s = d.sets[si.set];
   const bool l1 = s.kind == SIP_SET_L1;
   uint32_t* gc = s.hcnt[si.src];
-  double* gs = s.hsum[si.src];
-  double tot[2] = {0.0, 0.0};
+  acc_t* gs = (acc_t*)s.hsum[si.src];
+  acc_t tot[2] = {0, 0};
   for (int b = threadIdx.x; b < kNB; b += kBlock) {
     hc[b] = gc[b];
-    hs[b] = l1 ? gs[b] : 0.0;
-    tot[0] += (double)hc[b];
+    hs[b] = l1 ? gs[b] : (acc_t)0;
+    tot[0] += (acc_t)hc[b];
     tot[1] += hs[b];
     gc[b] = 0;
-    if (l1) gs[b] = 0.0;
+    if (l1) gs[b] = 0;
   }
   block_sum<2>(tot, lds);
   if (threadIdx.x == 0) {
@@ -1515,10 +1522,10 @@ __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D,
     if (nonfinite) st.err = SIP_ENUMERIC;
     if (l1) {
       if (!(s.tau > 0.0)) st.mode = SEL_ZERO;
-      else if (tot[1] <= s.tau) st.mode = SEL_INSIDE;
+      else if (tot[1] <= (acc_t)s.tau) st.mode = SEL_INSIDE;
       else st.mode = SEL_PROJECT;
     } else {
-      st.mode = ((double)s.k >= tot[0]) ? SEL_ALL : SEL_PROJECT;
+      st.mode = ((acc_t)s.k >= tot[0]) ? SEL_ALL : SEL_PROJECT;
     }
   }
   __syncthreads();
@@ -1552,7 +1559,7 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
   using KT = KeyT<T>;
   using K = typename KT::K;
   __shared__ uint32_t hc[kNB];
-  __shared__ double hs[kNB];
+  __shared__ acc_t hs[kNB];
   __shared__ uint32_t wcnt[kSW];
   __shared__ unsigned long long bbase;
   if ((int)blockIdx.x >= cnt->nthr) return;
@@ -1570,7 +1577,7 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
   const bool compact = pass_compacts<T>(st, pass);
   const bool l1 = s.kind == SIP_SET_L1;
   const int nb = 1 << KT::width(dig);
-  for (int b = threadIdx.x; b < nb; b += kSB) { hc[b] = 0; hs[b] = 0.0; }
+  for (int b = threadIdx.x; b < nb; b += kSB) { hc[b] = 0; hs[b] = 0; }
   __syncthreads();
   const int shp = digit_shift<T>(dig - 1), sh = digit_shift<T>(dig);
   const K want = (K)(st.prefix >> shp);
@@ -1627,7 +1634,7 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
       int nhit = 0;
       int cur = -1;
       uint32_t run = 0;
-      double rsum = 0.0;
+      acc_t rsum = 0;
 #pragma unroll
       for (int e = 0; e < W; ++e) {
         key[e] = KT::key(val[e]);
@@ -1643,10 +1650,10 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
             }
             cur = bkt;
             run = 0;
-            rsum = 0.0;
+            rsum = 0;
           }
           ++run;
-          rsum += KT::value(key[e]);
+          rsum += (acc_t)KT::value(key[e]);
         }
       }
       if (run) {
@@ -1684,7 +1691,7 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
   }
   __syncthreads();
   uint32_t* gc = s.hcnt[it.src];
-  double* gs = s.hsum[it.src];
+  acc_t* gs = (acc_t*)s.hsum[it.src];
   for (int b = threadIdx.x; b < nb; b += kSB) {
     if (hc[b]) {
       atomicAdd(&gc[b], hc[b]);
@@ -1704,9 +1711,9 @@ __global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict_
   using KT = KeyT<T>;
   using K = typename KT::K;
   __shared__ uint32_t hc[kNB];
-  __shared__ double hs[kNB];
+  __shared__ acc_t hs[kNB];
   __shared__ unsigned long long lc[kBlock];
-  __shared__ double ls[kBlock];
+  __shared__ acc_t ls[kBlock];
   __shared__ int lbest;
   __shared__ SelState st;
   if ((int)blockIdx.x >= cnt->nsel) return;
@@ -1723,14 +1730,14 @@ __global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict_
   const bool l1 = s.kind == SIP_SET_L1;
   const bool compacted = pass_compacts<T>(st, pass);
   uint32_t* gc = s.hcnt[si.src];
-  double* gs = s.hsum[si.src];
+  acc_t* gs = (acc_t*)s.hsum[si.src];
   int dig = st.digit;
   int nb = 1 << KT::width(dig);
   for (int b = threadIdx.x; b < nb; b += kBlock) {
     hc[b] = gc[b];
-    hs[b] = l1 ? gs[b] : 0.0;
+    hs[b] = l1 ? gs[b] : (acc_t)0;
     gc[b] = 0;
-    if (l1) gs[b] = 0.0;
+    if (l1) gs[b] = 0;
   }
   __syncthreads();
   unsigned long long last = select_digit<T>(st, hc, hs, nb, dig, s, l1, lc, ls, &lbest);
@@ -1743,14 +1750,14 @@ __global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict_
       nb = 1 << KT::width(dig);
       const int shp = digit_shift<T>(dig - 1), sh = digit_shift<T>(dig);
       const K want = (K)(st.prefix >> shp);
-      for (int b = threadIdx.x; b < nb; b += kBlock) { hc[b] = 0; hs[b] = 0.0; }
+      for (int b = threadIdx.x; b < nb; b += kBlock) { hc[b] = 0; hs[b] = 0; }
       __syncthreads();
       for (unsigned long long i = threadIdx.x; i < ncand; i += kBlock) {
         const K key = cand[i];
         if ((K)(key >> shp) == want) {
           const int bkt = (int)((key >> sh) & (K)(nb - 1));
           atomicAdd(&hc[bkt], 1u);
-          if (l1) atomicAdd(&hs[bkt], KT::value(key));
+          if (l1) atomicAdd(&hs[bkt], (acc_t)KT::value(key));
         }
       }
       __syncthreads();
@@ -1836,7 +1843,7 @@ __global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ 
                                                       const uint32_t* tie_part) {
   using KT = KeyT<T>;
   using K = typename KT::K;
-  __shared__ double lds[lds_sum<8, kSB>()];
+  __shared__ acc_t lds[lds_sum<8, kSB>()];
   __shared__ uint32_t wsum[kSW];
   __shared__ unsigned long long tie_base[3];
   if ((int)blockIdx.x >= cnt->nthr) return;
@@ -1879,7 +1886,7 @@ __global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ 
     }
     __syncthreads();
   }
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  acc_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int end = it.begin + it.len;
   for (int c = 0; c < s.ncomp; ++c) {
     const int axis = s.axis[c];
@@ -1907,13 +1914,13 @@ __global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ 
 #pragma unroll
             for (int e = 0; e < W; ++e) {
               if (!ok[e]) continue;
-              const double a = fabs((double)sv[e]);
-              double e2 = 0.0;
+              const acc_t a = (acc_t)fabs((double)sv[e]);
+              acc_t e2 = 0;
               if (l1) {
-                if (mode == SEL_PROJECT) { const double mn = a < st.theta ? a : st.theta; e2 = mn * mn; }
+                if (mode == SEL_PROJECT) { const acc_t th = (acc_t)st.theta; const acc_t mn = a < th ? a : th; e2 = mn * mn; }
                 else if (mode == SEL_ZERO) e2 = a * a;
               } else if (mode == SEL_PROJECT) {
-                e2 = KT::key(sv[e]) < tkey ? a * a : 0.0;
+                e2 = KT::key(sv[e]) < tkey ? a * a : (acc_t)0;
               }
               acc[6] += e2;
             }
@@ -1948,8 +1955,8 @@ __global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ 
 #pragma unroll
               for (int e = 0; e < W; ++e) {
                 if (!ok[e]) continue;
-                const double dg = -((double)yn[e] - (double)a0[e]);
-                const double dv = (double)vn[e] - (double)a1[e];
+                const acc_t dg = -((acc_t)yn[e] - (acc_t)a0[e]);
+                const acc_t dv = (acc_t)vn[e] - (acc_t)a1[e];
                 acc[3] += dg * dv; acc[4] += dg * dg; acc[5] += dv * dv;
               }
             }
@@ -1966,13 +1973,13 @@ __global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ 
           T sp = 0;
           if (it.src == 1) {
             if (!comp_value<T>(x, P, axis, iz, iy, ix, g, d, sp)) continue;
-            const double a = fabs((double)sp);
-            double e2 = 0.0;
+            const acc_t a = (acc_t)fabs((double)sp);
+            acc_t e2 = 0;
             if (l1) {
-              if (mode == SEL_PROJECT) { const double mn = a < st.theta ? a : st.theta; e2 = mn * mn; }
+              if (mode == SEL_PROJECT) { const acc_t th = (acc_t)st.theta; const acc_t mn = a < th ? a : th; e2 = mn * mn; }
               else if (mode == SEL_ZERO) e2 = a * a;
             } else if (mode == SEL_PROJECT) {
-              e2 = KT::key(sp) < tkey ? a * a : 0.0;
+              e2 = KT::key(sp) < tkey ? a * a : (acc_t)0;
             }
             acc[6] += e2;
             continue;
@@ -1994,8 +2001,8 @@ __global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ 
           v[P] = vv;
           if (adapt) {
             if (have) {
-              const double dg = -((double)r - (double)y0[P]);
-              const double dv = (double)vv - (double)v0[P];
+              const acc_t dg = -((acc_t)r - (acc_t)y0[P]);
+              const acc_t dv = (acc_t)vv - (acc_t)v0[P];
               acc[3] += dg * dv; acc[4] += dg * dg; acc[5] += dv * dv;
             }
             y0[P] = r;
@@ -2017,17 +2024,17 @@ __global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ 
       }
       if (it.src == 1) {
         if (valid) {
-          double e2;
-          const double a = fabs((double)sv);
+          acc_t e2;
+          const acc_t a = (acc_t)fabs((double)sv);
           if (l1) {
-            if (mode == SEL_PROJECT) { const double mn = a < st.theta ? a : st.theta; e2 = mn * mn; }
+            if (mode == SEL_PROJECT) { const acc_t th = (acc_t)st.theta; const acc_t mn = a < th ? a : th; e2 = mn * mn; }
             else if (mode == SEL_ZERO) e2 = a * a;
-            else e2 = 0.0;
+            else e2 = 0;
           } else {
             if (mode == SEL_PROJECT) {
               const K key = KT::key(sv);
-              e2 = key < tkey ? a * a : 0.0;
-            } else e2 = 0.0;
+              e2 = key < tkey ? a * a : (acc_t)0;
+            } else e2 = 0;
           }
           acc[6] += e2;
         }
@@ -2068,8 +2075,8 @@ __global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ 
       v[P] = vn;
       if (adapt) {
         if (have) {
-          const double dg = -((double)yn - (double)y0[P]);
-          const double dv = (double)vn - (double)v0[P];
+          const acc_t dg = -((acc_t)yn - (acc_t)y0[P]);
+          const acc_t dv = (acc_t)vn - (acc_t)v0[P];
           acc[3] += dg * dv; acc[4] += dg * dg; acc[5] += dv * dv;
         }
         y0[P] = yn;
@@ -2104,9 +2111,9 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const int32_t* __restrict__ insts, Opts o,
                                                    const double* proj_parts, const double* thrw_parts,
                                                    const double* thra_parts) {
-  __shared__ double lds[lds_sum<8>()];
-  __shared__ double dots[kMaxUnits][8];
-  __shared__ double evol[16];
+  __shared__ acc_t lds[lds_sum<8>()];
+  __shared__ acc_t dots[kMaxUnits][8];
+  __shared__ acc_t evol[16];
   if ((int)blockIdx.x >= cnt->ninst) return;
   const InstDesc& d = D[insts[blockIdx.x]];
   double* S = d.scal;
@@ -2123,16 +2130,16 @@ __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* __restrict__ 
   if (adapt || check) {
     for (int u = 0; u <= p; ++u) {
       const bool thr = u < p && d.sets[u].thr >= 0;
-      double v[8];
+      acc_t v[8];
       if (!thr) {
         reduce_range<8>(proj_parts, d.sp_begin, d.sp_end, kProjParts, u * kUnitParts, v, lds);
       } else {
         const SetDesc& s = d.sets[u];
-        double a[8], b[8];
+        acc_t a[8], b[8];
         reduce_range<8>(thrw_parts, s.item_begin[0], s.item_end[0], kThrParts, 0, a, lds);
         reduce_range<8>(thra_parts, s.item_begin[0], s.item_end[0], kThrParts, 0, b, lds);
         for (int j = 0; j < 3; ++j) { v[j] = a[j]; v[3 + j] = b[3 + j]; }
-        v[6] = v[7] = 0.0;
+        v[6] = v[7] = 0;
         if (check) {
           reduce_range<8>(thrw_parts, s.item_begin[1], s.item_end[1], kThrParts, 0, a, lds);
           reduce_range<8>(thra_parts, s.item_begin[1], s.item_end[1], kThrParts, 0, b, lds);
@@ -2154,7 +2161,7 @@ __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* __restrict__ 
     }
   }
   if (check && d.ring) {
-    double v[8], w[8];
+    acc_t v[8], w[8];
     reduce_range<8>(proj_parts, d.sp_begin, d.sp_end, kProjParts, kEvolOff, v, lds);
     reduce_range<8>(proj_parts, d.sp_begin, d.sp_end, kProjParts, kEvolOff + 8, w, lds);
     if (threadIdx.x == 0) {
@@ -2329,4 +2336,5 @@ void launch_zero(hipStream_t st, double* a, int64_t n) {
   if (n > 0) k_zero_f64<<<(int)((n + kBlock - 1) / kBlock < 1024 ? (n + kBlock - 1) / kBlock : 1024), kBlock, 0, st>>>(a, n);
 }
 
+}  // namespace SIP_KNS
 }  // namespace sip

@@ -41,7 +41,7 @@ class Opts(C.Structure):
                 ("rho0", C.c_double), ("gamma0", C.c_double), ("eps_corr", C.c_double),
                 ("rho_ratio_max", C.c_double), ("gamma_max", C.c_double), ("eps_evol", C.c_double),
                 ("eps_feas", C.c_double), ("cg_rel", C.c_double), ("field", C.c_int32),
-                ("log_schedule", C.c_int32)]
+                ("reduce", C.c_int32), ("log_schedule", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -163,10 +163,13 @@ def make_sets(sets) -> C.Array:
     return arr
 
 
-def make_opts(field="f32", **kw) -> Opts:
+def make_opts(field="f32", reduce="f64", **kw) -> Opts:
+    """Options with the library defaults, the field type, the reduction type
+    ("f64", or "f32" for the pure-FP32 ablation) and any sip_opts field."""
     o = Opts()
     check(lib().sip_opts_default(C.byref(o)), "sip_opts_default")
     o.field = F64 if field in ("f64", F64, "float64") else F32
+    o.reduce = F32 if reduce in ("f32", F32, "float32") else F64
     for k, v in kw.items():
         if not hasattr(o, k):
             raise KeyError(k)

@@ -131,6 +131,28 @@ def test_schedule_locked_f32(kind):
     assert err <= gate
 
 
+@pytest.mark.parametrize("kind", ["box_tv_2d", "four_sets_2d", "box_tv_lat_3d"])
+def test_reduce_f32_ablation(kind):
+    """Pure-FP32 reductions (the precision ablation) against FP64 ones, both
+    schedule-locked against the FP64 oracle: the ablation still projects
+    (error bounded) and its error is reported next to the default's."""
+    m, sets = _prep(kind, "f32", seed=2)
+    iters = 40
+    errs = {}
+    for red in ("f64", "f32"):
+        sl = Slot(m, sets, "f32", dict(max_iter=iters, cg_max=10, cg_fixed=1, log_schedule=1, reduce=red))
+        sl.batch.run(iters)
+        res = sl.batch.result(sl.slot)
+        assert res["status"] == 0 and res["iters"] == iters
+        rho, gam = sl.batch.schedule(sl.slot, iters)
+        sched = {k + 1: (rho[k], gam[k]) for k in range(iters)}
+        xo, _ = orc.parsdmm(m, m.shape, sets, orc.Options(max_iter=iters, cg_max=10, cg_fixed=True), schedule=sched)
+        errs[red] = rel(sl.x(), xo)
+    print(f"\n[reduce ablation] {kind}: schedule-locked rel err, FP64 reductions {errs['f64']:.2e}, "
+          f"FP32 reductions {errs['f32']:.2e}", flush=True)
+    assert np.isfinite(errs["f32"]) and errs["f32"] <= 1e-2
+
+
 def test_c1_full_config_f64():
     """The 64x64 float64 box + TV workload, 200 iterations x 10 CG steps."""
     m, sets, field, iters = wl.smooth2d_box_tv()

@@ -39,6 +39,18 @@ def test_opts_defaults(L):
     assert (o.max_iter, o.cg_max, o.adapt_every, o.stop_every, o.evol_hist) == (200, 10, 2, 0, 5)
     assert (o.rho0, o.gamma0, o.eps_corr, o.gamma_max, o.cg_rel) == (1.0, 1.0, 0.3, 1.999, 0.1)
     assert (o.eps_evol, o.eps_feas, o.rho_ratio_max) == (1e-2, 1e-3, 100.0)
+    assert (o.field, o.reduce, o.log_schedule) == (sip.F32, sip.F64, 0)
+
+
+def test_reduce_option_validation(L):
+    """FP32 reductions (the precision ablation) only with FP32 fields."""
+    box = [{"kind": "bounds", "op": "I", "lo": -1, "hi": 1}]
+    assert sip.validate((8, 8), box, sip.make_opts("f32", reduce="f32")) == 0
+    assert sip.validate((8, 8), box, sip.make_opts("f64", reduce="f64")) == 0
+    assert sip.validate((8, 8), box, sip.make_opts("f64", reduce="f32")) == sip.EINVAL
+    bad = sip.make_opts("f32")
+    bad.reduce = 7
+    assert sip.validate((8, 8), box, bad) == sip.EINVAL
 
 
 def test_rows(L):
