@@ -255,6 +255,47 @@ int32_t sip_stream_copy(void* dst, const void* src, int64_t bytes, void* stream)
 int32_t sip_batch_items(sip_batch* b, int32_t* n_point_items, int32_t* n_thr_items,
                         int32_t* n_pipelines, int32_t* n_instances);
 
+/* ---- Multilevel PARSDMM (section "Multilevel PARSDMM", ML-PARSDMM listing).
+ * Coarse-to-fine continuation: level l (0 = the given grid) has ceil(n / 2)
+ * points per axis of level l - 1 (samples 0, 2, 4, ...), spacing h * 2^l;
+ * PARSDMM runs on the coarsest level from the usual start (x = m_l,
+ * y_i = A_i m_l, v_i = 0), then x, y_i and v_i (i = 1..p+1) are interpolated
+ * as images to the next finer grid and used as its initial guess, up to
+ * level 0.  (rho, gamma) restart from (rho0, gamma0) on every level, or
+ * continue from the coarser level's final values (carry_params = 1). */
+
+/* Grid and set list of level `level`: bounds unchanged; an l1 tau and a
+ * cardinality k scaled by rows of A at that level / rows at level 0
+ * (k = floor(k * ratio + 1/2) within [1, rows]).  sets_out holds nsets
+ * entries.  SIP_EINVAL on bad arguments; does not validate the level's
+ * sets (an axis may become too short for a difference operator). */
+int32_t sip_level(const sip_grid* g, const sip_set* sets, int32_t nsets, int32_t level,
+                  sip_grid* g_out, sip_set* sets_out);
+
+/* The coarse model of the next level: the binomial [1, 2, 1] / 4 filter
+ * along every axis (edges replicated) followed by every other sample from 0.
+ * src_dev: N elements of type dtype on grid g; dst_dev: the coarse grid's
+ * elements (sip_level(g, ..., 1, ...)).  Enqueued on `stream`. */
+int32_t sip_restrict(const sip_grid* g, int32_t dtype, const void* src_dev, void* dst_dev, void* stream);
+
+/* Multilevel projection of m_dev onto the intersection, with nlevels levels
+ * (1 = plain PARSDMM) and level_iters[l] the iteration cap of level l
+ * (0 = the given grid; stopping rule per level as in opts); carry_params:
+ * 0 = every level starts from (rho0, gamma0), 1 = from the coarser level's
+ * final (rho, gamma).  Interpolation
+ * is linear along each axis at the geometric position of every fine sample
+ * (points at i / 2; rows of a difference along an axis at (i + 1/2) / 2 - 1/2
+ * on that axis), clamped to the coarse image.  Allocates the coarse models
+ * and iterates and each level's workspace, blocks until done, frees them.
+ * *res (may be NULL): the result on the given grid; level_iters_run (nlevels
+ * entries, may be NULL): iterations each level ran.  SIP_EINVAL when a level
+ * is invalid (e.g. an axis of a difference operator shorter than 2 points),
+ * otherwise as sip_project. */
+int32_t sip_project_multilevel(const sip_grid* g, const sip_set* sets, int32_t nsets, const sip_opts* o,
+                               int32_t nlevels, const int32_t* level_iters, int32_t carry_params,
+                               const void* m_dev, void* x_dev, sip_result* res, int32_t* level_iters_run,
+                               void* stream);
+
 #ifdef __cplusplus
 }
 #endif

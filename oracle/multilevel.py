@@ -22,10 +22,12 @@ The paper leaves the following open; this module fixes them (readings):
   * set parameters per level: bounds unchanged (difference quotients keep
     their units since h doubles with the spacing); an l1 budget tau and a
     cardinality k scale with the number of rows of the operator at that
-    level (k rounded, at least 1);
+    level (k rounded half up, at least 1, at most the rows);
   * the coarsest level starts like single-level PARSDMM (x = m, y_i = A_i m,
-    v_i = 0), so one level is exactly PARSDMM; (rho, gamma) restart from
-    (rho0, gamma0) on every level.
+    v_i = 0), so one level is exactly PARSDMM;
+  * (rho, gamma) on a finer level: either restart from (rho0, gamma0) or
+    continue from the coarser level's final values (carry_params); the
+    listing passes only x, y_i and v_i between levels.
 """
 from __future__ import annotations
 
@@ -74,7 +76,7 @@ def level_sets(sets, shape, shape_l):
         if s["kind"] == "l1":
             s2["tau"] = s["tau"] * ratio
         elif s["kind"] == "card":
-            s2["k"] = int(min(rows(shape_l, s["op"]), max(1, round(s["k"] * ratio))))
+            s2["k"] = int(min(rows(shape_l, s["op"]), max(1, math.floor(s["k"] * ratio + 0.5))))
         out.append(s2)
     return out
 
@@ -139,7 +141,8 @@ def prolong_rows(v, op, shape_c, shape_f):
     return np.concatenate(parts)
 
 
-def parsdmm_multilevel(m, shape, sets, nlevels, level_iters, opts: orc.Options | None = None, h=None):
+def parsdmm_multilevel(m, shape, sets, nlevels, level_iters, opts: orc.Options | None = None, h=None,
+                       carry_params=False):
     """Multilevel PARSDMM.  level_iters[l] caps the iterations of level l
     (0 = the given grid).  Returns (x, per-level final states)."""
     opts = opts or orc.Options()
@@ -165,6 +168,8 @@ def parsdmm_multilevel(m, shape, sets, nlevels, level_iters, opts: orc.Options |
             ops = [s["op"] for s in sets_l] + ["I"]
             st.y = [prolong_rows(pst.y[i], ops[i], psh, sh) for i in range(len(ops))]
             st.v = [prolong_rows(pst.v[i], ops[i], psh, sh) for i in range(len(ops))]
+            if carry_params:
+                st.rho, st.gamma = pst.rho.copy(), pst.gamma.copy()
         _, st = orc.parsdmm(ms[lev], sh, sets_l, o, h=hl, state=st)
         states[lev] = st
         prev = (prob, st, sh)

@@ -31,6 +31,12 @@ template <typename T> void launch_phase(hipStream_t st, const Tables& t, const O
 using r64::launch_init;
 using r64::launch_zero;
 using r64::launch_copy;
+// level transfer of multilevel PARSDMM
+template <typename T>
+void launch_restrict(hipStream_t st, const T* src, const int64_t (&n)[3], T* dst, const int64_t (&c)[3]);
+template <typename T>
+void launch_prolong(hipStream_t st, const T* src, const int64_t (&s)[3], int64_t ssz, int64_t ssy, T* dst,
+                    const int64_t (&f)[3], const int64_t (&d)[3], int64_t dsz, int64_t dsy, int stag);
 
 namespace {
 
@@ -962,3 +968,160 @@ int32_t sip_project_batched(int32_t B, const sip_grid* grids, const sip_set* set
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ multilevel
+
+namespace {
+
+// Grid and sets of level `level` (0 = the given grid): ceil(n / 2) points per
+// axis and level, spacing doubled; l1 budgets and cardinalities scaled by
+// the operator's row ratio (cardinality rounded half up, within [1, rows]).
+void level_of(const sip_grid& g, const sip_set* sets, int nsets, int level, sip_grid& gl, sip_set* sl) {
+  gl = g;
+  for (int a = 0; a < g.ndim; ++a) {
+    int64_t n = g.n[a];
+    for (int l = 0; l < level; ++l) n = (n + 1) / 2;
+    gl.n[a] = n;
+    gl.h[a] = g.h[a] * std::ldexp(1.0, level);
+  }
+  for (int i = 0; i < nsets; ++i) {
+    sl[i] = sets[i];
+    const int64_t r0 = rows_of(g, sets[i]), rl = rows_of(gl, sets[i]);
+    if (r0 <= 0 || rl <= 0) continue;  // rejected by validate()
+    const double ratio = (double)rl / (double)r0;
+    if (sets[i].kind == SIP_SET_L1) sl[i].tau = sets[i].tau * ratio;
+    if (sets[i].kind == SIP_SET_CARD) {
+      int64_t k = (int64_t)std::floor((double)sets[i].k * ratio + 0.5);
+      sl[i].k = std::min<int64_t>(rl, std::max<int64_t>(1, k));
+    }
+  }
+}
+
+template <typename T>
+void prolong_state(hipStream_t st, const Slot& c, const Slot& f) {
+  const InstDesc& dc = c.desc;
+  const InstDesc& df = f.desc;
+  const int64_t sc[3] = {dc.n[0], dc.n[1], dc.n[2]};
+  const int64_t sf[3] = {df.n[0], df.n[1], df.n[2]};
+  auto one = [&](const void* src, void* dst, int axis) {
+    int64_t si[3] = {sc[0], sc[1], sc[2]}, di[3] = {sf[0], sf[1], sf[2]};
+    if (axis >= 0) { si[axis] -= 1; di[axis] -= 1; }
+    launch_prolong<T>(st, (const T*)src, si, sc[1] * sc[2], sc[2], (T*)dst, sf, di, sf[1] * sf[2], sf[2], axis);
+  };
+  one(dc.x, df.x, -1);
+  if (df.ring) one(dc.x, df.ring, -1);  // history slot 0 = the initial x
+  one(dc.yl, df.yl, -1);
+  one(dc.vl, df.vl, -1);
+  for (int i = 0; i < df.nsets; ++i) {
+    const SetDesc& a = dc.sets[i];
+    const SetDesc& b = df.sets[i];
+    for (int k = 0; k < b.ncomp; ++k) {
+      one((const T*)a.y + (size_t)k * dc.cs, (T*)b.y + (size_t)k * df.cs, b.axis[k]);
+      one((const T*)a.v + (size_t)k * dc.cs, (T*)b.v + (size_t)k * df.cs, b.axis[k]);
+    }
+  }
+}
+
+}  // namespace
+
+int32_t sip_level(const sip_grid* g, const sip_set* sets, int32_t nsets, int32_t level, sip_grid* g_out,
+                  sip_set* sets_out) {
+  if (!g || !g_out || level < 0 || (nsets > 0 && (!sets || !sets_out))) return SIP_EINVAL;
+  if (nsets < 0 || nsets > SIP_MAX_SETS || (g->ndim != 2 && g->ndim != 3)) return SIP_EINVAL;
+  sip_set tmp[SIP_MAX_SETS];
+  level_of(*g, sets, nsets, level, *g_out, tmp);
+  for (int i = 0; i < nsets; ++i) sets_out[i] = tmp[i];
+  return SIP_OK;
+}
+
+int32_t sip_restrict(const sip_grid* g, int32_t dtype, const void* src_dev, void* dst_dev, void* stream_) {
+  if (!g || !src_dev || !dst_dev || (g->ndim != 2 && g->ndim != 3)) return SIP_EINVAL;
+  if (dtype != SIP_F32 && dtype != SIP_F64) return SIP_EINVAL;
+  for (int a = 0; a < g->ndim; ++a)
+    if (g->n[a] < 1) return SIP_EINVAL;
+  sip_grid gc;
+  level_of(*g, nullptr, 0, 1, gc, nullptr);
+  int64_t n[3], c[3];
+  double h[3];
+  internal_dims(*g, n, h);
+  internal_dims(gc, c, h);
+  hipStream_t st = (hipStream_t)stream_;
+  if (dtype == SIP_F64) launch_restrict<double>(st, (const double*)src_dev, n, (double*)dst_dev, c);
+  else launch_restrict<float>(st, (const float*)src_dev, n, (float*)dst_dev, c);
+  return hipGetLastError() == hipSuccess ? SIP_OK : SIP_EHIP;
+}
+
+int32_t sip_project_multilevel(const sip_grid* g, const sip_set* sets, int32_t nsets, const sip_opts* o,
+                               int32_t nlevels, const int32_t* level_iters, int32_t carry_params,
+                               const void* m_dev, void* x_dev, sip_result* res, int32_t* level_iters_run,
+                               void* stream_) {
+  if (!g || !o || !level_iters || !m_dev || !x_dev || nlevels < 1 || nlevels > 16) return SIP_EINVAL;
+  int32_t rc = validate(g, sets, nsets, o);
+  if (rc != SIP_OK) return rc;
+  std::vector<sip_grid> grids(nlevels);
+  std::vector<std::vector<sip_set>> lsets(nlevels, std::vector<sip_set>(std::max(nsets, 1)));
+  for (int l = 0; l < nlevels; ++l) {
+    if (level_iters[l] < 1) return SIP_EINVAL;
+    level_of(*g, sets, nsets, l, grids[l], lsets[l].data());
+    sip_opts ol = *o;
+    ol.max_iter = level_iters[l];
+    rc = validate(&grids[l], lsets[l].data(), nsets, &ol);
+    if (rc != SIP_OK) return rc;  // e.g. too many levels for a difference axis
+  }
+  hipStream_t stream = (hipStream_t)stream_;
+  const size_t esz = o->field == SIP_F64 ? 8 : 4;
+  // coarse models and iterates (level 0 uses the caller's m and x)
+  std::vector<void*> ms(nlevels, nullptr), xs(nlevels, nullptr);
+  ms[0] = const_cast<void*>(m_dev);
+  xs[0] = x_dev;
+  auto cleanup = [&]() {
+    for (int l = 1; l < nlevels; ++l) {
+      if (ms[l]) (void)hipFree(ms[l]);
+      if (xs[l]) (void)hipFree(xs[l]);
+    }
+  };
+  for (int l = 1; l < nlevels; ++l) {
+    int64_t n = 1;
+    for (int a = 0; a < g->ndim; ++a) n *= grids[l].n[a];
+    if (hipMalloc(&ms[l], (size_t)n * esz) != hipSuccess || hipMalloc(&xs[l], (size_t)n * esz) != hipSuccess) {
+      cleanup();
+      return SIP_ENOMEM;
+    }
+    rc = sip_restrict(&grids[l - 1], o->field, ms[l - 1], ms[l], stream);
+    if (rc != SIP_OK) { cleanup(); return rc; }
+  }
+  sip_batch* prev = nullptr;
+  sip_result r{};
+  for (int l = nlevels - 1; l >= 0 && rc == SIP_OK; --l) {
+    sip_opts ol = *o;
+    ol.max_iter = level_iters[l];
+    sip_batch* b = nullptr;
+    rc = sip_batch_create(&b, 1, sip_workspace_bytes(&grids[l], lsets[l].data(), nsets, &ol), &ol);
+    if (rc != SIP_OK) break;
+    int32_t slot = -1;
+    rc = sip_batch_add(b, &grids[l], lsets[l].data(), nsets, ms[l], xs[l], &slot, stream);
+    if (rc == SIP_OK && prev) {
+      if (o->field == SIP_F64) prolong_state<double>(stream, prev->slots[0], b->slots[slot]);
+      else prolong_state<float>(stream, prev->slots[0], b->slots[slot]);
+      if (hipGetLastError() != hipSuccess) rc = SIP_EHIP;
+      if (rc == SIP_OK && carry_params) {
+        // start from the coarser level's final (rho, gamma)
+        double rho[SIP_MAX_SETS + 1], gam[SIP_MAX_SETS + 1];
+        for (int i = 0; i <= nsets; ++i) { rho[i] = r.rho[i]; gam[i] = r.gamma[i]; }
+        rc = sip_batch_set_params(b, slot, rho, gam, 1, 0, stream);
+      }
+    }
+    if (rc == SIP_OK) rc = run_to_end(b, std::min(ol.max_iter, ol.stop_every > 0 ? 5 * ol.stop_every : 25), stream);
+    if (prev) { sip_batch_destroy(prev); prev = nullptr; }
+    if (rc == SIP_OK) rc = sip_batch_result(b, slot, &r, stream);
+    if (rc == SIP_OK && level_iters_run) level_iters_run[l] = r.iters;
+    if (rc == SIP_OK && r.status != SIP_OK) rc = r.status;
+    prev = b;
+  }
+  if (prev) sip_batch_destroy(prev);
+  if (hipStreamSynchronize(stream) != hipSuccess && rc == SIP_OK) rc = SIP_EHIP;
+  cleanup();
+  if (rc != SIP_OK) return rc;
+  if (res) *res = r;
+  return SIP_OK;
+}

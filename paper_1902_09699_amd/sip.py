@@ -104,6 +104,10 @@ def lib():
         "sip_batch_time_kernel": (i32, [vp, i32, i32, vp, C.POINTER(C.c_double)]),
         "sip_stream_copy": (i32, [vp, vp, i64, vp]),
         "sip_batch_items": (i32, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
+        "sip_level": (i32, [C.POINTER(Grid), C.POINTER(Set), i32, i32, C.POINTER(Grid), C.POINTER(Set)]),
+        "sip_restrict": (i32, [C.POINTER(Grid), i32, vp, vp, vp]),
+        "sip_project_multilevel": (i32, [C.POINTER(Grid), C.POINTER(Set), i32, C.POINTER(Opts), i32,
+                                         C.POINTER(i32), i32, vp, vp, C.POINTER(Result), C.POINTER(i32), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -118,7 +122,8 @@ def exported_symbols():
             "sip_project", "sip_project_batched", "sip_batch_create", "sip_batch_destroy", "sip_batch_add",
             "sip_batch_run", "sip_batch_poll", "sip_batch_remove", "sip_batch_result", "sip_batch_field",
             "sip_batch_get_params", "sip_batch_set_params", "sip_batch_schedule", "sip_batch_set_tiles",
-            "sip_batch_items", "sip_batch_reset", "sip_batch_time_kernel", "sip_stream_copy"]
+            "sip_batch_items", "sip_batch_reset", "sip_batch_time_kernel", "sip_stream_copy", "sip_level",
+            "sip_restrict", "sip_project_multilevel"]
 
 
 def strerror(status: int) -> str:
@@ -233,6 +238,70 @@ def project(m, sets, opts: Opts, x=None, h=None, stream=None):
                            C.c_void_p(x.data_ptr()), C.byref(res), _stream_ptr(stream))
     check(st, "sip_project")
     return x, res.as_dict()
+
+
+def level(shape, sets, lev, h=None):
+    """(shape, set dicts) of multilevel level ``lev`` (0 = the given grid)."""
+    g = make_grid(shape, h)
+    arr = make_sets(sets)
+    go = Grid()
+    out = (Set * max(1, len(sets)))()
+    check(lib().sip_level(C.byref(g), arr, len(sets), int(lev), C.byref(go), out), "sip_level")
+    shp = tuple(int(go.n[a]) for a in range(go.ndim))
+    inv_k = {v: k for k, v in KINDS.items()}
+    inv_o = {v: k for k, v in OPS.items()}
+    res = []
+    for i, d in enumerate(sets):
+        e = dict(d)
+        e.update(kind=inv_k[out[i].kind], op=inv_o[out[i].op])
+        if e["kind"] == "bounds":
+            e.update(lo=out[i].lo, hi=out[i].hi)
+        elif e["kind"] == "l1":
+            e["tau"] = out[i].tau
+        else:
+            e["k"] = int(out[i].k)
+        res.append(e)
+    return shp, res
+
+
+def restrict(m, stream=None):
+    """The next level's coarse model of device tensor m (new tensor)."""
+    import torch
+    shape = tuple(m.shape)
+    shp, _ = level(shape, [], 1)
+    dt = F64 if m.dtype == torch.float64 else F32
+    if m.dtype not in (torch.float32, torch.float64) or not m.is_contiguous():
+        raise ValueError("m: contiguous float32/float64 device tensor expected")
+    out = torch.empty(shp, dtype=m.dtype, device=m.device)
+    g = make_grid(shape)
+    check(lib().sip_restrict(C.byref(g), dt, C.c_void_p(m.data_ptr()), C.c_void_p(out.data_ptr()),
+                             _stream_ptr(stream)), "sip_restrict")
+    return out
+
+
+def project_multilevel(m, sets, opts: Opts, nlevels, level_iters, carry_params=True, x=None, h=None,
+                       stream=None):
+    """Multilevel projection (blocking).  level_iters[l] caps level l (0 =
+    the grid of m); carry_params: start each level from the coarser level's
+    final (rho, gamma) instead of (rho0, gamma0).  Returns (x, result dict of
+    level 0, iterations run per level)."""
+    import torch
+    shape = tuple(m.shape)
+    n = m.numel()
+    _check_tensor(m, n, opts, "m")
+    if x is None:
+        x = torch.empty_like(m)
+    _check_tensor(x, n, opts, "x")
+    g = make_grid(shape, h)
+    arr = make_sets(sets)
+    its = (C.c_int32 * nlevels)(*[int(v) for v in level_iters])
+    run = (C.c_int32 * nlevels)()
+    res = Result()
+    st = lib().sip_project_multilevel(C.byref(g), arr, len(sets), C.byref(opts), int(nlevels), its,
+                                      1 if carry_params else 0, C.c_void_p(m.data_ptr()), C.c_void_p(x.data_ptr()), C.byref(res), run,
+                                      _stream_ptr(stream))
+    check(st, "sip_project_multilevel")
+    return x, res.as_dict(), list(run)
 
 
 def project_batched(ms, sets_list, opts: Opts, xs=None, graph_iters=25, stream=None):

@@ -94,3 +94,29 @@ def test_workspace_bytes_exact_and_monotone(L):
 def test_strerror(L):
     assert sip.strerror(0) == "ok"
     assert "invalid" in sip.strerror(-1)
+
+
+@pytest.mark.parametrize("shape,nlev", [((21, 41), 3), ((341, 1361), 3), ((9, 12, 14), 2), ((1, 9), 2)])
+def test_level_grids_and_sets_match_oracle(L, shape, nlev):
+    """sip_level (the library's multilevel grids and set parameters) against
+    the multilevel oracle's definitions."""
+    from oracle import multilevel as ml
+    ndim = len(shape)
+    sets = [{"kind": "bounds", "op": "I", "lo": -1.0, "hi": 1.0},
+            {"kind": "l1", "op": "GRAD" if shape[0] > 1 else "DX", "tau": 57.0},
+            {"kind": "card", "op": "DX", "k": 7}]
+    if ndim == 3:
+        sets.append({"kind": "bounds", "op": "LAT", "lo": -0.1, "hi": 0.1})
+    shapes = ml.level_shapes(shape, nlev)
+    for lev in range(nlev):
+        shp, got = sip.level(shape, sets, lev)
+        assert shp == shapes[lev]
+        want = ml.level_sets(sets, shape, shapes[lev])
+        for a, b in zip(got, want):
+            assert a["kind"] == b["kind"] and a["op"] == b["op"]
+            if a["kind"] == "l1":
+                assert abs(a["tau"] - b["tau"]) <= 1e-12 * b["tau"]
+            elif a["kind"] == "card":
+                assert a["k"] == b["k"]
+            else:
+                assert (a["lo"], a["hi"]) == (b["lo"], b["hi"])
