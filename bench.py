@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--batched-count", type=int, default=256)
     ap.add_argument("--copy-mb", type=int, default=1024, help="plain-copy reference size (0: skip)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune single-instance workloads too (the batched workload always is)")
     ap.add_argument("--reduce", default="f64", choices=("f64", "f32"),
                     help="reduction type (f32: the pure-FP32 precision ablation)")
     ap.add_argument("--check-iters", type=int, default=10,
@@ -220,7 +222,7 @@ def main():
     if args.tiles:
         tiles = tuple(int(v) for v in args.tiles.split(","))
         batch.set_tiles(*tiles)
-    elif not args.no_autotune:
+    elif not args.no_autotune and (args.workload == "batched" or args.autotune):
         from paper_1902_09699_amd import autotune
         tiles, tile_ms = autotune.tune(batch, slots, ms, field, [m.shape for m, _ in insts], use_cache=False,
                                        cache=None)

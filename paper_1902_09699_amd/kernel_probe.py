@@ -21,6 +21,7 @@ def main():
     ap.add_argument("--workload", default="layered2d")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--copy-mb", type=int, default=256)
+    ap.add_argument("--tiles", default=None, help="pt_points,pt_max_items,thr_points,thr_max_items[,pt_threads]")
     a = ap.parse_args()
     import torch
 
@@ -38,6 +39,8 @@ def main():
     xs = [torch.empty_like(m) for m in ms]
     batch = sip.Batch(len(insts), sum(sip.workspace_bytes(m.shape, s, opts) for m, s in insts), opts)
     slots = [batch.add(md, s, xd) for md, (_, s), xd in zip(ms, insts, xs)]
+    if a.tiles:
+        batch.set_tiles(*[int(v) for v in a.tiles.split(",")])
     batch.run(2)
     torch.cuda.synchronize()
     for sl in slots:
@@ -45,7 +48,7 @@ def main():
         batch.set_params(sl, r_, g_, 2, True)
     out = {}
     for name, kid in (("cg_dir", sip.K_CG_DIR), ("cg_upd", sip.K_CG_UPD), ("rhs", sip.K_RHS),
-                      ("proj", sip.K_PROJ)):
+                      ("proj", sip.K_PROJ), ("thr_w", sip.K_THR_W), ("thr_apply", sip.K_THR_APPLY)):
         out[name] = batch.time_kernel(kid, a.reps)
         print(f"{name}: {out[name] * 1e3:.2f} us", flush=True)
     n = a.copy_mb * (1 << 20) // 4

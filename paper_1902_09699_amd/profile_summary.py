@@ -22,7 +22,10 @@ def _db(path):
 
 
 def _short(name: str) -> str:
-    return name.replace("sip::", "").replace("void ", "").split("(")[0]
+    """Kernel name without the library namespace (the FP32-reduction
+    ablation build keeps its r32:: prefix)."""
+    return name.replace("sip::", "").replace("r64::", "").replace("(anonymous namespace)::", "") \
+        .replace("void ", "").split("(")[0]
 
 
 def kernel_table(con, top=20):
