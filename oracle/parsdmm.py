@@ -152,14 +152,49 @@ def project_card(w, k):
     return y
 
 
+def project_l2(w, tau):
+    """Euclidean projection onto the l2 ball {y : ||y||_2 <= tau} (Table
+    set-overview): w itself when inside, otherwise w scaled back to the
+    sphere, tau w / ||w||."""
+    w = np.asarray(w, dtype=np.float64)
+    nrm = float(np.linalg.norm(w))
+    if nrm <= tau:
+        return w.copy()
+    return w * (tau / nrm)
+
+
+def project_annulus(w, lo, hi):
+    """Projection onto the annulus {y : lo <= ||y||_2 <= hi} (Table
+    set-overview; not convex when lo > 0): w itself inside, otherwise w
+    scaled radially to the nearer radius.  At w = 0 with lo > 0 every point of
+    the inner sphere is nearest; the reading takes lo e_0 (the first row)."""
+    w = np.asarray(w, dtype=np.float64)
+    nrm = float(np.linalg.norm(w))
+    if lo <= nrm <= hi:
+        return w.copy()
+    if nrm > hi:
+        return w * (hi / nrm)
+    if nrm > 0.0:
+        return w * (lo / nrm)
+    y = np.zeros_like(w)
+    y[0] = lo
+    return y
+
+
 def project_set(s: dict, w):
+    """P_{C_i}(w).  Bounds take scalars or per-row vectors (per-pixel
+    bounds l[i] <= (A x)[i] <= u[i], in A's row order)."""
     kind = s["kind"]
     if kind == "bounds":
-        return project_bounds(w, s["lo"], s["hi"])
+        return project_bounds(w, np.asarray(s["lo"], dtype=np.float64), np.asarray(s["hi"], dtype=np.float64))
     if kind == "l1":
         return project_l1(w, s["tau"])
     if kind == "card":
         return project_card(w, s["k"])
+    if kind == "l2":
+        return project_l2(w, s["tau"])
+    if kind == "annulus":
+        return project_annulus(w, s["lo"], s["hi"])
     raise ValueError(f"unknown set kind {kind!r}")
 
 
