@@ -64,9 +64,12 @@ typedef enum {
 
 /* Simple sets C_i (Table set-overview). */
 typedef enum {
-  SIP_SET_BOUNDS = 0, /* lo <= (A x)[j] <= hi, +-INFINITY allowed */
+  SIP_SET_BOUNDS = 0, /* lo <= (A x)[j] <= hi, +-INFINITY allowed; or per-row bound vectors */
   SIP_SET_L1 = 1,     /* ||A x||_1 <= tau */
-  SIP_SET_CARD = 2    /* card(A x) <= k: keep the k largest |.|, ties to the lower index */
+  SIP_SET_CARD = 2,   /* card(A x) <= k: keep the k largest |.|, ties to the lower index */
+  SIP_SET_L2 = 3,     /* ||A x||_2 <= tau */
+  SIP_SET_ANNULUS = 4 /* lo <= ||A x||_2 <= hi (not convex for lo > 0): radial projection;
+                         at A x = 0 the projection is lo times the first row's unit vector */
 } sip_set_kind;
 
 typedef struct {
@@ -79,9 +82,18 @@ typedef struct {
 typedef struct {
   int32_t kind;   /* sip_set_kind */
   int32_t op;     /* sip_op; the operator's axes need at least 2 points */
-  double lo, hi;  /* BOUNDS: lo <= hi */
-  double tau;     /* L1: tau >= 0 */
+  double lo, hi;  /* BOUNDS: lo <= hi; ANNULUS: radii, 0 <= lo <= hi */
+  double tau;     /* L1, L2: tau >= 0 */
   int64_t k;      /* CARD: 1 <= k <= rows of A */
+  /* BOUNDS only, per-pixel bounds l[j] <= (A x)[j] <= u[j] (NULL: the scalar
+   * lo / hi): device arrays of the field type, one block of N elements per
+   * component of A in the grid's C order (the row of grid point P of
+   * component c at c*N + P; entries of the unused last layer along the
+   * component's axis are ignored).  Copied into the workspace when the
+   * instance is admitted; the caller may free them afterwards.  Not
+   * supported by sip_project_multilevel. */
+  const void* lo_vec;
+  const void* hi_vec;
 } sip_set;
 
 typedef struct {

@@ -22,7 +22,8 @@ The paper leaves the following open; this module fixes them (readings):
   * set parameters per level: bounds unchanged (difference quotients keep
     their units since h doubles with the spacing); an l1 budget tau and a
     cardinality k scale with the number of rows of the operator at that
-    level (k rounded half up, at least 1, at most the rows);
+    level (k rounded half up, at least 1, at most the rows); l2 radii (the
+    l2 ball's tau, the annulus' lo and hi) with its square root;
   * the coarsest level starts like single-level PARSDMM (x = m, y_i = A_i m,
     v_i = 0), so one level is exactly PARSDMM;
   * (rho, gamma) on a finer level: either restart from (rho0, gamma0) or
@@ -75,6 +76,10 @@ def level_sets(sets, shape, shape_l):
         ratio = rows(shape_l, s["op"]) / rows(shape, s["op"])
         if s["kind"] == "l1":
             s2["tau"] = s["tau"] * ratio
+        elif s["kind"] == "l2":
+            s2["tau"] = s["tau"] * math.sqrt(ratio)
+        elif s["kind"] == "annulus":
+            s2["lo"], s2["hi"] = s["lo"] * math.sqrt(ratio), s["hi"] * math.sqrt(ratio)
         elif s["kind"] == "card":
             s2["k"] = int(min(rows(shape_l, s["op"]), max(1, math.floor(s["k"] * ratio + 0.5))))
         out.append(s2)

@@ -168,20 +168,31 @@ int32_t validate(const sip_grid* g, const sip_set* sets, int32_t nsets, const si
       case SIP_SET_CARD:
         if (s.k < 1 || s.k > M) return SIP_EINVAL;
         break;
+      case SIP_SET_L2:
+        if (!(s.tau >= 0.0) || !std::isfinite(s.tau)) return SIP_EINVAL;
+        break;
+      case SIP_SET_ANNULUS:
+        if (!(s.lo >= 0.0) || !std::isfinite(s.lo) || std::isnan(s.hi) || s.lo > s.hi) return SIP_EINVAL;
+        break;
       default:
         return SIP_EINVAL;
     }
+    if ((s.lo_vec || s.hi_vec) && s.kind != SIP_SET_BOUNDS) return SIP_EINVAL;
   }
   return SIP_OK;
 }
 
-bool is_thr(const sip_set& s) { return s.kind == SIP_SET_L1 || s.kind == SIP_SET_CARD; }
+// Sets projected through the selection pipeline (a global reduction over
+// the set's rows decides the projection).
+bool is_thr(const sip_set& s) {
+  return s.kind == SIP_SET_L1 || s.kind == SIP_SET_CARD || s.kind == SIP_SET_L2 || s.kind == SIP_SET_ANNULUS;
+}
 
 // Byte layout of one instance's workspace.
 struct Layout {
   int64_t total = 0;
   int64_t log = -1, m, r, p0, p1, yl, vl, vh0l = -1, v0l = -1, y0l = -1, xs0 = -1, xs1 = -1, ring = -1;
-  struct SetL { int64_t y, v, vh0 = -1, v0 = -1, y0 = -1; int64_t sel[2] = {-1, -1}, hc[2] = {-1, -1},
+  struct SetL { int64_t y, v, vh0 = -1, v0 = -1, y0 = -1, lov = -1, hiv = -1; int64_t sel[2] = {-1, -1}, hc[2] = {-1, -1},
                 hs[2] = {-1, -1}, cand[2] = {-1, -1}; } set[SIP_MAX_SETS];
 };
 
@@ -207,6 +218,8 @@ Layout layout_of(const sip_grid& g, const sip_set* sets, int nsets, const sip_op
     auto& S = L.set[i];
     S.y = take(blk); S.v = take(blk);
     if (adapt) { S.vh0 = take(blk); S.v0 = take(blk); S.y0 = take(blk); }
+    if (sets[i].lo_vec) S.lov = take(blk);
+    if (sets[i].hi_vec) S.hiv = take(blk);
     if (is_thr(sets[i])) {
       for (int src = 0; src < (stop ? 2 : 1); ++src) {
         S.sel[src] = take(sizeof(SelState));
@@ -616,6 +629,7 @@ int32_t sip_batch_add(sip_batch* b, const sip_grid* g, const sip_set* sets, int3
     sd.rows = rows_of(*g, sets[i]);
     const auto& SL = L.set[i];
     sd.y = at(SL.y); sd.v = at(SL.v); sd.vh0 = at(SL.vh0); sd.v0 = at(SL.v0); sd.y0 = at(SL.y0);
+    sd.lov = at(SL.lov); sd.hiv = at(SL.hiv);
     for (int src = 0; src < 2; ++src) {
       sd.sel[src] = (SelState*)at(SL.sel[src]);
       sd.hcnt[src] = (uint32_t*)at(SL.hc[src]);
@@ -631,6 +645,24 @@ int32_t sip_batch_add(sip_batch* b, const sip_grid* g, const sip_set* sets, int3
       hipMemcpyAsync(b->d_desc + si, &d, sizeof(InstDesc), hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipMemcpyAsync(d.scal, S, sizeof(S), hipMemcpyHostToDevice, stream) != hipSuccess) {
     rc = SIP_EHIP;
+  }
+  if (rc == SIP_OK) {
+    // per-row bound vectors into the padded component layout; waited for, so
+    // the caller may release its arrays when admission returns
+    bool vec_bounds = false;
+    for (int i = 0; i < nsets && rc == SIP_OK; ++i) {
+      const SetDesc& sd = d.sets[i];
+      const void* src[2] = {sets[i].lo_vec, sets[i].hi_vec};
+      void* dst[2] = {sd.lov, sd.hiv};
+      for (int q = 0; q < 2; ++q) {
+        if (!src[q]) continue;
+        vec_bounds = true;
+        if (hipMemcpy2DAsync(dst[q], (size_t)d.cs * esz, src[q], (size_t)s.N * esz, (size_t)s.N * esz,
+                             (size_t)sd.ncomp, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+          rc = SIP_EHIP;
+      }
+    }
+    if (rc == SIP_OK && vec_bounds && hipStreamSynchronize(stream) != hipSuccess) rc = SIP_EHIP;
   }
   if (rc == SIP_OK) {
     for (int i = 0; i < nsets; ++i) {
@@ -990,6 +1022,8 @@ void level_of(const sip_grid& g, const sip_set* sets, int nsets, int level, sip_
     if (r0 <= 0 || rl <= 0) continue;  // rejected by validate()
     const double ratio = (double)rl / (double)r0;
     if (sets[i].kind == SIP_SET_L1) sl[i].tau = sets[i].tau * ratio;
+    if (sets[i].kind == SIP_SET_L2) sl[i].tau = sets[i].tau * std::sqrt(ratio);
+    if (sets[i].kind == SIP_SET_ANNULUS) { sl[i].lo = sets[i].lo * std::sqrt(ratio); sl[i].hi = sets[i].hi * std::sqrt(ratio); }
     if (sets[i].kind == SIP_SET_CARD) {
       int64_t k = (int64_t)std::floor((double)sets[i].k * ratio + 0.5);
       sl[i].k = std::min<int64_t>(rl, std::max<int64_t>(1, k));
@@ -1058,6 +1092,8 @@ int32_t sip_project_multilevel(const sip_grid* g, const sip_set* sets, int32_t n
   if (!g || !o || !level_iters || !m_dev || !x_dev || nlevels < 1 || nlevels > 16) return SIP_EINVAL;
   int32_t rc = validate(g, sets, nsets, o);
   if (rc != SIP_OK) return rc;
+  for (int i = 0; i < nsets; ++i)
+    if (sets[i].lo_vec || sets[i].hi_vec) return SIP_EUNSUPPORTED;
   std::vector<sip_grid> grids(nlevels);
   std::vector<std::vector<sip_set>> lsets(nlevels, std::vector<sip_set>(std::max(nsets, 1)));
   for (int l = 0; l < nlevels; ++l) {

@@ -42,7 +42,8 @@ enum Scal : int {
   S_COUNT = S_RFEAS + SIP_MAX_SETS + 4
 };
 
-enum SelMode : int { SEL_PROJECT = 0, SEL_INSIDE = 1, SEL_ZERO = 2, SEL_ALL = 3 };
+// SEL_POINT: an annulus at w = 0 (y = lo on the first row, 0 elsewhere).
+enum SelMode : int { SEL_PROJECT = 0, SEL_INSIDE = 1, SEL_ZERO = 2, SEL_ALL = 3, SEL_POINT = 4 };
 
 // Selection state of one pipeline (a threshold set's w = x-bar - v/rho, or
 // on stopping-test iterations its s = A x).  Keys are the IEEE bit patterns
@@ -77,6 +78,7 @@ struct SetDesc {
   int64_t k, rows;                // rows = M_i
   void* y; void* v;               // ncomp blocks of N
   void* vh0; void* v0; void* y0;  // adapt snapshots (ncomp blocks of N)
+  void* lov; void* hiv;           // per-row bounds (ncomp blocks of N) or null
   // pipelines: [0] values w (every iteration), [1] values s (stopping test)
   SelState* sel[2];
   uint32_t* hcnt[2];

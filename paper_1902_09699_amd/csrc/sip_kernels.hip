@@ -973,12 +973,14 @@ struct ProjUnit {
   bool ident;
 };
 
+// lo, hi: this row's bounds (the set's scalars or its per-row vectors).
 template <typename T>
-__device__ __forceinline__ void proj_point(const ProjUnit<T>& U, T sv, T yo, T vo, T mv, T& yn, T& vn, T& xb) {
+__device__ __forceinline__ void proj_point(const ProjUnit<T>& U, T sv, T yo, T vo, T mv, T lo, T hi, T& yn, T& vn,
+                                           T& xb) {
   xb = U.gam * sv + U.one_m_g * yo;
   const T w = xb - vo * U.irho;
   if (U.ident) yn = (mv + U.rho * w) * U.inv1p;
-  else yn = w < U.lo ? U.lo : (w > U.hi ? U.hi : w);
+  else yn = w < lo ? lo : (w > hi ? hi : w);
   vn = vo + U.rho * (yn - xb);
 }
 
@@ -1029,6 +1031,9 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
       T* __restrict__ vh0 = (T*)(ident ? d.vh0l : s->vh0) + off;
       T* __restrict__ v0 = (T*)(ident ? d.v0l : s->v0) + off;
       T* __restrict__ y0 = (T*)(ident ? d.y0l : s->y0) + off;
+      // per-row bound vectors (padded like y)
+      const T* __restrict__ lov = (!ident && s->lov) ? (const T*)s->lov + off : nullptr;
+      const T* __restrict__ hiv = (!ident && s->hiv) ? (const T*)s->hiv + off : nullptr;
       for (int base = it.begin; base < end; base += kSB * W) {
         const int P0 = base + (int)threadIdx.x * W;
         GLane L{};
@@ -1041,14 +1046,24 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
           if (dots) group_diff<T>(xr, L, lane, g, d, of, axis, s0, ok0);
         }
         if (full) {
-          T yo[W], vo[W], yn[W], vn[W], mv[W];
+          T yo[W], vo[W], yn[W], vn[W], mv[W], lb[W], ub[W];
           ld16<T>(y + P0, yo);
           ld16<T>(v + P0, vo);
           if (ident) ld16<T>(m + P0, mv);
+          if (lov) ld16<T>(lov + P0, lb);
+          else {
+#pragma unroll
+            for (int e = 0; e < W; ++e) lb[e] = U.lo;
+          }
+          if (hiv) ld16<T>(hiv + P0, ub);
+          else {
+#pragma unroll
+            for (int e = 0; e < W; ++e) ub[e] = U.hi;
+          }
           T xbv[W];
 #pragma unroll
           for (int e = 0; e < W; ++e) {
-            if (ok[e]) proj_point<T>(U, sv[e], yo[e], vo[e], ident ? mv[e] : (T)0, yn[e], vn[e], xbv[e]);
+            if (ok[e]) proj_point<T>(U, sv[e], yo[e], vo[e], ident ? mv[e] : (T)0, lb[e], ub[e], yn[e], vn[e], xbv[e]);
             else { yn[e] = yo[e]; vn[e] = vo[e]; xbv[e] = 0; }
           }
           st16<T>(y + P0, yn);
@@ -1081,7 +1096,7 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
 #pragma unroll
             for (int e = 0; e < W; ++e) {
               if (!ok[e]) continue;
-              const T pc = sv[e] < U.lo ? U.lo : (sv[e] > U.hi ? U.hi : sv[e]);
+              const T pc = sv[e] < lb[e] ? lb[e] : (sv[e] > ub[e] ? ub[e] : sv[e]);
               const acc_t ee = (acc_t)sv[e] - (acc_t)pc;
               acc[6] += ee * ee;
               acc[7] += (acc_t)sv[e] * (acc_t)sv[e];
@@ -1096,8 +1111,9 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
             T sp;
             if (!comp_value<T>(x, P, axis, iz, iy, ix, g, d, sp)) continue;
             const T yo = y[P], vo = v[P];
+            const T lbp = lov ? lov[P] : U.lo, ubp = hiv ? hiv[P] : U.hi;
             T yn, vn, xb;
-            proj_point<T>(U, sp, yo, vo, ident ? m[P] : (T)0, yn, vn, xb);
+            proj_point<T>(U, sp, yo, vo, ident ? m[P] : (T)0, lbp, ubp, yn, vn, xb);
             y[P] = yn;
             v[P] = vn;
             if (adapt) {
@@ -1117,7 +1133,7 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
               y0[P] = yn;
             }
             if (check && !ident) {
-              const T pc = sp < U.lo ? U.lo : (sp > U.hi ? U.hi : sp);
+              const T pc = sp < lbp ? lbp : (sp > ubp ? ubp : sp);
               const acc_t ee = (acc_t)sp - (acc_t)pc;
               acc[6] += ee * ee;
               acc[7] += (acc_t)sp * (acc_t)sp;
@@ -1228,6 +1244,8 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, c
   const int call = adapt ? adapt_call(k, o) : 0;
   const SetDesc& s = d.sets[it.set];
   const bool l1 = s.kind == SIP_SET_L1;
+  // l2 ball / annulus: no histogram, ||w||^2 into slot 6 of the partials
+  const bool l2k = s.kind == SIP_SET_L2 || s.kind == SIP_SET_ANNULUS;
   for (int b = threadIdx.x; b < kNB; b += kSB) { hc[b] = 0; hs[b] = 0; }
   __syncthreads();
   const Geo g(d);
@@ -1246,6 +1264,10 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, c
   acc_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int end = it.begin + it.len;
   auto bin = [&](T val) {
+    if (l2k) {
+      acc[6] += (acc_t)val * (acc_t)val;
+      return;
+    }
     const typename KT::K key = KT::key(val);
     const int bkt = (int)(key >> sh0);
     atomicAdd(&hc[bkt], 1u);
@@ -1254,6 +1276,12 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, c
   // a group's values, runs of equal buckets merged into one update (the
   // bucket sums of float keys are exact, so the merge changes no result)
   auto bin_group = [&](const T (&v)[W], const bool (&ok)[W]) {
+    if (l2k) {
+#pragma unroll
+      for (int e = 0; e < W; ++e)
+        if (ok[e]) acc[6] += (acc_t)v[e] * (acc_t)v[e];
+      return;
+    }
     int cur = -1;
     uint32_t n = 0;
     acc_t sum = 0;
@@ -1483,7 +1511,8 @@ __device__ void finish_selection(SelState& st, const SetDesc& s, unsigned long l
 // Stage 1: totals, mode, first digit.  Clears the global histogram for the
 // refine pass.  The state is worked on in LDS and written back once.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const SelItem* __restrict__ items, Opts o) {
+__global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const SelItem* __restrict__ items, Opts o,
+                                                 const double* __restrict__ thrw_parts) {
   using KT = KeyT<T>;
   __shared__ uint32_t hc[kNB];
   __shared__ acc_t hs[kNB];
@@ -1500,6 +1529,32 @@ __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D,
   const int k = (int)S[S_K];
   if (si.src == 1 && !is_check_iter(k, o)) return;
   const SetDesc& s = d.sets[si.set];
+  if (s.kind == SIP_SET_L2 || s.kind == SIP_SET_ANNULUS) {
+    // ||w||^2 (pipeline 0) from the w pass's per-item partials in item order;
+    // the projection is a scaling (or, for an annulus at w = 0, a point)
+    acc_t n2[1];
+    reduce_range<1>(thrw_parts, s.item_begin[si.src], s.item_end[si.src], kThrParts, si.src == 0 ? 6 : 7, n2, lds);
+    if (threadIdx.x == 0) {
+      SelState q{};
+      q.final_ = 1;
+      q.mode = SEL_INSIDE;
+      const double sq = (double)n2[0];
+      if (!(sq <= 1.0e300)) q.err = SIP_ENUMERIC;
+      const double nrm = sqrt(sq);
+      if (si.src == 0 && !q.err) {
+        if (s.kind == SIP_SET_L2) {
+          if (nrm > s.tau) { q.mode = SEL_PROJECT; q.theta = s.tau / nrm; }
+        } else if (nrm > s.hi) {
+          q.mode = SEL_PROJECT; q.theta = s.hi / nrm;
+        } else if (nrm < s.lo) {
+          if (nrm > 0.0) { q.mode = SEL_PROJECT; q.theta = s.lo / nrm; }
+          else q.mode = SEL_POINT;
+        }
+      }
+      *s.sel[si.src] = q;
+    }
+    return;
+  }
   const bool l1 = s.kind == SIP_SET_L1;
   uint32_t* gc = s.hcnt[si.src];
   acc_t* gs = (acc_t*)s.hsum[si.src];
@@ -1861,6 +1916,10 @@ __global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ 
   const SelState& st = *s.sel[it.src];
   if (st.err) return;
   const bool l1 = s.kind == SIP_SET_L1;
+  // l2 ball / annulus: y = theta w, w, or the point lo e_0; their distance
+  // on stopping-test iterations follows from ||s|| alone (k_finish)
+  const bool l2k = s.kind == SIP_SET_L2 || s.kind == SIP_SET_ANNULUS;
+  if (l2k && it.src == 1) return;
   const int mode = st.mode;
   const Geo g(d);
   const bool grouped = item_grouped(d);
@@ -1869,6 +1928,12 @@ __global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ 
   const double rho_d = S[S_RHO + it.set];
   const T rho = (T)rho_d;
   const T theta = (T)st.theta;
+  const T lo_r = (T)s.lo;
+  auto l2_prox = [&](T we, int P, int c) -> T {
+    if (mode == SEL_PROJECT) return theta * we;
+    if (mode == SEL_POINT) return (P == 0 && c == 0) ? lo_r : (T)0;
+    return we;
+  };
   const K tkey = (K)st.tkey;
   const bool rank_ties = (!l1) && mode == SEL_PROJECT && st.need_ties && it.src == 0;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1932,7 +1997,9 @@ __global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ 
           for (int e = 0; e < W; ++e) {
             T r = w[e];
             if (ok[e]) {
-              if (l1) {
+              if (l2k) {
+                r = l2_prox(w[e], P0 + e, c);
+              } else if (l1) {
                 if (mode == SEL_PROJECT) {
                   const T a = (w[e] < 0 ? -w[e] : w[e]) - theta;
                   r = a > 0 ? (w[e] < 0 ? -a : a) : (T)0;
@@ -1987,7 +2054,9 @@ __global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ 
           if (!comp_valid(axis, iz, iy, ix, g)) continue;
           const T we = y[P];
           T r = we;
-          if (l1) {
+          if (l2k) {
+            r = l2_prox(we, P, c);
+          } else if (l1) {
             if (mode == SEL_PROJECT) {
               const T a = (we < 0 ? -we : we) - theta;
               r = a > 0 ? (we < 0 ? -a : a) : (T)0;
@@ -2182,6 +2251,13 @@ __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* __restrict__ 
       double num = dots[u][6];
       const double den = dots[u][7];
       const SetDesc& s = d.sets[u];
+      if (s.kind == SIP_SET_L2 || s.kind == SIP_SET_ANNULUS) {
+        // distance of s to the ball / shell from ||s|| (= sqrt(den)) alone
+        const double nrm = sqrt(den);
+        const double lo = s.kind == SIP_SET_L2 ? 0.0 : s.lo, hi = s.kind == SIP_SET_L2 ? s.tau : s.hi;
+        const double t = nrm < lo ? lo : (nrm > hi ? hi : nrm);
+        num = (nrm - t) * (nrm - t);
+      }
       if (s.thr >= 0 && s.kind == SIP_SET_CARD && s.sel[1]->mode == SEL_PROJECT) {
         // the dropped entries equal to the k-th magnitude all have that magnitude
         const SelState& q = *s.sel[1];
@@ -2284,7 +2360,7 @@ void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
   }
   if (t.nthr > 0) {
     k_thr_w<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thrw_part);
-    k_sel1<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o);
+    k_sel1<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, t.thrw_part);
     k_thr_refine<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, 0);
     k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 0);
     k_thr_refine<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, 1);

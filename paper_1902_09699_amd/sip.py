@@ -21,7 +21,7 @@ MAX_SETS = 16
 OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED, EBUDGET = 0, -1, -2, -3, -4, -5, -6
 F32, F64 = 0, 1
 OPS = {"I": 0, "DZ": 1, "DY": 2, "DX": 3, "GRAD": 4, "LAT": 5}
-KINDS = {"bounds": 0, "l1": 1, "card": 2}
+KINDS = {"bounds": 0, "l1": 1, "card": 2, "l2": 3, "annulus": 4}
 K_RHS, K_CG_DIR, K_CG_UPD, K_PROJ, K_THR_W, K_THR_APPLY = range(6)
 FIELD_Y, FIELD_V, FIELD_VHAT0, FIELD_V0, FIELD_Y0, FIELD_R, FIELD_XS0, FIELD_XS1 = range(8)
 
@@ -32,7 +32,7 @@ class Grid(C.Structure):
 
 class Set(C.Structure):
     _fields_ = [("kind", C.c_int32), ("op", C.c_int32), ("lo", C.c_double), ("hi", C.c_double),
-                ("tau", C.c_double), ("k", C.c_int64)]
+                ("tau", C.c_double), ("k", C.c_int64), ("lo_vec", C.c_void_p), ("hi_vec", C.c_void_p)]
 
 
 class Opts(C.Structure):
@@ -158,6 +158,14 @@ def make_set(d: dict) -> Set:
     s.hi = float(d.get("hi", math.inf))
     s.tau = float(d.get("tau", 0.0))
     s.k = int(d.get("k", 0))
+    # per-row bound vectors: device tensors of the field type, one block of N
+    # per operator component (the grid layout of the operator's rows)
+    for key in ("lo_vec", "hi_vec"):
+        t = d.get(key)
+        if t is not None:
+            if not t.is_contiguous():
+                raise ValueError(f"{key}: contiguous device tensor expected")
+            setattr(s, key, C.c_void_p(t.data_ptr()))
     return s
 
 
@@ -254,9 +262,9 @@ def level(shape, sets, lev, h=None):
     for i, d in enumerate(sets):
         e = dict(d)
         e.update(kind=inv_k[out[i].kind], op=inv_o[out[i].op])
-        if e["kind"] == "bounds":
+        if e["kind"] in ("bounds", "annulus"):
             e.update(lo=out[i].lo, hi=out[i].hi)
-        elif e["kind"] == "l1":
+        elif e["kind"] in ("l1", "l2"):
             e["tau"] = out[i].tau
         else:
             e["k"] = int(out[i].k)

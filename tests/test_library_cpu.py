@@ -5,6 +5,7 @@ import math
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1902_09699_amd import sip
@@ -120,3 +121,27 @@ def test_level_grids_and_sets_match_oracle(L, shape, nlev):
                 assert a["k"] == b["k"]
             else:
                 assert (a["lo"], a["hi"]) == (b["lo"], b["hi"])
+
+
+@pytest.mark.parametrize("s,ok", [
+    ({"kind": "l2", "op": "GRAD", "tau": 1.0}, True),
+    ({"kind": "l2", "op": "GRAD", "tau": -1.0}, False),
+    ({"kind": "annulus", "op": "I", "lo": 0.5, "hi": 2.0}, True),
+    ({"kind": "annulus", "op": "I", "lo": 2.0, "hi": 0.5}, False),
+    ({"kind": "annulus", "op": "I", "lo": -0.1, "hi": 0.5}, False),
+    ({"kind": "annulus", "op": "I", "lo": 0.0, "hi": np.inf}, True),
+])
+def test_validation_l2_and_annulus(L, s, ok):
+    assert (sip.validate((8, 9), [s], sip.make_opts()) == 0) == ok
+
+
+def test_bound_vectors_only_for_bounds(L):
+    """A bound-vector pointer on a non-bounds set is rejected (validation
+    only reads the pointer's presence)."""
+    g = sip.make_grid((8, 9))
+    arr = sip.make_sets([{"kind": "l1", "op": "DX", "tau": 1.0}])
+    arr[0].lo_vec = 16  # any non-null address
+    assert sip.lib().sip_validate(sip.C.byref(g), arr, 1, sip.C.byref(sip.make_opts())) == sip.EINVAL
+    arr = sip.make_sets([{"kind": "bounds", "op": "DX", "lo": -1.0, "hi": 1.0}])
+    arr[0].hi_vec = 16
+    assert sip.lib().sip_validate(sip.C.byref(g), arr, 1, sip.C.byref(sip.make_opts())) == 0
