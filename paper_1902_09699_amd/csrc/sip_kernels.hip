@@ -94,10 +94,46 @@ __device__ __forceinline__ void reduce_range(const double* __restrict__ parts, i
 // Sum of parts[begin .. end) computed by every wave on its own (lanes stride
 // the range, then the butterfly): no LDS, no barrier, and the same order, so
 // the same value, in every wave of every block.
-__device__ __forceinline__ acc_t wave_reduce(const double* __restrict__ parts, int begin, int end) {
+// The first kPre partials of each lane are loaded by part_issue without any
+// wait, so these loads fly together with a kernel's other first loads;
+// part_finish adds them, then any further ones, in index order.
+constexpr int kPre = 8;
+
+__device__ __forceinline__ double ldgd(const double* p) {
+  return *(__attribute__((address_space(1))) const double*)p;
+}
+
+__device__ __forceinline__ void part_issue(const double* __restrict__ parts, int begin, int end,
+                                           double (&pre)[kPre]) {
+  // every lane loads (an index past the range reads entry begin, whose value
+  // is then dropped), so no load sits behind a branch
+  const int i0 = begin + (int)(threadIdx.x & 63);
+  if (end <= begin) {
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) pre[k] = 0.0;
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < kPre; ++k) {
+    const int i = i0 + 64 * k;
+    const double v = ldgd(parts + (i < end ? i : begin));
+    pre[k] = i < end ? v : 0.0;
+  }
+}
+
+__device__ __forceinline__ acc_t part_finish(const double* __restrict__ parts, int begin, int end,
+                                             const double (&pre)[kPre]) {
   acc_t t = 0;
-  for (int i = begin + (int)(threadIdx.x & 63); i < end; i += 64) t += (acc_t)parts[i];
+#pragma unroll
+  for (int k = 0; k < kPre; ++k) t += (acc_t)pre[k];
+  for (int i = begin + (int)(threadIdx.x & 63) + 64 * kPre; i < end; i += 64) t += (acc_t)ldgd(parts + i);
   return wave_sum(t);
+}
+
+__device__ __forceinline__ acc_t wave_reduce(const double* __restrict__ parts, int begin, int end) {
+  double pre[kPre];
+  part_issue(parts, begin, end, pre);
+  return part_finish(parts, begin, end, pre);
 }
 
 // Block total of one double, valid in thread 0 only (one barrier; lds must
@@ -174,6 +210,29 @@ __device__ __forceinline__ T apply_C(F f, T fc, int P, int iz, int iy, int ix, c
 }
 
 __device__ __forceinline__ bool inst_live(const double* S) { return S[S_STATE] == 0.0 && S[S_ERR] == 0.0; }
+
+// The scalars the RHS and CG kernels read, loaded together at kernel start
+// (one round trip instead of one per use).
+struct CgScal {
+  double c0, cax[3], rr[2], done[2], rr0, state, err;
+  __device__ __forceinline__ bool live() const { return state == 0.0 && err == 0.0; }
+  // by step parity (selects, not an indexed access, so the block stays in registers)
+  __device__ __forceinline__ double rr_at(int j) const { return (j & 1) ? rr[1] : rr[0]; }
+  __device__ __forceinline__ double done_at(int j) const { return (j & 1) ? done[1] : done[0]; }
+};
+
+__device__ __forceinline__ CgScal cg_scal(const double* S) {
+  CgScal q;
+  q.c0 = ldgd(S + S_C0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) q.cax[a] = ldgd(S + S_CAX + a);
+#pragma unroll
+  for (int a = 0; a < 2; ++a) { q.rr[a] = ldgd(S + S_RR + a); q.done[a] = ldgd(S + S_DONE + a); }
+  q.rr0 = ldgd(S + S_RR0);
+  q.state = ldgd(S + S_STATE);
+  q.err = ldgd(S + S_ERR);
+  return q;
+}
 
 __device__ __forceinline__ bool is_adapt_iter(int k, const Opts& o) {
   return o.adapt_every > 0 && (k % o.adapt_every) == (1 % o.adapt_every);
@@ -707,15 +766,18 @@ __global__ __launch_bounds__(NT) void k_cg_dir(const InstDesc* __restrict__ D, c
   const PtItem it = items[iti];
   const InstDesc& d = D[it.inst];
   double* S = d.scal;
-  if (!inst_live(S)) return;
-  const double rr = wave_reduce(rr_part, d.pt_begin, d.pt_end);
+  const CgScal q = cg_scal(S);
+  double pre[kPre];
+  part_issue(rr_part, d.pt_begin, d.pt_end, pre);
+  if (!q.live()) return;
+  const double rr = part_finish(rr_part, d.pt_begin, d.pt_end, pre);
   bool done;
   double beta = 0.0;
   if (j == 0) {
     done = !(rr > 0.0);
   } else {
-    done = S[S_DONE + ((j - 1) & 1)] != 0.0 || !(rr > 0.0) || (!o.cg_fixed && rr < o.cg_rel2 * S[S_RR0]);
-    beta = rr / S[S_RR + ((j - 1) & 1)];
+    done = q.done_at(j - 1) != 0.0 || !(rr > 0.0) || (!o.cg_fixed && rr < o.cg_rel2 * q.rr0);
+    beta = rr / q.rr_at(j - 1);
   }
   const bool bad = !(rr <= 1.0e300) || rr != rr;  // non-finite residual
   if (iti == d.pt_begin && threadIdx.x == 0) {
@@ -729,7 +791,7 @@ __global__ __launch_bounds__(NT) void k_cg_dir(const InstDesc* __restrict__ D, c
   const T* r = (const T*)d.r;
   const T* pin = (const T*)d.p[(j + 1) & 1];
   T* pout = (T*)d.p[j & 1];
-  const double cf[4] = {S[S_C0], S[S_CAX + 0], S[S_CAX + 1], S[S_CAX + 2]};
+  const double cf[4] = {q.c0, q.cax[0], q.cax[1], q.cax[2]};
   acc_t acc;
   if (j == 0) {
     const Src<T, 1> f{{r}, (T)0};
@@ -754,20 +816,23 @@ __global__ __launch_bounds__(NT) void k_cg_upd(const InstDesc* __restrict__ D, c
   const PtItem it = items[iti];
   const InstDesc& d = D[it.inst];
   double* S = d.scal;
-  if (!inst_live(S)) return;
-  if (S[S_DONE + (j & 1)] != 0.0) return;
-  const double pq = wave_reduce(pq_part, d.pt_begin, d.pt_end);
+  const CgScal qs = cg_scal(S);
+  double pre[kPre];
+  part_issue(pq_part, d.pt_begin, d.pt_end, pre);
+  if (!qs.live()) return;
+  if (qs.done_at(j) != 0.0) return;
+  const double pq = part_finish(pq_part, d.pt_begin, d.pt_end, pre);
   if (!(pq > 0.0) || !(pq <= 1.0e300)) {
     if (iti == d.pt_begin && threadIdx.x == 0) S[S_ERR] = (double)SIP_ENUMERIC;
     return;
   }
-  const double alpha = S[S_RR + (j & 1)] / pq;
+  const double alpha = qs.rr_at(j) / pq;
   if (iti == d.pt_begin && threadIdx.x == 0) S[S_CGTOT] += 1.0;
   const Geo g(d);
   T* x = (T*)d.x;
   T* r = (T*)d.r;
   const T* p = (const T*)d.p[j & 1];
-  const T c0 = (T)S[S_C0], cz = (T)S[S_CAX + 0], cy = (T)S[S_CAX + 1], cx = (T)S[S_CAX + 2];
+  const T c0 = (T)qs.c0, cz = (T)qs.cax[0], cy = (T)qs.cax[1], cx = (T)qs.cax[2];
   const T al = (T)alpha;
   auto fs = [&](int Q) -> T { return p[Q]; };
   const Src<T, 1> f{{p}, (T)0};
@@ -828,14 +893,15 @@ __global__ __launch_bounds__(NT) void k_rhs(const InstDesc* __restrict__ D, cons
   const PtItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
-  if (!inst_live(S)) return;
+  const CgScal qs = cg_scal(S);
+  const T rl = (T)ldgd(S + S_RHO + d.nsets);
+  if (!qs.live()) return;
   const Geo g(d);
   const T* x = (const T*)d.x;
   T* r = (T*)d.r;
   const T* yl = (const T*)d.yl;
   const T* vl = (const T*)d.vl;
-  const T rl = (T)S[S_RHO + d.nsets];
-  const T c0 = (T)S[S_C0], cz = (T)S[S_CAX + 0], cy = (T)S[S_CAX + 1], cx = (T)S[S_CAX + 2];
+  const T c0 = (T)qs.c0, cz = (T)qs.cax[0], cy = (T)qs.cax[1], cx = (T)qs.cax[2];
   const int lane = threadIdx.x & 63;
   auto fs = [&](int Q) -> T { return x[Q]; };
   const Src<T, 1> fx{{x}, (T)0};
@@ -860,7 +926,7 @@ __global__ __launch_bounds__(NT) void k_rhs(const InstDesc* __restrict__ D, cons
       }
       for (int si = 0; si < d.nsets; ++si) {
         const SetDesc& s = d.sets[si];
-        const T rs = (T)S[S_RHO + si];
+        const T rs = (T)ldgd(S + S_RHO + si);
         for (int c = 0; c < s.ncomp; ++c) {
           // u = v + rho y
           const Src<T, 2> fu{{(const T*)s.v + (size_t)c * g.cs, (const T*)s.y + (size_t)c * g.cs}, rs};
@@ -929,7 +995,7 @@ __global__ __launch_bounds__(NT) void k_rhs(const InstDesc* __restrict__ D, cons
         T bb = rl * yl[P] + vl[P];
         for (int si = 0; si < d.nsets; ++si) {
           const SetDesc& s = d.sets[si];
-          const T rs = (T)S[S_RHO + si];
+          const T rs = (T)ldgd(S + S_RHO + si);
           for (int c = 0; c < s.ncomp; ++c) {
             const T* y = (const T*)s.y + (size_t)c * g.cs;
             const T* v = (const T*)s.v + (size_t)c * g.cs;
@@ -2180,7 +2246,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const int32_t* __restrict__ insts, Opts o,
                                                    const double* proj_parts, const double* thrw_parts,
                                                    const double* thra_parts) {
-  __shared__ acc_t lds[lds_sum<8>()];
+  __shared__ acc_t tout[4 * kMaxUnits + 2][8];
   __shared__ acc_t dots[kMaxUnits][8];
   __shared__ acc_t evol[16];
   if ((int)blockIdx.x >= cnt->ninst) return;
@@ -2196,49 +2262,82 @@ __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* __restrict__ 
   const bool check = is_check_iter(k, o);
   const int p = d.nsets;
   int err = 0;
-  if (adapt || check) {
-    for (int u = 0; u <= p; ++u) {
-      const bool thr = u < p && d.sets[u].thr >= 0;
-      acc_t v[8];
-      if (!thr) {
-        reduce_range<8>(proj_parts, d.sp_begin, d.sp_end, kProjParts, u * kUnitParts, v, lds);
+  // Every sum this kernel needs is a task: 8 consecutive per-item partial
+  // values summed over an item range (a projection unit's dots; a threshold
+  // set's w-pass and apply-pass dots, per pipeline; the evolution sums).
+  // Each wave takes whole tasks (lanes stride the items, then a butterfly), so
+  // all sums run at once with no barrier; the same order, so the same value,
+  // as any other wave would produce.
+  const int ntask_units = (adapt || check) ? p + 1 : 0;
+  auto unit_tasks = [&](int u) -> int { return (u < p && d.sets[u].thr >= 0) ? (check ? 4 : 2) : 1; };
+  int ntasks = 0;
+  for (int u = 0; u < ntask_units; ++u) ntasks += unit_tasks(u);
+  const bool evol_on = check && d.ring;
+  if (evol_on) ntasks += 2;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int t = wv; t < ntasks; t += kBlock / 64) {
+    // locate task t
+    const double* parts = proj_parts;
+    int b = d.sp_begin, e = d.sp_end, stride = kProjParts, off = 0;
+    int rem = t, u = 0;
+    for (; u < ntask_units; ++u) {
+      const int nt = unit_tasks(u);
+      if (rem < nt) break;
+      rem -= nt;
+    }
+    if (u < ntask_units) {
+      if (unit_tasks(u) == 1 && !(u < p && d.sets[u].thr >= 0)) {
+        off = u * kUnitParts;
       } else {
-        const SetDesc& s = d.sets[u];
-        acc_t a[8], b[8];
-        reduce_range<8>(thrw_parts, s.item_begin[0], s.item_end[0], kThrParts, 0, a, lds);
-        reduce_range<8>(thra_parts, s.item_begin[0], s.item_end[0], kThrParts, 0, b, lds);
-        for (int j = 0; j < 3; ++j) { v[j] = a[j]; v[3 + j] = b[3 + j]; }
-        v[6] = v[7] = 0;
-        if (check) {
-          reduce_range<8>(thrw_parts, s.item_begin[1], s.item_end[1], kThrParts, 0, a, lds);
-          reduce_range<8>(thra_parts, s.item_begin[1], s.item_end[1], kThrParts, 0, b, lds);
-          v[6] = b[6];
-          v[7] = a[7];
-        }
+        const SetDesc& sd = d.sets[u];
+        const int src = rem >> 1;
+        parts = (rem & 1) ? thra_parts : thrw_parts;
+        b = sd.item_begin[src];
+        e = sd.item_end[src];
+        stride = kThrParts;
       }
-      if (threadIdx.x == 0) {
+    } else {
+      off = kEvolOff + 8 * rem;
+    }
+    acc_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i = b + lane; i < e; i += 64) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) dots[u][j] = v[j];
-      }
+      for (int j = 0; j < 8; ++j) v[j] += (acc_t)parts[(size_t)i * stride + off + j];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = wave_sum(v[j]);
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) tout[t][j] = v[j];
     }
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
+    int t = 0;
+    for (int u = 0; u < ntask_units; ++u) {
+      if (!(u < p && d.sets[u].thr >= 0)) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) dots[u][j] = tout[t][j];
+        t += 1;
+      } else {
+        // w pass: dh dots in 0..2, ||s||^2 in 7 (pipeline 1); apply pass:
+        // dg/dv dots in 3..5, the feasibility distance in 6 (pipeline 1)
+        for (int j = 0; j < 3; ++j) { dots[u][j] = tout[t][j]; dots[u][3 + j] = tout[t + 1][3 + j]; }
+        dots[u][6] = check ? tout[t + 3][6] : (acc_t)0;
+        dots[u][7] = check ? tout[t + 2][7] : (acc_t)0;
+        t += check ? 4 : 2;
+      }
+    }
+    if (evol_on) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) { evol[j] = tout[t][j]; evol[8 + j] = tout[t + 1][j]; }
+    }
     for (int u = 0; u < p; ++u) {
       if (d.sets[u].thr < 0) continue;
       if (d.sets[u].sel[0]->err) err = d.sets[u].sel[0]->err;
       if (check && d.sets[u].sel[1]->err) err = d.sets[u].sel[1]->err;
     }
   }
-  if (check && d.ring) {
-    acc_t v[8], w[8];
-    reduce_range<8>(proj_parts, d.sp_begin, d.sp_end, kProjParts, kEvolOff, v, lds);
-    reduce_range<8>(proj_parts, d.sp_begin, d.sp_end, kProjParts, kEvolOff + 8, w, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) { evol[j] = v[j]; evol[8 + j] = w[j]; }
-    }
-  }
-  __syncthreads();
   if (threadIdx.x != 0) return;
   if (err) { S[S_ERR] = (double)err; S[S_STATE] = 3.0; return; }
   if (d.log && k <= d.log_cap) {
