@@ -39,14 +39,13 @@ def parse():
     ap.add_argument("--batched-count", type=int, default=256)
     ap.add_argument("--copy-mb", type=int, default=1024, help="plain-copy reference size (0: skip)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles")
-    ap.add_argument("--autotune", action="store_true",
-                    help="autotune single-instance workloads too (the batched workload always is)")
     ap.add_argument("--reduce", default="f64", choices=("f64", "f32"),
                     help="reduction type (f32: the pure-FP32 precision ablation)")
     ap.add_argument("--check-iters", type=int, default=10,
                     help="iterations of the schedule-locked error check against the oracle (0: skip)")
     ap.add_argument("--tiles", default=None,
-                    help="fixed tiles pt_points,pt_max_items,thr_points,thr_max_items[,pt_threads] (no autotune)")
+                    help="fixed tiles pt_points,pt_max_items,thr_points,thr_max_items[,pt_threads[,cg_form]] "
+                         "(no autotune)")
     return ap.parse_args()
 
 
@@ -84,12 +83,13 @@ def rows(shape, s):
 def algorithmic_bytes(insts, esz):
     """Compulsory bytes of one launch of each kernel (all instances):
     CG direction: read r, p, write p (3N); CG update: read x, r, p, write x, r
-    (5N); RHS: read x and every y_i, v_i (identity block included), write r;
+    (5N); one-reduction CG step: read x, p, r, w, s, write all five (10N);
+    its w_0 pass: read r, write w (2N); RHS: read x and every y_i, v_i (identity block included), write r;
     projection (non-adapt iteration): read x, m, y_i, v_i of the bounds sets
     and the identity block, write y_i, v_i; threshold w pass: read x, y_i,
     v_i, write w over y_i (N + 3 M_i per l1 / cardinality set); threshold
     apply pass: read w, write y_i, v_i (3 M_i)."""
-    b = {"cg_dir": 0, "cg_upd": 0, "rhs": 0, "proj": 0, "thr_w": 0, "thr_apply": 0}
+    b = {"cg_dir": 0, "cg_upd": 0, "cg1_step": 0, "cg1_w0": 0, "rhs": 0, "proj": 0, "thr_w": 0, "thr_apply": 0}
     for m, sets in insts:
         N = m.size
         sum_m = N + sum(rows(m.shape, s) for s in sets)
@@ -97,6 +97,8 @@ def algorithmic_bytes(insts, esz):
         thr = [rows(m.shape, s) for s in sets if s["kind"] != "bounds"]
         b["cg_dir"] += 3 * N * esz
         b["cg_upd"] += 5 * N * esz
+        b["cg1_step"] += 10 * N * esz
+        b["cg1_w0"] += 2 * N * esz
         b["rhs"] += (2 * N + 2 * sum_m) * esz
         b["proj"] += (2 * N + 4 * clip) * esz
         b["thr_w"] += sum(N + 3 * mi for mi in thr) * esz
@@ -125,9 +127,10 @@ def traffic_from_profiles(kernel, wname):
     return d.get("hbm_bytes_per_launch")
 
 
-def device_reference(inst, field, reduce, iters):
+def device_reference(inst, field, reduce, iters, tiles=None):
     """The first instance alone on the device for `iters` iterations with the
-    (rho, gamma) schedule logged: its x and the schedule."""
+    (rho, gamma) schedule logged (tiles and CG form as timed): its x and the
+    schedule."""
     import torch
     from paper_1902_09699_amd import sip
     m, sets = inst
@@ -135,6 +138,8 @@ def device_reference(inst, field, reduce, iters):
     md = torch.tensor(m, dtype=torch.float64 if field == "f64" else torch.float32, device="cuda")
     xd = torch.empty_like(md)
     b = sip.Batch(1, sip.workspace_bytes(m.shape, sets, opts), opts)
+    if tiles:
+        b.set_tiles(*tiles)
     slot = b.add(md, sets, xd)
     b.run(iters)
     rho, gam = b.schedule(slot, iters)
@@ -222,10 +227,12 @@ def main():
     if args.tiles:
         tiles = tuple(int(v) for v in args.tiles.split(","))
         batch.set_tiles(*tiles)
-    elif not args.no_autotune and (args.workload == "batched" or args.autotune):
+    elif not args.no_autotune:
         from paper_1902_09699_amd import autotune
         tiles, tile_ms = autotune.tune(batch, slots, ms, field, [m.shape for m, _ in insts], use_cache=False,
                                        cache=None)
+        for cand, t in sorted(tile_ms.items(), key=lambda kv: kv[1])[:6]:
+            print(f"autotune {cand}: {1e3 * t:.1f} us/iteration", file=sys.stderr, flush=True)
 
     def one_step():
         for sl, md in zip(slots, ms):
@@ -256,9 +263,14 @@ def main():
         r_, g_, _, _ = batch.get_params(sl)
         batch.set_params(sl, r_, g_, 2, True)
     ab = algorithmic_bytes(insts, esz)
-    ids = {"cg_dir": sip.K_CG_DIR, "cg_upd": sip.K_CG_UPD, "rhs": sip.K_RHS, "proj": sip.K_PROJ,
-           "thr_w": sip.K_THR_W, "thr_apply": sip.K_THR_APPLY}
-    per_iter = {"cg_dir": 10, "cg_upd": 10, "rhs": 1, "proj": 1, "thr_w": 1, "thr_apply": 1}
+    one_red = bool(tiles) and len(tiles) > 5 and tiles[5] == 1
+    if one_red:
+        ids = {"cg1_step": sip.K_CG1_STEP, "cg1_w0": sip.K_CG1_W0}
+    else:
+        ids = {"cg_dir": sip.K_CG_DIR, "cg_upd": sip.K_CG_UPD}
+    ids.update({"rhs": sip.K_RHS, "proj": sip.K_PROJ, "thr_w": sip.K_THR_W, "thr_apply": sip.K_THR_APPLY})
+    per_iter = {"cg_dir": 10, "cg_upd": 10, "cg1_step": 10, "cg1_w0": 1, "rhs": 1, "proj": 1, "thr_w": 1,
+                "thr_apply": 1}
     kernels = {}
     for name, kid in ids.items():
         if ab[name] == 0:
@@ -295,7 +307,7 @@ def main():
         sched, chk = None, None
         kc = min(args.check_iters, iters)
         if kc > 0:
-            xr, sched = device_reference(insts[0], field, args.reduce, kc)
+            xr, sched = device_reference(insts[0], field, args.reduce, kc, tiles)
             chk = (kc, xr)
         cpu, err = cpu_baseline(insts, iters, args.cpu_seconds, sched, chk)
         if chk is not None:

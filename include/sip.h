@@ -204,7 +204,9 @@ int32_t sip_batch_result(sip_batch* b, int32_t slot, sip_result* res, void* stre
 /* Device arrays of a slot's state for export/import by the caller (same
  * stream ordering rules as any device memory).  which: 0 y_i, 1 v_i,
  * 2 vhat snapshot, 3 v snapshot, 4 y snapshot (i = nsets means the identity
- * block p+1); 5 r, 6 x-snapshot buffer 0, 7 x-snapshot buffer 1.  Set
+ * block p+1); 5 r (the CG residual buffer; with cg_form 1 it holds the
+ * warm-start residual or that of an even step), 6 x-snapshot buffer 0,
+ * 7 x-snapshot buffer 1.  Set
  * arrays hold one block per operator component (z, y, x order), block c
  * starting at element c * comp_stride (comp_stride >= N, 256-byte aligned);
  * the first N entries of a block are the grid points, the unused last layer
@@ -228,13 +230,19 @@ int32_t sip_batch_schedule(sip_batch* b, int32_t slot, double* rho, double* gamm
 /* Work decomposition: grid points per item of the point kernels (RHS, CG,
  * projection) and of the threshold-set kernels, each a multiple of 256, and
  * grown when an instance would need more than max_items items; pt_threads
- * (256 or 512) is the block size of the RHS and CG kernels.  Results are
- * bit-identical for any batch composition at fixed tile settings.  Applies
- * from the next sip_batch_run.  Defaults 2048/512, 2048/512, 512 threads.
- * SIP_EINVAL for sizes that are not multiples of 256, max_items < 1 or
- * another thread count. */
+ * (256 or 512) is the block size of the RHS and CG kernels.  cg_form picks
+ * the arrangement of the CG steps of the x-minimization (section "Solving the
+ * linear system"): 0 the textbook form, two launches and two inner-product
+ * reductions per step; 1 Chronopoulos and Gear's one-reduction form, one
+ * launch per step (the same iterates in exact arithmetic, different
+ * rounding; 10 instead of 8 vectors of traffic per step, fewer launches: it
+ * pays on grids too small to keep the GPU busy).  Results are bit-identical
+ * for any batch composition at fixed tile settings.  Applies from the next
+ * sip_batch_run.  Defaults 2048/512, 2048/512, 512 threads, form 0.
+ * SIP_EINVAL for sizes that are not multiples of 256, max_items < 1, another
+ * thread count or another form. */
 int32_t sip_batch_set_tiles(sip_batch* b, int32_t pt_points, int32_t pt_max_items, int32_t thr_points,
-                            int32_t thr_max_items, int32_t pt_threads);
+                            int32_t thr_max_items, int32_t pt_threads, int32_t cg_form);
 
 /* Re-initialise a slot's state from a new m of the same grid (x = m,
  * y_i = A_i m, v_i = 0, rho0/gamma0, k = 1) without touching the work tables
@@ -248,7 +256,9 @@ typedef enum {
   SIP_K_CG_UPD = 2,    /* CG x / r update + r^T r (step 1) */
   SIP_K_PROJ = 3,      /* bounds sets + identity block: relax, project, dual update */
   SIP_K_THR_W = 4,     /* threshold sets: w and the first radix histogram */
-  SIP_K_THR_APPLY = 5  /* threshold sets: apply threshold + dual update */
+  SIP_K_THR_APPLY = 5, /* threshold sets: apply threshold + dual update */
+  SIP_K_CG1_STEP = 6,  /* one-reduction CG step (step 1; run a cg_form 1 iteration first) */
+  SIP_K_CG1_W0 = 7     /* one-reduction CG: w_0 = C r_0 + r_0^T w_0 */
 } sip_kernel_id;
 
 /* Launch one kernel of the iteration `reps` times on `stream` over the

@@ -12,17 +12,23 @@ import math
 import os
 
 CANDIDATES = [
-    # (pt_points, pt_max_items, thr_points, thr_max_items, pt_threads)
-    (2048, 512, 2048, 512, 512),
-    (1024, 512, 2048, 512, 512),
-    (2048, 1024, 4096, 512, 512),
-    (4096, 512, 4096, 256, 512),
-    (4096, 1024, 8192, 512, 512),
-    (1024, 1024, 2048, 512, 256),
-    (2048, 512, 2048, 512, 256),
-    (2048, 1024, 4096, 512, 256),
-    (4096, 512, 4096, 256, 256),
-    (1024, 2048, 2048, 512, 256),
+    # (pt_points, pt_max_items, thr_points, thr_max_items, pt_threads, cg_form)
+    (2048, 512, 2048, 512, 512, 0),
+    (1024, 512, 2048, 512, 512, 0),
+    (2048, 1024, 4096, 512, 512, 0),
+    (4096, 512, 4096, 256, 512, 0),
+    (4096, 1024, 8192, 512, 512, 0),
+    (1024, 1024, 2048, 512, 256, 0),
+    (2048, 512, 2048, 512, 256, 0),
+    (2048, 1024, 4096, 512, 256, 0),
+    (4096, 512, 4096, 256, 256, 0),
+    (1024, 2048, 2048, 512, 256, 0),
+    # one launch per CG step: fewer, heavier launches
+    (2048, 512, 2048, 512, 512, 1),
+    (1024, 512, 2048, 512, 512, 1),
+    (1024, 1024, 2048, 512, 256, 1),
+    (2048, 1024, 4096, 512, 512, 1),
+    (4096, 512, 4096, 256, 512, 1),
 ]
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "sip_tiles.json")

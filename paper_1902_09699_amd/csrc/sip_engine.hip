@@ -191,7 +191,7 @@ bool is_thr(const sip_set& s) {
 // Byte layout of one instance's workspace.
 struct Layout {
   int64_t total = 0;
-  int64_t log = -1, m, r, p0, p1, yl, vl, vh0l = -1, v0l = -1, y0l = -1, xs0 = -1, xs1 = -1, ring = -1;
+  int64_t log = -1, m, r, p0, p1, cr[2], cp[2], yl, vl, vh0l = -1, v0l = -1, y0l = -1, xs0 = -1, xs1 = -1, ring = -1;
   struct SetL { int64_t y, v, vh0 = -1, v0 = -1, y0 = -1, lov = -1, hiv = -1; int64_t sel[2] = {-1, -1}, hc[2] = {-1, -1},
                 hs[2] = {-1, -1}, cand[2] = {-1, -1}; } set[SIP_MAX_SETS];
 };
@@ -207,6 +207,7 @@ Layout layout_of(const sip_grid& g, const sip_set* sets, int nsets, const sip_op
   auto take = [&](int64_t bytes) { const int64_t at = off; off += align_up(bytes); return at; };
   if (o.log_schedule) L.log = take((int64_t)o.max_iter * 2 * kMaxUnits * 8);
   L.m = take(vec); L.r = take(vec); L.p0 = take(vec); L.p1 = take(vec);
+  for (int i = 0; i < 2; ++i) { L.cr[i] = take(vec); L.cp[i] = take(vec); }
   L.yl = take(vec); L.vl = take(vec);
   const bool adapt = o.adapt_every > 0, stop = o.stop_every > 0;
   if (adapt) { L.vh0l = take(vec); L.v0l = take(vec); L.y0l = take(vec); L.xs0 = take(vec); L.xs1 = take(vec); }
@@ -267,7 +268,11 @@ struct Slot {
   int64_t N = 0;
 };
 
-struct TileCfg { int64_t pt_base = 2048, pt_max_items = 512, thr_base = 2048, thr_max_items = 512; int pt_threads = 512; };
+struct TileCfg {
+  int64_t pt_base = 2048, pt_max_items = 512, thr_base = 2048, thr_max_items = 512;
+  int pt_threads = 512;
+  int cg_form = 0;
+};
 
 }  // namespace sip
 
@@ -287,7 +292,7 @@ struct sip_batch {
   sip::ThrItem* d_thr = nullptr; int cap_thr = 0;
   sip::SelItem* d_sel = nullptr; int cap_sel = 0;
   int32_t* d_inst = nullptr; int cap_inst = 0;
-  double *d_rr = nullptr, *d_pq = nullptr, *d_proj = nullptr, *d_thrw = nullptr, *d_thra = nullptr;
+  double *d_rr = nullptr, *d_pq = nullptr, *d_rr2 = nullptr, *d_pq2 = nullptr, *d_proj = nullptr, *d_thrw = nullptr, *d_thra = nullptr;
   uint32_t* d_tie = nullptr;
   int cap_ppt = 0, cap_pthr = 0, cap_psp = 0;   // item capacity of the partial-sum buffers
   sip::PtItem* d_sp = nullptr; int cap_sp = 0;
@@ -375,9 +380,14 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   bool moved = old_pt != b->cap_pt || old_thr != b->cap_thr || old_sel != b->cap_sel || old_inst != b->cap_inst ||
                old_sp != b->cap_sp;
   if (b->cap_ppt < b->cap_pt) {
-    if (b->d_rr) { HIP_OK(hipFree(b->d_rr)); HIP_OK(hipFree(b->d_pq)); }
+    if (b->d_rr) {
+      HIP_OK(hipFree(b->d_rr)); HIP_OK(hipFree(b->d_pq));
+      HIP_OK(hipFree(b->d_rr2)); HIP_OK(hipFree(b->d_pq2));
+    }
     HIP_OK(hipMalloc((void**)&b->d_rr, (size_t)b->cap_pt * 8));
     HIP_OK(hipMalloc((void**)&b->d_pq, (size_t)b->cap_pt * 8));
+    HIP_OK(hipMalloc((void**)&b->d_rr2, (size_t)b->cap_pt * 8));
+    HIP_OK(hipMalloc((void**)&b->d_pq2, (size_t)b->cap_pt * 8));
     b->cap_ppt = b->cap_pt;
     moved = true;
   }
@@ -418,10 +428,12 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   t.sel = b->d_sel; t.nsel = lsel;
   t.inst = b->d_inst; t.ninst = linst;
   t.rr_part = b->d_rr; t.pq_part = b->d_pq; t.proj_part = b->d_proj;
+  t.rr2_part = b->d_rr2; t.pq2_part = b->d_pq2;
   t.thrw_part = b->d_thrw; t.thra_part = b->d_thra; t.tie_part = b->d_tie;
   t.any_card = any_card;
-  const bool threads_changed = t.pt_threads != (int)b->tiles.pt_threads;
+  const bool threads_changed = t.pt_threads != (int)b->tiles.pt_threads || t.cg_form != b->tiles.cg_form;
   t.pt_threads = (int)b->tiles.pt_threads;
+  t.cg_form = b->tiles.cg_form;
   b->live_items = (int)pt.size() + (int)thr.size();
   b->live_inst = (int)inst.size();
   if (relaunch || moved || threads_changed) drop_graphs(b);
@@ -562,7 +574,7 @@ int32_t sip_batch_destroy(sip_batch* b) {
   drop_graphs(b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   void* dev[] = {b->d_desc, b->d_scal, b->d_pt, b->d_thr, b->d_sel, b->d_inst, b->d_rr, b->d_pq,
-                 b->d_proj, b->d_thrw, b->d_thra, b->d_tie, b->d_counts, b->d_sp};
+                 b->d_rr2, b->d_pq2, b->d_proj, b->d_thrw, b->d_thra, b->d_tie, b->d_counts, b->d_sp};
   for (void* p : dev) if (p) (void)hipFree(p);
   if (b->h_scal) (void)hipHostFree(b->h_scal);
   delete b;
@@ -612,6 +624,7 @@ int32_t sip_batch_add(sip_batch* b, const sip_grid* g, const sip_set* sets, int3
   const Layout& L = s.L;
   auto at = [&](int64_t off) -> void* { return off >= 0 ? (void*)(w + off) : nullptr; };
   d.m = at(L.m); d.x = x_dev; d.r = at(L.r); d.p[0] = at(L.p0); d.p[1] = at(L.p1);
+  for (int i = 0; i < 2; ++i) { d.cr[i] = at(L.cr[i]); d.cp[i] = at(L.cp[i]); }
   d.xs[0] = at(L.xs0); d.xs[1] = at(L.xs1); d.ring = at(L.ring);
   d.yl = at(L.yl); d.vl = at(L.vl); d.vh0l = at(L.vh0l); d.v0l = at(L.v0l); d.y0l = at(L.y0l);
   d.scal = b->d_scal + (size_t)si * S_COUNT;
@@ -860,7 +873,7 @@ int32_t sip_batch_reset(sip_batch* b, int32_t slot, const void* m_dev, void* str
 }
 
 int32_t sip_batch_time_kernel(sip_batch* b, int32_t kernel, int32_t reps, void* stream_, double* avg_ms) {
-  if (!b || kernel < SIP_K_RHS || kernel > SIP_K_THR_APPLY || reps < 1 || !avg_ms) return SIP_EINVAL;
+  if (!b || kernel < SIP_K_RHS || kernel > SIP_K_CG1_W0 || reps < 1 || !avg_ms) return SIP_EINVAL;
   hipStream_t stream = (hipStream_t)stream_;
   if (b->dirty) {
     const int32_t rc = rebuild_tables(b, stream);
@@ -897,12 +910,13 @@ int32_t sip_stream_copy(void* dst, const void* src, int64_t bytes, void* stream_
 }
 
 int32_t sip_batch_set_tiles(sip_batch* b, int32_t pt_points, int32_t pt_max_items, int32_t thr_points,
-                            int32_t thr_max_items, int32_t pt_threads) {
+                            int32_t thr_max_items, int32_t pt_threads, int32_t cg_form) {
   if (!b || pt_points < kTileQuantum || thr_points < kTileQuantum || pt_points % kTileQuantum ||
       thr_points % kTileQuantum || pt_max_items < 1 || thr_max_items < 1 ||
-      (pt_threads != 256 && pt_threads != 512))
+      (pt_threads != 256 && pt_threads != 512) || (cg_form != 0 && cg_form != 1))
     return SIP_EINVAL;
   b->tiles.pt_threads = pt_threads;
+  b->tiles.cg_form = cg_form;
   b->tiles.pt_base = pt_points;
   b->tiles.pt_max_items = pt_max_items;
   b->tiles.thr_base = thr_points;

@@ -38,7 +38,8 @@ enum Scal : int {
   S_HAVE_SNAP,                  // adapt-rho-gamma holds a k0 snapshot
   S_REVOL,                      // last r_evol (-1: never evaluated)
   S_ITERS,                      // iterations completed
-  S_RFEAS,                      // [SIP_MAX_SETS] last r_feas (-1: never)
+  S_ALPHA,                      // [2] CG step length by step parity (one-reduction form)
+  S_RFEAS = S_ALPHA + 2,        // [SIP_MAX_SETS] last r_feas (-1: never)
   S_COUNT = S_RFEAS + SIP_MAX_SETS + 4
 };
 
@@ -102,6 +103,7 @@ struct InstDesc {
   FastDiv div_x, div_y;           // point -> (row, x), row -> (z, y)
   double hinv[3], h2inv[3];
   void* m; void* x; void* r; void* p[2];
+  void* cr[2]; void* cp[2];       // one-reduction CG: w = C r and s = C p, by step parity
   void* xs[2];                    // x snapshots of adapt-rho-gamma (alternating)
   void* ring;                     // x history for r_evol ((evol_hist + 1) blocks)
   void* yl; void* vl; void* vh0l; void* v0l; void* y0l;  // identity block p+1
@@ -149,9 +151,11 @@ struct Tables {
   const SelItem* sel; int nsel;
   const int32_t* inst; int ninst;
   double* rr_part; double* pq_part; double* proj_part; double* thrw_part; double* thra_part;
+  double* rr2_part; double* pq2_part;  // one-reduction CG: odd-step partials
   uint32_t* tie_part;
   bool any_card;
   int pt_threads;  // threads per block of the RHS and CG kernels (256 or 512)
+  int cg_form;     // 0: two launches per CG step; 1: one (Chronopoulos-Gear)
 };
 
 inline FastDiv make_fastdiv(uint32_t d) {

@@ -407,12 +407,27 @@ __device__ __forceinline__ void pick(int off, const T (&A)[Grp<T>::W], const T (
   }
 }
 
-// A stencil operand: value(Q) = a[0][Q] (NA = 1) or a[0][Q] + beta a[1][Q].
+// A stencil operand: value(Q) = a[0][Q] (NA = 1), a[0][Q] + beta a[1][Q]
+// (NA = 2) or a[0][Q] + beta (a[1][Q] + beta2 a[2][Q]) (NA = 3).
 template <typename T, int NA>
 struct Src {
   const T* a[NA];
   T beta;
+  T beta2;
 };
+
+template <typename T, int NA>
+__device__ __forceinline__ T src_comb(const Src<T, NA>& f, T a0, T a1, T a2) {
+  if constexpr (NA == 1) return a0;
+  else if constexpr (NA == 2) return a0 + f.beta * a1;
+  else return a0 + f.beta * (a1 + f.beta2 * a2);
+}
+
+// The operand at one point, by element loads.
+template <typename T, int NA>
+__device__ __forceinline__ T src_at(const Src<T, NA>& f, int Q) {
+  return src_comb<T, NA>(f, f.a[0][Q], NA > 1 ? f.a[NA > 1 ? 1 : 0][Q] : (T)0, NA > 2 ? f.a[NA > 2 ? 2 : 0][Q] : (T)0);
+}
 
 template <typename T, int NA>
 __device__ __forceinline__ void src_load(const Src<T, NA>& f, int G, int N, T (&R)[NA][Grp<T>::W]) {
@@ -423,7 +438,8 @@ __device__ __forceinline__ void src_load(const Src<T, NA>& f, int G, int N, T (&
 template <typename T, int NA>
 __device__ __forceinline__ void src_mix(const Src<T, NA>& f, const T (&R)[NA][Grp<T>::W], T (&o)[Grp<T>::W]) {
 #pragma unroll
-  for (int e = 0; e < Grp<T>::W; ++e) o[e] = NA == 1 ? R[0][e] : R[0][e] + f.beta * R[NA - 1][e];
+  for (int e = 0; e < Grp<T>::W; ++e)
+    o[e] = src_comb<T, NA>(f, R[0][e], R[NA > 1 ? 1 : 0][e], R[NA > 2 ? 2 : 0][e]);
 }
 
 template <typename T, int NA>
@@ -434,7 +450,7 @@ __device__ __forceinline__ void src_load_head(const Src<T, NA>& f, int G, int N,
 
 template <typename T, int NA>
 __device__ __forceinline__ T src_one(const Src<T, NA>& f, const T (&r)[NA]) {
-  return NA == 1 ? r[0] : r[0] + f.beta * r[NA - 1];
+  return src_comb<T, NA>(f, r[0], r[NA > 1 ? 1 : 0], r[NA > 2 ? 2 : 0]);
 }
 
 // Loads of the window at P0c + delta (off = (P0c + delta) mod W).  AL: the
@@ -515,11 +531,11 @@ __device__ __forceinline__ GLane glane(int P0, int begin, int end, const Geo& g)
 // (3D); z windows are always read (clamped and unused when nz = 1).
 template <typename T, int NA, bool HY, bool AL>
 __device__ __forceinline__ void group_C_v(const Src<T, NA>& f, const GLane& L, int lane, const Geo& g,
-                                          const Offs& of, T (&c)[Grp<T>::W], T (&q)[Grp<T>::W], T c0, T cz, T cy,
-                                          T cx) {
+                                          const Offs& of, T (&R)[NA][Grp<T>::W], T (&c)[Grp<T>::W],
+                                          T (&q)[Grp<T>::W], T c0, T cz, T cy, T cx) {
   constexpr int W = Grp<T>::W;
   const int N = g.N;
-  T R[NA][W], yma[NA][W], ymb[NA][W], ypa[NA][W], ypb[NA][W], zma[NA][W], zmb[NA][W], zpa[NA][W], zpb[NA][W];
+  T yma[NA][W], ymb[NA][W], ypa[NA][W], ypb[NA][W], zma[NA][W], zmb[NA][W], zpa[NA][W], zpb[NA][W];
   src_load<T, NA>(f, L.P0c, N, R);
   if constexpr (HY) {
     win_load<T, NA, AL>(f, L.P0c, -g.sy, of.ym, N, yma, ymb);
@@ -571,17 +587,26 @@ __device__ __forceinline__ void group_C_v(const Src<T, NA>& f, const GLane& L, i
   }
 }
 
+// R: the operand's own arrays at the group, as loaded.
+template <typename T, int NA>
+__device__ __forceinline__ void group_C_R(const Src<T, NA>& f, const GLane& L, int lane, const Geo& g,
+                                          const Offs& of, T (&R)[NA][Grp<T>::W], T (&c)[Grp<T>::W],
+                                          T (&q)[Grp<T>::W], T c0, T cz, T cy, T cx) {
+  const bool al = rows_aligned<T>(g);
+  if (g.ny > 1) {
+    if (al) group_C_v<T, NA, true, true>(f, L, lane, g, of, R, c, q, c0, cz, cy, cx);
+    else group_C_v<T, NA, true, false>(f, L, lane, g, of, R, c, q, c0, cz, cy, cx);
+  } else {
+    if (al) group_C_v<T, NA, false, true>(f, L, lane, g, of, R, c, q, c0, cz, cy, cx);
+    else group_C_v<T, NA, false, false>(f, L, lane, g, of, R, c, q, c0, cz, cy, cx);
+  }
+}
+
 template <typename T, int NA>
 __device__ __forceinline__ void group_C(const Src<T, NA>& f, const GLane& L, int lane, const Geo& g, const Offs& of,
                                         T (&c)[Grp<T>::W], T (&q)[Grp<T>::W], T c0, T cz, T cy, T cx) {
-  const bool al = rows_aligned<T>(g);
-  if (g.ny > 1) {
-    if (al) group_C_v<T, NA, true, true>(f, L, lane, g, of, c, q, c0, cz, cy, cx);
-    else group_C_v<T, NA, true, false>(f, L, lane, g, of, c, q, c0, cz, cy, cx);
-  } else {
-    if (al) group_C_v<T, NA, false, true>(f, L, lane, g, of, c, q, c0, cz, cy, cx);
-    else group_C_v<T, NA, false, false>(f, L, lane, g, of, c, q, c0, cz, cy, cx);
-  }
+  T R[NA][Grp<T>::W];
+  group_C_R<T, NA>(f, L, lane, g, of, R, c, q, c0, cz, cy, cx);
 }
 
 // (C f)(P) at one point, f given by a scalar fetch.
@@ -877,6 +902,217 @@ __global__ __launch_bounds__(NT) void k_cg_upd(const InstDesc* __restrict__ D, c
   }
   const acc_t tot = block_total<NT>(acc[0], lds);
   if (threadIdx.x == 0) rr_part[iti] = tot;
+}
+
+// ------------------------------------------------- one-reduction CG form
+//
+// Chronopoulos and Gear's arrangement of CG: both inner products a step needs
+// (gamma = r^T r and delta = r^T C r) are taken from the same vectors, so a
+// step is one launch.  Entering step j: x_j, r_j, w_j = C r_j, p_{j-1},
+// s_{j-1} = C p_{j-1} and the per-item partials of gamma_j and delta_j.
+//   beta_j  = gamma_j / gamma_{j-1}                        (0 at j = 0)
+//   alpha_j = gamma_j / (delta_j - beta_j gamma_j / alpha_{j-1})
+// (the denominator is p_j^T C p_j), then
+//   p_j = r_j + beta_j p_{j-1},  s_j = w_j + beta_j s_{j-1},
+//   x_{j+1} = x_j + alpha_j p_j,  r_{j+1} = r_j - alpha_j s_j,
+//   w_{j+1} = C r_{j+1}, and the partials of gamma_{j+1}, delta_{j+1}.
+// In exact arithmetic these are the iterates of the two-launch form.  r, w
+// and s alternate between two buffers by step parity (neighbours' old values
+// are read while other blocks write the new ones); x and p are updated in
+// place.  r_{j+1} at a neighbour is formed from r_j, w_j and s_{j-1} there by
+// the same expression as at the point that owns it.
+
+// w_0 = C r_0 and the partials of delta_0 = r_0^T w_0 (r_0 from the RHS kernel).
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_cg1_w0(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt,
+                                                const PtItem* __restrict__ items, double* dpart) {
+  constexpr int W = Grp<T>::W;
+  __shared__ acc_t lds[lds_sum<1, NT>()];
+  if ((int)blockIdx.x >= cnt->npt) return;
+  const int iti = xcd_item(blockIdx.x, cnt->npt);
+  const PtItem it = items[iti];
+  const InstDesc& d = D[it.inst];
+  const CgScal qs = cg_scal(d.scal);
+  if (!qs.live()) return;
+  const Geo g(d);
+  const T* r = (const T*)d.r;
+  T* w = (T*)d.cr[0];
+  const T c0 = (T)qs.c0, cz = (T)qs.cax[0], cy = (T)qs.cax[1], cx = (T)qs.cax[2];
+  const Src<T, 1> f{{r}, (T)0, (T)0};
+  auto fs = [&](int Q) -> T { return r[Q]; };
+  const int lane = threadIdx.x & 63;
+  const bool grouped = item_grouped(d);
+  const Offs of = offs_of<T>(g);
+  acc_t acc = 0;
+  const int end = it.begin + it.len;
+  for (int base = it.begin; base < end; base += NT * W) {
+    const int P0 = base + (int)threadIdx.x * W;
+    bool vec = false;
+    if (grouped) {
+      const GLane L = glane<T>(P0, it.begin, end, g);
+      T c[W], q[W];
+      group_C<T, 1>(f, L, lane, g, of, c, q, c0, cz, cy, cx);
+      vec = L.vec;
+      if (vec) {
+#pragma unroll
+        for (int e = 0; e < W; ++e)
+          if (e < L.cnt) acc += (acc_t)c[e] * (acc_t)q[e];
+        st16<T>(w + P0, q);
+      }
+    }
+    if (!vec) {
+      for (int e = 0; e < W; ++e) {
+        const int P = P0 + e;
+        if (P >= end) break;
+        const T rc = r[P];
+        const T qq = point_apply_C<T>(P, g, fs, rc, c0, cz, cy, cx);
+        w[P] = qq;
+        acc += (acc_t)rc * (acc_t)qq;
+      }
+    }
+  }
+  const acc_t tot = block_total<NT>(acc, lds);
+  if (threadIdx.x == 0) dpart[iti] = tot;
+}
+
+// Step j (NA = 2 at j = 0, where p_0 = r_0 and s_0 = w_0; NA = 3 after).
+template <typename T, int NT, int NA>
+__global__ __launch_bounds__(NT) void k_cg1_step(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt,
+                                                  const PtItem* __restrict__ items, int j, const double* gin,
+                                                  const double* din, double* gout, double* dout, Opts o) {
+  constexpr int W = Grp<T>::W;
+  __shared__ acc_t lds_g[lds_sum<1, NT>()];
+  __shared__ acc_t lds_d[lds_sum<1, NT>()];
+  if ((int)blockIdx.x >= cnt->npt) return;
+  const int iti = xcd_item(blockIdx.x, cnt->npt);
+  const PtItem it = items[iti];
+  const InstDesc& d = D[it.inst];
+  double* S = d.scal;
+  const CgScal qs = cg_scal(S);
+  const double alpha_prev = ldgd(S + S_ALPHA + ((j + 1) & 1));
+  double pg[kPre], pd[kPre];
+  part_issue(gin, d.pt_begin, d.pt_end, pg);
+  part_issue(din, d.pt_begin, d.pt_end, pd);
+  if (!qs.live()) return;
+  const bool leader = iti == d.pt_begin && threadIdx.x == 0;
+  if (j > 0 && qs.done_at(j - 1) != 0.0) {
+    // finished at an earlier step (this step's partials were never written)
+    if (leader) S[S_DONE + (j & 1)] = 1.0;
+    return;
+  }
+  const double gam = part_finish(gin, d.pt_begin, d.pt_end, pg);
+  const double del = part_finish(din, d.pt_begin, d.pt_end, pd);
+  bool done = !(gam > 0.0);
+  double beta = 0.0;
+  if (j > 0) {
+    done = done || (!o.cg_fixed && gam < o.cg_rel2 * qs.rr0);
+    beta = gam / qs.rr_at(j - 1);
+  }
+  const bool bad = !(gam <= 1.0e300) || gam != gam;
+  if (leader) {
+    S[S_RR + (j & 1)] = gam;
+    S[S_DONE + (j & 1)] = (done || bad) ? 1.0 : 0.0;
+    if (j == 0) S[S_RR0] = gam;
+    if (bad) S[S_ERR] = (double)SIP_ENUMERIC;
+  }
+  if (done || bad) return;
+  const double pq = j == 0 ? del : del - beta * gam / alpha_prev;
+  if (!(pq > 0.0) || !(pq <= 1.0e300)) {
+    if (leader) S[S_ERR] = (double)SIP_ENUMERIC;
+    return;
+  }
+  const double alpha = gam / pq;
+  if (leader) {
+    S[S_ALPHA + (j & 1)] = alpha;
+    S[S_CGTOT] += 1.0;
+  }
+  const Geo g(d);
+  T* x = (T*)d.x;
+  T* p = (T*)d.p[0];
+  const T* rj = (const T*)((j & 1) ? d.p[1] : d.r);
+  T* rn = (T*)((j & 1) ? d.r : d.p[1]);
+  const T* wj = (const T*)d.cr[j & 1];
+  T* wn = (T*)d.cr[(j + 1) & 1];
+  const T* sprev = (const T*)d.cp[(j + 1) & 1];
+  T* sj = (T*)d.cp[j & 1];
+  const T al = (T)alpha, be = (T)beta;
+  const T c0 = (T)qs.c0, cz = (T)qs.cax[0], cy = (T)qs.cax[1], cx = (T)qs.cax[2];
+  Src<T, NA> f;
+  f.a[0] = rj;
+  f.a[1] = wj;
+  if constexpr (NA == 3) f.a[2] = sprev;
+  f.beta = -al;
+  f.beta2 = be;
+  auto fs = [&](int Q) -> T { return src_at<T, NA>(f, Q); };
+  const int lane = threadIdx.x & 63;
+  const bool grouped = item_grouped(d);
+  const Offs of = offs_of<T>(g);
+  acc_t ag = 0, ad = 0;
+  const int end = it.begin + it.len;
+  for (int base = it.begin; base < end; base += NT * W) {
+    const int P0 = base + (int)threadIdx.x * W;
+    bool vec = false;
+    if (grouped) {
+      const GLane L = glane<T>(P0, it.begin, end, g);
+      T xv[W], pv[W], R[NA][W], c[W], q[W];
+      ld16p<T>(x, L.P0c, g.N, xv);
+      if constexpr (NA == 3) ld16<T>(p + L.P0c, pv);
+      group_C_R<T, NA>(f, L, lane, g, of, R, c, q, c0, cz, cy, cx);
+      vec = L.vec;
+      if (vec) {
+        T pn[W], sn[W];
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+          if constexpr (NA == 3) {
+            pn[e] = R[0][e] + be * pv[e];
+            sn[e] = R[1][e] + be * R[2][e];
+          } else {
+            pn[e] = R[0][e];
+            sn[e] = R[1][e];
+          }
+          xv[e] = xv[e] + al * pn[e];
+          if (e < L.cnt) {
+            ag += (acc_t)c[e] * (acc_t)c[e];
+            ad += (acc_t)c[e] * (acc_t)q[e];
+          }
+        }
+        st16p<T>(x, P0, L.cnt, xv);
+        st16<T>(p + P0, pn);
+        st16<T>(sj + P0, sn);
+        st16<T>(rn + P0, c);
+        st16<T>(wn + P0, q);
+      }
+    }
+    if (!vec) {
+      for (int e = 0; e < W; ++e) {
+        const int P = P0 + e;
+        if (P >= end) break;
+        const T rc = fs(P);
+        const T qq = point_apply_C<T>(P, g, fs, rc, c0, cz, cy, cx);
+        T pn, sn;
+        if constexpr (NA == 3) {
+          pn = rj[P] + be * p[P];
+          sn = wj[P] + be * sprev[P];
+        } else {
+          pn = rj[P];
+          sn = wj[P];
+        }
+        x[P] = x[P] + al * pn;
+        p[P] = pn;
+        sj[P] = sn;
+        rn[P] = rc;
+        wn[P] = qq;
+        ag += (acc_t)rc * (acc_t)rc;
+        ad += (acc_t)rc * (acc_t)qq;
+      }
+    }
+  }
+  const acc_t tg = block_total<NT>(ag, lds_g);
+  const acc_t td = block_total<NT>(ad, lds_d);
+  if (threadIdx.x == 0) {
+    gout[iti] = tg;
+    dout[iti] = td;
+  }
 }
 
 // -------------------------------------------------------- RHS + residual
@@ -2436,6 +2672,19 @@ void launch_init(hipStream_t st, const InstDesc* __restrict__ D, int inst, int64
 template <typename T, int NT>
 void launch_cg(hipStream_t st, const Tables& t, const Opts& o) {
   k_rhs<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, t.rr_part);
+  if (t.cg_form == 1) {
+    k_cg1_w0<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, t.pq_part);
+    for (int j = 0; j < o.cg_max; ++j) {
+      double* g[2] = {t.rr_part, t.rr2_part};
+      double* dd[2] = {t.pq_part, t.pq2_part};
+      if (j == 0)
+        k_cg1_step<T, NT, 2><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, j, g[0], dd[0], g[1], dd[1], o);
+      else
+        k_cg1_step<T, NT, 3><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, j, g[j & 1], dd[j & 1], g[(j + 1) & 1],
+                                                    dd[(j + 1) & 1], o);
+    }
+    return;
+  }
   for (int j = 0; j < o.cg_max; ++j) {
     k_cg_dir<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, j, t.rr_part, t.pq_part, o);
     k_cg_upd<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, j, t.pq_part, t.rr_part);
@@ -2448,6 +2697,9 @@ void launch_point_phase(hipStream_t st, const Tables& t, const Opts& o, int phas
   if (phase == 0) k_rhs<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, t.rr_part);
   if (phase == 1) k_cg_dir<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, 1, t.rr_part, t.pq_part, o);
   if (phase == 2) k_cg_upd<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, 1, t.pq_part, t.rr_part);
+  if (phase == 6)
+    k_cg1_step<T, NT, 3><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, 1, t.rr2_part, t.pq2_part, t.rr_part, t.pq_part, o);
+  if (phase == 7) k_cg1_w0<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, t.pq_part);
 }
 
 template <typename T>
@@ -2472,12 +2724,16 @@ void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
 }
 
 // One kernel of the iteration on its own (timing); CG kernels use step 1.
+// 0 rhs, 1 cg_dir, 2 cg_upd, 3 proj, 4 thr_w, 5 thr_apply, 6 one-reduction
+// CG step, 7 its w_0 = C r_0 pass.
 template <typename T>
 void launch_phase(hipStream_t st, const Tables& t, const Opts& o, int phase) {
   switch (phase) {
     case 0:
     case 1:
     case 2:
+    case 6:
+    case 7:
       if (t.pt_threads == 256) launch_point_phase<T, 256>(st, t, o, phase);
       else launch_point_phase<T, 512>(st, t, o, phase);
       break;

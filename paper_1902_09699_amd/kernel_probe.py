@@ -39,16 +39,20 @@ def main():
     xs = [torch.empty_like(m) for m in ms]
     batch = sip.Batch(len(insts), sum(sip.workspace_bytes(m.shape, s, opts) for m, s in insts), opts)
     slots = [batch.add(md, s, xd) for md, (_, s), xd in zip(ms, insts, xs)]
-    if a.tiles:
-        batch.set_tiles(*[int(v) for v in a.tiles.split(",")])
+    tiles = [int(v) for v in a.tiles.split(",")] if a.tiles else []
+    if tiles:
+        batch.set_tiles(*tiles)
+    one_red = len(tiles) > 5 and tiles[5] == 1
     batch.run(2)
     torch.cuda.synchronize()
     for sl in slots:
         r_, g_, _, _ = batch.get_params(sl)
         batch.set_params(sl, r_, g_, 2, True)
     out = {}
-    for name, kid in (("cg_dir", sip.K_CG_DIR), ("cg_upd", sip.K_CG_UPD), ("rhs", sip.K_RHS),
-                      ("proj", sip.K_PROJ), ("thr_w", sip.K_THR_W), ("thr_apply", sip.K_THR_APPLY)):
+    cg = ((("cg1_step", sip.K_CG1_STEP), ("cg1_w0", sip.K_CG1_W0)) if one_red else
+          (("cg_dir", sip.K_CG_DIR), ("cg_upd", sip.K_CG_UPD)))
+    for name, kid in cg + (("rhs", sip.K_RHS), ("proj", sip.K_PROJ), ("thr_w", sip.K_THR_W),
+                           ("thr_apply", sip.K_THR_APPLY)):
         out[name] = batch.time_kernel(kid, a.reps)
         print(f"{name}: {out[name] * 1e3:.2f} us", flush=True)
     n = a.copy_mb * (1 << 20) // 4

@@ -22,7 +22,7 @@ OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED, EBUDGET = 0, -1, -2, -3, -4, -
 F32, F64 = 0, 1
 OPS = {"I": 0, "DZ": 1, "DY": 2, "DX": 3, "GRAD": 4, "LAT": 5}
 KINDS = {"bounds": 0, "l1": 1, "card": 2, "l2": 3, "annulus": 4}
-K_RHS, K_CG_DIR, K_CG_UPD, K_PROJ, K_THR_W, K_THR_APPLY = range(6)
+K_RHS, K_CG_DIR, K_CG_UPD, K_PROJ, K_THR_W, K_THR_APPLY, K_CG1_STEP, K_CG1_W0 = range(8)
 FIELD_Y, FIELD_V, FIELD_VHAT0, FIELD_V0, FIELD_Y0, FIELD_R, FIELD_XS0, FIELD_XS1 = range(8)
 
 
@@ -99,7 +99,7 @@ def lib():
         "sip_batch_set_params": (i32, [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_double), i32, i32, vp]),
         "sip_batch_schedule": (i32, [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_double), i32,
                                      C.POINTER(i32), vp]),
-        "sip_batch_set_tiles": (i32, [vp, i32, i32, i32, i32, i32]),
+        "sip_batch_set_tiles": (i32, [vp, i32, i32, i32, i32, i32, i32]),
         "sip_batch_reset": (i32, [vp, i32, vp, vp]),
         "sip_batch_time_kernel": (i32, [vp, i32, i32, vp, C.POINTER(C.c_double)]),
         "sip_stream_copy": (i32, [vp, vp, i64, vp]),
@@ -452,9 +452,10 @@ class Batch:
         cnt = n.value
         return (np.array(rho[:cnt * p1]).reshape(cnt, p1), np.array(gam[:cnt * p1]).reshape(cnt, p1))
 
-    def set_tiles(self, pt_points=2048, pt_max_items=512, thr_points=2048, thr_max_items=512, pt_threads=512):
+    def set_tiles(self, pt_points=2048, pt_max_items=512, thr_points=2048, thr_max_items=512, pt_threads=512,
+                  cg_form=0):
         check(lib().sip_batch_set_tiles(self.h, int(pt_points), int(pt_max_items), int(thr_points),
-                                        int(thr_max_items), int(pt_threads)), "sip_batch_set_tiles")
+                                        int(thr_max_items), int(pt_threads), int(cg_form)), "sip_batch_set_tiles")
 
     def reset(self, slot, m, stream=None):
         _check_tensor(m, m.numel(), self.opts, "m")

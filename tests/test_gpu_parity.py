@@ -34,17 +34,21 @@ def _card_mask(w, k, rtol):
     return np.abs(a - tk) > rtol * max(tk, 1e-300)
 
 
-@pytest.mark.parametrize("kind,field,threads", [
-    ("box_tv_2d", "f64", 512), ("box_tv_2d", "f32", 512),
-    ("four_sets_2d", "f32", 512), ("four_sets_2d", "f64", 512),
-    ("box_tv_lat_3d", "f32", 512), ("mixed_2d", "f32", 512), ("mixed_3d", "f64", 512), ("mixed_3d", "f32", 512),
-    ("four_sets_2d", "f32", 256), ("box_tv_lat_3d", "f32", 256), ("mixed_3d", "f64", 256),
+@pytest.mark.parametrize("kind,field,threads,form", [
+    ("box_tv_2d", "f64", 512, 0), ("box_tv_2d", "f32", 512, 0),
+    ("four_sets_2d", "f32", 512, 0), ("four_sets_2d", "f64", 512, 0),
+    ("box_tv_lat_3d", "f32", 512, 0), ("mixed_2d", "f32", 512, 0), ("mixed_3d", "f64", 512, 0),
+    ("mixed_3d", "f32", 512, 0),
+    ("four_sets_2d", "f32", 256, 0), ("box_tv_lat_3d", "f32", 256, 0), ("mixed_3d", "f64", 256, 0),
+    # one-reduction CG steps
+    ("box_tv_2d", "f64", 512, 1), ("four_sets_2d", "f32", 512, 1), ("box_tv_lat_3d", "f32", 512, 1),
+    ("mixed_2d", "f32", 256, 1), ("mixed_3d", "f64", 256, 1), ("box_tv_lat_3d", "f64", 512, 1),
 ])
-def test_step_parity(kind, field, threads):
+def test_step_parity(kind, field, threads, form):
     m, sets = _prep(kind, field)
     iters = 9
-    print(f"\n[step parity] {kind} {field} shape={m.shape} threads={threads}", flush=True)
-    sl = Slot(m, sets, field, dict(max_iter=50, cg_max=10, cg_fixed=1), tiles=(1024, 1024, 1024, 512, threads))
+    print(f"\n[step parity] {kind} {field} shape={m.shape} threads={threads} cg_form={form}", flush=True)
+    sl = Slot(m, sets, field, dict(max_iter=50, cg_max=10, cg_fixed=1), tiles=(1024, 1024, 1024, 512, threads, form))
     prob = orc.Problem(m, m.shape, sets)
     oo = orc.Options(max_iter=50, cg_max=10, cg_fixed=True)
     st = orc.initial_state(prob, oo)
@@ -242,8 +246,9 @@ def _oracle_run_with_schedule(m, shape, sets, opts):
     return st.x.reshape(shape), np.array(rho), np.array(gam)
 
 
+@pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("name", sorted(EDGE_CASES))
-def test_edge_cases_f64(name):
+def test_edge_cases_f64(name, form):
     """Degenerate inputs, float64.  The adapt-rho-gamma rule is discontinuous
     (the correlation threshold, the ratio guard), so a last-bit difference in
     a dot product can flip one decision and send a free-running run down a
@@ -255,8 +260,9 @@ def test_edge_cases_f64(name):
     rng = np.random.default_rng(zlib.crc32(name.encode()) % 1000)
     m = rng.standard_normal(shape)
     iters = 20
-    print(f"\n[edge] {name}", flush=True)
-    sl = Slot(m, sets, "f64", dict(max_iter=iters, cg_max=10, cg_fixed=1, log_schedule=1))
+    print(f"\n[edge] {name} cg_form={form}", flush=True)
+    sl = Slot(m, sets, "f64", dict(max_iter=iters, cg_max=10, cg_fixed=1, log_schedule=1),
+              tiles=(1024, 1024, 1024, 512, 512, form))
     sl.batch.run(iters)
     res = sl.batch.result(sl.slot)
     assert res["status"] == 0
@@ -306,3 +312,40 @@ def test_card_exact_ties_lockstep(field, seed):
             yg = sl.arr(sip.FIELD_Y, i)
             assert np.array_equal(yg != 0, st.y[i] != 0), (it, i)
             assert (yg != 0).sum() <= sets[i]["k"]
+
+
+@pytest.mark.parametrize("field,form", [("f64", 0), ("f64", 1), ("f32", 0), ("f32", 1)])
+def test_unaligned_x(field, form):
+    """x one element past a 16-byte boundary: the RHS and CG kernels take
+    their per-point path.  Its iterates must match the grouped path's (same
+    arithmetic, element by element) and the oracle."""
+    import torch
+    m, sets = _prep("four_sets_2d" if field == "f32" else "mixed_2d", field, seed=4)
+    iters = 6
+    print(f"\n[unaligned x] {field} cg_form={form} shape={m.shape}", flush=True)
+    opts = sip.make_opts(field, max_iter=iters, cg_max=10, cg_fixed=1, log_schedule=1)
+    dt = torch.float64 if field == "f64" else torch.float32
+    md = torch.tensor(m, dtype=dt, device="cuda")
+    xs = []
+    for shift in (0, 1):
+        buf = torch.empty(m.size + 4, dtype=dt, device="cuda")
+        assert buf.data_ptr() % 16 == 0
+        x = buf[shift:shift + m.size].view(m.shape)
+        b = sip.Batch(1, sip.workspace_bytes(m.shape, sets, opts), opts)
+        b.set_tiles(1024, 1024, 1024, 512, 512, form)
+        sl = b.add(md, sets, x)
+        b.run(iters)
+        res = b.result(sl)
+        assert res["status"] == 0 and res["iters"] == iters
+        rho, gam = b.schedule(sl, iters)
+        torch.cuda.synchronize()
+        xs.append(x.double().cpu().numpy().ravel())
+        b.close()
+    sched = {k + 1: (rho[k], gam[k]) for k in range(iters)}
+    xo, _ = orc.parsdmm(m, m.shape, sets, orc.Options(max_iter=iters, cg_max=10, cg_fixed=True), schedule=sched)
+    d_paths = rel(xs[1], xs[0])
+    err = rel(xs[1], xo)
+    print(f"[unaligned x] {field} cg_form={form}: grouped vs per-point {d_paths:.2e}, vs oracle {err:.2e}",
+          flush=True)
+    assert d_paths <= (1e-12 if field == "f64" else 1e-5)
+    assert err <= (1e-9 if field == "f64" else 1e-3)
