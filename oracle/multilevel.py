@@ -72,6 +72,8 @@ def level_sets(sets, shape, shape_l):
     """The set list on a coarser grid (tau and k scaled by the row ratio)."""
     out = []
     for s in sets:
+        if s.get("line") is not None:
+            raise NotImplementedError("multilevel PARSDMM with line-wise sets")
         s2 = dict(s)
         ratio = rows(shape_l, s["op"]) / rows(shape, s["op"])
         if s["kind"] == "l1":

@@ -198,6 +198,46 @@ def project_set(s: dict, w):
     raise ValueError(f"unknown set kind {kind!r}")
 
 
+# Line-wise sets (the paper's constraints "for each row / column / fiber"):
+# the operator is the same; the simple set's projection acts on every line
+# of A x on its own.  Readings: A x is split into its component blocks (one
+# image per component, one layer shorter along the component's difference
+# axis); within a block, the entries that share every grid coordinate except
+# the one along the line axis form one line, in increasing order along it
+# (2D: line "x" is a row X[i, :], line "z" a column X[:, j]; 3D adds "y");
+# l1, cardinality, l2 and annulus sets may be line-wise (bounds act entry by
+# entry anyway); the annulus at a zero line takes lo on the line's first entry.
+LINE_AXES = {2: {"z": 0, "x": 1}, 3: {"z": 0, "y": 1, "x": 2}}
+
+
+def line_rows(op: str, shape, line: str):
+    """Row indices of A (operator op on the grid) grouped into lines, A's row
+    order inside each line."""
+    shape = tuple(int(n) for n in shape)
+    ax_line = LINE_AXES[len(shape)][line]
+    axes = AXIS_OPS[len(shape)][op] if op != "I" else (None,)
+    out, off = [], 0
+    for a in axes:
+        sh = list(shape)
+        if a is not None:
+            sh[a] -= 1
+        cnt = int(np.prod(sh))
+        idx = (np.arange(cnt) + off).reshape(sh)
+        if cnt:
+            out.extend(np.moveaxis(idx, ax_line, -1).reshape(-1, sh[ax_line]))
+        off += cnt
+    return out
+
+
+def project_lines(s: dict, w, lines):
+    """The set's projection applied to every line of w independently."""
+    base = {k: v for k, v in s.items() if k != "line"}
+    y = np.asarray(w, dtype=np.float64).copy()
+    for idx in lines:
+        y[idx] = project_set(base, y[idx])
+    return y
+
+
 def prox_sq_dist(w, m, rho):
     """prox of f(z) = 1/2 ||z - m||^2 with penalty rho: (m + rho w)/(1 + rho),
     eq. (prox_sq_dist)."""
@@ -264,7 +304,12 @@ class Problem:
         self.m = np.asarray(m, dtype=np.float64).reshape(-1)
         self.n = self.m.size
         self.sets = [dict(s) for s in sets]
+        for s in self.sets:
+            if s.get("line") is not None and s["kind"] not in ("l1", "card", "l2", "annulus"):
+                raise ValueError("line-wise sets are l1, card, l2 or annulus sets")
         self.A = [operator(s["op"], self.shape, self.h) for s in self.sets]
+        self.lines = [line_rows(s["op"], self.shape, s["line"]) if s.get("line") is not None else None
+                      for s in self.sets]
         self.A.append(sp.identity(self.n, dtype=np.float64, format="csr"))
         self.B = [(a.T @ a).tocsr() for a in self.A]
         self.p = len(self.sets)
@@ -276,10 +321,16 @@ class Problem:
             c = c + self.B[i] * rho[i]
         return c.tocsr()
 
+    def project(self, i, w):
+        """P_{C_i}(w), line by line for a line-wise set."""
+        if self.lines[i] is not None:
+            return project_lines(self.sets[i], w, self.lines[i])
+        return project_set(self.sets[i], w)
+
     def prox(self, i, w, rho_i):
         if i == self.p:
             return prox_sq_dist(w, self.m, rho_i)
-        return project_set(self.sets[i], w)
+        return self.project(i, w)
 
 
 def initial_state(prob: Problem, opts: Options) -> State:
@@ -403,10 +454,10 @@ def guard_parameters(rho, gamma, opts: Options):
 # Stopping conditions (eqs. feas_stop, obj_stop, stopping_conditions)
 # ---------------------------------------------------------------------------
 
-def feasibility_error(s: dict, ax):
+def feasibility_error(s: dict, ax, lines=None):
     """r_feas = ||A x - P_C(A x)|| / ||A x||; with A x = 0 it is 0 when A x is
     in C and infinity otherwise."""
-    proj = project_set(s, ax)
+    proj = project_lines(s, ax, lines) if lines is not None else project_set(s, ax)
     num = float(np.linalg.norm(ax - proj))
     den = float(np.linalg.norm(ax))
     if den == 0.0:
@@ -456,7 +507,7 @@ def set_updates(prob: Problem, st: State):
 
 
 def stop_test(prob: Problem, st: State, opts: Options) -> bool:
-    st.r_feas = np.array([feasibility_error(s, a @ st.x) for s, a in zip(prob.sets, prob.A)])
+    st.r_feas = np.array([feasibility_error(s, a @ st.x, ln) for s, a, ln in zip(prob.sets, prob.A, prob.lines)])
     st.r_evol = relative_evolution(st.x, st.x_hist[-opts.evol_hist - 1:-1])
     return bool(st.r_evol < opts.eps_evol and np.all(st.r_feas < opts.eps_feas))
 
