@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-WORKLOADS = ("layered2d", "smooth2d", "smooth3d", "batched")
+WORKLOADS = ("layered2d", "layered2d_lines", "smooth2d", "smooth3d", "batched")
 
 
 def parse():
@@ -57,6 +57,10 @@ def workload(name, args):
     elif name == "smooth2d":
         m, sets, field, iters = wl.smooth2d_box_tv()
         desc = "smooth 64x64 f64: box, TV ball; 200 it x 10 CG"
+    elif name == "layered2d_lines":
+        m, sets, field, iters = wl.layered2d_line_sets()
+        desc = ("layered 341x1361 f32: box, card(D_z) <= nx, card(D_x) <= nz, card <= 2 of D_x per row and of "
+                "D_z per column; 300 it x 10 CG")
     elif name == "smooth3d":
         m, sets, field, iters = wl.smooth3d_box_tv_lat()
         desc = "smooth 200x200x100 f32: box, TV ball, lateral slopes; 200 it x 10 CG"
@@ -88,13 +92,16 @@ def algorithmic_bytes(insts, esz):
     projection (non-adapt iteration): read x, m, y_i, v_i of the bounds sets
     and the identity block, write y_i, v_i; threshold w pass: read x, y_i,
     v_i, write w over y_i (N + 3 M_i per l1 / cardinality set); threshold
-    apply pass: read w, write y_i, v_i (3 M_i)."""
-    b = {"cg_dir": 0, "cg_upd": 0, "cg1_step": 0, "cg1_w0": 0, "rhs": 0, "proj": 0, "thr_w": 0, "thr_apply": 0}
+    apply pass: read w, write y_i, v_i (3 M_i); line-wise sets: read x, y_i, v_i,
+    write y_i, v_i (N + 4 M_i)."""
+    b = {"cg_dir": 0, "cg_upd": 0, "cg1_step": 0, "cg1_w0": 0, "rhs": 0, "proj": 0, "thr_w": 0, "thr_apply": 0,
+         "line": 0}
     for m, sets in insts:
         N = m.size
         sum_m = N + sum(rows(m.shape, s) for s in sets)
         clip = N + sum(rows(m.shape, s) for s in sets if s["kind"] == "bounds")
-        thr = [rows(m.shape, s) for s in sets if s["kind"] != "bounds"]
+        thr = [rows(m.shape, s) for s in sets if s["kind"] != "bounds" and s.get("line") is None]
+        line = [rows(m.shape, s) for s in sets if s.get("line") is not None]
         b["cg_dir"] += 3 * N * esz
         b["cg_upd"] += 5 * N * esz
         b["cg1_step"] += 10 * N * esz
@@ -103,6 +110,7 @@ def algorithmic_bytes(insts, esz):
         b["proj"] += (2 * N + 4 * clip) * esz
         b["thr_w"] += sum(N + 3 * mi for mi in thr) * esz
         b["thr_apply"] += sum(3 * mi for mi in thr) * esz
+        b["line"] += sum(N + 4 * mi for mi in line) * esz
     return b
 
 
@@ -268,9 +276,10 @@ def main():
         ids = {"cg1_step": sip.K_CG1_STEP, "cg1_w0": sip.K_CG1_W0}
     else:
         ids = {"cg_dir": sip.K_CG_DIR, "cg_upd": sip.K_CG_UPD}
-    ids.update({"rhs": sip.K_RHS, "proj": sip.K_PROJ, "thr_w": sip.K_THR_W, "thr_apply": sip.K_THR_APPLY})
+    ids.update({"rhs": sip.K_RHS, "proj": sip.K_PROJ, "thr_w": sip.K_THR_W, "thr_apply": sip.K_THR_APPLY,
+                "line": sip.K_LINE})
     per_iter = {"cg_dir": 10, "cg_upd": 10, "cg1_step": 10, "cg1_w0": 1, "rhs": 1, "proj": 1, "thr_w": 1,
-                "thr_apply": 1}
+                "thr_apply": 1, "line": 1}
     kernels = {}
     for name, kid in ids.items():
         if ab[name] == 0:

@@ -72,6 +72,23 @@ typedef enum {
                          at A x = 0 the projection is lo times the first row's unit vector */
 } sip_set_kind;
 
+/* Line-wise sets (the paper's constraints on every row, column or fiber of
+ * the model, section "Software and numerical examples" and the
+ * full-waveform example): the set's projection acts on every line of A x on
+ * its own; the operator is unchanged.  A line is a run of entries of one
+ * component block of A x (an image of the grid, one layer shorter along the
+ * component's difference axis) that differ only in the coordinate along the
+ * line axis: 2D SIP_LINE_X is a row X[i, :], SIP_LINE_Z a column X[:, j].
+ * L1, CARD (k per line), L2 and ANNULUS (at a zero line: lo on its first
+ * entry) sets only; lines hold at most 4096 (float) or 2048 (double)
+ * entries (SIP_EUNSUPPORTED beyond); not supported by sip_project_multilevel. */
+typedef enum {
+  SIP_LINE_NONE = 0, /* the set acts on the whole vector A x */
+  SIP_LINE_Z = 1,
+  SIP_LINE_Y = 2,    /* 3D only */
+  SIP_LINE_X = 3
+} sip_line;
+
 typedef struct {
   int32_t ndim;   /* 2 or 3 */
   int32_t reserved;
@@ -84,7 +101,7 @@ typedef struct {
   int32_t op;     /* sip_op; the operator's axes need at least 2 points */
   double lo, hi;  /* BOUNDS: lo <= hi; ANNULUS: radii, 0 <= lo <= hi */
   double tau;     /* L1, L2: tau >= 0 */
-  int64_t k;      /* CARD: 1 <= k <= rows of A */
+  int64_t k;      /* CARD: 1 <= k <= rows of A (line-wise: k >= 1 per line) */
   /* BOUNDS only, per-pixel bounds l[j] <= (A x)[j] <= u[j] (NULL: the scalar
    * lo / hi): device arrays of the field type, one block of N elements per
    * component of A in the grid's C order (the row of grid point P of
@@ -94,6 +111,8 @@ typedef struct {
    * supported by sip_project_multilevel. */
   const void* lo_vec;
   const void* hi_vec;
+  int32_t line;   /* sip_line */
+  int32_t reserved_;
 } sip_set;
 
 typedef struct {
@@ -258,7 +277,8 @@ typedef enum {
   SIP_K_THR_W = 4,     /* threshold sets: w and the first radix histogram */
   SIP_K_THR_APPLY = 5, /* threshold sets: apply threshold + dual update */
   SIP_K_CG1_STEP = 6,  /* one-reduction CG step (step 1; run a cg_form 1 iteration first) */
-  SIP_K_CG1_W0 = 7     /* one-reduction CG: w_0 = C r_0 + r_0^T w_0 */
+  SIP_K_CG1_W0 = 7,    /* one-reduction CG: w_0 = C r_0 + r_0^T w_0 */
+  SIP_K_LINE = 8       /* line-wise sets: relax, project every line, dual update */
 } sip_kernel_id;
 
 /* Launch one kernel of the iteration `reps` times on `stream` over the

@@ -120,6 +120,9 @@ void internal_dims(const sip_grid& g, int64_t n[3], double h[3]) {
   }
 }
 
+// Internal grid axis of a sip_line (internal form (z, y, x); 2D has y = 1).
+int line_axis_of(int32_t line) { return line == SIP_LINE_Z ? 0 : (line == SIP_LINE_Y ? 1 : 2); }
+
 int64_t rows_of(const sip_grid& g, const sip_set& s) {
   OpInfo oi;
   if (!op_info(g.ndim, s.op, oi)) return -1;
@@ -158,6 +161,16 @@ int32_t validate(const sip_grid* g, const sip_set* sets, int32_t nsets, const si
     for (int c = 0; c < oi.ncomp; ++c)
       if (oi.axis[c] >= 0 && n[oi.axis[c]] < 2) return SIP_EINVAL;
     const int64_t M = rows_of(*g, s);
+    if (s.line != SIP_LINE_NONE) {
+      if (s.line != SIP_LINE_Z && s.line != SIP_LINE_Y && s.line != SIP_LINE_X) return SIP_EINVAL;
+      if (s.line == SIP_LINE_Y && g->ndim != 3) return SIP_EINVAL;
+      if (s.kind != SIP_SET_L1 && s.kind != SIP_SET_CARD && s.kind != SIP_SET_L2 && s.kind != SIP_SET_ANNULUS)
+        return SIP_EINVAL;
+      const int la = line_axis_of(s.line);
+      const int64_t cap = o->field == SIP_F64 ? LineCap<double>::v : LineCap<float>::v;
+      for (int c = 0; c < oi.ncomp; ++c)
+        if (n[la] - (oi.axis[c] == la ? 1 : 0) > cap) return SIP_EUNSUPPORTED;
+    }
     switch (s.kind) {
       case SIP_SET_BOUNDS:
         if (std::isnan(s.lo) || std::isnan(s.hi) || s.lo > s.hi) return SIP_EINVAL;
@@ -166,7 +179,7 @@ int32_t validate(const sip_grid* g, const sip_set* sets, int32_t nsets, const si
         if (!(s.tau >= 0.0) || !std::isfinite(s.tau)) return SIP_EINVAL;
         break;
       case SIP_SET_CARD:
-        if (s.k < 1 || s.k > M) return SIP_EINVAL;
+        if (s.k < 1 || (s.line == SIP_LINE_NONE && s.k > M)) return SIP_EINVAL;
         break;
       case SIP_SET_L2:
         if (!(s.tau >= 0.0) || !std::isfinite(s.tau)) return SIP_EINVAL;
@@ -185,7 +198,8 @@ int32_t validate(const sip_grid* g, const sip_set* sets, int32_t nsets, const si
 // Sets projected through the selection pipeline (a global reduction over
 // the set's rows decides the projection).
 bool is_thr(const sip_set& s) {
-  return s.kind == SIP_SET_L1 || s.kind == SIP_SET_CARD || s.kind == SIP_SET_L2 || s.kind == SIP_SET_ANNULUS;
+  return s.line == SIP_LINE_NONE &&
+         (s.kind == SIP_SET_L1 || s.kind == SIP_SET_CARD || s.kind == SIP_SET_L2 || s.kind == SIP_SET_ANNULUS);
 }
 
 // Byte layout of one instance's workspace.
@@ -296,6 +310,8 @@ struct sip_batch {
   uint32_t* d_tie = nullptr;
   int cap_ppt = 0, cap_pthr = 0, cap_psp = 0;   // item capacity of the partial-sum buffers
   sip::PtItem* d_sp = nullptr; int cap_sp = 0;
+  sip::LineItem* d_line = nullptr; int cap_line = 0;
+  double* d_linep = nullptr; int cap_plinep = 0;
   sip::Counts* d_counts = nullptr;
   sip::Tables tab{};
   int live_items = 0, live_inst = 0;
@@ -331,6 +347,7 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   std::vector<PtItem> pt, sp;
   std::vector<ThrItem> thr;
   std::vector<SelItem> sel;
+  std::vector<LineItem> line;
   std::vector<int32_t> inst;
   bool any_card = false;
   for (int si = 0; si < b->max_slots; ++si) {
@@ -358,6 +375,25 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
         sd.item_end[src] = (int)thr.size();
       }
     }
+    for (int k = 0; k < s.nsets; ++k) {
+      SetDesc& sd = s.desc.sets[k];
+      if (sd.line_axis < 0) continue;
+      sd.line_begin = (int)line.size();
+      const int la = sd.line_axis;
+      for (int c = 0; c < sd.ncomp; ++c) {
+        int64_t dims[3] = {s.desc.n[0], s.desc.n[1], s.desc.n[2]};
+        if (sd.axis[c] >= 0) dims[sd.axis[c]] -= 1;
+        if (dims[la] <= 0) continue;
+        const int64_t e0 = la == 0 ? 1 : dims[0], e1 = la == 1 ? 1 : dims[1], e2 = la == 2 ? 1 : dims[2];
+        for (int64_t i0 = 0; i0 < e0; ++i0)
+          for (int64_t i1 = 0; i1 < e1; ++i1)
+            for (int64_t i2 = 0; i2 < e2; ++i2)
+              line.push_back(LineItem{si, k, c, (int)dims[la],
+                                      (int)(i0 * s.desc.stride[0] + i1 * s.desc.stride[1] + i2),
+                                      (int)s.desc.stride[la]});
+      }
+      sd.line_end = (int)line.size();
+    }
   }
   // nothing queued may still read the tables or partial buffers replaced below
   HIP_OK(hipStreamSynchronize(stream));
@@ -367,18 +403,26 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   const int lpt = pow2((int)pt.size(), 64), lthr = pow2((int)thr.size(), 64);
   const int lsel = pow2((int)sel.size(), 8), linst = pow2((int)inst.size(), 8);
   const int lsp = pow2((int)sp.size(), 64);
+  const int lline = pow2((int)line.size(), 64);
   const bool relaunch = lpt != b->tab.npt || lthr != b->tab.nthr || lsel != b->tab.nsel || linst != b->tab.ninst ||
-                        lsp != b->tab.nsp || any_card != b->tab.any_card;
+                        lsp != b->tab.nsp || lline != b->tab.nline || any_card != b->tab.any_card;
   int32_t rc;
   const int old_pt = b->cap_pt, old_thr = b->cap_thr, old_sel = b->cap_sel, old_inst = b->cap_inst;
-  const int old_sp = b->cap_sp;
+  const int old_sp = b->cap_sp, old_line = b->cap_line;
   if ((rc = ensure(b->d_pt, b->cap_pt, std::max(lpt, 1), sizeof(PtItem)))) return rc;
   if ((rc = ensure(b->d_sp, b->cap_sp, std::max(lsp, 1), sizeof(PtItem)))) return rc;
   if ((rc = ensure(b->d_thr, b->cap_thr, std::max(lthr, 1), sizeof(ThrItem)))) return rc;
   if ((rc = ensure(b->d_sel, b->cap_sel, std::max(lsel, 1), sizeof(SelItem)))) return rc;
   if ((rc = ensure(b->d_inst, b->cap_inst, std::max(linst, 1), sizeof(int32_t)))) return rc;
+  if ((rc = ensure(b->d_line, b->cap_line, std::max(lline, 1), sizeof(LineItem)))) return rc;
   bool moved = old_pt != b->cap_pt || old_thr != b->cap_thr || old_sel != b->cap_sel || old_inst != b->cap_inst ||
-               old_sp != b->cap_sp;
+               old_sp != b->cap_sp || old_line != b->cap_line;
+  if (b->cap_plinep < b->cap_line) {
+    if (b->d_linep) HIP_OK(hipFree(b->d_linep));
+    HIP_OK(hipMalloc((void**)&b->d_linep, (size_t)b->cap_line * 8 * 8));
+    b->cap_plinep = b->cap_line;
+    moved = true;
+  }
   if (b->cap_ppt < b->cap_pt) {
     if (b->d_rr) {
       HIP_OK(hipFree(b->d_rr)); HIP_OK(hipFree(b->d_pq));
@@ -407,19 +451,22 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   }
   if (!b->d_counts) HIP_OK(hipMalloc((void**)&b->d_counts, sizeof(Counts)));
   const Counts counts{(int32_t)pt.size(), (int32_t)thr.size(), (int32_t)sel.size(), (int32_t)inst.size(),
-                      (int32_t)sp.size(), {0, 0, 0}};
+                      (int32_t)sp.size(), (int32_t)line.size(), {0, 0}};
   HIP_OK(hipMemcpyAsync(b->d_counts, &counts, sizeof(Counts), hipMemcpyHostToDevice, stream));
   if (!pt.empty()) HIP_OK(hipMemcpyAsync(b->d_pt, pt.data(), pt.size() * sizeof(PtItem), hipMemcpyHostToDevice, stream));
   if (!sp.empty()) HIP_OK(hipMemcpyAsync(b->d_sp, sp.data(), sp.size() * sizeof(PtItem), hipMemcpyHostToDevice, stream));
   if (!thr.empty()) HIP_OK(hipMemcpyAsync(b->d_thr, thr.data(), thr.size() * sizeof(ThrItem), hipMemcpyHostToDevice, stream));
   if (!sel.empty()) HIP_OK(hipMemcpyAsync(b->d_sel, sel.data(), sel.size() * sizeof(SelItem), hipMemcpyHostToDevice, stream));
   if (!inst.empty()) HIP_OK(hipMemcpyAsync(b->d_inst, inst.data(), inst.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  if (!line.empty())
+    HIP_OK(hipMemcpyAsync(b->d_line, line.data(), line.size() * sizeof(LineItem), hipMemcpyHostToDevice, stream));
   for (int si = 0; si < b->max_slots; ++si) {
     if (!b->slots[si].used) continue;
     HIP_OK(hipMemcpyAsync(b->d_desc + si, &b->slots[si].desc, sizeof(InstDesc), hipMemcpyHostToDevice, stream));
   }
   HIP_OK(hipStreamSynchronize(stream));
   Tables& t = b->tab;
+  bool relaunch_cap = false;
   t.D = b->d_desc;
   t.cnt = b->d_counts;
   t.pt = b->d_pt; t.npt = lpt;
@@ -429,14 +476,19 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   t.inst = b->d_inst; t.ninst = linst;
   t.rr_part = b->d_rr; t.pq_part = b->d_pq; t.proj_part = b->d_proj;
   t.rr2_part = b->d_rr2; t.pq2_part = b->d_pq2;
+  t.line = b->d_line; t.nline = lline; t.line_part = b->d_linep;
+  int cap = 2;
+  for (const LineItem& li : line) while (cap < li.len) cap <<= 1;
+  if (cap != t.line_cap) relaunch_cap = true;
+  t.line_cap = cap;
   t.thrw_part = b->d_thrw; t.thra_part = b->d_thra; t.tie_part = b->d_tie;
   t.any_card = any_card;
   const bool threads_changed = t.pt_threads != (int)b->tiles.pt_threads || t.cg_form != b->tiles.cg_form;
   t.pt_threads = (int)b->tiles.pt_threads;
   t.cg_form = b->tiles.cg_form;
-  b->live_items = (int)pt.size() + (int)thr.size();
+  b->live_items = (int)pt.size() + (int)thr.size() + (int)line.size();
   b->live_inst = (int)inst.size();
-  if (relaunch || moved || threads_changed) drop_graphs(b);
+  if (relaunch || moved || threads_changed || relaunch_cap) drop_graphs(b);
   b->dirty = false;
   return SIP_OK;
 }
@@ -574,7 +626,8 @@ int32_t sip_batch_destroy(sip_batch* b) {
   drop_graphs(b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   void* dev[] = {b->d_desc, b->d_scal, b->d_pt, b->d_thr, b->d_sel, b->d_inst, b->d_rr, b->d_pq,
-                 b->d_rr2, b->d_pq2, b->d_proj, b->d_thrw, b->d_thra, b->d_tie, b->d_counts, b->d_sp};
+                 b->d_rr2, b->d_pq2, b->d_proj, b->d_thrw, b->d_thra, b->d_tie, b->d_counts, b->d_sp,
+                 b->d_line, b->d_linep};
   for (void* p : dev) if (p) (void)hipFree(p);
   if (b->h_scal) (void)hipHostFree(b->h_scal);
   delete b;
@@ -638,6 +691,7 @@ int32_t sip_batch_add(sip_batch* b, const sip_grid* g, const sip_set* sets, int3
     sd.kind = sets[i].kind; sd.op = sets[i].op; sd.ncomp = oi.ncomp;
     for (int c = 0; c < 3; ++c) sd.axis[c] = c < oi.ncomp ? oi.axis[c] : -1;
     sd.thr = is_thr(sets[i]) ? nthr++ : -1;
+    sd.line_axis = sets[i].line != SIP_LINE_NONE ? line_axis_of(sets[i].line) : -1;
     sd.lo = sets[i].lo; sd.hi = sets[i].hi; sd.tau = sets[i].tau; sd.k = sets[i].k;
     sd.rows = rows_of(*g, sets[i]);
     const auto& SL = L.set[i];
@@ -873,7 +927,7 @@ int32_t sip_batch_reset(sip_batch* b, int32_t slot, const void* m_dev, void* str
 }
 
 int32_t sip_batch_time_kernel(sip_batch* b, int32_t kernel, int32_t reps, void* stream_, double* avg_ms) {
-  if (!b || kernel < SIP_K_RHS || kernel > SIP_K_CG1_W0 || reps < 1 || !avg_ms) return SIP_EINVAL;
+  if (!b || kernel < SIP_K_RHS || kernel > SIP_K_LINE || reps < 1 || !avg_ms) return SIP_EINVAL;
   hipStream_t stream = (hipStream_t)stream_;
   if (b->dirty) {
     const int32_t rc = rebuild_tables(b, stream);
@@ -1107,7 +1161,7 @@ int32_t sip_project_multilevel(const sip_grid* g, const sip_set* sets, int32_t n
   int32_t rc = validate(g, sets, nsets, o);
   if (rc != SIP_OK) return rc;
   for (int i = 0; i < nsets; ++i)
-    if (sets[i].lo_vec || sets[i].hi_vec) return SIP_EUNSUPPORTED;
+    if (sets[i].lo_vec || sets[i].hi_vec || sets[i].line != SIP_LINE_NONE) return SIP_EUNSUPPORTED;
   std::vector<sip_grid> grids(nlevels);
   std::vector<std::vector<sip_set>> lsets(nlevels, std::vector<sip_set>(std::max(nsets, 1)));
   for (int l = 0; l < nlevels; ++l) {

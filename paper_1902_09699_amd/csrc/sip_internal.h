@@ -74,7 +74,7 @@ constexpr unsigned long long kCandCap = 16384;
 struct SetDesc {
   int32_t kind, op, ncomp, thr;   // thr: index among threshold sets or -1
   int32_t axis[3];                // grid axis of each component (-1: identity)
-  int32_t pad_;
+  int32_t line_axis;              // line-wise set: grid axis of its lines; -1: whole vector
   double lo, hi, tau;
   int64_t k, rows;                // rows = M_i
   void* y; void* v;               // ncomp blocks of N
@@ -86,6 +86,7 @@ struct SetDesc {
   double* hsum[2];
   void* cand[2];                  // candidate keys (u32 or u64), ncomp*N entries
   int32_t item_begin[2], item_end[2];  // threshold-item range of each pipeline
+  int32_t line_begin, line_end;        // line-item range of a line-wise set
 };
 
 struct FastDiv {                  // n / d for 0 <= n < 2^31 (Granlund-Montgomery)
@@ -138,7 +139,17 @@ struct Opts {                     // options every kernel needs, by value
 // Live item counts of the work tables, read by the kernels from device
 // memory so a captured graph (launched over the table capacities) stays valid
 // when instances are admitted or retired.
-struct Counts { int32_t npt, nthr, nsel, ninst, nsp, pad_[3]; };
+struct Counts { int32_t npt, nthr, nsel, ninst, nsp, nline, pad_[2]; };
+
+// One line of one component of a line-wise set: points start + t * stride,
+// t = 0 .. len-1 (grid indexing of the component's block).
+struct LineItem {
+  int32_t inst, set, comp, len;
+  int32_t start, stride;
+};
+
+// Longest line a block sorts in LDS.
+template <typename T> struct LineCap { static constexpr int v = sizeof(T) == 4 ? 4096 : 2048; };
 
 // Device work tables and partial-sum buffers of one batch.  npt, nthr, nsel
 // and ninst are the launch sizes (capacities); cnt holds the live counts.
@@ -152,6 +163,9 @@ struct Tables {
   const int32_t* inst; int ninst;
   double* rr_part; double* pq_part; double* proj_part; double* thrw_part; double* thra_part;
   double* rr2_part; double* pq2_part;  // one-reduction CG: odd-step partials
+  const LineItem* line; int nline;     // line items of line-wise sets
+  int line_cap;                        // power of two >= the longest line (LDS entries per block)
+  double* line_part;                   // 8 partial sums per line item
   uint32_t* tie_part;
   bool any_card;
   int pt_threads;  // threads per block of the RHS and CG kernels (256 or 512)

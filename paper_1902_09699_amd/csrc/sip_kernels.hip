@@ -1315,7 +1315,7 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
   for (int u = 0; u <= d.nsets; ++u) {
     const bool ident = (u == d.nsets);
     const SetDesc* s = ident ? nullptr : &d.sets[u];
-    if (!ident && s->thr >= 0) continue;
+    if (!ident && (s->thr >= 0 || s->line_axis >= 0)) continue;
     const double rho_d = S[S_RHO + u];
     ProjUnit<T> U;
     U.rho = (T)rho_d; U.gam = (T)S[S_GAMMA + u]; U.irho = (T)(1.0 / rho_d);
@@ -2462,6 +2462,324 @@ __global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ 
   }
 }
 
+// ------------------------------------------------- line-wise threshold sets
+//
+// A set that acts on every line (row, column or fiber) of A x on its own:
+// one block per line.  The line's w goes to LDS; the l1 ball and the
+// cardinality set sort it there (a bitonic network on (|w|, index): larger
+// magnitude first, ties to the lower index along the line), the l2 ball and
+// the annulus only need the line's norm.  Lines are at most LineCap<T>::v
+// long (longer ones are rejected at admission).
+
+constexpr int kLB = 256;  // threads per line block
+
+// How one line is projected.
+enum LineMode : int { LM_KEEP = 0, LM_SOFT = 1, LM_ZERO = 2, LM_TOPK = 3, LM_SCALE = 4, LM_POINT = 5 };
+
+template <typename T>
+struct LineProj {
+  int mode;
+  T theta;                        // LM_SOFT: soft threshold; LM_SCALE: factor; LM_POINT: lo
+  typename KeyT<T>::K tkey;       // LM_TOPK: the k-th (key, index)
+  uint32_t tidx;
+};
+
+template <typename T>
+__device__ __forceinline__ T line_apply(const LineProj<T>& q, T w, int e) {
+  using KT = KeyT<T>;
+  switch (q.mode) {
+    case LM_SOFT: {
+      const T a = (w < 0 ? -w : w) - q.theta;
+      return a > 0 ? (w < 0 ? -a : a) : (T)0;
+    }
+    case LM_ZERO: return (T)0;
+    case LM_TOPK: {
+      const typename KT::K key = KT::key(w);
+      return (key > q.tkey || (key == q.tkey && (uint32_t)e <= q.tidx)) ? w : (T)0;
+    }
+    case LM_SCALE: return q.theta * w;
+    case LM_POINT: return e == 0 ? q.theta : (T)0;
+    default: return w;
+  }
+}
+
+// Block sum (every thread gets it) of one value per thread.
+__device__ __forceinline__ acc_t line_sum(acc_t v, acc_t* lds) {
+  acc_t a[1] = {v};
+  block_sum<1, kLB>(a, lds);
+  return a[0];
+}
+
+// Block maximum of one int per thread.
+__device__ __forceinline__ int line_max(int v, int* ldi) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int u = __shfl_xor(v, o, 64);
+    v = u > v ? u : v;
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) ldi[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int m = ldi[0];
+  for (int q = 1; q < kLB / 64; ++q) m = ldi[q] > m ? ldi[q] : m;
+  return m;
+}
+
+// Sort lv[0..L) by (|value| descending, index ascending) into (lk, li).
+template <typename T>
+__device__ void line_sort(const T* lv, int L, typename KeyT<T>::K* lk, uint32_t* li) {
+  using KT = KeyT<T>;
+  int Lp = 2;
+  while (Lp < L) Lp <<= 1;
+  for (int i = threadIdx.x; i < Lp; i += kLB) {
+    lk[i] = i < L ? KT::key(lv[i]) : (typename KT::K)0;
+    li[i] = i < L ? (uint32_t)i : 0xffffffffu;
+  }
+  __syncthreads();
+  for (int k2 = 2; k2 <= Lp; k2 <<= 1) {
+    for (int j = k2 >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < Lp; i += kLB) {
+        const int ixj = i ^ j;
+        if (ixj <= i) continue;
+        const typename KT::K ka = lk[i], kb = lk[ixj];
+        const uint32_t ia = li[i], ib = li[ixj];
+        // a sorts before b: larger key, then smaller index
+        const bool a_first = ka > kb || (ka == kb && ia < ib);
+        const bool up = (i & k2) == 0;
+        if (up ? !a_first : a_first) {
+          lk[i] = kb; lk[ixj] = ka;
+          li[i] = ib; li[ixj] = ia;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Cardinality with small k: the k-th entry of the line in the order
+// (|value| descending, index ascending) by k rounds of a block-wide argmax,
+// each over the entries after the previous round's pick.  Exact (keys and
+// indices only), so the same entry as the sort finds.
+constexpr int kTopkRounds = 32;
+
+template <typename T>
+__device__ void line_kth(const T* lv, int L, int k, typename KeyT<T>::K& tkey, uint32_t& tidx,
+                         typename KeyT<T>::K* rk, uint32_t* ri) {
+  using KT = KeyT<T>;
+  using K = typename KT::K;
+  K pk = ~(K)0;            // previous pick: above every key
+  uint32_t pi = 0;
+  for (int round = 0; round < k; ++round) {
+    K bk = 0;
+    uint32_t bi = 0xffffffffu;
+    for (int e = threadIdx.x; e < L; e += kLB) {
+      const K key = KT::key(lv[e]);
+      const bool after = key < pk || (key == pk && (uint32_t)e > pi);
+      const bool first = key > bk || (key == bk && (uint32_t)e < bi);
+      if (after && first) { bk = key; bi = (uint32_t)e; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const K ok = __shfl_xor(bk, o, 64);
+      const uint32_t oi = __shfl_xor(bi, o, 64);
+      if (ok > bk || (ok == bk && oi < bi)) { bk = ok; bi = oi; }
+    }
+    const int slot = (round & 1) * (kLB / 64);
+    if ((threadIdx.x & 63) == 0) { rk[slot + (threadIdx.x >> 6)] = bk; ri[slot + (threadIdx.x >> 6)] = bi; }
+    __syncthreads();
+    for (int q = 0; q < kLB / 64; ++q) {
+      const K ok = rk[slot + q];
+      const uint32_t oi = ri[slot + q];
+      if (ok > bk || (ok == bk && oi < bi)) { bk = ok; bi = oi; }
+    }
+    pk = bk;
+    pi = bi;
+  }
+  tkey = pk;
+  tidx = pi;
+}
+
+// The projection of the line lv[0..L) onto the set (l1 by the sorted
+// prefix-sum rule of the whole-vector l1 projection; cardinality by the k-th
+// sorted entry; l2 / annulus by the norm).
+template <typename T>
+__device__ LineProj<T> line_params(const SetDesc& s, int L, const T* lv, typename KeyT<T>::K* lk, uint32_t* li,
+                                   acc_t* lds, int* ldi) {
+  using KT = KeyT<T>;
+  LineProj<T> q{LM_KEEP, (T)0, 0, 0};
+  if (s.kind == SIP_SET_L2 || s.kind == SIP_SET_ANNULUS) {
+    acc_t t = 0;
+    for (int e = threadIdx.x; e < L; e += kLB) t += (acc_t)lv[e] * (acc_t)lv[e];
+    const double nrm = sqrt((double)line_sum(t, lds));
+    if (s.kind == SIP_SET_L2) {
+      if (nrm > s.tau) { q.mode = LM_SCALE; q.theta = (T)(s.tau / nrm); }
+    } else if (nrm > s.hi) {
+      q.mode = LM_SCALE; q.theta = (T)(s.hi / nrm);
+    } else if (nrm < s.lo) {
+      if (nrm > 0.0) { q.mode = LM_SCALE; q.theta = (T)(s.lo / nrm); }
+      else { q.mode = LM_POINT; q.theta = (T)s.lo; }
+    }
+    return q;
+  }
+  if (s.kind == SIP_SET_CARD) {
+    if (s.k >= L) return q;
+    q.mode = LM_TOPK;
+    if (s.k <= kTopkRounds) {
+      __shared__ typename KT::K rk[2 * kLB / 64];
+      __shared__ uint32_t ri[2 * kLB / 64];
+      line_kth<T>(lv, L, (int)s.k, q.tkey, q.tidx, rk, ri);
+      return q;
+    }
+    line_sort<T>(lv, L, lk, li);
+    q.tkey = lk[s.k - 1];
+    q.tidx = li[s.k - 1];
+    return q;
+  }
+  // l1 ball
+  if (!(s.tau > 0.0)) { q.mode = LM_ZERO; return q; }
+  acc_t t = 0;
+  for (int e = threadIdx.x; e < L; e += kLB) t += (acc_t)fabs((double)lv[e]);
+  if (line_sum(t, lds) <= (acc_t)s.tau) return q;
+  line_sort<T>(lv, L, lk, li);
+  // running sums c_r over the sorted magnitudes: each thread owns a
+  // contiguous chunk of positions; chunk totals are scanned in thread order
+  const int chunk = (L + kLB - 1) / kLB;
+  const int r0 = threadIdx.x * chunk, r1 = r0 + chunk < L ? r0 + chunk : L;
+  acc_t own = 0;
+  for (int r = r0; r < r1; ++r) own += (acc_t)KT::value(lk[r]);
+  acc_t* scan = lds + lds_sum<1, kLB>();
+  __syncthreads();
+  scan[threadIdx.x] = own;
+  __syncthreads();
+  acc_t c = 0;
+  for (int q2 = 0; q2 < (int)threadIdx.x; ++q2) c += scan[q2];
+  // rho = the largest r + 1 with a_r - (c_r - tau) / (r + 1) > 0
+  int best = 0;
+  acc_t cc = c;
+  for (int r = r0; r < r1; ++r) {
+    const acc_t a = (acc_t)KT::value(lk[r]);
+    cc += a;
+    if (a - (cc - (acc_t)s.tau) / (acc_t)(r + 1) > 0) best = r + 1;
+  }
+  const int rho = line_max(best, ldi);
+  __shared__ acc_t th_s;
+  cc = c;
+  for (int r = r0; r < r1; ++r) {
+    cc += (acc_t)KT::value(lk[r]);
+    if (r + 1 == rho) th_s = (cc - (acc_t)s.tau) / (acc_t)rho;
+  }
+  __syncthreads();
+  q.mode = LM_SOFT;
+  q.theta = (T)th_s;
+  return q;
+}
+
+// One line: pass 1 computes s = (A x) on the line, x-bar, w = x-bar - v/rho
+// into LDS and the v-hat snapshot with its adapt dots; the line projection;
+// pass 2 writes y = P(w), v = rho (y - w) and the y / v snapshots with their
+// dots; on stopping-test iterations the same projection of s gives the
+// feasibility distance.  Partial sums as the projection kernel's units.
+// Dynamic LDS: cap (a power of two >= the batch's longest line) values, keys
+// and indices.
+template <typename T>
+constexpr size_t line_lds_per_entry() { return sizeof(T) + sizeof(typename KeyT<T>::K) + 4; }
+
+template <typename T>
+__global__ __launch_bounds__(kLB) void k_line(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt,
+                                              const LineItem* __restrict__ items, Opts o, double* parts, int cap) {
+  using KT = KeyT<T>;
+  extern __shared__ __align__(16) unsigned char line_smem[];
+  typename KT::K* lk = (typename KT::K*)line_smem;
+  T* lv = (T*)(line_smem + (size_t)cap * sizeof(typename KT::K));
+  uint32_t* li = (uint32_t*)(line_smem + (size_t)cap * (sizeof(typename KT::K) + sizeof(T)));
+  __shared__ acc_t lds[lds_sum<8, kLB>() + kLB];
+  __shared__ int ldi[kLB / 64];
+  if ((int)blockIdx.x >= cnt->nline) return;
+  const int iti = xcd_item(blockIdx.x, cnt->nline);
+  const LineItem it = items[iti];
+  const InstDesc& d = D[it.inst];
+  const double* S = d.scal;
+  if (!inst_live(S)) return;
+  const int k = (int)S[S_K];
+  const bool adapt = is_adapt_iter(k, o);
+  const bool check = is_check_iter(k, o);
+  const bool have = S[S_HAVE_SNAP] != 0.0;
+  const int call = adapt ? adapt_call(k, o) : 0;
+  const SetDesc& s = d.sets[it.set];
+  const Geo g(d);
+  const int axis = s.axis[it.comp];
+  const size_t off = (size_t)it.comp * g.cs;
+  T* y = (T*)s.y + off;
+  T* v = (T*)s.v + off;
+  T* vh0 = (T*)s.vh0 + off;
+  T* v0 = (T*)s.v0 + off;
+  T* y0 = (T*)s.y0 + off;
+  const T* x = (const T*)d.x;
+  const T* xr = (const T*)d.xs[(call & 1) ^ 1];
+  const double rho_d = S[S_RHO + it.set];
+  const T rho = (T)rho_d, gam = (T)S[S_GAMMA + it.set], one_m_g = (T)(1.0 - S[S_GAMMA + it.set]);
+  const T irho = (T)(1.0 / rho_d);
+  const int ast = axis == 0 ? g.sz : (axis == 1 ? g.sy : 1);
+  const T h = axis >= 0 ? (T)d.hinv[axis] : (T)1;
+  auto sval = [&](const T* f, int P) -> T { return axis < 0 ? f[P] : (f[P + ast] - f[P]) * h; };
+  const int L = it.len;
+  acc_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int e = threadIdx.x; e < L; e += kLB) {
+    const int P = it.start + e * it.stride;
+    const T sp = sval(x, P);
+    const T yo = y[P], vo = v[P];
+    lv[e] = gam * sp + one_m_g * yo - vo * irho;
+    if (adapt) {
+      const T vh = vo + rho * (yo - sp);
+      if (have) {
+        const acc_t dh = (acc_t)sp - (acc_t)sval(xr, P);
+        const acc_t dvh = (acc_t)vh - (acc_t)vh0[P];
+        acc[0] += dh * dvh; acc[1] += dh * dh; acc[2] += dvh * dvh;
+      }
+      vh0[P] = vh;
+    }
+  }
+  __syncthreads();
+  const LineProj<T> qw = line_params<T>(s, L, lv, lk, li, lds, ldi);
+  for (int e = threadIdx.x; e < L; e += kLB) {
+    const int P = it.start + e * it.stride;
+    const T w = lv[e];
+    const T r = line_apply<T>(qw, w, e);
+    const T vn = rho * (r - w);
+    y[P] = r;
+    v[P] = vn;
+    if (adapt) {
+      if (have) {
+        const acc_t dg = -((acc_t)r - (acc_t)y0[P]);
+        const acc_t dv = (acc_t)vn - (acc_t)v0[P];
+        acc[3] += dg * dv; acc[4] += dg * dg; acc[5] += dv * dv;
+      }
+      y0[P] = r;
+      v0[P] = vn;
+    }
+  }
+  if (check) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < L; e += kLB) {
+      const T sp = sval(x, it.start + e * it.stride);
+      lv[e] = sp;
+      acc[7] += (acc_t)sp * (acc_t)sp;
+    }
+    __syncthreads();
+    const LineProj<T> qs = line_params<T>(s, L, lv, lk, li, lds, ldi);
+    for (int e = threadIdx.x; e < L; e += kLB) {
+      const T sp = lv[e];
+      const acc_t df = (acc_t)sp - (acc_t)line_apply<T>(qs, sp, e);
+      acc[6] += df * df;
+    }
+  }
+  block_sum<8, kLB>(acc, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) parts[(size_t)iti * 8 + q] = acc[q];
+  }
+}
+
 // ----------------------------------------------------- end of iteration
 
 __device__ bool spectral(double ab, double aa, double bb, double eps, double& est) {
@@ -2481,7 +2799,7 @@ __device__ bool spectral(double ab, double aa, double bb, double eps, double& es
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const int32_t* __restrict__ insts, Opts o,
                                                    const double* proj_parts, const double* thrw_parts,
-                                                   const double* thra_parts) {
+                                                   const double* thra_parts, const double* line_parts) {
   __shared__ acc_t tout[4 * kMaxUnits + 2][8];
   __shared__ acc_t dots[kMaxUnits][8];
   __shared__ acc_t evol[16];
@@ -2522,7 +2840,12 @@ __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* __restrict__ 
       rem -= nt;
     }
     if (u < ntask_units) {
-      if (unit_tasks(u) == 1 && !(u < p && d.sets[u].thr >= 0)) {
+      if (u < p && d.sets[u].line_axis >= 0) {
+        parts = line_parts;
+        b = d.sets[u].line_begin;
+        e = d.sets[u].line_end;
+        stride = 8;
+      } else if (unit_tasks(u) == 1 && !(u < p && d.sets[u].thr >= 0)) {
         off = u * kUnitParts;
       } else {
         const SetDesc& sd = d.sets[u];
@@ -2586,7 +2909,7 @@ __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* __restrict__ 
       double num = dots[u][6];
       const double den = dots[u][7];
       const SetDesc& s = d.sets[u];
-      if (s.kind == SIP_SET_L2 || s.kind == SIP_SET_ANNULUS) {
+      if ((s.kind == SIP_SET_L2 || s.kind == SIP_SET_ANNULUS) && s.line_axis < 0) {
         // distance of s to the ball / shell from ||s|| (= sqrt(den)) alone
         const double nrm = sqrt(den);
         const double lo = s.kind == SIP_SET_L2 ? 0.0 : s.lo, hi = s.kind == SIP_SET_L2 ? s.tau : s.hi;
@@ -2719,13 +3042,17 @@ void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
     if (t.any_card) k_card_ties<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.tie_part);
     k_thr_apply<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thra_part, t.tie_part);
   }
+  if (t.nline > 0)
+    k_line<T><<<t.nline, kLB, t.line_cap * line_lds_per_entry<T>(), st>>>(t.D, t.cnt, t.line, o, t.line_part,
+                                                                         t.line_cap);
   if (t.ninst > 0)
-    k_finish<T><<<t.ninst, kBlock, 0, st>>>(t.D, t.cnt, t.inst, o, t.proj_part, t.thrw_part, t.thra_part);
+    k_finish<T><<<t.ninst, kBlock, 0, st>>>(t.D, t.cnt, t.inst, o, t.proj_part, t.thrw_part, t.thra_part,
+                                            t.line_part);
 }
 
 // One kernel of the iteration on its own (timing); CG kernels use step 1.
 // 0 rhs, 1 cg_dir, 2 cg_upd, 3 proj, 4 thr_w, 5 thr_apply, 6 one-reduction
-// CG step, 7 its w_0 = C r_0 pass.
+// CG step, 7 its w_0 = C r_0 pass, 8 line-wise sets.
 template <typename T>
 void launch_phase(hipStream_t st, const Tables& t, const Opts& o, int phase) {
   switch (phase) {
@@ -2740,6 +3067,11 @@ void launch_phase(hipStream_t st, const Tables& t, const Opts& o, int phase) {
     case 3: if (t.nsp) k_proj<T><<<t.nsp, kSB, 0, st>>>(t.D, t.cnt, t.sp, o, t.proj_part); break;
     case 4: if (t.nthr) k_thr_w<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thrw_part); break;
     case 5: if (t.nthr) k_thr_apply<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thra_part, t.tie_part); break;
+    case 8:
+      if (t.nline)
+        k_line<T><<<t.nline, kLB, t.line_cap * line_lds_per_entry<T>(), st>>>(t.D, t.cnt, t.line, o, t.line_part,
+                                                                             t.line_cap);
+      break;
     default: break;
   }
 }

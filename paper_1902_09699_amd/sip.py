@@ -22,7 +22,7 @@ OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED, EBUDGET = 0, -1, -2, -3, -4, -
 F32, F64 = 0, 1
 OPS = {"I": 0, "DZ": 1, "DY": 2, "DX": 3, "GRAD": 4, "LAT": 5}
 KINDS = {"bounds": 0, "l1": 1, "card": 2, "l2": 3, "annulus": 4}
-K_RHS, K_CG_DIR, K_CG_UPD, K_PROJ, K_THR_W, K_THR_APPLY, K_CG1_STEP, K_CG1_W0 = range(8)
+K_RHS, K_CG_DIR, K_CG_UPD, K_PROJ, K_THR_W, K_THR_APPLY, K_CG1_STEP, K_CG1_W0, K_LINE = range(9)
 FIELD_Y, FIELD_V, FIELD_VHAT0, FIELD_V0, FIELD_Y0, FIELD_R, FIELD_XS0, FIELD_XS1 = range(8)
 
 
@@ -32,7 +32,12 @@ class Grid(C.Structure):
 
 class Set(C.Structure):
     _fields_ = [("kind", C.c_int32), ("op", C.c_int32), ("lo", C.c_double), ("hi", C.c_double),
-                ("tau", C.c_double), ("k", C.c_int64), ("lo_vec", C.c_void_p), ("hi_vec", C.c_void_p)]
+                ("tau", C.c_double), ("k", C.c_int64), ("lo_vec", C.c_void_p), ("hi_vec", C.c_void_p),
+                ("line", C.c_int32), ("reserved_", C.c_int32)]
+
+
+# line-wise sets: the axis of the lines ("z", "y", "x"; 2D: "x" rows, "z" columns)
+LINES = {None: 0, "z": 1, "y": 2, "x": 3}
 
 
 class Opts(C.Structure):
@@ -158,6 +163,7 @@ def make_set(d: dict) -> Set:
     s.hi = float(d.get("hi", math.inf))
     s.tau = float(d.get("tau", 0.0))
     s.k = int(d.get("k", 0))
+    s.line = LINES[d.get("line")]
     # per-row bound vectors: device tensors of the field type, one block of N
     # per operator component (the grid layout of the operator's rows)
     for key in ("lo_vec", "hi_vec"):

@@ -144,6 +144,20 @@ def layered2d_four_sets(n=(341, 1361), seed=1002):
     return m, sets, "f32", 300
 
 
+def layered2d_line_sets(n=(341, 1361), seed=1004):
+    """The layered section under the set list of the paper's full-waveform
+    example without its rank set: box [1.5, 4.5], at most n_x nonzeros of
+    D_z and n_z of D_x over the whole model, at most two nonzeros of D_x in
+    every row and of D_z in every column; 300 iterations x 10 CG steps;
+    float32."""
+    rng = rng_for(seed)
+    m = layered(n, rng)
+    nz, nx = n
+    sets = [bounds("I", 1.5, 4.5), {"kind": "card", "op": "DZ", "k": nx}, {"kind": "card", "op": "DX", "k": nz},
+            {"kind": "card", "op": "DX", "k": 2, "line": "x"}, {"kind": "card", "op": "DZ", "k": 2, "line": "z"}]
+    return m, sets, "f32", 300
+
+
 def smooth3d_box_tv_lat(n=(200, 200, 100), seed=1003):
     """200x200x100 smooth field; box [-1, 1], TV ball at 0.4 of the field's
     TV, lateral slope bounds |D_x x|, |D_y x| <= 0.05; 200 iterations x 10 CG

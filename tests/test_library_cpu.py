@@ -145,3 +145,33 @@ def test_bound_vectors_only_for_bounds(L):
     arr = sip.make_sets([{"kind": "bounds", "op": "DX", "lo": -1.0, "hi": 1.0}])
     arr[0].hi_vec = 16
     assert sip.lib().sip_validate(sip.C.byref(g), arr, 1, sip.C.byref(sip.make_opts())) == 0
+
+
+@pytest.mark.parametrize("shape,s,field,rc", [
+    ((8, 9), {"kind": "card", "op": "DX", "k": 2, "line": "x"}, "f32", 0),
+    ((8, 9), {"kind": "card", "op": "DZ", "k": 50, "line": "z"}, "f32", 0),     # k above the line length: keep all
+    ((8, 9), {"kind": "l1", "op": "GRAD", "tau": 1.0, "line": "z"}, "f64", 0),
+    ((4, 5, 6), {"kind": "l2", "op": "LAT", "tau": 1.0, "line": "y"}, "f32", 0),
+    ((4, 5, 6), {"kind": "annulus", "op": "I", "lo": 0.5, "hi": 1.0, "line": "x"}, "f64", 0),
+    ((8, 9), {"kind": "l1", "op": "DX", "tau": 1.0, "line": "y"}, "f32", "EINVAL"),  # no y axis in 2D
+    ((8, 9), {"kind": "bounds", "op": "I", "lo": 0, "hi": 1, "line": "x"}, "f32", "EINVAL"),
+    ((3, 4097), {"kind": "card", "op": "I", "k": 2, "line": "x"}, "f32", "EUNSUPPORTED"),
+    ((3, 4097), {"kind": "card", "op": "DX", "k": 2, "line": "x"}, "f32", 0),  # D_x rows hold 4096
+    ((3, 2049), {"kind": "card", "op": "I", "k": 2, "line": "x"}, "f64", "EUNSUPPORTED"),
+    ((3, 2049), {"kind": "card", "op": "I", "k": 2, "line": "z"}, "f64", 0),
+])
+def test_validation_line_sets(L, shape, s, field, rc):
+    want = 0 if rc == 0 else getattr(sip, rc)
+    assert sip.validate(shape, [s], sip.make_opts(field)) == want
+
+
+def test_multilevel_rejects_line_sets_on_host(L):
+    """The multilevel entry point refuses line-wise sets before touching the
+    device (null device pointers are never dereferenced on this path)."""
+    g = sip.make_grid((16, 16))
+    arr = sip.make_sets([{"kind": "l1", "op": "DX", "tau": 1.0, "line": "x"}])
+    iters = (sip.C.c_int32 * 2)(5, 5)
+    res = sip.Result()
+    rc = sip.lib().sip_project_multilevel(sip.C.byref(g), arr, 1, sip.C.byref(sip.make_opts()), 2, iters, 0,
+                                          sip.C.c_void_p(16), sip.C.c_void_p(16), sip.C.byref(res), None, None)
+    assert rc == sip.EUNSUPPORTED
