@@ -338,6 +338,21 @@ int32_t sip_project_multilevel(const sip_grid* g, const sip_set* sets, int32_t n
                                const void* m_dev, void* x_dev, sip_result* res, int32_t* level_iters_run,
                                void* stream);
 
+/* ---------------------------------------------------------------- parallel Dykstra
+ * The paper's baseline for its PARSDMM comparison (Appendix A, the
+ * Parallel-DYKSTRA listing): x^0 = m, v_i^0 = m; each iteration projects
+ * every v_i onto V_i = {x | A_i x in C_i} (independently: the single-set
+ * PARSDMM instances of one batch, the paper's inner adaptive ADMM), then
+ * x = sum_i w_i y_i and v_i = x + v_i - y_i.  This call does the last two
+ * steps on the device: y[i], v[i] (i < p) and x are device arrays of n
+ * elements of the field type (float for SIP_F32, double for SIP_F64),
+ * caller-owned; w holds p host weights (the listing asks for sum 1; not
+ * enforced).  x must not alias any y[i] or v[i].  Asynchronous on `stream`.
+ * SIP_EINVAL for p outside [1, SIP_MAX_SETS], a null pointer, n < 0 or
+ * another field. */
+int32_t sip_dykstra_update(int32_t p, const void* const* y, void* const* v, const double* w, void* x, int64_t n,
+                           int32_t field, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

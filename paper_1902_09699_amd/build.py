@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsip.so")
-SOURCES = ["sip_kernels.hip", "sip_kernels_r32.hip", "sip_levels.hip", "sip_engine.hip"]
+SOURCES = ["sip_kernels.hip", "sip_kernels_r32.hip", "sip_levels.hip", "sip_dykstra.hip", "sip_engine.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

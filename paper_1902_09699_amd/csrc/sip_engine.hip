@@ -31,6 +31,8 @@ template <typename T> void launch_phase(hipStream_t st, const Tables& t, const O
 using r64::launch_init;
 using r64::launch_zero;
 using r64::launch_copy;
+int32_t launch_dykstra(hipStream_t st, int p, const void* const* y, void* const* v, const double* w, void* x,
+                       int64_t n, bool f64);
 // level transfer of multilevel PARSDMM
 template <typename T>
 void launch_restrict(hipStream_t st, const T* src, const int64_t (&n)[3], T* dst, const int64_t (&c)[3]);
@@ -961,6 +963,16 @@ int32_t sip_stream_copy(void* dst, const void* src, int64_t bytes, void* stream_
   if (!dst || !src || bytes < 0 || bytes % 16) return SIP_EINVAL;
   launch_copy((hipStream_t)stream_, dst, src, bytes / 16);
   return hipGetLastError() == hipSuccess ? SIP_OK : SIP_EHIP;
+}
+
+int32_t sip_dykstra_update(int32_t p, const void* const* y, void* const* v, const double* w, void* x, int64_t n,
+                           int32_t field, void* stream_) {
+  if (p < 1 || p > SIP_MAX_SETS || !y || !v || !w || !x || n < 0 || (field != SIP_F32 && field != SIP_F64))
+    return SIP_EINVAL;
+  for (int i = 0; i < p; ++i)
+    if (!y[i] || !v[i]) return SIP_EINVAL;
+  if (n == 0) return SIP_OK;
+  return launch_dykstra((hipStream_t)stream_, p, y, v, w, x, n, field == SIP_F64);
 }
 
 int32_t sip_batch_set_tiles(sip_batch* b, int32_t pt_points, int32_t pt_max_items, int32_t thr_points,

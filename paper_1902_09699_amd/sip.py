@@ -113,6 +113,7 @@ def lib():
         "sip_restrict": (i32, [C.POINTER(Grid), i32, vp, vp, vp]),
         "sip_project_multilevel": (i32, [C.POINTER(Grid), C.POINTER(Set), i32, C.POINTER(Opts), i32,
                                          C.POINTER(i32), i32, vp, vp, C.POINTER(Result), C.POINTER(i32), vp]),
+        "sip_dykstra_update": (i32, [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_double), vp, i64, i32, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -128,7 +129,7 @@ def exported_symbols():
             "sip_batch_run", "sip_batch_poll", "sip_batch_remove", "sip_batch_result", "sip_batch_field",
             "sip_batch_get_params", "sip_batch_set_params", "sip_batch_schedule", "sip_batch_set_tiles",
             "sip_batch_items", "sip_batch_reset", "sip_batch_time_kernel", "sip_stream_copy", "sip_level",
-            "sip_restrict", "sip_project_multilevel"]
+            "sip_restrict", "sip_project_multilevel", "sip_dykstra_update"]
 
 
 def strerror(status: int) -> str:
@@ -479,6 +480,22 @@ class Batch:
         a, b, c, d = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         check(lib().sip_batch_items(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)), "sip_batch_items")
         return a.value, b.value, c.value, d.value
+
+
+def dykstra_update(ys, vs, weights, x, stream=None):
+    """Parallel Dykstra steps 2-3 on the device: x = sum_i w_i y_i, then
+    v_i = x + v_i - y_i (device tensors of one dtype and size)."""
+    import torch
+    p = len(ys)
+    f = F64 if x.dtype == torch.float64 else F32
+    for t in list(ys) + list(vs):
+        if t.dtype != x.dtype or t.numel() != x.numel() or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("dykstra_update: contiguous device tensors of one dtype and size expected")
+    yp = (C.c_void_p * p)(*[t.data_ptr() for t in ys])
+    vp_ = (C.c_void_p * p)(*[t.data_ptr() for t in vs])
+    w = (C.c_double * p)(*[float(v) for v in weights])
+    check(lib().sip_dykstra_update(p, yp, vp_, w, C.c_void_p(x.data_ptr()), x.numel(), f, _stream_ptr(stream)),
+          "sip_dykstra_update")
 
 
 def stream_copy(dst, src, stream=None):
