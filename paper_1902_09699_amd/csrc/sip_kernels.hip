@@ -209,7 +209,6 @@ __device__ __forceinline__ T apply_C(F f, T fc, int P, int iz, int iy, int ix, c
   return c0 * fc + cz * lz + cy * ly + cx * lx;
 }
 
-__device__ __forceinline__ bool inst_live(const double* S) { return S[S_STATE] == 0.0 && S[S_ERR] == 0.0; }
 
 // The scalars the RHS and CG kernels read, loaded together at kernel start
 // (one round trip instead of one per use).
@@ -231,6 +230,22 @@ __device__ __forceinline__ CgScal cg_scal(const double* S) {
   q.rr0 = ldgd(S + S_RR0);
   q.state = ldgd(S + S_STATE);
   q.err = ldgd(S + S_ERR);
+  return q;
+}
+
+// The iteration scalars every set and selection kernel reads first, loaded
+// together (one round trip instead of one per use).
+struct ItScal {
+  double state, err, k, have;
+  __device__ __forceinline__ bool live() const { return state == 0.0 && err == 0.0; }
+};
+
+__device__ __forceinline__ ItScal it_scal(const double* S) {
+  ItScal q;
+  q.state = ldgd(S + S_STATE);
+  q.err = ldgd(S + S_ERR);
+  q.k = ldgd(S + S_K);
+  q.have = ldgd(S + S_HAVE_SNAP);
   return q;
 }
 
@@ -1295,14 +1310,15 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
   const PtItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
-  if (!inst_live(S)) return;
+  const ItScal isc = it_scal(S);
+  if (!isc.live()) return;
   const Geo g(d);
   const bool grouped = item_grouped(d);
   const Offs of = offs_of<T>(g);
-  const int k = (int)S[S_K];
+  const int k = (int)isc.k;
   const bool adapt = is_adapt_iter(k, o);
   const bool check = is_check_iter(k, o);
-  const bool have = S[S_HAVE_SNAP] != 0.0;
+  const bool have = isc.have != 0.0;
   const bool dots = adapt && have;
   const int call = adapt ? adapt_call(k, o) : 0;
   const T* __restrict__ x = (const T*)d.x;
@@ -1316,10 +1332,10 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
     const bool ident = (u == d.nsets);
     const SetDesc* s = ident ? nullptr : &d.sets[u];
     if (!ident && (s->thr >= 0 || s->line_axis >= 0)) continue;
-    const double rho_d = S[S_RHO + u];
+    const double rho_d = ldgd(S + S_RHO + u), gam_d = ldgd(S + S_GAMMA + u);
     ProjUnit<T> U;
-    U.rho = (T)rho_d; U.gam = (T)S[S_GAMMA + u]; U.irho = (T)(1.0 / rho_d);
-    U.one_m_g = (T)(1.0 - S[S_GAMMA + u]);
+    U.rho = (T)rho_d; U.gam = (T)gam_d; U.irho = (T)(1.0 / rho_d);
+    U.one_m_g = (T)(1.0 - gam_d);
     U.lo = ident ? (T)0 : (T)s->lo; U.hi = ident ? (T)0 : (T)s->hi;
     U.inv1p = (T)(1.0 / (1.0 + rho_d));
     U.ident = ident;
@@ -1537,12 +1553,13 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, c
   const ThrItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
-  if (!inst_live(S)) return;
-  const int k = (int)S[S_K];
+  const ItScal isc = it_scal(S);
+  if (!isc.live()) return;
+  const int k = (int)isc.k;
   const bool adapt = is_adapt_iter(k, o);
   const bool check = is_check_iter(k, o);
   if (it.src == 1 && !check) return;
-  const bool have = S[S_HAVE_SNAP] != 0.0;
+  const bool have = isc.have != 0.0;
   const int call = adapt ? adapt_call(k, o) : 0;
   const SetDesc& s = d.sets[it.set];
   const bool l1 = s.kind == SIP_SET_L1;
@@ -1556,8 +1573,8 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, c
   const T* x = (const T*)d.x;
   const T* xr = (const T*)d.xs[(call & 1) ^ 1];
   const int u = it.set;
-  const double rho_d = S[S_RHO + u];
-  const T rho = (T)rho_d, gam = (T)S[S_GAMMA + u], one_m_g = (T)(1.0 - S[S_GAMMA + u]);
+  const double rho_d = ldgd(S + S_RHO + u), gam_d = ldgd(S + S_GAMMA + u);
+  const T rho = (T)rho_d, gam = (T)gam_d, one_m_g = (T)(1.0 - gam_d);
   const T irho = (T)(1.0 / rho_d);
   const int sh0 = digit_shift<T>(0);
   constexpr int W = Grp<T>::W;
@@ -1827,8 +1844,9 @@ __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D,
   const SelItem si = items[blockIdx.x];
   const InstDesc& d = D[si.inst];
   const double* S = d.scal;
-  if (!inst_live(S)) return;
-  const int k = (int)S[S_K];
+  const ItScal isc = it_scal(S);
+  if (!isc.live()) return;
+  const int k = (int)isc.k;
   if (si.src == 1 && !is_check_iter(k, o)) return;
   const SetDesc& s = d.sets[si.set];
   if (s.kind == SIP_SET_L2 || s.kind == SIP_SET_ANNULUS) {
@@ -1899,6 +1917,19 @@ __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D,
   if (threadIdx.x == 0) *s.sel[si.src] = st;
 }
 
+// A selection state read by every block of a kernel (written by an earlier
+// launch), loaded with 16-byte global loads issued together.
+__device__ __forceinline__ SelState load_sel(const SelState* p) {
+  static_assert(sizeof(SelState) % 16 == 0, "SelState is loaded in 16-byte pieces");
+  constexpr int NQ = sizeof(SelState) / 16;
+  u32x4 q[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) q[i] = ((g_cu32x4*)p)[i];
+  SelState st;
+  __builtin_memcpy(&st, q, sizeof(SelState));
+  return st;
+}
+
 // Whether refine pass `pass` (0 or 1) appends candidate keys: only if digits
 // remain after the one it histograms, and then when the bucket it refines is
 // small or on the second pass (the select kernel finishes over them).
@@ -1924,11 +1955,12 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
   const ThrItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
-  if (!inst_live(S)) return;
-  const int k = (int)S[S_K];
+  const ItScal isc = it_scal(S);
+  if (!isc.live()) return;
+  const int k = (int)isc.k;
   if (it.src == 1 && !is_check_iter(k, o)) return;
   const SetDesc& s = d.sets[it.set];
-  const SelState& st = *s.sel[it.src];
+  const SelState st = load_sel(s.sel[it.src]);
   if (st.mode != SEL_PROJECT || st.err || st.final_) return;
   const int dig = st.digit;
   const bool compact = pass_compacts<T>(st, pass);
@@ -2077,8 +2109,9 @@ __global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict_
   const SelItem si = items[blockIdx.x];
   const InstDesc& d = D[si.inst];
   const double* S = d.scal;
-  if (!inst_live(S)) return;
-  const int k = (int)S[S_K];
+  const ItScal isc = it_scal(S);
+  if (!isc.live()) return;
+  const int k = (int)isc.k;
   if (si.src == 1 && !is_check_iter(k, o)) return;
   const SetDesc& s = d.sets[si.set];
   if (threadIdx.x == 0) st = *s.sel[si.src];
@@ -2146,11 +2179,12 @@ __global__ __launch_bounds__(kSB) void k_card_ties(const InstDesc* __restrict__ 
   const ThrItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
-  if (!inst_live(S)) return;
+  const ItScal isc = it_scal(S);
+  if (!isc.live()) return;
   if (it.src != 0) return;
   const SetDesc& s = d.sets[it.set];
   if (s.kind != SIP_SET_CARD) return;
-  const SelState& st = *s.sel[0];
+  const SelState st = load_sel(s.sel[0]);
   if (st.mode != SEL_PROJECT || st.err || !st.need_ties) return;
   if (threadIdx.x < 3) tcnt[threadIdx.x] = 0;
   __syncthreads();
@@ -2208,14 +2242,15 @@ __global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ 
   const ThrItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
-  if (!inst_live(S)) return;
-  const int k = (int)S[S_K];
+  const ItScal isc = it_scal(S);
+  if (!isc.live()) return;
+  const int k = (int)isc.k;
   const bool adapt = is_adapt_iter(k, o);
   const bool check = is_check_iter(k, o);
   if (it.src == 1 && !check) return;
-  const bool have = S[S_HAVE_SNAP] != 0.0;
+  const bool have = isc.have != 0.0;
   const SetDesc& s = d.sets[it.set];
-  const SelState& st = *s.sel[it.src];
+  const SelState st = load_sel(s.sel[it.src]);
   if (st.err) return;
   const bool l1 = s.kind == SIP_SET_L1;
   // l2 ball / annulus: y = theta w, w, or the point lo e_0; their distance
@@ -2227,7 +2262,7 @@ __global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ 
   const bool grouped = item_grouped(d);
   const Offs of = offs_of<T>(g);
   const T* x = (const T*)d.x;
-  const double rho_d = S[S_RHO + it.set];
+  const double rho_d = ldgd(S + S_RHO + it.set);
   const T rho = (T)rho_d;
   const T theta = (T)st.theta;
   const T lo_r = (T)s.lo;
@@ -2699,11 +2734,12 @@ __global__ __launch_bounds__(kLB) void k_line(const InstDesc* __restrict__ D, co
   const LineItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
-  if (!inst_live(S)) return;
-  const int k = (int)S[S_K];
+  const ItScal isc = it_scal(S);
+  if (!isc.live()) return;
+  const int k = (int)isc.k;
   const bool adapt = is_adapt_iter(k, o);
   const bool check = is_check_iter(k, o);
-  const bool have = S[S_HAVE_SNAP] != 0.0;
+  const bool have = isc.have != 0.0;
   const int call = adapt ? adapt_call(k, o) : 0;
   const SetDesc& s = d.sets[it.set];
   const Geo g(d);
@@ -2716,8 +2752,8 @@ __global__ __launch_bounds__(kLB) void k_line(const InstDesc* __restrict__ D, co
   T* y0 = (T*)s.y0 + off;
   const T* x = (const T*)d.x;
   const T* xr = (const T*)d.xs[(call & 1) ^ 1];
-  const double rho_d = S[S_RHO + it.set];
-  const T rho = (T)rho_d, gam = (T)S[S_GAMMA + it.set], one_m_g = (T)(1.0 - S[S_GAMMA + it.set]);
+  const double rho_d = ldgd(S + S_RHO + it.set), gam_d = ldgd(S + S_GAMMA + it.set);
+  const T rho = (T)rho_d, gam = (T)gam_d, one_m_g = (T)(1.0 - gam_d);
   const T irho = (T)(1.0 / rho_d);
   const int ast = axis == 0 ? g.sz : (axis == 1 ? g.sy : 1);
   const T h = axis >= 0 ? (T)d.hinv[axis] : (T)1;
@@ -2806,12 +2842,13 @@ __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* __restrict__ 
   if ((int)blockIdx.x >= cnt->ninst) return;
   const InstDesc& d = D[insts[blockIdx.x]];
   double* S = d.scal;
-  if (S[S_STATE] != 0.0) return;
-  if (S[S_ERR] != 0.0) {
+  const ItScal isc = it_scal(S);
+  if (isc.state != 0.0) return;
+  if (isc.err != 0.0) {
     if (threadIdx.x == 0) S[S_STATE] = 3.0;
     return;
   }
-  const int k = (int)S[S_K];
+  const int k = (int)isc.k;
   const bool adapt = is_adapt_iter(k, o);
   const bool check = is_check_iter(k, o);
   const int p = d.nsets;
