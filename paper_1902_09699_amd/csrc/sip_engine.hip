@@ -483,6 +483,11 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   for (const LineItem& li : line) while (cap < li.len) cap <<= 1;
   if (cap != t.line_cap) relaunch_cap = true;
   t.line_cap = cap;
+  int units = 2;
+  for (int si = 0; si < b->max_slots; ++si)
+    if (b->slots[si].used) units = std::max(units, b->slots[si].nsets + 2);
+  if (units != t.proj_units) relaunch_cap = true;
+  t.proj_units = units;
   t.thrw_part = b->d_thrw; t.thra_part = b->d_thra; t.tie_part = b->d_tie;
   t.any_card = any_card;
   const bool threads_changed = t.pt_threads != (int)b->tiles.pt_threads || t.cg_form != b->tiles.cg_form;

@@ -165,6 +165,7 @@ struct Tables {
   double* rr2_part; double* pq2_part;  // one-reduction CG: odd-step partials
   const LineItem* line; int nline;     // line items of line-wise sets
   int line_cap;                        // power of two >= the longest line (LDS entries per block)
+  int proj_units;                      // projection blocks per item: max over instances of nsets + 2
   double* line_part;                   // 8 partial sums per line item
   uint32_t* tie_part;
   bool any_card;

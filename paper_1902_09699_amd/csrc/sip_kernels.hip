@@ -1328,10 +1328,13 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
   const int lane = threadIdx.x & 63;
   double* out = parts + (size_t)iti * kProjParts;
 
-  for (int u = 0; u <= d.nsets; ++u) {
+  // blockIdx.y: the unit (a bounds set or, at nsets, the identity block), or
+  // at nsets + 1 the x snapshot / history part; units run in parallel blocks
+  const int u = (int)blockIdx.y;
+  if (u <= d.nsets) {
     const bool ident = (u == d.nsets);
     const SetDesc* s = ident ? nullptr : &d.sets[u];
-    if (!ident && (s->thr >= 0 || s->line_axis >= 0)) continue;
+    if (!ident && (s->thr >= 0 || s->line_axis >= 0)) return;
     const double rho_d = ldgd(S + S_RHO + u), gam_d = ldgd(S + S_GAMMA + u);
     ProjUnit<T> U;
     U.rho = (T)rho_d; U.gam = (T)gam_d; U.irho = (T)(1.0 / rho_d);
@@ -1467,7 +1470,9 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
         for (int q = 0; q < 8; ++q) out[u * kUnitParts + q] = acc[q];
       }
     }
+    return;
   }
+  if (u != d.nsets + 1) return;
 
   // x snapshot for adapt-rho-gamma, x history and r_evol sums
   if (adapt || d.ring) {
@@ -3067,7 +3072,7 @@ void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
   if (t.npt > 0) {
     if (t.pt_threads == 256) launch_cg<T, 256>(st, t, o);
     else launch_cg<T, 512>(st, t, o);
-    if (t.nsp) k_proj<T><<<t.nsp, kSB, 0, st>>>(t.D, t.cnt, t.sp, o, t.proj_part);
+    if (t.nsp) k_proj<T><<<dim3(t.nsp, t.proj_units), kSB, 0, st>>>(t.D, t.cnt, t.sp, o, t.proj_part);
   }
   if (t.nthr > 0) {
     k_thr_w<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thrw_part);
@@ -3101,7 +3106,7 @@ void launch_phase(hipStream_t st, const Tables& t, const Opts& o, int phase) {
       if (t.pt_threads == 256) launch_point_phase<T, 256>(st, t, o, phase);
       else launch_point_phase<T, 512>(st, t, o, phase);
       break;
-    case 3: if (t.nsp) k_proj<T><<<t.nsp, kSB, 0, st>>>(t.D, t.cnt, t.sp, o, t.proj_part); break;
+    case 3: if (t.nsp) k_proj<T><<<dim3(t.nsp, t.proj_units), kSB, 0, st>>>(t.D, t.cnt, t.sp, o, t.proj_part); break;
     case 4: if (t.nthr) k_thr_w<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thrw_part); break;
     case 5: if (t.nthr) k_thr_apply<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thra_part, t.tie_part); break;
     case 8:
