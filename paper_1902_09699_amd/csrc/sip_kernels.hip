@@ -1732,6 +1732,32 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, c
 
 // ---------------------------------------------- selection (one block each)
 
+// Move nb (<= kNB) buckets of a pipeline's global histogram into LDS and
+// clear them there: all loads of a thread are issued before the first is
+// used (one round trip), through the global address space.
+__device__ __forceinline__ void pull_histogram(uint32_t* gc, acc_t* gs, bool l1, int nb, uint32_t* hc, acc_t* hs) {
+  constexpr int PER = kNB / kBlock;
+  uint32_t cv[PER];
+  acc_t sv[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int b = (int)threadIdx.x + r * kBlock;
+    const int bb = b < nb ? b : 0;
+    cv[r] = *(__attribute__((address_space(1))) const uint32_t*)(gc + bb);
+    sv[r] = l1 ? *(__attribute__((address_space(1))) const acc_t*)(gs + bb) : (acc_t)0;
+  }
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int b = (int)threadIdx.x + r * kBlock;
+    if (b < nb) {
+      hc[b] = cv[r];
+      hs[b] = sv[r];
+      *(__attribute__((address_space(1))) uint32_t*)(gc + b) = 0u;
+      if (l1) *(__attribute__((address_space(1))) acc_t*)(gs + b) = (acc_t)0;
+    }
+  }
+}
+
 // Pick the bucket of the current digit.  l1: the largest bucket b whose lower
 // edge L_b still has f(L_b) = sum_{u >= L_b} (u - L_b) >= tau (f decreases, so
 // the soft threshold theta with f(theta) = tau lies in bucket b).  Cardinality:
@@ -1884,13 +1910,10 @@ __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D,
   uint32_t* gc = s.hcnt[si.src];
   acc_t* gs = (acc_t*)s.hsum[si.src];
   acc_t tot[2] = {0, 0};
+  pull_histogram(gc, gs, l1, kNB, hc, hs);
   for (int b = threadIdx.x; b < kNB; b += kBlock) {
-    hc[b] = gc[b];
-    hs[b] = l1 ? gs[b] : (acc_t)0;
     tot[0] += (acc_t)hc[b];
     tot[1] += hs[b];
-    gc[b] = 0;
-    if (l1) gs[b] = 0;
   }
   block_sum<2>(tot, lds);
   if (threadIdx.x == 0) {
@@ -2128,12 +2151,7 @@ __global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict_
   acc_t* gs = (acc_t*)s.hsum[si.src];
   int dig = st.digit;
   int nb = 1 << KT::width(dig);
-  for (int b = threadIdx.x; b < nb; b += kBlock) {
-    hc[b] = gc[b];
-    hs[b] = l1 ? gs[b] : (acc_t)0;
-    gc[b] = 0;
-    if (l1) gs[b] = 0;
-  }
+  pull_histogram(gc, gs, l1, nb, hc, hs);
   __syncthreads();
   unsigned long long last = select_digit<T>(st, hc, hs, nb, dig, s, l1, lc, ls, &lbest);
   ++dig;
@@ -2147,12 +2165,23 @@ __global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict_
       const K want = (K)(st.prefix >> shp);
       for (int b = threadIdx.x; b < nb; b += kBlock) { hc[b] = 0; hs[b] = 0; }
       __syncthreads();
-      for (unsigned long long i = threadIdx.x; i < ncand; i += kBlock) {
-        const K key = cand[i];
-        if ((K)(key >> shp) == want) {
-          const int bkt = (int)((key >> sh) & (K)(nb - 1));
-          atomicAdd(&hc[bkt], 1u);
-          if (l1) atomicAdd(&hs[bkt], (acc_t)KT::value(key));
+      // eight keys per thread in flight at a time
+      constexpr int U = 8;
+      for (unsigned long long i0 = threadIdx.x; i0 < ncand; i0 += (unsigned long long)kBlock * U) {
+        K keys[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const unsigned long long i = i0 + (unsigned long long)u * kBlock;
+          keys[u] = *(__attribute__((address_space(1))) const K*)(cand + (i < ncand ? i : 0));
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const K key = keys[u];
+          if (i0 + (unsigned long long)u * kBlock < ncand && (K)(key >> shp) == want) {
+            const int bkt = (int)((key >> sh) & (K)(nb - 1));
+            atomicAdd(&hc[bkt], 1u);
+            if (l1) atomicAdd(&hs[bkt], (acc_t)KT::value(key));
+          }
         }
       }
       __syncthreads();
@@ -2857,7 +2886,6 @@ __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* __restrict__ 
   const bool adapt = is_adapt_iter(k, o);
   const bool check = is_check_iter(k, o);
   const int p = d.nsets;
-  int err = 0;
   // Every sum this kernel needs is a task: 8 consecutive per-item partial
   // values summed over an item range (a projection unit's dots; a threshold
   // set's w-pass and apply-pass dots, per pipeline; the evolution sums).
@@ -2933,21 +2961,33 @@ __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* __restrict__ 
 #pragma unroll
       for (int j = 0; j < 8; ++j) { evol[j] = tout[t][j]; evol[8 + j] = tout[t + 1][j]; }
     }
-    for (int u = 0; u < p; ++u) {
-      if (d.sets[u].thr < 0) continue;
-      if (d.sets[u].sel[0]->err) err = d.sets[u].sel[0]->err;
-      if (check && d.sets[u].sel[1]->err) err = d.sets[u].sel[1]->err;
-    }
   }
-  if (threadIdx.x != 0) return;
-  if (err) { S[S_ERR] = (double)err; S[S_STATE] = 3.0; return; }
-  if (d.log && k <= d.log_cap) {
+  // The per-set work runs in parallel, thread u for unit u (p + 1 <= 256):
+  // selection errors, the schedule log, r_feas, the new (rho, gamma); thread 0
+  // combines.  Every value is computed as a single thread would.
+  __shared__ int s_err, s_bad, s_conv;
+  __shared__ double s_rho[kMaxUnits], s_gam[kMaxUnits];
+  const int u = (int)threadIdx.x;
+  if (u == 0) { s_err = 0; s_bad = 0; s_conv = 0; }
+  __syncthreads();
+  if (u < p && d.sets[u].thr >= 0) {
+    const int e0 = d.sets[u].sel[0]->err;
+    const int e1 = check ? d.sets[u].sel[1]->err : 0;
+    if (e0 || e1) s_err = e1 ? e1 : e0;  // every selection error is SIP_ENUMERIC
+  }
+  __syncthreads();
+  if (s_err) {
+    if (u == 0) { S[S_ERR] = (double)s_err; S[S_STATE] = 3.0; }
+    return;
+  }
+  const double rho_u = u <= p ? ldgd(S + S_RHO + u) : 0.0, gam_u = u <= p ? ldgd(S + S_GAMMA + u) : 0.0;
+  if (d.log && k <= d.log_cap && u <= p) {
     double* row = d.log + (size_t)(k - 1) * 2 * kMaxUnits;
-    for (int u = 0; u <= p; ++u) { row[u] = S[S_RHO + u]; row[kMaxUnits + u] = S[S_GAMMA + u]; }
+    row[u] = rho_u;
+    row[kMaxUnits + u] = gam_u;
   }
   if (check) {
-    bool feas = true;
-    for (int u = 0; u < p; ++u) {
+    if (u < p) {
       double num = dots[u][6];
       const double den = dots[u][7];
       const SetDesc& s = d.sets[u];
@@ -2967,54 +3007,70 @@ __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* __restrict__ 
       if (den > 0.0) rf = sqrt(num) / sqrt(den);
       else rf = (num > 0.0) ? INFINITY : 0.0;
       S[S_RFEAS + u] = rf;
-      if (!(rf < o.eps_feas)) feas = false;
+      if (!(rf < o.eps_feas)) s_bad = 1;
     }
-    double worst = 0.0;
-    for (int j = 1; j <= o.evol_hist; ++j) worst = evol[j] > worst ? evol[j] : worst;
-    const double xn = evol[0];
-    double re;
-    if (xn > 0.0) re = sqrt(worst) / sqrt(xn);
-    else re = worst > 0.0 ? INFINITY : 0.0;
-    S[S_REVOL] = re;
-    if (re < o.eps_evol && feas) {
-      S[S_STATE] = 1.0;
-      S[S_ITERS] = (double)k;
-      return;
+    __syncthreads();
+    if (u == 0) {
+      double worst = 0.0;
+      for (int j = 1; j <= o.evol_hist; ++j) worst = evol[j] > worst ? evol[j] : worst;
+      const double xn = evol[0];
+      double re;
+      if (xn > 0.0) re = sqrt(worst) / sqrt(xn);
+      else re = worst > 0.0 ? INFINITY : 0.0;
+      S[S_REVOL] = re;
+      if (re < o.eps_evol && !s_bad) {
+        S[S_STATE] = 1.0;
+        S[S_ITERS] = (double)k;
+        s_conv = 1;
+      }
     }
+    __syncthreads();
+    if (s_conv) return;
   }
   if (adapt) {
-    if (S[S_HAVE_SNAP] != 0.0) {
-      double rho[kMaxUnits], gam[kMaxUnits];
-      for (int u = 0; u <= p; ++u) {
-        double a = 0.0, b = 0.0;
+    if (isc.have != 0.0) {
+      if (u <= p) {
+        double a = 0.0, b = 0.0, rn, gn;
         const bool oa = spectral(dots[u][0], dots[u][1], dots[u][2], o.eps_corr, a);
         const bool ob = spectral(dots[u][3], dots[u][4], dots[u][5], o.eps_corr, b);
-        if (oa && ob) { const double gm = sqrt(a * b); rho[u] = gm; gam[u] = 1.0 + 2.0 * gm / (a + b); }
-        else if (oa) { rho[u] = a; gam[u] = 1.9; }
-        else if (ob) { rho[u] = b; gam[u] = 1.1; }
-        else { rho[u] = S[S_RHO + u]; gam[u] = 1.5; }
-        if (gam[u] > o.gamma_max) gam[u] = o.gamma_max;
+        if (oa && ob) { const double gm = sqrt(a * b); rn = gm; gn = 1.0 + 2.0 * gm / (a + b); }
+        else if (oa) { rn = a; gn = 1.9; }
+        else if (ob) { rn = b; gn = 1.1; }
+        else { rn = rho_u; gn = 1.5; }
+        if (gn > o.gamma_max) gn = o.gamma_max;
+        s_rho[u] = rn;
+        s_gam[u] = gn;
       }
-      const double rl = rho[p];
-      for (int u = 0; u < p; ++u) {
+      __syncthreads();
+      if (u < p) {
+        const double rl = s_rho[p];
         const double lo = rl / o.rho_ratio_max, hi = rl * o.rho_ratio_max;
-        rho[u] = rho[u] < lo ? lo : (rho[u] > hi ? hi : rho[u]);
+        const double r = s_rho[u];
+        s_rho[u] = r < lo ? lo : (r > hi ? hi : r);
       }
-      for (int u = 0; u <= p; ++u) { S[S_RHO + u] = rho[u]; S[S_GAMMA + u] = gam[u]; }
+      __syncthreads();
+      if (u <= p) { S[S_RHO + u] = s_rho[u]; S[S_GAMMA + u] = s_gam[u]; }
+    } else {
+      if (u <= p) s_rho[u] = rho_u;
+      __syncthreads();
     }
-    S[S_HAVE_SNAP] = 1.0;
-    double c0 = S[S_RHO + p], ca[3] = {0.0, 0.0, 0.0};
-    for (int u = 0; u < p; ++u) {
-      const SetDesc& s = d.sets[u];
-      if (s.op == SIP_OP_I) c0 += S[S_RHO + u];
-      else for (int c = 0; c < s.ncomp; ++c) ca[s.axis[c]] += S[S_RHO + u];
+    if (u == 0) {
+      S[S_HAVE_SNAP] = 1.0;
+      double c0 = s_rho[p], ca[3] = {0.0, 0.0, 0.0};
+      for (int q = 0; q < p; ++q) {
+        const SetDesc& s = d.sets[q];
+        if (s.op == SIP_OP_I) c0 += s_rho[q];
+        else for (int c = 0; c < s.ncomp; ++c) ca[s.axis[c]] += s_rho[q];
+      }
+      S[S_C0] = c0;
+      for (int a = 0; a < 3; ++a) S[S_CAX + a] = ca[a] * d.h2inv[a];
     }
-    S[S_C0] = c0;
-    for (int a = 0; a < 3; ++a) S[S_CAX + a] = ca[a] * d.h2inv[a];
   }
-  S[S_ITERS] = (double)k;
-  S[S_K] = (double)(k + 1);
-  if (k + 1 > o.max_iter) S[S_STATE] = 2.0;
+  if (u == 0) {
+    S[S_ITERS] = (double)k;
+    S[S_K] = (double)(k + 1);
+    if (k + 1 > o.max_iter) S[S_STATE] = 2.0;
+  }
 }
 
 // Clears a pipeline's histogram (used at admission; graph-safe, no memset).
