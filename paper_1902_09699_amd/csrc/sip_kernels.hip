@@ -1301,12 +1301,14 @@ __device__ __forceinline__ void proj_point(const ProjUnit<T>& U, T sv, T yo, T v
   vn = vo + U.rho * (yn - xb);
 }
 
+// One block of the projection pass: item bx, unit by.
 template <typename T>
-__global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const PtItem* __restrict__ items, Opts o, double* parts) {
+__device__ void proj_block(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt,
+                           const PtItem* __restrict__ items, const Opts& o, double* parts, int bx, int by) {
   constexpr int W = Grp<T>::W;
   __shared__ acc_t lds[lds_sum<8, kSB>()];
-  if ((int)blockIdx.x >= cnt->nsp) return;
-  const int iti = xcd_item(blockIdx.x, cnt->nsp);
+  if (bx >= cnt->nsp) return;
+  const int iti = xcd_item(bx, cnt->nsp);
   const PtItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
@@ -1330,7 +1332,7 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
 
   // blockIdx.y: the unit (a bounds set or, at nsets, the identity block), or
   // at nsets + 1 the x snapshot / history part; units run in parallel blocks
-  const int u = (int)blockIdx.y;
+  const int u = by;
   if (u <= d.nsets) {
     const bool ident = (u == d.nsets);
     const SetDesc* s = ident ? nullptr : &d.sets[u];
@@ -1541,20 +1543,28 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt,
+                                              const PtItem* __restrict__ items, Opts o, double* parts) {
+  proj_block<T>(D, cnt, items, o, parts, (int)blockIdx.x, (int)blockIdx.y);
+}
+
 // --------------------------------------------- threshold sets: pass 1 (w)
 
 // Pipeline 0 (every iteration): w = x-bar - v/rho for the set's components,
 // stored over y (y's old value is used first for v-hat); adapt dots of the
 // (dh, dvh) pair; radix histogram of the first key digit of |w|.
 // Pipeline 1 (stopping-test iterations): histogram of |s| and ||s||^2.
+// One block of the w pass: item bx.
 template <typename T>
-__global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const ThrItem* __restrict__ items, Opts o, double* parts) {
+__device__ void thrw_block(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt,
+                           const ThrItem* __restrict__ items, const Opts& o, double* parts, int bx) {
   using KT = KeyT<T>;
   __shared__ uint32_t hc[kNB];
   __shared__ acc_t hs[kNB];
   __shared__ acc_t lds[lds_sum<8, kSB>()];
-  if ((int)blockIdx.x >= cnt->nthr) return;
-  const int iti = xcd_item(blockIdx.x, cnt->nthr);
+  if (bx >= cnt->nthr) return;
+  const int iti = xcd_item(bx, cnt->nthr);
   const ThrItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
@@ -1728,6 +1738,24 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, c
 #pragma unroll
     for (int q = 0; q < 8; ++q) parts[(size_t)iti * kThrParts + q] = acc[q];
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt,
+                                               const ThrItem* __restrict__ items, Opts o, double* parts) {
+  thrw_block<T>(D, cnt, items, o, parts, (int)blockIdx.x);
+}
+
+// The projection pass and the threshold sets' w pass in one launch: both read
+// only x and their own sets' arrays, so they run side by side (blocks below
+// nsp * units project, the rest take threshold items).
+template <typename T>
+__global__ __launch_bounds__(kSB) void k_sets(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt,
+                                              const PtItem* __restrict__ sp, const ThrItem* __restrict__ thr, Opts o,
+                                              double* proj_parts, double* thrw_parts, int nsp, int units) {
+  const int b = (int)blockIdx.x, np = nsp * units;
+  if (b < np) proj_block<T>(D, cnt, sp, o, proj_parts, b % nsp, b / nsp);
+  else thrw_block<T>(D, cnt, thr, o, thrw_parts, b - np);
 }
 
 // ---------------------------------------------- selection (one block each)
@@ -3128,10 +3156,16 @@ void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
   if (t.npt > 0) {
     if (t.pt_threads == 256) launch_cg<T, 256>(st, t, o);
     else launch_cg<T, 512>(st, t, o);
-    if (t.nsp) k_proj<T><<<dim3(t.nsp, t.proj_units), kSB, 0, st>>>(t.D, t.cnt, t.sp, o, t.proj_part);
   }
-  if (t.nthr > 0) {
+  const bool proj = t.npt > 0 && t.nsp > 0;
+  if (proj && t.nthr > 0)
+    k_sets<T><<<t.nsp * t.proj_units + t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.sp, t.thr, o, t.proj_part, t.thrw_part,
+                                                              t.nsp, t.proj_units);
+  else if (proj)
+    k_proj<T><<<dim3(t.nsp, t.proj_units), kSB, 0, st>>>(t.D, t.cnt, t.sp, o, t.proj_part);
+  else if (t.nthr > 0)
     k_thr_w<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thrw_part);
+  if (t.nthr > 0) {
     k_sel1<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, t.thrw_part);
     k_thr_refine<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, 0);
     k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 0);
