@@ -51,8 +51,9 @@ def main():
     out = {}
     cg = ((("cg1_step", sip.K_CG1_STEP), ("cg1_w0", sip.K_CG1_W0)) if one_red else
           (("cg_dir", sip.K_CG_DIR), ("cg_upd", sip.K_CG_UPD)))
+    has_line = any(s.get("line") is not None for _, sets in insts for s in sets)
     for name, kid in cg + (("rhs", sip.K_RHS), ("proj", sip.K_PROJ), ("thr_w", sip.K_THR_W),
-                           ("thr_apply", sip.K_THR_APPLY)):
+                           ("thr_apply", sip.K_THR_APPLY)) + ((("line", sip.K_LINE),) if has_line else ()):
         out[name] = batch.time_kernel(kid, a.reps)
         print(f"{name}: {out[name] * 1e3:.2f} us", flush=True)
     n = a.copy_mb * (1 << 20) // 4
