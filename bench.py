@@ -210,7 +210,7 @@ def cpu_baseline(insts, iters_full, budget_s, schedule=None, check=None):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no multi-GPU path",
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
     import torch

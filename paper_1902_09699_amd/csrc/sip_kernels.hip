@@ -42,11 +42,40 @@ __device__ __forceinline__ int xcd_item(int b, int G) {
   return x * q + (x < rem ? x : rem) + j;
 }
 
+// Data-parallel-primitive (DPP) moves: lane permutations inside the VALU,
+// with no LDS round trip.  Rows not in ROW_MASK receive 0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+
+__device__ __forceinline__ double lane63(double v) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
+
+// Sum over the 64 lanes, the same value in every lane: pairs, quads, the two
+// halves of each 8, of each 16 (every lane of a group adds the same two
+// partial sums, and IEEE addition commutes), then row 0 into row 1 and row 2
+// into row 3, then rows 0-1 into rows 2-3; lane 63 holds the total.  The
+// order is fixed, so every wave of every block gets the same bits.
 template <typename A>
 __device__ __forceinline__ A wave_sum(A v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_mov<0xB1>(v);        // quad_perm [1, 0, 3, 2]
+  v += dpp_mov<0x4E>(v);        // quad_perm [2, 3, 0, 1]
+  v += dpp_mov<0x141>(v);       // row_half_mirror
+  v += dpp_mov<0x140>(v);       // row_mirror
+  v += dpp_mov<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_mov<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return lane63(v);
 }
 
 // Deterministic block sum of NV doubles over NT threads (a fixed butterfly in
