@@ -55,6 +55,18 @@ __device__ __forceinline__ float dpp_mov(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
 }
 
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+
+// The value of lane i - 1 (lane 0 gets 0) and of lane i + 1 (lane 63 gets
+// 0): whole-wave shifts by one lane.
+template <typename T>
+__device__ __forceinline__ T lane_prev(T v) { return dpp_mov<0x138>(v); }
+template <typename T>
+__device__ __forceinline__ T lane_next(T v) { return dpp_mov<0x130>(v); }
+
 __device__ __forceinline__ double lane63(double v) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
@@ -563,7 +575,7 @@ __device__ __forceinline__ GLane glane(int P0, int begin, int end, const Geo& g)
   GLane L;
   L.vec = P0 < end;
   L.cnt = end - P0 < W ? end - P0 : W;
-  L.next_vec = __shfl_down(L.vec ? 1 : 0, 1, 64) != 0;
+  L.next_vec = dpp_mov_i<0x130>(L.vec ? 1 : 0) != 0;  // lane i + 1 (lane 63: none)
   L.P0c = L.vec ? P0 : begin;
   g.coords(L.P0c, L.iz, L.iy, L.ix0);
   L.straddle = L.ix0 + W > g.nx;
@@ -600,8 +612,8 @@ __device__ __forceinline__ void group_C_v(const Src<T, NA>& f, const GLane& L, i
     for (int a = 0; a < NA; ++a) re[a] = ldg(f.a[a] + L.P0c + W);
   }
   src_mix<T, NA>(f, R, c);
-  T left = __shfl_up(c[W - 1], 1, 64);
-  T right = __shfl_down(c[0], 1, 64);
+  T left = lane_prev(c[W - 1]);
+  T right = lane_next(c[0]);
   if (lane == 0) left = src_one<T, NA>(f, le);
   if (own_right) right = src_one<T, NA>(f, re);
   T ym[W], yp[W], zm[W], zp[W];
@@ -688,7 +700,7 @@ __device__ __forceinline__ void group_diff(const T* f, const GLane& L, int lane,
     const bool own_right = lane == 63 || !L.next_vec;
     T re = 0;
     if (own_right && L.P0c + W < g.N) re = ldg(f + L.P0c + W);
-    T right = __shfl_down(R[0][0], 1, 64);
+    T right = lane_next(R[0][0]);
     if (own_right) right = re;
 #pragma unroll
     for (int e = 0; e < W; ++e) {
@@ -752,7 +764,7 @@ __device__ __forceinline__ acc_t group_pCp_v(const Src<T, NA>& f, const GLane& L
     for (int a = 0; a < NA; ++a) re[a] = ldg(f.a[a] + L.P0c + W);
   }
   src_mix<T, NA>(f, R, c);
-  T right = __shfl_down(c[0], 1, 64);
+  T right = lane_next(c[0]);
   if (own_right) right = src_one<T, NA>(f, re);
   T yp[W], zp[W];
   if constexpr (HY) win_get<T, NA, AL>(f, of.yp, ypa, ypb, yp);
@@ -1231,7 +1243,7 @@ __global__ __launch_bounds__(NT) void k_rhs(const InstDesc* __restrict__ D, cons
           }
           T prev[W];
           if (a == 2) {
-            T left = __shfl_up(u[W - 1], 1, 64);
+            T left = lane_prev(u[W - 1]);
             if (lane == 0) left = src_one<T, 2>(fu, le);
 #pragma unroll
             for (int e = 0; e < W; ++e) prev[e] = e > 0 ? u[e > 0 ? e - 1 : 0] : left;
