@@ -179,6 +179,45 @@ __device__ __forceinline__ acc_t wave_reduce(const double* __restrict__ parts, i
 
 // Block total of one double, valid in thread 0 only (one barrier; lds must
 // not be in use by other threads).
+// Block totals of NV values, valid in thread 0 only, with one barrier (the
+// same summation order as block_sum); lds needs NV * NT / 64 entries.
+template <int NV, int NT, typename A>
+__device__ __forceinline__ void block_total_n(A (&v)[NV], A* lds) {
+  constexpr int NW = NT / 64;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) lds[i * NW + (threadIdx.x >> 6)] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      A t = 0;
+      for (int q = 0; q < NW; ++q) t += lds[i * NW + q];
+      v[i] = t;
+    }
+  }
+}
+
+// Block totals of two doubles with one barrier (thread 0 only); lds needs
+// 2 * NT / 64 entries.
+template <int NT, typename A>
+__device__ __forceinline__ void block_total2(A& a, A& b, A* lds) {
+  constexpr int NW = NT / 64;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if ((threadIdx.x & 63) == 0) { lds[threadIdx.x >> 6] = a; lds[NW + (threadIdx.x >> 6)] = b; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    A ta = 0, tb = 0;
+    for (int q = 0; q < NW; ++q) { ta += lds[q]; tb += lds[NW + q]; }
+    a = ta;
+    b = tb;
+  }
+}
+
 template <int NT, typename A>
 __device__ __forceinline__ A block_total(A v, A* lds) {
   constexpr int NW = NT / 64;
@@ -1037,8 +1076,7 @@ __global__ __launch_bounds__(NT) void k_cg1_step(const InstDesc* __restrict__ D,
                                                   const PtItem* __restrict__ items, int j, const double* gin,
                                                   const double* din, double* gout, double* dout, Opts o) {
   constexpr int W = Grp<T>::W;
-  __shared__ acc_t lds_g[lds_sum<1, NT>()];
-  __shared__ acc_t lds_d[lds_sum<1, NT>()];
+  __shared__ acc_t lds_g[2 * (NT / 64)];
   if ((int)blockIdx.x >= cnt->npt) return;
   const int iti = xcd_item(blockIdx.x, cnt->npt);
   const PtItem it = items[iti];
@@ -1163,11 +1201,10 @@ __global__ __launch_bounds__(NT) void k_cg1_step(const InstDesc* __restrict__ D,
       }
     }
   }
-  const acc_t tg = block_total<NT>(ag, lds_g);
-  const acc_t td = block_total<NT>(ad, lds_d);
+  block_total2<NT>(ag, ad, lds_g);
   if (threadIdx.x == 0) {
-    gout[iti] = tg;
-    dout[iti] = td;
+    gout[iti] = ag;
+    dout[iti] = ad;
   }
 }
 
@@ -1347,7 +1384,7 @@ template <typename T>
 __device__ void proj_block(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt,
                            const PtItem* __restrict__ items, const Opts& o, double* parts, int bx, int by) {
   constexpr int W = Grp<T>::W;
-  __shared__ acc_t lds[lds_sum<8, kSB>()];
+  __shared__ acc_t lds[lds_sum<16, kSB>()];
   if (bx >= cnt->nsp) return;
   const int iti = xcd_item(bx, cnt->nsp);
   const PtItem it = items[iti];
@@ -1507,7 +1544,7 @@ __device__ void proj_block(const InstDesc* __restrict__ D, const Counts* __restr
       }
     }
     if (adapt || check) {
-      block_sum<8, kSB>(acc, lds);
+      block_total_n<8, kSB>(acc, lds);
       if (threadIdx.x == 0) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) out[u * kUnitParts + q] = acc[q];
@@ -1572,13 +1609,15 @@ __device__ void proj_block(const InstDesc* __restrict__ D, const Counts* __restr
       }
     }
     if (check) {
-      block_sum<8, kSB>(acc, lds);
-      block_sum<8, kSB>(accx, lds);
-      if (threadIdx.x == 0) {
-        out[kEvolOff + 0] = accx[0];
+      acc_t all[16];
 #pragma unroll
-        for (int jj = 1; jj < 8; ++jj) out[kEvolOff + jj] = acc[jj];
-        out[kEvolOff + 8] = accx[1];  // evol_hist <= 8
+      for (int jj = 0; jj < 8; ++jj) { all[jj] = acc[jj]; all[8 + jj] = accx[jj]; }
+      block_total_n<16, kSB>(all, lds);
+      if (threadIdx.x == 0) {
+        out[kEvolOff + 0] = all[8];
+#pragma unroll
+        for (int jj = 1; jj < 8; ++jj) out[kEvolOff + jj] = all[jj];
+        out[kEvolOff + 8] = all[9];  // evol_hist <= 8
       }
     }
   }
@@ -1774,7 +1813,7 @@ __device__ void thrw_block(const InstDesc* __restrict__ D, const Counts* __restr
       if (l1) atomicAdd(&gs[b], hs[b]);
     }
   }
-  block_sum<8, kSB>(acc, lds);
+  block_total_n<8, kSB>(acc, lds);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) parts[(size_t)iti * kThrParts + q] = acc[q];
@@ -1984,7 +2023,7 @@ __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D,
     tot[0] += (acc_t)hc[b];
     tot[1] += hs[b];
   }
-  block_sum<2>(tot, lds);
+  block_total_n<2, kBlock>(tot, lds);
   if (threadIdx.x == 0) {
     st.prefix = 0; st.c_above = 0; st.s_above = 0.0; st.ncand = 0; st.err = 0; st.need_ties = 0;
     st.theta = 0.0; st.tkey = 0; st.tk = 0.0; st.keep_ties = 0; st.ties = 0; st.digit = 0;
@@ -2593,7 +2632,7 @@ __global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ 
       }
     }
   }
-  block_sum<8, kSB>(acc, lds);
+  block_total_n<8, kSB>(acc, lds);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) parts[(size_t)iti * kThrParts + q] = acc[q];
@@ -2912,7 +2951,7 @@ __global__ __launch_bounds__(kLB) void k_line(const InstDesc* __restrict__ D, co
       acc[6] += df * df;
     }
   }
-  block_sum<8, kLB>(acc, lds);
+  block_total_n<8, kLB>(acc, lds);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) parts[(size_t)iti * 8 + q] = acc[q];
