@@ -144,34 +144,31 @@ __device__ __forceinline__ double ldgd(const double* p) {
   return *(__attribute__((address_space(1))) const double*)p;
 }
 
+// Requires end > begin (every instance has point items).  Loads only: no
+// branch and no use of the values, so nothing here waits for them.
 __device__ __forceinline__ void part_issue(const double* __restrict__ parts, int begin, int end,
                                            double (&pre)[kPre]) {
-  // every lane loads (an index past the range reads entry begin, whose value
-  // is then dropped), so no load sits behind a branch
+  // a lane past the range reads entry begin; part_finish drops that value
   const int i0 = begin + (int)(threadIdx.x & 63);
-  if (end <= begin) {
-#pragma unroll
-    for (int k = 0; k < kPre; ++k) pre[k] = 0.0;
-    return;
-  }
 #pragma unroll
   for (int k = 0; k < kPre; ++k) {
     const int i = i0 + 64 * k;
-    const double v = ldgd(parts + (i < end ? i : begin));
-    pre[k] = i < end ? v : 0.0;
+    pre[k] = ldgd(parts + (i < end ? i : begin));
   }
 }
 
 __device__ __forceinline__ acc_t part_finish(const double* __restrict__ parts, int begin, int end,
                                              const double (&pre)[kPre]) {
+  const int i0 = begin + (int)(threadIdx.x & 63);
   acc_t t = 0;
 #pragma unroll
-  for (int k = 0; k < kPre; ++k) t += (acc_t)pre[k];
-  for (int i = begin + (int)(threadIdx.x & 63) + 64 * kPre; i < end; i += 64) t += (acc_t)ldgd(parts + i);
+  for (int k = 0; k < kPre; ++k) t += i0 + 64 * k < end ? (acc_t)pre[k] : (acc_t)0;
+  for (int i = i0 + 64 * kPre; i < end; i += 64) t += (acc_t)ldgd(parts + i);
   return wave_sum(t);
 }
 
 __device__ __forceinline__ acc_t wave_reduce(const double* __restrict__ parts, int begin, int end) {
+  if (end <= begin) return 0;
   double pre[kPre];
   part_issue(parts, begin, end, pre);
   return part_finish(parts, begin, end, pre);
@@ -889,8 +886,10 @@ __global__ __launch_bounds__(NT) void k_cg_dir(const InstDesc* __restrict__ D, c
   const CgScal q = cg_scal(S);
   double pre[kPre];
   part_issue(rr_part, d.pt_begin, d.pt_end, pre);
-  if (!q.live()) return;
+  // the sum comes before the state checks: a load whose only uses follow a
+  // branch is moved below it by the compiler, one more round trip
   const double rr = part_finish(rr_part, d.pt_begin, d.pt_end, pre);
+  if (!q.live()) return;
   bool done;
   double beta = 0.0;
   if (j == 0) {
@@ -939,9 +938,10 @@ __global__ __launch_bounds__(NT) void k_cg_upd(const InstDesc* __restrict__ D, c
   const CgScal qs = cg_scal(S);
   double pre[kPre];
   part_issue(pq_part, d.pt_begin, d.pt_end, pre);
+  // summed before the state checks (stale when this step is skipped)
+  const double pq = part_finish(pq_part, d.pt_begin, d.pt_end, pre);
   if (!qs.live()) return;
   if (qs.done_at(j) != 0.0) return;
-  const double pq = part_finish(pq_part, d.pt_begin, d.pt_end, pre);
   if (!(pq > 0.0) || !(pq <= 1.0e300)) {
     if (iti == d.pt_begin && threadIdx.x == 0) S[S_ERR] = (double)SIP_ENUMERIC;
     return;
@@ -1087,6 +1087,10 @@ __global__ __launch_bounds__(NT) void k_cg1_step(const InstDesc* __restrict__ D,
   double pg[kPre], pd[kPre];
   part_issue(gin, d.pt_begin, d.pt_end, pg);
   part_issue(din, d.pt_begin, d.pt_end, pd);
+  // summed before the state checks, so the partials' loads stay with the
+  // scalars' (the values are stale when the checks end the step)
+  const double gam = part_finish(gin, d.pt_begin, d.pt_end, pg);
+  const double del = part_finish(din, d.pt_begin, d.pt_end, pd);
   if (!qs.live()) return;
   const bool leader = iti == d.pt_begin && threadIdx.x == 0;
   if (j > 0 && qs.done_at(j - 1) != 0.0) {
@@ -1094,8 +1098,6 @@ __global__ __launch_bounds__(NT) void k_cg1_step(const InstDesc* __restrict__ D,
     if (leader) S[S_DONE + (j & 1)] = 1.0;
     return;
   }
-  const double gam = part_finish(gin, d.pt_begin, d.pt_end, pg);
-  const double del = part_finish(din, d.pt_begin, d.pt_end, pd);
   bool done = !(gam > 0.0);
   double beta = 0.0;
   if (j > 0) {
@@ -1841,21 +1843,29 @@ __global__ __launch_bounds__(kSB) void k_sets(const InstDesc* __restrict__ D, co
 // ---------------------------------------------- selection (one block each)
 
 // Move nb (<= kNB) buckets of a pipeline's global histogram into LDS and
-// clear them there: all loads of a thread are issued before the first is
-// used (one round trip), through the global address space.
-__device__ __forceinline__ void pull_histogram(uint32_t* gc, acc_t* gs, bool l1, int nb, uint32_t* hc, acc_t* hs) {
-  constexpr int PER = kNB / kBlock;
-  uint32_t cv[PER];
-  acc_t sv[PER];
+// clear them there, in two halves: pull_issue loads all kNB buckets (the
+// arrays always hold kNB, so it needs neither nb nor a wait and can be issued
+// with a kernel's first loads); pull_finish stores the first nb to LDS and
+// clears them in global memory.  Loads go through the global address space.
+constexpr int kPull = kNB / kBlock;
+
+__device__ __forceinline__ void pull_issue(const uint32_t* gc, const acc_t* gs, bool l1, uint32_t (&cv)[kPull],
+                                           acc_t (&sv)[kPull]) {
 #pragma unroll
-  for (int r = 0; r < PER; ++r) {
+  for (int r = 0; r < kPull; ++r) {
     const int b = (int)threadIdx.x + r * kBlock;
-    const int bb = b < nb ? b : 0;
-    cv[r] = *(__attribute__((address_space(1))) const uint32_t*)(gc + bb);
-    sv[r] = l1 ? *(__attribute__((address_space(1))) const acc_t*)(gs + bb) : (acc_t)0;
+    cv[r] = *(__attribute__((address_space(1))) const uint32_t*)(gc + b);
+    // unconditional load, then a select: a load behind a branch makes the
+    // compiler wait for the loads before it
+    const acc_t v = *(__attribute__((address_space(1))) const acc_t*)(gs + b);
+    sv[r] = l1 ? v : (acc_t)0;
   }
+}
+
+__device__ __forceinline__ void pull_finish(uint32_t* gc, acc_t* gs, bool l1, int nb, const uint32_t (&cv)[kPull],
+                                            const acc_t (&sv)[kPull], uint32_t* hc, acc_t* hs) {
 #pragma unroll
-  for (int r = 0; r < PER; ++r) {
+  for (int r = 0; r < kPull; ++r) {
     const int b = (int)threadIdx.x + r * kBlock;
     if (b < nb) {
       hc[b] = cv[r];
@@ -1983,11 +1993,19 @@ __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D,
   const SelItem si = items[blockIdx.x];
   const InstDesc& d = D[si.inst];
   const double* S = d.scal;
+  const SetDesc& s = d.sets[si.set];
+  const bool l1 = s.kind == SIP_SET_L1;
+  uint32_t* gc = s.hcnt[si.src];
+  acc_t* gs = (acc_t*)s.hsum[si.src];
+  // the histogram (allocated for every selection item) travels with the
+  // iteration scalars
   const ItScal isc = it_scal(S);
+  uint32_t cv[kPull];
+  acc_t sv[kPull];
+  pull_issue(gc, gs, l1, cv, sv);
   if (!isc.live()) return;
   const int k = (int)isc.k;
   if (si.src == 1 && !is_check_iter(k, o)) return;
-  const SetDesc& s = d.sets[si.set];
   if (s.kind == SIP_SET_L2 || s.kind == SIP_SET_ANNULUS) {
     // ||w||^2 (pipeline 0) from the w pass's per-item partials in item order;
     // the projection is a scaling (or, for an annulus at w = 0, a point)
@@ -2014,11 +2032,8 @@ __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D,
     }
     return;
   }
-  const bool l1 = s.kind == SIP_SET_L1;
-  uint32_t* gc = s.hcnt[si.src];
-  acc_t* gs = (acc_t*)s.hsum[si.src];
   acc_t tot[2] = {0, 0};
-  pull_histogram(gc, gs, l1, kNB, hc, hs);
+  pull_finish(gc, gs, l1, kNB, cv, sv, hc, hs);
   for (int b = threadIdx.x; b < kNB; b += kBlock) {
     tot[0] += (acc_t)hc[b];
     tot[1] += hs[b];
@@ -2091,12 +2106,12 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
   const ThrItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
+  const SetDesc& s = d.sets[it.set];
   const ItScal isc = it_scal(S);
+  const SelState st = load_sel(s.sel[it.src]);  // with the iteration scalars
   if (!isc.live()) return;
   const int k = (int)isc.k;
   if (it.src == 1 && !is_check_iter(k, o)) return;
-  const SetDesc& s = d.sets[it.set];
-  const SelState st = load_sel(s.sel[it.src]);
   if (st.mode != SEL_PROJECT || st.err || st.final_) return;
   const int dig = st.digit;
   const bool compact = pass_compacts<T>(st, pass);
@@ -2245,27 +2260,32 @@ __global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict_
   const SelItem si = items[blockIdx.x];
   const InstDesc& d = D[si.inst];
   const double* S = d.scal;
+  const SetDesc& s = d.sets[si.set];
+  // the state and the histogram (allocated for every selection item) are
+  // loaded with the iteration scalars
   const ItScal isc = it_scal(S);
+  const SelState st0 = load_sel(s.sel[si.src]);
+  const bool l1 = s.kind == SIP_SET_L1;
+  uint32_t* gc = s.hcnt[si.src];
+  acc_t* gs = (acc_t*)s.hsum[si.src];
+  uint32_t cv[kPull];
+  acc_t sv[kPull];
+  pull_issue(gc, gs, l1, cv, sv);
   if (!isc.live()) return;
   const int k = (int)isc.k;
   if (si.src == 1 && !is_check_iter(k, o)) return;
-  const SetDesc& s = d.sets[si.set];
-  if (threadIdx.x == 0) st = *s.sel[si.src];
-  __syncthreads();
-  if (st.mode != SEL_PROJECT || st.err || st.final_) return;
-  const bool l1 = s.kind == SIP_SET_L1;
-  const bool compacted = pass_compacts<T>(st, pass);
-  uint32_t* gc = s.hcnt[si.src];
-  acc_t* gs = (acc_t*)s.hsum[si.src];
-  int dig = st.digit;
+  if (st0.mode != SEL_PROJECT || st0.err || st0.final_) return;
+  if (threadIdx.x == 0) st = st0;  // first read after select_digit's barriers
+  const bool compacted = pass_compacts<T>(st0, pass);
+  const K* cand = (const K*)s.cand[si.src];
+  const unsigned long long ncand = compacted ? st0.ncand : 0ull;
+  int dig = st0.digit;
   int nb = 1 << KT::width(dig);
-  pull_histogram(gc, gs, l1, nb, hc, hs);
+  pull_finish(gc, gs, l1, nb, cv, sv, hc, hs);
   __syncthreads();
   unsigned long long last = select_digit<T>(st, hc, hs, nb, dig, s, l1, lc, ls, &lbest);
   ++dig;
   if (compacted) {
-    const K* cand = (const K*)s.cand[si.src];
-    const unsigned long long ncand = st.ncand;
     for (; dig < KT::ndig; ++dig) {
       if (st.err) break;
       nb = 1 << KT::width(dig);
@@ -2273,7 +2293,8 @@ __global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict_
       const K want = (K)(st.prefix >> shp);
       for (int b = threadIdx.x; b < nb; b += kBlock) { hc[b] = 0; hs[b] = 0; }
       __syncthreads();
-      // eight keys per thread in flight at a time
+      // eight keys per thread in flight at a time (all of them loaded into
+      // registers at once measured slower)
       constexpr int U = 8;
       for (unsigned long long i0 = threadIdx.x; i0 < ncand; i0 += (unsigned long long)kBlock * U) {
         K keys[U];
@@ -2321,12 +2342,12 @@ __global__ __launch_bounds__(kSB) void k_card_ties(const InstDesc* __restrict__ 
   const ThrItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
+  const SetDesc& s = d.sets[it.set];
   const ItScal isc = it_scal(S);
+  const SelState st = load_sel(s.sel[0]);  // with the iteration scalars
   if (!isc.live()) return;
   if (it.src != 0) return;
-  const SetDesc& s = d.sets[it.set];
   if (s.kind != SIP_SET_CARD) return;
-  const SelState st = load_sel(s.sel[0]);
   if (st.mode != SEL_PROJECT || st.err || !st.need_ties) return;
   if (threadIdx.x < 3) tcnt[threadIdx.x] = 0;
   __syncthreads();
@@ -2384,15 +2405,15 @@ __global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ 
   const ThrItem it = items[iti];
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
+  const SetDesc& s = d.sets[it.set];
   const ItScal isc = it_scal(S);
+  const SelState st = load_sel(s.sel[it.src]);  // with the iteration scalars
   if (!isc.live()) return;
   const int k = (int)isc.k;
   const bool adapt = is_adapt_iter(k, o);
   const bool check = is_check_iter(k, o);
   if (it.src == 1 && !check) return;
   const bool have = isc.have != 0.0;
-  const SetDesc& s = d.sets[it.set];
-  const SelState st = load_sel(s.sel[it.src]);
   if (st.err) return;
   const bool l1 = s.kind == SIP_SET_L1;
   // l2 ball / annulus: y = theta w, w, or the point lo e_0; their distance
