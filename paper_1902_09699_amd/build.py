@@ -20,6 +20,9 @@ HIPCC_FLAGS = [
     # packed FP32 instructions stay off: scalar and float2 code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
+    # kernel arguments preloaded into SGPRs at wave launch (no kernarg load
+    # at the head of every kernel's dependent load chain)
+    "-mllvm", "-amdgpu-kernarg-preload-count=16",
     "-Wall", "-Wno-unused-function",
 ]
 
