@@ -340,6 +340,34 @@ int32_t ensure(P*& ptr, int& cap, int need, size_t elem_bytes) {
   return SIP_OK;
 }
 
+// The item block b of a launch takes: block b runs on XCD b mod 8, and each
+// XCD sweeps one contiguous slice of the n live items, which keeps the z/y
+// neighbours a stencil reads in that XCD's L2.  A bijection on [0, n).
+int xcd_item(int b, int n) {
+  const int q = n >> 3, rem = n & 7, x = b & 7, j = b >> 3;
+  return x * q + (x < rem ? x : rem) + j;
+}
+
+// A table in launch order: entry b is the item block b takes (idx = its
+// index in the logical order), entries n .. cap - 1 are sentinels
+// (inst = -1), so a block reads only its own entry to find its work.
+template <typename Item>
+std::vector<Item> launch_order(const std::vector<Item>& v, int cap, bool spread) {
+  const int n = (int)v.size();
+  std::vector<Item> out((size_t)std::max(cap, 0));
+  for (int b = 0; b < cap; ++b) {
+    if (b < n) {
+      const int i = spread ? xcd_item(b, n) : b;
+      out[b] = v[i];
+      out[b].idx = i;
+    } else {
+      out[b] = Item{};
+      out[b].inst = -1;
+    }
+  }
+  return out;
+}
+
 void drop_graphs(sip_batch* b) {
   for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
   b->graphs.clear();
@@ -373,7 +401,7 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
         sel.push_back(SelItem{si, k, src, 0});
         sd.item_begin[src] = (int)thr.size();
         for (int64_t p0 = 0; p0 < N; p0 += tt)
-          thr.push_back(ThrItem{si, k, src, 0, (int)p0, (int)std::min<int64_t>(tt, N - p0)});
+          thr.push_back(ThrItem{si, k, src, 0, (int)p0, (int)std::min<int64_t>(tt, N - p0), 0, 0});
         sd.item_end[src] = (int)thr.size();
       }
     }
@@ -392,7 +420,7 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
             for (int64_t i2 = 0; i2 < e2; ++i2)
               line.push_back(LineItem{si, k, c, (int)dims[la],
                                       (int)(i0 * s.desc.stride[0] + i1 * s.desc.stride[1] + i2),
-                                      (int)s.desc.stride[la]});
+                                      (int)s.desc.stride[la], 0, 0});
       }
       sd.line_end = (int)line.size();
     }
@@ -455,13 +483,28 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   const Counts counts{(int32_t)pt.size(), (int32_t)thr.size(), (int32_t)sel.size(), (int32_t)inst.size(),
                       (int32_t)sp.size(), (int32_t)line.size(), {0, 0}};
   HIP_OK(hipMemcpyAsync(b->d_counts, &counts, sizeof(Counts), hipMemcpyHostToDevice, stream));
-  if (!pt.empty()) HIP_OK(hipMemcpyAsync(b->d_pt, pt.data(), pt.size() * sizeof(PtItem), hipMemcpyHostToDevice, stream));
-  if (!sp.empty()) HIP_OK(hipMemcpyAsync(b->d_sp, sp.data(), sp.size() * sizeof(PtItem), hipMemcpyHostToDevice, stream));
-  if (!thr.empty()) HIP_OK(hipMemcpyAsync(b->d_thr, thr.data(), thr.size() * sizeof(ThrItem), hipMemcpyHostToDevice, stream));
-  if (!sel.empty()) HIP_OK(hipMemcpyAsync(b->d_sel, sel.data(), sel.size() * sizeof(SelItem), hipMemcpyHostToDevice, stream));
-  if (!inst.empty()) HIP_OK(hipMemcpyAsync(b->d_inst, inst.data(), inst.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
-  if (!line.empty())
-    HIP_OK(hipMemcpyAsync(b->d_line, line.data(), line.size() * sizeof(LineItem), hipMemcpyHostToDevice, stream));
+  // every table is written up to its launch size (entries past the live
+  // items are sentinels), in launch order
+  const std::vector<PtItem> pt_l = launch_order(pt, lpt, true), sp_l = launch_order(sp, lsp, true);
+  const std::vector<ThrItem> thr_l = launch_order(thr, lthr, true);
+  const std::vector<LineItem> line_l = launch_order(line, lline, true);
+  std::vector<SelItem> sel_l((size_t)lsel);
+  for (int i = 0; i < lsel; ++i) {
+    if (i < (int)sel.size()) sel_l[i] = sel[i];
+    else { sel_l[i] = SelItem{}; sel_l[i].inst = -1; }
+  }
+  std::vector<int32_t> inst_l((size_t)linst, -1);
+  std::copy(inst.begin(), inst.end(), inst_l.begin());
+  if (lpt) HIP_OK(hipMemcpyAsync(b->d_pt, pt_l.data(), pt_l.size() * sizeof(PtItem), hipMemcpyHostToDevice, stream));
+  if (lsp) HIP_OK(hipMemcpyAsync(b->d_sp, sp_l.data(), sp_l.size() * sizeof(PtItem), hipMemcpyHostToDevice, stream));
+  if (lthr)
+    HIP_OK(hipMemcpyAsync(b->d_thr, thr_l.data(), thr_l.size() * sizeof(ThrItem), hipMemcpyHostToDevice, stream));
+  if (lsel)
+    HIP_OK(hipMemcpyAsync(b->d_sel, sel_l.data(), sel_l.size() * sizeof(SelItem), hipMemcpyHostToDevice, stream));
+  if (linst)
+    HIP_OK(hipMemcpyAsync(b->d_inst, inst_l.data(), inst_l.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  if (lline)
+    HIP_OK(hipMemcpyAsync(b->d_line, line_l.data(), line_l.size() * sizeof(LineItem), hipMemcpyHostToDevice, stream));
   for (int si = 0; si < b->max_slots; ++si) {
     if (!b->slots[si].used) continue;
     HIP_OK(hipMemcpyAsync(b->d_desc + si, &b->slots[si].desc, sizeof(InstDesc), hipMemcpyHostToDevice, stream));

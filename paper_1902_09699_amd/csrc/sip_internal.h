@@ -116,15 +116,18 @@ struct InstDesc {
   SetDesc sets[SIP_MAX_SETS];
 };
 
+// Work items.  inst < 0 marks an entry past the live items of a launch;
+// idx is the item's index in its table's logical order.
 struct PtItem {                   // a range of grid points of one instance
   int32_t inst;
   int32_t begin, len;
-  int32_t pad_;
+  int32_t idx;
 };
 
 struct ThrItem {                  // a range of grid points of one pipeline
   int32_t inst, set, src, comp_parts;
   int32_t begin, len;
+  int32_t idx, pad_;
 };
 
 struct SelItem {                  // one pipeline
@@ -146,6 +149,7 @@ struct Counts { int32_t npt, nthr, nsel, ninst, nsp, nline, pad_[2]; };
 struct LineItem {
   int32_t inst, set, comp, len;
   int32_t start, stride;
+  int32_t idx, pad_;
 };
 
 // Longest line a block sorts in LDS.

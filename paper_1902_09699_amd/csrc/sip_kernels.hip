@@ -2,9 +2,14 @@
 //
 // Every kernel walks a work table: point items (a contiguous range of grid
 // points of one instance), threshold items (a point range of one selection
-// pipeline), selection items (one pipeline) or instances.  Blocks are mapped
-// to items so that each of the 8 XCDs sweeps one contiguous slice of the
-// table, which keeps the z/y neighbours a stencil reads in that XCD's L2.
+// pipeline), selection items (one pipeline) or instances.  A table is stored
+// in launch order, one entry per block of the launch: entry b is the item
+// block b takes (with the item's index in the table's logical order, which
+// orders its partial sums), and entries past the live items have inst < 0.
+// The host orders the entries so that each of the 8 XCDs sweeps one
+// contiguous slice of the logical table, which keeps the z/y neighbours a
+// stencil reads in that XCD's L2; a block reads its entry with no other load
+// before it.
 //
 // Reductions never use atomics on floating point across blocks except the
 // histogram sums, which are exact for float keys (all values in one bucket
@@ -36,11 +41,6 @@ constexpr int kSB = 256;
 constexpr int kSW = kSB / 64;
 
 // ---------------------------------------------------------------- helpers
-
-__device__ __forceinline__ int xcd_item(int b, int G) {
-  const int q = G >> 3, rem = G & 7, x = b & 7, j = b >> 3;
-  return x * q + (x < rem ? x : rem) + j;
-}
 
 // Data-parallel-primitive (DPP) moves: lane permutations inside the VALU,
 // with no LDS round trip.  Rows not in ROW_MASK receive 0.
@@ -878,9 +878,9 @@ template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_cg_dir(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const PtItem* __restrict__ items, int j,
                                                 const double* rr_part, double* pq_part, Opts o) {
   __shared__ acc_t lds[lds_sum<1, NT>()];
-  if ((int)blockIdx.x >= cnt->npt) return;
-  const int iti = xcd_item(blockIdx.x, cnt->npt);
-  const PtItem it = items[iti];
+  const PtItem it = items[blockIdx.x];
+  if (it.inst < 0) return;
+  const int iti = it.idx;
   const InstDesc& d = D[it.inst];
   double* S = d.scal;
   const CgScal q = cg_scal(S);
@@ -930,9 +930,9 @@ __global__ __launch_bounds__(NT) void k_cg_upd(const InstDesc* __restrict__ D, c
                                                 const double* pq_part, double* rr_part) {
   constexpr int W = Grp<T>::W;
   __shared__ acc_t lds[lds_sum<1, NT>()];
-  if ((int)blockIdx.x >= cnt->npt) return;
-  const int iti = xcd_item(blockIdx.x, cnt->npt);
-  const PtItem it = items[iti];
+  const PtItem it = items[blockIdx.x];
+  if (it.inst < 0) return;
+  const int iti = it.idx;
   const InstDesc& d = D[it.inst];
   double* S = d.scal;
   const CgScal qs = cg_scal(S);
@@ -1023,9 +1023,9 @@ __global__ __launch_bounds__(NT) void k_cg1_w0(const InstDesc* __restrict__ D, c
                                                 const PtItem* __restrict__ items, double* dpart) {
   constexpr int W = Grp<T>::W;
   __shared__ acc_t lds[lds_sum<1, NT>()];
-  if ((int)blockIdx.x >= cnt->npt) return;
-  const int iti = xcd_item(blockIdx.x, cnt->npt);
-  const PtItem it = items[iti];
+  const PtItem it = items[blockIdx.x];
+  if (it.inst < 0) return;
+  const int iti = it.idx;
   const InstDesc& d = D[it.inst];
   const CgScal qs = cg_scal(d.scal);
   if (!qs.live()) return;
@@ -1077,9 +1077,9 @@ __global__ __launch_bounds__(NT) void k_cg1_step(const InstDesc* __restrict__ D,
                                                   const double* din, double* gout, double* dout, Opts o) {
   constexpr int W = Grp<T>::W;
   __shared__ acc_t lds_g[2 * (NT / 64)];
-  if ((int)blockIdx.x >= cnt->npt) return;
-  const int iti = xcd_item(blockIdx.x, cnt->npt);
-  const PtItem it = items[iti];
+  const PtItem it = items[blockIdx.x];
+  if (it.inst < 0) return;
+  const int iti = it.idx;
   const InstDesc& d = D[it.inst];
   double* S = d.scal;
   const CgScal qs = cg_scal(S);
@@ -1219,9 +1219,9 @@ template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_rhs(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const PtItem* __restrict__ items, double* rr_part) {
   constexpr int W = Grp<T>::W;
   __shared__ acc_t lds[lds_sum<1, NT>()];
-  if ((int)blockIdx.x >= cnt->npt) return;
-  const int iti = xcd_item(blockIdx.x, cnt->npt);
-  const PtItem it = items[iti];
+  const PtItem it = items[blockIdx.x];
+  if (it.inst < 0) return;
+  const int iti = it.idx;
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
   const CgScal qs = cg_scal(S);
@@ -1387,9 +1387,9 @@ __device__ void proj_block(const InstDesc* __restrict__ D, const Counts* __restr
                            const PtItem* __restrict__ items, const Opts& o, double* parts, int bx, int by) {
   constexpr int W = Grp<T>::W;
   __shared__ acc_t lds[lds_sum<16, kSB>()];
-  if (bx >= cnt->nsp) return;
-  const int iti = xcd_item(bx, cnt->nsp);
-  const PtItem it = items[iti];
+  const PtItem it = items[bx];
+  if (it.inst < 0) return;
+  const int iti = it.idx;
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
   const ItScal isc = it_scal(S);
@@ -1645,9 +1645,9 @@ __device__ void thrw_block(const InstDesc* __restrict__ D, const Counts* __restr
   __shared__ uint32_t hc[kNB];
   __shared__ acc_t hs[kNB];
   __shared__ acc_t lds[lds_sum<8, kSB>()];
-  if (bx >= cnt->nthr) return;
-  const int iti = xcd_item(bx, cnt->nthr);
-  const ThrItem it = items[iti];
+  const ThrItem it = items[bx];
+  if (it.inst < 0) return;
+  const int iti = it.idx;
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
   const ItScal isc = it_scal(S);
@@ -1989,8 +1989,8 @@ __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D,
   __shared__ int lbest;
   __shared__ acc_t lds[lds_sum<2>()];
   __shared__ SelState st;
-  if ((int)blockIdx.x >= cnt->nsel) return;
   const SelItem si = items[blockIdx.x];
+  if (si.inst < 0) return;
   const InstDesc& d = D[si.inst];
   const double* S = d.scal;
   const SetDesc& s = d.sets[si.set];
@@ -2101,9 +2101,8 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
   __shared__ acc_t hs[kNB];
   __shared__ uint32_t wcnt[kSW];
   __shared__ unsigned long long bbase;
-  if ((int)blockIdx.x >= cnt->nthr) return;
-  const int iti = xcd_item(blockIdx.x, cnt->nthr);
-  const ThrItem it = items[iti];
+  const ThrItem it = items[blockIdx.x];
+  if (it.inst < 0) return;
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
   const SetDesc& s = d.sets[it.set];
@@ -2256,8 +2255,8 @@ __global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict_
   __shared__ acc_t ls[kBlock];
   __shared__ int lbest;
   __shared__ SelState st;
-  if ((int)blockIdx.x >= cnt->nsel) return;
   const SelItem si = items[blockIdx.x];
+  if (si.inst < 0) return;
   const InstDesc& d = D[si.inst];
   const double* S = d.scal;
   const SetDesc& s = d.sets[si.set];
@@ -2337,9 +2336,9 @@ __global__ __launch_bounds__(kSB) void k_card_ties(const InstDesc* __restrict__ 
   using KT = KeyT<T>;
   using K = typename KT::K;
   __shared__ uint32_t tcnt[3];
-  if ((int)blockIdx.x >= cnt->nthr) return;
-  const int iti = xcd_item(blockIdx.x, cnt->nthr);
-  const ThrItem it = items[iti];
+  const ThrItem it = items[blockIdx.x];
+  if (it.inst < 0) return;
+  const int iti = it.idx;
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
   const SetDesc& s = d.sets[it.set];
@@ -2400,9 +2399,9 @@ __global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ 
   __shared__ acc_t lds[lds_sum<8, kSB>()];
   __shared__ uint32_t wsum[kSW];
   __shared__ unsigned long long tie_base[3];
-  if ((int)blockIdx.x >= cnt->nthr) return;
-  const int iti = xcd_item(blockIdx.x, cnt->nthr);
-  const ThrItem it = items[iti];
+  const ThrItem it = items[blockIdx.x];
+  if (it.inst < 0) return;
+  const int iti = it.idx;
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
   const SetDesc& s = d.sets[it.set];
@@ -2892,9 +2891,9 @@ __global__ __launch_bounds__(kLB) void k_line(const InstDesc* __restrict__ D, co
   uint32_t* li = (uint32_t*)(line_smem + (size_t)cap * (sizeof(typename KT::K) + sizeof(T)));
   __shared__ acc_t lds[lds_sum<8, kLB>() + kLB];
   __shared__ int ldi[kLB / 64];
-  if ((int)blockIdx.x >= cnt->nline) return;
-  const int iti = xcd_item(blockIdx.x, cnt->nline);
-  const LineItem it = items[iti];
+  const LineItem it = items[blockIdx.x];
+  if (it.inst < 0) return;
+  const int iti = it.idx;
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
   const ItScal isc = it_scal(S);
@@ -3002,8 +3001,9 @@ __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* __restrict__ 
   __shared__ acc_t tout[4 * kMaxUnits + 2][8];
   __shared__ acc_t dots[kMaxUnits][8];
   __shared__ acc_t evol[16];
-  if ((int)blockIdx.x >= cnt->ninst) return;
-  const InstDesc& d = D[insts[blockIdx.x]];
+  const int inst = insts[blockIdx.x];
+  if (inst < 0) return;
+  const InstDesc& d = D[inst];
   double* S = d.scal;
   const ItScal isc = it_scal(S);
   if (isc.state != 0.0) return;
