@@ -2994,8 +2994,11 @@ __device__ bool spectral(double ab, double aa, double bb, double eps, double& es
 // stopping test (eqs. feas_stop, obj_stop, stopping_conditions), then
 // adapt-rho-gamma for i = 1..p+1 with the gamma cap and rho-ratio guard,
 // recompute the stencil scalars of C, and advance k.
+// Eight waves, so the sums of an adapt iteration run in one round.
+constexpr int kFB = 512;
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const int32_t* __restrict__ insts, Opts o,
+__global__ __launch_bounds__(kFB) void k_finish(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const int32_t* __restrict__ insts, Opts o,
                                                    const double* proj_parts, const double* thrw_parts,
                                                    const double* thra_parts, const double* line_parts) {
   __shared__ acc_t tout[4 * kMaxUnits + 2][8];
@@ -3028,7 +3031,10 @@ __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* __restrict__ 
   const bool evol_on = check && d.ring;
   if (evol_on) ntasks += 2;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int t = wv; t < ntasks; t += kBlock / 64) {
+  // this thread's unit's (rho, gamma), loaded with the sums' partials
+  const int uc = (int)threadIdx.x <= p ? (int)threadIdx.x : 0;
+  const double rho_l = ldgd(S + S_RHO + uc), gam_l = ldgd(S + S_GAMMA + uc);
+  for (int t = wv; t < ntasks; t += kFB / 64) {
     // locate task t
     const double* parts = proj_parts;
     int b = d.sp_begin, e = d.sp_end, stride = kProjParts, off = 0;
@@ -3058,9 +3064,23 @@ __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* __restrict__ 
       off = kEvolOff + 8 * rem;
     }
     acc_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int i = b + lane; i < e; i += 64) {
+    // four items per lane in flight at a time, added in item order
+    constexpr int U = 4;
+    for (int i0 = b + lane; i0 < e; i0 += 64 * U) {
+      double q[U][8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] += (acc_t)parts[(size_t)i * stride + off + j];
+      for (int r = 0; r < U; ++r) {
+        const int i = i0 + 64 * r < e ? i0 + 64 * r : i0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) q[r][j] = ldgd(parts + (size_t)i * stride + off + j);
+      }
+#pragma unroll
+      for (int r = 0; r < U; ++r) {
+        if (i0 + 64 * r < e) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) v[j] += (acc_t)q[r][j];
+        }
+      }
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j) v[j] = wave_sum(v[j]);
@@ -3109,7 +3129,7 @@ __global__ __launch_bounds__(kBlock) void k_finish(const InstDesc* __restrict__ 
     if (u == 0) { S[S_ERR] = (double)s_err; S[S_STATE] = 3.0; }
     return;
   }
-  const double rho_u = u <= p ? ldgd(S + S_RHO + u) : 0.0, gam_u = u <= p ? ldgd(S + S_GAMMA + u) : 0.0;
+  const double rho_u = u <= p ? rho_l : 0.0, gam_u = u <= p ? gam_l : 0.0;
   if (d.log && k <= d.log_cap && u <= p) {
     double* row = d.log + (size_t)(k - 1) * 2 * kMaxUnits;
     row[u] = rho_u;
@@ -3279,7 +3299,7 @@ void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
     k_line<T><<<t.nline, kLB, t.line_cap * line_lds_per_entry<T>(), st>>>(t.D, t.cnt, t.line, o, t.line_part,
                                                                          t.line_cap);
   if (t.ninst > 0)
-    k_finish<T><<<t.ninst, kBlock, 0, st>>>(t.D, t.cnt, t.inst, o, t.proj_part, t.thrw_part, t.thra_part,
+    k_finish<T><<<t.ninst, kFB, 0, st>>>(t.D, t.cnt, t.inst, o, t.proj_part, t.thrw_part, t.thra_part,
                                             t.line_part);
 }
 
