@@ -209,7 +209,7 @@ struct Layout {
   int64_t total = 0;
   int64_t log = -1, m, r, p0, p1, cr[2], cp[2], yl, vl, vh0l = -1, v0l = -1, y0l = -1, xs0 = -1, xs1 = -1, ring = -1;
   struct SetL { int64_t y, v, vh0 = -1, v0 = -1, y0 = -1, lov = -1, hiv = -1; int64_t sel[2] = {-1, -1}, hc[2] = {-1, -1},
-                hs[2] = {-1, -1}, cand[2] = {-1, -1}; } set[SIP_MAX_SETS];
+                hs[2] = {-1, -1}, cand[2] = {-1, -1}, cix = -1; } set[SIP_MAX_SETS];
 };
 
 Layout layout_of(const sip_grid& g, const sip_set* sets, int nsets, const sip_opts& o) {
@@ -244,6 +244,7 @@ Layout layout_of(const sip_grid& g, const sip_set* sets, int nsets, const sip_op
         S.hs[src] = take(kNB * 8);
         S.cand[src] = take((int64_t)oi.ncomp * N * esz);
       }
+      if (sets[i].kind == SIP_SET_CARD) S.cix = take((int64_t)oi.ncomp * N * 4);
     }
   }
   L.total = align_up(off);
@@ -379,7 +380,6 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   std::vector<SelItem> sel;
   std::vector<LineItem> line;
   std::vector<int32_t> inst;
-  bool any_card = false;
   for (int si = 0; si < b->max_slots; ++si) {
     Slot& s = b->slots[si];
     if (!s.used) continue;
@@ -396,7 +396,6 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
     for (int k = 0; k < s.nsets; ++k) {
       SetDesc& sd = s.desc.sets[k];
       if (sd.thr < 0) continue;
-      if (sd.kind == SIP_SET_CARD) any_card = true;
       for (int src = 0; src < (b->opts.stop_every > 0 ? 2 : 1); ++src) {
         sel.push_back(SelItem{si, k, src, 0});
         sd.item_begin[src] = (int)thr.size();
@@ -435,7 +434,7 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   const int lsp = pow2((int)sp.size(), 64);
   const int lline = pow2((int)line.size(), 64);
   const bool relaunch = lpt != b->tab.npt || lthr != b->tab.nthr || lsel != b->tab.nsel || linst != b->tab.ninst ||
-                        lsp != b->tab.nsp || lline != b->tab.nline || any_card != b->tab.any_card;
+                        lsp != b->tab.nsp || lline != b->tab.nline;
   int32_t rc;
   const int old_pt = b->cap_pt, old_thr = b->cap_thr, old_sel = b->cap_sel, old_inst = b->cap_inst;
   const int old_sp = b->cap_sp, old_line = b->cap_line;
@@ -532,7 +531,6 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   if (units != t.proj_units) relaunch_cap = true;
   t.proj_units = units;
   t.thrw_part = b->d_thrw; t.thra_part = b->d_thra; t.tie_part = b->d_tie;
-  t.any_card = any_card;
   const bool threads_changed = t.pt_threads != (int)b->tiles.pt_threads || t.cg_form != b->tiles.cg_form;
   t.pt_threads = (int)b->tiles.pt_threads;
   t.cg_form = b->tiles.cg_form;
@@ -753,6 +751,7 @@ int32_t sip_batch_add(sip_batch* b, const sip_grid* g, const sip_set* sets, int3
       sd.hsum[src] = (double*)at(SL.hs[src]);
       sd.cand[src] = at(SL.cand[src]);
     }
+    sd.cand_ix = (uint32_t*)at(SL.cix);
   }
   const size_t esz = b->opts.field == SIP_F64 ? 8 : 4;
   double S[S_COUNT];

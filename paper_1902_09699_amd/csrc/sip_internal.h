@@ -85,6 +85,7 @@ struct SetDesc {
   uint32_t* hcnt[2];
   double* hsum[2];
   void* cand[2];                  // candidate keys (u32 or u64), ncomp*N entries
+  uint32_t* cand_ix;              // cardinality, pipeline 0: each candidate's item * 3 + component
   int32_t item_begin[2], item_end[2];  // threshold-item range of each pipeline
   int32_t line_begin, line_end;        // line-item range of a line-wise set
 };
@@ -172,7 +173,6 @@ struct Tables {
   int proj_units;                      // projection blocks per item: max over instances of nsets + 2
   double* line_part;                   // 8 partial sums per line item
   uint32_t* tie_part;
-  bool any_card;
   int pt_threads;  // threads per block of the RHS and CG kernels (256 or 512)
   int cg_form;     // 0: two launches per CG step; 1: one (Chronopoulos-Gear)
 };

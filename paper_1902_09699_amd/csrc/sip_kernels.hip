@@ -2081,12 +2081,14 @@ __device__ __forceinline__ SelState load_sel(const SelState* p) {
   return st;
 }
 
-// Whether refine pass `pass` (0 or 1) appends candidate keys: only if digits
-// remain after the one it histograms, and then when the bucket it refines is
-// small or on the second pass (the select kernel finishes over them).
+// Whether refine pass `pass` (0 or 1) appends candidate keys: the first when
+// digits remain after the one it histograms and the bucket it refines is
+// small, the second always.  The threshold is therefore always final in a
+// selection stage that holds the candidates, among them every entry equal to
+// the k-th magnitude (so that stage also counts the cardinality ties).
 template <typename T>
 __device__ __forceinline__ bool pass_compacts(const SelState& st, int pass) {
-  return st.digit + 1 < KeyT<T>::ndig && (st.compact_next || pass == 1);
+  return pass == 1 || (st.compact_next && st.digit + 1 < KeyT<T>::ndig);
 }
 
 // Refine pass over all values: histogram of digit st.digit among entries
@@ -2103,6 +2105,7 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
   __shared__ unsigned long long bbase;
   const ThrItem it = items[blockIdx.x];
   if (it.inst < 0) return;
+  const int iti = it.idx;
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
   const SetDesc& s = d.sets[it.set];
@@ -2123,6 +2126,7 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
   const Geo g(d);
   const T* __restrict__ x = (const T*)d.x;
   K* __restrict__ cand = (K*)s.cand[it.src];
+  uint32_t* __restrict__ cix = it.src == 0 ? s.cand_ix : nullptr;  // cardinality: where each candidate lies
   unsigned long long* ncand = &s.sel[it.src]->ncand;
   constexpr int W = Grp<T>::W;
   constexpr int CB = W == 4 ? 3 : 2;  // bits of a per-thread hit count (0..W)
@@ -2220,9 +2224,14 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
         if (nhit) {
           unsigned long long off = bbase + pre;
           for (int q = 0; q < wv; ++q) off += wcnt[q];
+          const uint32_t code = (uint32_t)iti * 3u + (uint32_t)c;
 #pragma unroll
-          for (int e = 0; e < W; ++e)
-            if (hit[e]) cand[off++] = key[e];
+          for (int e = 0; e < W; ++e) {
+            if (hit[e]) {
+              if (cix) cix[off] = code;
+              cand[off++] = key[e];
+            }
+          }
         }
         __syncthreads();
       }
@@ -2246,7 +2255,8 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
 // appends candidates.  Ends with theta (l1) or the k-th magnitude and the tie
 // bookkeeping (cardinality) once final.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const SelItem* __restrict__ items, Opts o, int pass) {
+__global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const SelItem* __restrict__ items, Opts o, int pass,
+                                                     uint32_t* tie_part) {
   using KT = KeyT<T>;
   using K = typename KT::K;
   __shared__ uint32_t hc[kNB];
@@ -2325,66 +2335,31 @@ __global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict_
     st.compact_next = last <= kCandCap ? 1 : 0;
   }
   __syncthreads();
-  if (threadIdx.x == 0) *s.sel[si.src] = st;
-}
-
-// Cardinality ties straddling the cut: count entries equal to the k-th
-// magnitude per (item, component) so the apply pass can rank them by index.
-template <typename T>
-__global__ __launch_bounds__(kSB) void k_card_ties(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const ThrItem* __restrict__ items, Opts o,
-                                                      uint32_t* tie_part) {
-  using KT = KeyT<T>;
-  using K = typename KT::K;
-  __shared__ uint32_t tcnt[3];
-  const ThrItem it = items[blockIdx.x];
-  if (it.inst < 0) return;
-  const int iti = it.idx;
-  const InstDesc& d = D[it.inst];
-  const double* S = d.scal;
-  const SetDesc& s = d.sets[it.set];
-  const ItScal isc = it_scal(S);
-  const SelState st = load_sel(s.sel[0]);  // with the iteration scalars
-  if (!isc.live()) return;
-  if (it.src != 0) return;
-  if (s.kind != SIP_SET_CARD) return;
-  if (st.mode != SEL_PROJECT || st.err || !st.need_ties) return;
-  if (threadIdx.x < 3) tcnt[threadIdx.x] = 0;
-  __syncthreads();
-  const Geo g(d);
-  const K tkey = (K)st.tkey;
-  const int end = it.begin + it.len;
-  constexpr int W = Grp<T>::W;
-  const bool grouped = item_grouped(d);
-  for (int c = 0; c < s.ncomp; ++c) {
-    const T* y = (const T*)s.y + (size_t)c * g.cs;
-    uint32_t local = 0;
-    for (int base = it.begin; base < end; base += kSB * W) {
-      const int P0 = base + (int)threadIdx.x * W;
-      if (grouped) {
-        const GLane L = glane<T>(P0, it.begin, end, g);
-        if (L.vec) {
-          bool ok[W];
-          T v[W];
-          group_valid<T>(L, g, s.axis[c], ok);
-          ld16<T>(y + P0, v);
+  if (st.final_ && st.need_ties && s.cand_ix && si.src == 0 && compacted) {
+    // entries equal to the k-th magnitude per (item, component), for the
+    // apply pass to rank them by linear index: every such entry is a
+    // candidate, and the candidate's code says where it lies
+    const int ib = s.item_begin[0], ie = s.item_end[0];
+    for (int q = ib * 3 + (int)threadIdx.x; q < ie * 3; q += kBlock) tie_part[q] = 0u;
+    __syncthreads();
+    const K tk = (K)st.tkey;
+    const uint32_t* __restrict__ cix = s.cand_ix;
+    constexpr int U = 8;
+    for (unsigned long long i0 = threadIdx.x; i0 < ncand; i0 += (unsigned long long)kBlock * U) {
+      K keys[U];
 #pragma unroll
-          for (int e = 0; e < W; ++e)
-            if (ok[e] && KT::key(v[e]) == tkey) ++local;
-        }
-      } else {
-        for (int e = 0; e < W; ++e) {
-          const int P = P0 + e;
-          if (P >= end) break;
-          int iz, iy, ix;
-          g.coords(P, iz, iy, ix);
-          if (comp_valid(s.axis[c], iz, iy, ix, g) && KT::key(y[P]) == tkey) ++local;
-        }
+      for (int u = 0; u < U; ++u) {
+        const unsigned long long i = i0 + (unsigned long long)u * kBlock;
+        keys[u] = *(__attribute__((address_space(1))) const K*)(cand + (i < ncand ? i : 0));
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const unsigned long long i = i0 + (unsigned long long)u * kBlock;
+        if (i < ncand && keys[u] == tk) atomicAdd(&tie_part[cix[i]], 1u);
       }
     }
-    if (local) atomicAdd(&tcnt[c], local);
   }
-  __syncthreads();
-  if (threadIdx.x < 3) tie_part[(size_t)iti * 3 + threadIdx.x] = tcnt[threadIdx.x];
+  if (threadIdx.x == 0) *s.sel[si.src] = st;
 }
 
 // Apply pass.  Pipeline 0: y = soft threshold of w (l1) or w on the kept
@@ -3289,10 +3264,9 @@ void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
   if (t.nthr > 0) {
     k_sel1<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, t.thrw_part);
     k_thr_refine<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, 0);
-    k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 0);
+    k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 0, t.tie_part);
     k_thr_refine<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, 1);
-    k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 1);
-    if (t.any_card) k_card_ties<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.tie_part);
+    k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 1, t.tie_part);
     k_thr_apply<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thra_part, t.tie_part);
   }
   if (t.nline > 0)

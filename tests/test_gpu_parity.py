@@ -314,6 +314,41 @@ def test_card_exact_ties_lockstep(field, seed):
             assert (yg != 0).sum() <= sets[i]["k"]
 
 
+@pytest.mark.parametrize("field", ["f64", "f32"])
+def test_card_exact_ties_across_items(field):
+    """Ties with the k-th magnitude spread over many threshold items (small
+    threshold tiles) and over the two components of GRAD: the kept support
+    ranks them by linear index across items and components, as the oracle
+    does, step by step."""
+    rng = np.random.default_rng(11)
+    m = rng.integers(-3, 4, size=(40, 70)).astype(np.float64)
+    sets = [{"kind": "card", "op": "I", "k": 900}, {"kind": "card", "op": "GRAD", "k": 1700}]
+    sl = Slot(m, sets, field, dict(max_iter=20, cg_max=10, cg_fixed=1), tiles=(1024, 1024, 256, 512, 256, 0))
+    print(f"\n[ties across items] {field} shape={m.shape}", flush=True)
+    prob = orc.Problem(m, m.shape, sets)
+    oo = orc.Options(max_iter=20, cg_max=10, cg_fixed=True)
+    st = orc.initial_state(prob, oo)
+    tied = 0
+    for it in range(6):
+        sync_oracle(sl, prob, st)
+        orc.iterate(prob, st, oo)
+        sl.batch.run(1)
+        if it == 0:
+            nthr = sl.batch.items()[1]
+            print(f"[ties across items] {nthr} threshold items", flush=True)
+            assert nthr >= 20
+        for i in range(2):
+            yg = sl.arr(sip.FIELD_Y, i)
+            nz = st.y[i] != 0
+            a = np.abs(st.y[i][nz])
+            if a.size:
+                tied = max(tied, int((a == a.min()).sum()))
+            assert np.array_equal(yg != 0, nz), (it, i)
+            assert (yg != 0).sum() <= sets[i]["k"]
+    # the check is only meaningful if the smallest kept magnitude is shared
+    assert tied > 1
+
+
 @pytest.mark.parametrize("field,form", [("f64", 0), ("f64", 1), ("f32", 0), ("f32", 1)])
 def test_unaligned_x(field, form):
     """x one element past a 16-byte boundary: the RHS and CG kernels take
