@@ -531,6 +531,16 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   if (units != t.proj_units) relaunch_cap = true;
   t.proj_units = units;
   t.thrw_part = b->d_thrw; t.thra_part = b->d_thra; t.tie_part = b->d_tie;
+  int64_t pipe_rows = 0;
+  for (int si = 0; si < b->max_slots; ++si) {
+    const Slot& sl = b->slots[si];
+    if (!sl.used) continue;
+    for (int k = 0; k < sl.nsets; ++k)
+      if (sl.desc.sets[k].thr >= 0) pipe_rows = std::max<int64_t>(pipe_rows, sl.desc.sets[k].rows);
+  }
+  const int passes = pipe_rows <= kOnePassRows ? 1 : 2;
+  if (passes != t.sel_passes) relaunch_cap = true;
+  t.sel_passes = passes;
   const bool threads_changed = t.pt_threads != (int)b->tiles.pt_threads || t.cg_form != b->tiles.cg_form;
   t.pt_threads = (int)b->tiles.pt_threads;
   t.cg_form = b->tiles.cg_form;

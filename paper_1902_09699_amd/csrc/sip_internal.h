@@ -175,7 +175,14 @@ struct Tables {
   uint32_t* tie_part;
   int pt_threads;  // threads per block of the RHS and CG kernels (256 or 512)
   int cg_form;     // 0: two launches per CG step; 1: one (Chronopoulos-Gear)
+  int sel_passes;  // refine + select passes after the first stage: 1 (it always compacts) or 2
 };
+
+// One refine pass (which then always appends candidates, and the select
+// stage after it finishes over them) when every threshold pipeline of the
+// batch has at most this many entries; two otherwise (the first appends only
+// a bucket of at most kCandCap entries).
+constexpr int64_t kOnePassRows = 1 << 19;
 
 inline FastDiv make_fastdiv(uint32_t d) {
   FastDiv f;

@@ -2081,9 +2081,9 @@ __device__ __forceinline__ SelState load_sel(const SelState* p) {
   return st;
 }
 
-// Whether refine pass `pass` (0 or 1) appends candidate keys: the first when
-// digits remain after the one it histograms and the bucket it refines is
-// small, the second always.  The threshold is therefore always final in a
+// Whether refine pass `pass` (0 or 1; 1 is the last pass of the iteration)
+// appends candidate keys: the first when digits remain after the one it
+// histograms and the bucket it refines is small, the last always.  The threshold is therefore always final in a
 // selection stage that holds the candidates, among them every entry equal to
 // the k-th magnitude (so that stage also counts the cardinality ties).
 template <typename T>
@@ -3263,8 +3263,11 @@ void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
     k_thr_w<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thrw_part);
   if (t.nthr > 0) {
     k_sel1<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, t.thrw_part);
-    k_thr_refine<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, 0);
-    k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 0, t.tie_part);
+    if (t.sel_passes == 2) {
+      k_thr_refine<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, 0);
+      k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 0, t.tie_part);
+    }
+    // the last pass always appends candidates, so its select stage is final
     k_thr_refine<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, 1);
     k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 1, t.tie_part);
     k_thr_apply<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thra_part, t.tie_part);
