@@ -1829,15 +1829,16 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, c
 }
 
 // The projection pass and the threshold sets' w pass in one launch: both read
-// only x and their own sets' arrays, so they run side by side (blocks below
-// nsp * units project, the rest take threshold items).
+// only x and their own sets' arrays, so they run side by side.  The w-pass
+// blocks (the longer ones) come first, so they are dispatched in the first
+// wave of resident blocks and the projection blocks fill in behind them.
 template <typename T>
 __global__ __launch_bounds__(kSB) void k_sets(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt,
                                               const PtItem* __restrict__ sp, const ThrItem* __restrict__ thr, Opts o,
-                                              double* proj_parts, double* thrw_parts, int nsp, int units) {
-  const int b = (int)blockIdx.x, np = nsp * units;
-  if (b < np) proj_block<T>(D, cnt, sp, o, proj_parts, b % nsp, b / nsp);
-  else thrw_block<T>(D, cnt, thr, o, thrw_parts, b - np);
+                                              double* proj_parts, double* thrw_parts, int nsp, int units, int nthr) {
+  const int b = (int)blockIdx.x;
+  if (b < nthr) thrw_block<T>(D, cnt, thr, o, thrw_parts, b);
+  else proj_block<T>(D, cnt, sp, o, proj_parts, (b - nthr) % nsp, (b - nthr) / nsp);
 }
 
 // ---------------------------------------------- selection (one block each)
@@ -3256,7 +3257,7 @@ void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
   const bool proj = t.npt > 0 && t.nsp > 0;
   if (proj && t.nthr > 0)
     k_sets<T><<<t.nsp * t.proj_units + t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.sp, t.thr, o, t.proj_part, t.thrw_part,
-                                                              t.nsp, t.proj_units);
+                                                              t.nsp, t.proj_units, t.nthr);
   else if (proj)
     k_proj<T><<<dim3(t.nsp, t.proj_units), kSB, 0, st>>>(t.D, t.cnt, t.sp, o, t.proj_part);
   else if (t.nthr > 0)
