@@ -541,6 +541,12 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   const int passes = pipe_rows <= kOnePassRows ? 1 : 2;
   if (passes != t.sel_passes) relaunch_cap = true;
   t.sel_passes = passes;
+  int64_t points = 0;
+  for (int si = 0; si < b->max_slots; ++si)
+    if (b->slots[si].used) points += b->slots[si].N;
+  const int fuse = points <= kFuseSetsPoints ? 1 : 0;
+  if (fuse != t.fuse_sets) relaunch_cap = true;
+  t.fuse_sets = fuse;
   const bool threads_changed = t.pt_threads != (int)b->tiles.pt_threads || t.cg_form != b->tiles.cg_form;
   t.pt_threads = (int)b->tiles.pt_threads;
   t.cg_form = b->tiles.cg_form;

@@ -176,7 +176,13 @@ struct Tables {
   int pt_threads;  // threads per block of the RHS and CG kernels (256 or 512)
   int cg_form;     // 0: two launches per CG step; 1: one (Chronopoulos-Gear)
   int sel_passes;  // refine + select passes after the first stage: 1 (it always compacts) or 2
+  int fuse_sets;   // projection and w passes in one launch (small, latency-bound batches)
 };
+
+// The projection and w passes share a launch when the batch holds at most
+// this many grid points (measured: one launch is faster up to a 4M-point
+// grid, two launches for a 21M-point batch of 256 instances).
+constexpr int64_t kFuseSetsPoints = 1 << 23;
 
 // One refine pass (which then always appends candidates, and the select
 // stage after it finishes over them) when every threshold pipeline of the

@@ -3255,13 +3255,13 @@ void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
     else launch_cg<T, 512>(st, t, o);
   }
   const bool proj = t.npt > 0 && t.nsp > 0;
-  if (proj && t.nthr > 0)
+  if (proj && t.nthr > 0 && t.fuse_sets) {
     k_sets<T><<<t.nsp * t.proj_units + t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.sp, t.thr, o, t.proj_part, t.thrw_part,
                                                               t.nsp, t.proj_units, t.nthr);
-  else if (proj)
-    k_proj<T><<<dim3(t.nsp, t.proj_units), kSB, 0, st>>>(t.D, t.cnt, t.sp, o, t.proj_part);
-  else if (t.nthr > 0)
-    k_thr_w<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thrw_part);
+  } else {
+    if (proj) k_proj<T><<<dim3(t.nsp, t.proj_units), kSB, 0, st>>>(t.D, t.cnt, t.sp, o, t.proj_part);
+    if (t.nthr > 0) k_thr_w<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thrw_part);
+  }
   if (t.nthr > 0) {
     k_sel1<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, t.thrw_part);
     if (t.sel_passes == 2) {
