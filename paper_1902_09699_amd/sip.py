@@ -72,6 +72,18 @@ class SipError(RuntimeError):
 _lib = None
 
 
+def _torch_first():
+    """torch (which allocates the caller's device tensors) brings its own HIP
+    runtime; it failed to find the GPU when the library's runtime had opened
+    it first, so torch's is initialised before the library is loaded."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 def lib():
     """Load libsip.so (raises when it has not been built)."""
     global _lib
@@ -79,6 +91,7 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_1902_09699_amd/build.py")
+    _torch_first()
     L = C.CDLL(LIB_PATH)
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     sig = {
