@@ -311,6 +311,7 @@ struct sip_batch {
   int32_t* d_inst = nullptr; int cap_inst = 0;
   double *d_rr = nullptr, *d_pq = nullptr, *d_rr2 = nullptr, *d_pq2 = nullptr, *d_proj = nullptr, *d_thrw = nullptr, *d_thra = nullptr;
   uint32_t* d_tie = nullptr;
+  uint32_t* d_h1c = nullptr; double* d_h1s = nullptr; int cap_h1 = 0;  // refine histograms, kNB per pipeline
   int cap_ppt = 0, cap_pthr = 0, cap_psp = 0;   // item capacity of the partial-sum buffers
   sip::PtItem* d_sp = nullptr; int cap_sp = 0;
   sip::LineItem* d_line = nullptr; int cap_line = 0;
@@ -400,7 +401,7 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
         sel.push_back(SelItem{si, k, src, 0});
         sd.item_begin[src] = (int)thr.size();
         for (int64_t p0 = 0; p0 < N; p0 += tt)
-          thr.push_back(ThrItem{si, k, src, 0, (int)p0, (int)std::min<int64_t>(tt, N - p0), 0, 0});
+          thr.push_back(ThrItem{si, k, src, 0, (int)p0, (int)std::min<int64_t>(tt, N - p0), 0, (int)sel.size() - 1});
         sd.item_end[src] = (int)thr.size();
       }
     }
@@ -470,6 +471,15 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
     b->cap_psp = b->cap_sp;
     moved = true;
   }
+  if (b->cap_h1 < b->cap_sel) {
+    if (b->d_h1c) { HIP_OK(hipFree(b->d_h1c)); HIP_OK(hipFree(b->d_h1s)); }
+    HIP_OK(hipMalloc((void**)&b->d_h1c, (size_t)b->cap_sel * kNB * 4));
+    HIP_OK(hipMalloc((void**)&b->d_h1s, (size_t)b->cap_sel * kNB * 8));
+    launch_zero(stream, b->d_h1c, (int64_t)b->cap_sel * kNB);
+    launch_zero(stream, b->d_h1s, (int64_t)b->cap_sel * kNB);
+    b->cap_h1 = b->cap_sel;
+    moved = true;
+  }
   if (b->cap_pthr < b->cap_thr) {
     if (b->d_thrw) { HIP_OK(hipFree(b->d_thrw)); HIP_OK(hipFree(b->d_thra)); HIP_OK(hipFree(b->d_tie)); }
     HIP_OK(hipMalloc((void**)&b->d_thrw, (size_t)b->cap_thr * kThrParts * 8));
@@ -531,6 +541,7 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   if (units != t.proj_units) relaunch_cap = true;
   t.proj_units = units;
   t.thrw_part = b->d_thrw; t.thra_part = b->d_thra; t.tie_part = b->d_tie;
+  t.h1c = b->d_h1c; t.h1s = b->d_h1s;
   int64_t pipe_rows = 0;
   for (int si = 0; si < b->max_slots; ++si) {
     const Slot& sl = b->slots[si];
@@ -547,6 +558,9 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   const int fuse = points <= kFuseSetsPoints ? 1 : 0;
   if (fuse != t.fuse_sets) relaunch_cap = true;
   t.fuse_sets = fuse;
+  const int sfuse = (passes == 1 && (int)thr.size() <= kFuseSelItems) ? 1 : 0;
+  if (sfuse != t.sel_fused) relaunch_cap = true;
+  t.sel_fused = sfuse;
   const bool threads_changed = t.pt_threads != (int)b->tiles.pt_threads || t.cg_form != b->tiles.cg_form;
   t.pt_threads = (int)b->tiles.pt_threads;
   t.cg_form = b->tiles.cg_form;
@@ -691,7 +705,7 @@ int32_t sip_batch_destroy(sip_batch* b) {
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   void* dev[] = {b->d_desc, b->d_scal, b->d_pt, b->d_thr, b->d_sel, b->d_inst, b->d_rr, b->d_pq,
                  b->d_rr2, b->d_pq2, b->d_proj, b->d_thrw, b->d_thra, b->d_tie, b->d_counts, b->d_sp,
-                 b->d_line, b->d_linep};
+                 b->d_line, b->d_linep, b->d_h1c, b->d_h1s};
   for (void* p : dev) if (p) (void)hipFree(p);
   if (b->h_scal) (void)hipHostFree(b->h_scal);
   delete b;
@@ -797,14 +811,6 @@ int32_t sip_batch_add(sip_batch* b, const sip_grid* g, const sip_set* sets, int3
     if (rc == SIP_OK && vec_bounds && hipStreamSynchronize(stream) != hipSuccess) rc = SIP_EHIP;
   }
   if (rc == SIP_OK) {
-    for (int i = 0; i < nsets; ++i) {
-      const SetDesc& sd = d.sets[i];
-      for (int src = 0; src < 2; ++src) {
-        if (!sd.hcnt[src]) continue;
-        launch_zero(stream, sd.hcnt[src], kNB);
-        launch_zero(stream, sd.hsum[src], kNB);
-      }
-    }
     if (b->opts.field == SIP_F64) launch_init<double>(stream, b->d_desc, si, s.N);
     else launch_init<float>(stream, b->d_desc, si, s.N);
     if (hipGetLastError() != hipSuccess) rc = SIP_EHIP;
@@ -976,14 +982,6 @@ int32_t sip_batch_reset(sip_batch* b, int32_t slot, const void* m_dev, void* str
   initial_scalars(b, s, S);
   HIP_OK(hipMemcpyAsync(s.desc.m, m_dev, (size_t)s.N * esz, hipMemcpyDeviceToDevice, stream));
   HIP_OK(hipMemcpyAsync(s.desc.scal, S, sizeof(S), hipMemcpyHostToDevice, stream));
-  for (int i = 0; i < s.nsets; ++i) {
-    const SetDesc& sd = s.desc.sets[i];
-    for (int src = 0; src < 2; ++src) {
-      if (!sd.hcnt[src]) continue;
-      launch_zero(stream, sd.hcnt[src], kNB);
-      launch_zero(stream, sd.hsum[src], kNB);
-    }
-  }
   if (b->opts.field == SIP_F64) launch_init<double>(stream, b->d_desc, slot, s.N);
   else launch_init<float>(stream, b->d_desc, slot, s.N);
   HIP_OK(hipGetLastError());

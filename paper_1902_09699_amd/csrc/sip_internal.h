@@ -128,7 +128,7 @@ struct PtItem {                   // a range of grid points of one instance
 struct ThrItem {                  // a range of grid points of one pipeline
   int32_t inst, set, src, comp_parts;
   int32_t begin, len;
-  int32_t idx, pad_;
+  int32_t idx, pipe;              // pipe: the pipeline's index in the selection table
 };
 
 struct SelItem {                  // one pipeline
@@ -173,11 +173,19 @@ struct Tables {
   int proj_units;                      // projection blocks per item: max over instances of nsets + 2
   double* line_part;                   // 8 partial sums per line item
   uint32_t* tie_part;
+  uint32_t* h1c; double* h1s;          // per pipeline (selection-table order): the refine histogram
+                                       // when the first selection stage runs inside the refine pass
   int pt_threads;  // threads per block of the RHS and CG kernels (256 or 512)
   int cg_form;     // 0: two launches per CG step; 1: one (Chronopoulos-Gear)
   int sel_passes;  // refine + select passes after the first stage: 1 (it always compacts) or 2
   int fuse_sets;   // projection and w passes in one launch (small, latency-bound batches)
+  int sel_fused;   // first selection stage done by every block of the (single) refine pass
 };
+
+// The first selection stage runs inside the refine pass (every block reads
+// the 2048-bucket first-digit histogram) when the batch has one refine pass
+// and at most this many threshold items.
+constexpr int kFuseSelItems = 1024;
 
 // The projection and w passes share a launch when the batch holds at most
 // this many grid points (measured: one launch is faster up to a 4M-point

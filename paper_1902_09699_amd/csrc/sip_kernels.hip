@@ -357,7 +357,8 @@ __device__ __forceinline__ bool comp_valid(int axis, int iz, int iy, int ix, con
 // ------------------------------------------------------------ initialise
 
 // Admission of one instance: x = m, y_i = A_i m, v_i = 0, y_{p+1} = m,
-// v_{p+1} = 0, x-history slot 0 = m.  d.m is the instance's private copy of m.
+// v_{p+1} = 0, x-history slot 0 = m, clear selection histograms and states.
+// d.m is the instance's private copy of m.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_init(const InstDesc* __restrict__ D, int inst) {
   const InstDesc& d = D[inst];
@@ -367,6 +368,21 @@ __global__ __launch_bounds__(kBlock) void k_init(const InstDesc* __restrict__ D,
   T* yl = (T*)d.yl;
   T* vl = (T*)d.vl;
   T* ring = (T*)d.ring;
+  if (blockIdx.x == 0) {
+    // the selection pipelines start from clear histograms and states
+    for (int si = 0; si < d.nsets; ++si) {
+      const SetDesc& s = d.sets[si];
+      for (int src = 0; src < 2; ++src) {
+        if (!s.hcnt[src]) continue;
+        for (int b = threadIdx.x; b < kNB; b += kBlock) {
+          s.hcnt[src][b] = 0u;
+          s.hsum[src][b] = 0.0;
+        }
+        uint32_t* q = (uint32_t*)s.sel[src];
+        for (int w = threadIdx.x; w < (int)(sizeof(SelState) / 4); w += kBlock) q[w] = 0u;
+      }
+    }
+  }
   for (int P = blockIdx.x * kBlock + (int)threadIdx.x; P < g.N; P += gridDim.x * kBlock) {
     int iz, iy, ix;
     g.coords(P, iz, iy, ix);
@@ -1877,6 +1893,27 @@ __device__ __forceinline__ void pull_finish(uint32_t* gc, acc_t* gs, bool l1, in
   }
 }
 
+// pull_finish without the clearing (the histogram is read by several blocks).
+__device__ __forceinline__ void pull_store(int nb, const uint32_t (&cv)[kPull], const acc_t (&sv)[kPull],
+                                           uint32_t* hc, acc_t* hs) {
+#pragma unroll
+  for (int r = 0; r < kPull; ++r) {
+    const int b = (int)threadIdx.x + r * kBlock;
+    if (b < nb) {
+      hc[b] = cv[r];
+      hs[b] = sv[r];
+    }
+  }
+}
+
+// The state fields a block publishes while other blocks of the same launch
+// may still append candidates (everything but the candidate count).
+__device__ __forceinline__ void store_sel_but_ncand(SelState* g, const SelState& v) {
+  g->prefix = v.prefix; g->c_above = v.c_above; g->tkey = v.tkey; g->keep_ties = v.keep_ties; g->ties = v.ties;
+  g->s_above = v.s_above; g->theta = v.theta; g->tk = v.tk; g->digit = v.digit; g->mode = v.mode;
+  g->need_ties = v.need_ties; g->err = v.err; g->compact_next = v.compact_next; g->final_ = v.final_;
+}
+
 // Pick the bucket of the current digit.  l1: the largest bucket b whose lower
 // edge L_b still has f(L_b) = sum_{u >= L_b} (u - L_b) >= tau (f decreases, so
 // the soft threshold theta with f(theta) = tau lies in bucket b).  Cardinality:
@@ -1977,12 +2014,78 @@ __device__ void finish_selection(SelState& st, const SetDesc& s, unsigned long l
   }
 }
 
-// Stage 1: totals, mode, first digit.  Clears the global histogram for the
-// refine pass.  The state is worked on in LDS and written back once.
+// The selection state of an l2 ball or annulus pipeline from ||w||^2 (the w
+// pass's per-item partials in item order): the projection is a scaling (or,
+// for an annulus at w = 0, a point).  Every thread calls this; the state is
+// valid in thread 0.
+__device__ __forceinline__ SelState l2_stage(const SetDesc& s, int src, const double* __restrict__ thrw_parts, acc_t* lds) {
+  acc_t n2[1];
+  reduce_range<1>(thrw_parts, s.item_begin[src], s.item_end[src], kThrParts, src == 0 ? 6 : 7, n2, lds);
+  SelState q{};
+  q.final_ = 1;
+  q.mode = SEL_INSIDE;
+  const double sq = (double)n2[0];
+  if (!(sq <= 1.0e300)) q.err = SIP_ENUMERIC;
+  const double nrm = sqrt(sq);
+  if (src == 0 && !q.err) {
+    if (s.kind == SIP_SET_L2) {
+      if (nrm > s.tau) { q.mode = SEL_PROJECT; q.theta = s.tau / nrm; }
+    } else if (nrm > s.hi) {
+      q.mode = SEL_PROJECT; q.theta = s.hi / nrm;
+    } else if (nrm < s.lo) {
+      if (nrm > 0.0) { q.mode = SEL_PROJECT; q.theta = s.lo / nrm; }
+      else q.mode = SEL_POINT;
+    }
+  }
+  return q;
+}
+
+// The first selection stage over the first digit's histogram, already in
+// LDS (hc, hs): totals, mode, non-finite keys, the first digit.  Every thread
+// calls this; st (LDS) holds the result.
+template <typename T>
+__device__ __forceinline__ void first_stage(SelState& st, const SetDesc& s, bool l1, const uint32_t* hc, const acc_t* hs,
+                            unsigned long long* lc, acc_t* ls, int* lbest, acc_t* lds) {
+  using KT = KeyT<T>;
+  acc_t tot[2] = {0, 0};
+  for (int b = threadIdx.x; b < kNB; b += kBlock) {
+    tot[0] += (acc_t)hc[b];
+    tot[1] += hs[b];
+  }
+  block_total_n<2, kBlock>(tot, lds);
+  if (threadIdx.x == 0) {
+    st.prefix = 0; st.c_above = 0; st.s_above = 0.0; st.ncand = 0; st.err = 0; st.need_ties = 0;
+    st.theta = 0.0; st.tkey = 0; st.tk = 0.0; st.keep_ties = 0; st.ties = 0; st.digit = 0;
+    const int infb = (int)(KT::inf_key >> digit_shift<T>(0));
+    unsigned long long nonfinite = 0;
+    for (int b = infb; b < kNB; ++b) nonfinite += hc[b];
+    if (nonfinite) st.err = SIP_ENUMERIC;
+    if (l1) {
+      if (!(s.tau > 0.0)) st.mode = SEL_ZERO;
+      else if (tot[1] <= (acc_t)s.tau) st.mode = SEL_INSIDE;
+      else st.mode = SEL_PROJECT;
+    } else {
+      st.mode = ((acc_t)s.k >= tot[0]) ? SEL_ALL : SEL_PROJECT;
+    }
+    st.final_ = 0;
+    st.compact_next = 0;
+  }
+  __syncthreads();
+  if (st.mode == SEL_PROJECT && !st.err) {
+    const unsigned long long cnt = select_digit<T>(st, hc, hs, kNB, 0, s, l1, lc, ls, lbest);
+    if (threadIdx.x == 0) {
+      st.digit = 1;
+      st.compact_next = cnt <= kCandCap ? 1 : 0;
+    }
+  }
+  __syncthreads();
+}
+
+// Stage 1 in its own launch (one block per pipeline): clears the first
+// digit's histogram once it is in LDS.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const SelItem* __restrict__ items, Opts o,
                                                  const double* __restrict__ thrw_parts) {
-  using KT = KeyT<T>;
   __shared__ uint32_t hc[kNB];
   __shared__ acc_t hs[kNB];
   __shared__ unsigned long long lc[kBlock];
@@ -2008,64 +2111,13 @@ __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D,
   const int k = (int)isc.k;
   if (si.src == 1 && !is_check_iter(k, o)) return;
   if (s.kind == SIP_SET_L2 || s.kind == SIP_SET_ANNULUS) {
-    // ||w||^2 (pipeline 0) from the w pass's per-item partials in item order;
-    // the projection is a scaling (or, for an annulus at w = 0, a point)
-    acc_t n2[1];
-    reduce_range<1>(thrw_parts, s.item_begin[si.src], s.item_end[si.src], kThrParts, si.src == 0 ? 6 : 7, n2, lds);
-    if (threadIdx.x == 0) {
-      SelState q{};
-      q.final_ = 1;
-      q.mode = SEL_INSIDE;
-      const double sq = (double)n2[0];
-      if (!(sq <= 1.0e300)) q.err = SIP_ENUMERIC;
-      const double nrm = sqrt(sq);
-      if (si.src == 0 && !q.err) {
-        if (s.kind == SIP_SET_L2) {
-          if (nrm > s.tau) { q.mode = SEL_PROJECT; q.theta = s.tau / nrm; }
-        } else if (nrm > s.hi) {
-          q.mode = SEL_PROJECT; q.theta = s.hi / nrm;
-        } else if (nrm < s.lo) {
-          if (nrm > 0.0) { q.mode = SEL_PROJECT; q.theta = s.lo / nrm; }
-          else q.mode = SEL_POINT;
-        }
-      }
-      *s.sel[si.src] = q;
-    }
+    const SelState q = l2_stage(s, si.src, thrw_parts, lds);
+    if (threadIdx.x == 0) *s.sel[si.src] = q;
     return;
   }
-  acc_t tot[2] = {0, 0};
   pull_finish(gc, gs, l1, kNB, cv, sv, hc, hs);
-  for (int b = threadIdx.x; b < kNB; b += kBlock) {
-    tot[0] += (acc_t)hc[b];
-    tot[1] += hs[b];
-  }
-  block_total_n<2, kBlock>(tot, lds);
-  if (threadIdx.x == 0) {
-    st.prefix = 0; st.c_above = 0; st.s_above = 0.0; st.ncand = 0; st.err = 0; st.need_ties = 0;
-    st.theta = 0.0; st.tkey = 0; st.tk = 0.0; st.keep_ties = 0; st.ties = 0; st.digit = 0;
-    const int infb = (int)(KT::inf_key >> digit_shift<T>(0));
-    unsigned long long nonfinite = 0;
-    for (int b = infb; b < kNB; ++b) nonfinite += hc[b];
-    if (nonfinite) st.err = SIP_ENUMERIC;
-    if (l1) {
-      if (!(s.tau > 0.0)) st.mode = SEL_ZERO;
-      else if (tot[1] <= (acc_t)s.tau) st.mode = SEL_INSIDE;
-      else st.mode = SEL_PROJECT;
-    } else {
-      st.mode = ((acc_t)s.k >= tot[0]) ? SEL_ALL : SEL_PROJECT;
-    }
-  }
   __syncthreads();
-  if (threadIdx.x == 0) { st.final_ = 0; st.compact_next = 0; }
-  __syncthreads();
-  if (st.mode == SEL_PROJECT && !st.err) {
-    const unsigned long long cnt = select_digit<T>(st, hc, hs, kNB, 0, s, l1, lc, ls, &lbest);
-    if (threadIdx.x == 0) {
-      st.digit = 1;
-      st.compact_next = cnt <= kCandCap ? 1 : 0;
-    }
-  }
-  __syncthreads();
+  first_stage<T>(st, s, l1, hc, hs, lc, ls, &lbest, lds);
   if (threadIdx.x == 0) *s.sel[si.src] = st;
 }
 
@@ -2096,8 +2148,9 @@ __device__ __forceinline__ bool pass_compacts(const SelState& st, int pass) {
 // whose higher digits match the resolved prefix; when the bucket is small
 // (or on the last pass of a long key) their keys go to the candidate list,
 // appended with one atomic per block round.
-template <typename T>
-__global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const ThrItem* __restrict__ items, Opts o, int pass) {
+template <typename T, bool FIRST>
+__global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const ThrItem* __restrict__ items, Opts o, int pass,
+                                                       const double* __restrict__ thrw_parts, uint32_t* h1c, double* h1s) {
   using KT = KeyT<T>;
   using K = typename KT::K;
   __shared__ uint32_t hc[kNB];
@@ -2110,15 +2163,41 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
   const InstDesc& d = D[it.inst];
   const double* S = d.scal;
   const SetDesc& s = d.sets[it.set];
+  const bool l1 = s.kind == SIP_SET_L1;
   const ItScal isc = it_scal(S);
-  const SelState st = load_sel(s.sel[it.src]);  // with the iteration scalars
+  SelState st = load_sel(s.sel[it.src]);  // with the iteration scalars
+  uint32_t cv[kPull];
+  acc_t sv[kPull];
+  if constexpr (FIRST) pull_issue(s.hcnt[it.src], (const acc_t*)s.hsum[it.src], l1, cv, sv);
   if (!isc.live()) return;
   const int k = (int)isc.k;
   if (it.src == 1 && !is_check_iter(k, o)) return;
+  if constexpr (FIRST) {
+    __shared__ unsigned long long lc[kBlock];
+    __shared__ acc_t ls[kBlock];
+    __shared__ int lbest;
+    __shared__ acc_t lds[lds_sum<2>()];
+    __shared__ SelState sst;
+    // the first selection stage, done by every block of the pipeline on its
+    // own (the same arithmetic, so the same state); its first block
+    // publishes the state (all but the candidate count, which other blocks
+    // may already be raising)
+    const bool lead = iti == s.item_begin[it.src];
+    if (s.kind == SIP_SET_L2 || s.kind == SIP_SET_ANNULUS) {
+      const SelState q = l2_stage(s, it.src, thrw_parts, lds);
+      if (lead && threadIdx.x == 0) *s.sel[it.src] = q;
+      return;
+    }
+    pull_store(kNB, cv, sv, hc, hs);
+    __syncthreads();
+    first_stage<T>(sst, s, l1, hc, hs, lc, ls, &lbest, lds);
+    if (lead && threadIdx.x == 0) store_sel_but_ncand(s.sel[it.src], sst);
+    st = sst;
+    __syncthreads();  // hc, hs are reused below
+  }
   if (st.mode != SEL_PROJECT || st.err || st.final_) return;
   const int dig = st.digit;
   const bool compact = pass_compacts<T>(st, pass);
-  const bool l1 = s.kind == SIP_SET_L1;
   const int nb = 1 << KT::width(dig);
   for (int b = threadIdx.x; b < nb; b += kSB) { hc[b] = 0; hs[b] = 0; }
   __syncthreads();
@@ -2239,8 +2318,10 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
     }
   }
   __syncthreads();
-  uint32_t* gc = s.hcnt[it.src];
-  acc_t* gs = (acc_t*)s.hsum[it.src];
+  // the refine histogram: the first digit's buffer, cleared by the first
+  // selection stage, unless every block is still reading that
+  uint32_t* gc = FIRST ? h1c + (size_t)it.pipe * kNB : s.hcnt[it.src];
+  acc_t* gs = (acc_t*)(FIRST ? h1s + (size_t)it.pipe * kNB : s.hsum[it.src]);
   for (int b = threadIdx.x; b < nb; b += kSB) {
     if (hc[b]) {
       atomicAdd(&gc[b], hc[b]);
@@ -2257,7 +2338,7 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
 // bookkeeping (cardinality) once final.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const SelItem* __restrict__ items, Opts o, int pass,
-                                                     uint32_t* tie_part) {
+                                                     uint32_t* tie_part, int clear0, uint32_t* h1c, double* h1s) {
   using KT = KeyT<T>;
   using K = typename KT::K;
   __shared__ uint32_t hc[kNB];
@@ -2276,14 +2357,25 @@ __global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict_
   const ItScal isc = it_scal(S);
   const SelState st0 = load_sel(s.sel[si.src]);
   const bool l1 = s.kind == SIP_SET_L1;
-  uint32_t* gc = s.hcnt[si.src];
-  acc_t* gs = (acc_t*)s.hsum[si.src];
+  // the refine histogram: the pipeline's own in the batch table when the
+  // first selection stage ran inside the refine pass
+  uint32_t* gc = clear0 ? h1c + (size_t)blockIdx.x * kNB : s.hcnt[si.src];
+  acc_t* gs = (acc_t*)(clear0 ? h1s + (size_t)blockIdx.x * kNB : s.hsum[si.src]);
   uint32_t cv[kPull];
   acc_t sv[kPull];
   pull_issue(gc, gs, l1, cv, sv);
   if (!isc.live()) return;
   const int k = (int)isc.k;
   if (si.src == 1 && !is_check_iter(k, o)) return;
+  if (clear0) {
+    // the first digit's histogram, read by every block of the refine pass
+    uint32_t* g0 = s.hcnt[si.src];
+    acc_t* s0 = (acc_t*)s.hsum[si.src];
+    for (int b = threadIdx.x; b < kNB; b += kBlock) {
+      g0[b] = 0u;
+      if (l1) s0[b] = (acc_t)0;
+    }
+  }
   if (st0.mode != SEL_PROJECT || st0.err || st0.final_) return;
   if (threadIdx.x == 0) st = st0;  // first read after select_digit's barriers
   const bool compacted = pass_compacts<T>(st0, pass);
@@ -2360,7 +2452,10 @@ __global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict_
       }
     }
   }
-  if (threadIdx.x == 0) *s.sel[si.src] = st;
+  if (threadIdx.x == 0) {
+    st.ncand = 0;  // the candidates are used up; the next refine pass appends from 0
+    *s.sel[si.src] = st;
+  }
 }
 
 // Apply pass.  Pipeline 0: y = soft threshold of w (l1) or w on the kept
@@ -3263,14 +3358,20 @@ void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
     if (t.nthr > 0) k_thr_w<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thrw_part);
   }
   if (t.nthr > 0) {
-    k_sel1<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, t.thrw_part);
-    if (t.sel_passes == 2) {
-      k_thr_refine<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, 0);
-      k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 0, t.tie_part);
+    if (t.sel_fused) {
+      // one refine pass that also does the first selection stage
+      k_thr_refine<T, true><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, 1, t.thrw_part, t.h1c, t.h1s);
+      k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 1, t.tie_part, 1, t.h1c, t.h1s);
+    } else {
+      k_sel1<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, t.thrw_part);
+      if (t.sel_passes == 2) {
+        k_thr_refine<T, false><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, 0, t.thrw_part, t.h1c, t.h1s);
+        k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 0, t.tie_part, 0, t.h1c, t.h1s);
+      }
+      // the last pass always appends candidates, so its select stage is final
+      k_thr_refine<T, false><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, 1, t.thrw_part, t.h1c, t.h1s);
+      k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 1, t.tie_part, 0, t.h1c, t.h1s);
     }
-    // the last pass always appends candidates, so its select stage is final
-    k_thr_refine<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, 1);
-    k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 1, t.tie_part);
     k_thr_apply<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thra_part, t.tie_part);
   }
   if (t.nline > 0)
