@@ -316,10 +316,10 @@ struct sip_batch {
   sip::PtItem* d_sp = nullptr; int cap_sp = 0;
   sip::LineItem* d_line = nullptr; int cap_line = 0;
   double* d_linep = nullptr; int cap_plinep = 0;
-  sip::Counts* d_counts = nullptr;
   sip::Tables tab{};
   int live_items = 0, live_inst = 0;
   bool dirty = true;
+  int32_t live[4] = {0, 0, 0, 0};  // point, threshold, selection, instance items of the tables
   std::map<int, hipGraphExec_t> graphs;
   sip::TileCfg tiles;
 };
@@ -488,10 +488,10 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
     b->cap_pthr = b->cap_thr;
     moved = true;
   }
-  if (!b->d_counts) HIP_OK(hipMalloc((void**)&b->d_counts, sizeof(Counts)));
-  const Counts counts{(int32_t)pt.size(), (int32_t)thr.size(), (int32_t)sel.size(), (int32_t)inst.size(),
-                      (int32_t)sp.size(), (int32_t)line.size(), {0, 0}};
-  HIP_OK(hipMemcpyAsync(b->d_counts, &counts, sizeof(Counts), hipMemcpyHostToDevice, stream));
+  b->live[0] = (int32_t)pt.size();
+  b->live[1] = (int32_t)thr.size();
+  b->live[2] = (int32_t)sel.size();
+  b->live[3] = (int32_t)inst.size();
   // every table is written up to its launch size (entries past the live
   // items are sentinels), in launch order
   const std::vector<PtItem> pt_l = launch_order(pt, lpt, true), sp_l = launch_order(sp, lsp, true);
@@ -522,7 +522,6 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   Tables& t = b->tab;
   bool relaunch_cap = false;
   t.D = b->d_desc;
-  t.cnt = b->d_counts;
   t.pt = b->d_pt; t.npt = lpt;
   t.sp = b->d_sp; t.nsp = lsp;
   t.thr = b->d_thr; t.nthr = lthr;
@@ -704,7 +703,7 @@ int32_t sip_batch_destroy(sip_batch* b) {
   drop_graphs(b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   void* dev[] = {b->d_desc, b->d_scal, b->d_pt, b->d_thr, b->d_sel, b->d_inst, b->d_rr, b->d_pq,
-                 b->d_rr2, b->d_pq2, b->d_proj, b->d_thrw, b->d_thra, b->d_tie, b->d_counts, b->d_sp,
+                 b->d_rr2, b->d_pq2, b->d_proj, b->d_thrw, b->d_thra, b->d_tie, b->d_sp,
                  b->d_line, b->d_linep, b->d_h1c, b->d_h1s};
   for (void* p : dev) if (p) (void)hipFree(p);
   if (b->h_scal) (void)hipHostFree(b->h_scal);
@@ -1054,12 +1053,10 @@ int32_t sip_batch_set_tiles(sip_batch* b, int32_t pt_points, int32_t pt_max_item
 
 int32_t sip_batch_items(sip_batch* b, int32_t* npt, int32_t* nthr, int32_t* nsel, int32_t* ninst) {
   if (!b) return SIP_EINVAL;
-  int32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (b->d_counts && hipMemcpy(c, b->d_counts, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess) return SIP_EHIP;
-  if (npt) *npt = c[0];
-  if (nthr) *nthr = c[1];
-  if (nsel) *nsel = c[2];
-  if (ninst) *ninst = c[3];
+  if (npt) *npt = b->live[0];
+  if (nthr) *nthr = b->live[1];
+  if (nsel) *nsel = b->live[2];
+  if (ninst) *ninst = b->live[3];
   return SIP_OK;
 }
 

@@ -140,11 +140,6 @@ struct Opts {                     // options every kernel needs, by value
   double cg_rel2, eps_corr, rho_ratio_max, gamma_max, eps_evol, eps_feas;
 };
 
-// Live item counts of the work tables, read by the kernels from device
-// memory so a captured graph (launched over the table capacities) stays valid
-// when instances are admitted or retired.
-struct Counts { int32_t npt, nthr, nsel, ninst, nsp, nline, pad_[2]; };
-
 // One line of one component of a line-wise set: points start + t * stride,
 // t = 0 .. len-1 (grid indexing of the component's block).
 struct LineItem {
@@ -157,10 +152,10 @@ struct LineItem {
 template <typename T> struct LineCap { static constexpr int v = sizeof(T) == 4 ? 4096 : 2048; };
 
 // Device work tables and partial-sum buffers of one batch.  npt, nthr, nsel
-// and ninst are the launch sizes (capacities); cnt holds the live counts.
+// and ninst are the launch sizes (capacities); entries past the live items
+// are sentinels (inst < 0).
 struct Tables {
   const InstDesc* D;
-  const Counts* cnt;
   const PtItem* pt; int npt;
   const PtItem* sp; int nsp;
   const ThrItem* thr; int nthr;

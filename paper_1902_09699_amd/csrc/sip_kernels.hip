@@ -891,7 +891,7 @@ __device__ __forceinline__ acc_t cg_dir_item(const InstDesc& d, const PtItem& it
 }
 
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_cg_dir(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const PtItem* __restrict__ items, int j,
+__global__ __launch_bounds__(NT) void k_cg_dir(const InstDesc* __restrict__ D, const PtItem* __restrict__ items, int j,
                                                 const double* rr_part, double* pq_part, Opts o) {
   __shared__ acc_t lds[lds_sum<1, NT>()];
   const PtItem it = items[blockIdx.x];
@@ -942,7 +942,7 @@ __global__ __launch_bounds__(NT) void k_cg_dir(const InstDesc* __restrict__ D, c
 // Step j, second half: alpha = rr_j / p^T C p; x += alpha p; r -= alpha C p
 // (C p recomputed from p); partial r^T r.
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_cg_upd(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const PtItem* __restrict__ items, int j,
+__global__ __launch_bounds__(NT) void k_cg_upd(const InstDesc* __restrict__ D, const PtItem* __restrict__ items, int j,
                                                 const double* pq_part, double* rr_part) {
   constexpr int W = Grp<T>::W;
   __shared__ acc_t lds[lds_sum<1, NT>()];
@@ -1035,8 +1035,7 @@ __global__ __launch_bounds__(NT) void k_cg_upd(const InstDesc* __restrict__ D, c
 
 // w_0 = C r_0 and the partials of delta_0 = r_0^T w_0 (r_0 from the RHS kernel).
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_cg1_w0(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt,
-                                                const PtItem* __restrict__ items, double* dpart) {
+__global__ __launch_bounds__(NT) void k_cg1_w0(const InstDesc* __restrict__ D, const PtItem* __restrict__ items, double* dpart) {
   constexpr int W = Grp<T>::W;
   __shared__ acc_t lds[lds_sum<1, NT>()];
   const PtItem it = items[blockIdx.x];
@@ -1088,8 +1087,7 @@ __global__ __launch_bounds__(NT) void k_cg1_w0(const InstDesc* __restrict__ D, c
 
 // Step j (NA = 2 at j = 0, where p_0 = r_0 and s_0 = w_0; NA = 3 after).
 template <typename T, int NT, int NA>
-__global__ __launch_bounds__(NT) void k_cg1_step(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt,
-                                                  const PtItem* __restrict__ items, int j, const double* gin,
+__global__ __launch_bounds__(NT) void k_cg1_step(const InstDesc* __restrict__ D, const PtItem* __restrict__ items, int j, const double* gin,
                                                   const double* din, double* gout, double* dout, Opts o) {
   constexpr int W = Grp<T>::W;
   __shared__ acc_t lds_g[2 * (NT / 64)];
@@ -1232,7 +1230,7 @@ __global__ __launch_bounds__(NT) void k_cg1_step(const InstDesc* __restrict__ D,
 // A_i^T of a forward difference needs u = rho y + v one point back along the
 // axis: the previous lane's last value for x, a window for y / z.
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_rhs(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const PtItem* __restrict__ items, double* rr_part) {
+__global__ __launch_bounds__(NT) void k_rhs(const InstDesc* __restrict__ D, const PtItem* __restrict__ items, double* rr_part) {
   constexpr int W = Grp<T>::W;
   __shared__ acc_t lds[lds_sum<1, NT>()];
   const PtItem it = items[blockIdx.x];
@@ -1399,8 +1397,7 @@ __device__ __forceinline__ void proj_point(const ProjUnit<T>& U, T sv, T yo, T v
 
 // One block of the projection pass: item bx, unit by.
 template <typename T>
-__device__ void proj_block(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt,
-                           const PtItem* __restrict__ items, const Opts& o, double* parts, int bx, int by) {
+__device__ void proj_block(const InstDesc* __restrict__ D, const PtItem* __restrict__ items, const Opts& o, double* parts, int bx, int by) {
   constexpr int W = Grp<T>::W;
   __shared__ acc_t lds[lds_sum<16, kSB>()];
   const PtItem it = items[bx];
@@ -1642,9 +1639,8 @@ __device__ void proj_block(const InstDesc* __restrict__ D, const Counts* __restr
 }
 
 template <typename T>
-__global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt,
-                                              const PtItem* __restrict__ items, Opts o, double* parts) {
-  proj_block<T>(D, cnt, items, o, parts, (int)blockIdx.x, (int)blockIdx.y);
+__global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, const PtItem* __restrict__ items, Opts o, double* parts) {
+  proj_block<T>(D, items, o, parts, (int)blockIdx.x, (int)blockIdx.y);
 }
 
 // --------------------------------------------- threshold sets: pass 1 (w)
@@ -1655,8 +1651,7 @@ __global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, co
 // Pipeline 1 (stopping-test iterations): histogram of |s| and ||s||^2.
 // One block of the w pass: item bx.
 template <typename T>
-__device__ void thrw_block(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt,
-                           const ThrItem* __restrict__ items, const Opts& o, double* parts, int bx) {
+__device__ void thrw_block(const InstDesc* __restrict__ D, const ThrItem* __restrict__ items, const Opts& o, double* parts, int bx) {
   using KT = KeyT<T>;
   __shared__ uint32_t hc[kNB];
   __shared__ acc_t hs[kNB];
@@ -1839,9 +1834,8 @@ __device__ void thrw_block(const InstDesc* __restrict__ D, const Counts* __restr
 }
 
 template <typename T>
-__global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt,
-                                               const ThrItem* __restrict__ items, Opts o, double* parts) {
-  thrw_block<T>(D, cnt, items, o, parts, (int)blockIdx.x);
+__global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, const ThrItem* __restrict__ items, Opts o, double* parts) {
+  thrw_block<T>(D, items, o, parts, (int)blockIdx.x);
 }
 
 // The projection pass and the threshold sets' w pass in one launch: both read
@@ -1849,12 +1843,11 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, c
 // blocks (the longer ones) come first, so they are dispatched in the first
 // wave of resident blocks and the projection blocks fill in behind them.
 template <typename T>
-__global__ __launch_bounds__(kSB) void k_sets(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt,
-                                              const PtItem* __restrict__ sp, const ThrItem* __restrict__ thr, Opts o,
+__global__ __launch_bounds__(kSB) void k_sets(const InstDesc* __restrict__ D, const PtItem* __restrict__ sp, const ThrItem* __restrict__ thr, Opts o,
                                               double* proj_parts, double* thrw_parts, int nsp, int units, int nthr) {
   const int b = (int)blockIdx.x;
-  if (b < nthr) thrw_block<T>(D, cnt, thr, o, thrw_parts, b);
-  else proj_block<T>(D, cnt, sp, o, proj_parts, (b - nthr) % nsp, (b - nthr) / nsp);
+  if (b < nthr) thrw_block<T>(D, thr, o, thrw_parts, b);
+  else proj_block<T>(D, sp, o, proj_parts, (b - nthr) % nsp, (b - nthr) / nsp);
 }
 
 // ---------------------------------------------- selection (one block each)
@@ -2084,7 +2077,7 @@ __device__ __forceinline__ void first_stage(SelState& st, const SetDesc& s, bool
 // Stage 1 in its own launch (one block per pipeline): clears the first
 // digit's histogram once it is in LDS.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const SelItem* __restrict__ items, Opts o,
+__global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D, const SelItem* __restrict__ items, Opts o,
                                                  const double* __restrict__ thrw_parts) {
   __shared__ uint32_t hc[kNB];
   __shared__ acc_t hs[kNB];
@@ -2149,7 +2142,7 @@ __device__ __forceinline__ bool pass_compacts(const SelState& st, int pass) {
 // (or on the last pass of a long key) their keys go to the candidate list,
 // appended with one atomic per block round.
 template <typename T, bool FIRST>
-__global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const ThrItem* __restrict__ items, Opts o, int pass,
+__global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__ D, const ThrItem* __restrict__ items, Opts o, int pass,
                                                        const double* __restrict__ thrw_parts, uint32_t* h1c, double* h1s) {
   using KT = KeyT<T>;
   using K = typename KT::K;
@@ -2337,7 +2330,7 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
 // appends candidates.  Ends with theta (l1) or the k-th magnitude and the tie
 // bookkeeping (cardinality) once final.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const SelItem* __restrict__ items, Opts o, int pass,
+__global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict__ D, const SelItem* __restrict__ items, Opts o, int pass,
                                                      uint32_t* tie_part, int clear0, uint32_t* h1c, double* h1s) {
   using KT = KeyT<T>;
   using K = typename KT::K;
@@ -2463,7 +2456,7 @@ __global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict_
 // adapt dots of the (dg, dv) pair and the new y/v snapshots.  Pipeline 1:
 // the feasibility distance ||s - P(s)||^2.
 template <typename T>
-__global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const ThrItem* __restrict__ items, Opts o, double* parts,
+__global__ __launch_bounds__(kSB) void k_thr_apply(const InstDesc* __restrict__ D, const ThrItem* __restrict__ items, Opts o, double* parts,
                                                       const uint32_t* tie_part) {
   using KT = KeyT<T>;
   using K = typename KT::K;
@@ -2953,8 +2946,7 @@ template <typename T>
 constexpr size_t line_lds_per_entry() { return sizeof(T) + sizeof(typename KeyT<T>::K) + 4; }
 
 template <typename T>
-__global__ __launch_bounds__(kLB) void k_line(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt,
-                                              const LineItem* __restrict__ items, Opts o, double* parts, int cap) {
+__global__ __launch_bounds__(kLB) void k_line(const InstDesc* __restrict__ D, const LineItem* __restrict__ items, Opts o, double* parts, int cap) {
   using KT = KeyT<T>;
   extern __shared__ __align__(16) unsigned char line_smem[];
   typename KT::K* lk = (typename KT::K*)line_smem;
@@ -3069,7 +3061,7 @@ __device__ bool spectral(double ab, double aa, double bb, double eps, double& es
 constexpr int kFB = 512;
 
 template <typename T>
-__global__ __launch_bounds__(kFB) void k_finish(const InstDesc* __restrict__ D, const Counts* __restrict__ cnt, const int32_t* __restrict__ insts, Opts o,
+__global__ __launch_bounds__(kFB) void k_finish(const InstDesc* __restrict__ D, const int32_t* __restrict__ insts, Opts o,
                                                    const double* proj_parts, const double* thrw_parts,
                                                    const double* thra_parts, const double* line_parts) {
   __shared__ acc_t tout[4 * kMaxUnits + 2][8];
@@ -3312,35 +3304,35 @@ void launch_init(hipStream_t st, const InstDesc* __restrict__ D, int inst, int64
 // RHS and the CG steps with NT threads per block.
 template <typename T, int NT>
 void launch_cg(hipStream_t st, const Tables& t, const Opts& o) {
-  k_rhs<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, t.rr_part);
+  k_rhs<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.pt, t.rr_part);
   if (t.cg_form == 1) {
-    k_cg1_w0<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, t.pq_part);
+    k_cg1_w0<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.pt, t.pq_part);
     for (int j = 0; j < o.cg_max; ++j) {
       double* g[2] = {t.rr_part, t.rr2_part};
       double* dd[2] = {t.pq_part, t.pq2_part};
       if (j == 0)
-        k_cg1_step<T, NT, 2><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, j, g[0], dd[0], g[1], dd[1], o);
+        k_cg1_step<T, NT, 2><<<t.npt, NT, 0, st>>>(t.D, t.pt, j, g[0], dd[0], g[1], dd[1], o);
       else
-        k_cg1_step<T, NT, 3><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, j, g[j & 1], dd[j & 1], g[(j + 1) & 1],
+        k_cg1_step<T, NT, 3><<<t.npt, NT, 0, st>>>(t.D, t.pt, j, g[j & 1], dd[j & 1], g[(j + 1) & 1],
                                                     dd[(j + 1) & 1], o);
     }
     return;
   }
   for (int j = 0; j < o.cg_max; ++j) {
-    k_cg_dir<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, j, t.rr_part, t.pq_part, o);
-    k_cg_upd<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, j, t.pq_part, t.rr_part);
+    k_cg_dir<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.pt, j, t.rr_part, t.pq_part, o);
+    k_cg_upd<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.pt, j, t.pq_part, t.rr_part);
   }
 }
 
 template <typename T, int NT>
 void launch_point_phase(hipStream_t st, const Tables& t, const Opts& o, int phase) {
   if (!t.npt) return;
-  if (phase == 0) k_rhs<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, t.rr_part);
-  if (phase == 1) k_cg_dir<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, 1, t.rr_part, t.pq_part, o);
-  if (phase == 2) k_cg_upd<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, 1, t.pq_part, t.rr_part);
+  if (phase == 0) k_rhs<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.pt, t.rr_part);
+  if (phase == 1) k_cg_dir<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.pt, 1, t.rr_part, t.pq_part, o);
+  if (phase == 2) k_cg_upd<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.pt, 1, t.pq_part, t.rr_part);
   if (phase == 6)
-    k_cg1_step<T, NT, 3><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, 1, t.rr2_part, t.pq2_part, t.rr_part, t.pq_part, o);
-  if (phase == 7) k_cg1_w0<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.cnt, t.pt, t.pq_part);
+    k_cg1_step<T, NT, 3><<<t.npt, NT, 0, st>>>(t.D, t.pt, 1, t.rr2_part, t.pq2_part, t.rr_part, t.pq_part, o);
+  if (phase == 7) k_cg1_w0<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.pt, t.pq_part);
 }
 
 template <typename T>
@@ -3351,34 +3343,34 @@ void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
   }
   const bool proj = t.npt > 0 && t.nsp > 0;
   if (proj && t.nthr > 0 && t.fuse_sets) {
-    k_sets<T><<<t.nsp * t.proj_units + t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.sp, t.thr, o, t.proj_part, t.thrw_part,
+    k_sets<T><<<t.nsp * t.proj_units + t.nthr, kSB, 0, st>>>(t.D, t.sp, t.thr, o, t.proj_part, t.thrw_part,
                                                               t.nsp, t.proj_units, t.nthr);
   } else {
-    if (proj) k_proj<T><<<dim3(t.nsp, t.proj_units), kSB, 0, st>>>(t.D, t.cnt, t.sp, o, t.proj_part);
-    if (t.nthr > 0) k_thr_w<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thrw_part);
+    if (proj) k_proj<T><<<dim3(t.nsp, t.proj_units), kSB, 0, st>>>(t.D, t.sp, o, t.proj_part);
+    if (t.nthr > 0) k_thr_w<T><<<t.nthr, kSB, 0, st>>>(t.D, t.thr, o, t.thrw_part);
   }
   if (t.nthr > 0) {
     if (t.sel_fused) {
       // one refine pass that also does the first selection stage
-      k_thr_refine<T, true><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, 1, t.thrw_part, t.h1c, t.h1s);
-      k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 1, t.tie_part, 1, t.h1c, t.h1s);
+      k_thr_refine<T, true><<<t.nthr, kSB, 0, st>>>(t.D, t.thr, o, 1, t.thrw_part, t.h1c, t.h1s);
+      k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.sel, o, 1, t.tie_part, 1, t.h1c, t.h1s);
     } else {
-      k_sel1<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, t.thrw_part);
+      k_sel1<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.sel, o, t.thrw_part);
       if (t.sel_passes == 2) {
-        k_thr_refine<T, false><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, 0, t.thrw_part, t.h1c, t.h1s);
-        k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 0, t.tie_part, 0, t.h1c, t.h1s);
+        k_thr_refine<T, false><<<t.nthr, kSB, 0, st>>>(t.D, t.thr, o, 0, t.thrw_part, t.h1c, t.h1s);
+        k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.sel, o, 0, t.tie_part, 0, t.h1c, t.h1s);
       }
       // the last pass always appends candidates, so its select stage is final
-      k_thr_refine<T, false><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, 1, t.thrw_part, t.h1c, t.h1s);
-      k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.cnt, t.sel, o, 1, t.tie_part, 0, t.h1c, t.h1s);
+      k_thr_refine<T, false><<<t.nthr, kSB, 0, st>>>(t.D, t.thr, o, 1, t.thrw_part, t.h1c, t.h1s);
+      k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.sel, o, 1, t.tie_part, 0, t.h1c, t.h1s);
     }
-    k_thr_apply<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thra_part, t.tie_part);
+    k_thr_apply<T><<<t.nthr, kSB, 0, st>>>(t.D, t.thr, o, t.thra_part, t.tie_part);
   }
   if (t.nline > 0)
-    k_line<T><<<t.nline, kLB, t.line_cap * line_lds_per_entry<T>(), st>>>(t.D, t.cnt, t.line, o, t.line_part,
+    k_line<T><<<t.nline, kLB, t.line_cap * line_lds_per_entry<T>(), st>>>(t.D, t.line, o, t.line_part,
                                                                          t.line_cap);
   if (t.ninst > 0)
-    k_finish<T><<<t.ninst, kFB, 0, st>>>(t.D, t.cnt, t.inst, o, t.proj_part, t.thrw_part, t.thra_part,
+    k_finish<T><<<t.ninst, kFB, 0, st>>>(t.D, t.inst, o, t.proj_part, t.thrw_part, t.thra_part,
                                             t.line_part);
 }
 
@@ -3396,12 +3388,12 @@ void launch_phase(hipStream_t st, const Tables& t, const Opts& o, int phase) {
       if (t.pt_threads == 256) launch_point_phase<T, 256>(st, t, o, phase);
       else launch_point_phase<T, 512>(st, t, o, phase);
       break;
-    case 3: if (t.nsp) k_proj<T><<<dim3(t.nsp, t.proj_units), kSB, 0, st>>>(t.D, t.cnt, t.sp, o, t.proj_part); break;
-    case 4: if (t.nthr) k_thr_w<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thrw_part); break;
-    case 5: if (t.nthr) k_thr_apply<T><<<t.nthr, kSB, 0, st>>>(t.D, t.cnt, t.thr, o, t.thra_part, t.tie_part); break;
+    case 3: if (t.nsp) k_proj<T><<<dim3(t.nsp, t.proj_units), kSB, 0, st>>>(t.D, t.sp, o, t.proj_part); break;
+    case 4: if (t.nthr) k_thr_w<T><<<t.nthr, kSB, 0, st>>>(t.D, t.thr, o, t.thrw_part); break;
+    case 5: if (t.nthr) k_thr_apply<T><<<t.nthr, kSB, 0, st>>>(t.D, t.thr, o, t.thra_part, t.tie_part); break;
     case 8:
       if (t.nline)
-        k_line<T><<<t.nline, kLB, t.line_cap * line_lds_per_entry<T>(), st>>>(t.D, t.cnt, t.line, o, t.line_part,
+        k_line<T><<<t.nline, kLB, t.line_cap * line_lds_per_entry<T>(), st>>>(t.D, t.line, o, t.line_part,
                                                                              t.line_cap);
       break;
     default: break;
