@@ -23,7 +23,7 @@ CANDIDATES = [
     (2048, 1024, 4096, 512, 256, 0),
     (4096, 512, 4096, 256, 256, 0),
     (1024, 2048, 2048, 512, 256, 0),
-    # large grids: threshold items of one full block round (4096 float points)
+    # large grids: threshold items of four full block rounds (4096 float points)
     (1024, 512, 2048, 1024, 512, 0),
     (2048, 512, 2048, 1024, 512, 0),
     # one launch per CG step: fewer, heavier launches
