@@ -15,7 +15,8 @@ pytestmark = pytest.mark.gpu
 
 TILES = {"default": (2048, 512, 2048, 512, 512), "tuned": (1024, 256, 2048, 256, 512),
          "small_blocks": (2048, 1024, 4096, 512, 256), "one_reduction": (1024, 512, 2048, 512, 512, 1),
-         "one_reduction_256": (1024, 1024, 2048, 512, 256, 1)}
+         "one_reduction_256": (1024, 1024, 2048, 512, 256, 1),
+         "thr_items_1024": (2048, 512, 2048, 1024, 512)}
 
 
 def _load(name):
@@ -30,7 +31,7 @@ def _load(name):
 @pytest.mark.parametrize("name,tiles", [("layered2d", "default"), ("layered2d", "tuned"), ("layered2d", "small_blocks"),
                                         ("layered2d", "one_reduction"), ("layered2d", "one_reduction_256"),
                                         ("smooth3d", "tuned"), ("smooth3d", "small_blocks"),
-                                        ("smooth3d", "one_reduction")])
+                                        ("smooth3d", "one_reduction"), ("smooth3d", "thr_items_1024")])
 def test_fullsize_lockstep(name, tiles):
     m, sets, field, iters = _load(name)
     print(f"\n[fullsize] {name} {m.shape} tiles={TILES[tiles]}", flush=True)
