@@ -428,7 +428,7 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   // nothing queued may still read the tables or partial buffers replaced below
   HIP_OK(hipStreamSynchronize(stream));
   // launch sizes are capacities (powers of two): a captured graph stays valid
-  // while the live counts (read by the kernels) change below them
+  // while the live items change below them (the rest of a table is sentinels)
   auto pow2 = [](int n, int lo) { if (n <= 0) return 0; int c = lo; while (c < n) c <<= 1; return c; };
   const int lpt = pow2((int)pt.size(), 64), lthr = pow2((int)thr.size(), 64);
   const int lsel = pow2((int)sel.size(), 8), linst = pow2((int)inst.size(), 8);
