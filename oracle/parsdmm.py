@@ -121,20 +121,6 @@ def project_l1(w, tau):
     return np.sign(w) * np.maximum(a - theta, 0.0)
 
 
-def l1_threshold(w, tau):
-    """The theta used by project_l1 (0 when w is already inside)."""
-    a = np.abs(np.asarray(w, dtype=np.float64))
-    if tau <= 0.0:
-        return float(a.max()) if a.size else 0.0
-    if a.sum() <= tau:
-        return 0.0
-    u = np.sort(a)[::-1]
-    c = np.cumsum(u)
-    j = np.arange(1, u.size + 1)
-    rho = int(np.nonzero(u - (c - tau) / j > 0)[0][-1]) + 1
-    return float((c[rho - 1] - tau) / rho)
-
-
 def card_support(w, k):
     """Indices kept by the cardinality projection card(y) <= k: the k entries
     of largest |w|, ties broken toward the lower linear index (stable sort)."""

@@ -100,3 +100,39 @@ def test_multilevel_reaches_the_projection():
                                                    (-Dx, np.full(Dx.shape[0], 0.2))], bounds=(1.5, 4.5))
     assert np.linalg.norm(x.ravel() - ref) <= 1e-5 * np.linalg.norm(ref)
     assert states[1].x.shape == (4 * 4,)
+
+
+@pytest.mark.parametrize("kind", ["l2", "annulus"])
+@pytest.mark.parametrize("op,shape", [("I", (9, 13)), ("DX", (9, 13)), ("DZ", (11, 7)), ("DX", (5, 6, 9)),
+                                      ("DY", (5, 7, 6))])
+def test_l2_radius_transfer_matches_sampled_norms(kind, op, shape):
+    """The l2 radius carried to a coarser level is the radius the coarse
+    samples of a field sit at.  A field that is linear along the operator's
+    axis (constant for the identity) has the same value in every row of A
+    on every level (the spacing doubles with the sample distance), so
+    ||A_l m_l||_2 = sqrt(rows_l / rows) ||A m||_2 exactly.  A field lying on
+    the fine sphere must therefore lie on the transferred coarse sphere; a
+    transfer by the row ratio itself (or not at all) misses it."""
+    nd = len(shape)
+    h = (1.0,) * nd
+    ax = {"I": None, "DZ": 0, "DY": 1, "DX": nd - 1}[op]
+    grids = np.meshgrid(*[np.arange(float(n)) for n in shape], indexing="ij")
+    m = np.full(shape, 1.7) if ax is None else 0.35 * grids[ax] + 2.0
+    shape_c = ml.coarse_shape(shape)
+    m_c = m[tuple(slice(0, None, 2) for _ in shape)]
+    assert m_c.shape == shape_c
+    fine = np.linalg.norm(orc.operator(op, shape, h) @ m.ravel())
+    coarse = np.linalg.norm(orc.operator(op, shape_c, tuple(2.0 * v for v in h)) @ m_c.ravel())
+    ratio = ml.rows(shape_c, op) / ml.rows(shape, op)
+    assert abs(coarse - np.sqrt(ratio) * fine) <= 1e-12 * fine
+    # the alternatives a slip would produce differ measurably here
+    assert abs(coarse - ratio * fine) > 1e-3 * fine and abs(coarse - fine) > 1e-3 * fine
+    if kind == "l2":
+        s = {"kind": "l2", "op": op, "tau": fine}
+        got = ml.level_sets([s], shape, shape_c)[0]
+        assert abs(got["tau"] - coarse) <= 1e-12 * coarse
+    else:
+        s = {"kind": "annulus", "op": op, "lo": 0.5 * fine, "hi": fine}
+        got = ml.level_sets([s], shape, shape_c)[0]
+        assert abs(got["hi"] - coarse) <= 1e-12 * coarse
+        assert abs(got["lo"] - 0.5 * coarse) <= 1e-12 * coarse
