@@ -313,9 +313,19 @@ class Problem:
             return project_lines(self.sets[i], w, self.lines[i])
         return project_set(self.sets[i], w)
 
-    def prox(self, i, w, rho_i):
+    def prox(self, i, w, rho_i, keep=None):
+        """prox_i(w); ``keep`` (cardinality sets only) replaces the set's own
+        choice of the k kept rows by the given row indices (support-locked
+        replay of another run: the projection is then y = w on those rows and
+        0 elsewhere)."""
         if i == self.p:
             return prox_sq_dist(w, self.m, rho_i)
+        if keep is not None:
+            if self.sets[i]["kind"] != "card" or self.lines[i] is not None:
+                raise ValueError("a kept support is replayed only for whole-vector cardinality sets")
+            y = np.zeros_like(w)
+            y[keep] = w[keep]
+            return y
         return self.project(i, w)
 
 
@@ -473,7 +483,7 @@ def x_update(prob: Problem, st: State, opts: Options) -> int:
     return steps
 
 
-def set_updates(prob: Problem, st: State):
+def set_updates(prob: Problem, st: State, keep=None):
     """For i = 1..p+1: s_i = A_i x, x-bar_i = gamma_i s_i + (1 - gamma_i) y_i,
     y_i = prox_i(x-bar_i - v_i/rho_i), v_i += rho_i (y_i - x-bar_i).
     Returns the s_i and the pre-update y_i and v_i (adapt-rho-gamma needs them)."""
@@ -486,7 +496,7 @@ def set_updates(prob: Problem, st: State):
         st.w_last.append(w)
         y_old.append(st.y[i])
         v_old.append(st.v[i])
-        st.y[i] = prob.prox(i, w, st.rho[i])
+        st.y[i] = prob.prox(i, w, st.rho[i], None if keep is None else keep.get(i))
         st.v[i] = st.v[i] + st.rho[i] * (st.y[i] - xbar)
         s_all.append(s)
     return s_all, y_old, v_old
@@ -509,15 +519,20 @@ def adapt(prob: Problem, st: State, s_all, y_old, v_old, opts: Options):
     st.rho, st.gamma = guard_parameters(rho, gamma, opts)
 
 
-def iterate(prob: Problem, st: State, opts: Options, schedule=None) -> bool:
+def iterate(prob: Problem, st: State, opts: Options, schedule=None, supports=None) -> bool:
     """One PARSDMM iteration.  ``schedule`` (optional) maps k to (rho, gamma)
     to use in iteration k instead of the adapted values (schedule-locked
-    replay of another run).  Returns True when the stopping test passed."""
+    replay of another run); ``supports`` (optional) maps k to {set index:
+    kept row indices} for cardinality sets (support-locked replay: a
+    non-convex set has several equally valid projections where entries tie
+    or nearly tie at the k-th magnitude, so a replay may take the other run's
+    choice; the caller checks that choice against the oracle's own w).
+    Returns True when the stopping test passed."""
     if schedule is not None and st.k in schedule:
         st.rho = np.array(schedule[st.k][0], dtype=np.float64)
         st.gamma = np.array(schedule[st.k][1], dtype=np.float64)
     x_update(prob, st, opts)
-    s_all, y_old, v_old = set_updates(prob, st)
+    s_all, y_old, v_old = set_updates(prob, st, None if supports is None else supports.get(st.k))
     st.x_hist.append(st.x.copy())
     if len(st.x_hist) > opts.evol_hist + 1:
         st.x_hist.pop(0)
@@ -531,13 +546,13 @@ def iterate(prob: Problem, st: State, opts: Options, schedule=None) -> bool:
 
 
 def parsdmm(m, shape, sets, opts: Options | None = None, h=None, schedule=None,
-            state: State | None = None):
+            state: State | None = None, supports=None):
     """Project m onto the intersection of the sets.  Returns (x, state)."""
     opts = opts or Options()
     prob = Problem(m, shape, sets, h)
     st = state if state is not None else initial_state(prob, opts)
     while st.k <= opts.max_iter:
-        if iterate(prob, st, opts, schedule):
+        if iterate(prob, st, opts, schedule, supports):
             st.converged = True
             break
     return st.x.reshape(prob.shape), st

@@ -343,3 +343,37 @@ def test_adapt_runs_on_odd_iterations_only():
     assert all(a is b for a, b in zip(st.snaps, snaps1))
     orc.iterate(prob, st, opts)               # k = 3: new snapshots
     assert all(a is not b for a, b in zip(st.snaps, snaps1))
+
+
+def test_support_replay_of_own_choice_reproduces_free_run():
+    """Replaying a run's own cardinality supports (and schedule) changes
+    nothing: the replay only substitutes the choice of rows."""
+    from paper_1902_09699_amd import workloads as wl
+    m, sets, _, _ = wl.layered2d_four_sets(n=(14, 19), seed=6)
+    sets = wl.finalize(m, sets)
+    icard = [i for i, s in enumerate(sets) if s["kind"] == "card"]
+    assert icard
+    opts = orc.Options(max_iter=12)
+    prob = orc.Problem(m, m.shape, sets)
+    st = orc.initial_state(prob, opts)
+    sched, sup = {}, {}
+    while st.k <= opts.max_iter:
+        k = st.k
+        sched[k] = (st.rho.copy(), st.gamma.copy())
+        orc.iterate(prob, st, opts)
+        sup[k] = {i: np.nonzero(st.y[i])[0] for i in icard}
+        for i in icard:
+            assert np.array_equal(np.sort(orc.card_support(st.w_last[i], sets[i]["k"])), sup[k][i])
+    x2, _ = orc.parsdmm(m, m.shape, sets, opts, schedule=sched, supports=sup)
+    np.testing.assert_array_equal(x2.ravel(), st.x)
+
+
+def test_support_replay_takes_the_other_tied_row():
+    """At an exact tie the set has two projections; a replay of the other
+    choice keeps the other row (and only the cardinality set's y changes)."""
+    prob = orc.Problem(np.array([0.0, 0.0, 0.0]), (1, 3), [{"kind": "card", "op": "I", "k": 1}])
+    w = np.array([2.0, -2.0, 0.5])
+    np.testing.assert_array_equal(prob.prox(0, w, 1.0), [2.0, 0.0, 0.0])      # ties to the lower index
+    np.testing.assert_array_equal(prob.prox(0, w, 1.0, keep=np.array([1])), [0.0, -2.0, 0.0])
+    with pytest.raises(ValueError):
+        orc.Problem(np.zeros(3), (1, 3), [{"kind": "l1", "op": "I", "tau": 1.0}]).prox(0, w, 1.0, keep=np.array([0]))
