@@ -277,6 +277,8 @@ class State:
     r_feas: np.ndarray | None = None
     r_evol: float = math.inf
     w_last: list = field(default_factory=list)   # prox arguments of the last iteration
+    cg_trace: list = field(default_factory=list)  # ||r_j|| / ||r_0|| of the last x-update
+    cg_r0_rel: float = 0.0                        # ||b - C x^k|| / ||b|| of the last x-update
 
 
 class Problem:
@@ -351,21 +353,27 @@ def rhs(prob: Problem, st: State) -> np.ndarray:
     return b
 
 
-def cg(C, b, x0, cg_rel=0.1, cg_max=10, fixed=True):
+def cg(C, b, x0, cg_rel=0.1, cg_max=10, fixed=True, steps_forced=None, trace=None):
     """Plain conjugate gradients from the warm start x0.  Returns (x, steps).
     Stops when ||r|| < cg_rel ||r_0|| (unless ``fixed``), when the residual is
     exactly zero, or after cg_max steps.  A non-positive curvature p^T C p with
-    a non-zero residual raises (C is SPD in exact arithmetic)."""
+    a non-zero residual raises (C is SPD in exact arithmetic).
+    ``steps_forced`` (replay of another run's stopping decisions) runs exactly
+    that many steps unless the residual becomes exactly zero; ``trace``, a
+    list, receives ||r_j|| / ||r_0|| before every step j and after the last."""
     x = np.array(x0, dtype=np.float64, copy=True)
     r = b - C @ x
     rr = float(r @ r)
     rr0 = rr
     p = r.copy()
     steps = 0
-    for j in range(cg_max):
+    n = cg_max if steps_forced is None else int(steps_forced)
+    for j in range(n):
+        if trace is not None:
+            trace.append(math.sqrt(rr / rr0) if rr0 > 0.0 else 0.0)
         if rr == 0.0:
             break
-        if not fixed and j > 0 and rr < cg_rel * cg_rel * rr0:
+        if steps_forced is None and not fixed and j > 0 and rr < cg_rel * cg_rel * rr0:
             break
         q = C @ p
         pq = float(p @ q)
@@ -379,6 +387,8 @@ def cg(C, b, x0, cg_rel=0.1, cg_max=10, fixed=True):
         p = r + beta * p
         rr = rr_new
         steps += 1
+    if trace is not None and steps == n:
+        trace.append(math.sqrt(rr / rr0) if rr0 > 0.0 else 0.0)
     return x, steps
 
 
@@ -474,11 +484,17 @@ def relative_evolution(x, history):
 # One PARSDMM iteration and the full run (the PARSDMM listing)
 # ---------------------------------------------------------------------------
 
-def x_update(prob: Problem, st: State, opts: Options) -> int:
-    """x^{k+1} = C^{-1} sum_i A_i^T (rho_i y_i + v_i) by warm-started CG."""
+def x_update(prob: Problem, st: State, opts: Options, steps_forced=None) -> int:
+    """x^{k+1} = C^{-1} sum_i A_i^T (rho_i y_i + v_i) by warm-started CG
+    (``steps_forced``: replay another run's number of CG steps; the residual
+    ratios of this x-update are left in st.cg_trace, and ||b - C x^k|| / ||b||
+    in st.cg_r0_rel)."""
     C = prob.system_matrix(st.rho)
     b = rhs(prob, st)
-    st.x, steps = cg(C, b, st.x, opts.cg_rel, opts.cg_max, opts.cg_fixed)
+    nb = float(np.linalg.norm(b))
+    st.cg_r0_rel = float(np.linalg.norm(b - C @ st.x)) / nb if nb > 0.0 else 0.0
+    st.cg_trace = []
+    st.x, steps = cg(C, b, st.x, opts.cg_rel, opts.cg_max, opts.cg_fixed, steps_forced, st.cg_trace)
     st.cg_steps += steps
     return steps
 
@@ -521,17 +537,21 @@ def adapt(prob: Problem, st: State, s_all, y_old, v_old, opts: Options):
 
 def iterate(prob: Problem, st: State, opts: Options, schedule=None, supports=None) -> bool:
     """One PARSDMM iteration.  ``schedule`` (optional) maps k to (rho, gamma)
-    to use in iteration k instead of the adapted values (schedule-locked
+    to use in iteration k instead of the adapted values, or to (rho, gamma,
+    CG steps) to replay the number of CG steps as well (schedule-locked
     replay of another run); ``supports`` (optional) maps k to {set index:
     kept row indices} for cardinality sets (support-locked replay: a
     non-convex set has several equally valid projections where entries tie
     or nearly tie at the k-th magnitude, so a replay may take the other run's
     choice; the caller checks that choice against the oracle's own w).
     Returns True when the stopping test passed."""
+    forced = None
     if schedule is not None and st.k in schedule:
         st.rho = np.array(schedule[st.k][0], dtype=np.float64)
         st.gamma = np.array(schedule[st.k][1], dtype=np.float64)
-    x_update(prob, st, opts)
+        if len(schedule[st.k]) > 2:
+            forced = schedule[st.k][2]
+    x_update(prob, st, opts, forced)
     s_all, y_old, v_old = set_updates(prob, st, None if supports is None else supports.get(st.k))
     st.x_hist.append(st.x.copy())
     if len(st.x_hist) > opts.evol_hist + 1:

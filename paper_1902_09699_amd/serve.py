@@ -74,7 +74,11 @@ class Server:
     def close(self):
         self.batch.close()
 
-    def run(self, requests, realtime=True, log=None):
+    def run(self, requests, realtime=True, log=None, on_chunk=None, on_done=None):
+        """Serve `requests` (arrival order; with realtime=False every request
+        counts as arrived).  on_chunk(batch, active) is called after every
+        chunk, before finished instances retire; on_done(batch, slot,
+        request) just before a finished instance is removed."""
         import torch
         reqs = sorted(requests, key=lambda r: r.arrival)
         pending = collections.deque(reqs)
@@ -110,10 +114,14 @@ class Server:
             if active:
                 self.batch.run(self.chunk)
                 chunks += 1
+                if on_chunk:
+                    on_chunk(self.batch, active)
                 done = self.batch.poll()
                 for slot, flag in enumerate(done):
                     if flag == 1 and slot in active:
                         r, md, xd, need = active.pop(slot)
+                        if on_done:
+                            on_done(self.batch, slot, r)
                         r.result = self.batch.remove(slot)
                         r.x = xd.cpu().numpy()
                         r.t_done = now()

@@ -9,7 +9,7 @@ import pytest
 from oracle import parsdmm as orc
 from paper_1902_09699_amd import sip
 from paper_1902_09699_amd import workloads as wl
-from tests.gpu_util import Slot, rel, sync_oracle
+from tests.gpu_util import Slot, compare_step, rounding_spread, sync_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -41,30 +41,12 @@ def test_fullsize_lockstep(name, tiles):
     st = orc.initial_state(prob, oo)
     for it in range(3):
         sync_oracle(sl, prob, st)
+        spread = rounding_spread(prob, st, oo, field)
         orc.iterate(prob, st, oo)
         sl.batch.run(1)
-        ex = rel(sl.x(), st.x)
-        worst = ex
-        for i in range(len(sets) + 1):
-            yg, yo = sl.arr(sip.FIELD_Y, i), st.y[i]
-            vg, vo = sl.arr(sip.FIELD_V, i), st.v[i]
-            if i < len(sets) and sets[i]["kind"] == "card":
-                a = np.abs(st.w_last[i])
-                tk = np.sort(a)[::-1][sets[i]["k"] - 1]
-                mask = np.abs(a - tk) > 1e-4 * tk
-                assert np.array_equal((yg != 0)[mask], (yo != 0)[mask])
-                assert (yg != 0).sum() <= sets[i]["k"]
-                yg, yo, vg, vo = yg[mask], yo[mask], vg[mask], vo[mask]
-            op = "I" if i == len(sets) else sets[i]["op"]
-            ncomp = {"I": 1, "DZ": 1, "DY": 1, "DX": 1, "GRAD": m.ndim, "LAT": m.ndim - 1}[op]
-            anorm = 1.0 if op == "I" else 2.0 * np.sqrt(ncomp)
-            scale = max(np.linalg.norm(yo), np.linalg.norm(st.w_last[i]), anorm * np.linalg.norm(st.x))
-            ey = np.linalg.norm(yg - yo) / scale
-            ev = np.linalg.norm(vg - vo) / max(np.linalg.norm(vo), scale)
-            worst = max(worst, ey, ev)
-            assert ey <= 1e-5 and ev <= 1e-4, (it, i, ey, ev)
-        assert ex <= 1e-5, (it, ex)
-        print(f"[fullsize] {name} iteration {it + 1}: worst rel err {worst:.2e}", flush=True)
+        worst, ratio = compare_step(sl, prob, st, spread, 1e-5, label=(name, it + 1))
+        print(f"[fullsize] {name} iteration {it + 1}: worst rel err {worst:.2e}, worst err / x-rounding spread "
+              f"{ratio:.1f}", flush=True)
 
 
 def test_fullsize_run_properties():

@@ -2,11 +2,15 @@
 
 Protocol: (1) step parity — before every iteration the oracle is set to the
 device state (exact upcast), both run one iteration, and every state array
-is compared; (2) end-to-end — float64 free-running runs must agree with the
-oracle to 1e-9, float32 runs must agree to 1e-5 when the oracle replays the
-device's (rho, gamma) schedule; (3) cardinality supports must be identical
-away from ties with the k-th magnitude."""
-import math
+is compared: x to 1e-5 (float32) / 1e-10 (float64) of ||x||; y_i and v_i to
+the same tolerance of max(||y_i||, ||w_i||), or, where larger, 16x the
+measured spread one float32 rounding of the oracle's own x causes (float32
+rounding of x reaches A_i x amplified by the difference operators);
+(2) end to end — float64 free-running runs must agree with the oracle to
+1e-9, float32 runs to 1e-5 when the oracle replays the device's (rho,
+gamma) schedule and cardinality supports (each replayed support a valid
+top-k of the oracle's own w); (3) cardinality supports must be identical
+outside a band of 1e-4 t_k around the k-th magnitude t_k."""
 import zlib
 
 import numpy as np
@@ -15,7 +19,8 @@ import pytest
 from oracle import parsdmm as orc
 from paper_1902_09699_amd import sip
 from paper_1902_09699_amd import workloads as wl
-from tests.gpu_util import Slot, make_case, rel, sync_oracle
+from tests.gpu_util import (Slot, card_sets, compare_step, make_case, rel, replay_locked, rounding_spread,
+                            run_logged, sync_oracle, unpad)
 
 pytestmark = pytest.mark.gpu
 
@@ -26,12 +31,6 @@ def _prep(kind, field, seed=0):
     m, sets = make_case(kind, seed)
     m = wl.rounded(m, field)
     return m, wl.finalize(m, sets)
-
-
-def _card_mask(w, k, rtol):
-    a = np.abs(w)
-    tk = np.sort(a)[::-1][k - 1]
-    return np.abs(a - tk) > rtol * max(tk, 1e-300)
 
 
 @pytest.mark.parametrize("kind,field,threads,form", [
@@ -53,43 +52,21 @@ def test_step_parity(kind, field, threads, form):
     oo = orc.Options(max_iter=50, cg_max=10, cg_fixed=True)
     st = orc.initial_state(prob, oo)
     tol = STEP_TOL[field]
-    worst = 0.0
+    worst, ratio = 0.0, 0.0
     for it in range(iters):
         sync_oracle(sl, prob, st)
+        spread = rounding_spread(prob, st, oo, field)
         orc.iterate(prob, st, oo)
         sl.batch.run(1)
-        ex = rel(sl.x(), st.x)
-        worst = max(worst, ex)
-        assert ex <= tol, (it, "x", ex)
-        for i in range(len(sets) + 1):
-            yg, vg = sl.arr(sip.FIELD_Y, i), sl.arr(sip.FIELD_V, i)
-            yo, vo = st.y[i], st.v[i]
-            if i < len(sets) and sets[i]["kind"] == "card":
-                mask = _card_mask(st.w_last[i], sets[i]["k"], 1e-4 if field == "f32" else 1e-10)
-                assert mask.mean() > 0.98
-                sup_g, sup_o = yg != 0, yo != 0
-                assert np.array_equal(sup_g[mask], sup_o[mask]), (it, i, "card support")
-                yg, yo, vg, vo = yg[mask], yo[mask], vg[mask], vo[mask]
-            # the projection is nonexpansive: an error in its input w moves y by no
-            # more, so y and v are measured against the scale of w as well
-            # float32 rounding of x reaches s = A_i x amplified by ||A_i||
-            # (at most 2 sqrt(components) / h for the difference operators)
-            wo = st.w_last[i][mask] if (i < len(sets) and sets[i]["kind"] == "card") else st.w_last[i]
-            op = "I" if i == len(sets) else sets[i]["op"]
-            ncomp = {"I": 1, "DZ": 1, "DY": 1, "DX": 1, "GRAD": m.ndim, "LAT": m.ndim - 1}[op]
-            anorm = 1.0 if op == "I" else 2.0 * math.sqrt(ncomp)
-            scale = max(np.linalg.norm(yo), np.linalg.norm(wo), anorm * np.linalg.norm(st.x), 1e-30)
-            ey = np.linalg.norm(yg - yo) / scale
-            ev = np.linalg.norm(vg - vo) / max(np.linalg.norm(vo), scale)
-            worst = max(worst, ey, ev)
-            assert ey <= tol, (it, i, "y", ey)
-            assert ev <= 10 * tol, (it, i, "v", ev)
+        w, r = compare_step(sl, prob, st, spread, tol, label=(kind, it))
+        worst, ratio = max(worst, w), max(ratio, r)
         rg, gg, kg, _ = sl.batch.get_params(sl.slot)
         assert kg == st.k
         if field == "f64":
             np.testing.assert_allclose(rg, st.rho, rtol=1e-8)
             np.testing.assert_allclose(gg, st.gamma, rtol=1e-8)
-    print(f"[step parity] {kind} {field}: worst rel err {worst:.2e}", flush=True)
+    print(f"[step parity] {kind} {field}: worst rel err {worst:.2e}, worst err / x-rounding spread {ratio:.1f}",
+          flush=True)
 
 
 @pytest.mark.parametrize("kind", ["box_tv_2d", "four_sets_2d", "box_tv_lat_3d", "mixed_3d"])
@@ -110,28 +87,39 @@ def test_free_running_f64(kind):
 
 @pytest.mark.parametrize("kind", ["box_tv_2d", "four_sets_2d", "box_tv_lat_3d", "mixed_2d"])
 def test_schedule_locked_f32(kind):
+    """Float32 end to end against the FP64 oracle replaying the device's
+    (rho, gamma) schedule and, for cardinality sets, its kept rows (each
+    replayed choice must be a valid top-k of the oracle's own w, ties within
+    the band going either way).  Gate: 1e-5, or 8x the oracle's own change
+    under a one-unit-roundoff perturbation of m where that is larger (the
+    stiff 3D case, whose lateral-slope penalty reaches the ratio cap)."""
     m, sets = _prep(kind, "f32", seed=2)
     iters = 40
     print(f"\n[f32 locked] {kind} shape={m.shape}", flush=True)
     sl = Slot(m, sets, "f32", dict(max_iter=iters, cg_max=10, cg_fixed=1, log_schedule=1))
-    sl.batch.run(iters)
+    sched, sup = run_logged(sl, iters)
     rho, gam = sl.batch.schedule(sl.slot, iters)
     assert rho.shape == (iters, len(sets) + 1)
-    sched = {k + 1: (rho[k], gam[k]) for k in range(iters)}
-    xo, _ = orc.parsdmm(m, m.shape, sets, orc.Options(max_iter=iters, cg_max=10, cg_fixed=True), schedule=sched)
-    xf, _ = orc.parsdmm(m, m.shape, sets, orc.Options(max_iter=iters, cg_max=10, cg_fixed=True))
-    # the problem's own float32 sensitivity: the oracle rerun (same schedule)
-    # on m perturbed by one float32 unit roundoff, relative, at random
+    for k in range(iters):
+        np.testing.assert_array_equal(rho[k], sched[k + 1][0])
+    oo = orc.Options(max_iter=iters, cg_max=10, cg_fixed=True)
+    st, rep, _ = replay_locked(m, sets, oo, sched, sup or None)
+    xo = st.x
+    xf, _ = orc.parsdmm(m, m.shape, sets, oo)
+    # the problem's own float32 sensitivity: the oracle rerun (same schedule
+    # and supports) on m perturbed by one float32 unit roundoff, at random
     mp = m * (1.0 + 2.0 ** -24 * np.random.default_rng(5).standard_normal(m.shape))
-    xs, _ = orc.parsdmm(mp, m.shape, sets, orc.Options(max_iter=iters, cg_max=10, cg_fixed=True), schedule=sched)
+    xs, _ = orc.parsdmm(mp, m.shape, sets, oo, schedule=sched, supports=sup or None)
     sens = rel(xs, xo)
     err = rel(sl.x(), xo)
     err_free = rel(sl.x(), xf)
     gate = max(1e-5, 8.0 * sens)
-    print(f"[f32 locked] {kind}: schedule-locked rel err {err:.2e}, free-running {err_free:.2e}, "
-          f"oracle sensitivity to 1 ulp of m {sens:.2e}, gate {gate:.1e}", flush=True)
-    if any(s["kind"] == "card" for s in sets):
-        gate = max(gate, 1e-3)  # support flips near ties move single entries
+    flips = sum(r[3] for r in rep)
+    print(f"[f32 locked] {kind}: locked rel err {err:.2e}, free-running {err_free:.2e}, "
+          f"oracle sensitivity to 1 ulp of m {sens:.2e}, gate {gate:.1e}; replayed supports {len(rep)}, "
+          f"entries chosen differently from the oracle {flips}, "
+          f"farthest from t_k {max([r[4] for r in rep], default=0):.1e}", flush=True)
+    assert all(r[2] for r in rep), [r for r in rep if not r[2]][:3]
     assert err <= gate
 
 
@@ -189,6 +177,33 @@ def test_stopping_rule_matches_oracle():
     assert rel(sl.x(), xo) <= 1e-9
     np.testing.assert_allclose(res["r_feas"], st.r_feas, rtol=1e-6, atol=1e-12)
     assert res["r_evol"] == pytest.approx(st.r_evol, rel=1e-6)
+
+
+@pytest.mark.parametrize("kind", ["box_tv_2d", "mixed_2d", "four_sets_2d"])
+def test_stopping_rule_matches_oracle_f32(kind):
+    """Float32 fields with the stopping rule (eqs. feas_stop, obj_stop every 5
+    iterations) and the relative CG stop (eq. cg_stop): the oracle replays
+    the device's (rho, gamma), CG step counts and kept rows (each count and
+    support must be a valid decision for the oracle's own values) and must
+    stop at the same iteration, with the same r_feas and r_evol."""
+    m, sets = _prep(kind, "f32", seed=3)
+    kw = dict(max_iter=300, cg_max=10, cg_fixed=0, stop_every=5)
+    print(f"\n[stop f32] {kind} {m.shape}", flush=True)
+    sl = Slot(m, sets, "f32", kw)
+    sched, sup = run_logged(sl, 300)
+    res = sl.batch.result(sl.slot)
+    st, rep, cgrep = replay_locked(m, sets, orc.Options(**kw), sched, sup or None)
+    err = rel(sl.x(), st.x)
+    print(f"[stop f32] {kind}: gpu iters {res['iters']} converged {res['converged']} r_evol {res['r_evol']:.4e}; "
+          f"oracle iters {st.k - 1} converged {st.converged} r_evol {st.r_evol:.4e}; rel err {err:.2e}; "
+          f"CG decisions differing from the oracle's own {sum(c[2] for c in cgrep)} of {len(cgrep)}", flush=True)
+    assert all(c[1] for c in cgrep), [c for c in cgrep if not c[1]][:3]
+    assert all(r[2] for r in rep)
+    assert res["converged"] and st.converged
+    assert res["iters"] == st.k - 1
+    assert err <= 1e-5
+    np.testing.assert_allclose(res["r_feas"], st.r_feas, rtol=1e-3, atol=1e-7)
+    assert res["r_evol"] == pytest.approx(st.r_evol, rel=1e-3)
 
 
 def test_alone_vs_batched_bitwise_f32():
@@ -277,13 +292,12 @@ def test_edge_cases_f64(name, form):
     print(f"[edge] {name}: schedule-locked rel err {err_locked:.2e}, free-running {err:.2e}, "
           f"same schedule {same}", flush=True)
     if name == "one_set_box_only":
-        # the iterate reaches clip(m) exactly within a few iterations; after
-        # that the adapt dots are rounding noise on both sides, so compare both
-        # to the closed form instead
+        # the iterate approaches clip(m) within a few iterations; after that
+        # the adapt dots are rounding noise on both sides, so the free runs
+        # may take different (rho, gamma) and are compared with the closed
+        # form; the schedule-locked run must still agree to 1e-9
         np.testing.assert_allclose(sl.x(), np.clip(m, -0.1, 0.2).ravel(), atol=1e-5)
         np.testing.assert_allclose(xo.ravel(), np.clip(m, -0.1, 0.2).ravel(), atol=1e-5)
-        assert err <= 1e-4
-        return
     assert err_locked <= 1e-9
     if same:
         assert err <= 1e-9
@@ -353,7 +367,8 @@ def test_card_exact_ties_across_items(field):
 def test_unaligned_x(field, form):
     """x one element past a 16-byte boundary: the RHS and CG kernels take
     their per-point path.  Its iterates must match the grouped path's (same
-    arithmetic, element by element) and the oracle."""
+    arithmetic, element by element) and the oracle replaying the device's
+    schedule and cardinality supports (1e-5 in float32, 1e-9 in float64)."""
     import torch
     m, sets = _prep("four_sets_2d" if field == "f32" else "mixed_2d", field, seed=4)
     iters = 6
@@ -361,6 +376,7 @@ def test_unaligned_x(field, form):
     opts = sip.make_opts(field, max_iter=iters, cg_max=10, cg_fixed=1, log_schedule=1)
     dt = torch.float64 if field == "f64" else torch.float32
     md = torch.tensor(m, dtype=dt, device="cuda")
+    ic = card_sets(sets)
     xs = []
     for shift in (0, 1):
         buf = torch.empty(m.size + 4, dtype=dt, device="cuda")
@@ -369,7 +385,11 @@ def test_unaligned_x(field, form):
         b = sip.Batch(1, sip.workspace_bytes(m.shape, sets, opts), opts)
         b.set_tiles(1024, 1024, 1024, 512, 512, form)
         sl = b.add(md, sets, x)
-        b.run(iters)
+        sup = {}
+        for k in range(1, iters + 1):
+            b.run(1)
+            sup[k] = {i: np.nonzero(unpad(m.shape, sets[i]["op"], b.field_tensor(sl, sip.FIELD_Y, i).double().cpu().numpy(),
+                                          b.field(sl, sip.FIELD_Y, i)[2]))[0] for i in ic}
         res = b.result(sl)
         assert res["status"] == 0 and res["iters"] == iters
         rho, gam = b.schedule(sl, iters)
@@ -377,10 +397,12 @@ def test_unaligned_x(field, form):
         xs.append(x.double().cpu().numpy().ravel())
         b.close()
     sched = {k + 1: (rho[k], gam[k]) for k in range(iters)}
-    xo, _ = orc.parsdmm(m, m.shape, sets, orc.Options(max_iter=iters, cg_max=10, cg_fixed=True), schedule=sched)
+    st, rep, _ = replay_locked(m, sets, orc.Options(max_iter=iters, cg_max=10, cg_fixed=True), sched,
+                               sup if ic else None)
     d_paths = rel(xs[1], xs[0])
-    err = rel(xs[1], xo)
+    err = rel(xs[1], st.x)
     print(f"[unaligned x] {field} cg_form={form}: grouped vs per-point {d_paths:.2e}, vs oracle {err:.2e}",
           flush=True)
+    assert all(r[2] for r in rep)
     assert d_paths <= (1e-12 if field == "f64" else 1e-5)
-    assert err <= (1e-9 if field == "f64" else 1e-3)
+    assert err <= (1e-9 if field == "f64" else 1e-5)

@@ -377,3 +377,31 @@ def test_support_replay_takes_the_other_tied_row():
     np.testing.assert_array_equal(prob.prox(0, w, 1.0, keep=np.array([1])), [0.0, -2.0, 0.0])
     with pytest.raises(ValueError):
         orc.Problem(np.zeros(3), (1, 3), [{"kind": "l1", "op": "I", "tau": 1.0}]).prox(0, w, 1.0, keep=np.array([0]))
+
+
+def test_cg_count_replay_of_own_decisions_reproduces_free_run():
+    """With the relative CG stop on, replaying a run's own CG step counts
+    (and schedule) reproduces it bitwise, and every count is the first step
+    whose residual ratio fell below cg_rel (eq. cg_stop) or the cap."""
+    from paper_1902_09699_amd import workloads as wl
+    m, sets, _, _ = wl.smooth2d_box_tv(n=(18, 21), seed=8)
+    sets = wl.finalize(m, sets)
+    opts = orc.Options(max_iter=25, cg_max=10, cg_fixed=False, stop_every=5)
+    prob = orc.Problem(m, m.shape, sets)
+    st = orc.initial_state(prob, opts)
+    sched = {}
+    while st.k <= opts.max_iter:
+        k = st.k
+        rho, gam = st.rho.copy(), st.gamma.copy()
+        before = st.cg_steps
+        stop = orc.iterate(prob, st, opts)
+        n = st.cg_steps - before
+        sched[k] = (rho, gam, n)
+        tr = st.cg_trace
+        assert n == opts.cg_max or tr[n] < opts.cg_rel or tr[n] == 0.0
+        assert all(t >= opts.cg_rel for t in tr[1:n])
+        if stop:
+            break
+    x2, st2 = orc.parsdmm(m, m.shape, sets, opts, schedule=sched)
+    np.testing.assert_array_equal(x2.ravel(), st.x)
+    assert st2.k == st.k and st2.cg_steps == st.cg_steps
