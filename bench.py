@@ -1,11 +1,22 @@
 """Benchmark: PARSDMM grid-points x iterations per second on one MI355X.
 
-One step = one complete projection (state reset from m, then every
-iteration of the PARSDMM listing) of the chosen workload, inputs resident in
-HBM.  Prints one JSON line with the throughput, the roofline of the dominant
-kernel (algorithmic bytes per launch over its HIP-event-timed mean launch
-duration, against the 8 TB/s HBM peak) and the FP64 CPU oracle timed on a
-bounded sample of the same workload.
+One step = one complete projection of every instance of the workload (state
+reset from m, then every iteration of the PARSDMM listing), inputs resident
+in HBM.  The default workload is the largest single-GPU configuration: 256
+uneven 2D instances in one batch.  One JSON line carries
+
+* the throughput (grid-pts*iters/s) and instances/s of that batch;
+* the roofline of its dominant kernel (algorithmic bytes per launch over the
+  HIP-event mean launch duration) and of the whole iteration (the compulsory
+  words of an iteration, (5 + 8 n_cg) N + 9 sum M + 2 sum M_thr + N per
+  instance with an l1/cardinality set, over the measured time per iteration),
+  both against the 8 TB/s HBM peak;
+* the same whole-iteration figures on the 200x200x100 grid (the single
+  instance that streams from HBM) and the served form's p50/p99 latency next
+  to the plain one-at-a-time form on the same requests;
+* the FP64 CPU oracle timed on a bounded sample of the workload on the host's
+  cores, and the error against it of a sample of instances (the oracle
+  replays each device run's (rho, gamma) schedule and kept cardinality rows).
 """
 from __future__ import annotations
 
@@ -24,7 +35,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-WORKLOADS = ("layered2d", "layered2d_lines", "smooth2d", "smooth3d", "batched")
+METRIC = "PARSDMM grid-pts·iters/s, % HBM peak; served p50/p99 latency vs plain"
+WORKLOADS = ("batched", "layered2d", "layered2d_lines", "smooth2d", "smooth3d")
+# relative band around the k-th magnitude inside which a cardinality
+# support may go either way (ties of the non-convex projection)
+CARD_BAND = 1e-4
 
 
 def parse():
@@ -32,25 +47,44 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="layered2d", choices=WORKLOADS)
+    ap.add_argument("--workload", default="batched", choices=WORKLOADS)
     ap.add_argument("--graph-iters", type=int, default=50)
     ap.add_argument("--reps", type=int, default=30, help="launches per kernel timing")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle sample budget (0: skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle timing budget (0: skip the CPU leg)")
     ap.add_argument("--batched-count", type=int, default=256)
     ap.add_argument("--copy-mb", type=int, default=1024, help="plain-copy reference size (0: skip)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles")
     ap.add_argument("--reduce", default="f64", choices=("f64", "f32"),
                     help="reduction type (f32: the pure-FP32 precision ablation)")
-    ap.add_argument("--check-iters", type=int, default=10,
-                    help="iterations of the schedule-locked error check against the oracle (0: skip)")
+    ap.add_argument("--check-iters", type=int, default=40,
+                    help="iterations of the locked error check against the oracle (0: skip)")
+    ap.add_argument("--check-instances", type=int, default=4, help="sampled instances of the error check")
     ap.add_argument("--tiles", default=None,
                     help="fixed tiles pt_points,pt_max_items,thr_points,thr_max_items[,pt_threads[,cg_form]] "
                          "(no autotune)")
+    ap.add_argument("--extras", default="auto", choices=("auto", "on", "off"),
+                    help="200x200x100 and served legs (auto: with the batched workload)")
+    ap.add_argument("--c3-steps", type=int, default=2)
+    ap.add_argument("--served-requests", type=int, default=100)
+    ap.add_argument("--served-rate", type=float, default=200.0)
     return ap.parse_args()
 
 
-def workload(name, args):
+def say(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------- workloads
+
+def load_workload(name, args):
     from paper_1902_09699_amd import workloads as wl
+    if name == "batched":
+        out = []
+        for m, sets in wl.batched_instances(args.batched_count):
+            m = wl.rounded(m, "f32")
+            out.append((m, wl.finalize(m, sets)))
+        return out, "f32", 200, (f"{args.batched_count} uneven 2D instances (sides U[32,512]), 2-5 sets from "
+                                 f"{{box, TV, l1(D_z), card(D_x)}}; 200 it x 10 CG, f32 fields, f64 reductions")
     if name == "layered2d":
         m, sets, field, iters = wl.layered2d_four_sets()
         desc = "layered 341x1361 f32: box, D_z>=0, l1(D_x), card(D_x); 300 it x 10 CG"
@@ -70,30 +104,38 @@ def workload(name, args):
     return [(m, wl.finalize(m, sets))], field, iters, desc
 
 
-def batched_workload(args):
-    from paper_1902_09699_amd import workloads as wl
-    out = []
-    for m, sets in wl.batched_instances(args.batched_count):
-        m = wl.rounded(m, "f32")
-        out.append((m, wl.finalize(m, sets)))
-    return out, "f32", 200, f"{args.batched_count} uneven 2D instances (sides U[32,512]), 2-5 sets; 200 it x 10 CG"
-
-
 def rows(shape, s):
     from paper_1902_09699_amd import workloads as wl
     return wl.rows_of(shape, s["op"])
 
 
-def algorithmic_bytes(insts, esz):
-    """Compulsory bytes of one launch of each kernel (all instances):
-    CG direction: read r, p, write p (3N); CG update: read x, r, p, write x, r
-    (5N); one-reduction CG step: read x, p, r, w, s, write all five (10N);
-    its w_0 pass: read r, write w (2N); RHS: read x and every y_i, v_i (identity block included), write r;
-    projection (non-adapt iteration): read x, m, y_i, v_i of the bounds sets
-    and the identity block, write y_i, v_i; threshold w pass: read x, y_i,
-    v_i, write w over y_i (N + 3 M_i per l1 / cardinality set); threshold
-    apply pass: read w, write y_i, v_i (3 M_i); line-wise sets: read x, y_i, v_i,
-    write y_i, v_i (N + 4 M_i)."""
+def iteration_words(insts, n_cg=10):
+    """Compulsory words of one PARSDMM iteration, summed over instances: each
+    phase between two global reductions streams its operands once.
+    RHS + CG init 2 sum M + 2N; CG 8N per step (3N direction + 5N update);
+    projections 2N + 4 sum M; threshold sets' histogram pass 2 M_i (+N for x
+    once); adapt-rho-gamma snapshots 3 sum M + N every second iteration
+    (amortised 1.5 sum M + N/2, rounded into 9 sum M and the 5N)."""
+    w = 0
+    for m, sets in insts:
+        N = m.size
+        sum_m = N + sum(rows(m.shape, s) for s in sets)
+        thr = [rows(m.shape, s) for s in sets if s["kind"] != "bounds"]
+        w += (5 + 8 * n_cg) * N + 9 * sum_m + 2 * sum(thr) + (N if thr else 0)
+    return w
+
+
+def kernel_bytes(insts, esz):
+    """Algorithmic bytes of one launch of each kernel (all instances), on the
+    same per-phase accounting as iteration_words: CG direction read r, p,
+    write p (3N); CG update read x, r, p, write x, r (5N); a one-reduction CG
+    step counts as one CG step of the same accounting (8N, although that
+    arrangement moves 10N); its w_0 pass read r, write w (2N); RHS read x and
+    every y_i, v_i (identity block included), write r; projection read x, m
+    and y_i, v_i of the bounds sets and the identity block, write y_i, v_i;
+    threshold w pass read x, y_i, v_i, write w (N + 3 M_i); apply pass read
+    w, write y_i, v_i (3 M_i); line-wise sets read x, y_i, v_i, write y_i,
+    v_i (N + 4 M_i)."""
     b = {"cg_dir": 0, "cg_upd": 0, "cg1_step": 0, "cg1_w0": 0, "rhs": 0, "proj": 0, "thr_w": 0, "thr_apply": 0,
          "line": 0}
     for m, sets in insts:
@@ -104,7 +146,7 @@ def algorithmic_bytes(insts, esz):
         line = [rows(m.shape, s) for s in sets if s.get("line") is not None]
         b["cg_dir"] += 3 * N * esz
         b["cg_upd"] += 5 * N * esz
-        b["cg1_step"] += 10 * N * esz
+        b["cg1_step"] += 8 * N * esz
         b["cg1_w0"] += 2 * N * esz
         b["rhs"] += (2 * N + 2 * sum_m) * esz
         b["proj"] += (2 * N + 4 * clip) * esz
@@ -135,92 +177,14 @@ def traffic_from_profiles(kernel, wname):
     return d.get("hbm_bytes_per_launch")
 
 
-def device_reference(inst, field, reduce, iters, tiles=None):
-    """The first instance alone on the device for `iters` iterations with the
-    (rho, gamma) schedule logged (tiles and CG form as timed): its x and the
-    schedule."""
+# ------------------------------------------------------------------ GPU legs
+
+def run_timed(insts, field, iters, args, steps, warmup, tiles_arg=None, autotune=True):
+    """Admit every instance into one batch, pick tiles, then time `steps`
+    complete projections (reset from m + every iteration, chunks of
+    graph_iters iterations replayed from captured graphs)."""
     import torch
     from paper_1902_09699_amd import sip
-    m, sets = inst
-    opts = sip.make_opts(field, reduce=reduce, max_iter=iters, cg_max=10, cg_fixed=1, log_schedule=1)
-    md = torch.tensor(m, dtype=torch.float64 if field == "f64" else torch.float32, device="cuda")
-    xd = torch.empty_like(md)
-    b = sip.Batch(1, sip.workspace_bytes(m.shape, sets, opts), opts)
-    if tiles:
-        b.set_tiles(*tiles)
-    slot = b.add(md, sets, xd)
-    b.run(iters)
-    rho, gam = b.schedule(slot, iters)
-    x = xd.double().cpu().numpy()
-    b.close()
-    return x, {k + 1: (rho[k], gam[k]) for k in range(len(rho))}
-
-
-def oracle_sensitivity(inst, iters, schedule, field):
-    """How far the oracle's own x moves after `iters` iterations (same
-    schedule) when m is perturbed by one unit roundoff of the field type:
-    the scale an error against the oracle is to be read on."""
-    from oracle import parsdmm as orc
-    m, sets = inst
-    u = 2.0 ** -24 if field == "f32" else 2.0 ** -53
-    mp = m * (1.0 + u * np.random.default_rng(5).standard_normal(m.shape))
-    oo = orc.Options(max_iter=iters, cg_max=10, cg_fixed=True)
-    xa, _ = orc.parsdmm(m, m.shape, sets, oo, schedule=schedule)
-    xb, _ = orc.parsdmm(mp, m.shape, sets, oo, schedule=schedule)
-    return float(np.linalg.norm(xb - xa) / max(np.linalg.norm(xa), 1e-300))
-
-
-def cpu_baseline(insts, iters_full, budget_s, schedule=None, check=None):
-    """The FP64 oracle as it stands, on the first instance, for as many
-    iterations as fit the budget (at least 2), replaying the device's (rho,
-    gamma) schedule where one is given; check = (k, x_device) compares the
-    oracle's x after iteration k with the device's."""
-    from oracle import parsdmm as orc
-    m, sets = insts[0]
-    prob = orc.Problem(m, m.shape, sets)
-    opts = orc.Options(max_iter=iters_full, cg_max=10, cg_fixed=True)
-    st = orc.initial_state(prob, opts)
-    err = None
-
-    def step():
-        nonlocal err
-        orc.iterate(prob, st, opts, schedule)
-        if check is not None and st.k - 1 == check[0]:
-            xo = st.x.ravel()
-            err = float(np.linalg.norm(check[1].ravel() - xo) / max(np.linalg.norm(xo), 1e-300))
-
-    step()  # first iteration: warm-up, untimed
-    ru0 = resource.getrusage(resource.RUSAGE_SELF)
-    t0 = time.perf_counter()
-    done = 0
-    while done < 2 or (time.perf_counter() - t0 < budget_s and st.k <= iters_full) or \
-            (check is not None and err is None and st.k <= check[0]):
-        step()
-        done += 1
-    wall = time.perf_counter() - t0
-    ru1 = resource.getrusage(resource.RUSAGE_SELF)
-    cpu = (ru1.ru_utime - ru0.ru_utime) + (ru1.ru_stime - ru0.ru_stime)
-    cores = max(1, int(round(cpu / wall)))
-    out = {"value": m.size * done / wall, "unit": "grid-pts*iters/s", "cores": cores, "kind": "oracle",
-           "sample": f"iterations 2..{done + 1} of the first instance ({m.shape}), FP64 CSR oracle, "
-                     f"{wall:.1f} s wall, {cpu:.1f} s CPU"}
-    return out, err
-
-
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the library has no multi-GPU path",
-              file=sys.stderr)
-        sys.exit(2)
-    import torch
-    from paper_1902_09699_amd import sip
-
-    if args.workload == "batched":
-        insts, field, iters, desc = batched_workload(args)
-    else:
-        insts, field, iters, desc = workload(args.workload, args)
-    esz = 8 if field == "f64" else 4
     dt = torch.float64 if field == "f64" else torch.float32
     opts = sip.make_opts(field, reduce=args.reduce, max_iter=iters, cg_max=10, cg_fixed=1)
     ms = [torch.tensor(m, dtype=dt, device="cuda") for m, _ in insts]
@@ -229,18 +193,16 @@ def main():
     batch = sip.Batch(len(insts), arena, opts)
     slots = [batch.add(md, s, xd) for md, (_, s), xd in zip(ms, insts, xs)]
     assert all(s >= 0 for s in slots)
-    chunk = min(args.graph_iters, iters)
-    n_pts = sum(m.size for m, _ in insts)
     tiles = None
-    if args.tiles:
-        tiles = tuple(int(v) for v in args.tiles.split(","))
+    if tiles_arg:
+        tiles = tuple(int(v) for v in tiles_arg.split(","))
         batch.set_tiles(*tiles)
-    elif not args.no_autotune:
-        from paper_1902_09699_amd import autotune
-        tiles, tile_ms = autotune.tune(batch, slots, ms, field, [m.shape for m, _ in insts], use_cache=False,
-                                       cache=None)
-        for cand, t in sorted(tile_ms.items(), key=lambda kv: kv[1])[:6]:
-            print(f"autotune {cand}: {1e3 * t:.1f} us/iteration", file=sys.stderr, flush=True)
+    elif autotune:
+        from paper_1902_09699_amd import autotune as at
+        tiles, tile_ms = at.tune(batch, slots, ms, field, [m.shape for m, _ in insts], use_cache=False, cache=None)
+        for cand, t in sorted(tile_ms.items(), key=lambda kv: kv[1])[:4]:
+            say(f"autotune {cand}: {1e3 * t:.1f} us/iteration")
+    chunk = min(args.graph_iters, iters)
 
     def one_step():
         for sl, md in zip(slots, ms):
@@ -251,31 +213,35 @@ def main():
             batch.run(n)
             left -= n
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         one_step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         one_step()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
+    wall = time.perf_counter() - t0
     results = [batch.result(sl) for sl in slots]
     assert all(r["status"] == 0 and r["iters"] == iters for r in results), results[:3]
-    value = n_pts * iters * args.steps / wall
-    ms_step = 1e3 * wall / args.steps
+    n_pts = sum(m.size for m, _ in insts)
+    return {"batch": batch, "slots": slots, "ms": ms, "xs": xs, "tiles": tiles, "wall": wall,
+            "ms_step": 1e3 * wall / steps, "value": n_pts * iters * steps / wall, "n_pts": n_pts}
 
-    # roofline: time each kernel on its own (HIP events on the launch stream)
-    batch.set_params(slots[0], *batch.get_params(slots[0])[:2], 2, True)
-    for sl in slots[1:]:
+
+def kernel_table(run, insts, field, reps):
+    """Each iteration kernel timed on its own over the batch's work tables
+    (HIP events on the launch stream), with its algorithmic bytes."""
+    from paper_1902_09699_amd import sip
+    batch, slots = run["batch"], run["slots"]
+    for sl in slots:  # an adapt iteration follows: the snapshot branches run
         r_, g_, _, _ = batch.get_params(sl)
         batch.set_params(sl, r_, g_, 2, True)
-    ab = algorithmic_bytes(insts, esz)
+    esz = 8 if field == "f64" else 4
+    ab = kernel_bytes(insts, esz)
+    tiles = run["tiles"]
     one_red = bool(tiles) and len(tiles) > 5 and tiles[5] == 1
-    if one_red:
-        ids = {"cg1_step": sip.K_CG1_STEP, "cg1_w0": sip.K_CG1_W0}
-    else:
-        ids = {"cg_dir": sip.K_CG_DIR, "cg_upd": sip.K_CG_UPD}
+    ids = {"cg1_step": sip.K_CG1_STEP, "cg1_w0": sip.K_CG1_W0} if one_red else \
+        {"cg_dir": sip.K_CG_DIR, "cg_upd": sip.K_CG_UPD}
     ids.update({"rhs": sip.K_RHS, "proj": sip.K_PROJ, "thr_w": sip.K_THR_W, "thr_apply": sip.K_THR_APPLY,
                 "line": sip.K_LINE})
     per_iter = {"cg_dir": 10, "cg_upd": 10, "cg1_step": 10, "cg1_w0": 1, "rhs": 1, "proj": 1, "thr_w": 1,
@@ -284,70 +250,309 @@ def main():
     for name, kid in ids.items():
         if ab[name] == 0:
             continue
-        t_ms = batch.time_kernel(kid, args.reps)
+        t_ms = batch.time_kernel(kid, reps)
         kernels[name] = {"ms": t_ms, "GBs": ab[name] / (t_ms * 1e-3) / 1e9, "bytes": ab[name],
                          "launches_per_iter": per_iter[name]}
+    return kernels
+
+
+def roofline_of(kernels, wname):
     dom = max(kernels, key=lambda k: kernels[k]["ms"] * kernels[k]["launches_per_iter"])
     ach = kernels[dom]["GBs"]
-    traffic = traffic_from_profiles(dom, args.workload)
-    roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                "bytes_per_launch": ab[dom], "launch_ms": round(kernels[dom]["ms"], 5)}
-    copy = None
-    if args.copy_mb > 0:
-        n = args.copy_mb * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(2):
-            sip.stream_copy(dst, src)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        reps = 10
-        for _ in range(reps):
-            sip.stream_copy(dst, src)
-        e1.record()
-        torch.cuda.synchronize()
-        t = e0.elapsed_time(e1) / reps
-        copy = {"bytes_moved": 2 * n * 4, "ms": round(t, 4), "GBs": round(2 * n * 4 / (t * 1e-3) / 1e9, 1)}
-        del src, dst
-    cpu = None
-    check = None
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(dom, wname), "kernel": dom,
+            "bytes_per_launch": kernels[dom]["bytes"], "launch_ms": round(kernels[dom]["ms"], 5)}
+
+
+def iteration_roofline(insts, field, iters, ms_step):
+    esz = 8 if field == "f64" else 4
+    words = iteration_words(insts)
+    t = ms_step * 1e-3 / iters
+    gbs = words * esz / t / 1e9
+    return {"bytes": words * esz, "ms": round(1e3 * t, 5), "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def c3_leg(args):
+    """The 200x200x100 grid (box, TV ball, lateral slopes): whole-iteration
+    figures of the single instance that streams from HBM."""
+    insts, field, iters, desc = load_workload("smooth3d", args)
+    say("200x200x100: autotune and timing")
+    run = run_timed(insts, field, iters, args, args.c3_steps, 1)
+    kernels = kernel_table(run, insts, field, max(5, args.reps // 3))
+    out = {"workload": desc, "grid_points": run["n_pts"], "iterations": iters, "steps": args.c3_steps,
+           "ms_per_step": round(run["ms_step"], 3), "value": round(run["value"], 1),
+           "tiles": list(run["tiles"]) if run["tiles"] else "default",
+           "iteration": iteration_roofline(insts, field, iters, run["ms_step"]),
+           "roofline": roofline_of(kernels, "smooth3d"),
+           "kernels": {k: {"ms": round(v["ms"], 5), "GBs": round(v["GBs"], 1)} for k, v in kernels.items()}}
+    run["batch"].close()
+    return out
+
+
+def served_leg(args):
+    """The served mix (Poisson arrivals, 5% 3D, stopping rule on, continuous
+    batching) and the plain one-at-a-time form on the same requests."""
+    from paper_1902_09699_amd import serve
+    opts = serve.serving_opts(200)
+    arena = 64 << 30
+    n, rate = args.served_requests, args.served_rate
+    say(f"served: {n} requests at {rate:g} req/s")
+    warm = serve.make_requests(4, 1e9, 0.0, seed0=9000, max2d=128)
+    srv = serve.Server(opts, arena, 256, 10)
+    srv.run(warm, realtime=False)
+    reqs = serve.make_requests(n, rate)
+    info = srv.run(reqs, realtime=True)
+    srv.close()
+    served = serve.summary(reqs, "served")
+    served.update(info)
+    say("plain: the same requests one at a time")
+    plain_reqs = serve.make_requests(n, rate)
+    pinfo = serve.serve_plain(plain_reqs, opts, arena, 10)
+    plain = serve.summary(plain_reqs, "plain")
+    plain.update(pinfo)
+    offered = sum(r.m.size for r in reqs) / max(reqs[-1].arrival - reqs[0].arrival, 1e-9)
+    return {"requests": n, "rate_per_s": rate, "frac_3d": 0.05, "offered_grid_pts_per_s": round(offered, 1),
+            "stopping": "eqs. feas_stop/obj_stop every 5 it, cap 200, CG cap 10 at 0.1 relative residual",
+            "served": served, "plain": plain,
+            "speedup_instances_per_s": round(served["instances_per_s"] / max(plain["instances_per_s"], 1e-9), 2)}
+
+
+def copy_reference(mb):
+    import torch
+    from paper_1902_09699_amd import sip
+    n = mb * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        sip.stream_copy(dst, src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 10
+    for _ in range(reps):
+        sip.stream_copy(dst, src)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps
+    return {"bytes_moved": 2 * n * 4, "ms": round(t, 4), "GBs": round(2 * n * 4 / (t * 1e-3) / 1e9, 1)}
+
+
+def device_logged(inst, field, reduce, tiles, iters):
+    """One instance alone on the device (tiles and CG form as timed; results
+    are bit-identical alone and in a batch), one iteration at a time: its x,
+    the (rho, gamma) of every iteration and the rows every whole-vector
+    cardinality set kept (operator row order)."""
+    import torch
+    from paper_1902_09699_amd import sip
+    m, sets = inst
+    opts = sip.make_opts(field, reduce=reduce, max_iter=iters, cg_max=10, cg_fixed=1)
+    md = torch.tensor(m, dtype=torch.float64 if field == "f64" else torch.float32, device="cuda")
+    xd = torch.empty_like(md)
+    b = sip.Batch(1, sip.workspace_bytes(m.shape, sets, opts), opts)
+    if tiles:
+        b.set_tiles(*tiles)
+    slot = b.add(md, sets, xd)
+    card = [i for i, s in enumerate(sets) if s["kind"] == "card" and s.get("line") is None]
+    sched, sup = {}, {}
+    for _ in range(iters):
+        rho, gam, k, _ = b.get_params(slot)
+        b.run(1)
+        sched[k] = (rho.copy(), gam.copy())
+        if card:
+            sup[k] = {i: np.nonzero(b.rows(slot, sip.FIELD_Y, i, m.shape, sets[i]["op"]))[0] for i in card}
+    torch.cuda.synchronize()
+    x = xd.double().cpu().numpy()
+    b.close()
+    return x, sched, sup
+
+
+# ------------------------------------------------------------------ CPU leg
+
+def host_info():
+    info = {"logical_cpus": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS"),
+            "OPENBLAS_NUM_THREADS": os.environ.get("OPENBLAS_NUM_THREADS")}
+    model, cores = None, set()
+    try:
+        phys = None
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "model name" and model is None:
+                    model = v
+                elif k == "physical id":
+                    phys = v
+                elif k == "core id":
+                    cores.add((phys, v))
+    except OSError:
+        pass
+    info["model"] = model
+    info["physical_cores"] = len(cores) or None
+    return info
+
+
+def cpu_baseline(insts, iters_full, budget_s):
+    """The FP64 oracle as it stands, free-running, on instances of the
+    workload in order, each from its second iteration on, until the budget
+    is spent (at least two iterations)."""
+    from oracle import parsdmm as orc
+    pts_iters, done_desc = 0, []
+    wall = cpu = 0.0
+    for j, (m, sets) in enumerate(insts):
+        prob = orc.Problem(m, m.shape, sets)
+        opts = orc.Options(max_iter=iters_full, cg_max=10, cg_fixed=True)
+        st = orc.initial_state(prob, opts)
+        orc.iterate(prob, st, opts)  # first iteration untimed (x = m)
+        ru0 = resource.getrusage(resource.RUSAGE_SELF)
+        t0 = time.perf_counter()
+        n = 0
+        while st.k <= iters_full and (n < 2 or wall + time.perf_counter() - t0 < budget_s):
+            orc.iterate(prob, st, opts)
+            n += 1
+        dt = time.perf_counter() - t0
+        ru1 = resource.getrusage(resource.RUSAGE_SELF)
+        wall += dt
+        cpu += (ru1.ru_utime - ru0.ru_utime) + (ru1.ru_stime - ru0.ru_stime)
+        pts_iters += m.size * n
+        done_desc.append(f"#{j} {'x'.join(map(str, m.shape))} it 2..{n + 1}")
+        if wall >= budget_s:
+            break
+    threads = max(1, int(round(cpu / wall)))
+    return {"value": round(pts_iters / wall, 1), "unit": "grid-pts*iters/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 CSR oracle, free-running, fixed 10 CG steps: {'; '.join(done_desc)} "
+                      f"({wall:.1f} s wall, {cpu:.1f} s CPU)",
+            "host": host_info()}
+
+
+def pick_sample(insts, count):
+    """Indices of up to `count` instances covering every set kind present
+    (TV ball, l1 on D_z, cardinality, box), first occurrences first."""
+    want = [("l1", "GRAD"), ("l1", "DZ"), ("card", None), ("bounds", None)]
+    pick = []
+    for kind, op in want:
+        for j, (_, sets) in enumerate(insts):
+            if j in pick:
+                continue
+            if any(s["kind"] == kind and (op is None or s["op"] == op) for s in sets):
+                pick.append(j)
+                break
+    for j in range(len(insts)):
+        if len(pick) >= count:
+            break
+        if j not in pick:
+            pick.append(j)
+    return sorted(pick[:count])
+
+
+def oracle_errors(insts, field, reduce, tiles, iters, count):
+    """Relative L2 error of x after `iters` iterations for a sample of
+    instances; the oracle replays each device run's (rho, gamma) schedule
+    and, for cardinality sets, its kept rows, each checked to be a valid
+    top-k choice of the oracle's own w within CARD_BAND of the k-th
+    magnitude (equal choices within the band are ties)."""
+    from oracle import parsdmm as orc
+    out = []
+    for j in pick_sample(insts, count):
+        m, sets = insts[j]
+        x, sched, sup = device_logged(insts[j], field, reduce, tiles, iters)
+        prob = orc.Problem(m, m.shape, sets)
+        oo = orc.Options(max_iter=iters, cg_max=10, cg_fixed=True)
+        st = orc.initial_state(prob, oo)
+        valid, differ, worst = True, 0, 0.0
+        card = [i for i, s in enumerate(sets) if s["kind"] == "card" and s.get("line") is None]
+        while st.k <= iters:
+            k = st.k
+            orc.iterate(prob, st, oo, sched, sup or None)
+            for i in card:
+                a = np.abs(st.w_last[i])
+                kk = sets[i]["k"]
+                tk = np.partition(a, a.size - kk)[a.size - kk]
+                keep = sup[k][i]
+                drop = np.ones(a.size, bool)
+                drop[keep] = False
+                valid &= keep.size <= kk and bool(np.all(a[keep] >= tk * (1 - CARD_BAND))) and \
+                    bool(np.all(a[drop] <= tk * (1 + CARD_BAND)))
+                diff = np.setxor1d(orc.card_support(st.w_last[i], kk), keep)
+                differ += int(diff.size)
+                if diff.size:
+                    worst = max(worst, float(np.max(np.abs(a[diff] - tk)) / max(tk, 1e-300)))
+        xo = st.x
+        err = float(np.linalg.norm(x.ravel() - xo) / max(np.linalg.norm(xo), 1e-300))
+        out.append({"instance": j, "shape": list(m.shape), "sets": [f"{s['kind']}({s['op']})" for s in sets],
+                    "iterations": iters, "rel_l2_x": err,
+                    **({"card_supports_valid": bool(valid), "card_rows_differing_from_oracle_choice": differ,
+                        "card_max_rel_distance_from_tk": worst} if card else {})})
+    return out
+
+
+# -------------------------------------------------------------------- main
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the library has no multi-GPU path; "
+              f"independent instances would be routed to GPUs by free memory, which is not built",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch  # noqa: F401
+
+    insts, field, iters, desc = load_workload(args.workload, args)
+    say(f"workload {args.workload}: {len(insts)} instance(s), {sum(m.size for m, _ in insts)} points")
+    run = run_timed(insts, field, iters, args, args.steps, args.warmup, args.tiles, not args.no_autotune)
+    say(f"timed {args.steps} steps: {run['ms_step']:.3f} ms/step")
+    kernels = kernel_table(run, insts, field, args.reps)
+    roofline = roofline_of(kernels, args.workload)
+    tiles = run["tiles"]
+    run["batch"].close()
+    copy = copy_reference(args.copy_mb) if args.copy_mb > 0 else None
+
+    extras = args.extras == "on" or (args.extras == "auto" and args.workload == "batched")
+    c3 = served = None
+    if extras:
+        c3 = c3_leg(args)
+        say(f"200x200x100: {c3['ms_per_step']:.3f} ms/step, iteration {c3['iteration']['frac']:.3f} of HBM peak")
+        served = served_leg(args)
+        say(f"served p50 {served['served']['p50_ms']} ms p99 {served['served']['p99_ms']} ms; "
+            f"plain p50 {served['plain']['p50_ms']} ms p99 {served['plain']['p99_ms']} ms")
+
+    cpu = errors = None
     if args.cpu_seconds > 0:
-        sched, chk = None, None
-        kc = min(args.check_iters, iters)
-        if kc > 0:
-            xr, sched = device_reference(insts[0], field, args.reduce, kc, tiles)
-            chk = (kc, xr)
-        cpu, err = cpu_baseline(insts, iters, args.cpu_seconds, sched, chk)
-        if chk is not None:
-            check = {"iterations": kc, "rel_l2_x": err, "instance": "first",
-                     "oracle": "FP64, replaying the device (rho, gamma) schedule",
-                     "oracle_sensitivity": oracle_sensitivity(insts[0], kc, sched, field)}
+        say(f"CPU oracle: {args.cpu_seconds:g} s timing budget")
+        cpu = cpu_baseline(insts, iters, args.cpu_seconds)
+        if args.check_iters > 0:
+            say(f"oracle errors: {args.check_instances} instance(s), {args.check_iters} iterations")
+            errors = oracle_errors(insts, field, args.reduce, tiles, min(args.check_iters, iters),
+                                   args.check_instances)
+
     line = {
-        "metric": "PARSDMM grid-pts*iters/s",
-        "value": round(value, 1),
+        "metric": METRIC,
+        "value": round(run["value"], 1),
         "unit": "grid-pts*iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 3),
+        "ms_per_step": round(run["ms_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": field,
         "data": "synthetic (seeded generators)",
-        "config": {"workload": desc, "instances": len(insts), "grid_points": n_pts, "iterations": iters,
+        "config": {"workload": desc, "instances": len(insts), "grid_points": run["n_pts"], "iterations": iters,
                    "cg_steps": 10, "reductions": args.reduce, "tiles": list(tiles) if tiles else "default"},
         "roofline": roofline,
+        "iteration": iteration_roofline(insts, field, iters, run["ms_step"]),
         "kernels": {k: {"ms": round(v["ms"], 5), "GBs": round(v["GBs"], 1)} for k, v in kernels.items()},
         "cpu_baseline": cpu,
-        "oracle_error": check,
+        "oracle_error": errors,
         "copy_reference": copy,
     }
-    if args.workload == "batched":
-        line["instances_per_s"] = round(len(insts) * args.steps / wall, 2)
+    if len(insts) > 1:
+        line["instances_per_s"] = round(len(insts) * args.steps / run["wall"], 2)
+    if c3 is not None:
+        line["smooth3d_200x200x100"] = c3
+    if served is not None:
+        line["served"] = served
     print(json.dumps(line), flush=True)
-    batch.close()
 
 
 if __name__ == "__main__":

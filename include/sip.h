@@ -47,7 +47,7 @@ typedef enum {
   SIP_EHIP = -3,         /* a HIP runtime call failed */
   SIP_ENUMERIC = -4,     /* non-finite input/iterate or CG breakdown (p^T C p <= 0) */
   SIP_EUNSUPPORTED = -5, /* combination the library does not implement */
-  SIP_EBUDGET = -6       /* batch: no free slot or not enough arena memory */
+  SIP_EBUDGET = -6       /* batch: no free slot or not enough arena memory; plan: workspace too small */
 } sip_status;
 
 typedef enum { SIP_F32 = 0, SIP_F64 = 1 } sip_dtype;
@@ -191,8 +191,12 @@ int32_t sip_project_batched(int32_t B, const sip_grid* grids, const sip_set* set
 /* ---- resident batches (the served form and step-level control) ---------- */
 
 /* A batch holds up to max_slots instances whose state stays on the device in
- * an arena of arena_bytes (one allocation made here; admission never
- * allocates again).  All instances share the options and field type. */
+ * an arena of arena_bytes (one allocation made here, from which admission
+ * carves every instance's state).  The work tables and per-item partial-sum
+ * buffers are sized to the admitted instances: the first sip_batch_run after
+ * an admission or removal that outgrows their capacity (capacities double)
+ * reallocates them, after waiting for the stream.  All instances share the
+ * options and field type. */
 int32_t sip_batch_create(sip_batch** out, int32_t max_slots, int64_t arena_bytes,
                          const sip_opts* o);
 int32_t sip_batch_destroy(sip_batch* b);
@@ -352,6 +356,75 @@ int32_t sip_project_multilevel(const sip_grid* g, const sip_set* sets, int32_t n
  * another field. */
 int32_t sip_dykstra_update(int32_t p, const void* const* y, void* const* v, const double* w, void* x, int64_t n,
                            int32_t field, void* stream);
+
+/* ------------------------------------------------------------------ plans
+ * The paper's set-up-once / project-many sequence (section "Software and
+ * numerical examples": the constraint set-up and precomputation are done
+ * once and reused) for one grid and set list: a plan precomputes the
+ * operator descriptors, the state layout and the work tables at creation,
+ * captures the iteration graphs at its first run and reuses all of them for
+ * every later model m.  Not thread-safe; one plan per stream at a time. */
+
+typedef struct sip_plan sip_plan;
+
+/* Work decomposition of a plan (the tiles of sip_batch_set_tiles). */
+typedef struct {
+  int32_t pt_points, pt_max_items;   /* grid points per item of the RHS, CG and projection kernels; item cap */
+  int32_t thr_points, thr_max_items; /* the same for the threshold-set kernels */
+  int32_t pt_threads;                /* 256 or 512 */
+  int32_t cg_form;                   /* 0 textbook CG, 1 one-reduction CG */
+} sip_tiles;
+
+/* Fill *t with the default tiles (2048/512, 2048/512, 512 threads, form 0). */
+int32_t sip_tiles_default(sip_tiles* t);
+
+/* Exact device bytes a plan needs for (grid, sets, options, tiles) when it
+ * takes its memory from a caller workspace: descriptor, scalars, the
+ * instance's state and the work tables; tiles NULL = defaults.  -1 when the
+ * arguments are invalid. */
+int64_t sip_plan_bytes(const sip_grid* g, const sip_set* sets, int32_t nsets, const sip_opts* o,
+                       const sip_tiles* tiles);
+
+/* Create a plan.  workspace NULL: the library allocates its device memory;
+ * otherwise every device buffer of the plan is carved from the caller's
+ * block [workspace, workspace + workspace_bytes) (256-byte aligned, at
+ * least sip_plan_bytes, owned by the caller and left alone until
+ * sip_plan_destroy).  Per-row bound vectors of the sets are copied into the
+ * plan here.  SIP_EINVAL for bad arguments or an unaligned workspace,
+ * SIP_EBUDGET for a workspace smaller than sip_plan_bytes. */
+int32_t sip_plan_create(sip_plan** out, const sip_grid* g, const sip_set* sets, int32_t nsets, const sip_opts* o,
+                        const sip_tiles* tiles, void* workspace, int64_t workspace_bytes, void* stream);
+int32_t sip_plan_destroy(sip_plan* p);
+
+/* One blocking projection of m_dev with the plan (the PARSDMM listing, as
+ * sip_project): x_dev (N field elements, may equal m_dev) receives the
+ * result; *res (may be NULL) the result record.  Returns the status. */
+int32_t sip_plan_project(sip_plan* p, const void* m_dev, void* x_dev, sip_result* res, void* stream);
+
+/* Step-level control: sip_plan_start restarts the plan's state from m_dev
+ * (x = m, y_i = A_i m, v_i = 0, rho0, gamma0, k = 1; waits for the stream)
+ * with the iterate kept in x_dev; sip_plan_iterate enqueues up to `iters`
+ * more iterations (fewer when the stopping test or max_iter ends the run);
+ * sip_plan_result waits for the stream and reads the result record. */
+int32_t sip_plan_start(sip_plan* p, const void* m_dev, void* x_dev, void* stream);
+int32_t sip_plan_iterate(sip_plan* p, int32_t iters, void* stream);
+int32_t sip_plan_result(sip_plan* p, sip_result* res, void* stream);
+
+/* The whole iteration state of a started plan, for the listing's optional
+ * initial guess of x, y_i and v_i (PARSDMM listing, input line): the
+ * iterate x, every y_i and v_i (identity block included), rho_i, gamma_i,
+ * the iteration counter, the adapt-rho-gamma snapshots, the x history of
+ * the stopping test, the selection state and the schedule log, behind a
+ * header naming the layout.  sip_state_bytes: size of the blob;
+ * sip_state_export copies it into dst_dev (device memory of that size;
+ * waits for the stream); sip_state_import overwrites the plan's state from
+ * a blob exported by a plan of the same grid, set kinds and operators and
+ * options (SIP_EINVAL otherwise, or before sip_plan_start), asynchronously
+ * on `stream`.  Iterating after an import continues exactly as the
+ * exporting plan would have. */
+int64_t sip_state_bytes(const sip_plan* p);
+int32_t sip_state_export(sip_plan* p, void* dst_dev, void* stream);
+int32_t sip_state_import(sip_plan* p, const void* src_dev, void* stream);
 
 #ifdef __cplusplus
 }

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <new>
 #include <vector>
@@ -47,18 +48,28 @@ inline int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; 
 
 // ---------------------------------------------------------------- arena
 
-// First-fit allocator over one device allocation; admission never calls the
-// HIP allocator.
+// First-fit allocator over one device block (the batch's own allocation, or
+// a borrowed block that it never frees); admission never calls the HIP
+// allocator.
 class Arena {
  public:
   bool init(int64_t bytes) {
     if (bytes <= 0) return false;
     if (hipMalloc(&base_, (size_t)bytes) != hipSuccess) { base_ = nullptr; return false; }
+    owned_ = true;
     size_ = bytes;
     free_[0] = bytes;
     return true;
   }
-  ~Arena() { if (base_) (void)hipFree(base_); }
+  bool borrow(char* base, int64_t bytes) {
+    if (bytes <= 0 || !base) return false;
+    base_ = base;
+    owned_ = false;
+    size_ = bytes;
+    free_[0] = bytes;
+    return true;
+  }
+  ~Arena() { if (base_ && owned_) (void)hipFree(base_); }
   char* alloc(int64_t bytes) {
     bytes = align_up(bytes);
     for (auto it = free_.begin(); it != free_.end(); ++it) {
@@ -90,6 +101,7 @@ class Arena {
 
  private:
   char* base_ = nullptr;
+  bool owned_ = false;
   int64_t size_ = 0;
   std::map<int64_t, int64_t> free_, used_;
 };
@@ -322,6 +334,19 @@ struct sip_batch {
   int32_t live[4] = {0, 0, 0, 0};  // point, threshold, selection, instance items of the tables
   std::map<int, hipGraphExec_t> graphs;
   sip::TileCfg tiles;
+  // Fixed-memory mode (a plan over a caller workspace, the allocation-free
+  // entry point): every device buffer is carved once from
+  // [fixed, fixed + fixed_size) and never freed.
+  char* fixed = nullptr;
+  int64_t fixed_size = 0, fixed_used = 0;
+  bool no_graph = false;  // launch the iterations directly (no capture, no graph objects)
+  bool pinned = true;     // h_scal from hipHostMalloc (else plain host memory)
+};
+
+struct sip_plan {
+  sip_batch* b = nullptr;
+  int32_t slot = 0;
+  bool started = false;  // an m and x were given (sip_plan_start / sip_plan_project)
 };
 
 namespace sip {
@@ -332,12 +357,40 @@ namespace {
     if ((expr) != hipSuccess) return SIP_EHIP;        \
   } while (0)
 
+// Device memory of a batch: the HIP allocator, or in fixed-memory mode the
+// next 256-byte aligned piece of the fixed block (SIP_EBUDGET when it is
+// used up; pieces are never returned).
+int32_t dev_alloc(sip_batch* b, void** p, int64_t bytes) {
+  *p = nullptr;
+  if (b->fixed) {
+    const int64_t need = align_up(std::max<int64_t>(bytes, 1));
+    if (b->fixed_used + need > b->fixed_size) return SIP_EBUDGET;
+    *p = b->fixed + b->fixed_used;
+    b->fixed_used += need;
+    return SIP_OK;
+  }
+  HIP_OK(hipMalloc(p, (size_t)std::max<int64_t>(bytes, 1)));
+  return SIP_OK;
+}
+
+int32_t dev_free(sip_batch* b, void* p) {
+  if (!p || b->fixed) return SIP_OK;
+  HIP_OK(hipFree(p));
+  return SIP_OK;
+}
+
+// Capacity-managed device table: grows by doubling (fixed-memory mode: to
+// exactly `need`, carved once per growth).
 template <typename P>
-int32_t ensure(P*& ptr, int& cap, int need, size_t elem_bytes) {
+int32_t ensure(sip_batch* b, P*& ptr, int& cap, int need, size_t elem_bytes) {
   if (need <= cap && ptr) return SIP_OK;
-  int nc = std::max(need, std::max(64, cap * 2));
-  if (ptr) { HIP_OK(hipFree(ptr)); ptr = nullptr; }
-  HIP_OK(hipMalloc((void**)&ptr, (size_t)nc * elem_bytes));
+  int nc = b->fixed ? need : std::max(need, std::max(64, cap * 2));
+  int32_t rc;
+  if ((rc = dev_free(b, ptr))) return rc;
+  ptr = nullptr;
+  void* q = nullptr;
+  if ((rc = dev_alloc(b, &q, (int64_t)nc * (int64_t)elem_bytes))) { cap = 0; return rc; }
+  ptr = (P*)q;
   cap = nc;
   return SIP_OK;
 }
@@ -375,40 +428,51 @@ void drop_graphs(sip_batch* b) {
   b->graphs.clear();
 }
 
-int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
+// Host form of a batch's work tables, in logical order, with their launch
+// sizes (powers of two: a captured graph stays valid while the live items
+// change below them; the rest of a launch is sentinel entries).
+struct HostTables {
   std::vector<PtItem> pt, sp;
   std::vector<ThrItem> thr;
   std::vector<SelItem> sel;
   std::vector<LineItem> line;
   std::vector<int32_t> inst;
-  for (int si = 0; si < b->max_slots; ++si) {
-    Slot& s = b->slots[si];
+  int lpt = 0, lsp = 0, lthr = 0, lsel = 0, linst = 0, lline = 0;
+};
+
+// The work tables of the used slots; fills each slot's item ranges.
+void build_host_tables(std::vector<Slot>& slots, const TileCfg& tiles, const sip_opts& o, HostTables& h) {
+  for (int si = 0; si < (int)slots.size(); ++si) {
+    Slot& s = slots[si];
     if (!s.used) continue;
-    inst.push_back(si);
+    h.inst.push_back(si);
     const int N = (int)s.N;
-    const int64_t tp = tile_points(N, b->tiles.pt_base, b->tiles.pt_max_items);
-    s.desc.pt_begin = (int)pt.size();
-    for (int64_t p0 = 0; p0 < N; p0 += tp) pt.push_back(PtItem{si, (int)p0, (int)std::min<int64_t>(tp, N - p0), 0});
-    s.desc.pt_end = (int)pt.size();
-    const int64_t tt = tile_points(N, b->tiles.thr_base, b->tiles.thr_max_items);
-    s.desc.sp_begin = (int)sp.size();
-    for (int64_t p0 = 0; p0 < N; p0 += tt) sp.push_back(PtItem{si, (int)p0, (int)std::min<int64_t>(tt, N - p0), 0});
-    s.desc.sp_end = (int)sp.size();
+    const int64_t tp = tile_points(N, tiles.pt_base, tiles.pt_max_items);
+    s.desc.pt_begin = (int)h.pt.size();
+    for (int64_t p0 = 0; p0 < N; p0 += tp)
+      h.pt.push_back(PtItem{si, (int)p0, (int)std::min<int64_t>(tp, N - p0), 0});
+    s.desc.pt_end = (int)h.pt.size();
+    const int64_t tt = tile_points(N, tiles.thr_base, tiles.thr_max_items);
+    s.desc.sp_begin = (int)h.sp.size();
+    for (int64_t p0 = 0; p0 < N; p0 += tt)
+      h.sp.push_back(PtItem{si, (int)p0, (int)std::min<int64_t>(tt, N - p0), 0});
+    s.desc.sp_end = (int)h.sp.size();
     for (int k = 0; k < s.nsets; ++k) {
       SetDesc& sd = s.desc.sets[k];
       if (sd.thr < 0) continue;
-      for (int src = 0; src < (b->opts.stop_every > 0 ? 2 : 1); ++src) {
-        sel.push_back(SelItem{si, k, src, 0});
-        sd.item_begin[src] = (int)thr.size();
+      for (int src = 0; src < (o.stop_every > 0 ? 2 : 1); ++src) {
+        h.sel.push_back(SelItem{si, k, src, 0});
+        sd.item_begin[src] = (int)h.thr.size();
         for (int64_t p0 = 0; p0 < N; p0 += tt)
-          thr.push_back(ThrItem{si, k, src, 0, (int)p0, (int)std::min<int64_t>(tt, N - p0), 0, (int)sel.size() - 1});
-        sd.item_end[src] = (int)thr.size();
+          h.thr.push_back(ThrItem{si, k, src, 0, (int)p0, (int)std::min<int64_t>(tt, N - p0), 0,
+                                  (int)h.sel.size() - 1});
+        sd.item_end[src] = (int)h.thr.size();
       }
     }
     for (int k = 0; k < s.nsets; ++k) {
       SetDesc& sd = s.desc.sets[k];
       if (sd.line_axis < 0) continue;
-      sd.line_begin = (int)line.size();
+      sd.line_begin = (int)h.line.size();
       const int la = sd.line_axis;
       for (int c = 0; c < sd.ncomp; ++c) {
         int64_t dims[3] = {s.desc.n[0], s.desc.n[1], s.desc.n[2]};
@@ -418,73 +482,100 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
         for (int64_t i0 = 0; i0 < e0; ++i0)
           for (int64_t i1 = 0; i1 < e1; ++i1)
             for (int64_t i2 = 0; i2 < e2; ++i2)
-              line.push_back(LineItem{si, k, c, (int)dims[la],
-                                      (int)(i0 * s.desc.stride[0] + i1 * s.desc.stride[1] + i2),
-                                      (int)s.desc.stride[la], 0, 0});
+              h.line.push_back(LineItem{si, k, c, (int)dims[la],
+                                        (int)(i0 * s.desc.stride[0] + i1 * s.desc.stride[1] + i2),
+                                        (int)s.desc.stride[la], 0, 0});
       }
-      sd.line_end = (int)line.size();
+      sd.line_end = (int)h.line.size();
     }
   }
+  auto pow2 = [](int n, int lo) { if (n <= 0) return 0; int c = lo; while (c < n) c <<= 1; return c; };
+  h.lpt = pow2((int)h.pt.size(), 64);
+  h.lthr = pow2((int)h.thr.size(), 64);
+  h.lsel = pow2((int)h.sel.size(), 8);
+  h.linst = pow2((int)h.inst.size(), 8);
+  h.lsp = pow2((int)h.sp.size(), 64);
+  h.lline = pow2((int)h.line.size(), 64);
+}
+
+// Device bytes of the work tables and partial-sum buffers at exactly the
+// launch sizes of h: what fixed-memory mode carves, in rebuild_tables' order.
+int64_t table_bytes(const HostTables& h) {
+  auto A = [](int64_t b) { return align_up(std::max<int64_t>(b, 1)); };
+  const int64_t pt = std::max(h.lpt, 1), sp = std::max(h.lsp, 1), thr = std::max(h.lthr, 1);
+  const int64_t sel = std::max(h.lsel, 1), inst = std::max(h.linst, 1), line = std::max(h.lline, 1);
+  return A(pt * (int64_t)sizeof(PtItem)) + A(sp * (int64_t)sizeof(PtItem)) + A(thr * (int64_t)sizeof(ThrItem)) +
+         A(sel * (int64_t)sizeof(SelItem)) + A(inst * 4) + A(line * (int64_t)sizeof(LineItem)) + A(line * 64) +
+         4 * A(pt * 8) + A(sp * kProjParts * 8) + A(sel * kNB * 4) + A(sel * kNB * 8) +
+         2 * A(thr * kThrParts * 8) + A(thr * 12);
+}
+
+int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
+  HostTables h;
+  build_host_tables(b->slots, b->tiles, b->opts, h);
+  const std::vector<PtItem>& pt = h.pt;
+  const std::vector<ThrItem>& thr = h.thr;
+  const std::vector<SelItem>& sel = h.sel;
+  const std::vector<LineItem>& line = h.line;
+  const std::vector<int32_t>& inst = h.inst;
   // nothing queued may still read the tables or partial buffers replaced below
   HIP_OK(hipStreamSynchronize(stream));
-  // launch sizes are capacities (powers of two): a captured graph stays valid
-  // while the live items change below them (the rest of a table is sentinels)
-  auto pow2 = [](int n, int lo) { if (n <= 0) return 0; int c = lo; while (c < n) c <<= 1; return c; };
-  const int lpt = pow2((int)pt.size(), 64), lthr = pow2((int)thr.size(), 64);
-  const int lsel = pow2((int)sel.size(), 8), linst = pow2((int)inst.size(), 8);
-  const int lsp = pow2((int)sp.size(), 64);
-  const int lline = pow2((int)line.size(), 64);
+  const int lpt = h.lpt, lthr = h.lthr, lsel = h.lsel, linst = h.linst, lsp = h.lsp, lline = h.lline;
   const bool relaunch = lpt != b->tab.npt || lthr != b->tab.nthr || lsel != b->tab.nsel || linst != b->tab.ninst ||
                         lsp != b->tab.nsp || lline != b->tab.nline;
   int32_t rc;
   const int old_pt = b->cap_pt, old_thr = b->cap_thr, old_sel = b->cap_sel, old_inst = b->cap_inst;
   const int old_sp = b->cap_sp, old_line = b->cap_line;
-  if ((rc = ensure(b->d_pt, b->cap_pt, std::max(lpt, 1), sizeof(PtItem)))) return rc;
-  if ((rc = ensure(b->d_sp, b->cap_sp, std::max(lsp, 1), sizeof(PtItem)))) return rc;
-  if ((rc = ensure(b->d_thr, b->cap_thr, std::max(lthr, 1), sizeof(ThrItem)))) return rc;
-  if ((rc = ensure(b->d_sel, b->cap_sel, std::max(lsel, 1), sizeof(SelItem)))) return rc;
-  if ((rc = ensure(b->d_inst, b->cap_inst, std::max(linst, 1), sizeof(int32_t)))) return rc;
-  if ((rc = ensure(b->d_line, b->cap_line, std::max(lline, 1), sizeof(LineItem)))) return rc;
+  if ((rc = ensure(b, b->d_pt, b->cap_pt, std::max(lpt, 1), sizeof(PtItem)))) return rc;
+  if ((rc = ensure(b, b->d_sp, b->cap_sp, std::max(lsp, 1), sizeof(PtItem)))) return rc;
+  if ((rc = ensure(b, b->d_thr, b->cap_thr, std::max(lthr, 1), sizeof(ThrItem)))) return rc;
+  if ((rc = ensure(b, b->d_sel, b->cap_sel, std::max(lsel, 1), sizeof(SelItem)))) return rc;
+  if ((rc = ensure(b, b->d_inst, b->cap_inst, std::max(linst, 1), sizeof(int32_t)))) return rc;
+  if ((rc = ensure(b, b->d_line, b->cap_line, std::max(lline, 1), sizeof(LineItem)))) return rc;
   bool moved = old_pt != b->cap_pt || old_thr != b->cap_thr || old_sel != b->cap_sel || old_inst != b->cap_inst ||
                old_sp != b->cap_sp || old_line != b->cap_line;
+  auto regrow = [&](std::initializer_list<void**> ptrs, int64_t bytes) -> int32_t {
+    for (void** q : ptrs) {
+      int32_t r;
+      if ((r = dev_free(b, *q))) return r;
+      *q = nullptr;
+    }
+    for (void** q : ptrs) {
+      int32_t r;
+      if ((r = dev_alloc(b, q, bytes))) return r;
+    }
+    return SIP_OK;
+  };
   if (b->cap_plinep < b->cap_line) {
-    if (b->d_linep) HIP_OK(hipFree(b->d_linep));
-    HIP_OK(hipMalloc((void**)&b->d_linep, (size_t)b->cap_line * 8 * 8));
+    if ((rc = regrow({(void**)&b->d_linep}, (int64_t)b->cap_line * 8 * 8))) return rc;
     b->cap_plinep = b->cap_line;
     moved = true;
   }
   if (b->cap_ppt < b->cap_pt) {
-    if (b->d_rr) {
-      HIP_OK(hipFree(b->d_rr)); HIP_OK(hipFree(b->d_pq));
-      HIP_OK(hipFree(b->d_rr2)); HIP_OK(hipFree(b->d_pq2));
-    }
-    HIP_OK(hipMalloc((void**)&b->d_rr, (size_t)b->cap_pt * 8));
-    HIP_OK(hipMalloc((void**)&b->d_pq, (size_t)b->cap_pt * 8));
-    HIP_OK(hipMalloc((void**)&b->d_rr2, (size_t)b->cap_pt * 8));
-    HIP_OK(hipMalloc((void**)&b->d_pq2, (size_t)b->cap_pt * 8));
+    if ((rc = regrow({(void**)&b->d_rr, (void**)&b->d_pq, (void**)&b->d_rr2, (void**)&b->d_pq2},
+                     (int64_t)b->cap_pt * 8)))
+      return rc;
     b->cap_ppt = b->cap_pt;
     moved = true;
   }
   if (b->cap_psp < b->cap_sp) {
-    if (b->d_proj) HIP_OK(hipFree(b->d_proj));
-    HIP_OK(hipMalloc((void**)&b->d_proj, (size_t)b->cap_sp * kProjParts * 8));
+    if ((rc = regrow({(void**)&b->d_proj}, (int64_t)b->cap_sp * kProjParts * 8))) return rc;
     b->cap_psp = b->cap_sp;
     moved = true;
   }
   if (b->cap_h1 < b->cap_sel) {
-    if (b->d_h1c) { HIP_OK(hipFree(b->d_h1c)); HIP_OK(hipFree(b->d_h1s)); }
-    HIP_OK(hipMalloc((void**)&b->d_h1c, (size_t)b->cap_sel * kNB * 4));
-    HIP_OK(hipMalloc((void**)&b->d_h1s, (size_t)b->cap_sel * kNB * 8));
+    if ((rc = regrow({(void**)&b->d_h1c}, (int64_t)b->cap_sel * kNB * 4))) return rc;
+    if ((rc = regrow({(void**)&b->d_h1s}, (int64_t)b->cap_sel * kNB * 8))) return rc;
+    // the refine histograms start at zero (their consumers clear them after use)
     launch_zero(stream, b->d_h1c, (int64_t)b->cap_sel * kNB);
     launch_zero(stream, b->d_h1s, (int64_t)b->cap_sel * kNB);
+    HIP_OK(hipGetLastError());
     b->cap_h1 = b->cap_sel;
     moved = true;
   }
   if (b->cap_pthr < b->cap_thr) {
-    if (b->d_thrw) { HIP_OK(hipFree(b->d_thrw)); HIP_OK(hipFree(b->d_thra)); HIP_OK(hipFree(b->d_tie)); }
-    HIP_OK(hipMalloc((void**)&b->d_thrw, (size_t)b->cap_thr * kThrParts * 8));
-    HIP_OK(hipMalloc((void**)&b->d_thra, (size_t)b->cap_thr * kThrParts * 8));
-    HIP_OK(hipMalloc((void**)&b->d_tie, (size_t)b->cap_thr * 3 * 4));
+    if ((rc = regrow({(void**)&b->d_thrw, (void**)&b->d_thra}, (int64_t)b->cap_thr * kThrParts * 8))) return rc;
+    if ((rc = regrow({(void**)&b->d_tie}, (int64_t)b->cap_thr * 3 * 4))) return rc;
     b->cap_pthr = b->cap_thr;
     moved = true;
   }
@@ -494,7 +585,7 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   b->live[3] = (int32_t)inst.size();
   // every table is written up to its launch size (entries past the live
   // items are sentinels), in launch order
-  const std::vector<PtItem> pt_l = launch_order(pt, lpt, true), sp_l = launch_order(sp, lsp, true);
+  const std::vector<PtItem> pt_l = launch_order(pt, lpt, true), sp_l = launch_order(h.sp, lsp, true);
   const std::vector<ThrItem> thr_l = launch_order(thr, lthr, true);
   const std::vector<LineItem> line_l = launch_order(line, lline, true);
   std::vector<SelItem> sel_l((size_t)lsel);
@@ -570,15 +661,21 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   return SIP_OK;
 }
 
+// Enqueue `iters` iterations of every kernel on `stream` (for capture, or
+// launched directly).
+void launch_iterations(sip_batch* b, hipStream_t stream, int iters) {
+  for (int i = 0; i < iters; ++i) {
+    if (b->opts.field == SIP_F64) r64::launch_iteration<double>(stream, b->tab, b->kopts);
+    else if (b->opts.reduce == SIP_F32) r32::launch_iteration<float>(stream, b->tab, b->kopts);
+    else r64::launch_iteration<float>(stream, b->tab, b->kopts);
+  }
+}
+
 int32_t get_graph(sip_batch* b, int iters, hipGraphExec_t& out) {
   auto it = b->graphs.find(iters);
   if (it != b->graphs.end()) { out = it->second; return SIP_OK; }
   HIP_OK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-  for (int i = 0; i < iters; ++i) {
-    if (b->opts.field == SIP_F64) r64::launch_iteration<double>(b->cap_stream, b->tab, b->kopts);
-    else if (b->opts.reduce == SIP_F32) r32::launch_iteration<float>(b->cap_stream, b->tab, b->kopts);
-    else r64::launch_iteration<float>(b->cap_stream, b->tab, b->kopts);
-  }
+  launch_iterations(b, b->cap_stream, iters);
   hipGraph_t g = nullptr;
   if (hipStreamEndCapture(b->cap_stream, &g) != hipSuccess || !g) return SIP_EHIP;
   hipGraphExec_t ge = nullptr;
@@ -619,6 +716,243 @@ void fill_result(const Slot& s, const double* S, sip_result* r) {
   for (int u = 0; u <= s.nsets; ++u) { r->rho[u] = S[S_RHO + u]; r->gamma[u] = S[S_GAMMA + u]; }
 }
 
+// A batch whose device buffers come from the HIP allocator (mem = null) or
+// are all carved from the block [mem, mem + mem_bytes) (fixed-memory mode:
+// descriptors, scalars, the arena, then the work tables at the first run).
+// no_graph: iterations are launched directly and the host mirror of the
+// scalars is plain memory, so the batch makes no HIP allocation at all.
+int32_t create_batch(sip_batch** out, int32_t max_slots, int64_t arena_bytes, const sip_opts* o, char* mem,
+                     int64_t mem_bytes, bool no_graph) {
+  if (!out || !o || max_slots < 1 || arena_bytes <= 0) return SIP_EINVAL;
+  *out = nullptr;
+  sip_opts probe = *o;
+  sip_grid g{}; g.ndim = 2; g.n[0] = 2; g.n[1] = 2; g.h[0] = g.h[1] = 1.0;
+  if (validate(&g, nullptr, 0, &probe) != SIP_OK) return SIP_EINVAL;
+  sip_batch* b = new (std::nothrow) sip_batch();
+  if (!b) return SIP_ENOMEM;
+  b->opts = *o;
+  b->kopts = kernel_opts(*o);
+  b->max_slots = max_slots;
+  b->slots.resize(max_slots);
+  b->fixed = mem;
+  b->fixed_size = mem ? mem_bytes : 0;
+  b->no_graph = no_graph;
+  b->pinned = !no_graph;
+  int32_t rc = SIP_OK;
+  void* q = nullptr;
+  if ((rc = dev_alloc(b, &q, (int64_t)sizeof(InstDesc) * max_slots)) != SIP_OK) { sip_batch_destroy(b); return rc; }
+  b->d_desc = (InstDesc*)q;
+  if ((rc = dev_alloc(b, &q, (int64_t)sizeof(double) * S_COUNT * max_slots)) != SIP_OK) {
+    sip_batch_destroy(b);
+    return rc;
+  }
+  b->d_scal = (double*)q;
+  if (mem) {
+    if ((rc = dev_alloc(b, &q, arena_bytes)) != SIP_OK || !b->arena.borrow((char*)q, align_up(arena_bytes))) {
+      sip_batch_destroy(b);
+      return rc != SIP_OK ? rc : SIP_EINVAL;
+    }
+  } else if (!b->arena.init(arena_bytes)) {
+    sip_batch_destroy(b);
+    return SIP_ENOMEM;
+  }
+  if (!no_graph && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    sip_batch_destroy(b);
+    return SIP_EHIP;
+  }
+  const size_t hbytes = sizeof(double) * S_COUNT * max_slots;
+  if (b->pinned) {
+    if (hipHostMalloc((void**)&b->h_scal, hbytes, 0) != hipSuccess) {
+      b->h_scal = nullptr;
+      sip_batch_destroy(b);
+      return SIP_ENOMEM;
+    }
+  } else {
+    b->h_scal = new (std::nothrow) double[(size_t)S_COUNT * max_slots];
+    if (!b->h_scal) { sip_batch_destroy(b); return SIP_ENOMEM; }
+  }
+  std::memset(b->h_scal, 0, hbytes);
+  if (hipMemcpy(b->d_scal, b->h_scal, hbytes, hipMemcpyHostToDevice) != hipSuccess) {
+    sip_batch_destroy(b);
+    return SIP_EHIP;
+  }
+  *out = b;
+  return SIP_OK;
+}
+
+// A slot's descriptor: grid, sets, operator components, the state arrays
+// of the workspace at ws (null: sizes only) and the iterate x_dev.
+void describe_slot(Slot& s, const sip_grid& g, const sip_set* sets, int nsets, const sip_opts& o, char* ws,
+                   void* x_dev, double* scal) {
+  s.used = true;
+  s.grid = g;
+  s.nsets = nsets;
+  for (int i = 0; i < nsets; ++i) s.sets[i] = sets[i];
+  s.L = layout_of(g, sets, nsets, o);
+  s.ws = ws;
+  s.x = x_dev;
+  int64_t n[3]; double h[3];
+  internal_dims(g, n, h);
+  s.N = n[0] * n[1] * n[2];
+  InstDesc& d = s.desc;
+  std::memset(&d, 0, sizeof(d));
+  d.ndim = g.ndim; d.nsets = nsets; d.active = 1;
+  for (int a = 0; a < 3; ++a) { d.n[a] = n[a]; d.hinv[a] = 1.0 / h[a]; d.h2inv[a] = 1.0 / (h[a] * h[a]); }
+  d.N = s.N;
+  const int64_t esz = o.field == SIP_F64 ? 8 : 4;
+  d.cs = align_up(s.N * esz) / esz;
+  d.stride[2] = 1; d.stride[1] = n[2]; d.stride[0] = n[1] * n[2];
+  d.div_x = make_fastdiv((uint32_t)n[2]);
+  const int64_t grp = 16 / esz;
+  d.vec_ok = ((uintptr_t)x_dev % 16 == 0) ? 1 : 0;
+  d.vec_nb = (n[2] % grp == 0) ? 1 : 0;  // then both row strides (nx, ny*nx) are multiples
+  d.div_y = make_fastdiv((uint32_t)n[1]);
+  const Layout& L = s.L;
+  auto at = [&](int64_t off) -> void* { return (off >= 0 && ws) ? (void*)(ws + off) : nullptr; };
+  d.m = at(L.m); d.x = x_dev; d.r = at(L.r); d.p[0] = at(L.p0); d.p[1] = at(L.p1);
+  for (int i = 0; i < 2; ++i) { d.cr[i] = at(L.cr[i]); d.cp[i] = at(L.cp[i]); }
+  d.xs[0] = at(L.xs0); d.xs[1] = at(L.xs1); d.ring = at(L.ring);
+  d.yl = at(L.yl); d.vl = at(L.vl); d.vh0l = at(L.vh0l); d.v0l = at(L.v0l); d.y0l = at(L.y0l);
+  d.scal = scal;
+  d.log = (double*)at(L.log);
+  d.log_cap = o.log_schedule ? o.max_iter : 0;
+  int nthr = 0;
+  for (int i = 0; i < nsets; ++i) {
+    SetDesc& sd = d.sets[i];
+    OpInfo oi;
+    op_info(g.ndim, sets[i].op, oi);
+    sd.kind = sets[i].kind; sd.op = sets[i].op; sd.ncomp = oi.ncomp;
+    for (int c = 0; c < 3; ++c) sd.axis[c] = c < oi.ncomp ? oi.axis[c] : -1;
+    sd.thr = is_thr(sets[i]) ? nthr++ : -1;
+    sd.line_axis = sets[i].line != SIP_LINE_NONE ? line_axis_of(sets[i].line) : -1;
+    sd.lo = sets[i].lo; sd.hi = sets[i].hi; sd.tau = sets[i].tau; sd.k = sets[i].k;
+    sd.rows = rows_of(g, sets[i]);
+    const auto& SL = L.set[i];
+    sd.y = at(SL.y); sd.v = at(SL.v); sd.vh0 = at(SL.vh0); sd.v0 = at(SL.v0); sd.y0 = at(SL.y0);
+    sd.lov = at(SL.lov); sd.hiv = at(SL.hiv);
+    for (int src = 0; src < 2; ++src) {
+      sd.sel[src] = (SelState*)at(SL.sel[src]);
+      sd.hcnt[src] = (uint32_t*)at(SL.hc[src]);
+      sd.hsum[src] = (double*)at(SL.hs[src]);
+      sd.cand[src] = at(SL.cand[src]);
+    }
+    sd.cand_ix = (uint32_t*)at(SL.cix);
+  }
+}
+
+// Carve slot si's workspace from the arena, describe it and copy the
+// per-row bound vectors into it (waited for, so the caller may release
+// them on return).
+int32_t place_slot(sip_batch* b, int si, const sip_grid& g, const sip_set* sets, int nsets, void* x_dev,
+                   hipStream_t stream) {
+  Slot& s = b->slots[si];
+  s = Slot();
+  const Layout L = layout_of(g, sets, nsets, b->opts);
+  char* ws = b->arena.alloc(L.total);
+  if (!ws) return SIP_EBUDGET;
+  describe_slot(s, g, sets, nsets, b->opts, ws, x_dev, b->d_scal + (size_t)si * S_COUNT);
+  const InstDesc& d = s.desc;
+  const size_t esz = b->opts.field == SIP_F64 ? 8 : 4;
+  bool vec_bounds = false;
+  for (int i = 0; i < nsets; ++i) {
+    const SetDesc& sd = d.sets[i];
+    const void* src[2] = {sets[i].lo_vec, sets[i].hi_vec};
+    void* dst[2] = {sd.lov, sd.hiv};
+    for (int q = 0; q < 2; ++q) {
+      if (!src[q]) continue;
+      vec_bounds = true;
+      HIP_OK(hipMemcpy2DAsync(dst[q], (size_t)d.cs * esz, src[q], (size_t)s.N * esz, (size_t)s.N * esz,
+                              (size_t)sd.ncomp, hipMemcpyDeviceToDevice, stream));
+    }
+  }
+  if (vec_bounds) HIP_OK(hipStreamSynchronize(stream));
+  return SIP_OK;
+}
+
+void initial_scalars(const sip_batch* b, const Slot& s, double* S);
+
+// (Re)start slot si from m_dev: private copy of m, descriptor upload,
+// initial scalars (rho0, gamma0, k = 1) and the init kernel (x = m,
+// y_i = A_i m, v_i = 0, selection state cleared).  Waits for the stream
+// (the host copies read stack memory).
+int32_t start_slot(sip_batch* b, int si, const void* m_dev, hipStream_t stream) {
+  Slot& s = b->slots[si];
+  const size_t esz = b->opts.field == SIP_F64 ? 8 : 4;
+  double S[S_COUNT];
+  initial_scalars(b, s, S);
+  HIP_OK(hipMemcpyAsync(s.desc.m, m_dev, (size_t)s.N * esz, hipMemcpyDeviceToDevice, stream));
+  HIP_OK(hipMemcpyAsync(b->d_desc + si, &s.desc, sizeof(InstDesc), hipMemcpyHostToDevice, stream));
+  HIP_OK(hipMemcpyAsync(s.desc.scal, S, sizeof(S), hipMemcpyHostToDevice, stream));
+  if (b->opts.field == SIP_F64) launch_init<double>(stream, b->d_desc, si, s.N);
+  else launch_init<float>(stream, b->d_desc, si, s.N);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(stream));
+  return SIP_OK;
+}
+
+bool tiles_from(const sip_tiles& t, TileCfg& tc) {
+  if (t.pt_points < kTileQuantum || t.thr_points < kTileQuantum || t.pt_points % kTileQuantum ||
+      t.thr_points % kTileQuantum || t.pt_max_items < 1 || t.thr_max_items < 1 ||
+      (t.pt_threads != 256 && t.pt_threads != 512) || (t.cg_form != 0 && t.cg_form != 1))
+    return false;
+  tc.pt_base = t.pt_points; tc.pt_max_items = t.pt_max_items;
+  tc.thr_base = t.thr_points; tc.thr_max_items = t.thr_max_items;
+  tc.pt_threads = t.pt_threads; tc.cg_form = t.cg_form;
+  return true;
+}
+
+// Device bytes of a one-instance batch in fixed-memory mode, in the order
+// create_batch and rebuild_tables carve them: descriptor, scalars, the
+// instance workspace, the work tables and partial-sum buffers.
+int64_t plan_bytes_of(const sip_grid& g, const sip_set* sets, int nsets, const sip_opts& o, const TileCfg& tc) {
+  std::vector<Slot> one(1);
+  describe_slot(one[0], g, sets, nsets, o, nullptr, nullptr, nullptr);
+  HostTables h;
+  build_host_tables(one, tc, o, h);
+  return align_up((int64_t)sizeof(InstDesc)) + align_up((int64_t)S_COUNT * 8) + one[0].L.total + table_bytes(h);
+}
+
+// Exported state of a plan: a header naming its layout, the scalar block,
+// x, and the instance workspace (m, CG vectors, y_i, v_i, snapshots, x
+// history, selection state, schedule log).
+struct StateHeader {
+  uint64_t magic;
+  int64_t N, ws_total, n[3];
+  int32_t ndim, nsets, field, reduce, adapt_every, stop_every, evol_hist, log;
+  int32_t kinds[SIP_MAX_SETS], ops[SIP_MAX_SETS];
+};
+constexpr int64_t kStateScal = 256;                              // header in the first 256 bytes
+constexpr int64_t kStateX = kStateScal + ((S_COUNT * 8 + 255) / 256) * 256;
+static_assert(sizeof(StateHeader) <= kStateScal, "state header");
+
+StateHeader state_header(const Slot& s, const sip_opts& o) {
+  StateHeader h;
+  std::memset(&h, 0, sizeof(h));
+  h.magic = 0x5349505354415445ull;  // "SIPSTATE"
+  h.N = s.N;
+  h.ws_total = s.L.total;
+  for (int a = 0; a < 3; ++a) h.n[a] = s.desc.n[a];
+  h.ndim = s.grid.ndim; h.nsets = s.nsets; h.field = o.field; h.reduce = o.reduce;
+  h.adapt_every = o.adapt_every; h.stop_every = o.stop_every; h.evol_hist = o.evol_hist; h.log = o.log_schedule;
+  for (int i = 0; i < s.nsets; ++i) { h.kinds[i] = s.sets[i].kind; h.ops[i] = s.sets[i].op; }
+  return h;
+}
+
+int64_t state_bytes_of(const Slot& s, const sip_opts& o) {
+  const int64_t esz = o.field == SIP_F64 ? 8 : 4;
+  return kStateX + align_up(s.N * esz) + s.L.total;
+}
+
+// A plan's slot restarted from m with the iterate in x_dev (the descriptor
+// is uploaded again, so x may change from call to call without new graphs).
+int32_t restart_plan(sip_plan* p, const void* m_dev, void* x_dev, hipStream_t stream) {
+  Slot& s = p->b->slots[p->slot];
+  s.x = x_dev;
+  s.desc.x = x_dev;
+  s.desc.vec_ok = ((uintptr_t)x_dev % 16 == 0) ? 1 : 0;
+  return start_slot(p->b, p->slot, m_dev, stream);
+}
+
 int32_t read_scal(sip_batch* b, hipStream_t stream) {
   HIP_OK(hipMemcpyAsync(b->h_scal, b->d_scal, (size_t)b->max_slots * S_COUNT * 8, hipMemcpyDeviceToHost, stream));
   HIP_OK(hipStreamSynchronize(stream));
@@ -642,7 +976,7 @@ const char* sip_strerror(int32_t st) {
     case SIP_EHIP: return "HIP runtime error";
     case SIP_ENUMERIC: return "numerical failure (non-finite value or CG breakdown)";
     case SIP_EUNSUPPORTED: return "unsupported";
-    case SIP_EBUDGET: return "batch full (slots or arena)";
+    case SIP_EBUDGET: return "batch full (slots or arena) or workspace too small";
     default: return "unknown status";
   }
 }
@@ -671,31 +1005,7 @@ int64_t sip_workspace_bytes(const sip_grid* g, const sip_set* sets, int32_t nset
 }
 
 int32_t sip_batch_create(sip_batch** out, int32_t max_slots, int64_t arena_bytes, const sip_opts* o) {
-  if (!out || !o || max_slots < 1 || arena_bytes <= 0) return SIP_EINVAL;
-  sip_opts probe = *o;
-  sip_grid g{}; g.ndim = 2; g.n[0] = 2; g.n[1] = 2; g.h[0] = g.h[1] = 1.0;
-  if (validate(&g, nullptr, 0, &probe) != SIP_OK) return SIP_EINVAL;
-  sip_batch* b = new (std::nothrow) sip_batch();
-  if (!b) return SIP_ENOMEM;
-  b->opts = *o;
-  b->kopts = kernel_opts(*o);
-  b->max_slots = max_slots;
-  b->slots.resize(max_slots);
-  if (!b->arena.init(arena_bytes)) { delete b; return SIP_ENOMEM; }
-  if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) { delete b; return SIP_EHIP; }
-  if (hipMalloc((void**)&b->d_desc, sizeof(InstDesc) * max_slots) != hipSuccess ||
-      hipMalloc((void**)&b->d_scal, sizeof(double) * S_COUNT * max_slots) != hipSuccess ||
-      hipHostMalloc((void**)&b->h_scal, sizeof(double) * S_COUNT * max_slots, 0) != hipSuccess) {
-    sip_batch_destroy(b);
-    return SIP_ENOMEM;
-  }
-  std::memset(b->h_scal, 0, sizeof(double) * S_COUNT * max_slots);
-  if (hipMemcpy(b->d_scal, b->h_scal, sizeof(double) * S_COUNT * max_slots, hipMemcpyHostToDevice) != hipSuccess) {
-    sip_batch_destroy(b);
-    return SIP_EHIP;
-  }
-  *out = b;
-  return SIP_OK;
+  return create_batch(out, max_slots, arena_bytes, o, nullptr, 0, false);
 }
 
 int32_t sip_batch_destroy(sip_batch* b) {
@@ -705,8 +1015,11 @@ int32_t sip_batch_destroy(sip_batch* b) {
   void* dev[] = {b->d_desc, b->d_scal, b->d_pt, b->d_thr, b->d_sel, b->d_inst, b->d_rr, b->d_pq,
                  b->d_rr2, b->d_pq2, b->d_proj, b->d_thrw, b->d_thra, b->d_tie, b->d_sp,
                  b->d_line, b->d_linep, b->d_h1c, b->d_h1s};
-  for (void* p : dev) if (p) (void)hipFree(p);
-  if (b->h_scal) (void)hipHostFree(b->h_scal);
+  for (void* p : dev) (void)dev_free(b, p);
+  if (b->h_scal) {
+    if (b->pinned) (void)hipHostFree(b->h_scal);
+    else delete[] b->h_scal;
+  }
   delete b;
   return SIP_OK;
 }
@@ -720,105 +1033,11 @@ int32_t sip_batch_add(sip_batch* b, const sip_grid* g, const sip_set* sets, int3
   int si = -1;
   for (int i = 0; i < b->max_slots; ++i) if (!b->slots[i].used) { si = i; break; }
   if (si < 0) return SIP_EBUDGET;
-  Slot& s = b->slots[si];
-  s = Slot();
-  s.L = layout_of(*g, sets, nsets, b->opts);
-  s.ws = b->arena.alloc(s.L.total);
-  if (!s.ws) return SIP_EBUDGET;
-  s.used = true;
-  s.grid = *g;
-  s.nsets = nsets;
-  for (int i = 0; i < nsets; ++i) s.sets[i] = sets[i];
-  s.x = x_dev;
-  int64_t n[3]; double h[3];
-  internal_dims(*g, n, h);
-  s.N = n[0] * n[1] * n[2];
-  InstDesc& d = s.desc;
-  std::memset(&d, 0, sizeof(d));
-  d.ndim = g->ndim; d.nsets = nsets; d.active = 1;
-  for (int a = 0; a < 3; ++a) { d.n[a] = n[a]; d.hinv[a] = 1.0 / h[a]; d.h2inv[a] = 1.0 / (h[a] * h[a]); }
-  d.N = s.N;
-  {
-    const int64_t esz = b->opts.field == SIP_F64 ? 8 : 4;
-    d.cs = align_up(s.N * esz) / esz;
-  }
-  d.stride[2] = 1; d.stride[1] = n[2]; d.stride[0] = n[1] * n[2];
-  d.div_x = make_fastdiv((uint32_t)n[2]);
-  {
-    const int64_t grp = 16 / (b->opts.field == SIP_F64 ? 8 : 4);
-    d.vec_ok = ((uintptr_t)x_dev % 16 == 0) ? 1 : 0;
-    d.vec_nb = (n[2] % grp == 0) ? 1 : 0;  // then both row strides (nx, ny*nx) are multiples
-  }
-  d.div_y = make_fastdiv((uint32_t)n[1]);
-  char* w = s.ws;
-  const Layout& L = s.L;
-  auto at = [&](int64_t off) -> void* { return off >= 0 ? (void*)(w + off) : nullptr; };
-  d.m = at(L.m); d.x = x_dev; d.r = at(L.r); d.p[0] = at(L.p0); d.p[1] = at(L.p1);
-  for (int i = 0; i < 2; ++i) { d.cr[i] = at(L.cr[i]); d.cp[i] = at(L.cp[i]); }
-  d.xs[0] = at(L.xs0); d.xs[1] = at(L.xs1); d.ring = at(L.ring);
-  d.yl = at(L.yl); d.vl = at(L.vl); d.vh0l = at(L.vh0l); d.v0l = at(L.v0l); d.y0l = at(L.y0l);
-  d.scal = b->d_scal + (size_t)si * S_COUNT;
-  d.log = (double*)at(L.log);
-  d.log_cap = b->opts.log_schedule ? b->opts.max_iter : 0;
-  int nthr = 0;
-  for (int i = 0; i < nsets; ++i) {
-    SetDesc& sd = d.sets[i];
-    OpInfo oi;
-    op_info(g->ndim, sets[i].op, oi);
-    sd.kind = sets[i].kind; sd.op = sets[i].op; sd.ncomp = oi.ncomp;
-    for (int c = 0; c < 3; ++c) sd.axis[c] = c < oi.ncomp ? oi.axis[c] : -1;
-    sd.thr = is_thr(sets[i]) ? nthr++ : -1;
-    sd.line_axis = sets[i].line != SIP_LINE_NONE ? line_axis_of(sets[i].line) : -1;
-    sd.lo = sets[i].lo; sd.hi = sets[i].hi; sd.tau = sets[i].tau; sd.k = sets[i].k;
-    sd.rows = rows_of(*g, sets[i]);
-    const auto& SL = L.set[i];
-    sd.y = at(SL.y); sd.v = at(SL.v); sd.vh0 = at(SL.vh0); sd.v0 = at(SL.v0); sd.y0 = at(SL.y0);
-    sd.lov = at(SL.lov); sd.hiv = at(SL.hiv);
-    for (int src = 0; src < 2; ++src) {
-      sd.sel[src] = (SelState*)at(SL.sel[src]);
-      sd.hcnt[src] = (uint32_t*)at(SL.hc[src]);
-      sd.hsum[src] = (double*)at(SL.hs[src]);
-      sd.cand[src] = at(SL.cand[src]);
-    }
-    sd.cand_ix = (uint32_t*)at(SL.cix);
-  }
-  const size_t esz = b->opts.field == SIP_F64 ? 8 : 4;
-  double S[S_COUNT];
-  initial_scalars(b, s, S);
-  int32_t rc = SIP_OK;
-  if (hipMemcpyAsync(d.m, m_dev, (size_t)s.N * esz, hipMemcpyDeviceToDevice, stream) != hipSuccess ||
-      hipMemcpyAsync(b->d_desc + si, &d, sizeof(InstDesc), hipMemcpyHostToDevice, stream) != hipSuccess ||
-      hipMemcpyAsync(d.scal, S, sizeof(S), hipMemcpyHostToDevice, stream) != hipSuccess) {
-    rc = SIP_EHIP;
-  }
-  if (rc == SIP_OK) {
-    // per-row bound vectors into the padded component layout; waited for, so
-    // the caller may release its arrays when admission returns
-    bool vec_bounds = false;
-    for (int i = 0; i < nsets && rc == SIP_OK; ++i) {
-      const SetDesc& sd = d.sets[i];
-      const void* src[2] = {sets[i].lo_vec, sets[i].hi_vec};
-      void* dst[2] = {sd.lov, sd.hiv};
-      for (int q = 0; q < 2; ++q) {
-        if (!src[q]) continue;
-        vec_bounds = true;
-        if (hipMemcpy2DAsync(dst[q], (size_t)d.cs * esz, src[q], (size_t)s.N * esz, (size_t)s.N * esz,
-                             (size_t)sd.ncomp, hipMemcpyDeviceToDevice, stream) != hipSuccess)
-          rc = SIP_EHIP;
-      }
-    }
-    if (rc == SIP_OK && vec_bounds && hipStreamSynchronize(stream) != hipSuccess) rc = SIP_EHIP;
-  }
-  if (rc == SIP_OK) {
-    if (b->opts.field == SIP_F64) launch_init<double>(stream, b->d_desc, si, s.N);
-    else launch_init<float>(stream, b->d_desc, si, s.N);
-    if (hipGetLastError() != hipSuccess) rc = SIP_EHIP;
-    // the host copies above read stack memory: finish them before returning
-    if (hipStreamSynchronize(stream) != hipSuccess) rc = SIP_EHIP;
-  }
+  int32_t rc = place_slot(b, si, *g, sets, nsets, x_dev, stream);
+  if (rc == SIP_OK) rc = start_slot(b, si, m_dev, stream);
   if (rc != SIP_OK) {
-    b->arena.release(s.ws);
-    s = Slot();
+    if (b->slots[si].ws) b->arena.release(b->slots[si].ws);
+    b->slots[si] = Slot();
     return rc;
   }
   b->dirty = true;
@@ -834,6 +1053,11 @@ int32_t sip_batch_run(sip_batch* b, int32_t iters, void* stream_) {
     if (rc != SIP_OK) return rc;
   }
   if (b->live_inst == 0 || iters == 0) return SIP_OK;
+  if (b->no_graph) {
+    for (int i = 0; i < iters; ++i) launch_iterations(b, stream, 1);
+    HIP_OK(hipGetLastError());
+    return SIP_OK;
+  }
   hipGraphExec_t ge;
   const int32_t rc = get_graph(b, iters, ge);
   if (rc != SIP_OK) return rc;
@@ -974,18 +1198,7 @@ int32_t sip_batch_schedule(sip_batch* b, int32_t slot, double* rho, double* gamm
 
 int32_t sip_batch_reset(sip_batch* b, int32_t slot, const void* m_dev, void* stream_) {
   if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used || !m_dev) return SIP_EINVAL;
-  hipStream_t stream = (hipStream_t)stream_;
-  Slot& s = b->slots[slot];
-  const size_t esz = b->opts.field == SIP_F64 ? 8 : 4;
-  double S[S_COUNT];
-  initial_scalars(b, s, S);
-  HIP_OK(hipMemcpyAsync(s.desc.m, m_dev, (size_t)s.N * esz, hipMemcpyDeviceToDevice, stream));
-  HIP_OK(hipMemcpyAsync(s.desc.scal, S, sizeof(S), hipMemcpyHostToDevice, stream));
-  if (b->opts.field == SIP_F64) launch_init<double>(stream, b->d_desc, slot, s.N);
-  else launch_init<float>(stream, b->d_desc, slot, s.N);
-  HIP_OK(hipGetLastError());
-  HIP_OK(hipStreamSynchronize(stream));
-  return SIP_OK;
+  return start_slot(b, slot, m_dev, (hipStream_t)stream_);
 }
 
 int32_t sip_batch_time_kernel(sip_batch* b, int32_t kernel, int32_t reps, void* stream_, double* avg_ms) {
@@ -1135,6 +1348,130 @@ int32_t sip_project_batched(int32_t B, const sip_grid* grids, const sip_set* set
   }
   sip_batch_destroy(b);
   return rc != SIP_OK ? rc : first_bad;
+}
+
+// ---------------------------------------------------------------- plans
+
+int32_t sip_tiles_default(sip_tiles* t) {
+  if (!t) return SIP_EINVAL;
+  const TileCfg d;
+  t->pt_points = (int32_t)d.pt_base; t->pt_max_items = (int32_t)d.pt_max_items;
+  t->thr_points = (int32_t)d.thr_base; t->thr_max_items = (int32_t)d.thr_max_items;
+  t->pt_threads = d.pt_threads; t->cg_form = d.cg_form;
+  return SIP_OK;
+}
+
+int64_t sip_plan_bytes(const sip_grid* g, const sip_set* sets, int32_t nsets, const sip_opts* o,
+                       const sip_tiles* tiles) {
+  if (validate(g, sets, nsets, o) != SIP_OK) return -1;
+  TileCfg tc;
+  if (tiles && !tiles_from(*tiles, tc)) return -1;
+  return plan_bytes_of(*g, sets, nsets, *o, tc);
+}
+
+int32_t sip_plan_create(sip_plan** out, const sip_grid* g, const sip_set* sets, int32_t nsets, const sip_opts* o,
+                        const sip_tiles* tiles, void* workspace, int64_t workspace_bytes, void* stream_) {
+  if (!out) return SIP_EINVAL;
+  *out = nullptr;
+  const int32_t vr = validate(g, sets, nsets, o);
+  if (vr != SIP_OK) return vr;
+  TileCfg tc;
+  if (tiles && !tiles_from(*tiles, tc)) return SIP_EINVAL;
+  const int64_t need = plan_bytes_of(*g, sets, nsets, *o, tc);
+  if (workspace && workspace_bytes < need) return SIP_EBUDGET;
+  if (workspace && (uintptr_t)workspace % kAlign) return SIP_EINVAL;
+  sip_plan* p = new (std::nothrow) sip_plan();
+  if (!p) return SIP_ENOMEM;
+  const int64_t ws = layout_of(*g, sets, nsets, *o).total;
+  int32_t rc = create_batch(&p->b, 1, ws, o, (char*)workspace, workspace ? workspace_bytes : 0, false);
+  if (rc == SIP_OK) {
+    p->b->tiles = tc;
+    rc = place_slot(p->b, 0, *g, sets, nsets, nullptr, (hipStream_t)stream_);
+  }
+  if (rc == SIP_OK) rc = rebuild_tables(p->b, (hipStream_t)stream_);
+  if (rc != SIP_OK) {
+    sip_plan_destroy(p);
+    return rc;
+  }
+  *out = p;
+  return SIP_OK;
+}
+
+int32_t sip_plan_destroy(sip_plan* p) {
+  if (!p) return SIP_OK;
+  if (p->b) sip_batch_destroy(p->b);
+  delete p;
+  return SIP_OK;
+}
+
+int32_t sip_plan_start(sip_plan* p, const void* m_dev, void* x_dev, void* stream_) {
+  if (!p || !m_dev || !x_dev) return SIP_EINVAL;
+  const int32_t rc = restart_plan(p, m_dev, x_dev, (hipStream_t)stream_);
+  if (rc == SIP_OK) p->started = true;
+  return rc;
+}
+
+int32_t sip_plan_iterate(sip_plan* p, int32_t iters, void* stream) {
+  if (!p || !p->started || iters < 0) return SIP_EINVAL;
+  return sip_batch_run(p->b, iters, stream);
+}
+
+int32_t sip_plan_result(sip_plan* p, sip_result* res, void* stream) {
+  if (!p || !p->started || !res) return SIP_EINVAL;
+  return sip_batch_result(p->b, p->slot, res, stream);
+}
+
+int32_t sip_plan_project(sip_plan* p, const void* m_dev, void* x_dev, sip_result* res, void* stream_) {
+  if (!p || !m_dev || !x_dev) return SIP_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  int32_t rc = sip_plan_start(p, m_dev, x_dev, stream_);
+  const sip_opts& o = p->b->opts;
+  if (rc == SIP_OK) rc = run_to_end(p->b, std::min(o.max_iter, o.stop_every > 0 ? 5 * o.stop_every : 25), stream);
+  sip_result r{};
+  if (rc == SIP_OK) rc = sip_batch_result(p->b, p->slot, &r, stream_);
+  if (rc != SIP_OK) return rc;
+  if (res) *res = r;
+  return r.status;
+}
+
+int64_t sip_state_bytes(const sip_plan* p) {
+  if (!p) return -1;
+  return state_bytes_of(p->b->slots[p->slot], p->b->opts);
+}
+
+int32_t sip_state_export(sip_plan* p, void* dst_dev, void* stream_) {
+  if (!p || !p->started || !dst_dev) return SIP_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  const Slot& s = p->b->slots[p->slot];
+  const StateHeader hd = state_header(s, p->b->opts);
+  const size_t esz = p->b->opts.field == SIP_F64 ? 8 : 4;
+  char* dst = (char*)dst_dev;
+  HIP_OK(hipMemcpyAsync(dst, &hd, sizeof(hd), hipMemcpyHostToDevice, stream));
+  HIP_OK(hipMemcpyAsync(dst + kStateScal, s.desc.scal, S_COUNT * 8, hipMemcpyDeviceToDevice, stream));
+  HIP_OK(hipMemcpyAsync(dst + kStateX, s.x, (size_t)s.N * esz, hipMemcpyDeviceToDevice, stream));
+  HIP_OK(hipMemcpyAsync(dst + kStateX + align_up(s.N * (int64_t)esz), s.ws, (size_t)s.L.total,
+                        hipMemcpyDeviceToDevice, stream));
+  // the header copy reads stack memory
+  HIP_OK(hipStreamSynchronize(stream));
+  return SIP_OK;
+}
+
+int32_t sip_state_import(sip_plan* p, const void* src_dev, void* stream_) {
+  if (!p || !p->started || !src_dev) return SIP_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  const Slot& s = p->b->slots[p->slot];
+  const StateHeader want = state_header(s, p->b->opts);
+  StateHeader got;
+  const char* src = (const char*)src_dev;
+  HIP_OK(hipMemcpyAsync(&got, src, sizeof(got), hipMemcpyDeviceToHost, stream));
+  HIP_OK(hipStreamSynchronize(stream));
+  if (std::memcmp(&got, &want, sizeof(got)) != 0) return SIP_EINVAL;
+  const size_t esz = p->b->opts.field == SIP_F64 ? 8 : 4;
+  HIP_OK(hipMemcpyAsync(s.desc.scal, src + kStateScal, S_COUNT * 8, hipMemcpyDeviceToDevice, stream));
+  HIP_OK(hipMemcpyAsync(s.x, src + kStateX, (size_t)s.N * esz, hipMemcpyDeviceToDevice, stream));
+  HIP_OK(hipMemcpyAsync(s.ws, src + kStateX + align_up(s.N * (int64_t)esz), (size_t)s.L.total,
+                        hipMemcpyDeviceToDevice, stream));
+  return SIP_OK;
 }
 
 }  // extern "C"

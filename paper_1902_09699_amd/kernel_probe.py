@@ -29,10 +29,7 @@ def main():
     from paper_1902_09699_amd import sip
 
     args = argparse.Namespace(batched_count=256)
-    if a.workload == "batched":
-        insts, field, iters, _ = bench.batched_workload(args)
-    else:
-        insts, field, iters, _ = bench.workload(a.workload, args)
+    insts, field, iters, _ = bench.load_workload(a.workload, args)
     dt = torch.float64 if field == "f64" else torch.float32
     opts = sip.make_opts(field, max_iter=iters, cg_max=10, cg_fixed=1)
     ms = [torch.tensor(m, dtype=dt, device="cuda") for m, _ in insts]

@@ -37,6 +37,19 @@ def kernel_table(con, top=20):
     return "\n".join(out)
 
 
+def kernel_grid_table(con, top=40):
+    """Per kernel and launch shape (grid and work-group size): dispatch
+    count and mean duration, so launches of different workloads in one
+    process (a batch, a single grid, a served mix) are told apart."""
+    q = ("select name, grid_x, workgroup_x, count(*), avg(duration), sum(duration) from kernels "
+         "group by 1, 2, 3 order by 6 desc")
+    rows = con.execute(q).fetchall()
+    out = [f"{'kernel':40s} {'grid_x':>9s} {'wg':>5s} {'calls':>7s} {'avg_us':>9s} {'total_ms':>10s}"]
+    for name, gx, wx, calls, avg, tot in rows[:top]:
+        out.append(f"{_short(name)[:40]:40s} {gx:9d} {wx:5d} {calls:7d} {avg / 1e3:9.2f} {tot / 1e6:10.3f}")
+    return "\n".join(out)
+
+
 def counter_table(con):
     try:
         cols = [c[1] for c in con.execute("pragma table_info(counters_collection)")]
@@ -87,12 +100,16 @@ def main():
     ap.add_argument("--write-db", help="with --kernel: traffic from a FETCH_SIZE db (path) and this WRITE_SIZE db")
     ap.add_argument("--kernel")
     ap.add_argument("--copy-bytes", type=float, default=256 * (1 << 20))
+    ap.add_argument("--by-grid", action="store_true", help="kernel trace per launch shape")
     a = ap.parse_args()
     if a.write_db:
         import json
         print(json.dumps(traffic(a.path, a.write_db, a.kernel, a.copy_bytes), indent=1))
         return
     con = _db(a.path)
+    if a.by_grid:
+        print(kernel_grid_table(con, a.top))
+        return
     ct = counter_table(con)
     print(ct if ct else kernel_table(con, a.top))
 

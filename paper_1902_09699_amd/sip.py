@@ -49,6 +49,11 @@ class Opts(C.Structure):
                 ("reduce", C.c_int32), ("log_schedule", C.c_int32)]
 
 
+class Tiles(C.Structure):
+    _fields_ = [("pt_points", C.c_int32), ("pt_max_items", C.c_int32), ("thr_points", C.c_int32),
+                ("thr_max_items", C.c_int32), ("pt_threads", C.c_int32), ("cg_form", C.c_int32)]
+
+
 class Result(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("cg_steps", C.c_int32),
                 ("converged", C.c_int32), ("nsets", C.c_int32), ("reserved", C.c_int32),
@@ -127,6 +132,18 @@ def lib():
         "sip_project_multilevel": (i32, [C.POINTER(Grid), C.POINTER(Set), i32, C.POINTER(Opts), i32,
                                          C.POINTER(i32), i32, vp, vp, C.POINTER(Result), C.POINTER(i32), vp]),
         "sip_dykstra_update": (i32, [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_double), vp, i64, i32, vp]),
+        "sip_tiles_default": (i32, [C.POINTER(Tiles)]),
+        "sip_plan_bytes": (i64, [C.POINTER(Grid), C.POINTER(Set), i32, C.POINTER(Opts), C.POINTER(Tiles)]),
+        "sip_plan_create": (i32, [C.POINTER(vp), C.POINTER(Grid), C.POINTER(Set), i32, C.POINTER(Opts),
+                                  C.POINTER(Tiles), vp, i64, vp]),
+        "sip_plan_destroy": (i32, [vp]),
+        "sip_plan_project": (i32, [vp, vp, vp, C.POINTER(Result), vp]),
+        "sip_plan_start": (i32, [vp, vp, vp, vp]),
+        "sip_plan_iterate": (i32, [vp, i32, vp]),
+        "sip_plan_result": (i32, [vp, C.POINTER(Result), vp]),
+        "sip_state_bytes": (i64, [vp]),
+        "sip_state_export": (i32, [vp, vp, vp]),
+        "sip_state_import": (i32, [vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -142,7 +159,9 @@ def exported_symbols():
             "sip_batch_run", "sip_batch_poll", "sip_batch_remove", "sip_batch_result", "sip_batch_field",
             "sip_batch_get_params", "sip_batch_set_params", "sip_batch_schedule", "sip_batch_set_tiles",
             "sip_batch_items", "sip_batch_reset", "sip_batch_time_kernel", "sip_stream_copy", "sip_level",
-            "sip_restrict", "sip_project_multilevel", "sip_dykstra_update"]
+            "sip_restrict", "sip_project_multilevel", "sip_dykstra_update", "sip_tiles_default", "sip_plan_bytes",
+            "sip_plan_create", "sip_plan_destroy", "sip_plan_project", "sip_plan_start", "sip_plan_iterate",
+            "sip_plan_result", "sip_state_bytes", "sip_state_export", "sip_state_import"]
 
 
 def strerror(status: int) -> str:
@@ -266,6 +285,104 @@ def project(m, sets, opts: Opts, x=None, h=None, stream=None):
                            C.c_void_p(x.data_ptr()), C.byref(res), _stream_ptr(stream))
     check(st, "sip_project")
     return x, res.as_dict()
+
+
+def make_tiles(tiles=None) -> Tiles:
+    """Tiles from a (pt_points, pt_max_items, thr_points, thr_max_items[,
+    pt_threads[, cg_form]]) tuple; None: the library defaults."""
+    t = Tiles()
+    check(lib().sip_tiles_default(C.byref(t)), "sip_tiles_default")
+    if tiles is not None:
+        names = ["pt_points", "pt_max_items", "thr_points", "thr_max_items", "pt_threads", "cg_form"]
+        for k, v in zip(names, tiles):
+            setattr(t, k, int(v))
+    return t
+
+
+def plan_bytes(shape, sets, opts: Opts, tiles=None, h=None) -> int:
+    g = make_grid(shape, h)
+    arr = make_sets(sets)
+    t = make_tiles(tiles)
+    return int(lib().sip_plan_bytes(C.byref(g), arr, len(sets), C.byref(opts), C.byref(t)))
+
+
+class Plan:
+    """A plan for one grid and set list (sip_plan_*): precomputed once,
+    reused for many models m.  workspace: optional device tensor (uint8) of at
+    least plan_bytes() from which the plan takes all its device memory."""
+
+    def __init__(self, shape, sets, opts: Opts, tiles=None, workspace=None, h=None, stream=None):
+        self.opts = opts
+        self.shape = tuple(shape)
+        self.sets = list(sets)
+        g = make_grid(self.shape, h)
+        arr = make_sets(self.sets)
+        t = make_tiles(tiles)
+        hnd = C.c_void_p()
+        ws_ptr = C.c_void_p(workspace.data_ptr()) if workspace is not None else None
+        ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+        self.workspace = workspace
+        check(lib().sip_plan_create(C.byref(hnd), C.byref(g), arr, len(self.sets), C.byref(opts), C.byref(t),
+                                    ws_ptr, int(ws_bytes), _stream_ptr(stream)), "sip_plan_create")
+        self.h = hnd
+        self.x = None
+
+    def close(self):
+        if self.h:
+            lib().sip_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _tensors(self, m, x):
+        import torch
+        n = m.numel()
+        _check_tensor(m, n, self.opts, "m")
+        if x is None:
+            x = torch.empty_like(m)
+        _check_tensor(x, n, self.opts, "x")
+        return x
+
+    def project(self, m, x=None, stream=None):
+        x = self._tensors(m, x)
+        res = Result()
+        st = lib().sip_plan_project(self.h, C.c_void_p(m.data_ptr()), C.c_void_p(x.data_ptr()), C.byref(res),
+                                    _stream_ptr(stream))
+        check(st, "sip_plan_project")
+        self.x = x
+        return x, res.as_dict()
+
+    def start(self, m, x=None, stream=None):
+        x = self._tensors(m, x)
+        check(lib().sip_plan_start(self.h, C.c_void_p(m.data_ptr()), C.c_void_p(x.data_ptr()),
+                                   _stream_ptr(stream)), "sip_plan_start")
+        self.x = x
+        return x
+
+    def iterate(self, iters, stream=None):
+        check(lib().sip_plan_iterate(self.h, int(iters), _stream_ptr(stream)), "sip_plan_iterate")
+
+    def result(self, stream=None):
+        r = Result()
+        check(lib().sip_plan_result(self.h, C.byref(r), _stream_ptr(stream)), "sip_plan_result")
+        return r.as_dict()
+
+    def state_bytes(self) -> int:
+        return int(lib().sip_state_bytes(self.h))
+
+    def export_state(self, stream=None):
+        """The plan's whole state as a new device tensor (uint8)."""
+        import torch
+        out = torch.empty(self.state_bytes(), dtype=torch.uint8, device="cuda")
+        check(lib().sip_state_export(self.h, C.c_void_p(out.data_ptr()), _stream_ptr(stream)), "sip_state_export")
+        return out
+
+    def import_state(self, blob, stream=None):
+        check(lib().sip_state_import(self.h, C.c_void_p(blob.data_ptr()), _stream_ptr(stream)), "sip_state_import")
 
 
 def level(shape, sets, lev, h=None):
@@ -437,6 +554,12 @@ class Batch:
         _memcpy_d2d(out.data_ptr(), ptr, n * out.element_size())
         return out
 
+    def rows(self, slot, which, set_index, shape, op):
+        """A slot's set array (FIELD_Y, FIELD_V, ...) copied to the host as
+        the operator's row vector (float64)."""
+        t = self.field_tensor(slot, which, set_index).double().cpu().numpy()
+        return component_rows(shape, op, t, self.field(slot, which, set_index)[2])
+
     def load_field(self, slot, which, set_index, values):
         import torch
         ptr, n, _ = self.field(slot, which, set_index)
@@ -493,6 +616,31 @@ class Batch:
         a, b, c, d = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         check(lib().sip_batch_items(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)), "sip_batch_items")
         return a.value, b.value, c.value, d.value
+
+
+# components of each operator, by grid axis (None: the identity block)
+_COMP_AXES = {
+    2: {"I": (None,), "DZ": (0,), "DX": (1,), "GRAD": (0, 1), "LAT": (1,)},
+    3: {"I": (None,), "DZ": (0,), "DY": (1,), "DX": (2,), "GRAD": (0, 1, 2), "LAT": (1, 2)},
+}
+
+
+def component_rows(shape, op, flat, stride=None):
+    """A set array in the device layout (one block of `stride` elements per
+    operator component, each the grid image with the last layer along the
+    component's axis unused) as the operator's row vector (components
+    stacked, rows in C order): host-side layout conversion only."""
+    N = int(np.prod(shape))
+    stride = N if stride is None else int(stride)
+    parts = []
+    for c, ax in enumerate(_COMP_AXES[len(shape)][op]):
+        blk = np.asarray(flat[c * stride:c * stride + N]).reshape(shape)
+        if ax is not None:
+            sl = [slice(None)] * len(shape)
+            sl[ax] = slice(0, shape[ax] - 1)
+            blk = blk[tuple(sl)]
+        parts.append(blk.ravel())
+    return np.concatenate(parts)
 
 
 def dykstra_update(ys, vs, weights, x, stream=None):

@@ -175,3 +175,24 @@ def test_multilevel_rejects_line_sets_on_host(L):
     rc = sip.lib().sip_project_multilevel(sip.C.byref(g), arr, 1, sip.C.byref(sip.make_opts()), 2, iters, 0,
                                           sip.C.c_void_p(16), sip.C.c_void_p(16), sip.C.byref(res), None, None)
     assert rc == sip.EUNSUPPORTED
+
+
+def test_plan_sizes(L):
+    """A plan's device bytes: the instance workspace plus its descriptor,
+    scalars and work tables; the default tiles are the library's; invalid
+    sets or tiles give -1."""
+    box_tv = [{"kind": "bounds", "op": "I", "lo": -1, "hi": 1}, {"kind": "l1", "op": "GRAD", "tau": 3.0}]
+    o = sip.make_opts("f32")
+    t = sip.make_tiles()
+    assert (t.pt_points, t.pt_max_items, t.thr_points, t.thr_max_items, t.pt_threads, t.cg_form) == \
+        (2048, 512, 2048, 512, 512, 0)
+    ws = sip.workspace_bytes((64, 80), box_tv, o)
+    pb = sip.plan_bytes((64, 80), box_tv, o)
+    assert ws < pb < ws + (1 << 20)
+    assert pb % 256 == 0
+    # finer tiles need more table entries and partial sums
+    assert sip.plan_bytes((640, 800), box_tv, o, (256, 4096, 256, 4096, 256, 0)) > \
+        sip.plan_bytes((640, 800), box_tv, o)
+    assert sip.plan_bytes((64, 80), [{"kind": "l1", "op": "GRAD", "tau": -1.0}], o) == -1
+    assert sip.plan_bytes((64, 80), box_tv, o, (100, 512, 2048, 512, 512, 0)) == -1
+    assert sip.plan_bytes((64, 80), box_tv, o, (2048, 512, 2048, 512, 384, 0)) == -1
