@@ -393,13 +393,19 @@ def cg(C, b, x0, cg_rel=0.1, cg_max=10, fixed=True, steps_forced=None, trace=Non
 
 
 # ---------------------------------------------------------------------------
-# adapt-rho-gamma (the second algorithm listing), one set at a time
+# Automatic penalty and relaxation (section "Solving the linear system and
+# automatic parameter selection"; the adaptive relaxed ADMM of Xu et al. 2017
+# that the paper adopts), one set at a time
 # ---------------------------------------------------------------------------
 
 def _spectral(d_a, d_b, eps_corr):
-    """Correlation test and hybrid steepest-descent / minimum-gradient
-    spectral estimate for one pair (Delta-h-hat, Delta-v-hat) or
-    (Delta-g-hat, Delta-v).  Returns (reliable, estimate)."""
+    """Spectral (Barzilai-Borwein type) curvature estimate of one of the two
+    dual-function pieces from a pair of differences over the adaptation
+    interval: the pair is trusted only when the differences are correlated,
+    cos(d_a, d_b) > eps_corr, and then the estimate blends the
+    minimum-gradient value d_a.d_b / d_a.d_a with the steepest-descent value
+    d_b.d_b / d_a.d_b (the former when twice it exceeds the latter, else
+    the latter minus half the former).  Returns (trusted, estimate)."""
     ab = float(d_a @ d_b)
     aa = float(d_a @ d_a)
     bb = float(d_b @ d_b)
@@ -415,34 +421,41 @@ def _spectral(d_a, d_b, eps_corr):
     return True, est
 
 
-def adapt_rho_gamma(s, y_old, y_new, v_old, v_new, rho, gamma, snap, eps_corr=0.3):
-    """One call of adapt-rho-gamma for one set.
+def _penalty_relaxation(trusted_a, a, trusted_b, b, rho):
+    """The new (rho, gamma) from the two curvature estimates: with both
+    trusted, rho is their geometric mean and gamma = 1 + 2 sqrt(a b)/(a + b);
+    with one, rho follows it and gamma is 1.9 (from a) or 1.1 (from b); with
+    neither, rho stays and gamma is 1.5."""
+    if trusted_a and trusted_b:
+        g = math.sqrt(a * b)
+        return g, 1.0 + 2.0 * g / (a + b)
+    if trusted_a:
+        return a, 1.9
+    if trusted_b:
+        return b, 1.1
+    return rho, 1.5
 
-    v-hat = v^k + rho (y^k - s^{k+1}), with y^k the y before this iteration's
-    update.  Against the previous call's snapshot: dh = s - s0,
-    dvh = vhat - vhat0, dg = -(y^{k+1} - y0), dv = v^{k+1} - v0; both pairs go
-    through the correlation test and the spectral estimate; the four cases
-    give (sqrt(a b), 1 + 2 sqrt(a b)/(a + b)), (a, 1.9), (b, 1.1) or
-    (rho, 1.5).  Without a snapshot (first call) rho and gamma are kept.
-    Returns (rho, gamma, new snapshot)."""
+
+def adapt_rho_gamma(s, y_old, y_new, v_old, v_new, rho, gamma, snap, eps_corr=0.3):
+    """One adaptation of (rho_i, gamma_i) for one set.
+
+    The two dual pieces are probed through their iterates: the unrelaxed
+    multiplier v-hat = v^k + rho (y^k - s^{k+1}) against s = A_i x^{k+1}
+    (the x-side piece), and v^{k+1} against -y^{k+1} (the y-side piece), y^k
+    being y before this iteration's update.  Their differences since the
+    snapshot of the previous adaptation give the two curvature estimates
+    (_spectral), which set the new penalty and relaxation
+    (_penalty_relaxation).  The first adaptation has no snapshot and keeps
+    (rho, gamma).  Returns (rho, gamma, the snapshot for the next
+    adaptation)."""
     vhat = v_old + rho * (y_old - s)
     new_snap = Snapshot(vhat=vhat.copy(), v=v_new.copy(), s=s.copy(), y=y_new.copy())
     if snap is None:
         return rho, gamma, new_snap
-    dh = s - snap.s
-    dvh = vhat - snap.vhat
-    dg = -(y_new - snap.y)
-    dv = v_new - snap.v
-    ok_a, a = _spectral(dh, dvh, eps_corr)
-    ok_b, b = _spectral(dg, dv, eps_corr)
-    if ok_a and ok_b:
-        g = math.sqrt(a * b)
-        return g, 1.0 + 2.0 * g / (a + b), new_snap
-    if ok_a:
-        return a, 1.9, new_snap
-    if ok_b:
-        return b, 1.1, new_snap
-    return rho, 1.5, new_snap
+    trusted_a, a = _spectral(s - snap.s, vhat - snap.vhat, eps_corr)
+    trusted_b, b = _spectral(-(y_new - snap.y), v_new - snap.v, eps_corr)
+    rho_new, gamma_new = _penalty_relaxation(trusted_a, a, trusted_b, b, rho)
+    return rho_new, gamma_new, new_snap
 
 
 def guard_parameters(rho, gamma, opts: Options):
