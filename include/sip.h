@@ -47,7 +47,8 @@ typedef enum {
   SIP_EHIP = -3,         /* a HIP runtime call failed */
   SIP_ENUMERIC = -4,     /* non-finite input/iterate or CG breakdown (p^T C p <= 0) */
   SIP_EUNSUPPORTED = -5, /* combination the library does not implement */
-  SIP_EBUDGET = -6       /* batch: no free slot or not enough arena memory; plan: workspace too small */
+  SIP_EBUDGET = -6,      /* batch: no free slot or not enough arena memory; plan: workspace too small */
+  SIP_ETOOLARGE = -7     /* sip_project_noalloc: the instance needs more than its fixed device array */
 } sip_status;
 
 typedef enum { SIP_F32 = 0, SIP_F64 = 1 } sip_dtype;
@@ -425,6 +426,23 @@ int32_t sip_plan_result(sip_plan* p, sip_result* res, void* stream);
 int64_t sip_state_bytes(const sip_plan* p);
 int32_t sip_state_export(sip_plan* p, void* dst_dev, void* stream);
 int32_t sip_state_import(sip_plan* p, const void* src_dev, void* stream);
+
+/* ------------------------------------------------------ allocation-free form
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * projection of sip_project with the default tiles, whose every device
+ * buffer (descriptor, scalars, instance state, work tables, partial sums,
+ * selection histograms) is carved from a fixed 128 MiB device array of the
+ * library (one per GPU, held until the process ends).  It makes no HIP
+ * allocation (no hipMalloc, hipHostMalloc, hipFree, stream or graph
+ * creation) and launches the iterations directly on `stream`; host-side
+ * bookkeeping uses ordinary heap memory.  SIP_ETOOLARGE when the instance
+ * needs more than the array (sip_plan_bytes with default tiles above
+ * 128 MiB; e.g. a 341 x 1361 grid with four sets needs about 70 MiB).
+ * Blocking.  Every call on a GPU reuses that GPU's array, so calls that
+ * overlap on one GPU (other threads, other streams) race: serialise them. */
+int32_t sip_project_noalloc(const sip_grid* g, const sip_set* sets, int32_t nsets, const sip_opts* o,
+                            const void* m_dev, void* x_dev, sip_result* res, void* stream);
 
 #ifdef __cplusplus
 }

@@ -8,10 +8,17 @@
 #include <cstring>
 #include <initializer_list>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include "sip_internal.h"
+
+// Device memory of sip_project_noalloc: every call on a GPU carves its
+// descriptor, scalars, instance workspace, work tables and partial sums
+// from this array (one copy per GPU, held until the process ends).
+static constexpr long long kScratchBytes = 128ll << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace sip {
 
@@ -953,6 +960,28 @@ int32_t restart_plan(sip_plan* p, const void* m_dev, void* x_dev, hipStream_t st
   return start_slot(p->b, p->slot, m_dev, stream);
 }
 
+// The allocation-free entry point's device memory: a fixed array in every
+// GPU's copy of the code object, found once per device by its symbol
+// address (the array's name in host code is only a host-side stand-in).
+constexpr int kMaxDevices = 64;
+char* g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+int32_t scratch_of_device(char** out) {
+  int dev = -1;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return SIP_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return SIP_EHIP;
+    g_scratch[dev] = (char*)ptr;
+  }
+  *out = g_scratch[dev];
+  return SIP_OK;
+}
+
 int32_t read_scal(sip_batch* b, hipStream_t stream) {
   HIP_OK(hipMemcpyAsync(b->h_scal, b->d_scal, (size_t)b->max_slots * S_COUNT * 8, hipMemcpyDeviceToHost, stream));
   HIP_OK(hipStreamSynchronize(stream));
@@ -977,6 +1006,7 @@ const char* sip_strerror(int32_t st) {
     case SIP_ENUMERIC: return "numerical failure (non-finite value or CG breakdown)";
     case SIP_EUNSUPPORTED: return "unsupported";
     case SIP_EBUDGET: return "batch full (slots or arena) or workspace too small";
+    case SIP_ETOOLARGE: return "instance too large for the fixed device array of the allocation-free entry point";
     default: return "unknown status";
   }
 }
@@ -1472,6 +1502,34 @@ int32_t sip_state_import(sip_plan* p, const void* src_dev, void* stream_) {
   HIP_OK(hipMemcpyAsync(s.ws, src + kStateX + align_up(s.N * (int64_t)esz), (size_t)s.L.total,
                         hipMemcpyDeviceToDevice, stream));
   return SIP_OK;
+}
+
+// ----------------------------------------------- allocation-free projection
+
+int32_t sip_project_noalloc(const sip_grid* g, const sip_set* sets, int32_t nsets, const sip_opts* o,
+                            const void* m_dev, void* x_dev, sip_result* res, void* stream_) {
+  const int32_t vr = validate(g, sets, nsets, o);
+  if (vr != SIP_OK) return vr;
+  if (!m_dev || !x_dev) return SIP_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  const TileCfg tc;
+  if (plan_bytes_of(*g, sets, nsets, *o, tc) > kScratchBytes) return SIP_ETOOLARGE;
+  char* base = nullptr;
+  int32_t rc = scratch_of_device(&base);
+  if (rc != SIP_OK) return rc;
+  sip_batch* b = nullptr;
+  rc = create_batch(&b, 1, layout_of(*g, sets, nsets, *o).total, o, base, kScratchBytes, true);
+  if (rc != SIP_OK) return rc;
+  rc = place_slot(b, 0, *g, sets, nsets, x_dev, stream);
+  if (rc == SIP_OK) rc = start_slot(b, 0, m_dev, stream);
+  if (rc == SIP_OK) rc = rebuild_tables(b, stream);
+  if (rc == SIP_OK) rc = run_to_end(b, std::min(o->max_iter, o->stop_every > 0 ? 5 * o->stop_every : 25), stream);
+  sip_result r{};
+  if (rc == SIP_OK) rc = sip_batch_result(b, 0, &r, stream_);
+  sip_batch_destroy(b);
+  if (rc != SIP_OK) return rc;
+  if (res) *res = r;
+  return r.status;
 }
 
 }  // extern "C"

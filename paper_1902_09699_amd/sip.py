@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libsip.so")
 
 MAX_SETS = 16
 
-OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED, EBUDGET = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED, EBUDGET, ETOOLARGE = 0, -1, -2, -3, -4, -5, -6, -7
 F32, F64 = 0, 1
 OPS = {"I": 0, "DZ": 1, "DY": 2, "DX": 3, "GRAD": 4, "LAT": 5}
 KINDS = {"bounds": 0, "l1": 1, "card": 2, "l2": 3, "annulus": 4}
@@ -144,6 +144,8 @@ def lib():
         "sip_state_bytes": (i64, [vp]),
         "sip_state_export": (i32, [vp, vp, vp]),
         "sip_state_import": (i32, [vp, vp, vp]),
+        "sip_project_noalloc": (i32, [C.POINTER(Grid), C.POINTER(Set), i32, C.POINTER(Opts), vp, vp,
+                                      C.POINTER(Result), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -161,7 +163,7 @@ def exported_symbols():
             "sip_batch_items", "sip_batch_reset", "sip_batch_time_kernel", "sip_stream_copy", "sip_level",
             "sip_restrict", "sip_project_multilevel", "sip_dykstra_update", "sip_tiles_default", "sip_plan_bytes",
             "sip_plan_create", "sip_plan_destroy", "sip_plan_project", "sip_plan_start", "sip_plan_iterate",
-            "sip_plan_result", "sip_state_bytes", "sip_state_export", "sip_state_import"]
+            "sip_plan_result", "sip_state_bytes", "sip_state_export", "sip_state_import", "sip_project_noalloc"]
 
 
 def strerror(status: int) -> str:
@@ -284,6 +286,26 @@ def project(m, sets, opts: Opts, x=None, h=None, stream=None):
     st = lib().sip_project(C.byref(g), arr, len(sets), C.byref(opts), C.c_void_p(m.data_ptr()),
                            C.c_void_p(x.data_ptr()), C.byref(res), _stream_ptr(stream))
     check(st, "sip_project")
+    return x, res.as_dict()
+
+
+def project_noalloc(m, sets, opts: Opts, x=None, h=None, stream=None):
+    """sip_project_noalloc: the projection of project() with every device
+    buffer taken from the library's fixed array (blocking).  Raises
+    SipError with ETOOLARGE when the instance does not fit it."""
+    import torch
+    shape = tuple(m.shape)
+    n = m.numel()
+    _check_tensor(m, n, opts, "m")
+    if x is None:
+        x = torch.empty_like(m)
+    _check_tensor(x, n, opts, "x")
+    g = make_grid(shape, h)
+    arr = make_sets(sets)
+    res = Result()
+    st = lib().sip_project_noalloc(C.byref(g), arr, len(sets), C.byref(opts), C.c_void_p(m.data_ptr()),
+                                   C.c_void_p(x.data_ptr()), C.byref(res), _stream_ptr(stream))
+    check(st, "sip_project_noalloc")
     return x, res.as_dict()
 
 
