@@ -85,7 +85,7 @@ def test_free_running_f64(kind):
     np.testing.assert_allclose(res["rho"], st.rho, rtol=1e-7)
 
 
-@pytest.mark.parametrize("kind", ["box_tv_2d", "four_sets_2d", "box_tv_lat_3d", "mixed_2d"])
+@pytest.mark.parametrize("kind", ["box_tv_2d", "four_sets_2d", "box_tv_lat_3d", "mixed_2d", "mixed_3d"])
 def test_schedule_locked_f32(kind):
     """Float32 end to end against the FP64 oracle replaying the device's
     (rho, gamma) schedule and, for cardinality sets, its kept rows (each
