@@ -39,6 +39,13 @@ using acc_t = SIP_ACC;
 // stay resident per CU (latency hiding on many small items).
 constexpr int kSB = 256;
 constexpr int kSW = kSB / 64;
+// Rounds of 16-byte groups a refine-pass thread loads before it bins any
+// (the pass has no store to overlap with: without this each round is one
+// memory round trip).
+#ifndef SIP_REFINE_ROUNDS
+#define SIP_REFINE_ROUNDS 2
+#endif
+constexpr int kRefineRounds = SIP_REFINE_ROUNDS;
 
 // ---------------------------------------------------------------- helpers
 
@@ -2202,7 +2209,10 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
   uint32_t* __restrict__ cix = it.src == 0 ? s.cand_ix : nullptr;  // cardinality: where each candidate lies
   unsigned long long* ncand = &s.sel[it.src]->ncand;
   constexpr int W = Grp<T>::W;
-  constexpr int CB = W == 4 ? 3 : 2;  // bits of a per-thread hit count (0..W)
+  // bits of a per-thread hit count (0 .. kRefineRounds * W)
+  constexpr int CB = kRefineRounds * W < 2 ? 1 : (kRefineRounds * W < 4 ? 2 : (kRefineRounds * W < 8 ? 3 :
+                     (kRefineRounds * W < 16 ? 4 : (kRefineRounds * W < 32 ? 5 : 6))));
+  static_assert(kRefineRounds * W <= 32, "hit mask bits");
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int end = it.begin + it.len;
@@ -2211,10 +2221,14 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
   for (int c = 0; c < s.ncomp; ++c) {
     const int axis = s.axis[c];
     const T* __restrict__ y = (const T*)s.y + (size_t)c * g.cs;
-    for (int base = it.begin; base < end; base += kSB * W) {
-      const int P0 = base + (int)threadIdx.x * W;
-      T val[W];
-      bool ok[W];
+    for (int base0 = it.begin; base0 < end; base0 += kSB * W * kRefineRounds) {
+    T valr[kRefineRounds][W];
+    bool okr[kRefineRounds][W];
+#pragma unroll
+    for (int r = 0; r < kRefineRounds; ++r) {
+      const int P0 = base0 + r * kSB * W + (int)threadIdx.x * W;
+      T (&val)[W] = valr[r];
+      bool (&ok)[W] = okr[r];
       if (grouped) {
         const GLane L = glane<T>(P0, it.begin, end, g);
         if (it.src == 1) {
@@ -2245,20 +2259,26 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
           }
         }
       }
-      K key[W];
-      bool hit[W];
-      int nhit = 0;
+    }
+    // keys, hits and the histogram of every round; the hits of all rounds
+    // are appended with one block prefix and one global atomic
+    K keyr[kRefineRounds][W];
+    uint32_t hitm = 0;  // bit r * W + e: round r, element e is a hit
+    int nhit = 0;
+#pragma unroll
+    for (int r = 0; r < kRefineRounds; ++r) {
       int cur = -1;
       uint32_t run = 0;
       acc_t rsum = 0;
 #pragma unroll
       for (int e = 0; e < W; ++e) {
-        key[e] = KT::key(val[e]);
-        hit[e] = ok[e] && (K)(key[e] >> shp) == want;
-        if (hit[e]) {
+        const K key = KT::key(valr[r][e]);
+        keyr[r][e] = key;
+        if (okr[r][e] && (K)(key >> shp) == want) {
+          hitm |= 1u << (r * W + e);
           ++nhit;
           // runs of equal buckets merged into one update (exact sums for float keys)
-          const int bkt = (int)((key[e] >> sh) & (K)(nb - 1));
+          const int bkt = (int)((key >> sh) & (K)(nb - 1));
           if (bkt != cur) {
             if (run) {
               atomicAdd(&hc[cur], run);
@@ -2269,45 +2289,49 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
             rsum = 0;
           }
           ++run;
-          rsum += (acc_t)KT::value(key[e]);
+          rsum += (acc_t)KT::value(key);
         }
       }
       if (run) {
         atomicAdd(&hc[cur], run);
         if (l1) atomicAdd(&hs[cur], rsum);
       }
-      if (compact) {
-        // block-aggregated append: wave prefix of the per-thread hit counts
-        // (one ballot per count bit), one atomic for the block
-        unsigned long long pre = 0, tot = 0;
+    }
+    if (compact) {
+      // block-aggregated append: wave prefix of the per-thread hit counts
+      // (one ballot per count bit), one atomic for the block
+      unsigned long long pre = 0, tot = 0;
 #pragma unroll
-        for (int bit = 0; bit < CB; ++bit) {
-          const unsigned long long m = __ballot((nhit >> bit) & 1);
-          pre += (unsigned long long)__popcll(m & below) << bit;
-          tot += (unsigned long long)__popcll(m) << bit;
-        }
-        if (lane == 0) wcnt[wv] = (uint32_t)tot;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-          unsigned long long t = 0;
-          for (int q = 0; q < kSW; ++q) t += wcnt[q];
-          bbase = t ? atomicAdd(ncand, t) : 0ull;
-        }
-        __syncthreads();
-        if (nhit) {
-          unsigned long long off = bbase + pre;
-          for (int q = 0; q < wv; ++q) off += wcnt[q];
-          const uint32_t code = (uint32_t)iti * 3u + (uint32_t)c;
+      for (int bit = 0; bit < CB; ++bit) {
+        const unsigned long long m = __ballot((nhit >> bit) & 1);
+        pre += (unsigned long long)__popcll(m & below) << bit;
+        tot += (unsigned long long)__popcll(m) << bit;
+      }
+      if (lane == 0) wcnt[wv] = (uint32_t)tot;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int q = 0; q < kSW; ++q) t += wcnt[q];
+        bbase = t ? atomicAdd(ncand, t) : 0ull;
+      }
+      __syncthreads();
+      if (nhit) {
+        unsigned long long off = bbase + pre;
+        for (int q = 0; q < wv; ++q) off += wcnt[q];
+        const uint32_t code = (uint32_t)iti * 3u + (uint32_t)c;
+#pragma unroll
+        for (int r = 0; r < kRefineRounds; ++r) {
 #pragma unroll
           for (int e = 0; e < W; ++e) {
-            if (hit[e]) {
+            if (hitm & (1u << (r * W + e))) {
               if (cix) cix[off] = code;
-              cand[off++] = key[e];
+              cand[off++] = keyr[r][e];
             }
           }
         }
-        __syncthreads();
       }
+      __syncthreads();
+    }
     }
   }
   __syncthreads();
