@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--c3-steps", type=int, default=2)
     ap.add_argument("--served-requests", type=int, default=100)
     ap.add_argument("--served-rate", type=float, default=200.0)
+    ap.add_argument("--served-check", type=int, default=3,
+                    help="smallest served requests rerun alone and compared with the oracle")
     return ap.parse_args()
 
 
@@ -291,14 +293,15 @@ def c3_leg(args):
 
 def served_leg(args):
     """The served mix (Poisson arrivals, 5% 3D, stopping rule on, continuous
-    batching) and the plain one-at-a-time form on the same requests."""
+    batching in two resident batches split by size) and the plain
+    one-at-a-time form on the same requests."""
     from paper_1902_09699_amd import serve
     opts = serve.serving_opts(200)
     arena = 64 << 30
     n, rate = args.served_requests, args.served_rate
     say(f"served: {n} requests at {rate:g} req/s")
     warm = serve.make_requests(4, 1e9, 0.0, seed0=9000, max2d=128)
-    srv = serve.Server(opts, arena, 256, 10)
+    srv = serve.Server(opts, arena, 256, 10, lanes=2, split_points=1 << 18)
     srv.run(warm, realtime=False)
     reqs = serve.make_requests(n, rate)
     info = srv.run(reqs, realtime=True)
@@ -312,6 +315,7 @@ def served_leg(args):
     plain.update(pinfo)
     offered = sum(r.m.size for r in reqs) / max(reqs[-1].arrival - reqs[0].arrival, 1e-9)
     return {"requests": n, "rate_per_s": rate, "frac_3d": 0.05, "offered_grid_pts_per_s": round(offered, 1),
+            "server": "two resident batches on two streams (requests up to 2^18 points / larger), chunks of 10",
             "stopping": "eqs. feas_stop/obj_stop every 5 it, cap 200, CG cap 10 at 0.1 relative residual",
             "served": served, "plain": plain,
             "speedup_instances_per_s": round(served["instances_per_s"] / max(plain["instances_per_s"], 1e-9), 2)}
@@ -336,15 +340,19 @@ def copy_reference(mb):
     return {"bytes_moved": 2 * n * 4, "ms": round(t, 4), "GBs": round(2 * n * 4 / (t * 1e-3) / 1e9, 1)}
 
 
-def device_logged(inst, field, reduce, tiles, iters):
+def device_logged(inst, field, reduce, tiles, iters, stop_every=0):
     """One instance alone on the device (tiles and CG form as timed; results
     are bit-identical alone and in a batch), one iteration at a time: its x,
-    the (rho, gamma) of every iteration and the rows every whole-vector
-    cardinality set kept (operator row order)."""
+    the (rho, gamma) and CG step count of every iteration, the rows every
+    whole-vector cardinality set kept (operator row order) and the result.
+    stop_every > 0: the served options (stopping rule on, relative CG stop)."""
     import torch
     from paper_1902_09699_amd import sip
     m, sets = inst
-    opts = sip.make_opts(field, reduce=reduce, max_iter=iters, cg_max=10, cg_fixed=1)
+    if stop_every:
+        opts = sip.make_opts(field, reduce=reduce, max_iter=iters, cg_max=10, cg_fixed=0, stop_every=stop_every)
+    else:
+        opts = sip.make_opts(field, reduce=reduce, max_iter=iters, cg_max=10, cg_fixed=1)
     md = torch.tensor(m, dtype=torch.float64 if field == "f64" else torch.float32, device="cuda")
     xd = torch.empty_like(md)
     b = sip.Batch(1, sip.workspace_bytes(m.shape, sets, opts), opts)
@@ -353,16 +361,24 @@ def device_logged(inst, field, reduce, tiles, iters):
     slot = b.add(md, sets, xd)
     card = [i for i, s in enumerate(sets) if s["kind"] == "card" and s.get("line") is None]
     sched, sup = {}, {}
+    cg_before = 0
     for _ in range(iters):
         rho, gam, k, _ = b.get_params(slot)
         b.run(1)
-        sched[k] = (rho.copy(), gam.copy())
+        res = b.result(slot)
+        if res["iters"] < k:
+            break  # finished before this iteration
+        sched[k] = (rho.copy(), gam.copy(), res["cg_steps"] - cg_before)
+        cg_before = res["cg_steps"]
         if card:
             sup[k] = {i: np.nonzero(b.rows(slot, sip.FIELD_Y, i, m.shape, sets[i]["op"]))[0] for i in card}
+        if b.poll()[slot] == 1:
+            break
     torch.cuda.synchronize()
+    res = b.result(slot)
     x = xd.double().cpu().numpy()
     b.close()
-    return x, sched, sup
+    return x, sched, sup, res
 
 
 # ------------------------------------------------------------------ CPU leg
@@ -444,25 +460,31 @@ def pick_sample(insts, count):
     return sorted(pick[:count])
 
 
-def oracle_errors(insts, field, reduce, tiles, iters, count):
+def oracle_errors(insts, field, reduce, tiles, iters, count, picks=None, stop_every=0):
     """Relative L2 error of x after `iters` iterations for a sample of
     instances; the oracle replays each device run's (rho, gamma) schedule
-    and, for cardinality sets, its kept rows, each checked to be a valid
-    top-k choice of the oracle's own w within CARD_BAND of the k-th
-    magnitude (equal choices within the band are ties)."""
+    (and, with the relative CG stop, its CG step counts) and, for
+    cardinality sets, its kept rows, each checked to be a valid top-k choice
+    of the oracle's own w within CARD_BAND of the k-th magnitude (equal
+    choices within the band are ties).  stop_every > 0: the served options;
+    the oracle then also stops by its own stopping test, and the iteration
+    counts of both sides are reported."""
     from oracle import parsdmm as orc
     out = []
-    for j in pick_sample(insts, count):
+    for j in (picks if picks is not None else pick_sample(insts, count)):
         m, sets = insts[j]
-        x, sched, sup = device_logged(insts[j], field, reduce, tiles, iters)
+        x, sched, sup, res = device_logged(insts[j], field, reduce, tiles, iters, stop_every)
         prob = orc.Problem(m, m.shape, sets)
-        oo = orc.Options(max_iter=iters, cg_max=10, cg_fixed=True)
+        if stop_every:
+            oo = orc.Options(max_iter=iters, cg_max=10, cg_fixed=False, stop_every=stop_every)
+        else:
+            oo = orc.Options(max_iter=iters, cg_max=10, cg_fixed=True)
         st = orc.initial_state(prob, oo)
         valid, differ, worst = True, 0, 0.0
         card = [i for i, s in enumerate(sets) if s["kind"] == "card" and s.get("line") is None]
-        while st.k <= iters:
+        while st.k <= iters and st.k in sched:
             k = st.k
-            orc.iterate(prob, st, oo, sched, sup or None)
+            stop = orc.iterate(prob, st, oo, sched, sup or None)
             for i in card:
                 a = np.abs(st.w_last[i])
                 kk = sets[i]["k"]
@@ -476,10 +498,17 @@ def oracle_errors(insts, field, reduce, tiles, iters, count):
                 differ += int(diff.size)
                 if diff.size:
                     worst = max(worst, float(np.max(np.abs(a[diff] - tk)) / max(tk, 1e-300)))
+            if stop:
+                st.converged = True
+                break
         xo = st.x
         err = float(np.linalg.norm(x.ravel() - xo) / max(np.linalg.norm(xo), 1e-300))
+        extra = {}
+        if stop_every:
+            extra = {"device_iterations": res["iters"], "oracle_iterations": st.k - 1,
+                     "device_converged": bool(res["converged"]), "oracle_converged": bool(st.converged)}
         out.append({"instance": j, "shape": list(m.shape), "sets": [f"{s['kind']}({s['op']})" for s in sets],
-                    "iterations": iters, "rel_l2_x": err,
+                    "iterations": res["iters"] if stop_every else iters, "rel_l2_x": err, **extra,
                     **({"card_supports_valid": bool(valid), "card_rows_differing_from_oracle_choice": differ,
                         "card_max_rel_distance_from_tk": worst} if card else {})})
     return out
@@ -523,6 +552,15 @@ def main():
             say(f"oracle errors: {args.check_instances} instance(s), {args.check_iters} iterations")
             errors = oracle_errors(insts, field, args.reduce, tiles, min(args.check_iters, iters),
                                    args.check_instances)
+        if served is not None and args.served_check > 0:
+            # the served results are bit-identical to the same request alone:
+            # the smallest requests rerun alone with logging, against the oracle
+            from paper_1902_09699_amd import serve
+            reqs = serve.make_requests(args.served_requests, args.served_rate)
+            small = sorted(range(len(reqs)), key=lambda j: reqs[j].m.size)[:args.served_check]
+            say(f"oracle errors of served requests {small}")
+            sinst = [(r.m, r.sets) for r in reqs]
+            served["oracle_error"] = oracle_errors(sinst, "f32", "f64", None, 200, 0, picks=small, stop_every=5)
 
     line = {
         "metric": METRIC,

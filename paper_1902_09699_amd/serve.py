@@ -6,9 +6,12 @@ arena bytes are free (exact sizes from sip_workspace_bytes); every admitted
 instance keeps its whole state on the device; the batch advances all
 instances together by `chunk` iterations (one captured HIP graph replay),
 after which finished instances (stopping test passed or iteration cap) are
-retired, their x copied out and their workspace returned to the arena.  The
-plain form serves the same requests one at a time through the same engine
-(a one-slot batch).
+retired, their x copied out and their workspace returned to the arena.  Two
+resident batches, one for small and one for large requests, run on two
+streams: small requests are not held to the pace of large ones, and the host
+serves one batch's admissions and retirements while the other computes.
+The plain form serves the same requests one at a time through the same
+engine (a one-slot batch).
 
     python -m paper_1902_09699_amd.serve --requests 400 --rate 200
 """
@@ -61,75 +64,126 @@ def serving_opts(max_iter=200, stop_every=5, cg_max=10):
     return sip.make_opts("f32", max_iter=max_iter, cg_max=cg_max, cg_fixed=0, stop_every=stop_every)
 
 
-class Server:
-    """Continuous batching over one resident batch."""
+class Lane:
+    """One resident batch advanced on its own stream."""
 
-    def __init__(self, opts, arena_bytes, max_slots=256, chunk=10):
+    def __init__(self, opts, arena_bytes, max_slots, stream):
+        self.batch = sip.Batch(max_slots, arena_bytes, opts)
+        self.arena_bytes = int(arena_bytes)
+        self.stream = stream
+        self.active = {}
+        self.pending = collections.deque()
+        self.in_use = 0
+        self.event = None  # recorded after the chunk in flight
+
+
+class Server:
+    """Continuous batching over resident batches ("lanes").  With two lanes,
+    requests of at most `split_points` grid points go to one batch and larger
+    ones to the other; each lane runs its chunks on its own stream, so small
+    requests iterate at their own pace while large ones are on the GPU, and
+    the host admits and retires on one lane while the other computes."""
+
+    def __init__(self, opts, arena_bytes, max_slots=256, chunk=10, lanes=1, split_points=1 << 18):
+        import torch
         self.opts = opts
         self.chunk = int(chunk)
         self.arena_bytes = int(arena_bytes)
-        self.batch = sip.Batch(max_slots, arena_bytes, opts)
+        self.split_points = int(split_points)
         self.max_slots = max_slots
+        n = int(lanes)
+        if n not in (1, 2):
+            raise ValueError("lanes must be 1 or 2")
+        per = self.arena_bytes // n
+        streams = [torch.cuda.current_stream()] if n == 1 else [torch.cuda.Stream() for _ in range(n)]
+        self.lanes = [Lane(opts, per, max_slots, st) for st in streams]
+        self.batch = self.lanes[0].batch  # the one batch of a single-lane server
 
     def close(self):
-        self.batch.close()
+        for ln in self.lanes:
+            ln.batch.close()
+
+    def _lane_of(self, r):
+        if len(self.lanes) == 1:
+            return self.lanes[0]
+        return self.lanes[0] if r.m.size <= self.split_points else self.lanes[1]
 
     def run(self, requests, realtime=True, log=None, on_chunk=None, on_done=None):
         """Serve `requests` (arrival order; with realtime=False every request
         counts as arrived).  on_chunk(batch, active) is called after every
-        chunk, before finished instances retire; on_done(batch, slot,
-        request) just before a finished instance is removed."""
+        chunk of a lane, before its finished instances retire; on_done(batch,
+        slot, request) just before a finished instance is removed."""
         import torch
         reqs = sorted(requests, key=lambda r: r.arrival)
-        pending = collections.deque(reqs)
-        active = {}
+        arrivals = collections.deque(reqs)
         rejected = []
         peak_bytes = 0
-        in_use = 0
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0  # noqa: E731
         chunks = 0
-        while pending or active:
+
+        def in_use():
+            return sum(ln.in_use for ln in self.lanes)
+
+        while arrivals or any(ln.pending or ln.active for ln in self.lanes):
             t = now()
-            # admit every arrived request that fits, in arrival order
-            while pending and (pending[0].arrival <= t or not realtime):
-                r = pending[0]
-                need = sip.workspace_bytes(r.m.shape, r.sets, self.opts)
-                if need > self.arena_bytes:
-                    rejected.append(pending.popleft())
-                    continue
-                md = torch.tensor(r.m, dtype=torch.float32, device="cuda")
-                xd = torch.empty_like(md)
-                slot = self.batch.add(md, r.sets, xd)
-                if slot < 0:
-                    if not active:  # cannot fit even into an empty batch
-                        rejected.append(pending.popleft())
+            while arrivals and (arrivals[0].arrival <= t or not realtime):
+                r = arrivals.popleft()
+                self._lane_of(r).pending.append(r)
+            busy = 0
+            for ln in self.lanes:
+                if ln.event is not None:
+                    if not ln.event.query():
+                        busy += 1
+                        continue  # its chunk is still on the GPU
+                    ln.event = None
+                    chunks += 1
+                    if on_chunk:
+                        on_chunk(ln.batch, ln.active)
+                    done = ln.batch.poll(stream=ln.stream)
+                    for slot, flag in enumerate(done):
+                        if flag == 1 and slot in ln.active:
+                            r, md, xd, need = ln.active.pop(slot)
+                            if on_done:
+                                on_done(ln.batch, slot, r)
+                            r.result = ln.batch.remove(slot, stream=ln.stream)
+                            r.x = xd.cpu().numpy()
+                            r.t_done = now()
+                            ln.in_use -= need
+                            if log:
+                                log(r)
+                # admit this lane's arrived requests that fit, in arrival order
+                while ln.pending:
+                    r = ln.pending[0]
+                    need = sip.workspace_bytes(r.m.shape, r.sets, self.opts)
+                    if need > ln.arena_bytes:
+                        rejected.append(ln.pending.popleft())
                         continue
-                    break  # no slot or arena room: wait for a retirement
-                r.t_admit = now()
-                active[slot] = (r, md, xd, need)
-                in_use += need
-                peak_bytes = max(peak_bytes, in_use)
-                pending.popleft()
-            if active:
-                self.batch.run(self.chunk)
-                chunks += 1
-                if on_chunk:
-                    on_chunk(self.batch, active)
-                done = self.batch.poll()
-                for slot, flag in enumerate(done):
-                    if flag == 1 and slot in active:
-                        r, md, xd, need = active.pop(slot)
-                        if on_done:
-                            on_done(self.batch, slot, r)
-                        r.result = self.batch.remove(slot)
-                        r.x = xd.cpu().numpy()
-                        r.t_done = now()
-                        in_use -= need
-                        if log:
-                            log(r)
-            elif pending and realtime:
-                time.sleep(max(0.0, pending[0].arrival - now()))
+                    md = torch.tensor(r.m, dtype=torch.float32, device="cuda")
+                    xd = torch.empty_like(md)
+                    slot = ln.batch.add(md, r.sets, xd, stream=ln.stream)
+                    if slot < 0:
+                        if not ln.active:  # cannot fit even into an empty batch
+                            rejected.append(ln.pending.popleft())
+                            continue
+                        break  # no slot or arena room: wait for a retirement
+                    r.t_admit = now()
+                    ln.active[slot] = (r, md, xd, need)
+                    ln.in_use += need
+                    peak_bytes = max(peak_bytes, in_use())
+                    ln.pending.popleft()
+                if ln.active:
+                    with torch.cuda.stream(ln.stream):
+                        ln.batch.run(self.chunk, stream=ln.stream)
+                        ln.event = torch.cuda.Event()
+                        ln.event.record(ln.stream)
+                    busy += 1
+            if busy == 0:
+                # nothing resident anywhere: wait for the next arrival
+                if arrivals and realtime:
+                    time.sleep(max(0.0, arrivals[0].arrival - now()))
+            else:
+                time.sleep(20e-6)  # chunks in flight: look again shortly
         return {"chunks": chunks, "peak_arena_bytes": peak_bytes, "rejected": len(rejected)}
 
 
@@ -137,7 +191,7 @@ def serve_plain(requests, opts, arena_bytes, chunk=10):
     """The plain per-instance form: the same engine with one slot, so each
     request runs alone, in arrival order (graphs are reused across requests
     whose work tables fit the same launch sizes)."""
-    srv = Server(opts, arena_bytes, max_slots=1, chunk=chunk)
+    srv = Server(opts, arena_bytes, max_slots=1, chunk=chunk, lanes=1)
     srv.run(make_requests(2, 1e9, 0.0, seed0=9100, max2d=128), realtime=False)
     info = srv.run(requests, realtime=True)
     srv.close()
@@ -172,6 +226,7 @@ def main():
     ap.add_argument("--plain", action="store_true", help="also serve the same requests one at a time")
     ap.add_argument("--plain-requests", type=int, default=0, help="requests for the plain form (0: same)")
     ap.add_argument("--check", type=int, default=8, help="requests re-run alone to compare results")
+    ap.add_argument("--lanes", type=int, default=2, help="resident batches (1, or 2 split by size)")
     a = ap.parse_args()
     import torch
     opts = serving_opts(a.max_iter)
@@ -181,7 +236,7 @@ def main():
           flush=True)
     # warm the code objects and graph capture on a few small requests
     warm = make_requests(4, 1e9, 0.0, seed0=9000, max2d=128)
-    srv = Server(opts, int(a.arena_gb * (1 << 30)), a.slots, a.chunk)
+    srv = Server(opts, int(a.arena_gb * (1 << 30)), a.slots, a.chunk, lanes=a.lanes)
     srv.run(warm, realtime=False)
     t = time.perf_counter()
     info = srv.run(reqs, realtime=True)

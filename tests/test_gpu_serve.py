@@ -13,18 +13,22 @@ def _small_mix(n):
     return serve.make_requests(n, rate=1e9, frac3d=0.25, seed0=5000, max2d=96, side3d=(12, 20))
 
 
-@pytest.mark.parametrize("chunk", [5, 10, 7])
-def test_served_results_equal_alone_and_respect_the_arena(chunk):
+@pytest.mark.parametrize("chunk,lanes", [(5, 1), (10, 1), (7, 1), (5, 2), (10, 2)])
+def test_served_results_equal_alone_and_respect_the_arena(chunk, lanes):
+    """With two lanes the small requests (at most 5000 points here) and the
+    large ones run in two resident batches on two streams."""
     import torch
     opts = serve.serving_opts(max_iter=60)
     reqs = _small_mix(14)
     need = [sip.workspace_bytes(r.m.shape, r.sets, opts) for r in reqs]
-    arena = 3 * max(need)          # forces queueing: at most a few fit at once
-    srv = serve.Server(opts, arena, max_slots=4, chunk=chunk)
+    arena = 3 * max(need) * lanes  # forces queueing: at most a few fit at once (per lane)
+    srv = serve.Server(opts, arena, max_slots=4, chunk=chunk, lanes=lanes, split_points=5000)
     info = srv.run(reqs, realtime=False)
     srv.close()
-    print(f"\n[serve] chunk {chunk}: peak arena {info['peak_arena_bytes']} of {arena}, chunks {info['chunks']}",
-          flush=True)
+    if lanes == 2:
+        assert any(r.m.size <= 5000 for r in reqs) and any(r.m.size > 5000 for r in reqs)
+    print(f"\n[serve] chunk {chunk}, lanes {lanes}: peak arena {info['peak_arena_bytes']} of {arena}, "
+          f"chunks {info['chunks']}", flush=True)
     assert info["rejected"] == 0
     assert info["peak_arena_bytes"] <= arena
     assert all(r.result is not None and r.result["status"] == 0 for r in reqs)
