@@ -65,7 +65,9 @@ def parse():
     ap.add_argument("--extras", default="auto", choices=("auto", "on", "off"),
                     help="200x200x100 and served legs (auto: with the batched workload)")
     ap.add_argument("--c3-steps", type=int, default=2)
-    ap.add_argument("--served-requests", type=int, default=100)
+    ap.add_argument("--c3-check-iters", type=int, default=0,
+                    help="locked iterations of the 200x200x100 error check against the oracle (0: skip)")
+    ap.add_argument("--served-requests", type=int, default=200)
     ap.add_argument("--served-rate", type=float, default=200.0)
     ap.add_argument("--served-check", type=int, default=3,
                     help="smallest served requests rerun alone and compared with the oracle")
@@ -288,7 +290,7 @@ def c3_leg(args):
            "roofline": roofline_of(kernels, "smooth3d"),
            "kernels": {k: {"ms": round(v["ms"], 5), "GBs": round(v["GBs"], 1)} for k, v in kernels.items()}}
     run["batch"].close()
-    return out
+    return out, insts
 
 
 def served_leg(args):
@@ -300,7 +302,9 @@ def served_leg(args):
     arena = 64 << 30
     n, rate = args.served_requests, args.served_rate
     say(f"served: {n} requests at {rate:g} req/s")
-    warm = serve.make_requests(4, 1e9, 0.0, seed0=9000, max2d=128)
+    # warm both lanes (code objects, graph capture at their first sizes)
+    warm = serve.make_requests(4, 1e9, 0.0, seed0=9000, max2d=128) + \
+        serve.make_requests(2, 1e9, 1.0, seed0=9050, side3d=(66, 72))
     srv = serve.Server(opts, arena, 256, 10, lanes=2, split_points=1 << 18)
     srv.run(warm, realtime=False)
     reqs = serve.make_requests(n, rate)
@@ -538,7 +542,7 @@ def main():
     extras = args.extras == "on" or (args.extras == "auto" and args.workload == "batched")
     c3 = served = None
     if extras:
-        c3 = c3_leg(args)
+        c3, c3_insts = c3_leg(args)
         say(f"200x200x100: {c3['ms_per_step']:.3f} ms/step, iteration {c3['iteration']['frac']:.3f} of HBM peak")
         served = served_leg(args)
         say(f"served p50 {served['served']['p50_ms']} ms p99 {served['served']['p99_ms']} ms; "
@@ -552,6 +556,11 @@ def main():
             say(f"oracle errors: {args.check_instances} instance(s), {args.check_iters} iterations")
             errors = oracle_errors(insts, field, args.reduce, tiles, min(args.check_iters, iters),
                                    args.check_instances)
+        if c3 is not None and args.c3_check_iters > 0:
+            say(f"oracle error on 200x200x100: {args.c3_check_iters} iterations")
+            tiles3 = tuple(c3["tiles"]) if isinstance(c3["tiles"], list) else None
+            c3["oracle_error"] = oracle_errors(c3_insts, "f32", args.reduce, tiles3, args.c3_check_iters, 1,
+                                               picks=[0])
         if served is not None and args.served_check > 0:
             # the served results are bit-identical to the same request alone:
             # the smallest requests rerun alone with logging, against the oracle

@@ -39,6 +39,12 @@ using acc_t = SIP_ACC;
 // stay resident per CU (latency hiding on many small items).
 constexpr int kSB = 256;
 constexpr int kSW = kSB / 64;
+// The RHS and projection kernels are held to at most 96 registers, five
+// waves per SIMD (the compiler's own choice, 97-113 registers and four
+// waves, measured 2-4% slower on the 256-instance batch; six waves spill).
+#define SIP_SETS_ATTR __attribute__((amdgpu_waves_per_eu(5)))
+#define SIP_RHS_ATTR __attribute__((amdgpu_waves_per_eu(5)))
+
 // Rounds of 16-byte groups a refine-pass thread loads before it bins any
 // (the pass has no store to overlap with: without this each round is one
 // memory round trip).
@@ -444,6 +450,16 @@ __device__ __forceinline__ void st16(T* p, const T (&o)[Grp<T>::W]) {
   u32x4 u;
   __builtin_memcpy(&u, o, 16);
   *(g_u32x4*)p = u;
+}
+
+// A streaming store (non-temporal hint): for arrays not read again before
+// they would leave the caches (the projection and apply passes' y_i, v_i and
+// snapshots; 0.3-0.5% on the 256-instance batch).
+template <typename T>
+__device__ __forceinline__ void st16nt(T* p, const T (&o)[Grp<T>::W]) {
+  u32x4 u;
+  __builtin_memcpy(&u, o, 16);
+  __builtin_nontemporal_store(u, (g_u32x4*)p);
 }
 
 // The first W - 1 values of an aligned group (12 or 8 bytes).
@@ -1237,7 +1253,7 @@ __global__ __launch_bounds__(NT) void k_cg1_step(const InstDesc* __restrict__ D,
 // A_i^T of a forward difference needs u = rho y + v one point back along the
 // axis: the previous lane's last value for x, a window for y / z.
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_rhs(const InstDesc* __restrict__ D, const PtItem* __restrict__ items, double* rr_part) {
+__global__ __launch_bounds__(NT) SIP_RHS_ATTR void k_rhs(const InstDesc* __restrict__ D, const PtItem* __restrict__ items, double* rr_part) {
   constexpr int W = Grp<T>::W;
   __shared__ acc_t lds[lds_sum<1, NT>()];
   const PtItem it = items[blockIdx.x];
@@ -1489,8 +1505,8 @@ __device__ void proj_block(const InstDesc* __restrict__ D, const PtItem* __restr
             if (ok[e]) proj_point<T>(U, sv[e], yo[e], vo[e], ident ? mv[e] : (T)0, lb[e], ub[e], yn[e], vn[e], xbv[e]);
             else { yn[e] = yo[e]; vn[e] = vo[e]; xbv[e] = 0; }
           }
-          st16<T>(y + P0, yn);
-          st16<T>(v + P0, vn);
+          st16nt<T>(y + P0, yn);
+          st16nt<T>(v + P0, vn);
           if (adapt) {
             T vh[W];
 #pragma unroll
@@ -1511,9 +1527,9 @@ __device__ void proj_block(const InstDesc* __restrict__ D, const PtItem* __restr
                 acc[3] += dg * dv; acc[4] += dg * dg; acc[5] += dv * dv;
               }
             }
-            st16<T>(vh0 + P0, vh);
-            st16<T>(v0 + P0, vn);
-            st16<T>(y0 + P0, yn);
+            st16nt<T>(vh0 + P0, vh);
+            st16nt<T>(v0 + P0, vn);
+            st16nt<T>(y0 + P0, yn);
           }
           if (check && !ident) {
 #pragma unroll
@@ -1646,7 +1662,7 @@ __device__ void proj_block(const InstDesc* __restrict__ D, const PtItem* __restr
 }
 
 template <typename T>
-__global__ __launch_bounds__(kSB) void k_proj(const InstDesc* __restrict__ D, const PtItem* __restrict__ items, Opts o, double* parts) {
+__global__ __launch_bounds__(kSB) SIP_SETS_ATTR void k_proj(const InstDesc* __restrict__ D, const PtItem* __restrict__ items, Opts o, double* parts) {
   proj_block<T>(D, items, o, parts, (int)blockIdx.x, (int)blockIdx.y);
 }
 
@@ -1841,7 +1857,7 @@ __device__ void thrw_block(const InstDesc* __restrict__ D, const ThrItem* __rest
 }
 
 template <typename T>
-__global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, const ThrItem* __restrict__ items, Opts o, double* parts) {
+__global__ __launch_bounds__(kSB) SIP_SETS_ATTR void k_thr_w(const InstDesc* __restrict__ D, const ThrItem* __restrict__ items, Opts o, double* parts) {
   thrw_block<T>(D, items, o, parts, (int)blockIdx.x);
 }
 
@@ -1850,7 +1866,7 @@ __global__ __launch_bounds__(kSB) void k_thr_w(const InstDesc* __restrict__ D, c
 // blocks (the longer ones) come first, so they are dispatched in the first
 // wave of resident blocks and the projection blocks fill in behind them.
 template <typename T>
-__global__ __launch_bounds__(kSB) void k_sets(const InstDesc* __restrict__ D, const PtItem* __restrict__ sp, const ThrItem* __restrict__ thr, Opts o,
+__global__ __launch_bounds__(kSB) SIP_SETS_ATTR void k_sets(const InstDesc* __restrict__ D, const PtItem* __restrict__ sp, const ThrItem* __restrict__ thr, Opts o,
                                               double* proj_parts, double* thrw_parts, int nsp, int units, int nthr) {
   const int b = (int)blockIdx.x;
   if (b < nthr) thrw_block<T>(D, thr, o, thrw_parts, b);
@@ -2136,9 +2152,10 @@ __device__ __forceinline__ SelState load_sel(const SelState* p) {
 
 // Whether refine pass `pass` (0 or 1; 1 is the last pass of the iteration)
 // appends candidate keys: the first when digits remain after the one it
-// histograms and the bucket it refines is small, the last always.  The threshold is therefore always final in a
-// selection stage that holds the candidates, among them every entry equal to
-// the k-th magnitude (so that stage also counts the cardinality ties).
+// histograms and the bucket it refines is small, the last always.  The
+// threshold is therefore always final in a selection stage that holds the
+// candidates, among them every entry equal to the k-th magnitude (so that
+// stage also counts the cardinality ties).
 template <typename T>
 __device__ __forceinline__ bool pass_compacts(const SelState& st, int pass) {
   return pass == 1 || (st.compact_next && st.digit + 1 < KeyT<T>::ndig);
@@ -2599,8 +2616,8 @@ __device__ void apply_item(const InstDesc* __restrict__ D, const ThrItem* __rest
             yn[e] = r;
             vn[e] = ok[e] ? rho * (r - w[e]) : (T)0;
           }
-          st16<T>(y + P0, yn);
-          st16<T>(v + P0, vn);
+          st16nt<T>(y + P0, yn);
+          st16nt<T>(v + P0, vn);
           if (adapt) {
             if (have) {
               T a0[W], a1[W];
@@ -2614,8 +2631,8 @@ __device__ void apply_item(const InstDesc* __restrict__ D, const ThrItem* __rest
                 acc[3] += dg * dv; acc[4] += dg * dg; acc[5] += dv * dv;
               }
             }
-            st16<T>(y0 + P0, yn);
-            st16<T>(v0 + P0, vn);
+            st16nt<T>(y0 + P0, yn);
+            st16nt<T>(v0 + P0, vn);
           }
           continue;
         }
