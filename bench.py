@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--batched-count", type=int, default=256)
     ap.add_argument("--copy-mb", type=int, default=1024, help="plain-copy reference size (0: skip)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles")
+    ap.add_argument("--sel-fresh", type=int, default=0, choices=(0, 1),
+                    help="1: threshold selections read all of w (no reuse of the previous first digit)")
     ap.add_argument("--reduce", default="f64", choices=("f64", "f32"),
                     help="reduction type (f32: the pure-FP32 precision ablation)")
     ap.add_argument("--check-iters", type=int, default=40,
@@ -190,7 +192,7 @@ def run_timed(insts, field, iters, args, steps, warmup, tiles_arg=None, autotune
     import torch
     from paper_1902_09699_amd import sip
     dt = torch.float64 if field == "f64" else torch.float32
-    opts = sip.make_opts(field, reduce=args.reduce, max_iter=iters, cg_max=10, cg_fixed=1)
+    opts = sip.make_opts(field, reduce=args.reduce, max_iter=iters, cg_max=10, cg_fixed=1, sel_fresh=args.sel_fresh)
     ms = [torch.tensor(m, dtype=dt, device="cuda") for m, _ in insts]
     xs = [torch.empty_like(m) for m in ms]
     arena = sum(sip.workspace_bytes(m.shape, s, opts) for m, s in insts)
@@ -228,8 +230,13 @@ def run_timed(insts, field, iters, args, steps, warmup, tiles_arg=None, autotune
     results = [batch.result(sl) for sl in slots]
     assert all(r["status"] == 0 and r["iters"] == iters for r in results), results[:3]
     n_pts = sum(m.size for m, _ in insts)
+    # threshold selections of the last step that refined over the w pass's
+    # list A (the previous iteration's first-digit bucket)
+    n_sel = iters * sum(sum(1 for q in s if q["kind"] in ("l1", "card") and not q.get("line")) for _, s in insts)
+    reuse = {"reused": int(sum(r["sel_reused"] for r in results)), "selections": int(n_sel)}
     return {"batch": batch, "slots": slots, "ms": ms, "xs": xs, "tiles": tiles, "wall": wall,
-            "ms_step": 1e3 * wall / steps, "value": n_pts * iters * steps / wall, "n_pts": n_pts}
+            "ms_step": 1e3 * wall / steps, "value": n_pts * iters * steps / wall, "n_pts": n_pts,
+            "selection_reuse": reuse}
 
 
 def kernel_table(run, insts, field, reps):
@@ -287,6 +294,7 @@ def c3_leg(args):
            "ms_per_step": round(run["ms_step"], 3), "value": round(run["value"], 1),
            "tiles": list(run["tiles"]) if run["tiles"] else "default",
            "iteration": iteration_roofline(insts, field, iters, run["ms_step"]),
+           "selection_reuse": run["selection_reuse"],
            "roofline": roofline_of(kernels, "smooth3d"),
            "kernels": {k: {"ms": round(v["ms"], 5), "GBs": round(v["GBs"], 1)} for k, v in kernels.items()}}
     run["batch"].close()
@@ -588,6 +596,7 @@ def main():
                    "cg_steps": 10, "reductions": args.reduce, "tiles": list(tiles) if tiles else "default"},
         "roofline": roofline,
         "iteration": iteration_roofline(insts, field, iters, run["ms_step"]),
+        "selection_reuse": run["selection_reuse"],
         "kernels": {k: {"ms": round(v["ms"], 5), "GBs": round(v["GBs"], 1)} for k, v in kernels.items()},
         "cpu_baseline": cpu,
         "oracle_error": errors,

@@ -135,6 +135,10 @@ typedef struct {
                            norms, adapt dots, l1 bucket and prefix sums): SIP_F64 (default), or
                            SIP_F32 with field SIP_F32 (the pure-FP32 precision ablation) */
   int32_t log_schedule; /* 1: record (rho, gamma) of every iteration (sip_batch_schedule) */
+  int32_t sel_fresh;    /* 1: every threshold selection reads all of w in its refine passes; 0
+                           (default): the w pass also gathers the entries of the previous
+                           iteration's first-digit bucket, and a selection whose first digit falls in
+                           that bucket refines over them alone.  The same results either way. */
 } sip_opts;
 
 typedef struct {
@@ -143,7 +147,8 @@ typedef struct {
   int32_t cg_steps;   /* CG steps run, summed over iterations */
   int32_t converged;  /* 1 when the stopping test passed */
   int32_t nsets;
-  int32_t reserved;
+  int32_t sel_reused; /* threshold selections (pipelines x iterations) that refined over the
+                         entries the w pass gathered (see sip_opts.sel_fresh) */
   double r_evol;                    /* last evaluated r_evol (eq. obj_stop), or -1 */
   double r_feas[SIP_MAX_SETS];      /* last evaluated r_feas_i (eq. feas_stop), or -1 */
   double rho[SIP_MAX_SETS + 1];     /* final rho_i, index nsets is rho_{p+1} */

@@ -273,7 +273,7 @@ Layout layout_of(const sip_grid& g, const sip_set* sets, int nsets, const sip_op
 Opts kernel_opts(const sip_opts& o) {
   Opts k;
   k.cg_max = o.cg_max; k.cg_fixed = o.cg_fixed; k.adapt_every = o.adapt_every; k.stop_every = o.stop_every;
-  k.evol_hist = o.evol_hist; k.max_iter = o.max_iter;
+  k.evol_hist = o.evol_hist; k.max_iter = o.max_iter; k.sel_fresh = o.sel_fresh ? 1 : 0;
   k.cg_rel2 = o.cg_rel * o.cg_rel; k.eps_corr = o.eps_corr; k.rho_ratio_max = o.rho_ratio_max;
   k.gamma_max = o.gamma_max; k.eps_evol = o.eps_evol; k.eps_feas = o.eps_feas;
   return k;
@@ -718,6 +718,7 @@ void fill_result(const Slot& s, const double* S, sip_result* r) {
   r->cg_steps = (int32_t)S[S_CGTOT];
   r->converged = S[S_STATE] == 1.0 ? 1 : 0;
   r->nsets = s.nsets;
+  r->sel_reused = (int32_t)S[S_REUSE];
   r->r_evol = S[S_REVOL];
   for (int i = 0; i < SIP_MAX_SETS; ++i) r->r_feas[i] = i < s.nsets ? S[S_RFEAS + i] : -1.0;
   for (int u = 0; u <= s.nsets; ++u) { r->rho[u] = S[S_RHO + u]; r->gamma[u] = S[S_GAMMA + u]; }
@@ -1016,7 +1017,7 @@ int32_t sip_opts_default(sip_opts* o) {
   std::memset(o, 0, sizeof(*o));
   o->max_iter = 200; o->cg_max = 10; o->cg_fixed = 0; o->adapt_every = 2; o->stop_every = 0; o->evol_hist = 5;
   o->rho0 = 1.0; o->gamma0 = 1.0; o->eps_corr = 0.3; o->rho_ratio_max = 100.0; o->gamma_max = 1.999;
-  o->eps_evol = 1e-2; o->eps_feas = 1e-3; o->cg_rel = 0.1; o->field = SIP_F32; o->reduce = SIP_F64; o->log_schedule = 0;
+  o->eps_evol = 1e-2; o->eps_feas = 1e-3; o->cg_rel = 0.1; o->field = SIP_F32; o->reduce = SIP_F64; o->log_schedule = 0; o->sel_fresh = 0;
   return SIP_OK;
 }
 

@@ -40,6 +40,7 @@ enum Scal : int {
   S_ITERS,                      // iterations completed
   S_ALPHA,                      // [2] CG step length by step parity (one-reduction form)
   S_RFEAS = S_ALPHA + 2,        // [SIP_MAX_SETS] last r_feas (-1: never)
+  S_REUSE = S_RFEAS + SIP_MAX_SETS,  // selections that started from the w pass's list A
   S_COUNT = S_RFEAS + SIP_MAX_SETS + 4
 };
 
@@ -65,6 +66,17 @@ struct SelState {
   int32_t err;
   int32_t compact_next;         // the next refine pass also appends candidate keys
   int32_t final_;               // threshold known; later refine/select passes skip
+  // Reuse of the previous iteration's first digit: the w pass gathers every
+  // entry whose first-digit bucket is spec - 1 into the candidate buffer
+  // from its start ("list A", nspec entries; spec 0: none).  When the first
+  // selection stage picks that bucket and nspec equals its count, list A
+  // holds the whole bucket (have_cand) and the refine passes read it instead
+  // of every value; their candidates then follow it (from entry nspec).
+  unsigned long long nspec;
+  unsigned long long cnt0;      // entries in the first digit's chosen bucket
+  int32_t spec;
+  int32_t have_cand;
+  unsigned long long pad_;
 };
 
 // A refine pass appends candidate keys only when the bucket it refines holds
@@ -137,6 +149,7 @@ struct SelItem {                  // one pipeline
 
 struct Opts {                     // options every kernel needs, by value
   int32_t cg_max, cg_fixed, adapt_every, stop_every, evol_hist, max_iter;
+  int32_t sel_fresh;              // 1: no reuse of the previous first digit (SelState::spec stays 0)
   double cg_rel2, eps_corr, rho_ratio_max, gamma_max, eps_evol, eps_feas;
 };
 

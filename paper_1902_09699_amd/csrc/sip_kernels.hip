@@ -1673,12 +1673,23 @@ __global__ __launch_bounds__(kSB) SIP_SETS_ATTR void k_proj(const InstDesc* __re
 // (dh, dvh) pair; radix histogram of the first key digit of |w|.
 // Pipeline 1 (stopping-test iterations): histogram of |s| and ||s||^2.
 // One block of the w pass: item bx.
+// Entries of list A (see SelState) a w-pass block holds in LDS before it
+// appends them with one atomic; a wave whose entries do not fit any more
+// appends them at once (one atomic per wave and element).
+template <typename T> struct StageCap { static constexpr int v = 4096 / (int)sizeof(typename KeyT<T>::K); };
+
 template <typename T>
 __device__ void thrw_block(const InstDesc* __restrict__ D, const ThrItem* __restrict__ items, const Opts& o, double* parts, int bx) {
   using KT = KeyT<T>;
+  using K = typename KT::K;
+  constexpr int SC = StageCap<T>::v;
   __shared__ uint32_t hc[kNB];
   __shared__ acc_t hs[kNB];
   __shared__ acc_t lds[lds_sum<8, kSB>()];
+  __shared__ K stk[SC];
+  __shared__ uint8_t stc[SC];
+  __shared__ uint32_t scnt;
+  __shared__ unsigned long long sbase;
   const ThrItem it = items[bx];
   if (it.inst < 0) return;
   const int iti = it.idx;
@@ -1696,7 +1707,13 @@ __device__ void thrw_block(const InstDesc* __restrict__ D, const ThrItem* __rest
   const bool l1 = s.kind == SIP_SET_L1;
   // l2 ball / annulus: no histogram, ||w||^2 into slot 6 of the partials
   const bool l2k = s.kind == SIP_SET_L2 || s.kind == SIP_SET_ANNULUS;
+  // the first-digit bucket whose entries go to list A (-1: none)
+  const int spec = l2k ? -1 : s.sel[it.src]->spec - 1;
+  K* __restrict__ la = (K*)s.cand[it.src];
+  uint32_t* __restrict__ lx = (it.src == 0 && s.cand_ix) ? s.cand_ix : nullptr;
+  unsigned long long* nsp = &s.sel[it.src]->nspec;
   for (int b = threadIdx.x; b < kNB; b += kSB) { hc[b] = 0; hs[b] = 0; }
+  if (threadIdx.x == 0) scnt = 0u;
   __syncthreads();
   const Geo g(d);
   const bool grouped = item_grouped(d);
@@ -1710,27 +1727,102 @@ __device__ void thrw_block(const InstDesc* __restrict__ D, const ThrItem* __rest
   const int sh0 = digit_shift<T>(0);
   constexpr int W = Grp<T>::W;
   const int lane = threadIdx.x & 63;
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const bool dots = it.src == 0 && adapt && have;
   acc_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int end = it.begin + it.len;
-  auto bin = [&](T val) {
+  auto stage = [&](K key, int c) {
+    const uint32_t q = atomicAdd(&scnt, 1u);
+    if (q < (uint32_t)SC) {
+      stk[q] = key;
+      stc[q] = (uint8_t)c;
+    } else {
+      const unsigned long long at = atomicAdd(nsp, 1ull);
+      la[at] = key;
+      if (lx) lx[at] = (uint32_t)iti * 3u + (uint32_t)c;
+    }
+  };
+  auto bin = [&](T val, int c) {
     if (l2k) {
       acc[6] += (acc_t)val * (acc_t)val;
       return;
     }
-    const typename KT::K key = KT::key(val);
+    const K key = KT::key(val);
     const int bkt = (int)(key >> sh0);
     atomicAdd(&hc[bkt], 1u);
     if (l1) atomicAdd(&hs[bkt], (acc_t)KT::value(key));
+    if (bkt == spec) stage(key, c);
   };
   // a group's values, runs of equal buckets merged into one update (the
   // bucket sums of float keys are exact, so the merge changes no result)
-  auto bin_group = [&](const T (&v)[W], const bool (&ok)[W]) {
+  auto bin_group = [&](const T (&v)[W], const bool (&ok)[W], int c) {
     if (l2k) {
 #pragma unroll
       for (int e = 0; e < W; ++e)
         if (ok[e]) acc[6] += (acc_t)v[e] * (acc_t)v[e];
       return;
+    }
+    K keys[W];
+#pragma unroll
+    for (int e = 0; e < W; ++e) keys[e] = KT::key(v[e]);
+    if (spec >= 0) {
+      // list A: the group's hits get consecutive LDS slots, one slot
+      // reservation per wave (a wave prefix of the hit counts, 0..W)
+      uint32_t hmask = 0u;
+#pragma unroll
+      for (int e = 0; e < W; ++e)
+        if (ok[e] && (int)(keys[e] >> sh0) == spec) hmask |= 1u << e;
+      const int nh = __popc(hmask);
+      if (__ballot(nh != 0)) {
+        uint32_t pre = 0u, tot = 0u;
+#pragma unroll
+        for (int bit = 0; bit < 3; ++bit) {
+          const unsigned long long m = __ballot((nh >> bit) & 1);
+          pre += (uint32_t)__popcll(m & below) << bit;
+          tot += (uint32_t)__popcll(m) << bit;
+        }
+        const unsigned long long act = __ballot(true);
+        const int lead = __ffsll((unsigned long long)act) - 1;
+        uint32_t base = 0u;
+        if (lane == lead) base = atomicAdd(&scnt, tot);
+        base = __shfl(base, lead, 64);
+        uint32_t q = base + pre;
+        int nover = 0;
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+          if (hmask & (1u << e)) {
+            if (q < (uint32_t)SC) { stk[q] = keys[e]; stc[q] = (uint8_t)c; }
+            else ++nover;
+            ++q;
+          }
+        }
+        if (__ballot(nover != 0)) {
+          // the stage is full: the rest straight to list A
+          uint32_t opre = 0u, otot = 0u;
+#pragma unroll
+          for (int bit = 0; bit < 3; ++bit) {
+            const unsigned long long m = __ballot((nover >> bit) & 1);
+            opre += (uint32_t)__popcll(m & below) << bit;
+            otot += (uint32_t)__popcll(m) << bit;
+          }
+          unsigned long long gb = 0ull;
+          if (lane == lead) gb = atomicAdd(nsp, (unsigned long long)otot);
+          gb = __shfl(gb, lead, 64) + opre;
+          int skip = nh - nover;  // this thread's staged hits come first
+#pragma unroll
+          for (int e = 0; e < W; ++e) {
+            if (hmask & (1u << e)) {
+              if (skip > 0) {
+                --skip;
+              } else {
+                la[gb] = keys[e];
+                if (lx) lx[gb] = (uint32_t)iti * 3u + (uint32_t)c;
+                ++gb;
+              }
+            }
+          }
+        }
+      }
     }
     int cur = -1;
     uint32_t n = 0;
@@ -1738,7 +1830,7 @@ __device__ void thrw_block(const InstDesc* __restrict__ D, const ThrItem* __rest
 #pragma unroll
     for (int e = 0; e < W; ++e) {
       if (!ok[e]) continue;
-      const typename KT::K key = KT::key(v[e]);
+      const K key = keys[e];
       const int bkt = (int)(key >> sh0);
       if (bkt != cur) {
         if (n) {
@@ -1799,12 +1891,12 @@ __device__ void thrw_block(const InstDesc* __restrict__ D, const ThrItem* __rest
             }
             st16<T>(vh0 + P0, vh);
           }
-          bin_group(wv, ok);
+          bin_group(wv, ok, c);
         } else {
 #pragma unroll
           for (int e = 0; e < W; ++e)
             if (ok[e]) acc[7] += (acc_t)sv[e] * (acc_t)sv[e];
-          bin_group(sv, ok);
+          bin_group(sv, ok, c);
         }
         continue;
       }
@@ -1835,11 +1927,17 @@ __device__ void thrw_block(const InstDesc* __restrict__ D, const ThrItem* __rest
           val = sp;
           acc[7] += (acc_t)sp * (acc_t)sp;
         }
-        bin(val);
+        bin(val, c);
       }
     }
   }
   __syncthreads();
+  // the place of the block's staged list-A entries, asked for first: the
+  // histogram flush and the block sums run while the atomic is in flight
+  const uint32_t ns = scnt < (uint32_t)SC ? scnt : (uint32_t)SC;
+  const bool app = spec >= 0 && ns > 0u;
+  unsigned long long at = 0ull;
+  if (app && threadIdx.x == 0) at = atomicAdd(nsp, (unsigned long long)ns);
   uint32_t* gc = s.hcnt[it.src];
   acc_t* gs = (acc_t*)s.hsum[it.src];
   for (int b = threadIdx.x; b < kNB; b += kSB) {
@@ -1853,6 +1951,15 @@ __device__ void thrw_block(const InstDesc* __restrict__ D, const ThrItem* __rest
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) parts[(size_t)iti * kThrParts + q] = acc[q];
+    if (app) sbase = at;
+  }
+  if (app) {
+    // the entries, with where they lie (cardinality ties)
+    __syncthreads();
+    for (int q = threadIdx.x; q < (int)ns; q += kSB) {
+      la[sbase + q] = stk[q];
+      if (lx) lx[sbase + q] = (uint32_t)iti * 3u + (uint32_t)stc[q];
+    }
   }
 }
 
@@ -1922,12 +2029,26 @@ __device__ __forceinline__ void pull_store(int nb, const uint32_t (&cv)[kPull], 
   }
 }
 
+// A selection state read by every block of a kernel (written by an earlier
+// launch), loaded with 16-byte global loads issued together.
+__device__ __forceinline__ SelState load_sel(const SelState* p) {
+  static_assert(sizeof(SelState) % 16 == 0, "SelState is loaded in 16-byte pieces");
+  constexpr int NQ = sizeof(SelState) / 16;
+  u32x4 q[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) q[i] = ((g_cu32x4*)p)[i];
+  SelState st;
+  __builtin_memcpy(&st, q, sizeof(SelState));
+  return st;
+}
+
 // The state fields a block publishes while other blocks of the same launch
 // may still append candidates (everything but the candidate count).
 __device__ __forceinline__ void store_sel_but_ncand(SelState* g, const SelState& v) {
   g->prefix = v.prefix; g->c_above = v.c_above; g->tkey = v.tkey; g->keep_ties = v.keep_ties; g->ties = v.ties;
   g->s_above = v.s_above; g->theta = v.theta; g->tk = v.tk; g->digit = v.digit; g->mode = v.mode;
   g->need_ties = v.need_ties; g->err = v.err; g->compact_next = v.compact_next; g->final_ = v.final_;
+  g->have_cand = v.have_cand; g->cnt0 = v.cnt0;
 }
 
 // Pick the bucket of the current digit.  l1: the largest bucket b whose lower
@@ -2057,11 +2178,12 @@ __device__ __forceinline__ SelState l2_stage(const SetDesc& s, int src, const do
 }
 
 // The first selection stage over the first digit's histogram, already in
-// LDS (hc, hs): totals, mode, non-finite keys, the first digit.  Every thread
-// calls this; st (LDS) holds the result.
+// LDS (hc, hs): totals, mode, non-finite keys, the first digit, and whether
+// list A (prev: the state the w pass saw) holds that digit's whole bucket.
+// Every thread calls this; st (LDS) holds the result.
 template <typename T>
 __device__ __forceinline__ void first_stage(SelState& st, const SetDesc& s, bool l1, const uint32_t* hc, const acc_t* hs,
-                            unsigned long long* lc, acc_t* ls, int* lbest, acc_t* lds) {
+                            unsigned long long* lc, acc_t* ls, int* lbest, acc_t* lds, const SelState& prev) {
   using KT = KeyT<T>;
   acc_t tot[2] = {0, 0};
   for (int b = threadIdx.x; b < kNB; b += kBlock) {
@@ -2085,6 +2207,10 @@ __device__ __forceinline__ void first_stage(SelState& st, const SetDesc& s, bool
     }
     st.final_ = 0;
     st.compact_next = 0;
+    st.nspec = prev.nspec;
+    st.spec = prev.spec;
+    st.have_cand = 0;
+    st.cnt0 = 0;
   }
   __syncthreads();
   if (st.mode == SEL_PROJECT && !st.err) {
@@ -2092,6 +2218,13 @@ __device__ __forceinline__ void first_stage(SelState& st, const SetDesc& s, bool
     if (threadIdx.x == 0) {
       st.digit = 1;
       st.compact_next = cnt <= kCandCap ? 1 : 0;
+      st.cnt0 = cnt;
+      // list A is the bucket when it was gathered for this bucket and holds
+      // as many entries (every block appended its own); at most half the
+      // candidate buffer, so that the refine passes' candidates fit after it
+      const unsigned long long b0 = st.prefix >> digit_shift<T>(0);
+      st.have_cand = (!st.err && prev.spec > 0 && (unsigned long long)(prev.spec - 1) == b0 &&
+                      prev.nspec == cnt && 2ull * cnt <= (unsigned long long)s.rows) ? 1 : 0;
     }
   }
   __syncthreads();
@@ -2131,24 +2264,19 @@ __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D,
     if (threadIdx.x == 0) *s.sel[si.src] = q;
     return;
   }
+  const SelState prev = load_sel(s.sel[si.src]);
   pull_finish(gc, gs, l1, kNB, cv, sv, hc, hs);
   __syncthreads();
-  first_stage<T>(st, s, l1, hc, hs, lc, ls, &lbest, lds);
-  if (threadIdx.x == 0) *s.sel[si.src] = st;
+  first_stage<T>(st, s, l1, hc, hs, lc, ls, &lbest, lds, prev);
+  if (threadIdx.x == 0) {
+    *s.sel[si.src] = st;
+    if (st.have_cand) atomicAdd(d.scal + S_REUSE, 1.0);
+  }
 }
 
-// A selection state read by every block of a kernel (written by an earlier
-// launch), loaded with 16-byte global loads issued together.
-__device__ __forceinline__ SelState load_sel(const SelState* p) {
-  static_assert(sizeof(SelState) % 16 == 0, "SelState is loaded in 16-byte pieces");
-  constexpr int NQ = sizeof(SelState) / 16;
-  u32x4 q[NQ];
-#pragma unroll
-  for (int i = 0; i < NQ; ++i) q[i] = ((g_cu32x4*)p)[i];
-  SelState st;
-  __builtin_memcpy(&st, q, sizeof(SelState));
-  return st;
-}
+// Keys of list A one refine block reads (at least): list A goes to the
+// pipeline's first ceil(nspec / kListChunk) blocks, the others have no work.
+constexpr unsigned long long kListChunk = 8192;
 
 // Whether refine pass `pass` (0 or 1; 1 is the last pass of the iteration)
 // appends candidate keys: the first when digits remain after the one it
@@ -2207,14 +2335,24 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
     }
     pull_store(kNB, cv, sv, hc, hs);
     __syncthreads();
-    first_stage<T>(sst, s, l1, hc, hs, lc, ls, &lbest, lds);
-    if (lead && threadIdx.x == 0) store_sel_but_ncand(s.sel[it.src], sst);
+    first_stage<T>(sst, s, l1, hc, hs, lc, ls, &lbest, lds, st);
+    if (lead && threadIdx.x == 0) {
+      store_sel_but_ncand(s.sel[it.src], sst);
+      if (sst.have_cand) atomicAdd(d.scal + S_REUSE, 1.0);
+    }
     st = sst;
     __syncthreads();  // hc, hs are reused below
   }
   if (st.mode != SEL_PROJECT || st.err || st.final_) return;
   const int dig = st.digit;
-  const bool compact = pass_compacts<T>(st, pass);
+  // With list A holding the first digit's bucket, a pass that would append
+  // that bucket appends nothing: list A is the candidate list.  A small one
+  // (at most kCandCap entries) makes the pass needless: the select stage
+  // after it resolves every remaining digit over list A.
+  const bool compact0 = pass_compacts<T>(st, pass);
+  const bool a_cand = st.have_cand && dig == 1 && compact0;
+  if (a_cand && st.nspec <= kCandCap) return;
+  const bool compact = compact0 && !a_cand;
   const int nb = 1 << KT::width(dig);
   for (int b = threadIdx.x; b < nb; b += kSB) { hc[b] = 0; hs[b] = 0; }
   __syncthreads();
@@ -2235,7 +2373,76 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
   const int end = it.begin + it.len;
   const bool grouped = item_grouped(d);
   const Offs of = offs_of<T>(g);
-  for (int c = 0; c < s.ncomp; ++c) {
+  if (st.have_cand) {
+    // list A instead of the values, in chunks of at least kListChunk keys to
+    // the pipeline's first items (few blocks, so few histogram atomics); the
+    // pass's candidates (a subset of list A) go after list A
+    const unsigned long long na = st.nspec;
+    const unsigned long long j = (unsigned long long)(iti - s.item_begin[it.src]);
+    const unsigned long long nj = (unsigned long long)(s.item_end[it.src] - s.item_begin[it.src]);
+    const unsigned long long ch = (na + nj - 1) / nj > kListChunk ? (na + nj - 1) / nj : kListChunk;
+    const unsigned long long q0 = j * ch;
+    if (q0 >= na) return;
+    const unsigned long long q1 = q0 + ch < na ? q0 + ch : na;
+    const K* __restrict__ la = cand;
+    const uint32_t* __restrict__ lx = cix;
+    K* __restrict__ lb = cand + na;
+    uint32_t* __restrict__ lbx = cix ? cix + na : nullptr;
+    constexpr int U = 16;  // keys per thread and round (a hit count of 0..16: 5 ballot bits)
+    for (unsigned long long r0 = q0; r0 < q1; r0 += (unsigned long long)kSB * U) {
+      K key[U];
+      bool hit[U];
+      int nh = 0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const unsigned long long q = r0 + (unsigned long long)(u * kSB) + threadIdx.x;
+        key[u] = q < q1 ? *(__attribute__((address_space(1))) const K*)(la + q) : (K)0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const unsigned long long q = r0 + (unsigned long long)(u * kSB) + threadIdx.x;
+        hit[u] = q < q1 && (K)(key[u] >> shp) == want;
+        if (hit[u]) {
+          ++nh;
+          const int bkt = (int)((key[u] >> sh) & (K)(nb - 1));
+          atomicAdd(&hc[bkt], 1u);
+          if (l1) atomicAdd(&hs[bkt], (acc_t)KT::value(key[u]));
+        }
+      }
+      if (compact) {
+        unsigned long long pre = 0, tot = 0;
+#pragma unroll
+        for (int bit = 0; bit < 5; ++bit) {
+          const unsigned long long m = __ballot((nh >> bit) & 1);
+          pre += (unsigned long long)__popcll(m & below) << bit;
+          tot += (unsigned long long)__popcll(m) << bit;
+        }
+        if (lane == 0) wcnt[wv] = (uint32_t)tot;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          unsigned long long t = 0;
+          for (int w = 0; w < kSW; ++w) t += wcnt[w];
+          bbase = t ? atomicAdd(ncand, t) : 0ull;
+        }
+        __syncthreads();
+        if (nh) {
+          unsigned long long off = bbase + pre;
+          for (int w = 0; w < wv; ++w) off += wcnt[w];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            if (hit[u]) {
+              if (lbx) lbx[off] = lx[r0 + (unsigned long long)(u * kSB) + threadIdx.x];
+              lb[off++] = key[u];
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+  // the components swept over the values (none when list A was read)
+  const int ncomp_w = st.have_cand ? 0 : s.ncomp;
+  for (int c = 0; c < ncomp_w; ++c) {
     const int axis = s.axis[c];
     const T* __restrict__ y = (const T*)s.y + (size_t)c * g.cs;
     for (int base0 = it.begin; base0 < end; base0 += kSB * W * kRefineRounds) {
@@ -2413,14 +2620,24 @@ __global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict_
   if (st0.mode != SEL_PROJECT || st0.err || st0.final_) return;
   if (threadIdx.x == 0) st = st0;  // first read after select_digit's barriers
   const bool compacted = pass_compacts<T>(st0, pass);
-  const K* cand = (const K*)s.cand[si.src];
-  const unsigned long long ncand = compacted ? st0.ncand : 0ull;
+  // a_cand: list A (the first digit's bucket) is the candidate list; from_a:
+  // the refine pass skipped it (small), so every digit from the second on is
+  // resolved over it here.  Otherwise the pass's own candidates, after list A
+  // if it was read.
+  const bool a_cand = st0.have_cand && st0.digit == 1 && compacted;
+  const bool from_a = a_cand && st0.nspec <= kCandCap;
+  const unsigned long long cbase = (st0.have_cand && !a_cand) ? st0.nspec : 0ull;
+  const K* cand = (const K*)s.cand[si.src] + cbase;
+  const unsigned long long ncand = a_cand ? st0.nspec : (compacted ? st0.ncand : 0ull);
   int dig = st0.digit;
   int nb = 1 << KT::width(dig);
   pull_finish(gc, gs, l1, nb, cv, sv, hc, hs);
   __syncthreads();
-  unsigned long long last = select_digit<T>(st, hc, hs, nb, dig, s, l1, lc, ls, &lbest);
-  ++dig;
+  unsigned long long last = 0;
+  if (!from_a) {
+    last = select_digit<T>(st, hc, hs, nb, dig, s, l1, lc, ls, &lbest);
+    ++dig;
+  }
   if (compacted) {
     for (; dig < KT::ndig; ++dig) {
       if (st.err) break;
@@ -2470,7 +2687,7 @@ __global__ __launch_bounds__(kBlock) void k_sel_next(const InstDesc* __restrict_
     for (int q = ib * 3 + (int)threadIdx.x; q < ie * 3; q += kBlock) tie_part[q] = 0u;
     __syncthreads();
     const K tk = (K)st.tkey;
-    const uint32_t* __restrict__ cix = s.cand_ix;
+    const uint32_t* __restrict__ cix = s.cand_ix + cbase;
     constexpr int U = 8;
     for (unsigned long long i0 = threadIdx.x; i0 < ncand; i0 += (unsigned long long)kBlock * U) {
       K keys[U];
@@ -3245,6 +3462,23 @@ __global__ __launch_bounds__(kFB) void k_finish(const InstDesc* __restrict__ D, 
   if (s_err) {
     if (u == 0) { S[S_ERR] = (double)s_err; S[S_STATE] = 3.0; }
     return;
+  }
+  if (u < p && d.sets[u].thr >= 0 && (d.sets[u].kind == SIP_SET_L1 || d.sets[u].kind == SIP_SET_CARD)) {
+    // the next w pass gathers the entries of this iteration's first-digit
+    // bucket (list A) when the selection went through the radix digits
+    // and the bucket is small enough to be of use: at most half the rows
+    // (list A and the candidates after it share the candidate buffer) and on
+    // average at most half a w-pass block's LDS stage per item
+    const SetDesc& sd = d.sets[u];
+    for (int src = 0; src < (check ? 2 : 1); ++src) {
+      SelState* q = sd.sel[src];
+      const unsigned long long nit = (unsigned long long)(sd.item_end[src] - sd.item_begin[src]);
+      const bool radix = q->mode == SEL_PROJECT && q->final_ && !q->err && !o.sel_fresh &&
+                         2ull * q->cnt0 <= (unsigned long long)sd.rows &&
+                         2ull * q->cnt0 <= nit * (unsigned long long)StageCap<T>::v;
+      q->spec = radix ? (int)(q->prefix >> digit_shift<T>(0)) + 1 : 0;
+      q->nspec = 0ull;
+    }
   }
   const double rho_u = u <= p ? rho_l : 0.0, gam_u = u <= p ? gam_l : 0.0;
   if (d.log && k <= d.log_cap && u <= p) {

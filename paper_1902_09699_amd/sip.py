@@ -46,7 +46,8 @@ class Opts(C.Structure):
                 ("rho0", C.c_double), ("gamma0", C.c_double), ("eps_corr", C.c_double),
                 ("rho_ratio_max", C.c_double), ("gamma_max", C.c_double), ("eps_evol", C.c_double),
                 ("eps_feas", C.c_double), ("cg_rel", C.c_double), ("field", C.c_int32),
-                ("reduce", C.c_int32), ("log_schedule", C.c_int32)]
+                ("reduce", C.c_int32), ("log_schedule", C.c_int32),
+                ("sel_fresh", C.c_int32)]
 
 
 class Tiles(C.Structure):
@@ -56,14 +57,14 @@ class Tiles(C.Structure):
 
 class Result(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("cg_steps", C.c_int32),
-                ("converged", C.c_int32), ("nsets", C.c_int32), ("reserved", C.c_int32),
+                ("converged", C.c_int32), ("nsets", C.c_int32), ("sel_reused", C.c_int32),
                 ("r_evol", C.c_double), ("r_feas", C.c_double * MAX_SETS),
                 ("rho", C.c_double * (MAX_SETS + 1)), ("gamma", C.c_double * (MAX_SETS + 1))]
 
     def as_dict(self):
         p = self.nsets
         return {"status": self.status, "iters": self.iters, "cg_steps": self.cg_steps,
-                "converged": bool(self.converged), "r_evol": self.r_evol,
+                "converged": bool(self.converged), "sel_reused": self.sel_reused, "r_evol": self.r_evol,
                 "r_feas": list(self.r_feas[:p]), "rho": list(self.rho[:p + 1]),
                 "gamma": list(self.gamma[:p + 1])}
 
