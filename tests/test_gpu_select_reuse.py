@@ -10,7 +10,8 @@ that reads all of w (sel_fresh = 1); with float64 fields the l1 bucket sums
 are accumulated in another order (equal to 1e-10).  The result's sel_reused
 count shows that the reuse path ran.  Cases: one refine pass (pipelines up to 2^19 entries),
 two refine passes with list A above the candidate cap (a 3D TV ball and a
-cardinality set), the stopping test's pipeline, and a batch of uneven
+cardinality set), a bucket concentrated in one w-pass block (more than its
+LDS stage holds), the stopping test's pipeline, and a batch of uneven
 instances."""
 import numpy as np
 import pytest
@@ -70,6 +71,34 @@ def test_reuse_matches_full_refine(kind, field):
     reuse = _project(m, sets, field, False, **kw)
     print(f"[select reuse] selections over list A: {reuse[1]['sel_reused']} "
           f"(of {iters * sum(s['kind'] in ('l1', 'card') for s in sets)})", flush=True)
+    assert fresh[1]["sel_reused"] == 0
+    assert reuse[1]["sel_reused"] > 0
+    _compare(reuse, fresh, field)
+
+
+@pytest.mark.parametrize("field", ["f32", "f64"])
+def test_reuse_with_a_full_stage(field):
+    """A bucket concentrated in one w-pass block: every entry of the k-th
+    magnitude's first-digit bucket lies in the first eight rows (4088
+    entries, the first 4096-point item), more than a block stages in LDS
+    (1024 float / 512 double keys), so that block appends the rest straight
+    to list A."""
+    rng = wl.rng_for(5)
+    nz, nx = 256, 512
+    d = np.empty((nz, nx - 1))
+    d[:8] = rng.uniform(0.50, 0.56, size=(8, nx - 1))
+    d[8:64] = rng.uniform(1.0, 2.0, size=(56, nx - 1))
+    d[64:] = rng.uniform(0.0, 0.1, size=(192, nx - 1))
+    d *= rng.choice([-1.0, 1.0], size=d.shape)
+    m = np.zeros((nz, nx))
+    m[:, 1:] = np.cumsum(d, axis=1)
+    m = wl.rounded(m, field)
+    sets = wl.finalize(m, [{"kind": "card", "op": "DX", "k": 56 * 511 + 2000}, wl.bounds("I", -1e4, 1e4)])
+    kw = dict(max_iter=12, cg_max=10, cg_fixed=1)
+    print(f"\n[select reuse] full stage {field} {m.shape}", flush=True)
+    fresh = _project(m, sets, field, True, **kw)
+    reuse = _project(m, sets, field, False, **kw)
+    print(f"[select reuse] selections over list A: {reuse[1]['sel_reused']} of 12", flush=True)
     assert fresh[1]["sel_reused"] == 0
     assert reuse[1]["sel_reused"] > 0
     _compare(reuse, fresh, field)
