@@ -2180,10 +2180,13 @@ __device__ __forceinline__ SelState l2_stage(const SetDesc& s, int src, const do
 // The first selection stage over the first digit's histogram, already in
 // LDS (hc, hs): totals, mode, non-finite keys, the first digit, and whether
 // list A (prev: the state the w pass saw) holds that digit's whole bucket.
+// passes: refine passes of the batch (with two, the second pass's
+// candidates go after list A, so list A may fill at most half the buffer).
 // Every thread calls this; st (LDS) holds the result.
 template <typename T>
 __device__ __forceinline__ void first_stage(SelState& st, const SetDesc& s, bool l1, const uint32_t* hc, const acc_t* hs,
-                            unsigned long long* lc, acc_t* ls, int* lbest, acc_t* lds, const SelState& prev) {
+                            unsigned long long* lc, acc_t* ls, int* lbest, acc_t* lds, const SelState& prev,
+                            int passes) {
   using KT = KeyT<T>;
   acc_t tot[2] = {0, 0};
   for (int b = threadIdx.x; b < kNB; b += kBlock) {
@@ -2220,11 +2223,12 @@ __device__ __forceinline__ void first_stage(SelState& st, const SetDesc& s, bool
       st.compact_next = cnt <= kCandCap ? 1 : 0;
       st.cnt0 = cnt;
       // list A is the bucket when it was gathered for this bucket and holds
-      // as many entries (every block appended its own); at most half the
-      // candidate buffer, so that the refine passes' candidates fit after it
+      // as many entries (every block appended its own); with two refine
+      // passes at most half the candidate buffer, so that the second pass's
+      // candidates fit after it
       const unsigned long long b0 = st.prefix >> digit_shift<T>(0);
       st.have_cand = (!st.err && prev.spec > 0 && (unsigned long long)(prev.spec - 1) == b0 &&
-                      prev.nspec == cnt && 2ull * cnt <= (unsigned long long)s.rows) ? 1 : 0;
+                      prev.nspec == cnt && (passes == 1 || 2ull * cnt <= (unsigned long long)s.rows)) ? 1 : 0;
     }
   }
   __syncthreads();
@@ -2234,7 +2238,7 @@ __device__ __forceinline__ void first_stage(SelState& st, const SetDesc& s, bool
 // digit's histogram once it is in LDS.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D, const SelItem* __restrict__ items, Opts o,
-                                                 const double* __restrict__ thrw_parts) {
+                                                 const double* __restrict__ thrw_parts, int passes) {
   __shared__ uint32_t hc[kNB];
   __shared__ acc_t hs[kNB];
   __shared__ unsigned long long lc[kBlock];
@@ -2267,7 +2271,7 @@ __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D,
   const SelState prev = load_sel(s.sel[si.src]);
   pull_finish(gc, gs, l1, kNB, cv, sv, hc, hs);
   __syncthreads();
-  first_stage<T>(st, s, l1, hc, hs, lc, ls, &lbest, lds, prev);
+  first_stage<T>(st, s, l1, hc, hs, lc, ls, &lbest, lds, prev, passes);
   if (threadIdx.x == 0) {
     *s.sel[si.src] = st;
     if (st.have_cand) atomicAdd(d.scal + S_REUSE, 1.0);
@@ -2335,7 +2339,7 @@ __global__ __launch_bounds__(kSB) void k_thr_refine(const InstDesc* __restrict__
     }
     pull_store(kNB, cv, sv, hc, hs);
     __syncthreads();
-    first_stage<T>(sst, s, l1, hc, hs, lc, ls, &lbest, lds, st);
+    first_stage<T>(sst, s, l1, hc, hs, lc, ls, &lbest, lds, st, 1);
     if (lead && threadIdx.x == 0) {
       store_sel_but_ncand(s.sel[it.src], sst);
       if (sst.have_cand) atomicAdd(d.scal + S_REUSE, 1.0);
@@ -3466,15 +3470,13 @@ __global__ __launch_bounds__(kFB) void k_finish(const InstDesc* __restrict__ D, 
   if (u < p && d.sets[u].thr >= 0 && (d.sets[u].kind == SIP_SET_L1 || d.sets[u].kind == SIP_SET_CARD)) {
     // the next w pass gathers the entries of this iteration's first-digit
     // bucket (list A) when the selection went through the radix digits
-    // and the bucket is small enough to be of use: at most half the rows
-    // (list A and the candidates after it share the candidate buffer) and on
-    // average at most half a w-pass block's LDS stage per item
+    // and the bucket is small enough to be of use: on average at most half a
+    // w-pass block's LDS stage per item
     const SetDesc& sd = d.sets[u];
     for (int src = 0; src < (check ? 2 : 1); ++src) {
       SelState* q = sd.sel[src];
       const unsigned long long nit = (unsigned long long)(sd.item_end[src] - sd.item_begin[src]);
       const bool radix = q->mode == SEL_PROJECT && q->final_ && !q->err && !o.sel_fresh &&
-                         2ull * q->cnt0 <= (unsigned long long)sd.rows &&
                          2ull * q->cnt0 <= nit * (unsigned long long)StageCap<T>::v;
       q->spec = radix ? (int)(q->prefix >> digit_shift<T>(0)) + 1 : 0;
       q->nspec = 0ull;
@@ -3643,7 +3645,7 @@ void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
       k_thr_refine<T, true><<<t.nthr, kSB, 0, st>>>(t.D, t.thr, o, 1, t.thrw_part, t.h1c, t.h1s);
       k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.sel, o, 1, t.tie_part, 1, t.h1c, t.h1s);
     } else {
-      k_sel1<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.sel, o, t.thrw_part);
+      k_sel1<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.sel, o, t.thrw_part, t.sel_passes);
       if (t.sel_passes == 2) {
         k_thr_refine<T, false><<<t.nthr, kSB, 0, st>>>(t.D, t.thr, o, 0, t.thrw_part, t.h1c, t.h1s);
         k_sel_next<T><<<t.nsel, kBlock, 0, st>>>(t.D, t.sel, o, 0, t.tie_part, 0, t.h1c, t.h1s);
