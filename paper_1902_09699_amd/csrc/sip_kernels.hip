@@ -3470,14 +3470,15 @@ __global__ __launch_bounds__(kFB) void k_finish(const InstDesc* __restrict__ D, 
   if (u < p && d.sets[u].thr >= 0 && (d.sets[u].kind == SIP_SET_L1 || d.sets[u].kind == SIP_SET_CARD)) {
     // the next w pass gathers the entries of this iteration's first-digit
     // bucket (list A) when the selection went through the radix digits
-    // and the bucket is small enough to be of use: on average at most half a
-    // w-pass block's LDS stage per item
+    // and the bucket is small enough to be of use: on average at most a
+    // w-pass block's LDS stage per item (a block whose stage fills appends
+    // the rest with a global atomic per wave and group)
     const SetDesc& sd = d.sets[u];
     for (int src = 0; src < (check ? 2 : 1); ++src) {
       SelState* q = sd.sel[src];
       const unsigned long long nit = (unsigned long long)(sd.item_end[src] - sd.item_begin[src]);
       const bool radix = q->mode == SEL_PROJECT && q->final_ && !q->err && !o.sel_fresh &&
-                         2ull * q->cnt0 <= nit * (unsigned long long)StageCap<T>::v;
+                         q->cnt0 <= nit * (unsigned long long)StageCap<T>::v;
       q->spec = radix ? (int)(q->prefix >> digit_shift<T>(0)) + 1 : 0;
       q->nspec = 0ull;
     }

@@ -10,9 +10,9 @@ that reads all of w (sel_fresh = 1); with float64 fields the l1 bucket sums
 are accumulated in another order (equal to 1e-10).  The result's sel_reused
 count shows that the reuse path ran.  Cases: one refine pass (pipelines up to 2^19 entries),
 two refine passes with list A above the candidate cap (a 3D TV ball and a
-cardinality set), a bucket concentrated in one w-pass block (more than its
-LDS stage holds), the stopping test's pipeline, and a batch of uneven
-instances."""
+cardinality set; the 200x200x100 workload), a bucket concentrated in one
+w-pass block (more than its LDS stage holds), the stopping test's pipeline,
+and a batch of uneven instances."""
 import numpy as np
 import pytest
 
@@ -73,6 +73,24 @@ def test_reuse_matches_full_refine(kind, field):
           f"(of {iters * sum(s['kind'] in ('l1', 'card') for s in sets)})", flush=True)
     assert fresh[1]["sel_reused"] == 0
     assert reuse[1]["sel_reused"] > 0
+    _compare(reuse, fresh, field)
+
+
+def test_reuse_at_200x200x100():
+    """The 200x200x100 workload (box, TV ball, lateral slopes) at its own
+    size: a TV pipeline of 11.9M entries (two refine passes, list A of
+    ~0.35M keys read in chunks, blocks whose stage fills); 40 iterations with
+    and without reuse, bit-identical."""
+    m, sets, field, _ = wl.smooth3d_box_tv_lat()
+    m = wl.rounded(m, field)
+    sets = wl.finalize(m, sets)
+    kw = dict(max_iter=40, cg_max=10, cg_fixed=1)
+    print("\n[select reuse] 200x200x100 f32, 40 iterations", flush=True)
+    fresh = _project(m, sets, field, True, **kw)
+    reuse = _project(m, sets, field, False, **kw)
+    print(f"[select reuse] selections over list A: {reuse[1]['sel_reused']} of 40", flush=True)
+    assert fresh[1]["sel_reused"] == 0
+    assert reuse[1]["sel_reused"] >= 20
     _compare(reuse, fresh, field)
 
 
