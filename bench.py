@@ -140,14 +140,16 @@ def kernel_bytes(insts, esz):
     same per-phase accounting as iteration_words: CG direction read r, p,
     write p (3N); CG update read x, r, p, write x, r (5N); a one-reduction CG
     step counts as one CG step of the same accounting (8N, although that
-    arrangement moves 10N); its w_0 pass read r, write w (2N); RHS read x and
+    arrangement moves 10N); its w_0 pass read r, write w (2N); the
+    LDS-staged form's step likewise counts 8N (it moves 6N) and its
+    r_0^T C r_0 pass N; RHS read x and
     every y_i, v_i (identity block included), write r; projection read x, m
     and y_i, v_i of the bounds sets and the identity block, write y_i, v_i;
     threshold w pass read x, y_i, v_i, write w (N + 3 M_i); apply pass read
     w, write y_i, v_i (3 M_i); line-wise sets read x, y_i, v_i, write y_i,
     v_i (N + 4 M_i)."""
-    b = {"cg_dir": 0, "cg_upd": 0, "cg1_step": 0, "cg1_w0": 0, "rhs": 0, "proj": 0, "thr_w": 0, "thr_apply": 0,
-         "line": 0}
+    b = {"cg_dir": 0, "cg_upd": 0, "cg1_step": 0, "cg1_w0": 0, "cg2_step": 0, "cg2_d0": 0, "rhs": 0, "proj": 0,
+         "thr_w": 0, "thr_apply": 0, "line": 0}
     for m, sets in insts:
         N = m.size
         sum_m = N + sum(rows(m.shape, s) for s in sets)
@@ -158,6 +160,8 @@ def kernel_bytes(insts, esz):
         b["cg_upd"] += 5 * N * esz
         b["cg1_step"] += 8 * N * esz
         b["cg1_w0"] += 2 * N * esz
+        b["cg2_step"] += 8 * N * esz
+        b["cg2_d0"] += N * esz
         b["rhs"] += (2 * N + 2 * sum_m) * esz
         b["proj"] += (2 * N + 4 * clip) * esz
         b["thr_w"] += sum(N + 3 * mi for mi in thr) * esz
@@ -254,13 +258,16 @@ def kernel_table(run, insts, field, reps):
     esz = 8 if field == "f64" else 4
     ab = kernel_bytes(insts, esz)
     tiles = run["tiles"]
-    one_red = bool(tiles) and len(tiles) > 5 and tiles[5] == 1
-    ids = {"cg1_step": sip.K_CG1_STEP, "cg1_w0": sip.K_CG1_W0} if one_red else \
-        {"cg_dir": sip.K_CG_DIR, "cg_upd": sip.K_CG_UPD}
+    form = tiles[5] if tiles and len(tiles) > 5 else 0
+    if form == 2 and any(m.ndim == 3 for m, _ in insts):
+        form = 0  # the LDS-staged form runs the steps of 2D grids only
+    ids = {0: {"cg_dir": sip.K_CG_DIR, "cg_upd": sip.K_CG_UPD},
+           1: {"cg1_step": sip.K_CG1_STEP, "cg1_w0": sip.K_CG1_W0},
+           2: {"cg2_step": sip.K_CG2_STEP, "cg2_d0": sip.K_CG2_D0}}[form]
     ids.update({"rhs": sip.K_RHS, "proj": sip.K_PROJ, "thr_w": sip.K_THR_W, "thr_apply": sip.K_THR_APPLY,
                 "line": sip.K_LINE})
-    per_iter = {"cg_dir": 10, "cg_upd": 10, "cg1_step": 10, "cg1_w0": 1, "rhs": 1, "proj": 1, "thr_w": 1,
-                "thr_apply": 1, "line": 1}
+    per_iter = {"cg_dir": 10, "cg_upd": 10, "cg1_step": 10, "cg1_w0": 1, "cg2_step": 10, "cg2_d0": 1, "rhs": 1,
+                "proj": 1, "thr_w": 1, "thr_apply": 1, "line": 1}
     kernels = {}
     for name, kid in ids.items():
         if ab[name] == 0:

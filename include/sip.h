@@ -233,7 +233,7 @@ int32_t sip_batch_result(sip_batch* b, int32_t slot, sip_result* res, void* stre
 /* Device arrays of a slot's state for export/import by the caller (same
  * stream ordering rules as any device memory).  which: 0 y_i, 1 v_i,
  * 2 vhat snapshot, 3 v snapshot, 4 y snapshot (i = nsets means the identity
- * block p+1); 5 r (the CG residual buffer; with cg_form 1 it holds the
+ * block p+1); 5 r (the CG residual buffer; with cg_form 1 or 2 it holds the
  * warm-start residual or that of an even step), 6 x-snapshot buffer 0,
  * 7 x-snapshot buffer 1.  Set
  * arrays hold one block per operator component (z, y, x order), block c
@@ -265,7 +265,15 @@ int32_t sip_batch_schedule(sip_batch* b, int32_t slot, double* rho, double* gamm
  * reductions per step; 1 Chronopoulos and Gear's one-reduction form, one
  * launch per step (the same iterates in exact arithmetic, different
  * rounding; 10 instead of 8 vectors of traffic per step, fewer launches: it
- * pays on grids too small to keep the GPU busy).  Results are bit-identical
+ * pays on grids too small to keep the GPU busy); 2 one launch per step that
+ * stages r and p of each item (and one row before, two after) in LDS, forms
+ * C p and the next residual there and stores x, r, p only (6 vectors), with
+ * p^T C p from its expansion in the previous step's sums (the textbook
+ * iterates' expressions; only that double is summed another way), plus one
+ * r_0^T C r_0 pass per x-minimization — for the instances without a y
+ * axis whose items and three rows fit 60 KiB of LDS (the batch's other
+ * instances run form 0 steps beside them).
+ * Results are bit-identical
  * for any batch composition at fixed tile settings.  Applies from the next
  * sip_batch_run.  Defaults 2048/512, 2048/512, 512 threads, form 0.
  * SIP_EINVAL for sizes that are not multiples of 256, max_items < 1, another
@@ -288,7 +296,9 @@ typedef enum {
   SIP_K_THR_APPLY = 5, /* threshold sets: apply threshold + dual update */
   SIP_K_CG1_STEP = 6,  /* one-reduction CG step (step 1; run a cg_form 1 iteration first) */
   SIP_K_CG1_W0 = 7,    /* one-reduction CG: w_0 = C r_0 + r_0^T w_0 */
-  SIP_K_LINE = 8       /* line-wise sets: relax, project every line, dual update */
+  SIP_K_LINE = 8,      /* line-wise sets: relax, project every line, dual update */
+  SIP_K_CG2_STEP = 9,  /* LDS-staged CG step (step 1; only where the batch runs cg_form 2) */
+  SIP_K_CG2_D0 = 10    /* LDS-staged CG: r_0^T C r_0 */
 } sip_kernel_id;
 
 /* Launch one kernel of the iteration `reps` times on `stream` over the
@@ -378,7 +388,7 @@ typedef struct {
   int32_t pt_points, pt_max_items;   /* grid points per item of the RHS, CG and projection kernels; item cap */
   int32_t thr_points, thr_max_items; /* the same for the threshold-set kernels */
   int32_t pt_threads;                /* 256 or 512 */
-  int32_t cg_form;                   /* 0 textbook CG, 1 one-reduction CG */
+  int32_t cg_form;                   /* 0 textbook CG, 1 one-reduction CG, 2 LDS-staged one-launch CG */
 } sip_tiles;
 
 /* Fill *t with the default tiles (2048/512, 2048/512, 512 threads, form 0). */

@@ -32,6 +32,12 @@ CANDIDATES = [
     (1024, 1024, 2048, 512, 256, 1),
     (2048, 1024, 4096, 512, 512, 1),
     (4096, 512, 4096, 256, 512, 1),
+    # one launch per CG step, LDS-staged, 6 vectors of traffic (2D batches;
+    # others run the textbook form under these tiles)
+    (4096, 512, 4096, 256, 256, 2),
+    (4096, 512, 4096, 256, 512, 2),
+    (2048, 512, 2048, 512, 512, 2),
+    (2048, 1024, 4096, 512, 256, 2),
 ]
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "sip_tiles.json")

@@ -328,6 +328,7 @@ struct sip_batch {
   sip::ThrItem* d_thr = nullptr; int cap_thr = 0;
   sip::SelItem* d_sel = nullptr; int cap_sel = 0;
   int32_t* d_inst = nullptr; int cap_inst = 0;
+  double *d_xq = nullptr, *d_xq2 = nullptr;
   double *d_rr = nullptr, *d_pq = nullptr, *d_rr2 = nullptr, *d_pq2 = nullptr, *d_proj = nullptr, *d_thrw = nullptr, *d_thra = nullptr;
   uint32_t* d_tie = nullptr;
   uint32_t* d_h1c = nullptr; double* d_h1s = nullptr; int cap_h1 = 0;  // refine histograms, kNB per pipeline
@@ -513,7 +514,7 @@ int64_t table_bytes(const HostTables& h) {
   const int64_t sel = std::max(h.lsel, 1), inst = std::max(h.linst, 1), line = std::max(h.lline, 1);
   return A(pt * (int64_t)sizeof(PtItem)) + A(sp * (int64_t)sizeof(PtItem)) + A(thr * (int64_t)sizeof(ThrItem)) +
          A(sel * (int64_t)sizeof(SelItem)) + A(inst * 4) + A(line * (int64_t)sizeof(LineItem)) + A(line * 64) +
-         4 * A(pt * 8) + A(sp * kProjParts * 8) + A(sel * kNB * 4) + A(sel * kNB * 8) +
+         6 * A(pt * 8) + A(sp * kProjParts * 8) + A(sel * kNB * 4) + A(sel * kNB * 8) +
          2 * A(thr * kThrParts * 8) + A(thr * 12);
 }
 
@@ -559,7 +560,8 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
     moved = true;
   }
   if (b->cap_ppt < b->cap_pt) {
-    if ((rc = regrow({(void**)&b->d_rr, (void**)&b->d_pq, (void**)&b->d_rr2, (void**)&b->d_pq2},
+    if ((rc = regrow({(void**)&b->d_rr, (void**)&b->d_pq, (void**)&b->d_rr2, (void**)&b->d_pq2, (void**)&b->d_xq,
+                      (void**)&b->d_xq2},
                      (int64_t)b->cap_pt * 8)))
       return rc;
     b->cap_ppt = b->cap_pt;
@@ -612,6 +614,33 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
     HIP_OK(hipMemcpyAsync(b->d_inst, inst_l.data(), inst_l.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
   if (lline)
     HIP_OK(hipMemcpyAsync(b->d_line, line_l.data(), line_l.size() * sizeof(LineItem), hipMemcpyHostToDevice, stream));
+  // The LDS-staged CG form runs the steps of each instance without a y axis
+  // whose items, with one row before and two after, fit 60 KiB of a block's
+  // LDS (the rest of 64 KiB holds the block sums); the batch's other
+  // instances run the two-launch steps beside them.  Whether an instance
+  // qualifies depends on its own grid and the tile settings only.
+  int form = b->tiles.cg_form, cap2 = 0, rest2 = 0;
+  if (form == 2) {
+    const int64_t W = b->opts.field == SIP_F64 ? 2 : 4, esz = b->opts.field == SIP_F64 ? 8 : 4;
+    std::vector<int64_t> need((size_t)b->max_slots, 0);
+    for (const PtItem& q : pt) {
+      const Slot& sl = b->slots[q.inst];
+      need[q.inst] = std::max<int64_t>(need[q.inst], (int64_t)q.len + 3 * sl.desc.n[2] + 2 * W);
+    }
+    int64_t cap = 0;
+    for (int si = 0; si < b->max_slots; ++si) {
+      Slot& sl = b->slots[si];
+      if (!sl.used) continue;
+      const int64_t c = (need[si] + W - 1) / W * W;
+      sl.desc.cg2 = (sl.desc.n[1] == 1 && need[si] > 0 && 2 * c * esz <= 61440) ? 1 : 0;
+      if (sl.desc.cg2) cap = std::max(cap, c);
+      else rest2 = 1;
+    }
+    if (cap == 0) form = 0;
+    cap2 = (int)cap;
+  } else {
+    for (int si = 0; si < b->max_slots; ++si) b->slots[si].desc.cg2 = 0;
+  }
   for (int si = 0; si < b->max_slots; ++si) {
     if (!b->slots[si].used) continue;
     HIP_OK(hipMemcpyAsync(b->d_desc + si, &b->slots[si].desc, sizeof(InstDesc), hipMemcpyHostToDevice, stream));
@@ -626,7 +655,7 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   t.sel = b->d_sel; t.nsel = lsel;
   t.inst = b->d_inst; t.ninst = linst;
   t.rr_part = b->d_rr; t.pq_part = b->d_pq; t.proj_part = b->d_proj;
-  t.rr2_part = b->d_rr2; t.pq2_part = b->d_pq2;
+  t.rr2_part = b->d_rr2; t.pq2_part = b->d_pq2; t.xq_part = b->d_xq; t.xq2_part = b->d_xq2;
   t.line = b->d_line; t.nline = lline; t.line_part = b->d_linep;
   int cap = 2;
   for (const LineItem& li : line) while (cap < li.len) cap <<= 1;
@@ -658,9 +687,12 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   const int sfuse = (passes == 1 && (int)thr.size() <= kFuseSelItems) ? 1 : 0;
   if (sfuse != t.sel_fused) relaunch_cap = true;
   t.sel_fused = sfuse;
-  const bool threads_changed = t.pt_threads != (int)b->tiles.pt_threads || t.cg_form != b->tiles.cg_form;
+  const bool threads_changed = t.pt_threads != (int)b->tiles.pt_threads || t.cg_form != form || t.cg2_cap != cap2 ||
+                               t.cg2_rest != rest2;
   t.pt_threads = (int)b->tiles.pt_threads;
-  t.cg_form = b->tiles.cg_form;
+  t.cg_form = form;
+  t.cg2_cap = cap2;
+  t.cg2_rest = form == 2 ? rest2 : 0;
   b->live_items = (int)pt.size() + (int)thr.size() + (int)line.size();
   b->live_inst = (int)inst.size();
   if (relaunch || moved || threads_changed || relaunch_cap) drop_graphs(b);
@@ -901,7 +933,7 @@ int32_t start_slot(sip_batch* b, int si, const void* m_dev, hipStream_t stream) 
 bool tiles_from(const sip_tiles& t, TileCfg& tc) {
   if (t.pt_points < kTileQuantum || t.thr_points < kTileQuantum || t.pt_points % kTileQuantum ||
       t.thr_points % kTileQuantum || t.pt_max_items < 1 || t.thr_max_items < 1 ||
-      (t.pt_threads != 256 && t.pt_threads != 512) || (t.cg_form != 0 && t.cg_form != 1))
+      (t.pt_threads != 256 && t.pt_threads != 512) || (t.cg_form < 0 || t.cg_form > 2))
     return false;
   tc.pt_base = t.pt_points; tc.pt_max_items = t.pt_max_items;
   tc.thr_base = t.thr_points; tc.thr_max_items = t.thr_max_items;
@@ -1044,7 +1076,7 @@ int32_t sip_batch_destroy(sip_batch* b) {
   drop_graphs(b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   void* dev[] = {b->d_desc, b->d_scal, b->d_pt, b->d_thr, b->d_sel, b->d_inst, b->d_rr, b->d_pq,
-                 b->d_rr2, b->d_pq2, b->d_proj, b->d_thrw, b->d_thra, b->d_tie, b->d_sp,
+                 b->d_rr2, b->d_pq2, b->d_xq, b->d_xq2, b->d_proj, b->d_thrw, b->d_thra, b->d_tie, b->d_sp,
                  b->d_line, b->d_linep, b->d_h1c, b->d_h1s};
   for (void* p : dev) (void)dev_free(b, p);
   if (b->h_scal) {
@@ -1233,7 +1265,7 @@ int32_t sip_batch_reset(sip_batch* b, int32_t slot, const void* m_dev, void* str
 }
 
 int32_t sip_batch_time_kernel(sip_batch* b, int32_t kernel, int32_t reps, void* stream_, double* avg_ms) {
-  if (!b || kernel < SIP_K_RHS || kernel > SIP_K_LINE || reps < 1 || !avg_ms) return SIP_EINVAL;
+  if (!b || kernel < SIP_K_RHS || kernel > SIP_K_CG2_D0 || reps < 1 || !avg_ms) return SIP_EINVAL;
   hipStream_t stream = (hipStream_t)stream_;
   if (b->dirty) {
     const int32_t rc = rebuild_tables(b, stream);
@@ -1283,7 +1315,7 @@ int32_t sip_batch_set_tiles(sip_batch* b, int32_t pt_points, int32_t pt_max_item
                             int32_t thr_max_items, int32_t pt_threads, int32_t cg_form) {
   if (!b || pt_points < kTileQuantum || thr_points < kTileQuantum || pt_points % kTileQuantum ||
       thr_points % kTileQuantum || pt_max_items < 1 || thr_max_items < 1 ||
-      (pt_threads != 256 && pt_threads != 512) || (cg_form != 0 && cg_form != 1))
+      (pt_threads != 256 && pt_threads != 512) || (cg_form < 0 || cg_form > 2))
     return SIP_EINVAL;
   b->tiles.pt_threads = pt_threads;
   b->tiles.cg_form = cg_form;

@@ -41,6 +41,7 @@ enum Scal : int {
   S_ALPHA,                      // [2] CG step length by step parity (one-reduction form)
   S_RFEAS = S_ALPHA + 2,        // [SIP_MAX_SETS] last r_feas (-1: never)
   S_REUSE = S_RFEAS + SIP_MAX_SETS,  // selections that started from the w pass's list A
+  S_PCP,                        // [2] p^T C p of the LDS-staged CG form, by step parity
   S_COUNT = S_RFEAS + SIP_MAX_SETS + 4
 };
 
@@ -109,7 +110,8 @@ struct FastDiv {                  // n / d for 0 <= n < 2^31 (Granlund-Montgomer
 struct InstDesc {
   int32_t ndim, nsets, active;
   int32_t vec_ok;                 // x and the workspace are 16-byte aligned: CG uses 128-bit groups
-  int32_t vec_nb, pad_;           // row strides are multiples of the group: 128-bit y/z neighbours
+  int32_t vec_nb;                 // row strides are multiples of the group: 128-bit y/z neighbours
+  int32_t cg2;                    // the batch runs this instance's CG steps in the LDS-staged form
   int64_t n[3];                   // axis sizes (3D: z, y, x; 2D: z, x, 1)
   int64_t N;
   int64_t cs;                     // element stride between operator components (N rounded up, 256-byte aligned)
@@ -175,7 +177,8 @@ struct Tables {
   const SelItem* sel; int nsel;
   const int32_t* inst; int ninst;
   double* rr_part; double* pq_part; double* proj_part; double* thrw_part; double* thra_part;
-  double* rr2_part; double* pq2_part;  // one-reduction CG: odd-step partials
+  double* rr2_part; double* pq2_part;  // one-launch CG forms: odd-step partials
+  double* xq_part; double* xq2_part;   // LDS-staged CG form: r^T s partials by step parity
   const LineItem* line; int nline;     // line items of line-wise sets
   int line_cap;                        // power of two >= the longest line (LDS entries per block)
   int proj_units;                      // projection blocks per item: max over instances of nsets + 2
@@ -184,7 +187,9 @@ struct Tables {
   uint32_t* h1c; double* h1s;          // per pipeline (selection-table order): the refine histogram
                                        // when the first selection stage runs inside the refine pass
   int pt_threads;  // threads per block of the RHS and CG kernels (256 or 512)
-  int cg_form;     // 0: two launches per CG step; 1: one (Chronopoulos-Gear)
+  int cg_form;     // 0: two launches per CG step; 1: one (Chronopoulos-Gear); 2: one, LDS-staged (2D)
+  int cg2_cap;     // form 2: LDS field values per array (longest item + 3 rows + 2 groups)
+  int cg2_rest;    // form 2: some instances (3D, or rows too long for LDS) run the two-launch steps
   int sel_passes;  // refine + select passes after the first stage: 1 (it always compacts) or 2
   int fuse_sets;   // projection and w passes in one launch (small, latency-bound batches)
   int sel_fused;   // first selection stage done by every block of the (single) refine pass

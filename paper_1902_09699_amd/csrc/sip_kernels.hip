@@ -862,7 +862,7 @@ __device__ __forceinline__ acc_t group_pCp_v(const Src<T, NA>& f, const GLane& L
   return acc;
 }
 
-template <typename T, int NA, int NT>
+template <typename T, int NA, int NT, bool ST = true>
 __device__ __forceinline__ acc_t cg_dir_item(const InstDesc& d, const PtItem& it, const Geo& g, const Src<T, NA>& f,
                                               T* __restrict__ pout, const double (&cf)[4]) {
   constexpr int W = Grp<T>::W;
@@ -890,7 +890,7 @@ __device__ __forceinline__ acc_t cg_dir_item(const InstDesc& d, const PtItem& it
                   : group_pCp_v<T, NA, false, false>(f, L, lane, g, of, c, cf);
       vec = L.vec;
       if (vec) {
-        st16<T>(pout + P0, c);
+        if constexpr (ST) st16<T>(pout + P0, c);
         acc += t;
       }
     }
@@ -905,7 +905,7 @@ __device__ __forceinline__ acc_t cg_dir_item(const InstDesc& d, const PtItem& it
         if (ix < g.nx - 1) { const acc_t dd = fs(P + 1) - pc; t += (acc_t)cf[3] * dd * dd; }
         if (iy < g.ny - 1) { const acc_t dd = fs(P + g.sy) - pc; t += (acc_t)cf[2] * dd * dd; }
         if (iz < g.nz - 1) { const acc_t dd = fs(P + g.sz) - pc; t += (acc_t)cf[1] * dd * dd; }
-        pout[P] = (T)pc;
+        if constexpr (ST) pout[P] = (T)pc;
         acc += t;
       }
     }
@@ -921,6 +921,7 @@ __global__ __launch_bounds__(NT) void k_cg_dir(const InstDesc* __restrict__ D, c
   if (it.inst < 0) return;
   const int iti = it.idx;
   const InstDesc& d = D[it.inst];
+  if (d.cg2) return;  // its steps run in k_cg2_step
   double* S = d.scal;
   const CgScal q = cg_scal(S);
   double pre[kPre];
@@ -973,6 +974,7 @@ __global__ __launch_bounds__(NT) void k_cg_upd(const InstDesc* __restrict__ D, c
   if (it.inst < 0) return;
   const int iti = it.idx;
   const InstDesc& d = D[it.inst];
+  if (d.cg2) return;  // its steps run in k_cg2_step
   double* S = d.scal;
   const CgScal qs = cg_scal(S);
   double pre[kPre];
@@ -1244,6 +1246,267 @@ __global__ __launch_bounds__(NT) void k_cg1_step(const InstDesc* __restrict__ D,
   if (threadIdx.x == 0) {
     gout[iti] = ag;
     dout[iti] = ad;
+  }
+}
+
+// ------------------------------------------ one-launch CG form, LDS-staged (2D)
+//
+// The two-launch form's iterates with one launch per step and no stored
+// C-products, for grids without a y axis: a step reads x_j, r_j and p_{j-1}
+// and writes x_{j+1}, r_{j+1} and p_j (6 vectors instead of 8).  Entering step
+// j: the per-item partials of gamma_j = r_j^T r_j and, for j > 0, of
+// Q_j = r_j^T C r_j and X_j = r_j^T s_{j-1} (s = C p); at j = 0 those of
+// r_0^T C r_0 (a pass over r_0) in place of Q_0.
+//   beta_j = gamma_j / gamma_{j-1}                            (0 at j = 0)
+//   p_j^T C p_j = Q_j + 2 beta_j X_j + beta_j^2 p_{j-1}^T C p_{j-1}
+// (p_j = r_j + beta_j p_{j-1} expanded; r_0^T C r_0 at j = 0) and
+// alpha_j = gamma_j / p_j^T C p_j; then at every point
+//   p_j = r_j + beta_j p_{j-1},  s_j = C p_j,
+//   x_{j+1} = x_j + alpha_j p_j,  r_{j+1} = r_j - alpha_j s_j,
+// and the partials of gamma_{j+1}, X_{j+1} = r_{j+1}^T s_j and
+// Q_{j+1} = c0 |r_{j+1}|^2 + sum_a c_a |D_a r_{j+1}|^2 (unit forward
+// differences, c_a folding 1/h_a^2 as in C).  A block stages r_j and p_j of
+// its item and of one row before and two after it in LDS, forms s_j and
+// r_{j+1} there for its points and the row after them (the forward
+// neighbours of its last row), then the partial sums, and writes its points'
+// x_{j+1}, p_j and r_{j+1}.  p_j, s_j, x_{j+1} and r_{j+1} are the two-launch
+// form's expressions in the same order; only the double p_j^T C p_j is
+// summed another way.  r and p alternate between two buffers by step parity
+// (neighbours' old values are read while other blocks write the new ones); x
+// is updated in place.
+
+// (C f) at one point from its value and its six neighbours' (those outside
+// the grid are not used), in the order of the other stencil kernels.
+template <typename T, bool HY>
+__device__ __forceinline__ T stencil7(T ce, T lft, T rgt, T ym, T yp, T zm, T zp, int iz, int iy, int ix,
+                                      const Geo& g, T c0, T cz, T cy, T cx) {
+  T lx = 0, ly = 0, lz = 0;
+  if (ix > 0) lx += ce - lft;
+  if (ix < g.nx - 1) lx += ce - rgt;
+  if constexpr (HY) {
+    if (iy > 0) ly += ce - ym;
+    if (iy < g.ny - 1) ly += ce - yp;
+  }
+  if (iz > 0) lz += ce - zm;
+  if (iz < g.nz - 1) lz += ce - zp;
+  return c0 * ce + cz * lz + cy * ly + cx * lx;
+}
+
+// r_0^T C r_0 per item (the denominator of step 0), from r_0 of the RHS kernel.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_cg2_d0(const InstDesc* __restrict__ D, const PtItem* __restrict__ items,
+                                                double* qpart) {
+  __shared__ acc_t lds[lds_sum<1, NT>()];
+  const PtItem it = items[blockIdx.x];
+  if (it.inst < 0) return;
+  const InstDesc& d = D[it.inst];
+  if (!d.cg2) return;  // an instance of the two-launch form
+  const CgScal q = cg_scal(d.scal);
+  if (!q.live()) return;
+  const Geo g(d);
+  const double cf[4] = {q.c0, q.cax[0], q.cax[1], q.cax[2]};
+  const Src<T, 1> f{{(const T*)d.r}, (T)0};
+  acc_t acc = cg_dir_item<T, 1, NT, false>(d, it, g, f, nullptr, cf);
+  acc = block_total<NT>(acc, lds);
+  if (threadIdx.x == 0) qpart[it.idx] = acc;
+}
+
+// Step j (NA = 1 at j = 0, where p_0 = r_0; NA = 2 after).  Dynamic LDS: two
+// arrays of `cap` field values (cap >= the longest item + 3 rows + 2 W).
+template <typename T, int NT, int NA>
+__global__ __launch_bounds__(NT) void k_cg2_step(const InstDesc* __restrict__ D, const PtItem* __restrict__ items, int j,
+                                                  const double* gin, const double* qin, const double* xin,
+                                                  double* gout, double* qout, double* xout, Opts o, int cap) {
+  constexpr int W = Grp<T>::W;
+  extern __shared__ __align__(16) unsigned char cg2_dyn[];
+  __shared__ acc_t lds[lds_sum<3, NT>()];
+  T* lr = (T*)cg2_dyn;
+  T* lp = lr + cap;
+  const PtItem it = items[blockIdx.x];
+  if (it.inst < 0) return;
+  const int iti = it.idx;
+  const InstDesc& d = D[it.inst];
+  if (!d.cg2) return;  // an instance of the two-launch form
+  double* S = d.scal;
+  const CgScal qs = cg_scal(S);
+  const double pcp_prev = ldgd(S + S_PCP + ((j + 1) & 1));
+  double pg[kPre], pq[kPre], px[kPre];
+  part_issue(gin, d.pt_begin, d.pt_end, pg);
+  part_issue(qin, d.pt_begin, d.pt_end, pq);
+  if (NA == 2) part_issue(xin, d.pt_begin, d.pt_end, px);
+  // summed before the state checks, so the partials' loads stay with the
+  // scalars' (the values are stale when the checks end the step)
+  const double gam = part_finish(gin, d.pt_begin, d.pt_end, pg);
+  const double qq = part_finish(qin, d.pt_begin, d.pt_end, pq);
+  const double xx = NA == 2 ? part_finish(xin, d.pt_begin, d.pt_end, px) : 0.0;
+  if (!qs.live()) return;
+  const bool leader = iti == d.pt_begin && threadIdx.x == 0;
+  if (j > 0 && qs.done_at(j - 1) != 0.0) {
+    // finished at an earlier step (this step's partials were never written)
+    if (leader) S[S_DONE + (j & 1)] = 1.0;
+    return;
+  }
+  bool done = !(gam > 0.0);
+  double beta = 0.0;
+  if (j > 0) {
+    done = done || (!o.cg_fixed && gam < o.cg_rel2 * qs.rr0);
+    beta = gam / qs.rr_at(j - 1);
+  }
+  const bool bad = !(gam <= 1.0e300) || gam != gam;
+  if (leader) {
+    S[S_RR + (j & 1)] = gam;
+    S[S_DONE + (j & 1)] = (done || bad) ? 1.0 : 0.0;
+    if (j == 0) S[S_RR0] = gam;
+    if (bad) S[S_ERR] = (double)SIP_ENUMERIC;
+  }
+  if (done || bad) return;
+  const double pcp = j == 0 ? qq : qq + 2.0 * beta * xx + beta * beta * pcp_prev;
+  if (!(pcp > 0.0) || !(pcp <= 1.0e300)) {
+    if (leader) S[S_ERR] = (double)SIP_ENUMERIC;
+    return;
+  }
+  const double alpha = gam / pcp;
+  if (leader) {
+    S[S_PCP + (j & 1)] = pcp;
+    S[S_CGTOT] += 1.0;
+  }
+  const Geo g(d);
+  const int N = g.N, nx = g.nx, nz = g.nz;
+  T* x = (T*)d.x;
+  const T* rj = (const T*)((j & 1) ? d.p[1] : d.r);
+  T* rnb = (T*)((j & 1) ? d.r : d.p[1]);
+  T* pnb = (T*)((j & 1) ? d.cr[0] : d.p[0]);
+  const T* pold = (const T*)((j & 1) ? d.p[0] : d.cr[0]);
+  const T al = (T)alpha, be = (T)beta;
+  const T c0 = (T)qs.c0, cz = (T)qs.cax[0], cy = (T)qs.cax[1], cx = (T)qs.cax[2];
+  const double cf[4] = {qs.c0, qs.cax[0], qs.cax[1], qs.cax[2]};
+  const int b = it.begin, e = it.begin + it.len;
+  // staged range: one row before the item and two after it, whole groups
+  // (the work arrays are padded to whole 256-byte blocks past N)
+  const int s0 = (b - nx > 0 ? b - nx : 0) & ~(W - 1);
+  const int hi = e + 2 * nx < N ? e + 2 * nx : N;
+  const int s1 = (hi + W - 1) & ~(W - 1);
+  // x of the thread's first UX groups of the item, loaded with the staging
+  // (x by elements when the caller's x is not 16-byte aligned)
+  constexpr int UX = 2, UA = 4;
+  const bool xvec = item_grouped(d);
+  T xpre[UX][W];
+#pragma unroll
+  for (int a = 0; a < UX; ++a) {
+    const int G = b + (int)threadIdx.x * W + a * NT * W;
+    const int cnt = e - G < W ? e - G : W;
+    if (G >= e) continue;
+    if (xvec) {
+      ld16p<T>(x, G, N, xpre[a]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < W; ++u) xpre[a][u] = u < cnt ? x[G + u] : (T)0;
+    }
+  }
+  for (int G0 = s0 + (int)threadIdx.x * W; G0 < s1; G0 += UA * NT * W) {
+    T rv[UA][W], pv[UA][W];
+#pragma unroll
+    for (int a = 0; a < UA; ++a) {
+      const int G = G0 + a * NT * W;
+      if (G >= s1) continue;
+      ld16<T>(rj + G, rv[a]);
+      if constexpr (NA == 2) ld16<T>(pold + G, pv[a]);
+    }
+#pragma unroll
+    for (int a = 0; a < UA; ++a) {
+      const int G = G0 + a * NT * W;
+      if (G >= s1) continue;
+#pragma unroll
+      for (int u = 0; u < W; ++u) pv[a][u] = NA == 2 ? rv[a][u] + be * pv[a][u] : rv[a][u];
+      u32x4 ra, pa;
+      __builtin_memcpy(&ra, rv[a], 16);
+      __builtin_memcpy(&pa, pv[a], 16);
+      *(u32x4*)(lr + (G - s0)) = ra;
+      *(u32x4*)(lp + (G - s0)) = pa;
+    }
+  }
+  __syncthreads();
+  // s = C p at a point of the staged range (its neighbours are staged)
+  auto s_at = [&](int P, int iz, int ix) -> T {
+    const int q = P - s0;
+    const T pc = lp[q];
+    const T lft = ix > 0 ? lp[q - 1] : (T)0, rgt = ix < nx - 1 ? lp[q + 1] : (T)0;
+    const T up = iz > 0 ? lp[q - nx] : (T)0, dn = iz < nz - 1 ? lp[q + nx] : (T)0;
+    return stencil7<T, false>(pc, lft, rgt, (T)0, (T)0, up, dn, iz, 0, ix, g, c0, cz, cy, cx);
+  };
+  // r_{j+1} over the item and the row after it, in place of r_j
+  const int pe = e + nx < N ? e + nx : N;
+  for (int G = b + (int)threadIdx.x * W; G < pe; G += NT * W) {
+    int iz, iy, ix0;
+    g.coords(G, iz, iy, ix0);
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+      const int P = G + u;
+      if (P >= pe) break;
+      int izu = iz, ixu = ix0 + u;
+      if (ixu >= nx) g.coords(P, izu, iy, ixu);
+      const T sv = s_at(P, izu, ixu);
+      lr[P - s0] = lr[P - s0] - al * sv;
+    }
+  }
+  __syncthreads();
+  // the item's points: partial sums and stores
+  acc_t acc[3] = {0, 0, 0};  // gamma, Q, X
+  auto point_group = [&](int G, T (&xv)[W]) {
+    int iz, iy, ix0;
+    g.coords(G, iz, iy, ix0);
+    const int cnt = e - G < W ? e - G : W;
+    T pn[W], rn[W];
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+      const int P = G + u;
+      const int q = P - s0;
+      pn[u] = lp[q];
+      rn[u] = lr[q];
+      xv[u] = xv[u] + al * pn[u];
+      if (u >= cnt) continue;
+      int izu = iz, ixu = ix0 + u;
+      if (ixu >= nx) g.coords(P, izu, iy, ixu);
+      const T sv = s_at(P, izu, ixu);
+      const acc_t rc = (acc_t)rn[u];
+      acc[0] += rc * rc;
+      acc[2] += rc * (acc_t)sv;
+      acc_t t = (acc_t)cf[0] * rc * rc;
+      if (ixu < nx - 1) { const acc_t dd = (acc_t)lr[q + 1] - rc; t += (acc_t)cf[3] * dd * dd; }
+      if (izu < nz - 1) { const acc_t dd = (acc_t)lr[q + nx] - rc; t += (acc_t)cf[1] * dd * dd; }
+      acc[1] += t;
+    }
+    if (xvec) {
+      st16p<T>(x, G, cnt, xv);
+    } else {
+#pragma unroll
+      for (int u = 0; u < W; ++u)
+        if (u < cnt) x[G + u] = xv[u];
+    }
+    st16<T>(pnb + G, pn);
+    st16<T>(rnb + G, rn);
+  };
+#pragma unroll
+  for (int a = 0; a < UX; ++a) {
+    const int G = b + (int)threadIdx.x * W + a * NT * W;
+    if (G < e) point_group(G, xpre[a]);
+  }
+  for (int G = b + (int)threadIdx.x * W + UX * NT * W; G < e; G += NT * W) {
+    const int cnt = e - G < W ? e - G : W;
+    T xv[W];
+    if (xvec) {
+      ld16p<T>(x, G, N, xv);
+    } else {
+#pragma unroll
+      for (int u = 0; u < W; ++u) xv[u] = u < cnt ? x[G + u] : (T)0;
+    }
+    point_group(G, xv);
+  }
+  block_total_n<3, NT>(acc, lds);
+  if (threadIdx.x == 0) {
+    gout[iti] = acc[0];
+    qout[iti] = acc[1];
+    xout[iti] = acc[2];
   }
 }
 
@@ -3596,6 +3859,26 @@ void launch_init(hipStream_t st, const InstDesc* __restrict__ D, int inst, int64
 template <typename T, int NT>
 void launch_cg(hipStream_t st, const Tables& t, const Opts& o) {
   k_rhs<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.pt, t.rr_part);
+  if (t.cg_form == 2) {
+    k_cg2_d0<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.pt, t.pq_part);
+    double* g[2] = {t.rr_part, t.rr2_part};
+    double* q[2] = {t.pq_part, t.pq2_part};
+    double* x[2] = {t.xq_part, t.xq2_part};
+    const size_t lb = (size_t)2 * t.cg2_cap * sizeof(T);
+    for (int j = 0; j < o.cg_max; ++j) {
+      const int a = j & 1, b = (j + 1) & 1;
+      if (j == 0)
+        k_cg2_step<T, NT, 1><<<t.npt, NT, lb, st>>>(t.D, t.pt, j, g[a], q[a], x[a], g[b], q[b], x[b], o, t.cg2_cap);
+      else
+        k_cg2_step<T, NT, 2><<<t.npt, NT, lb, st>>>(t.D, t.pt, j, g[a], q[a], x[a], g[b], q[b], x[b], o, t.cg2_cap);
+      if (t.cg2_rest) {
+        // the other instances' steps (their items' partials only)
+        k_cg_dir<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.pt, j, t.rr_part, t.pq_part, o);
+        k_cg_upd<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.pt, j, t.pq_part, t.rr_part);
+      }
+    }
+    return;
+  }
   if (t.cg_form == 1) {
     k_cg1_w0<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.pt, t.pq_part);
     for (int j = 0; j < o.cg_max; ++j) {
@@ -3624,6 +3907,10 @@ void launch_point_phase(hipStream_t st, const Tables& t, const Opts& o, int phas
   if (phase == 6)
     k_cg1_step<T, NT, 3><<<t.npt, NT, 0, st>>>(t.D, t.pt, 1, t.rr2_part, t.pq2_part, t.rr_part, t.pq_part, o);
   if (phase == 7) k_cg1_w0<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.pt, t.pq_part);
+  if (phase == 9 && t.cg_form == 2)
+    k_cg2_step<T, NT, 2><<<t.npt, NT, (size_t)2 * t.cg2_cap * sizeof(T), st>>>(
+        t.D, t.pt, 1, t.rr2_part, t.pq2_part, t.xq2_part, t.rr_part, t.pq_part, t.xq_part, o, t.cg2_cap);
+  if (phase == 10) k_cg2_d0<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.pt, t.pq_part);
 }
 
 template <typename T>
@@ -3667,7 +3954,8 @@ void launch_iteration(hipStream_t st, const Tables& t, const Opts& o) {
 
 // One kernel of the iteration on its own (timing); CG kernels use step 1.
 // 0 rhs, 1 cg_dir, 2 cg_upd, 3 proj, 4 thr_w, 5 thr_apply, 6 one-reduction
-// CG step, 7 its w_0 = C r_0 pass, 8 line-wise sets.
+// CG step, 7 its w_0 = C r_0 pass, 8 line-wise sets, 9 LDS-staged CG step
+// (only where the batch runs that form), 10 its r_0^T C r_0 pass.
 template <typename T>
 void launch_phase(hipStream_t st, const Tables& t, const Opts& o, int phase) {
   switch (phase) {
@@ -3676,6 +3964,8 @@ void launch_phase(hipStream_t st, const Tables& t, const Opts& o, int phase) {
     case 2:
     case 6:
     case 7:
+    case 9:
+    case 10:
       if (t.pt_threads == 256) launch_point_phase<T, 256>(st, t, o, phase);
       else launch_point_phase<T, 512>(st, t, o, phase);
       break;

@@ -39,15 +39,16 @@ def main():
     tiles = [int(v) for v in a.tiles.split(",")] if a.tiles else []
     if tiles:
         batch.set_tiles(*tiles)
-    one_red = len(tiles) > 5 and tiles[5] == 1
+    form = tiles[5] if len(tiles) > 5 else 0
     batch.run(2)
     torch.cuda.synchronize()
     for sl in slots:
         r_, g_, _, _ = batch.get_params(sl)
         batch.set_params(sl, r_, g_, 2, True)
     out = {}
-    cg = ((("cg1_step", sip.K_CG1_STEP), ("cg1_w0", sip.K_CG1_W0)) if one_red else
-          (("cg_dir", sip.K_CG_DIR), ("cg_upd", sip.K_CG_UPD)))
+    cg = {0: (("cg_dir", sip.K_CG_DIR), ("cg_upd", sip.K_CG_UPD)),
+          1: (("cg1_step", sip.K_CG1_STEP), ("cg1_w0", sip.K_CG1_W0)),
+          2: (("cg2_step", sip.K_CG2_STEP), ("cg2_d0", sip.K_CG2_D0))}[form]
     has_line = any(s.get("line") is not None for _, sets in insts for s in sets)
     for name, kid in cg + (("rhs", sip.K_RHS), ("proj", sip.K_PROJ), ("thr_w", sip.K_THR_W),
                            ("thr_apply", sip.K_THR_APPLY)) + ((("line", sip.K_LINE),) if has_line else ()):

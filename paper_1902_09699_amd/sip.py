@@ -22,7 +22,7 @@ OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED, EBUDGET, ETOOLARGE = 0, -1, -2
 F32, F64 = 0, 1
 OPS = {"I": 0, "DZ": 1, "DY": 2, "DX": 3, "GRAD": 4, "LAT": 5}
 KINDS = {"bounds": 0, "l1": 1, "card": 2, "l2": 3, "annulus": 4}
-K_RHS, K_CG_DIR, K_CG_UPD, K_PROJ, K_THR_W, K_THR_APPLY, K_CG1_STEP, K_CG1_W0, K_LINE = range(9)
+K_RHS, K_CG_DIR, K_CG_UPD, K_PROJ, K_THR_W, K_THR_APPLY, K_CG1_STEP, K_CG1_W0, K_LINE, K_CG2_STEP, K_CG2_D0 = range(11)
 FIELD_Y, FIELD_V, FIELD_VHAT0, FIELD_V0, FIELD_Y0, FIELD_R, FIELD_XS0, FIELD_XS1 = range(8)
 
 

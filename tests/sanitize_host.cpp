@@ -75,11 +75,11 @@ int main() {
       t.pt_max_items = uni(0, 4096);
       t.thr_max_items = uni(0, 4096);
       t.pt_threads = uni(0, 10) == 0 ? 384 : (uni(0, 1) ? 256 : 512);
-      t.cg_form = uni(0, 10) == 0 ? 2 : uni(0, 1);
+      t.cg_form = uni(0, 10) == 0 ? 3 : uni(0, 2);
     }
     const bool tiles_ok = t.pt_points >= 256 && t.thr_points >= 256 && t.pt_max_items >= 1 &&
                           t.thr_max_items >= 1 && (t.pt_threads == 256 || t.pt_threads == 512) &&
-                          (t.cg_form == 0 || t.cg_form == 1);
+                          (t.cg_form >= 0 && t.cg_form <= 2);
     const int64_t pb = sip_plan_bytes(&g, sets, nsets, &o, &t);
     if (v == SIP_OK) {
       ++valid;

@@ -1,6 +1,6 @@
 """The tile autotuner's host side: every candidate is a setting the library
 accepts (sizes multiples of 256, item caps >= 1, 256- or 512-thread blocks,
-CG form 0 or 1, as sip_batch_set_tiles documents), candidates are distinct,
+CG form 0, 1 or 2, as sip_batch_set_tiles documents), candidates are distinct,
 and the workload key separates the classes it is meant to separate."""
 import pytest
 
@@ -14,11 +14,11 @@ def test_candidates_are_valid_and_distinct():
         assert pt_points % 256 == 0 and thr_points % 256 == 0 and pt_points >= 256 and thr_points >= 256
         assert pt_max_items >= 1 and thr_max_items >= 1
         assert pt_threads in (256, 512)
-        assert cg_form in (0, 1)
+        assert cg_form in (0, 1, 2)
         assert c not in seen
         seen.add(c)
-    # both CG arrangements and both block sizes are on the list
-    assert {c[5] for c in autotune.CANDIDATES} == {0, 1}
+    # every CG arrangement and both block sizes are on the list
+    assert {c[5] for c in autotune.CANDIDATES} == {0, 1, 2}
     assert {c[4] for c in autotune.CANDIDATES} == {256, 512}
 
 

@@ -57,7 +57,7 @@ def _e1_case(shape, seed):
     return m, wl.finalize(m, sets)
 
 
-@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("form", [0, 1, 2])
 def test_outer_iterations_match_oracle(form):
     """Four outer iterations on a 13x17 layered model with the paper's first
     comparison sets; 25 inner iterations x 10 CG steps per sub-problem (no

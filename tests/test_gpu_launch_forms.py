@@ -30,7 +30,7 @@ def _run(instances, opts, iters, tiles):
     return out
 
 
-@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("form", [0, 1, 2])
 def test_same_iterates_in_small_and_large_batches(form):
     m, sets = make_case("four_sets_2d", 3)
     m = wl.rounded(m, "f32")

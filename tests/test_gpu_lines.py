@@ -78,7 +78,8 @@ def _card_line_mask(w, k, lines, rtol):
 
 CASES = [("rows_card_2d", "f32", 0), ("rows_card_2d", "f64", 0), ("cols_mixed_2d", "f32", 0),
          ("cols_mixed_2d", "f64", 1), ("fibers_3d", "f32", 0), ("fibers_3d", "f64", 0),
-         ("annulus_rows_2d", "f64", 0), ("annulus_rows_2d", "f32", 1)]
+         ("annulus_rows_2d", "f64", 0), ("annulus_rows_2d", "f32", 1), ("rows_card_2d", "f32", 2),
+         ("cols_mixed_2d", "f64", 2)]
 
 
 @pytest.mark.parametrize("kind,field,form", CASES)

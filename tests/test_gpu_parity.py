@@ -42,6 +42,10 @@ def _prep(kind, field, seed=0):
     # one-reduction CG steps
     ("box_tv_2d", "f64", 512, 1), ("four_sets_2d", "f32", 512, 1), ("box_tv_lat_3d", "f32", 512, 1),
     ("mixed_2d", "f32", 256, 1), ("mixed_3d", "f64", 256, 1), ("box_tv_lat_3d", "f64", 512, 1),
+    # LDS-staged one-launch CG steps (3D grids run the textbook form under it)
+    ("box_tv_2d", "f64", 512, 2), ("box_tv_2d", "f32", 256, 2), ("four_sets_2d", "f32", 512, 2),
+    ("four_sets_2d", "f64", 256, 2), ("mixed_2d", "f32", 256, 2), ("mixed_2d", "f64", 512, 2),
+    ("box_tv_lat_3d", "f32", 512, 2),
 ])
 def test_step_parity(kind, field, threads, form):
     m, sets = _prep(kind, field)
@@ -265,7 +269,7 @@ def _oracle_run_with_schedule(m, shape, sets, opts):
     return st.x.reshape(shape), np.array(rho), np.array(gam)
 
 
-@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("form", [0, 1, 2])
 @pytest.mark.parametrize("name", sorted(EDGE_CASES))
 def test_edge_cases_f64(name, form):
     """Degenerate inputs, float64.  The adapt-rho-gamma rule is discontinuous
@@ -367,7 +371,7 @@ def test_card_exact_ties_across_items(field):
     assert tied > 1
 
 
-@pytest.mark.parametrize("field,form", [("f64", 0), ("f64", 1), ("f32", 0), ("f32", 1)])
+@pytest.mark.parametrize("field,form", [("f64", 0), ("f64", 1), ("f64", 2), ("f32", 0), ("f32", 1), ("f32", 2)])
 def test_unaligned_x(field, form):
     """x one element past a 16-byte boundary: the RHS and CG kernels take
     their per-point path.  Its iterates must match the grouped path's (same
