@@ -266,13 +266,14 @@ int32_t sip_batch_schedule(sip_batch* b, int32_t slot, double* rho, double* gamm
  * launch per step (the same iterates in exact arithmetic, different
  * rounding; 10 instead of 8 vectors of traffic per step, fewer launches: it
  * pays on grids too small to keep the GPU busy); 2 one launch per step that
- * stages r and p of each item (and one row before, two after) in LDS, forms
- * C p and the next residual there and stores x, r, p only (6 vectors), with
- * p^T C p from its expansion in the previous step's sums (the textbook
- * iterates' expressions; only that double is summed another way), plus one
- * r_0^T C r_0 pass per x-minimization — for the instances without a y
- * axis whose items and three rows fit 60 KiB of LDS (the batch's other
- * instances run form 0 steps beside them).
+ * stages p of each item with one row before and two after, and r of the
+ * item and the row after, in LDS, forms C p and the next residual there and
+ * stores x, r, p only (6 vectors), with p^T C p from its expansion in the
+ * previous step's sums (the textbook iterates' expressions; only that
+ * double is summed another way), plus one r_0^T C r_0 pass per
+ * x-minimization — for the instances without a y axis whose staged rows
+ * fit 60 KiB of LDS (the batch's other instances run form 0 steps beside
+ * them).
  * Results are bit-identical
  * for any batch composition at fixed tile settings.  Applies from the next
  * sip_batch_run.  Defaults 2048/512, 2048/512, 512 threads, form 0.

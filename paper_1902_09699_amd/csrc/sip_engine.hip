@@ -615,29 +615,29 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   if (lline)
     HIP_OK(hipMemcpyAsync(b->d_line, line_l.data(), line_l.size() * sizeof(LineItem), hipMemcpyHostToDevice, stream));
   // The LDS-staged CG form runs the steps of each instance without a y axis
-  // whose items, with one row before and two after, fit 60 KiB of a block's
-  // LDS (the rest of 64 KiB holds the block sums); the batch's other
-  // instances run the two-launch steps beside them.  Whether an instance
-  // qualifies depends on its own grid and the tile settings only.
-  int form = b->tiles.cg_form, cap2 = 0, rest2 = 0;
+  // whose items fit a block's LDS with one row before and two after (p) and
+  // one row after (r) in 60 KiB (the rest of 64 KiB holds the block sums);
+  // the batch's other instances run the two-launch steps beside them.
+  // Whether an instance qualifies depends on its own grid and the tile
+  // settings only.
+  int form = b->tiles.cg_form, cap2 = 0, capr2 = 0, rest2 = 0;
   if (form == 2) {
     const int64_t W = b->opts.field == SIP_F64 ? 2 : 4, esz = b->opts.field == SIP_F64 ? 8 : 4;
-    std::vector<int64_t> need((size_t)b->max_slots, 0);
-    for (const PtItem& q : pt) {
-      const Slot& sl = b->slots[q.inst];
-      need[q.inst] = std::max<int64_t>(need[q.inst], (int64_t)q.len + 3 * sl.desc.n[2] + 2 * W);
-    }
-    int64_t cap = 0;
+    std::vector<int64_t> len((size_t)b->max_slots, 0);
+    for (const PtItem& q : pt) len[q.inst] = std::max<int64_t>(len[q.inst], q.len);
+    int64_t cp = 0, cr = 0;
     for (int si = 0; si < b->max_slots; ++si) {
       Slot& sl = b->slots[si];
       if (!sl.used) continue;
-      const int64_t c = (need[si] + W - 1) / W * W;
-      sl.desc.cg2 = (sl.desc.n[1] == 1 && need[si] > 0 && 2 * c * esz <= 61440) ? 1 : 0;
-      if (sl.desc.cg2) cap = std::max(cap, c);
+      const int64_t nx = sl.desc.n[2];
+      const int64_t p = (len[si] + 3 * nx + 2 * W + W - 1) / W * W, r = (len[si] + nx + W + W - 1) / W * W;
+      sl.desc.cg2 = (sl.desc.n[1] == 1 && len[si] > 0 && (p + r) * esz <= 61440) ? 1 : 0;
+      if (sl.desc.cg2) { cp = std::max(cp, p); cr = std::max(cr, r); }
       else rest2 = 1;
     }
-    if (cap == 0) form = 0;
-    cap2 = (int)cap;
+    if (cp == 0) form = 0;
+    cap2 = (int)cp;
+    capr2 = (int)cr;
   } else {
     for (int si = 0; si < b->max_slots; ++si) b->slots[si].desc.cg2 = 0;
   }
@@ -688,10 +688,11 @@ int32_t rebuild_tables(sip_batch* b, hipStream_t stream) {
   if (sfuse != t.sel_fused) relaunch_cap = true;
   t.sel_fused = sfuse;
   const bool threads_changed = t.pt_threads != (int)b->tiles.pt_threads || t.cg_form != form || t.cg2_cap != cap2 ||
-                               t.cg2_rest != rest2;
+                               t.cg2_capr != capr2 || t.cg2_rest != rest2;
   t.pt_threads = (int)b->tiles.pt_threads;
   t.cg_form = form;
   t.cg2_cap = cap2;
+  t.cg2_capr = capr2;
   t.cg2_rest = form == 2 ? rest2 : 0;
   b->live_items = (int)pt.size() + (int)thr.size() + (int)line.size();
   b->live_inst = (int)inst.size();

@@ -188,7 +188,8 @@ struct Tables {
                                        // when the first selection stage runs inside the refine pass
   int pt_threads;  // threads per block of the RHS and CG kernels (256 or 512)
   int cg_form;     // 0: two launches per CG step; 1: one (Chronopoulos-Gear); 2: one, LDS-staged (2D)
-  int cg2_cap;     // form 2: LDS field values per array (longest item + 3 rows + 2 groups)
+  int cg2_cap;     // form 2: LDS field values of p (longest item + 3 rows + 2 groups)
+  int cg2_capr;    // form 2: LDS field values of r (longest item + 1 row + 1 group)
   int cg2_rest;    // form 2: some instances (3D, or rows too long for LDS) run the two-launch steps
   int sel_passes;  // refine + select passes after the first stage: 1 (it always compacts) or 2
   int fuse_sets;   // projection and w passes in one launch (small, latency-bound batches)

@@ -1311,8 +1311,9 @@ __global__ __launch_bounds__(NT) void k_cg2_d0(const InstDesc* __restrict__ D, c
   if (threadIdx.x == 0) qpart[it.idx] = acc;
 }
 
-// Step j (NA = 1 at j = 0, where p_0 = r_0; NA = 2 after).  Dynamic LDS: two
-// arrays of `cap` field values (cap >= the longest item + 3 rows + 2 W).
+// Step j (NA = 1 at j = 0, where p_0 = r_0; NA = 2 after).  Dynamic LDS: p
+// over the staged range (`cap` >= the longest item + 3 rows + 2 W field
+// values), then r over the item and the row after it (the rest).
 template <typename T, int NT, int NA>
 __global__ __launch_bounds__(NT) void k_cg2_step(const InstDesc* __restrict__ D, const PtItem* __restrict__ items, int j,
                                                   const double* gin, const double* qin, const double* xin,
@@ -1320,8 +1321,8 @@ __global__ __launch_bounds__(NT) void k_cg2_step(const InstDesc* __restrict__ D,
   constexpr int W = Grp<T>::W;
   extern __shared__ __align__(16) unsigned char cg2_dyn[];
   __shared__ acc_t lds[lds_sum<3, NT>()];
-  T* lr = (T*)cg2_dyn;
-  T* lp = lr + cap;
+  T* lp = (T*)cg2_dyn;  // p_j at P - s0
+  T* lr = lp + cap;     // r_j, then r_{j+1}, at P - b
   const PtItem it = items[blockIdx.x];
   if (it.inst < 0) return;
   const int iti = it.idx;
@@ -1381,11 +1382,13 @@ __global__ __launch_bounds__(NT) void k_cg2_step(const InstDesc* __restrict__ D,
   const T c0 = (T)qs.c0, cz = (T)qs.cax[0], cy = (T)qs.cax[1], cx = (T)qs.cax[2];
   const double cf[4] = {qs.c0, qs.cax[0], qs.cax[1], qs.cax[2]};
   const int b = it.begin, e = it.begin + it.len;
-  // staged range: one row before the item and two after it, whole groups
-  // (the work arrays are padded to whole 256-byte blocks past N)
+  // staged range of p: one row before the item and two after it, whole
+  // groups (the work arrays are padded to whole 256-byte blocks past N); r
+  // over the item and the row after it
   const int s0 = (b - nx > 0 ? b - nx : 0) & ~(W - 1);
   const int hi = e + 2 * nx < N ? e + 2 * nx : N;
   const int s1 = (hi + W - 1) & ~(W - 1);
+  const int pe = e + nx < N ? e + nx : N;
   // x of the thread's first UX groups of the item, loaded with the staging
   // (x by elements when the caller's x is not 16-byte aligned)
   constexpr int UX = 2, UA = 4;
@@ -1421,7 +1424,7 @@ __global__ __launch_bounds__(NT) void k_cg2_step(const InstDesc* __restrict__ D,
       u32x4 ra, pa;
       __builtin_memcpy(&ra, rv[a], 16);
       __builtin_memcpy(&pa, pv[a], 16);
-      *(u32x4*)(lr + (G - s0)) = ra;
+      if (G >= b && G < pe) *(u32x4*)(lr + (G - b)) = ra;
       *(u32x4*)(lp + (G - s0)) = pa;
     }
   }
@@ -1435,7 +1438,6 @@ __global__ __launch_bounds__(NT) void k_cg2_step(const InstDesc* __restrict__ D,
     return stencil7<T, false>(pc, lft, rgt, (T)0, (T)0, up, dn, iz, 0, ix, g, c0, cz, cy, cx);
   };
   // r_{j+1} over the item and the row after it, in place of r_j
-  const int pe = e + nx < N ? e + nx : N;
   for (int G = b + (int)threadIdx.x * W; G < pe; G += NT * W) {
     int iz, iy, ix0;
     g.coords(G, iz, iy, ix0);
@@ -1446,7 +1448,7 @@ __global__ __launch_bounds__(NT) void k_cg2_step(const InstDesc* __restrict__ D,
       int izu = iz, ixu = ix0 + u;
       if (ixu >= nx) g.coords(P, izu, iy, ixu);
       const T sv = s_at(P, izu, ixu);
-      lr[P - s0] = lr[P - s0] - al * sv;
+      lr[P - b] = lr[P - b] - al * sv;
     }
   }
   __syncthreads();
@@ -1460,8 +1462,8 @@ __global__ __launch_bounds__(NT) void k_cg2_step(const InstDesc* __restrict__ D,
 #pragma unroll
     for (int u = 0; u < W; ++u) {
       const int P = G + u;
-      const int q = P - s0;
-      pn[u] = lp[q];
+      const int q = P - b;
+      pn[u] = lp[P - s0];
       rn[u] = lr[q];
       xv[u] = xv[u] + al * pn[u];
       if (u >= cnt) continue;
@@ -3864,7 +3866,7 @@ void launch_cg(hipStream_t st, const Tables& t, const Opts& o) {
     double* g[2] = {t.rr_part, t.rr2_part};
     double* q[2] = {t.pq_part, t.pq2_part};
     double* x[2] = {t.xq_part, t.xq2_part};
-    const size_t lb = (size_t)2 * t.cg2_cap * sizeof(T);
+    const size_t lb = (size_t)(t.cg2_cap + t.cg2_capr) * sizeof(T);
     for (int j = 0; j < o.cg_max; ++j) {
       const int a = j & 1, b = (j + 1) & 1;
       if (j == 0)
@@ -3908,7 +3910,7 @@ void launch_point_phase(hipStream_t st, const Tables& t, const Opts& o, int phas
     k_cg1_step<T, NT, 3><<<t.npt, NT, 0, st>>>(t.D, t.pt, 1, t.rr2_part, t.pq2_part, t.rr_part, t.pq_part, o);
   if (phase == 7) k_cg1_w0<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.pt, t.pq_part);
   if (phase == 9 && t.cg_form == 2)
-    k_cg2_step<T, NT, 2><<<t.npt, NT, (size_t)2 * t.cg2_cap * sizeof(T), st>>>(
+    k_cg2_step<T, NT, 2><<<t.npt, NT, (size_t)(t.cg2_cap + t.cg2_capr) * sizeof(T), st>>>(
         t.D, t.pt, 1, t.rr2_part, t.pq2_part, t.xq2_part, t.rr_part, t.pq_part, t.xq_part, o, t.cg2_cap);
   if (phase == 10) k_cg2_d0<T, NT><<<t.npt, NT, 0, st>>>(t.D, t.pt, t.pq_part);
 }
