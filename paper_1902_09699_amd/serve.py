@@ -67,8 +67,10 @@ def serving_opts(max_iter=200, stop_every=5, cg_max=10):
 class Lane:
     """One resident batch advanced on its own stream."""
 
-    def __init__(self, opts, arena_bytes, max_slots, stream):
+    def __init__(self, opts, arena_bytes, max_slots, stream, tiles=None):
         self.batch = sip.Batch(max_slots, arena_bytes, opts)
+        if tiles:
+            self.batch.set_tiles(*tiles)
         self.arena_bytes = int(arena_bytes)
         self.stream = stream
         self.active = {}
@@ -82,9 +84,11 @@ class Server:
     requests of at most `split_points` grid points go to one batch and larger
     ones to the other; each lane runs its chunks on its own stream, so small
     requests iterate at their own pace while large ones are on the GPU, and
-    the host admits and retires on one lane while the other computes."""
+    the host admits and retires on one lane while the other computes.
+    tiles: sip_batch_set_tiles arguments of every lane (None: the engine's
+    defaults)."""
 
-    def __init__(self, opts, arena_bytes, max_slots=256, chunk=10, lanes=1, split_points=1 << 18):
+    def __init__(self, opts, arena_bytes, max_slots=256, chunk=10, lanes=1, split_points=1 << 18, tiles=None):
         import torch
         self.opts = opts
         self.chunk = int(chunk)
@@ -96,7 +100,7 @@ class Server:
             raise ValueError("lanes must be 1 or 2")
         per = self.arena_bytes // n
         streams = [torch.cuda.current_stream()] if n == 1 else [torch.cuda.Stream() for _ in range(n)]
-        self.lanes = [Lane(opts, per, max_slots, st) for st in streams]
+        self.lanes = [Lane(opts, per, max_slots, st, tiles) for st in streams]
         self.batch = self.lanes[0].batch  # the one batch of a single-lane server
 
     def close(self):
@@ -227,7 +231,9 @@ def main():
     ap.add_argument("--plain-requests", type=int, default=0, help="requests for the plain form (0: same)")
     ap.add_argument("--check", type=int, default=8, help="requests re-run alone to compare results")
     ap.add_argument("--lanes", type=int, default=2, help="resident batches (1, or 2 split by size)")
+    ap.add_argument("--tiles", default=None, help="sip_batch_set_tiles arguments, comma-separated")
     a = ap.parse_args()
+    tiles = tuple(int(v) for v in a.tiles.split(",")) if a.tiles else None
     import torch
     opts = serving_opts(a.max_iter)
     reqs = make_requests(a.requests, a.rate, a.frac3d)
@@ -236,7 +242,7 @@ def main():
           flush=True)
     # warm the code objects and graph capture on a few small requests
     warm = make_requests(4, 1e9, 0.0, seed0=9000, max2d=128)
-    srv = Server(opts, int(a.arena_gb * (1 << 30)), a.slots, a.chunk, lanes=a.lanes)
+    srv = Server(opts, int(a.arena_gb * (1 << 30)), a.slots, a.chunk, lanes=a.lanes, tiles=tiles)
     srv.run(warm, realtime=False)
     t = time.perf_counter()
     info = srv.run(reqs, realtime=True)
