@@ -48,3 +48,29 @@ def test_oversized_request_is_rejected_not_hung():
     info = srv.run(reqs, realtime=False)
     srv.close()
     assert info["rejected"] >= 1
+
+
+@pytest.mark.parametrize("tiles", [(1024, 512, 1024, 512, 256, 2), (1024, 512, 1024, 512, 512, 1)])
+def test_served_results_under_other_tiles_equal_a_plan(tiles):
+    """Lanes under fixed tiles (the LDS-staged CG form, whose 2D requests run
+    the one-launch steps and 3D ones the textbook steps beside them, and the
+    one-reduction form): every result equals a plan of the same tiles run
+    alone."""
+    import torch
+    opts = serve.serving_opts(max_iter=60)
+    reqs = _small_mix(10)
+    need = [sip.workspace_bytes(r.m.shape, r.sets, opts) for r in reqs]
+    srv = serve.Server(opts, 4 * max(need) * 2, max_slots=4, chunk=5, lanes=2, split_points=5000, tiles=tiles)
+    info = srv.run(reqs, realtime=False)
+    srv.close()
+    print(f"\n[serve] tiles {tiles}: chunks {info['chunks']}", flush=True)
+    assert info["rejected"] == 0
+    assert any(r.m.ndim == 3 for r in reqs) and any(r.m.ndim == 2 for r in reqs)
+    for r in reqs:
+        assert r.result is not None and r.result["status"] == 0
+        md = torch.tensor(r.m, dtype=torch.float32, device="cuda")
+        plan = sip.Plan(r.m.shape, r.sets, opts, tiles=tiles)
+        x, res = plan.project(md)
+        plan.close()
+        assert np.array_equal(x.cpu().numpy(), r.x), r.rid
+        assert res["iters"] == r.result["iters"]
