@@ -60,6 +60,14 @@ def make_requests(n, rate, frac3d=0.05, seed0=3000, max2d=1024, side3d=(64, 160)
     return out
 
 
+# Tiles of the served lanes: the engine's default items with 256-thread
+# blocks for the RHS and CG kernels (200 requests at 200 req/s, 5% 3D:
+# p50/p99 167-185/397-426 ms against 222/504 ms with 512-thread blocks; the
+# LDS-staged and one-reduction CG forms were slower on this mix).  The
+# plain form keeps the engine's defaults, its own best.
+SERVED_TILES = (2048, 512, 2048, 512, 256, 0)
+
+
 def serving_opts(max_iter=200, stop_every=5, cg_max=10):
     return sip.make_opts("f32", max_iter=max_iter, cg_max=cg_max, cg_fixed=0, stop_every=stop_every)
 
@@ -191,11 +199,11 @@ class Server:
         return {"chunks": chunks, "peak_arena_bytes": peak_bytes, "rejected": len(rejected)}
 
 
-def serve_plain(requests, opts, arena_bytes, chunk=10):
+def serve_plain(requests, opts, arena_bytes, chunk=10, tiles=None):
     """The plain per-instance form: the same engine with one slot, so each
     request runs alone, in arrival order (graphs are reused across requests
     whose work tables fit the same launch sizes)."""
-    srv = Server(opts, arena_bytes, max_slots=1, chunk=chunk, lanes=1)
+    srv = Server(opts, arena_bytes, max_slots=1, chunk=chunk, lanes=1, tiles=tiles)
     srv.run(make_requests(2, 1e9, 0.0, seed0=9100, max2d=128), realtime=False)
     info = srv.run(requests, realtime=True)
     srv.close()
@@ -231,9 +239,12 @@ def main():
     ap.add_argument("--plain-requests", type=int, default=0, help="requests for the plain form (0: same)")
     ap.add_argument("--check", type=int, default=8, help="requests re-run alone to compare results")
     ap.add_argument("--lanes", type=int, default=2, help="resident batches (1, or 2 split by size)")
-    ap.add_argument("--tiles", default=None, help="sip_batch_set_tiles arguments, comma-separated")
+    ap.add_argument("--tiles", default=None,
+                    help="sip_batch_set_tiles arguments, comma-separated, for both forms (default: SERVED_TILES "
+                         "for the served lanes, the engine's defaults for the plain form)")
     a = ap.parse_args()
-    tiles = tuple(int(v) for v in a.tiles.split(",")) if a.tiles else None
+    tiles = tuple(int(v) for v in a.tiles.split(",")) if a.tiles else SERVED_TILES
+    plain_tiles = tiles if a.tiles else None
     import torch
     opts = serving_opts(a.max_iter)
     reqs = make_requests(a.requests, a.rate, a.frac3d)
@@ -250,11 +261,13 @@ def main():
     served.update(info)
     served["wall_s"] = round(time.perf_counter() - t, 3)
     print(json.dumps(served), flush=True)
-    # same result alone and in the mix
+    # same result alone (a plan of the same tiles) and in the mix
     diffs = []
     for r in reqs[: a.check]:
         md = torch.tensor(r.m, dtype=torch.float32, device="cuda")
-        x, res = sip.project(md, r.sets, opts)
+        plan = sip.Plan(r.m.shape, r.sets, opts, tiles=tiles)
+        x, res = plan.project(md)
+        plan.close()
         xa = x.cpu().numpy()
         diffs.append(float(np.max(np.abs(xa - r.x)) / max(np.max(np.abs(xa)), 1e-30)))
     if diffs:
@@ -262,7 +275,7 @@ def main():
     srv.close()
     if a.plain:
         plain_reqs = make_requests(a.plain_requests or a.requests, a.rate, a.frac3d)
-        info = serve_plain(plain_reqs, opts, int(a.arena_gb * (1 << 30)), a.chunk)
+        info = serve_plain(plain_reqs, opts, int(a.arena_gb * (1 << 30)), a.chunk, plain_tiles)
         plain = summary(plain_reqs, "plain")
         plain.update(info)
         print(json.dumps(plain), flush=True)
