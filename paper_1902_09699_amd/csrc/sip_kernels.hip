@@ -2545,7 +2545,7 @@ __global__ __launch_bounds__(kBlock) void k_sel1(const InstDesc* __restrict__ D,
 
 // Keys of list A one refine block reads (at least): list A goes to the
 // pipeline's first ceil(nspec / kListChunk) blocks, the others have no work.
-constexpr unsigned long long kListChunk = 8192;
+constexpr unsigned long long kListChunk = 2048;
 
 // Whether refine pass `pass` (0 or 1; 1 is the last pass of the iteration)
 // appends candidate keys: the first when digits remain after the one it
