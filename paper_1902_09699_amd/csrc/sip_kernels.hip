@@ -1429,53 +1429,102 @@ __global__ __launch_bounds__(NT) void k_cg2_step(const InstDesc* __restrict__ D,
     }
   }
   __syncthreads();
-  // s = C p at a point of the staged range (its neighbours are staged)
-  auto s_at = [&](int P, int iz, int ix) -> T {
-    const int q = P - s0;
-    const T pc = lp[q];
-    const T lft = ix > 0 ? lp[q - 1] : (T)0, rgt = ix < nx - 1 ? lp[q + 1] : (T)0;
-    const T up = iz > 0 ? lp[q - nx] : (T)0, dn = iz < nz - 1 ? lp[q + nx] : (T)0;
-    return stencil7<T, false>(pc, lft, rgt, (T)0, (T)0, up, dn, iz, 0, ix, g, c0, cz, cy, cx);
+  // The stencil and update phases read LDS by whole groups (16 bytes per
+  // lane, consecutive lanes on consecutive groups: no bank conflicts), the
+  // row neighbours too when the row length is a multiple of W (then a
+  // group never straddles two rows), and single values only at a group's
+  // two ends.  Values read for a point outside the grid or past the staged
+  // rows are never used (the stencil's bounds checks drop them).
+  const bool zvec = d.vec_nb != 0;
+  auto ldg = [&](const T* base, int q, T (&o)[W]) {
+    const u32x4 v4 = *(const u32x4*)(base + q);
+    __builtin_memcpy(o, &v4, 16);
   };
-  // r_{j+1} over the item and the row after it, in place of r_j
-  for (int G = b + (int)threadIdx.x * W; G < pe; G += NT * W) {
-    int iz, iy, ix0;
-    g.coords(G, iz, iy, ix0);
+  // s = C p at the W points of the group at G (its centre values into pc)
+  auto s_group = [&](int G, int iz0, int ix0, T (&pc)[W], T (&sv)[W]) {
+    const int q0 = G - s0;
+    ldg(lp, q0, pc);
+    const T pl = lp[q0 > 0 ? q0 - 1 : 0], pr = lp[q0 + W];
+    T up[W], dn[W];
+    if (zvec) {
+      if (iz0 > 0) ldg(lp, q0 - nx, up);
+      else {
+#pragma unroll
+        for (int u = 0; u < W; ++u) up[u] = (T)0;
+      }
+      if (iz0 < nz - 1) ldg(lp, q0 + nx, dn);
+      else {
+#pragma unroll
+        for (int u = 0; u < W; ++u) dn[u] = (T)0;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < W; ++u) {
+        const int qu = q0 + u - nx, qd = q0 + u + nx;
+        up[u] = qu >= 0 ? lp[qu] : (T)0;
+        dn[u] = lp[qd];
+      }
+    }
 #pragma unroll
     for (int u = 0; u < W; ++u) {
-      const int P = G + u;
-      if (P >= pe) break;
-      int izu = iz, ixu = ix0 + u;
-      if (ixu >= nx) g.coords(P, izu, iy, ixu);
-      const T sv = s_at(P, izu, ixu);
-      lr[P - b] = lr[P - b] - al * sv;
+      int izu = iz0, iyu = 0, ixu = ix0 + u;
+      if (ixu >= nx) g.coords(G + u, izu, iyu, ixu);
+      const T lft = u == 0 ? pl : pc[u > 0 ? u - 1 : 0];
+      const T rgt = u == W - 1 ? pr : pc[u < W - 1 ? u + 1 : 0];
+      sv[u] = stencil7<T, false>(pc[u], lft, rgt, (T)0, (T)0, up[u], dn[u], izu, 0, ixu, g, c0, cz, cy, cx);
     }
+  };
+  // r_{j+1} over the item and the row after it, in place of r_j (the last
+  // group's values past the row after it are never read)
+  for (int G = b + (int)threadIdx.x * W; G < pe; G += NT * W) {
+    int iz0, iy0, ix0;
+    g.coords(G, iz0, iy0, ix0);
+    T pc[W], sv[W], rv[W];
+    s_group(G, iz0, ix0, pc, sv);
+    ldg(lr, G - b, rv);
+#pragma unroll
+    for (int u = 0; u < W; ++u) rv[u] = rv[u] - al * sv[u];
+    u32x4 v4;
+    __builtin_memcpy(&v4, rv, 16);
+    *(u32x4*)(lr + (G - b)) = v4;
   }
   __syncthreads();
   // the item's points: partial sums and stores
   acc_t acc[3] = {0, 0, 0};  // gamma, Q, X
   auto point_group = [&](int G, T (&xv)[W]) {
-    int iz, iy, ix0;
-    g.coords(G, iz, iy, ix0);
+    int iz0, iy0, ix0;
+    g.coords(G, iz0, iy0, ix0);
     const int cnt = e - G < W ? e - G : W;
-    T pn[W], rn[W];
+    const int q = G - b;
+    T pn[W], sv[W], rn[W], rz[W];
+    s_group(G, iz0, ix0, pn, sv);
+    ldg(lr, q, rn);
+    const T rx = lr[q + W];
+    if (zvec) {
+      if (iz0 < nz - 1) ldg(lr, q + nx, rz);
+      else {
+#pragma unroll
+        for (int u = 0; u < W; ++u) rz[u] = (T)0;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < W; ++u) rz[u] = lr[q + u + nx];
+    }
 #pragma unroll
     for (int u = 0; u < W; ++u) {
-      const int P = G + u;
-      const int q = P - b;
-      pn[u] = lp[P - s0];
-      rn[u] = lr[q];
       xv[u] = xv[u] + al * pn[u];
       if (u >= cnt) continue;
-      int izu = iz, ixu = ix0 + u;
-      if (ixu >= nx) g.coords(P, izu, iy, ixu);
-      const T sv = s_at(P, izu, ixu);
+      int izu = iz0, iyu = 0, ixu = ix0 + u;
+      if (ixu >= nx) g.coords(G + u, izu, iyu, ixu);
       const acc_t rc = (acc_t)rn[u];
       acc[0] += rc * rc;
-      acc[2] += rc * (acc_t)sv;
+      acc[2] += rc * (acc_t)sv[u];
       acc_t t = (acc_t)cf[0] * rc * rc;
-      if (ixu < nx - 1) { const acc_t dd = (acc_t)lr[q + 1] - rc; t += (acc_t)cf[3] * dd * dd; }
-      if (izu < nz - 1) { const acc_t dd = (acc_t)lr[q + nx] - rc; t += (acc_t)cf[1] * dd * dd; }
+      if (ixu < nx - 1) {
+        const acc_t dd = (acc_t)(u < W - 1 ? rn[u < W - 1 ? u + 1 : 0] : rx) - rc;
+        t += (acc_t)cf[3] * dd * dd;
+      }
+      if (izu < nz - 1) { const acc_t dd = (acc_t)rz[u] - rc; t += (acc_t)cf[1] * dd * dd; }
       acc[1] += t;
     }
     if (xvec) {
