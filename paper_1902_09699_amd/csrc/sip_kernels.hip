@@ -1475,11 +1475,12 @@ __global__ __launch_bounds__(NT) void k_cg2_step(const InstDesc* __restrict__ D,
     }
   };
   // r_{j+1} over the item and the row after it, in place of r_j (the last
-  // group's values past the row after it are never read)
-  for (int G = b + (int)threadIdx.x * W; G < pe; G += NT * W) {
+  // group's values past the row after it are never read); a thread's first
+  // UX groups are its first UX groups of the item too, so their p_j, s_j
+  // and r_{j+1} stay in registers for the sums and stores below
+  auto r_next = [&](int G, T (&pc)[W], T (&sv)[W], T (&rv)[W]) {
     int iz0, iy0, ix0;
     g.coords(G, iz0, iy0, ix0);
-    T pc[W], sv[W], rv[W];
     s_group(G, iz0, ix0, pc, sv);
     ldg(lr, G - b, rv);
 #pragma unroll
@@ -1487,18 +1488,27 @@ __global__ __launch_bounds__(NT) void k_cg2_step(const InstDesc* __restrict__ D,
     u32x4 v4;
     __builtin_memcpy(&v4, rv, 16);
     *(u32x4*)(lr + (G - b)) = v4;
+  };
+  T pk[UX][W], sk[UX][W], rk[UX][W];
+#pragma unroll
+  for (int a = 0; a < UX; ++a) {
+    const int G = b + (int)threadIdx.x * W + a * NT * W;
+    if (G < pe) r_next(G, pk[a], sk[a], rk[a]);
+  }
+  for (int G = b + (int)threadIdx.x * W + UX * NT * W; G < pe; G += NT * W) {
+    T pc[W], sv[W], rv[W];
+    r_next(G, pc, sv, rv);
   }
   __syncthreads();
-  // the item's points: partial sums and stores
+  // the item's points: partial sums and stores (pn = p_j, sv = s_j and
+  // rn = r_{j+1} of the group)
   acc_t acc[3] = {0, 0, 0};  // gamma, Q, X
-  auto point_group = [&](int G, T (&xv)[W]) {
+  auto point_group = [&](int G, T (&xv)[W], const T (&pn)[W], const T (&sv)[W], const T (&rn)[W]) {
     int iz0, iy0, ix0;
     g.coords(G, iz0, iy0, ix0);
     const int cnt = e - G < W ? e - G : W;
     const int q = G - b;
-    T pn[W], sv[W], rn[W], rz[W];
-    s_group(G, iz0, ix0, pn, sv);
-    ldg(lr, q, rn);
+    T rz[W];
     const T rx = lr[q + W];
     if (zvec) {
       if (iz0 < nz - 1) ldg(lr, q + nx, rz);
@@ -1540,18 +1550,22 @@ __global__ __launch_bounds__(NT) void k_cg2_step(const InstDesc* __restrict__ D,
 #pragma unroll
   for (int a = 0; a < UX; ++a) {
     const int G = b + (int)threadIdx.x * W + a * NT * W;
-    if (G < e) point_group(G, xpre[a]);
+    if (G < e) point_group(G, xpre[a], pk[a], sk[a], rk[a]);
   }
   for (int G = b + (int)threadIdx.x * W + UX * NT * W; G < e; G += NT * W) {
     const int cnt = e - G < W ? e - G : W;
-    T xv[W];
+    T xv[W], pn[W], sv[W], rn[W];
     if (xvec) {
       ld16p<T>(x, G, N, xv);
     } else {
 #pragma unroll
       for (int u = 0; u < W; ++u) xv[u] = u < cnt ? x[G + u] : (T)0;
     }
-    point_group(G, xv);
+    int iz0, iy0, ix0;
+    g.coords(G, iz0, iy0, ix0);
+    s_group(G, iz0, ix0, pn, sv);
+    ldg(lr, G - b, rn);
+    point_group(G, xv, pn, sv, rn);
   }
   block_total_n<3, NT>(acc, lds);
   if (threadIdx.x == 0) {
