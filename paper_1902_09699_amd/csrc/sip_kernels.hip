@@ -1265,11 +1265,11 @@ __global__ __launch_bounds__(NT) void k_cg1_step(const InstDesc* __restrict__ D,
 //   x_{j+1} = x_j + alpha_j p_j,  r_{j+1} = r_j - alpha_j s_j,
 // and the partials of gamma_{j+1}, X_{j+1} = r_{j+1}^T s_j and
 // Q_{j+1} = c0 |r_{j+1}|^2 + sum_a c_a |D_a r_{j+1}|^2 (unit forward
-// differences, c_a folding 1/h_a^2 as in C).  A block stages r_j and p_j of
-// its item and of one row before and two after it in LDS, forms s_j and
-// r_{j+1} there for its points and the row after them (the forward
-// neighbours of its last row), then the partial sums, and writes its points'
-// x_{j+1}, p_j and r_{j+1}.  p_j, s_j, x_{j+1} and r_{j+1} are the two-launch
+// differences, c_a folding 1/h_a^2 as in C).  A block stages p_j of its
+// item and of one row before and two after it, and r_j of its item and the
+// row after it, in LDS, forms s_j and r_{j+1} there for its points and the
+// row after them (the forward neighbours of its last row), then the partial
+// sums, and writes its points' x_{j+1}, p_j and r_{j+1}.  p_j, s_j, x_{j+1} and r_{j+1} are the two-launch
 // form's expressions in the same order; only the double p_j^T C p_j is
 // summed another way.  r and p alternate between two buffers by step parity
 // (neighbours' old values are read while other blocks write the new ones); x
