@@ -324,7 +324,7 @@ def served_leg(args):
     # warm both lanes (code objects, graph capture at their first sizes)
     warm = serve.make_requests(4, 1e9, 0.0, seed0=9000, max2d=128) + \
         serve.make_requests(2, 1e9, 1.0, seed0=9050, side3d=(66, 72))
-    srv = serve.Server(opts, arena, 256, 10, lanes=2, split_points=1 << 18, tiles=serve.SERVED_TILES)
+    srv = serve.Server(opts, arena, 256, 5, lanes=2, split_points=1 << 18, tiles=serve.SERVED_TILES)
     srv.run(warm, realtime=False)
     reqs = serve.make_requests(n, rate)
     info = srv.run(reqs, realtime=True)
@@ -338,7 +338,8 @@ def served_leg(args):
     plain.update(pinfo)
     offered = sum(r.m.size for r in reqs) / max(reqs[-1].arrival - reqs[0].arrival, 1e-9)
     return {"requests": n, "rate_per_s": rate, "frac_3d": 0.05, "offered_grid_pts_per_s": round(offered, 1),
-            "server": ("two resident batches on two streams (requests up to 2^18 points / larger), chunks of 10, "
+            "server": ("two resident batches on two streams (requests up to 2^18 points / larger), chunks of 5 "
+                       "(plain form: 10), "
                        f"tiles {list(serve.SERVED_TILES)} (plain form: the engine's defaults)"),
             "stopping": "eqs. feas_stop/obj_stop every 5 it, cap 200, CG cap 10 at 0.1 relative residual",
             "served": served, "plain": plain,

@@ -230,10 +230,10 @@ def main():
     ap.add_argument("--arena-gb", type=float, default=96.0)
     ap.add_argument("--slots", type=int, default=256)
     # a multiple of the stopping test's period (5): a finished instance is
-    # seen at the end of the chunk that finished it (on 400 requests at 200
-    # req/s, chunks of 10 gave p50 365 ms against 400 ms with 5 or 8, and 440
-    # ms with 2, 3 or 15)
-    ap.add_argument("--chunk", type=int, default=10)
+    # seen at the end of the chunk that finished it (200 requests at 200
+    # req/s with SERVED_TILES: chunks of 5 gave p50/p99 184-189/439-466 ms
+    # against 198-209/476-486 ms with 10 and 204-212/480-484 ms with 15)
+    ap.add_argument("--chunk", type=int, default=5)
     ap.add_argument("--max-iter", type=int, default=200)
     ap.add_argument("--plain", action="store_true", help="also serve the same requests one at a time")
     ap.add_argument("--plain-requests", type=int, default=0, help="requests for the plain form (0: same)")
@@ -275,7 +275,7 @@ def main():
     srv.close()
     if a.plain:
         plain_reqs = make_requests(a.plain_requests or a.requests, a.rate, a.frac3d)
-        info = serve_plain(plain_reqs, opts, int(a.arena_gb * (1 << 30)), a.chunk, plain_tiles)
+        info = serve_plain(plain_reqs, opts, int(a.arena_gb * (1 << 30)), 10, plain_tiles)
         plain = summary(plain_reqs, "plain")
         plain.update(info)
         print(json.dumps(plain), flush=True)
