@@ -3115,11 +3115,20 @@ __device__ void apply_item(const InstDesc* __restrict__ D, const ThrItem* __rest
     T* v0 = (T*)s.v0 + off;
     unsigned long long run = rank_ties ? tie_base[c] : 0ull;
     if (!rank_ties) {
-      // 16-byte groups (no index ranking needed)
+      // 16-byte groups (no index ranking needed); w of the thread's next
+      // group is loaded while this one is processed (the arrays are padded
+      // to whole groups)
       constexpr int W = Grp<T>::W;
+      const bool pre = it.src == 0 && grouped;
+      T wnext[W];
+      if (pre && it.begin + (int)threadIdx.x * W < end) ld16<T>(y + it.begin + (int)threadIdx.x * W, wnext);
       int base = it.begin;
       for (; base < end; base += kSB * W) {
         const int P0 = base + (int)threadIdx.x * W;
+        T wcur[W];
+#pragma unroll
+        for (int e = 0; e < W; ++e) wcur[e] = wnext[e];
+        if (pre && P0 + kSB * W < end) ld16<T>(y + P0 + kSB * W, wnext);
         GLane L{};
         if (grouped) L = glane<T>(P0, it.begin, end, g);
         const bool full = grouped && L.vec;
@@ -3144,8 +3153,8 @@ __device__ void apply_item(const InstDesc* __restrict__ D, const ThrItem* __rest
             }
             continue;
           }
-          T w[W], yn[W], vn[W];
-          ld16<T>(y + P0, w);
+          T yn[W], vn[W];
+          const T (&w)[W] = wcur;
 #pragma unroll
           for (int e = 0; e < W; ++e) {
             T r = w[e];
