@@ -46,3 +46,27 @@ def test_same_iterates_in_small_and_large_batches(form):
     alone = _run([(m, sets)], opts, 6, tiles)
     mixed = _run([(m, sets), (big, big_sets)], opts, 6, tiles)
     assert np.array_equal(alone, mixed)
+
+
+@pytest.mark.parametrize("kind", ["3d", "wide_rows"])
+def test_lds_staged_form_falls_back_to_the_textbook_steps(kind):
+    """Under cg_form 2, an instance the LDS-staged step cannot take (a 3D
+    grid, or rows too long for a block's LDS with three halo rows) runs the
+    two-launch textbook steps: its iterates equal those under cg_form 0 bit
+    for bit, and differ from the one-reduction form's."""
+    rng = wl.rng_for(91)
+    if kind == "3d":
+        m = wl.grf((24, 20, 18), 4.0, rng)
+        sets = [wl.bounds("I", -1.0, 1.0), wl.l1("GRAD", 0.5)]
+    else:
+        m = wl.grf((8, 6000), 8.0, rng)
+        sets = [wl.bounds("I", -1.0, 1.0), wl.card("DX", 0.2)]
+    m = wl.rounded(m, "f32")
+    sets = wl.finalize(m, sets)
+    opts = sip.make_opts("f32", max_iter=5, cg_max=10, cg_fixed=1)
+    print(f"\n[launch forms] {kind} {m.shape}: cg_form 2 against 0", flush=True)
+    f2 = _run([(m, sets)], opts, 5, (2048, 512, 2048, 512, 256, 2))
+    f0 = _run([(m, sets)], opts, 5, (2048, 512, 2048, 512, 256, 0))
+    f1 = _run([(m, sets)], opts, 5, (2048, 512, 2048, 512, 256, 1))
+    assert np.array_equal(f2, f0)
+    assert not np.array_equal(f1, f0)
