@@ -127,16 +127,20 @@ def test_schedule_locked_f32(kind):
     assert err <= gate
 
 
-@pytest.mark.parametrize("kind", ["box_tv_2d", "four_sets_2d", "box_tv_lat_3d"])
-def test_reduce_f32_ablation(kind):
+@pytest.mark.parametrize("kind,form", [("box_tv_2d", 0), ("four_sets_2d", 0), ("box_tv_lat_3d", 0),
+                                       ("box_tv_2d", 1), ("four_sets_2d", 2), ("box_tv_2d", 2)])
+def test_reduce_f32_ablation(kind, form):
     """Pure-FP32 reductions (the precision ablation) against FP64 ones, both
-    schedule-locked against the FP64 oracle: the ablation still projects
-    (error bounded) and its error is reported next to the default's."""
+    schedule-locked against the FP64 oracle, under each CG form: the
+    ablation still projects (error bounded) and its error is reported next
+    to the default's."""
     m, sets = _prep(kind, "f32", seed=2)
     iters = 40
     errs = {}
+    tiles = (1024, 1024, 1024, 512, 256, form)
     for red in ("f64", "f32"):
-        sl = Slot(m, sets, "f32", dict(max_iter=iters, cg_max=10, cg_fixed=1, log_schedule=1, reduce=red))
+        sl = Slot(m, sets, "f32", dict(max_iter=iters, cg_max=10, cg_fixed=1, log_schedule=1, reduce=red),
+                  tiles=tiles)
         sl.batch.run(iters)
         res = sl.batch.result(sl.slot)
         assert res["status"] == 0 and res["iters"] == iters
@@ -144,8 +148,8 @@ def test_reduce_f32_ablation(kind):
         sched = {k + 1: (rho[k], gam[k]) for k in range(iters)}
         xo, _ = orc.parsdmm(m, m.shape, sets, orc.Options(max_iter=iters, cg_max=10, cg_fixed=True), schedule=sched)
         errs[red] = rel(sl.x(), xo)
-    print(f"\n[reduce ablation] {kind}: schedule-locked rel err, FP64 reductions {errs['f64']:.2e}, "
-          f"FP32 reductions {errs['f32']:.2e}", flush=True)
+    print(f"\n[reduce ablation] {kind}, CG form {form}: schedule-locked rel err, FP64 reductions "
+          f"{errs['f64']:.2e}, FP32 reductions {errs['f32']:.2e}", flush=True)
     assert np.isfinite(errs["f32"]) and errs["f32"] <= 1e-2
 
 
