@@ -116,6 +116,19 @@ class Slot:
         return self.batch.field_tensor(self.slot, which, i).double().cpu().numpy()
 
 
+class SlotView(Slot):
+    """One instance of a batch that holds others too (same helpers as Slot)."""
+
+    def __init__(self, batch, slot, m, sets, field, md, xd):
+        self.shape = m.shape
+        self.sets = sets
+        self.field = field
+        self.batch = batch
+        self.slot = slot
+        self.md = md
+        self.xd = xd
+
+
 def sync_oracle(sl: Slot, prob: orc.Problem, st: orc.State):
     """Overwrite the oracle state with the device state (exact upcast)."""
     p = len(sl.sets)
