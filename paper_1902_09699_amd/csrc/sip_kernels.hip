@@ -1992,11 +1992,12 @@ __device__ void proj_block(const InstDesc* __restrict__ D, const PtItem* __restr
 // Block b of the projection launch -> (item, unit).  Workgroups are dealt
 // to the 8 XCDs in turn, so blocks b, b + 8, b + 16, ... share an XCD and
 // its L2: the units of one item (each reads the item's x and its stencil
-// neighbours) go to consecutive blocks of one XCD, and the items are dealt
-// to the XCDs in turn (item-major order cut the batch's re-reads of x by
-// 80 MB per launch).  A launch has ceil(nsp / 8) * 8 * units blocks; the
-// caller drops items >= nsp.  The fused projection and w launch keeps the
-// unit-major order, which measured faster there.
+// neighbours) go to consecutive blocks of one XCD, and table entry e goes
+// to XCD e mod 8 (the host writes the table so that each XCD's entries are
+// a contiguous run of items).  Units back to back cut the batch's re-reads
+// of x by 80 MB per launch.  A launch has ceil(nsp / 8) * 8 * units blocks;
+// the caller drops entries >= nsp.  The fused projection and w launch keeps
+// the unit-major order, which measured faster there.
 __device__ __forceinline__ void proj_map(int b, int units, int& item, int& unit) {
   const int grp = b / (8 * units), r = b - grp * 8 * units;
   unit = r >> 3;
